@@ -1,0 +1,581 @@
+"""Generators of realised, fully unrolled Clifford syndrome-measurement circuits.
+
+Every generator returns a :class:`Circuit` holding Stim-format text (the circuit
+language subset accepted by the compiler) plus the counts a caller needs to
+build a per-channel rate array. Channels are enumerated in program order and,
+within one noise instruction, in target-group order (one qubit, or one pair for
+DEPOLARIZE2); this is the order in which a rate array overrides the rates
+written in the text.
+
+Workloads follow the paper's evaluation (Sec. 4): Z-basis memory experiments of
+the rotated surface code and of the bivariate bicycle code [[144,12,12]], d
+rounds, no REPEAT blocks, with circuit-level noise (Sec. 2.1.3): DEPOLARIZE1
+after single-qubit gates and resets, DEPOLARIZE2 after each CX, X_ERROR before
+each measurement. No idle noise is inserted.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+import random
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Circuit:
+    text: str
+    n_qubits: int
+    n_channels: int
+    n_measurements: int
+    n_detectors: int
+    n_observables: int
+    rounds: int
+    name: str
+
+    def channel_kinds(self) -> List[str]:
+        """Noise instruction name of each channel, in channel order."""
+        kinds: List[str] = []
+        for line in self.text.splitlines():
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            head = line.split()[0]
+            name = head.split("(")[0].upper()
+            tail = line[len(head):].split()
+            if name in ("X_ERROR", "Y_ERROR", "Z_ERROR", "DEPOLARIZE1"):
+                kinds += [name] * len(tail)
+            elif name == "DEPOLARIZE2":
+                kinds += [name] * (len(tail) // 2)
+        return kinds
+
+
+class _Builder:
+    """Accumulates circuit text and keeps the running counts."""
+
+    def __init__(self) -> None:
+        self.lines: List[str] = []
+        self.n_meas = 0
+        self.n_det = 0
+        self.n_obs = 0
+        self.n_chan = 0
+        self.max_q = -1
+
+    def _touch(self, qs: Sequence[int]) -> None:
+        if qs:
+            self.max_q = max(self.max_q, max(qs))
+
+    def gate(self, name: str, qs: Sequence[int]) -> None:
+        if len(qs) == 0:
+            return
+        self._touch(qs)
+        self.lines.append(name + " " + " ".join(str(q) for q in qs))
+
+    def pairs(self, name: str, ps: Sequence[Tuple[int, int]]) -> None:
+        flat = [q for p in ps for q in p]
+        self.gate(name, flat)
+
+    def noise1(self, name: str, p: float, qs: Sequence[int]) -> None:
+        if len(qs) == 0 or p is None:
+            return
+        self._touch(qs)
+        self.lines.append(f"{name}({p!r}) " + " ".join(str(q) for q in qs))
+        self.n_chan += len(qs)
+
+    def noise2(self, p: float, ps: Sequence[Tuple[int, int]]) -> None:
+        if len(ps) == 0 or p is None:
+            return
+        flat = [q for pr in ps for q in pr]
+        self._touch(flat)
+        self.lines.append(f"DEPOLARIZE2({p!r}) " + " ".join(str(q) for q in flat))
+        self.n_chan += len(ps)
+
+    def measure(self, name: str, qs: Sequence[int]) -> List[int]:
+        """Emit a measurement instruction; return absolute measurement indices."""
+        self.gate(name, qs)
+        idx = list(range(self.n_meas, self.n_meas + len(qs)))
+        self.n_meas += len(qs)
+        return idx
+
+    def _recs(self, meas: Sequence[int]) -> str:
+        return " ".join(f"rec[{m - self.n_meas}]" for m in meas)
+
+    def detector(self, meas: Sequence[int], coords: Optional[Sequence[float]] = None) -> int:
+        c = "" if coords is None else "(" + ", ".join(repr(float(x)) for x in coords) + ")"
+        self.lines.append(f"DETECTOR{c} " + self._recs(meas))
+        self.n_det += 1
+        return self.n_det - 1
+
+    def observable(self, k: int, meas: Sequence[int]) -> None:
+        self.lines.append(f"OBSERVABLE_INCLUDE({k}) " + self._recs(meas))
+        self.n_obs = max(self.n_obs, k + 1)
+
+    def tick(self) -> None:
+        self.lines.append("TICK")
+
+    def build(self, rounds: int, name: str, n_qubits: Optional[int] = None) -> Circuit:
+        return Circuit(
+            text="\n".join(self.lines) + "\n",
+            n_qubits=(self.max_q + 1) if n_qubits is None else n_qubits,
+            n_channels=self.n_chan,
+            n_measurements=self.n_meas,
+            n_detectors=self.n_det,
+            n_observables=self.n_obs,
+            rounds=rounds,
+            name=name,
+        )
+
+
+# ---------------------------------------------------------------------------
+# Rotated surface code
+# ---------------------------------------------------------------------------
+
+def _rotated_layout(d: int):
+    """Data qubit (r, c) -> r*d + c. Plaquette with corner index (i, j),
+    0 <= i, j <= d, covers data (i-1, j-1), (i-1, j), (i, j-1), (i, j).
+    Checkerboard: X type if (i + j) is even. Weight-2 plaquettes are kept on the
+    top/bottom edges for X type and on the left/right edges for Z type.
+    Returns lists of (type, corners) with corners = (TL, TR, BL, BR), None where
+    the corner falls outside the lattice."""
+    plaqs = []
+    for i in range(d + 1):
+        for j in range(d + 1):
+            typ = "X" if (i + j) % 2 == 0 else "Z"
+            interior = 1 <= i <= d - 1 and 1 <= j <= d - 1
+            top_bottom = (i == 0 or i == d) and 1 <= j <= d - 1
+            left_right = (j == 0 or j == d) and 1 <= i <= d - 1
+            if not (interior or (top_bottom and typ == "X") or (left_right and typ == "Z")):
+                continue
+
+            def dq(r, c):
+                return r * d + c if (0 <= r < d and 0 <= c < d) else None
+
+            corners = (dq(i - 1, j - 1), dq(i - 1, j), dq(i, j - 1), dq(i, j))
+            plaqs.append((typ, corners))
+    return plaqs
+
+
+def rotated_surface_code_memory(d: int, rounds: int, p: float = 1e-3,
+                                p1: Optional[float] = None, p2: Optional[float] = None,
+                                pm: Optional[float] = None, pr: Optional[float] = None,
+                                ticks: bool = True) -> Circuit:
+    """Z-basis memory of the distance-d rotated surface code, `rounds` rounds.
+
+    CX order: X checks visit (TL, TR, BL, BR) ("Z" shape), Z checks visit
+    (TL, BL, TR, BR) ("N" shape), so that hook errors of each type run
+    perpendicular to the logical operator of the same type. Detectors: first
+    round Z checks, consecutive-round parity of every check, final data parity of
+    every Z check. Observable 0: Z on data row 0.
+    """
+    p1 = p if p1 is None else p1
+    p2 = p if p2 is None else p2
+    pm = p if pm is None else pm
+    pr = p if pr is None else pr
+    plaqs = _rotated_layout(d)
+    n_data = d * d
+    anc = [n_data + k for k in range(len(plaqs))]
+    xanc = [anc[k] for k, (t, _) in enumerate(plaqs) if t == "X"]
+    zanc = [anc[k] for k, (t, _) in enumerate(plaqs) if t == "Z"]
+    data = list(range(n_data))
+    allq = data + anc
+    order_x = (0, 1, 2, 3)
+    order_z = (0, 2, 1, 3)
+    b = _Builder()
+    b.gate("R", allq)
+    b.noise1("DEPOLARIZE1", pr, allq)
+    if ticks:
+        b.tick()
+    last: Dict[int, int] = {}
+    for rnd in range(rounds):
+        b.gate("H", xanc)
+        b.noise1("DEPOLARIZE1", p1, xanc)
+        if ticks:
+            b.tick()
+        for layer in range(4):
+            pairs = []
+            for k, (typ, corners) in enumerate(plaqs):
+                slot = order_x[layer] if typ == "X" else order_z[layer]
+                q = corners[slot]
+                if q is None:
+                    continue
+                pairs.append((anc[k], q) if typ == "X" else (q, anc[k]))
+            b.pairs("CX", pairs)
+            b.noise2(p2, pairs)
+            if ticks:
+                b.tick()
+        b.gate("H", xanc)
+        b.noise1("DEPOLARIZE1", p1, xanc)
+        if ticks:
+            b.tick()
+        b.noise1("X_ERROR", pm, anc)
+        ms = b.measure("MR", anc)
+        b.noise1("DEPOLARIZE1", pr, anc)
+        cur = dict(zip(anc, ms))
+        for k, (typ, _) in enumerate(plaqs):
+            a = anc[k]
+            if rnd == 0:
+                if typ == "Z":
+                    b.detector([cur[a]])
+            else:
+                b.detector([cur[a], last[a]])
+        last = cur
+        if ticks:
+            b.tick()
+    b.noise1("X_ERROR", pm, data)
+    mdata = dict(zip(data, b.measure("M", data)))
+    for k, (typ, corners) in enumerate(plaqs):
+        if typ != "Z":
+            continue
+        ms = [mdata[q] for q in corners if q is not None]
+        b.detector(ms + [last[anc[k]]])
+    b.observable(0, [mdata[c] for c in range(d)])
+    return b.build(rounds, f"rotated_surface_code_d{d}_r{rounds}")
+
+
+def rotated_surface_code_checks(d: int):
+    """(H_X, H_Z) parity-check matrices of the layout used above (tests only)."""
+    plaqs = _rotated_layout(d)
+    hx, hz = [], []
+    for typ, corners in plaqs:
+        row = np.zeros(d * d, dtype=np.uint8)
+        for q in corners:
+            if q is not None:
+                row[q] = 1
+        (hx if typ == "X" else hz).append(row)
+    return np.array(hx), np.array(hz)
+
+
+# ---------------------------------------------------------------------------
+# Repetition code and the bit-flip example of the paper's Fig. 1
+# ---------------------------------------------------------------------------
+
+def repetition_code_memory(d: int, rounds: int, p_data: float = 0.0, p_meas: float = 0.0,
+                           p2: float = 0.0, p1: float = 0.0,
+                           data_noise: str = "X_ERROR") -> Circuit:
+    """Bit-flip repetition code: data 0..d-1, ancilla d+i checks Z_i Z_{i+1}.
+
+    p_data: `data_noise` on every data qubit before each round
+    (phenomenological-style); p_meas: X_ERROR before each measurement;
+    p2: DEPOLARIZE2 after every CX; p1: DEPOLARIZE1 after every reset.
+    A rate of 0 omits the channel. Observable 0: final measurement of data 0.
+    """
+    data = list(range(d))
+    anc = [d + i for i in range(d - 1)]
+    b = _Builder()
+    b.gate("R", data + anc)
+    if p1:
+        b.noise1("DEPOLARIZE1", p1, data + anc)
+    b.tick()
+    last: Dict[int, int] = {}
+    for rnd in range(rounds):
+        if p_data:
+            b.noise1(data_noise, p_data, data)
+        for off in (0, 1):
+            pairs = [(i + off, anc[i]) for i in range(d - 1)]
+            b.pairs("CX", pairs)
+            if p2:
+                b.noise2(p2, pairs)
+            b.tick()
+        if p_meas:
+            b.noise1("X_ERROR", p_meas, anc)
+        ms = b.measure("MR", anc)
+        if p1:
+            b.noise1("DEPOLARIZE1", p1, anc)
+        cur = dict(zip(anc, ms))
+        for a in anc:
+            b.detector([cur[a]] if rnd == 0 else [cur[a], last[a]])
+        last = cur
+        b.tick()
+    if p_meas:
+        b.noise1("X_ERROR", p_meas, data)
+    md = b.measure("M", data)
+    for i, a in enumerate(anc):
+        b.detector([md[i], md[i + 1], last[a]])
+    b.observable(0, [md[0]])
+    return b.build(rounds, f"repetition_d{d}_r{rounds}")
+
+
+def bit_flip_code_fig1(error_after_second_cnot_layer: bool = True) -> Circuit:
+    """The d = 3 bit-flip code of the paper's Fig. 1 over two rounds.
+
+    Qubits 0, 2, 4 are data, 1 and 3 are ancillas. Round: CX 0->1, 2->3; then
+    CX 2->1, 4->3; then MR 1 3. Detectors in declaration order: orange (first
+    measurement of ancilla 1), green (first measurement of ancilla 3), blue
+    (parity of the two ancilla-1 measurements), yellow (same for ancilla 3).
+    The single noise channel is an X error on data qubit 2 placed after the
+    second CNOT layer of the first round (the error called E12 in the figure).
+    """
+    b = _Builder()
+    b.gate("R", [0, 1, 2, 3, 4])
+    b.tick()
+    ms_rounds = []
+    for rnd in range(2):
+        b.pairs("CX", [(0, 1), (2, 3)])
+        b.tick()
+        b.pairs("CX", [(2, 1), (4, 3)])
+        if rnd == 0 and error_after_second_cnot_layer:
+            b.noise1("X_ERROR", 0.01, [2])
+        b.tick()
+        ms_rounds.append(b.measure("MR", [1, 3]))
+        b.tick()
+    (a1, a3), (b1, b3) = ms_rounds
+    b.detector([a1])       # orange
+    b.detector([a3])       # green
+    b.detector([a1, b1])   # blue
+    b.detector([a3, b3])   # yellow
+    return b.build(2, "bit_flip_fig1", n_qubits=5)
+
+
+# ---------------------------------------------------------------------------
+# Bivariate bicycle code [[144,12,12]]
+# ---------------------------------------------------------------------------
+
+def _shift(n: int, k: int) -> np.ndarray:
+    m = np.zeros((n, n), dtype=np.uint8)
+    for i in range(n):
+        m[i, (i + k) % n] = 1
+    return m
+
+
+def bb_matrices(l: int = 12, m: int = 6):
+    """A = x^3 + y + y^2, B = y^3 + x + x^2 with x = S_l (x) I_m, y = I_l (x) S_m.
+    Returns the three permutation terms of A and of B."""
+    x = np.kron(_shift(l, 1), np.eye(m, dtype=np.uint8))
+    y = np.kron(np.eye(l, dtype=np.uint8), _shift(m, 1))
+
+    def mpow(a, k):
+        r = np.eye(a.shape[0], dtype=np.uint8)
+        for _ in range(k):
+            r = (r @ a) % 2
+        return r.astype(np.uint8)
+
+    a_terms = [mpow(x, 3), mpow(y, 1), mpow(y, 2)]
+    b_terms = [mpow(y, 3), mpow(x, 1), mpow(x, 2)]
+    return a_terms, b_terms
+
+
+def _gf2_rank(mat: np.ndarray) -> int:
+    a = (mat.copy() % 2).astype(np.uint8)
+    rank = 0
+    rows, cols = a.shape
+    for c in range(cols):
+        piv = None
+        for r in range(rank, rows):
+            if a[r, c]:
+                piv = r
+                break
+        if piv is None:
+            continue
+        a[[rank, piv]] = a[[piv, rank]]
+        for r in range(rows):
+            if r != rank and a[r, c]:
+                a[r] ^= a[rank]
+        rank += 1
+        if rank == rows:
+            break
+    return rank
+
+
+def _gf2_nullspace(mat: np.ndarray) -> np.ndarray:
+    a = (mat.copy() % 2).astype(np.uint8)
+    rows, cols = a.shape
+    pivots = []
+    r = 0
+    for c in range(cols):
+        piv = None
+        for k in range(r, rows):
+            if a[k, c]:
+                piv = k
+                break
+        if piv is None:
+            continue
+        a[[r, piv]] = a[[piv, r]]
+        for k in range(rows):
+            if k != r and a[k, c]:
+                a[k] ^= a[r]
+        pivots.append(c)
+        r += 1
+        if r == rows:
+            break
+    free = [c for c in range(cols) if c not in pivots]
+    basis = []
+    for f in free:
+        v = np.zeros(cols, dtype=np.uint8)
+        v[f] = 1
+        for i, pc in enumerate(pivots):
+            if a[i, f]:
+                v[pc] = 1
+        basis.append(v)
+    return np.array(basis, dtype=np.uint8)
+
+
+def bb_check_matrices(l: int = 12, m: int = 6):
+    a_terms, b_terms = bb_matrices(l, m)
+    a = sum(a_terms) % 2
+    bm = sum(b_terms) % 2
+    hx = np.concatenate([a, bm], axis=1).astype(np.uint8)
+    hz = np.concatenate([bm.T, a.T], axis=1).astype(np.uint8)
+    return hx, hz
+
+
+def bb_logical_z(l: int = 12, m: int = 6) -> np.ndarray:
+    """Basis of Z-type logical operators: ker(H_X) modulo rowspace(H_Z)."""
+    hx, hz = bb_check_matrices(l, m)
+    ker = _gf2_nullspace(hx)
+    chosen: List[np.ndarray] = []
+    base_rank = _gf2_rank(hz)
+    cur = hz.copy()
+    for v in ker:
+        trial = np.concatenate([cur, v[None, :]], axis=0)
+        if _gf2_rank(trial) > base_rank + len(chosen):
+            chosen.append(v)
+            cur = trial
+    return np.array(chosen, dtype=np.uint8)
+
+
+def bivariate_bicycle_memory(rounds: int = 12, p: float = 1e-3, l: int = 12, m: int = 6) -> Circuit:
+    """Z-basis memory of the bivariate bicycle code (default [[144,12,12]]).
+
+    Qubits: L data 0..lm-1, R data lm..2lm-1, X ancillas, then Z ancillas.
+    Syndrome circuit: the six permutation terms of [A|B] are applied as six CX
+    layers from the X ancillas, then the six terms of [B^T|A^T] as six CX
+    layers onto the Z ancillas (twelve CX layers per round; every layer is a
+    permutation, so each qubit is touched once per layer).
+    """
+    nd = l * m
+    a_terms, b_terms = bb_matrices(l, m)
+    L = list(range(nd))
+    R = list(range(nd, 2 * nd))
+    xa = list(range(2 * nd, 3 * nd))
+    za = list(range(3 * nd, 4 * nd))
+    anc = xa + za
+    data = L + R
+    allq = data + anc
+    b = _Builder()
+    b.gate("R", allq)
+    b.noise1("DEPOLARIZE1", p, allq)
+    b.tick()
+    last: Dict[int, int] = {}
+    for rnd in range(rounds):
+        b.gate("H", xa)
+        b.noise1("DEPOLARIZE1", p, xa)
+        b.tick()
+        # X checks: row i of A (on L) and of B (on R).
+        for blk, terms in ((L, a_terms), (R, b_terms)):
+            for t in terms:
+                pairs = [(xa[i], blk[int(np.nonzero(t[i])[0][0])]) for i in range(nd)]
+                b.pairs("CX", pairs)
+                b.noise2(p, pairs)
+                b.tick()
+        b.gate("H", xa)
+        b.noise1("DEPOLARIZE1", p, xa)
+        b.tick()
+        # Z checks: row i of B^T (on L) and of A^T (on R).
+        for blk, terms in ((L, b_terms), (R, a_terms)):
+            for t in terms:
+                tt = t.T
+                pairs = [(blk[int(np.nonzero(tt[i])[0][0])], za[i]) for i in range(nd)]
+                b.pairs("CX", pairs)
+                b.noise2(p, pairs)
+                b.tick()
+        b.noise1("X_ERROR", p, anc)
+        ms = b.measure("MR", anc)
+        b.noise1("DEPOLARIZE1", p, anc)
+        cur = dict(zip(anc, ms))
+        if rnd == 0:
+            for a in za:
+                b.detector([cur[a]])
+        else:
+            for a in anc:
+                b.detector([cur[a], last[a]])
+        last = cur
+        b.tick()
+    b.noise1("X_ERROR", p, data)
+    md = b.measure("M", data)
+    hx, hz = bb_check_matrices(l, m)
+    for i, a in enumerate(za):
+        supp = np.nonzero(hz[i])[0]
+        b.detector([md[int(q)] for q in supp] + [last[a]])
+    logicals = bb_logical_z(l, m)
+    for k, v in enumerate(logicals):
+        b.observable(k, [md[int(q)] for q in np.nonzero(v)[0]])
+    return b.build(rounds, f"bivariate_bicycle_{2 * nd}_r{rounds}")
+
+
+# ---------------------------------------------------------------------------
+# Mirror circuits: random Clifford layers followed by their inverse
+# ---------------------------------------------------------------------------
+
+_INVERSE = {"H": "H", "S": "S_DAG", "S_DAG": "S", "SQRT_X": "SQRT_X_DAG",
+            "SQRT_X_DAG": "SQRT_X", "X": "X", "Y": "Y", "Z": "Z", "I": "I",
+            "CX": "CX", "CZ": "CZ", "SWAP": "SWAP"}
+
+
+def mirror_circuit(n: int, depth: int, seed: int, p: float = 0.05,
+                   x_basis: Sequence[int] = ()) -> Circuit:
+    """Random layers of {H, S, S_DAG, SQRT_X, SQRT_X_DAG, X, Y, Z, I, CX, CZ,
+    SWAP} followed by the inverse layers, so every final measurement is
+    deterministic. Qubits listed in `x_basis` are prepared with RX and read with
+    MX. A DEPOLARIZE1 / DEPOLARIZE2 follows every gate; Y_ERROR and Z_ERROR
+    channels are sprinkled in; one mid-circuit MR on an extra qubit checks
+    measurement-reset handling. Every final measurement is a detector (one of
+    them listed twice with another record, which must cancel), and observable 0
+    is split over two OBSERVABLE_INCLUDE instructions."""
+    rng = random.Random(seed)
+    one_q = ["H", "S", "S_DAG", "SQRT_X", "SQRT_X_DAG", "X", "Y", "Z", "I"]
+    two_q = ["CX", "CZ", "SWAP"]
+    layers: List[List[Tuple[str, Tuple[int, ...]]]] = []
+    for _ in range(depth):
+        qs = list(range(n))
+        rng.shuffle(qs)
+        layer = []
+        while qs:
+            if len(qs) >= 2 and rng.random() < 0.5:
+                a, c = qs.pop(), qs.pop()
+                layer.append((rng.choice(two_q), (a, c)))
+            else:
+                layer.append((rng.choice(one_q), (qs.pop(),)))
+        layers.append(layer)
+    b = _Builder()
+    zq = [q for q in range(n) if q not in x_basis]
+    b.gate("R", zq + [n])
+    b.gate("RX", list(x_basis))
+    b.noise1("DEPOLARIZE1", p, list(range(n)))
+    b.tick()
+
+    def emit(layer, inverse):
+        for g, qs in layer:
+            name = _INVERSE[g] if inverse else g
+            b.gate(name, list(qs))
+            if len(qs) == 1:
+                b.noise1("DEPOLARIZE1", p, list(qs))
+            else:
+                b.noise2(p, [qs])
+        b.tick()
+
+    for k, layer in enumerate(layers):
+        emit(layer, False)
+        if k == depth // 2:
+            b.noise1("Y_ERROR", p, [0])
+            b.noise1("Z_ERROR", p, [n - 1])
+    # mid-circuit measure-and-reset of an extra qubit whose outcome is fixed
+    b.noise1("X_ERROR", p, [n])
+    m_extra = b.measure("MR", [n])
+    b.detector(m_extra)
+    for layer in reversed(layers):
+        emit([(g, qs) for g, qs in reversed(layer)], True)
+    b.noise1("X_ERROR", p, zq)
+    b.noise1("Z_ERROR", p, list(x_basis))
+    mz = dict(zip(zq, b.measure("M", zq)))
+    mx = dict(zip(x_basis, b.measure("MX", list(x_basis))))
+    allm = {**mz, **mx}
+    for q in range(n):
+        if q == 0 and n > 1:
+            b.detector([allm[0], allm[1], allm[1]])
+        else:
+            b.detector([allm[q]])
+    b.observable(0, [allm[0]])
+    if n > 1:
+        b.observable(0, [allm[n - 1]])
+    return b.build(2 * depth, f"mirror_n{n}_d{depth}_s{seed}", n_qubits=n + 1)
