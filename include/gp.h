@@ -1,0 +1,178 @@
+/*
+ * gp.h -- C ABI of the MI355X just-in-time compiler for decoding hypergraphs.
+ *
+ * The library compiles one realised, fully unrolled Clifford circuit with
+ * Pauli noise channels into its decoding hypergraph (the detector error model
+ * of paper Sec. 2.1.4): one hyperedge per equivalence class of faults, carrying
+ * the exact set of detectors and logical observables the class flips and the
+ * merged probability of its faults (Eq. 3). The pipeline is the paper's
+ * two-stage method (Sec. 3): lowering to the space-time error propagation graph
+ * (Sec. 2.3.1), stage 1 error-equivalence-class generation by a backward XOR
+ * sweep (Alg. 1, Eq. 1, Eq. 2), stage 2 probability aggregation by hash, sort
+ * and segmented reduction (Sec. 3.2, Eq. 3). Lowering runs on the host; both
+ * stages run in HIP kernels on one gfx950 device.
+ *
+ * Conventions for every function:
+ *   - the return value is a status: GP_OK (0) or a negative GP_E_* code; on a
+ *     non-zero status gp_last_error() returns a thread-local message and no
+ *     output argument is written;
+ *   - pointers named text/rates are host pointers owned by the caller and only
+ *     read during the call;
+ *   - objects returned through an out-pointer are owned by the caller and are
+ *     released with the matching *_destroy / *_free function;
+ *   - a driver is not thread-safe: use one driver per host thread.
+ *
+ * Circuit language: a subset of the Stim text format. Gates R RZ RX M MZ MX MR
+ * MRZ MRX H H_XZ S S_DAG SQRT_Z SQRT_Z_DAG SQRT_X SQRT_X_DAG I X Y Z CX CNOT
+ * ZCX CZ ZCZ SWAP; noise X_ERROR Y_ERROR Z_ERROR DEPOLARIZE1 DEPOLARIZE2 (one
+ * probability argument); annotations DETECTOR OBSERVABLE_INCLUDE(k) with
+ * rec[-k] targets; TICK QUBIT_COORDS SHIFT_COORDS are accepted and ignored.
+ * REPEAT blocks, measurement-flip arguments and inverted targets are rejected
+ * with GP_E_UNSUPPORTED. Every qubit starts in |0>.
+ *
+ * Channels are numbered in program order and, inside one noise instruction,
+ * in target-group order (one qubit; one pair for DEPOLARIZE2). A rate array
+ * passed to the compile functions is indexed by that channel number.
+ *
+ * Per-fault probabilities (the paper does not state them): X/Y/Z_ERROR(r)
+ * give one fault with p = r; DEPOLARIZE1(r) gives X, Y and Z each with the p
+ * for which (1-2p)^2 = 1 - 4r/3, DEPOLARIZE2(r) the fifteen non-identity
+ * two-qubit Paulis each with (1-2p)^8 = 1 - 16r/15 (independent channels with
+ * the same Pauli transfer eigenvalues as the depolarising channel).
+ */
+#ifndef GP_H
+#define GP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  GP_OK = 0,
+  GP_E_ARG = -1,              /* null pointer, bad size, bad handle */
+  GP_E_PARSE = -2,            /* malformed circuit text */
+  GP_E_UNSUPPORTED = -3,      /* instruction or target outside the subset, REPEAT */
+  GP_E_BOUNDS = -4,           /* circuit exceeds the driver's bounds (no silent re-allocation) */
+  GP_E_NONDETERMINISTIC = -5, /* a detector or observable is not deterministic */
+  GP_E_NOISE = -6,            /* rate outside its domain, or wrong rate-array length */
+  GP_E_HIP = -7,              /* HIP runtime error, or no usable gfx950 device */
+  GP_E_OOM = -8,              /* host or device allocation failed */
+  GP_E_COLLISION = -9,        /* two different signatures share both 64-bit hashes */
+  GP_E_STATE = -10            /* call out of order (e.g. gp_run before gp_lower) */
+};
+
+typedef struct gp_driver gp_driver;
+typedef struct gp_edges gp_edges;
+
+/* Size bounds of a driver; every device buffer is allocated once from these
+ * (paper Sec. 3.4, buffer reuse). Circuits within the bounds reuse the buffers. */
+typedef struct gp_bounds {
+  uint32_t max_qubits;
+  uint32_t max_layers;        /* gate layers after as-soon-as-possible scheduling */
+  uint32_t max_measurements;
+  uint32_t max_detectors;
+  uint32_t max_observables;
+  uint32_t max_channels;
+  uint64_t max_faults;
+  uint64_t max_ops;           /* elementary gate/measurement/reset operations */
+  uint64_t max_leaf_bits;     /* total (measurement, detector-or-observable) memberships */
+  uint64_t max_slab_words;    /* 64-bit words of stage-1 signature storage */
+  uint64_t max_items;         /* stage-1 sweep work items */
+} gp_bounds;
+
+/* Sizes of the most recently lowered circuit (and, after a fetch, its result). */
+typedef struct gp_circuit_info {
+  uint32_t n_qubits, n_layers, n_measurements, n_detectors, n_observables;
+  uint32_t n_words;           /* 64-bit signature words: ceil(D/64) + ceil(O/64) */
+  uint64_t n_channels, n_faults, n_ops, n_items, slab_words;
+  uint64_t n_classes;         /* equivalence classes incl. the empty one (valid after fetch) */
+  uint64_t n_edges;           /* hyperedges = non-empty classes (valid after fetch) */
+  uint64_t n_edge_bits;       /* total signature bits over all hyperedges (valid after fetch) */
+  uint64_t n_live_words;      /* stage-1 signature words written (valid after fetch) */
+} gp_circuit_info;
+
+/* Thread-local description of the last non-zero status. Never NULL. */
+const char* gp_last_error(void);
+
+/* Lower `text` on the host only and report the bounds it needs. No GPU use. */
+int gp_bounds_from_circuit(const char* text, size_t len, gp_bounds* out);
+
+/* Create a driver on HIP device `device`: allocates every device buffer from
+ * `bounds` and a HIP stream of default priority. Fails with GP_E_HIP when the
+ * device is missing or is not gfx950. */
+int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out);
+
+/* Listing 1 of the paper: a driver whose bounds are those of a maximum circuit. */
+int gp_driver_create_from_circuit(const char* text, size_t len, int device, gp_driver** out);
+
+/* Waits for outstanding work, frees device and host buffers. NULL is ignored. */
+void gp_driver_destroy(gp_driver* drv);
+
+/* Whole path, blocking: lower, run both stages, copy the hypergraph to the
+ * host. `rates` (NULL = rates written in the text) must hold exactly one rate
+ * per channel. On success *out owns the result. */
+int gp_compile_hypergraph(gp_driver* drv, const char* text, size_t len,
+                          const double* rates, size_t n_rates, gp_edges** out);
+
+/* Split form of gp_compile_hypergraph, for callers that keep state on the
+ * device and time the device stages alone:
+ *   gp_lower  -- host lowering + asynchronous upload of the tables to the
+ *                driver's buffers (the upload is ordered on the driver's stream);
+ *   gp_run    -- enqueue stage 1 and stage 2 on the driver's stream; returns
+ *                without waiting; may be called repeatedly on one lowering;
+ *   gp_fetch  -- wait for the stream, check device-side error flags
+ *                (GP_E_NONDETERMINISTIC, GP_E_COLLISION, GP_E_BOUNDS) and copy
+ *                the hypergraph to a new host gp_edges. */
+int gp_lower(gp_driver* drv, const char* text, size_t len, const double* rates, size_t n_rates);
+int gp_run(gp_driver* drv);
+int gp_fetch(gp_driver* drv, gp_edges** out);
+
+/* Wait for every operation enqueued on the driver's stream. */
+int gp_sync(gp_driver* drv);
+
+/* The driver's hipStream_t, as an opaque pointer. */
+void* gp_driver_stream(gp_driver* drv);
+
+int gp_circuit_info_get(const gp_driver* drv, gp_circuit_info* out);
+
+/* Per-kernel timing with HIP events recorded on the driver's stream around
+ * every launch while enabled. Totals accumulate over gp_run calls until reset;
+ * they are read after gp_sync / gp_fetch. */
+int gp_set_timing(gp_driver* drv, int enable);
+int gp_reset_timing(gp_driver* drv);
+int gp_timing_count(const gp_driver* drv);
+int gp_timing_entry(const gp_driver* drv, int index, const char** name,
+                    double* total_ms, uint64_t* launches);
+
+/* Test hooks. gp_debug_set_key_bits keeps only the low `bits` bits of the
+ * stage-2 class key (default 64), which forces key collisions; the result must
+ * not change, because a collision found on the device makes gp_fetch compile
+ * again keyed on both hashes. gp_debug_collision_retries counts such re-runs. */
+int gp_debug_set_key_bits(gp_driver* drv, int bits);
+uint64_t gp_debug_collision_retries(const gp_driver* drv);
+
+/* Result accessors. Hyperedge e has signature bits
+ *   bits[offsets[e]] ... bits[offsets[e+1]-1]   (strictly increasing),
+ * where bit b < n_detectors is detector b and bit n_detectors + k is
+ * observable k, and probability probabilities[e]. Edge order is unspecified
+ * (deterministic for a given circuit). Pointers stay valid until gp_edges_free. */
+uint64_t gp_edges_count(const gp_edges* e);
+uint32_t gp_edges_detectors(const gp_edges* e);
+uint32_t gp_edges_observables(const gp_edges* e);
+const uint64_t* gp_edges_offsets(const gp_edges* e);
+const uint32_t* gp_edges_bits(const gp_edges* e);
+const double* gp_edges_probabilities(const gp_edges* e);
+/* Detector error model text, one "error(q) D.. L.." line per hyperedge. The
+ * caller releases *text with gp_free. */
+int gp_edges_to_dem_text(const gp_edges* e, char** text, size_t* len);
+void gp_edges_free(gp_edges* e);
+void gp_free(void* p);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GP_H */

@@ -1,0 +1,278 @@
+"""ctypes binding of ``include/gp.h``: one Python function per C entry point,
+same names, argument marshalling only. Every computation happens in
+``libgp.so``; if the library is missing this module raises instead of falling
+back to anything else."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libgp.so")
+
+GP_OK = 0
+STATUS = {
+    -1: "GP_E_ARG", -2: "GP_E_PARSE", -3: "GP_E_UNSUPPORTED", -4: "GP_E_BOUNDS",
+    -5: "GP_E_NONDETERMINISTIC", -6: "GP_E_NOISE", -7: "GP_E_HIP", -8: "GP_E_OOM",
+    -9: "GP_E_COLLISION", -10: "GP_E_STATE",
+}
+
+#: every symbol include/gp.h declares
+EXPORTS = (
+    "gp_last_error", "gp_bounds_from_circuit", "gp_driver_create", "gp_driver_create_from_circuit",
+    "gp_driver_destroy", "gp_compile_hypergraph", "gp_lower", "gp_run", "gp_fetch", "gp_sync",
+    "gp_driver_stream", "gp_circuit_info_get", "gp_set_timing", "gp_reset_timing", "gp_timing_count",
+    "gp_timing_entry", "gp_edges_count", "gp_edges_detectors", "gp_edges_observables",
+    "gp_edges_offsets", "gp_edges_bits", "gp_edges_probabilities", "gp_edges_to_dem_text",
+    "gp_edges_free", "gp_free", "gp_debug_set_key_bits", "gp_debug_collision_retries",
+)
+
+
+class GpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+
+
+class GpBounds(ctypes.Structure):
+    _fields_ = [
+        ("max_qubits", ctypes.c_uint32), ("max_layers", ctypes.c_uint32),
+        ("max_measurements", ctypes.c_uint32), ("max_detectors", ctypes.c_uint32),
+        ("max_observables", ctypes.c_uint32), ("max_channels", ctypes.c_uint32),
+        ("max_faults", ctypes.c_uint64), ("max_ops", ctypes.c_uint64),
+        ("max_leaf_bits", ctypes.c_uint64), ("max_slab_words", ctypes.c_uint64),
+        ("max_items", ctypes.c_uint64),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class GpCircuitInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_qubits", ctypes.c_uint32), ("n_layers", ctypes.c_uint32),
+        ("n_measurements", ctypes.c_uint32), ("n_detectors", ctypes.c_uint32),
+        ("n_observables", ctypes.c_uint32), ("n_words", ctypes.c_uint32),
+        ("n_channels", ctypes.c_uint64), ("n_faults", ctypes.c_uint64), ("n_ops", ctypes.c_uint64),
+        ("n_items", ctypes.c_uint64), ("slab_words", ctypes.c_uint64),
+        ("n_classes", ctypes.c_uint64), ("n_edges", ctypes.c_uint64), ("n_edge_bits", ctypes.c_uint64),
+        ("n_live_words", ctypes.c_uint64),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_u64 = ctypes.c_uint64
+
+
+def load():
+    """Load libgp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(the compiler has no other implementation to fall back to)")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "gp_last_error": ([], ctypes.c_char_p),
+        "gp_bounds_from_circuit": ([ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(GpBounds)], ctypes.c_int),
+        "gp_driver_create": ([ctypes.POINTER(GpBounds), ctypes.c_int, ctypes.POINTER(_vp)], ctypes.c_int),
+        "gp_driver_create_from_circuit": ([ctypes.c_char_p, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_vp)],
+                                          ctypes.c_int),
+        "gp_driver_destroy": ([_vp], None),
+        "gp_compile_hypergraph": ([_vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.c_size_t, ctypes.POINTER(_vp)], ctypes.c_int),
+        "gp_lower": ([_vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
+                     ctypes.c_int),
+        "gp_run": ([_vp], ctypes.c_int),
+        "gp_fetch": ([_vp, ctypes.POINTER(_vp)], ctypes.c_int),
+        "gp_sync": ([_vp], ctypes.c_int),
+        "gp_driver_stream": ([_vp], _vp),
+        "gp_circuit_info_get": ([_vp, ctypes.POINTER(GpCircuitInfo)], ctypes.c_int),
+        "gp_set_timing": ([_vp, ctypes.c_int], ctypes.c_int),
+        "gp_reset_timing": ([_vp], ctypes.c_int),
+        "gp_timing_count": ([_vp], ctypes.c_int),
+        "gp_timing_entry": ([_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(_u64)], ctypes.c_int),
+        "gp_edges_count": ([_vp], _u64),
+        "gp_edges_detectors": ([_vp], ctypes.c_uint32),
+        "gp_edges_observables": ([_vp], ctypes.c_uint32),
+        "gp_edges_offsets": ([_vp], ctypes.POINTER(_u64)),
+        "gp_edges_bits": ([_vp], ctypes.POINTER(ctypes.c_uint32)),
+        "gp_edges_probabilities": ([_vp], ctypes.POINTER(ctypes.c_double)),
+        "gp_edges_to_dem_text": ([_vp, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_size_t)],
+                                 ctypes.c_int),
+        "gp_edges_free": ([_vp], None),
+        "gp_free": ([_vp], None),
+        "gp_debug_set_key_bits": ([_vp, ctypes.c_int], ctypes.c_int),
+        "gp_debug_collision_retries": ([_vp], _u64),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int) -> None:
+    if rc != GP_OK:
+        raise GpError(rc, load().gp_last_error().decode(errors="replace"))
+
+
+def _rates(rates: Optional[Sequence[float]]):
+    if rates is None:
+        return None, 0, None
+    arr = np.ascontiguousarray(rates, dtype=np.float64)
+    return arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(arr), arr
+
+
+# ---------------------------------------------------------------- functions
+
+def gp_last_error() -> str:
+    return load().gp_last_error().decode(errors="replace")
+
+
+def gp_bounds_from_circuit(text: str) -> GpBounds:
+    raw = text.encode()
+    b = GpBounds()
+    _check(load().gp_bounds_from_circuit(raw, len(raw), ctypes.byref(b)))
+    return b
+
+
+def gp_driver_create(bounds: GpBounds, device: int = 0) -> int:
+    h = _vp()
+    _check(load().gp_driver_create(ctypes.byref(bounds), device, ctypes.byref(h)))
+    return h.value
+
+
+def gp_driver_create_from_circuit(text: str, device: int = 0) -> int:
+    raw = text.encode()
+    h = _vp()
+    _check(load().gp_driver_create_from_circuit(raw, len(raw), device, ctypes.byref(h)))
+    return h.value
+
+
+def gp_driver_destroy(drv: int) -> None:
+    load().gp_driver_destroy(drv)
+
+
+def gp_compile_hypergraph(drv: int, text: str, rates: Optional[Sequence[float]] = None) -> int:
+    raw = text.encode()
+    rp, nr, _keep = _rates(rates)
+    h = _vp()
+    _check(load().gp_compile_hypergraph(drv, raw, len(raw), rp, nr, ctypes.byref(h)))
+    return h.value
+
+
+def gp_lower(drv: int, text: str, rates: Optional[Sequence[float]] = None) -> None:
+    raw = text.encode()
+    rp, nr, _keep = _rates(rates)
+    _check(load().gp_lower(drv, raw, len(raw), rp, nr))
+
+
+def gp_run(drv: int) -> None:
+    _check(load().gp_run(drv))
+
+
+def gp_fetch(drv: int) -> int:
+    h = _vp()
+    _check(load().gp_fetch(drv, ctypes.byref(h)))
+    return h.value
+
+
+def gp_sync(drv: int) -> None:
+    _check(load().gp_sync(drv))
+
+
+def gp_driver_stream(drv: int) -> int:
+    return load().gp_driver_stream(drv) or 0
+
+
+def gp_circuit_info_get(drv: int) -> GpCircuitInfo:
+    i = GpCircuitInfo()
+    _check(load().gp_circuit_info_get(drv, ctypes.byref(i)))
+    return i
+
+
+def gp_set_timing(drv: int, enable: bool) -> None:
+    _check(load().gp_set_timing(drv, int(enable)))
+
+
+def gp_reset_timing(drv: int) -> None:
+    _check(load().gp_reset_timing(drv))
+
+
+def gp_timing_count(drv: int) -> int:
+    return load().gp_timing_count(drv)
+
+
+def gp_timing_entry(drv: int, index: int) -> Tuple[str, float, int]:
+    name = ctypes.c_char_p()
+    ms = ctypes.c_double()
+    n = _u64()
+    _check(load().gp_timing_entry(drv, index, ctypes.byref(name), ctypes.byref(ms), ctypes.byref(n)))
+    return name.value.decode(), ms.value, n.value
+
+
+def gp_edges_count(e: int) -> int:
+    return int(load().gp_edges_count(e))
+
+
+def gp_edges_detectors(e: int) -> int:
+    return int(load().gp_edges_detectors(e))
+
+
+def gp_edges_observables(e: int) -> int:
+    return int(load().gp_edges_observables(e))
+
+
+def gp_edges_offsets(e: int) -> np.ndarray:
+    n = gp_edges_count(e) + 1
+    return np.ctypeslib.as_array(load().gp_edges_offsets(e), shape=(n,)).copy()
+
+
+def gp_edges_bits(e: int) -> np.ndarray:
+    off = gp_edges_offsets(e)
+    nb = int(off[-1])
+    if nb == 0:
+        return np.zeros(0, dtype=np.uint32)
+    return np.ctypeslib.as_array(load().gp_edges_bits(e), shape=(nb,)).copy()
+
+
+def gp_edges_probabilities(e: int) -> np.ndarray:
+    n = gp_edges_count(e)
+    if n == 0:
+        return np.zeros(0, dtype=np.float64)
+    return np.ctypeslib.as_array(load().gp_edges_probabilities(e), shape=(n,)).copy()
+
+
+def gp_edges_to_dem_text(e: int) -> str:
+    p = ctypes.c_void_p()
+    n = ctypes.c_size_t()
+    _check(load().gp_edges_to_dem_text(e, ctypes.byref(p), ctypes.byref(n)))
+    try:
+        return ctypes.string_at(p.value, n.value).decode() if n.value else ""
+    finally:
+        load().gp_free(p)
+
+
+def gp_edges_free(e: int) -> None:
+    load().gp_edges_free(e)
+
+
+def gp_debug_set_key_bits(drv: int, bits: int) -> None:
+    _check(load().gp_debug_set_key_bits(drv, bits))
+
+
+def gp_debug_collision_retries(drv: int) -> int:
+    return int(load().gp_debug_collision_retries(drv))

@@ -1,0 +1,125 @@
+"""Python face of the compiler, shaped like the paper's Listing 1 (Sec. 3.4):
+a driver built from a maximum circuit reuses its device buffers for every
+circuit within those bounds.
+
+    drv = get_driver(max_circuit_text)
+    dem = drv.compile_detector_error_model(circuit_text)
+    hg = drv.compile_hypergraph(circuit_text, rates)   # arrays of the edges
+"""
+
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import _gp
+
+
+@dataclasses.dataclass
+class Hypergraph:
+    """Hyperedge e: bits[offsets[e]:offsets[e+1]] (detector b < n_detectors,
+    else observable b - n_detectors) with probability q[e]."""
+    n_detectors: int
+    n_observables: int
+    offsets: np.ndarray
+    bits: np.ndarray
+    q: np.ndarray
+
+    def __len__(self) -> int:
+        return len(self.q)
+
+    def edges(self) -> Dict[Tuple[int, ...], float]:
+        out = {}
+        for e in range(len(self.q)):
+            out[tuple(int(x) for x in self.bits[self.offsets[e]:self.offsets[e + 1]])] = float(self.q[e])
+        return out
+
+
+def _take(handle: int) -> Hypergraph:
+    try:
+        return Hypergraph(
+            n_detectors=_gp.gp_edges_detectors(handle),
+            n_observables=_gp.gp_edges_observables(handle),
+            offsets=_gp.gp_edges_offsets(handle),
+            bits=_gp.gp_edges_bits(handle),
+            q=_gp.gp_edges_probabilities(handle),
+        )
+    finally:
+        _gp.gp_edges_free(handle)
+
+
+class Driver:
+    """Owns one gp_driver (device buffers + stream) on one HIP device."""
+
+    def __init__(self, bounds: _gp.GpBounds, device: int = 0):
+        self.bounds = bounds
+        self.handle = _gp.gp_driver_create(bounds, device)
+
+    @classmethod
+    def from_circuit(cls, max_circuit: str, device: int = 0) -> "Driver":
+        return cls(_gp.gp_bounds_from_circuit(max_circuit), device)
+
+    def close(self) -> None:
+        if self.handle:
+            _gp.gp_driver_destroy(self.handle)
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # whole path
+    def compile_hypergraph(self, circuit: str, rates: Optional[Sequence[float]] = None) -> Hypergraph:
+        return _take(_gp.gp_compile_hypergraph(self.handle, circuit, rates))
+
+    def compile_detector_error_model(self, circuit: str, rates: Optional[Sequence[float]] = None) -> str:
+        h = _gp.gp_compile_hypergraph(self.handle, circuit, rates)
+        try:
+            return _gp.gp_edges_to_dem_text(h)
+        finally:
+            _gp.gp_edges_free(h)
+
+    # split path
+    def lower(self, circuit: str, rates: Optional[Sequence[float]] = None) -> None:
+        _gp.gp_lower(self.handle, circuit, rates)
+
+    def run(self) -> None:
+        _gp.gp_run(self.handle)
+
+    def sync(self) -> None:
+        _gp.gp_sync(self.handle)
+
+    def fetch(self) -> Hypergraph:
+        return _take(_gp.gp_fetch(self.handle))
+
+    def info(self) -> dict:
+        return _gp.gp_circuit_info_get(self.handle).as_dict()
+
+    def set_timing(self, enable: bool) -> None:
+        _gp.gp_set_timing(self.handle, enable)
+
+    def reset_timing(self) -> None:
+        _gp.gp_reset_timing(self.handle)
+
+    def timing(self) -> Dict[str, Tuple[float, int]]:
+        out = {}
+        for k in range(_gp.gp_timing_count(self.handle)):
+            name, ms, n = _gp.gp_timing_entry(self.handle, k)
+            if n:
+                out[name] = (ms, n)
+        return out
+
+
+def get_driver(max_circuit: str, device: int = 0) -> Driver:
+    """Listing 1: a driver whose buffers are sized for `max_circuit`."""
+    return Driver.from_circuit(max_circuit, device)

@@ -1,0 +1,592 @@
+// C ABI of the compiler: driver lifetime, buffers sized from bounds (paper
+// Sec. 3.4), host lowering + upload, device stages, result download.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cinttypes>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gp.h"
+#include "kernels.h"
+#include "lower.h"
+
+namespace {
+
+thread_local std::string g_error = "no error";
+
+int fail(int code, const std::string& msg) {
+  g_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(GP_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                          \
+  do {                                               \
+    hipError_t _e = (expr);                          \
+    if (_e != hipSuccess) return hip_fail(_e, what); \
+  } while (0)
+
+constexpr uint32_t kObsChunkFaults = 65536;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+uint32_t words_for(uint32_t det, uint32_t obs) { return (det + 63) / 64 + (obs + 63) / 64; }
+
+// Layout of the per-circuit input tables inside one device arena and one
+// pinned host buffer of the same shape, so one copy uploads them all.
+struct TableLayout {
+  size_t ops, layer_off, leaf_off, leaf_bits, chan_qa, chan_qb, chan_kind, chan_rate, chan_foff, bnd_chan_off,
+      bnd_fault_off, col_top, col_lo, col_base, item_col, item_blo, item_bhi, fnv_pow, total;
+};
+
+TableLayout layout_for(uint64_t ops, uint32_t layers, uint32_t meas, uint64_t leaf_bits, uint64_t chans, uint32_t w,
+                       uint64_t items) {
+  TableLayout t{};
+  size_t o = 0;
+  auto take = [&](size_t& f, size_t bytes) {
+    f = o;
+    o += align_up(bytes ? bytes : 1);
+  };
+  take(t.ops, ops * 8);
+  take(t.layer_off, (size_t(layers) + 1) * 4);
+  take(t.leaf_off, (size_t(meas) + 1) * 4);
+  take(t.leaf_bits, leaf_bits * 4);
+  take(t.chan_qa, chans * 4);
+  take(t.chan_qb, chans * 4);
+  take(t.chan_kind, chans);
+  take(t.chan_rate, chans * 8);
+  take(t.chan_foff, (chans + 1) * 4);
+  take(t.bnd_chan_off, (size_t(layers) + 2) * 4);
+  take(t.bnd_fault_off, (size_t(layers) + 2) * 4);
+  take(t.col_top, size_t(w) * 4);
+  take(t.col_lo, size_t(w) * 4);
+  take(t.col_base, size_t(w) * 8);
+  take(t.item_col, items * 4);
+  take(t.item_blo, items * 4);
+  take(t.item_bhi, items * 4);
+  take(t.fnv_pow, (size_t(w) + 1) * 8);
+  t.total = o;
+  return t;
+}
+
+struct TimedLaunch {
+  int id;
+  hipEvent_t a, b;
+};
+
+}  // namespace
+
+struct gp_edges {
+  uint32_t n_det = 0, n_obs = 0;
+  std::vector<uint64_t> off;
+  std::vector<uint32_t> bits;
+  std::vector<double> q;
+};
+
+struct gp_driver {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  gp_bounds bounds{};
+  uint32_t max_w = 1;
+  uint64_t bits_cap = 0;
+  uint32_t max_tiles = 1;
+
+  std::vector<void*> allocations;
+  char* d_tables = nullptr;
+  size_t tables_cap = 0;
+  char* h_tables = nullptr;  // pinned
+  void* h_out = nullptr;     // pinned download staging
+  size_t h_out_cap = 0;
+  gp::DevHeader* h_hdr = nullptr;  // pinned
+
+  gp::Lowered lw;
+  bool lowered = false;
+  bool ran = false;
+  gp::DevState st{};
+
+  uint32_t key_bits = 64;      // test hook: class keys cut to this many bits
+  uint64_t collision_retries = 0;
+
+  bool timing = false;
+  std::vector<hipEvent_t> ev_free;
+  std::vector<TimedLaunch> pending;
+  double total_ms[gp::K_COUNT] = {};
+  uint64_t launches[gp::K_COUNT] = {};
+};
+
+namespace {
+
+template <typename T>
+int dev_alloc(gp_driver* d, T** p, size_t count, const char* what) {
+  void* v = nullptr;
+  hipError_t e = hipMalloc(&v, std::max<size_t>(count * sizeof(T), 256));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? GP_E_OOM : GP_E_HIP,
+                std::string("device allocation of ") + what + " failed: " + hipGetErrorString(e));
+  }
+  d->allocations.push_back(v);
+  *p = static_cast<T*>(v);
+  return GP_OK;
+}
+
+void hook_before(void* ctx, int id) {
+  gp_driver* d = static_cast<gp_driver*>(ctx);
+  TimedLaunch t{id, nullptr, nullptr};
+  for (hipEvent_t* e : {&t.a, &t.b}) {
+    if (!d->ev_free.empty()) {
+      *e = d->ev_free.back();
+      d->ev_free.pop_back();
+    } else if (hipEventCreate(e) != hipSuccess) {
+      *e = nullptr;
+    }
+  }
+  if (t.a) (void)hipEventRecord(t.a, d->stream);
+  d->pending.push_back(t);
+}
+
+void hook_after(void* ctx, int) {
+  gp_driver* d = static_cast<gp_driver*>(ctx);
+  if (!d->pending.empty() && d->pending.back().b) (void)hipEventRecord(d->pending.back().b, d->stream);
+}
+
+void collect_timing(gp_driver* d) {
+  for (TimedLaunch& t : d->pending) {
+    float ms = 0.f;
+    if (t.a && t.b && hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+      d->total_ms[t.id] += ms;
+      d->launches[t.id]++;
+    }
+    if (t.a) d->ev_free.push_back(t.a);
+    if (t.b) d->ev_free.push_back(t.b);
+  }
+  d->pending.clear();
+}
+
+int check_bounds(const gp_driver* d, const gp::Lowered& lw) {
+  const gp_bounds& b = d->bounds;
+  char msg[256];
+  auto over = [&](const char* what, uint64_t have, uint64_t cap) {
+    std::snprintf(msg, sizeof msg, "circuit exceeds the driver bounds: %s %" PRIu64 " > %" PRIu64, what, have, cap);
+    return fail(GP_E_BOUNDS, msg);
+  };
+  if (lw.n_qubits > b.max_qubits) return over("qubits", lw.n_qubits, b.max_qubits);
+  if (lw.n_layers > b.max_layers) return over("layers", lw.n_layers, b.max_layers);
+  if (lw.n_meas > b.max_measurements) return over("measurements", lw.n_meas, b.max_measurements);
+  if (lw.n_det > b.max_detectors) return over("detectors", lw.n_det, b.max_detectors);
+  if (lw.n_obs > b.max_observables) return over("observables", lw.n_obs, b.max_observables);
+  if (lw.chan_kind.size() > b.max_channels) return over("channels", lw.chan_kind.size(), b.max_channels);
+  if (lw.n_faults > b.max_faults) return over("faults", lw.n_faults, b.max_faults);
+  if (lw.ops.size() > b.max_ops) return over("operations", lw.ops.size(), b.max_ops);
+  if (lw.leaf_bits.size() > b.max_leaf_bits) return over("leaf bits", lw.leaf_bits.size(), b.max_leaf_bits);
+  if (lw.slab_words > b.max_slab_words) return over("slab words", lw.slab_words, b.max_slab_words);
+  if (lw.item_col.size() > b.max_items) return over("sweep items", lw.item_col.size(), b.max_items);
+  if (lw.w > d->max_w) return over("signature words", lw.w, d->max_w);
+  if (gp::sweep_lds_bytes(lw.n_qubits) > gp::sweep_lds_limit())
+    return over("LDS bytes for the qubit frame", gp::sweep_lds_bytes(lw.n_qubits), gp::sweep_lds_limit());
+  return GP_OK;
+}
+
+void fill_bounds(const gp::Lowered& lw, gp_bounds* out) {
+  gp_bounds b{};
+  b.max_qubits = lw.n_qubits;
+  b.max_layers = lw.n_layers;
+  b.max_measurements = lw.n_meas;
+  b.max_detectors = lw.n_det;
+  b.max_observables = lw.n_obs;
+  b.max_channels = uint32_t(lw.chan_kind.size());
+  b.max_faults = lw.n_faults;
+  b.max_ops = lw.ops.size();
+  b.max_leaf_bits = lw.leaf_bits.size();
+  // any circuit within these bounds needs at most one word per (fault, column)
+  b.max_slab_words = std::max<uint64_t>(lw.slab_words, lw.n_faults * uint64_t(lw.w));
+  b.max_items = uint64_t(lw.w) + (lw.n_faults / kObsChunkFaults + 2) * uint64_t((lw.n_obs + 63) / 64) + 16;
+  *out = b;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gp_last_error(void) { return g_error.c_str(); }
+
+int gp_bounds_from_circuit(const char* text, size_t len, gp_bounds* out) {
+  if (!text || !out) return fail(GP_E_ARG, "null argument");
+  gp::Lowered lw;
+  gp::LowerError err{};
+  int rc = gp::lower_circuit(text, len, nullptr, 0, kObsChunkFaults, lw, err);
+  if (rc) return fail(rc, err.msg);
+  fill_bounds(lw, out);
+  return GP_OK;
+}
+
+void gp_driver_destroy(gp_driver* d) {
+  if (!d) return;
+  (void)hipSetDevice(d->device);
+  if (d->stream) (void)hipStreamSynchronize(d->stream);
+  for (void* p : d->allocations) (void)hipFree(p);
+  if (d->h_tables) (void)hipHostFree(d->h_tables);
+  if (d->h_out) (void)hipHostFree(d->h_out);
+  if (d->h_hdr) (void)hipHostFree(d->h_hdr);
+  for (TimedLaunch& t : d->pending) {
+    if (t.a) (void)hipEventDestroy(t.a);
+    if (t.b) (void)hipEventDestroy(t.b);
+  }
+  for (hipEvent_t e : d->ev_free) (void)hipEventDestroy(e);
+  if (d->stream) (void)hipStreamDestroy(d->stream);
+  delete d;
+}
+
+int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
+  if (!bounds || !out) return fail(GP_E_ARG, "null argument");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+    (void)hipGetLastError();
+    return fail(GP_E_HIP, "no HIP device available");
+  }
+  if (device < 0 || device >= ndev) return fail(GP_E_ARG, "device index out of range");
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, device), "hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(GP_E_HIP, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
+  HIP_TRY(hipSetDevice(device), "hipSetDevice");
+  HIP_TRY(gp::configure_kernels(), "configure kernels");
+
+  gp_driver* d = new gp_driver();
+  d->device = device;
+  d->bounds = *bounds;
+  gp_bounds& b = d->bounds;
+  b.max_layers = std::max<uint32_t>(b.max_layers, 1);
+  b.max_faults = std::max<uint64_t>(b.max_faults, 1);
+  if (b.max_faults >= (1ull << 32)) {
+    delete d;
+    return fail(GP_E_BOUNDS, "at most 2^32 - 1 faults per circuit");
+  }
+  d->max_w = std::max<uint32_t>(words_for(b.max_detectors, b.max_observables), 1);
+  if (!b.max_slab_words) b.max_slab_words = b.max_faults * d->max_w;
+  if (!b.max_items) b.max_items = uint64_t(d->max_w) + (b.max_faults / kObsChunkFaults + 2) * ((b.max_observables + 63) / 64) + 16;
+  d->bits_cap = std::max<uint64_t>(b.max_faults * 8, 1u << 20);
+  d->max_tiles = uint32_t((b.max_faults + 4095) / 4096) + 1;
+
+  int rc = GP_OK;
+  auto cleanup = [&](int code) {
+    gp_driver_destroy(d);
+    return code;
+  };
+  if (hipStreamCreateWithFlags(&d->stream, hipStreamNonBlocking) != hipSuccess)
+    return cleanup(hip_fail(hipGetLastError(), "hipStreamCreate"));
+
+  TableLayout tl = layout_for(b.max_ops, b.max_layers, b.max_measurements, b.max_leaf_bits, b.max_channels, d->max_w,
+                              b.max_items);
+  d->tables_cap = tl.total;
+  if ((rc = dev_alloc(d, &d->d_tables, d->tables_cap, "tables"))) return cleanup(rc);
+  if (hipHostMalloc(reinterpret_cast<void**>(&d->h_tables), d->tables_cap, hipHostMallocDefault) != hipSuccess)
+    return cleanup(fail(GP_E_OOM, "pinned host allocation failed"));
+  if (hipHostMalloc(reinterpret_cast<void**>(&d->h_hdr), sizeof(gp::DevHeader), hipHostMallocDefault) != hipSuccess)
+    return cleanup(fail(GP_E_OOM, "pinned host allocation failed"));
+
+  gp::DevState& st = d->st;
+  const uint64_t F = b.max_faults;
+  uint64_t* slab = nullptr;
+  if ((rc = dev_alloc(d, &slab, b.max_slab_words, "signature slab"))) return cleanup(rc);
+  st.slab = slab;
+  if ((rc = dev_alloc(d, &st.cover_lo, d->max_w, "cover_lo"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.cov, (size_t(b.max_layers) + 1) * d->max_w, "cover lists"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.ncov, size_t(b.max_layers) + 1, "cover counts"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.pfault, F, "fault probabilities"))) return cleanup(rc);
+  for (int k = 0; k < 2; k++) {
+    if ((rc = dev_alloc(d, &st.key[k], F, "keys"))) return cleanup(rc);
+    if ((rc = dev_alloc(d, &st.val[k], F, "values"))) return cleanup(rc);
+  }
+  if ((rc = dev_alloc(d, &st.chk, F, "check hashes"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.hist, size_t(256) * d->max_tiles, "histograms"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.tile_sum, size_t(d->max_tiles) + 1, "tile sums"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.segstart, F, "class starts"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.seg_q, F, "class probabilities"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.seg_rep, F, "class representatives"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.seg_cnt, F, "class bit counts"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.seg_off, F, "class bit offsets"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.edge_off32, F + 1, "edge offsets"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.edge_bits, d->bits_cap, "edge bits"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.edge_q, F, "edge probabilities"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.hdr, 1, "header"))) return cleanup(rc);
+  st.bits_cap = d->bits_cap;
+  // download staging: offsets + bits + probabilities of the largest result
+  d->h_out_cap = (F + 1) * 4 + d->bits_cap * 4 + F * 8 + 3 * kAlign;
+  if (hipHostMalloc(&d->h_out, d->h_out_cap, hipHostMallocDefault) != hipSuccess)
+    return cleanup(fail(GP_E_OOM, "pinned host allocation failed"));
+  *out = d;
+  return GP_OK;
+}
+
+int gp_driver_create_from_circuit(const char* text, size_t len, int device, gp_driver** out) {
+  gp_bounds b;
+  int rc = gp_bounds_from_circuit(text, len, &b);
+  if (rc) return rc;
+  return gp_driver_create(&b, device, out);
+}
+
+int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, size_t n_rates) {
+  if (!d || !text) return fail(GP_E_ARG, "null argument");
+  gp::LowerError err{};
+  d->lowered = false;
+  d->ran = false;
+  int rc = gp::lower_circuit(text, len, rates, n_rates, kObsChunkFaults, d->lw, err);
+  if (rc) return fail(rc, err.msg);
+  if ((rc = check_bounds(d, d->lw))) return rc;
+  const gp::Lowered& lw = d->lw;
+  HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
+  // the previous compile may still read the pinned buffer
+  HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
+  TableLayout tl = layout_for(lw.ops.size(), lw.n_layers, lw.n_meas, lw.leaf_bits.size(), lw.chan_kind.size(), lw.w,
+                              lw.item_col.size());
+  if (tl.total > d->tables_cap) return fail(GP_E_BOUNDS, "lowered tables exceed the driver's table arena");
+  char* h = d->h_tables;
+  auto put = [&](size_t off, const void* src, size_t bytes) {
+    if (bytes) std::memcpy(h + off, src, bytes);
+  };
+  put(tl.ops, lw.ops.data(), lw.ops.size() * 8);
+  put(tl.layer_off, lw.layer_off.data(), lw.layer_off.size() * 4);
+  put(tl.leaf_off, lw.leaf_off.data(), lw.leaf_off.size() * 4);
+  put(tl.leaf_bits, lw.leaf_bits.data(), lw.leaf_bits.size() * 4);
+  put(tl.chan_qa, lw.chan_qa.data(), lw.chan_qa.size() * 4);
+  put(tl.chan_qb, lw.chan_qb.data(), lw.chan_qb.size() * 4);
+  put(tl.chan_kind, lw.chan_kind.data(), lw.chan_kind.size());
+  put(tl.chan_rate, lw.chan_rate.data(), lw.chan_rate.size() * 8);
+  put(tl.chan_foff, lw.chan_foff.data(), lw.chan_foff.size() * 4);
+  put(tl.bnd_chan_off, lw.bnd_chan_off.data(), lw.bnd_chan_off.size() * 4);
+  put(tl.bnd_fault_off, lw.bnd_fault_off.data(), lw.bnd_fault_off.size() * 4);
+  put(tl.col_top, lw.col_top.data(), lw.col_top.size() * 4);
+  put(tl.col_lo, lw.col_lo.data(), lw.col_lo.size() * 4);
+  put(tl.col_base, lw.col_base.data(), lw.col_base.size() * 8);
+  put(tl.item_col, lw.item_col.data(), lw.item_col.size() * 4);
+  put(tl.item_blo, lw.item_blo.data(), lw.item_blo.size() * 4);
+  put(tl.item_bhi, lw.item_bhi.data(), lw.item_bhi.size() * 4);
+  put(tl.fnv_pow, lw.fnv_pow.data(), lw.fnv_pow.size() * 8);
+  HIP_TRY(hipMemcpyAsync(d->d_tables, d->h_tables, tl.total, hipMemcpyHostToDevice, d->stream), "upload tables");
+
+  gp::DevState& st = d->st;
+  char* D = d->d_tables;
+  st.ops = reinterpret_cast<const uint64_t*>(D + tl.ops);
+  st.layer_off = reinterpret_cast<const uint32_t*>(D + tl.layer_off);
+  st.leaf_off = reinterpret_cast<const uint32_t*>(D + tl.leaf_off);
+  st.leaf_bits = reinterpret_cast<const uint32_t*>(D + tl.leaf_bits);
+  st.chan_qa = reinterpret_cast<const uint32_t*>(D + tl.chan_qa);
+  st.chan_qb = reinterpret_cast<const uint32_t*>(D + tl.chan_qb);
+  st.chan_kind = reinterpret_cast<const uint8_t*>(D + tl.chan_kind);
+  st.chan_rate = reinterpret_cast<const double*>(D + tl.chan_rate);
+  st.chan_foff = reinterpret_cast<const uint32_t*>(D + tl.chan_foff);
+  st.bnd_chan_off = reinterpret_cast<const uint32_t*>(D + tl.bnd_chan_off);
+  st.bnd_fault_off = reinterpret_cast<const uint32_t*>(D + tl.bnd_fault_off);
+  st.col_top = reinterpret_cast<const int32_t*>(D + tl.col_top);
+  st.col_lo = reinterpret_cast<const int32_t*>(D + tl.col_lo);
+  st.col_base = reinterpret_cast<const uint64_t*>(D + tl.col_base);
+  st.item_col = reinterpret_cast<const uint32_t*>(D + tl.item_col);
+  st.item_blo = reinterpret_cast<const uint32_t*>(D + tl.item_blo);
+  st.item_bhi = reinterpret_cast<const uint32_t*>(D + tl.item_bhi);
+  st.fnv_pow = reinterpret_cast<const uint64_t*>(D + tl.fnv_pow);
+  st.n_qubits = lw.n_qubits;
+  st.n_layers = lw.n_layers;
+  st.n_det = lw.n_det;
+  st.wd = lw.wd;
+  st.w = lw.w;
+  st.n_chan = uint32_t(lw.chan_kind.size());
+  st.n_items = uint32_t(lw.item_col.size());
+  st.n_faults = uint32_t(lw.n_faults);
+  d->lowered = true;
+  return GP_OK;
+}
+
+int gp_run(gp_driver* d) {
+  if (!d) return fail(GP_E_ARG, "null driver");
+  if (!d->lowered) return fail(GP_E_STATE, "gp_run before gp_lower");
+  HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
+  gp::LaunchHook hook;
+  if (d->timing) {
+    hook.before = hook_before;
+    hook.after = hook_after;
+    hook.ctx = d;
+  }
+  d->st.key_mode = 0;
+  d->st.key_bits = d->key_bits;
+  hipError_t e = gp::enqueue_compile(d->st, d->stream, hook);
+  if (e != hipSuccess) return hip_fail(e, "kernel launch");
+  d->ran = true;
+  return GP_OK;
+}
+
+int gp_sync(gp_driver* d) {
+  if (!d) return fail(GP_E_ARG, "null driver");
+  HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
+  HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
+  collect_timing(d);
+  return GP_OK;
+}
+
+int gp_fetch(gp_driver* d, gp_edges** out) {
+  if (!d || !out) return fail(GP_E_ARG, "null argument");
+  *out = nullptr;
+  if (!d->ran) return fail(GP_E_STATE, "gp_fetch before gp_run");
+  HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
+  HIP_TRY(hipMemcpyAsync(d->h_hdr, d->st.hdr, sizeof(gp::DevHeader), hipMemcpyDeviceToHost, d->stream),
+          "download header");
+  HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
+  collect_timing(d);
+  gp::DevHeader hdr = *d->h_hdr;
+  if ((hdr.flags & gp::FLAG_COLLISION) && !(hdr.flags & gp::FLAG_GAUGE)) {
+    // two signatures met under one key: compile again keyed on both hashes
+    d->collision_retries++;
+    d->st.key_mode = 1;
+    gp::LaunchHook none;
+    hipError_t e = gp::enqueue_compile(d->st, d->stream, none);
+    d->st.key_mode = 0;
+    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    HIP_TRY(hipMemcpyAsync(d->h_hdr, d->st.hdr, sizeof(gp::DevHeader), hipMemcpyDeviceToHost, d->stream),
+            "download header");
+    HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
+    hdr = *d->h_hdr;
+  }
+  if (hdr.flags & gp::FLAG_GAUGE)
+    return fail(GP_E_NONDETERMINISTIC,
+                "a detector or observable is sensitive to an error right after a reset or measurement "
+                "(or at the start), so it is not deterministic");
+  if (hdr.flags & gp::FLAG_COLLISION)
+    return fail(GP_E_COLLISION, "two different signatures share both 64-bit hashes");
+  if ((hdr.flags & gp::FLAG_OVERFLOW) || hdr.n_bits > d->bits_cap)
+    return fail(GP_E_BOUNDS, "hyperedge signature bits exceed the driver's output capacity");
+  const uint64_t U = hdr.n_edges;
+  const uint64_t nb = hdr.n_bits;
+  char* h = static_cast<char*>(d->h_out);
+  const size_t o_off = 0, o_bits = align_up((U + 1) * 4), o_q = o_bits + align_up(nb * 4);
+  if (o_q + U * 8 > d->h_out_cap) return fail(GP_E_BOUNDS, "result exceeds the download staging buffer");
+  HIP_TRY(hipMemcpyAsync(h + o_off, d->st.edge_off32, (U + 1) * 4, hipMemcpyDeviceToHost, d->stream), "download");
+  if (nb) HIP_TRY(hipMemcpyAsync(h + o_bits, d->st.edge_bits, nb * 4, hipMemcpyDeviceToHost, d->stream), "download");
+  if (U) HIP_TRY(hipMemcpyAsync(h + o_q, d->st.edge_q, U * 8, hipMemcpyDeviceToHost, d->stream), "download");
+  HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
+  gp_edges* e = new gp_edges();
+  e->n_det = d->lw.n_det;
+  e->n_obs = d->lw.n_obs;
+  e->off.resize(U + 1);
+  const uint32_t* off32 = reinterpret_cast<const uint32_t*>(h + o_off);
+  for (uint64_t i = 0; i <= U; i++) e->off[i] = off32[i];
+  e->bits.assign(reinterpret_cast<const uint32_t*>(h + o_bits), reinterpret_cast<const uint32_t*>(h + o_bits) + nb);
+  e->q.assign(reinterpret_cast<const double*>(h + o_q), reinterpret_cast<const double*>(h + o_q) + U);
+  *out = e;
+  return GP_OK;
+}
+
+int gp_compile_hypergraph(gp_driver* d, const char* text, size_t len, const double* rates, size_t n_rates,
+                          gp_edges** out) {
+  if (!out) return fail(GP_E_ARG, "null argument");
+  int rc = gp_lower(d, text, len, rates, n_rates);
+  if (rc) return rc;
+  if ((rc = gp_run(d))) return rc;
+  return gp_fetch(d, out);
+}
+
+void* gp_driver_stream(gp_driver* d) { return d ? static_cast<void*>(d->stream) : nullptr; }
+
+int gp_circuit_info_get(const gp_driver* d, gp_circuit_info* out) {
+  if (!d || !out) return fail(GP_E_ARG, "null argument");
+  gp_circuit_info i{};
+  const gp::Lowered& lw = d->lw;
+  i.n_qubits = lw.n_qubits;
+  i.n_layers = lw.n_layers;
+  i.n_measurements = lw.n_meas;
+  i.n_detectors = lw.n_det;
+  i.n_observables = lw.n_obs;
+  i.n_words = lw.w;
+  i.n_channels = lw.chan_kind.size();
+  i.n_faults = lw.n_faults;
+  i.n_ops = lw.ops.size();
+  i.n_items = lw.item_col.size();
+  i.slab_words = lw.slab_words;
+  if (d->h_hdr) {
+    i.n_classes = d->h_hdr->n_seg;
+    i.n_edges = d->h_hdr->n_edges;
+    i.n_edge_bits = d->h_hdr->n_bits;
+    i.n_live_words = d->h_hdr->n_words;
+  }
+  *out = i;
+  return GP_OK;
+}
+
+int gp_set_timing(gp_driver* d, int enable) {
+  if (!d) return fail(GP_E_ARG, "null driver");
+  d->timing = enable != 0;
+  return GP_OK;
+}
+
+int gp_reset_timing(gp_driver* d) {
+  if (!d) return fail(GP_E_ARG, "null driver");
+  for (int k = 0; k < gp::K_COUNT; k++) {
+    d->total_ms[k] = 0;
+    d->launches[k] = 0;
+  }
+  return GP_OK;
+}
+
+int gp_timing_count(const gp_driver*) { return gp::K_COUNT; }
+
+int gp_debug_set_key_bits(gp_driver* d, int bits) {
+  if (!d || bits < 1 || bits > 64) return fail(GP_E_ARG, "key bits must be in [1, 64]");
+  d->key_bits = uint32_t(bits);
+  return GP_OK;
+}
+
+uint64_t gp_debug_collision_retries(const gp_driver* d) { return d ? d->collision_retries : 0; }
+
+int gp_timing_entry(const gp_driver* d, int index, const char** name, double* total_ms, uint64_t* launches) {
+  if (!d || index < 0 || index >= gp::K_COUNT) return fail(GP_E_ARG, "bad timing index");
+  if (name) *name = gp::kernel_name(index);
+  if (total_ms) *total_ms = d->total_ms[index];
+  if (launches) *launches = d->launches[index];
+  return GP_OK;
+}
+
+uint64_t gp_edges_count(const gp_edges* e) { return e ? e->q.size() : 0; }
+uint32_t gp_edges_detectors(const gp_edges* e) { return e ? e->n_det : 0; }
+uint32_t gp_edges_observables(const gp_edges* e) { return e ? e->n_obs : 0; }
+const uint64_t* gp_edges_offsets(const gp_edges* e) { return e ? e->off.data() : nullptr; }
+const uint32_t* gp_edges_bits(const gp_edges* e) { return e ? e->bits.data() : nullptr; }
+const double* gp_edges_probabilities(const gp_edges* e) { return e ? e->q.data() : nullptr; }
+
+int gp_edges_to_dem_text(const gp_edges* e, char** text, size_t* len) {
+  if (!e || !text) return fail(GP_E_ARG, "null argument");
+  std::string s;
+  s.reserve(e->q.size() * 32);
+  char buf[64];
+  for (size_t k = 0; k < e->q.size(); k++) {
+    std::snprintf(buf, sizeof buf, "error(%.17g)", e->q[k]);
+    s += buf;
+    for (uint64_t i = e->off[k]; i < e->off[k + 1]; i++) {
+      uint32_t b = e->bits[i];
+      if (b < e->n_det)
+        std::snprintf(buf, sizeof buf, " D%u", b);
+      else
+        std::snprintf(buf, sizeof buf, " L%u", b - e->n_det);
+      s += buf;
+    }
+    s += '\n';
+  }
+  char* out = static_cast<char*>(std::malloc(s.size() + 1));
+  if (!out) return fail(GP_E_OOM, "out of memory");
+  std::memcpy(out, s.data(), s.size() + 1);
+  *text = out;
+  if (len) *len = s.size();
+  return GP_OK;
+}
+
+void gp_edges_free(gp_edges* e) { delete e; }
+void gp_free(void* p) { std::free(p); }
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+// Device stages of the compiler (gfx950). Launch wrappers take device pointers
+// and enqueue on the given stream; none of them synchronises.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gp {
+
+// Device-side status block shared by the kernels of one compile.
+struct DevHeader {
+  uint32_t n_seg;      // classes found after sorting (incl. the empty one)
+  uint32_t empty_seg;  // class index of the empty signature, or 0xFFFFFFFF
+  uint32_t n_edges;    // hyperedges = classes minus the empty one
+  uint32_t flags;      // FLAG_* bits
+  uint64_t n_bits;     // total signature bits over all hyperedges
+  uint64_t n_words;    // stage-1 signature words written (= words the hash reads)
+};
+
+enum : uint32_t {
+  FLAG_GAUGE = 1u,      // a detector/observable is sensitive right after a reset/measurement
+  FLAG_COLLISION = 2u,  // equal 64-bit keys with different check hashes
+  FLAG_OVERFLOW = 4u,   // output signature bits exceed the reserved capacity
+};
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// Everything one compile reads or writes on the device.
+struct DevState {
+  // lowered tables (inputs, uploaded per circuit)
+  const uint64_t* ops;
+  const uint32_t* layer_off;
+  const uint32_t* leaf_off;
+  const uint32_t* leaf_bits;
+  const uint32_t* chan_qa;
+  const uint32_t* chan_qb;
+  const uint8_t* chan_kind;
+  const double* chan_rate;
+  const uint32_t* chan_foff;
+  const uint32_t* bnd_chan_off;
+  const uint32_t* bnd_fault_off;
+  const int32_t* col_top;
+  const int32_t* col_lo;
+  const uint64_t* col_base;
+  const uint32_t* item_col;
+  const uint32_t* item_blo;
+  const uint32_t* item_bhi;
+  const uint64_t* fnv_pow;
+
+  // sizes
+  uint32_t n_qubits, n_layers, n_det, wd, w;
+  uint32_t n_chan, n_items;
+  uint32_t n_faults;
+  // class key: 0 = FNV-1a of the signature (kept to its low key_bits bits);
+  // 1 = FNV-1a mixed with the check hash (used after a key collision)
+  uint32_t key_mode;
+  uint32_t key_bits;
+
+  // work buffers
+  uint64_t* slab;        // stage-1 signature words, column slabs
+  int32_t* cover_lo;     // per column: lowest boundary written
+  uint32_t* cov;         // per boundary: covered columns, ascending ((L+1) x W)
+  uint32_t* ncov;        // per boundary: number of covered columns
+  double* pfault;        // per fault position: probability
+  uint64_t* key[2];      // class key (FNV-1a), ping-pong for the sort
+  uint32_t* val[2];      // fault position, ping-pong for the sort
+  uint64_t* chk;         // per fault position: check hash
+  uint32_t* hist;        // radix digit counts (256 x tiles)
+  uint32_t* tile_sum;    // scan tile sums
+  uint32_t* segstart;    // first sorted index of each class
+  double* seg_q;         // merged probability per class
+  uint32_t* seg_rep;     // representative fault position per class
+  uint32_t* seg_cnt;     // signature bits per class (0 for the empty class)
+  uint32_t* seg_off;     // exclusive prefix of seg_cnt
+  uint32_t* edge_off32;  // per hyperedge: first bit (n_edges + 1)
+  uint32_t* edge_bits;   // output signature bits (external numbering)
+  double* edge_q;        // output probabilities
+  uint64_t bits_cap;
+  DevHeader* hdr;
+};
+
+// Names of the kernels, in launch order of one compile (for timing tables).
+enum KernelId : int {
+  K_PREPARE = 0, K_SWEEP, K_COVER, K_HASH, K_RADIX_HIST, K_SCAN_SINGLE, K_RADIX_SCATTER,
+  K_HEADS_COUNT, K_HEADS_APPLY, K_REDUCE, K_SCAN_TILES, K_SCAN_APPLY, K_EDGE_WRITE, K_COUNT
+};
+const char* kernel_name(int id);
+
+// A hook the driver uses to time launches: called before and after each one.
+struct LaunchHook {
+  void (*before)(void* ctx, int kernel_id) = nullptr;
+  void (*after)(void* ctx, int kernel_id) = nullptr;
+  void* ctx = nullptr;
+};
+
+// Enqueue both stages for the lowered circuit described by `st`.
+hipError_t enqueue_compile(const DevState& st, hipStream_t stream, const LaunchHook& hook);
+
+// Dynamic LDS the sweep needs for n qubits, and the largest it may use.
+size_t sweep_lds_bytes(uint32_t n_qubits);
+size_t sweep_lds_limit();
+hipError_t configure_kernels();
+
+}  // namespace gp

@@ -1,0 +1,735 @@
+// Device stages for gfx950 (wave64, 160 KB LDS per CU).
+//
+// Stage 1 (paper Sec. 3.1, Alg. 1, Eq. 1-2): one work item sweeps the layers
+// of the circuit backwards for one 64-bit word column of the class bit
+// vectors. The column's X/Z vertex words of all qubits live in LDS; a layer
+// is applied in place, one thread per operation (the operations of a layer
+// touch disjoint qubits, so their updates are independent). After each layer
+// the faults placed at that boundary read their qubits' words and write their
+// signature word (composite Paulis are XORs of the X and Z words, Sec. 2.3.4)
+// into the column's slab. A column's sweep starts at the highest layer that
+// holds one of its leaves and stops once its frame is all zero below its last
+// leaf: every lower boundary is then zero in that column and is not written.
+//
+// Stage 2 (Sec. 3.2, Eq. 3): per fault, the 64-bit FNV-1a hash of its
+// signature's 8W octets (zero words only multiply by prime^8) as class key and
+// an independent check hash; a stable LSD radix sort of (key, fault) pairs;
+// class heads; merged probabilities q <- q + p(1 - 2q) per class in sorted
+// order; the class with the empty signature is dropped; the remaining classes
+// are written as bit lists. If two faults share a key but not a check hash,
+// the host re-runs the compile keyed on both hashes.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+#include "lower.h"
+
+namespace gp {
+
+namespace {
+
+constexpr int kSweepBlock = 256;
+constexpr int kBlock = 256;
+constexpr int kTile = 4096;          // items per block in sort / scan kernels
+constexpr int kPerThread = kTile / kBlock;
+constexpr int kScanSingleBlock = 1024;
+constexpr uint32_t kBigSegment = 64;  // classes with more faults reduce in a whole block
+
+__device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// Exclusive scan over a block; s_wave needs BLOCK/64 + 1 entries and holds the
+// block total in s_wave[BLOCK/64] on return. Callers barrier before reuse.
+template <int BLOCK>
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* s_wave) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint32_t inc = wave_inclusive_scan(v);
+  if (lane == 63) s_wave[wv] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int k = 0; k < BLOCK / 64; ++k) {
+      uint32_t t = s_wave[k];
+      s_wave[k] = run;
+      run += t;
+    }
+    s_wave[BLOCK / 64] = run;
+  }
+  __syncthreads();
+  return s_wave[wv] + inc - v;
+}
+
+// MurmurHash3's 64-bit finaliser (public domain): a bijective avalanche mix.
+__device__ __forceinline__ uint64_t fmix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+__device__ __forceinline__ uint64_t check_term(uint32_t w, uint64_t v) {
+  return fmix64(v + 0x9E3779B97F4A7C15ull * (uint64_t(w) + 1));
+}
+
+// Per-fault probability of one Pauli of a channel (see gp.h): the p with
+// (1-2p)^k = 1 - x, i.e. p = -expm1(log1p(-x)/k)/2.
+__device__ __forceinline__ double fault_probability(uint32_t kind, double r) {
+  if (kind == CH_DEP1) return -0.5 * expm1(0.5 * log1p(-4.0 * r / 3.0));
+  if (kind == CH_DEP2) return -0.5 * expm1(0.125 * log1p(-16.0 * r / 15.0));
+  return r;
+}
+
+// Boundary b holding fault position pos: bnd_fault_off[b] <= pos < bnd_fault_off[b+1].
+__device__ __forceinline__ uint32_t boundary_of(const uint32_t* off, uint32_t n_bnd, uint32_t pos) {
+  uint32_t lo = 0, hi = n_bnd;  // off has n_bnd + 1 entries
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= pos) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint64_t leaf_word(const uint32_t* leaf_off, const uint32_t* leaf_bits, uint32_t m,
+                                              uint32_t w) {
+  uint64_t v = 0;
+  const uint32_t k1 = leaf_off[m + 1];
+  for (uint32_t k = leaf_off[m]; k < k1; ++k) {
+    const uint32_t b = leaf_bits[k];
+    if ((b >> 6) == w) v |= 1ull << (b & 63);
+  }
+  return v;
+}
+
+// ------------------------------------------------------------------ prepare
+
+__global__ void k_prepare(DevState st) {
+  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid < st.n_chan) {
+    const double p = fault_probability(st.chan_kind[gid], st.chan_rate[gid]);
+    const uint32_t f1 = st.chan_foff[gid + 1];
+    for (uint32_t f = st.chan_foff[gid]; f < f1; ++f) st.pfault[f] = p;
+  }
+  if (gid < st.w) st.cover_lo[gid] = 0;
+  if (gid == 0) {
+    st.hdr->n_seg = 0;
+    st.hdr->empty_seg = kNone;
+    st.hdr->n_edges = 0;
+    st.hdr->flags = 0;
+    st.hdr->n_bits = 0;
+    st.hdr->n_words = 0;
+  }
+}
+
+// ------------------------------------------------------------------ stage 1
+
+__device__ __forceinline__ int nzd(uint64_t nv, uint64_t ov) { return int(nv != 0) - int(ov != 0); }
+
+__global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
+  extern __shared__ uint64_t frame[];  // X_q at 2q, Z_q at 2q+1
+  __shared__ int s_nz;
+  const int tid = threadIdx.x;
+  const uint32_t item = blockIdx.x;
+  const uint32_t w = st.item_col[item];
+  const int top = st.col_top[w];
+  const int clo = st.col_lo[w];
+  const int blo = int(st.item_blo[item]);
+  const int bhi = int(st.item_bhi[item]);
+  uint64_t* out = st.slab + st.col_base[w];
+  const uint32_t nv = 2 * st.n_qubits;
+  for (uint32_t i = tid; i < nv; i += kSweepBlock) frame[i] = 0;
+  if (tid == 0) s_nz = 0;
+  __syncthreads();
+  int gauge = 0;
+  bool dead = false;
+  for (int t = top; t >= blo; --t) {
+    // transform the frame from boundary t+1 to boundary t (one layer, in place)
+    int dnz = 0;
+    const uint32_t o1 = st.layer_off[t + 1];
+    for (uint32_t o = st.layer_off[t] + tid; o < o1; o += kSweepBlock) {
+      const uint64_t op = st.ops[o];
+      const uint32_t kind = uint32_t(op >> 56);
+      const uint32_t a = uint32_t(op >> 28) & uint32_t(kField);
+      const uint32_t b = uint32_t(op) & uint32_t(kField);
+      uint64_t* fa = frame + 2 * a;
+      const uint64_t xa = fa[0], za = fa[1];
+      switch (kind) {
+        case OP_H:
+          fa[0] = za;
+          fa[1] = xa;
+          break;
+        case OP_S: {  // X -> XZ
+          const uint64_t n = xa ^ za;
+          fa[0] = n;
+          dnz += nzd(n, xa);
+          break;
+        }
+        case OP_SQRTX: {  // Z -> XZ
+          const uint64_t n = xa ^ za;
+          fa[1] = n;
+          dnz += nzd(n, za);
+          break;
+        }
+        case OP_CX: {  // X_c -> X_c X_t, Z_t -> Z_t Z_c
+          uint64_t* fb = frame + 2 * b;
+          const uint64_t xb = fb[0], zb = fb[1];
+          const uint64_t nxa = xa ^ xb, nzb = zb ^ za;
+          fa[0] = nxa;
+          fb[1] = nzb;
+          dnz += nzd(nxa, xa) + nzd(nzb, zb);
+          break;
+        }
+        case OP_CZ: {  // X_a -> X_a Z_b, X_b -> X_b Z_a
+          uint64_t* fb = frame + 2 * b;
+          const uint64_t xb = fb[0], zb = fb[1];
+          const uint64_t nxa = xa ^ zb, nxb = xb ^ za;
+          fa[0] = nxa;
+          fb[0] = nxb;
+          dnz += nzd(nxa, xa) + nzd(nxb, xb);
+          break;
+        }
+        case OP_SWAP: {
+          uint64_t* fb = frame + 2 * b;
+          const uint64_t xb = fb[0], zb = fb[1];
+          fa[0] = xb;
+          fa[1] = zb;
+          fb[0] = xa;
+          fb[1] = za;
+          break;
+        }
+        case OP_R:  // a Z error right after a Z reset must be invisible
+          gauge |= za != 0;
+          fa[0] = 0;
+          fa[1] = 0;
+          dnz -= int(xa != 0) + int(za != 0);
+          break;
+        case OP_RX:
+          gauge |= xa != 0;
+          fa[0] = 0;
+          fa[1] = 0;
+          dnz -= int(xa != 0) + int(za != 0);
+          break;
+        case OP_M: {  // X before the measurement flips it (leaf) and persists
+          gauge |= za != 0;
+          const uint64_t n = xa ^ leaf_word(st.leaf_off, st.leaf_bits, b, w);
+          fa[0] = n;
+          dnz += nzd(n, xa);
+          break;
+        }
+        case OP_MX: {
+          gauge |= xa != 0;
+          const uint64_t n = za ^ leaf_word(st.leaf_off, st.leaf_bits, b, w);
+          fa[1] = n;
+          dnz += nzd(n, za);
+          break;
+        }
+        case OP_MR: {  // the reset erases what the measurement did not see
+          gauge |= za != 0;
+          const uint64_t n = leaf_word(st.leaf_off, st.leaf_bits, b, w);
+          fa[0] = n;
+          fa[1] = 0;
+          dnz += nzd(n, xa) - int(za != 0);
+          break;
+        }
+        case OP_MRX: {
+          gauge |= xa != 0;
+          const uint64_t n = leaf_word(st.leaf_off, st.leaf_bits, b, w);
+          fa[1] = n;
+          fa[0] = 0;
+          dnz += nzd(n, za) - int(xa != 0);
+          break;
+        }
+        default:
+          break;
+      }
+    }
+    if (dnz) atomicAdd(&s_nz, dnz);
+    __syncthreads();
+    const int nz = s_nz;
+    // faults at boundary t: signature word = XOR of their Pauli's X/Z words
+    if (t <= bhi) {
+      const uint32_t c1 = st.bnd_chan_off[t + 1];
+      for (uint32_t c = st.bnd_chan_off[t] + tid; c < c1; c += kSweepBlock) {
+        const uint32_t qa = st.chan_qa[c];
+        const uint64_t x0 = frame[2 * qa], z0 = frame[2 * qa + 1];
+        uint64_t* o = out + st.chan_foff[c];
+        switch (st.chan_kind[c]) {
+          case CH_X: o[0] = x0; break;
+          case CH_Y: o[0] = x0 ^ z0; break;
+          case CH_Z: o[0] = z0; break;
+          case CH_DEP1:
+            o[0] = x0;
+            o[1] = x0 ^ z0;
+            o[2] = z0;
+            break;
+          case CH_DEP2: {
+            const uint32_t qb = st.chan_qb[c];
+            const uint64_t x1 = frame[2 * qb], z1 = frame[2 * qb + 1];
+            // Pauli code k = xa | za<<1 | xb<<2 | zb<<3, k = 1..15
+            const uint64_t A[4] = {0, x0, z0, x0 ^ z0};
+            const uint64_t B[4] = {0, x1, z1, x1 ^ z1};
+#pragma unroll
+            for (int k = 1; k < 16; ++k) o[k - 1] = A[k & 3] ^ B[k >> 2];
+            break;
+          }
+          default:
+            break;
+        }
+      }
+    }
+    if (nz == 0 && t <= clo) {
+      // no leaf of this column lies below t and the frame is zero: every lower
+      // boundary is zero in this column
+      if (t <= bhi && tid == 0) st.cover_lo[w] = t;
+      dead = true;
+      break;
+    }
+    __syncthreads();
+  }
+  if (!dead && blo == 0) {
+    // every qubit starts in |0>: a Z error at the very start must be invisible
+    for (uint32_t q = tid; q < st.n_qubits; q += kSweepBlock) gauge |= frame[2 * q + 1] != 0;
+  }
+  if (gauge) atomicOr(&st.hdr->flags, FLAG_GAUGE);
+}
+
+// Per boundary, the ascending list of columns whose word there may be non-zero.
+__global__ void k_cover(DevState st) {
+  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b > st.n_layers) return;
+  uint32_t n = 0;
+  uint32_t* dst = st.cov + size_t(b) * st.w;
+  for (uint32_t w = 0; w < st.w; ++w) {
+    const int top = st.col_top[w];
+    if (top >= 0 && int(b) <= top && int(b) >= st.cover_lo[w]) dst[n++] = w;
+  }
+  st.ncov[b] = n;
+}
+
+// ------------------------------------------------------------------ stage 2
+
+// FNV-1a over the W words of each fault's signature, word-wise
+// (h <- (h ^ word) * prime); a run of k zero words multiplies by prime^k.
+__global__ __launch_bounds__(kBlock) void k_hash(DevState st) {
+  const uint32_t pos = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = pos < st.n_faults;
+  const uint32_t b = valid ? boundary_of(st.bnd_fault_off, st.n_layers + 1, pos) : 0;
+  const uint32_t n = valid ? st.ncov[b] : 0;
+  {
+    // words read here = words stage 1 wrote; one atomic per wave (all lanes
+    // take part in the sum, lanes past the end contribute 0)
+    uint32_t t = n;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+    if ((threadIdx.x & 63) == 0 && t)
+      atomicAdd(reinterpret_cast<unsigned long long*>(&st.hdr->n_words), static_cast<unsigned long long>(t));
+  }
+  if (!valid) return;
+  const uint32_t* cl = st.cov + size_t(b) * st.w;
+  uint64_t h1 = kFnvOffset, h2 = 0;
+  uint32_t wn = 0;
+  for (uint32_t k = 0; k < n; ++k) {
+    const uint32_t w = cl[k];
+    const uint64_t v = st.slab[st.col_base[w] + pos];
+    if (v) {
+      h1 *= st.fnv_pow[w - wn];
+#pragma unroll
+      for (int o = 0; o < 8; ++o) h1 = (h1 ^ ((v >> (8 * o)) & 0xffu)) * kFnvPrime;
+      wn = w + 1;
+      h2 += check_term(w, v);
+    }
+  }
+  h1 *= st.fnv_pow[st.w - wn];
+  uint64_t key = h1;
+  if (st.key_mode == 1) key = h1 ^ fmix64(h2 ^ 0x5851f42d4c957f2dull);
+  else if (st.key_bits < 64) key &= (1ull << st.key_bits) - 1;
+  st.key[0][pos] = key;
+  st.chk[pos] = h2;
+  st.val[0][pos] = pos;
+}
+
+__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t* __restrict__ keys, uint32_t n, int shift,
+                                                       uint32_t* __restrict__ hist, uint32_t ntiles) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t base = blockIdx.x * kTile;
+#pragma unroll 4
+  for (int r = 0; r < kPerThread; ++r) {
+    const uint32_t i = base + r * kBlock + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1u);
+  }
+  __syncthreads();
+  hist[threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter of one 8-bit digit. Wave v of the block owns items
+// [v*1024, (v+1)*1024) of the tile and ranks them in order, 64 at a time.
+__global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t* __restrict__ kin,
+                                                          const uint32_t* __restrict__ vin,
+                                                          uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                          uint32_t n, int shift, const uint32_t* __restrict__ offs,
+                                                          uint32_t ntiles) {
+  __shared__ uint32_t cnt[kBlock / 64][256];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int k = tid; k < (kBlock / 64) * 256; k += kBlock) (&cnt[0][0])[k] = 0;
+  __syncthreads();
+  const uint32_t base = blockIdx.x * kTile + wv * (kTile / (kBlock / 64));
+  constexpr int kRounds = kTile / kBlock;
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t i = base + r * 64 + lane;
+    if (i < n) atomicAdd(&cnt[wv][(kin[i] >> shift) & 255], 1u);
+  }
+  __syncthreads();
+  {
+    uint32_t run = offs[tid * ntiles + blockIdx.x];
+    for (int v = 0; v < kBlock / 64; ++v) {
+      const uint32_t c = cnt[v][tid];
+      cnt[v][tid] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  const uint64_t lt = (1ull << lane) - 1;
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t i = base + r * 64 + lane;
+    const bool valid = i < n;
+    uint64_t k = 0;
+    uint32_t v = 0, d = 0;
+    if (valid) {
+      k = kin[i];
+      v = vin[i];
+      d = uint32_t(k >> shift) & 255u;
+    }
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const uint64_t m = __ballot(on);
+      peers &= on ? m : ~m;
+    }
+    const uint32_t rank = __popcll(peers & lt);
+    uint32_t dst = 0;
+    if (valid) dst = cnt[wv][d] + rank;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && rank == 0) cnt[wv][d] += __popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    if (valid) {
+      kout[dst] = k;
+      vout[dst] = v;
+    }
+  }
+}
+
+// In-place exclusive scan of n (host value, or *n_dev when given) words by one
+// block; each thread scans a contiguous chunk. The total goes to *total.
+template <typename TotalT>
+__global__ __launch_bounds__(kScanSingleBlock) void k_scan_single(uint32_t* data, uint32_t n_host,
+                                                                  const uint32_t* n_dev, TotalT* total) {
+  __shared__ uint32_t s_wave[kScanSingleBlock / 64 + 1];
+  const uint32_t n = n_dev ? *n_dev : n_host;
+  const uint32_t chunk = (n + kScanSingleBlock - 1) / kScanSingleBlock;
+  const uint32_t b0 = min(n, threadIdx.x * chunk), b1 = min(n, b0 + chunk);
+  uint32_t s = 0;
+  for (uint32_t i = b0; i < b1; ++i) s += data[i];
+  uint32_t run = block_exclusive_scan<kScanSingleBlock>(s, s_wave);
+  for (uint32_t i = b0; i < b1; ++i) {
+    const uint32_t v = data[i];
+    data[i] = run;
+    run += v;
+  }
+  if (threadIdx.x == 0 && total) *total = TotalT(s_wave[kScanSingleBlock / 64]);
+}
+
+// Tile sums of n words (n = *n_dev when given).
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(const uint32_t* __restrict__ in, uint32_t n_host,
+                                                       const uint32_t* n_dev, uint32_t* __restrict__ tile_sum) {
+  __shared__ uint32_t s_wave[kBlock / 64 + 1];
+  const uint32_t n = n_dev ? *n_dev : n_host;
+  const uint32_t base = blockIdx.x * kTile;
+  if (base >= n) {
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = 0;
+    return;
+  }
+  uint32_t s = 0;
+  for (int r = 0; r < kPerThread; ++r) {
+    const uint32_t i = base + r * kBlock + threadIdx.x;
+    if (i < n) s += in[i];
+  }
+  block_exclusive_scan<kBlock>(s, s_wave);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = s_wave[kBlock / 64];
+}
+
+// out[i] = exclusive prefix of in[i] given scanned tile sums.
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                       uint32_t n_host, const uint32_t* n_dev,
+                                                       const uint32_t* __restrict__ tile_off) {
+  __shared__ uint32_t s_wave[kBlock / 64 + 1];
+  const uint32_t n = n_dev ? *n_dev : n_host;
+  const uint32_t base = blockIdx.x * kTile;
+  if (base >= n) return;
+  const uint32_t i0 = base + threadIdx.x * kPerThread;
+  uint32_t v[kPerThread];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    v[k] = (i0 + k < n) ? in[i0 + k] : 0;
+    s += v[k];
+  }
+  uint32_t run = block_exclusive_scan<kBlock>(s, s_wave) + tile_off[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    if (i0 + k < n) out[i0 + k] = run;
+    run += v[k];
+  }
+}
+
+// Class heads in the sorted key array: counts per tile.
+__global__ __launch_bounds__(kBlock) void k_heads_count(const uint64_t* __restrict__ keys, uint32_t n,
+                                                        uint32_t* __restrict__ tile_sum) {
+  __shared__ uint32_t s_wave[kBlock / 64 + 1];
+  const uint32_t base = blockIdx.x * kTile;
+  uint32_t s = 0;
+  for (int r = 0; r < kPerThread; ++r) {
+    const uint32_t i = base + r * kBlock + threadIdx.x;
+    if (i < n) s += (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+  }
+  block_exclusive_scan<kBlock>(s, s_wave);
+  if (threadIdx.x == 0) tile_sum[blockIdx.x] = s_wave[kBlock / 64];
+}
+
+// segstart[class] = first sorted index of the class.
+__global__ __launch_bounds__(kBlock) void k_heads_apply(const uint64_t* __restrict__ keys, uint32_t n,
+                                                        const uint32_t* __restrict__ tile_off,
+                                                        uint32_t* __restrict__ segstart) {
+  __shared__ uint32_t s_wave[kBlock / 64 + 1];
+  const uint32_t i0 = blockIdx.x * kTile + threadIdx.x * kPerThread;
+  uint32_t flags = 0, s = 0;
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const uint32_t i = i0 + k;
+    const bool h = i < n && (i == 0 || keys[i] != keys[i - 1]);
+    flags |= uint32_t(h) << k;
+    s += h;
+  }
+  uint32_t run = block_exclusive_scan<kBlock>(s, s_wave) + tile_off[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k)
+    if ((flags >> k) & 1u) segstart[run++] = i0 + k;
+}
+
+__device__ __forceinline__ uint32_t signature_popcount(const DevState& st, uint32_t pos) {
+  const uint32_t b = boundary_of(st.bnd_fault_off, st.n_layers + 1, pos);
+  const uint32_t n = st.ncov[b];
+  const uint32_t* cl = st.cov + size_t(b) * st.w;
+  uint32_t c = 0;
+  for (uint32_t k = 0; k < n; ++k) c += __popcll(st.slab[st.col_base[cl[k]] + pos]);
+  return c;
+}
+
+// One thread per class of at most kBigSegment faults: merge probabilities in
+// sorted (fault position) order, check the check hashes agree, count bits.
+__global__ __launch_bounds__(kBlock) void k_reduce(DevState st, uint32_t n) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t S = st.hdr->n_seg;
+  if (s >= S) return;
+  const uint32_t i0 = st.segstart[s];
+  const uint32_t i1 = (s + 1 < S) ? st.segstart[s + 1] : n;
+  if (i1 - i0 > kBigSegment) return;  // handled by k_reduce_big
+  const uint32_t* vals = st.val[0];
+  const uint32_t rep = vals[i0];
+  const uint64_t c0 = st.chk[rep];
+  bool bad = false;
+  double q = 0.0;
+  for (uint32_t i = i0; i < i1; ++i) {
+    const uint32_t pos = vals[i];
+    bad |= st.chk[pos] != c0;
+    const double p = st.pfault[pos];
+    q = fma(p, 1.0 - 2.0 * q, q);  // Eq. 3: q(1-p) + p(1-q)
+  }
+  if (bad) atomicOr(&st.hdr->flags, FLAG_COLLISION);
+  const uint32_t cnt = signature_popcount(st, rep);
+  st.seg_q[s] = q;
+  st.seg_rep[s] = rep;
+  if (cnt == 0) st.hdr->empty_seg = s;
+  st.seg_cnt[s] = cnt;
+}
+
+// One block per class of more than kBigSegment faults (grid-stride over classes):
+// strided partial merges per thread, then a fixed-shape tree, so the result is
+// the same on every run.
+__global__ __launch_bounds__(kBlock) void k_reduce_big(DevState st, uint32_t n) {
+  __shared__ double s_q[kBlock];
+  __shared__ int s_bad;
+  const uint32_t S = st.hdr->n_seg;
+  const uint32_t* vals = st.val[0];
+  for (uint32_t s = blockIdx.x; s < S; s += gridDim.x) {
+    const uint32_t i0 = st.segstart[s];
+    const uint32_t i1 = (s + 1 < S) ? st.segstart[s + 1] : n;
+    if (i1 - i0 <= kBigSegment) continue;
+    if (threadIdx.x == 0) s_bad = 0;
+    const uint32_t rep = vals[i0];
+    const uint64_t c0 = st.chk[rep];
+    bool bad = false;
+    double q = 0.0;
+    for (uint32_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
+      const uint32_t pos = vals[i];
+      bad |= st.chk[pos] != c0;
+      q = fma(st.pfault[pos], 1.0 - 2.0 * q, q);
+    }
+    s_q[threadIdx.x] = q;
+    __syncthreads();
+    if (bad) s_bad = 1;
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+      if (threadIdx.x < h) {
+        const double a = s_q[threadIdx.x], c = s_q[threadIdx.x + h];
+        s_q[threadIdx.x] = fma(c, 1.0 - 2.0 * a, a);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      if (s_bad) atomicOr(&st.hdr->flags, FLAG_COLLISION);
+      const uint32_t cnt = signature_popcount(st, rep);
+      st.seg_q[s] = s_q[0];
+      st.seg_rep[s] = rep;
+      if (cnt == 0) st.hdr->empty_seg = s;
+      st.seg_cnt[s] = cnt;
+    }
+    __syncthreads();
+  }
+}
+
+// Hyperedge e (class s without the empty one): bits in external numbering
+// (detector d -> d, observable k -> D + k) and its probability.
+__global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
+  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  const uint32_t S = st.hdr->n_seg;
+  const uint32_t empty = st.hdr->empty_seg;
+  const uint32_t U = S - (empty != kNone ? 1u : 0u);
+  if (s == 0) {
+    st.hdr->n_edges = U;
+    st.edge_off32[U] = uint32_t(st.hdr->n_bits);
+    if (st.hdr->n_bits > st.bits_cap) atomicOr(&st.hdr->flags, FLAG_OVERFLOW);
+  }
+  if (s >= S || s == empty) return;
+  const uint32_t e = s - ((empty != kNone && s > empty) ? 1u : 0u);
+  const uint32_t o0 = st.seg_off[s];
+  st.edge_off32[e] = o0;
+  st.edge_q[e] = st.seg_q[s];
+  if (uint64_t(o0) + st.seg_cnt[s] > st.bits_cap) return;
+  const uint32_t pos = st.seg_rep[s];
+  const uint32_t b = boundary_of(st.bnd_fault_off, st.n_layers + 1, pos);
+  const uint32_t n = st.ncov[b];
+  const uint32_t* cl = st.cov + size_t(b) * st.w;
+  uint32_t o = o0;
+  const uint32_t obs0 = st.wd * 64;
+  for (uint32_t k = 0; k < n; ++k) {
+    const uint32_t w = cl[k];
+    uint64_t v = st.slab[st.col_base[w] + pos];
+    while (v) {
+      const uint32_t bit = w * 64 + uint32_t(__builtin_ctzll(v));
+      st.edge_bits[o++] = bit < obs0 ? bit : st.n_det + (bit - obs0);
+      v &= v - 1;
+    }
+  }
+}
+
+inline uint32_t cdiv(uint64_t a, uint64_t b) { return uint32_t((a + b - 1) / b); }
+
+}  // namespace
+
+const char* kernel_name(int id) {
+  static const char* names[K_COUNT] = {"k_prepare",      "k_sweep",       "k_cover",        "k_hash",
+                                       "k_radix_hist",   "k_scan_single", "k_radix_scatter", "k_heads_count",
+                                       "k_heads_apply",  "k_reduce",      "k_scan_tiles",   "k_scan_apply",
+                                       "k_edge_write"};
+  return (id >= 0 && id < K_COUNT) ? names[id] : "?";
+}
+
+size_t sweep_lds_bytes(uint32_t n_qubits) { return size_t(2) * n_qubits * sizeof(uint64_t); }
+
+static size_t g_lds_limit = 64 * 1024;
+
+size_t sweep_lds_limit() { return g_lds_limit; }
+
+hipError_t configure_kernels() {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  int lds = 0;
+  e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  if (e != hipSuccess) return e;
+  // leave room for the sweep's static shared words
+  size_t lim = size_t(lds) > 1024 ? size_t(lds) - 1024 : size_t(lds);
+  if (lim > 64 * 1024) {
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            int(lim));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      lim = 64 * 1024 - 1024;
+    }
+  }
+  g_lds_limit = lim;
+  return hipSuccess;
+}
+
+#define GP_LAUNCH(id, ...)                     \
+  do {                                         \
+    if (hook.before) hook.before(hook.ctx, id); \
+    __VA_ARGS__;                               \
+    if (hook.after) hook.after(hook.ctx, id);  \
+    hipError_t _e = hipGetLastError();         \
+    if (_e != hipSuccess) return _e;           \
+  } while (0)
+
+hipError_t enqueue_compile(const DevState& st, hipStream_t stream, const LaunchHook& hook) {
+  const uint32_t n = st.n_faults;
+  {
+    const uint32_t m = st.n_chan > st.w ? st.n_chan : st.w;
+    GP_LAUNCH(K_PREPARE, k_prepare<<<cdiv(m ? m : 1, kBlock), kBlock, 0, stream>>>(st));
+  }
+  if (st.n_items) {
+    GP_LAUNCH(K_SWEEP, k_sweep<<<st.n_items, kSweepBlock, sweep_lds_bytes(st.n_qubits), stream>>>(st));
+  }
+  GP_LAUNCH(K_COVER, k_cover<<<cdiv(st.n_layers + 1, 64), 64, 0, stream>>>(st));
+  if (n == 0) {
+    GP_LAUNCH(K_EDGE_WRITE, k_edge_write<<<1, kBlock, 0, stream>>>(st));
+    return hipSuccess;
+  }
+  GP_LAUNCH(K_HASH, k_hash<<<cdiv(n, kBlock), kBlock, 0, stream>>>(st));
+  const uint32_t ntiles = cdiv(n, kTile);
+  for (int pass = 0; pass < 8; ++pass) {
+    const int shift = 8 * pass;
+    const int src = pass & 1, dst = src ^ 1;
+    GP_LAUNCH(K_RADIX_HIST, k_radix_hist<<<ntiles, kBlock, 0, stream>>>(st.key[src], n, shift, st.hist, ntiles));
+    GP_LAUNCH(K_SCAN_SINGLE, k_scan_single<uint32_t><<<1, kScanSingleBlock, 0, stream>>>(
+                                 st.hist, 256 * ntiles, nullptr, static_cast<uint32_t*>(nullptr)));
+    GP_LAUNCH(K_RADIX_SCATTER, k_radix_scatter<<<ntiles, kBlock, 0, stream>>>(
+                                   st.key[src], st.val[src], st.key[dst], st.val[dst], n, shift, st.hist, ntiles));
+  }
+  GP_LAUNCH(K_HEADS_COUNT, k_heads_count<<<ntiles, kBlock, 0, stream>>>(st.key[0], n, st.tile_sum));
+  GP_LAUNCH(K_SCAN_SINGLE,
+            k_scan_single<uint32_t><<<1, kScanSingleBlock, 0, stream>>>(st.tile_sum, ntiles, nullptr, &st.hdr->n_seg));
+  GP_LAUNCH(K_HEADS_APPLY, k_heads_apply<<<ntiles, kBlock, 0, stream>>>(st.key[0], n, st.tile_sum, st.segstart));
+  GP_LAUNCH(K_REDUCE, k_reduce<<<cdiv(n, kBlock), kBlock, 0, stream>>>(st, n));
+  GP_LAUNCH(K_REDUCE, k_reduce_big<<<cdiv(n, kBigSegment * 64) + 1, kBlock, 0, stream>>>(st, n));
+  GP_LAUNCH(K_SCAN_TILES,
+            k_scan_tiles<<<ntiles, kBlock, 0, stream>>>(st.seg_cnt, n, &st.hdr->n_seg, st.tile_sum));
+  GP_LAUNCH(K_SCAN_SINGLE, k_scan_single<uint64_t><<<1, kScanSingleBlock, 0, stream>>>(st.tile_sum, ntiles, nullptr,
+                                                                                      &st.hdr->n_bits));
+  GP_LAUNCH(K_SCAN_APPLY,
+            k_scan_apply<<<ntiles, kBlock, 0, stream>>>(st.seg_cnt, st.seg_off, n, &st.hdr->n_seg, st.tile_sum));
+  GP_LAUNCH(K_EDGE_WRITE, k_edge_write<<<cdiv(n, kBlock), kBlock, 0, stream>>>(st));
+  return hipSuccess;
+}
+
+}  // namespace gp

@@ -1,0 +1,412 @@
+// Host lowering of circuit text to the device tables (see lower.h).
+#include "lower.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+
+#include "gp.h"
+
+namespace gp {
+namespace {
+
+enum Cls : uint8_t { G_1Q = 1, G_2Q, G_MEAS, G_RESET, G_PAULI, G_N1, G_N2, G_DET, G_OBS, G_IGNORE };
+
+struct Gate {
+  const char* name;
+  uint8_t cls;
+  uint8_t kind;
+};
+
+const Gate kGates[] = {
+    {"CX", G_2Q, OP_CX},          {"CNOT", G_2Q, OP_CX},       {"ZCX", G_2Q, OP_CX},
+    {"CZ", G_2Q, OP_CZ},          {"ZCZ", G_2Q, OP_CZ},        {"SWAP", G_2Q, OP_SWAP},
+    {"H", G_1Q, OP_H},            {"H_XZ", G_1Q, OP_H},        {"S", G_1Q, OP_S},
+    {"S_DAG", G_1Q, OP_S},        {"SQRT_Z", G_1Q, OP_S},      {"SQRT_Z_DAG", G_1Q, OP_S},
+    {"SQRT_X", G_1Q, OP_SQRTX},   {"SQRT_X_DAG", G_1Q, OP_SQRTX},
+    {"I", G_PAULI, 0},            {"X", G_PAULI, 0},           {"Y", G_PAULI, 0},
+    {"Z", G_PAULI, 0},            {"R", G_RESET, OP_R},        {"RZ", G_RESET, OP_R},
+    {"RX", G_RESET, OP_RX},       {"M", G_MEAS, OP_M},         {"MZ", G_MEAS, OP_M},
+    {"MX", G_MEAS, OP_MX},        {"MR", G_MEAS, OP_MR},       {"MRZ", G_MEAS, OP_MR},
+    {"MRX", G_MEAS, OP_MRX},      {"X_ERROR", G_N1, CH_X},     {"Y_ERROR", G_N1, CH_Y},
+    {"Z_ERROR", G_N1, CH_Z},      {"DEPOLARIZE1", G_N1, CH_DEP1},
+    {"DEPOLARIZE2", G_N2, CH_DEP2}, {"DETECTOR", G_DET, 0},    {"OBSERVABLE_INCLUDE", G_OBS, 0},
+    {"TICK", G_IGNORE, 0},        {"QUBIT_COORDS", G_IGNORE, 0}, {"SHIFT_COORDS", G_IGNORE, 0},
+};
+
+constexpr uint32_t kObsFlag = 0x80000000u;
+constexpr uint32_t kMaxIndex = (1u << 28) - 1;
+
+double rate_limit(uint8_t kind) {
+  return kind == CH_DEP1 ? 0.75 : kind == CH_DEP2 ? 15.0 / 16.0 : 0.5;
+}
+
+uint32_t faults_of(uint8_t kind) { return kind == CH_DEP2 ? 15u : kind == CH_DEP1 ? 3u : 1u; }
+
+int set_err(LowerError& err, int code, int line, const char* fmt, const char* what) {
+  char buf[256];
+  std::snprintf(buf, sizeof buf, fmt, what);
+  char full[320];
+  if (line > 0)
+    std::snprintf(full, sizeof full, "line %d: %s", line, buf);
+  else
+    std::snprintf(full, sizeof full, "%s", buf);
+  err.code = code;
+  err.msg = full;
+  return code;
+}
+
+struct RawChan {
+  uint32_t boundary, qa, qb;
+  uint8_t kind;
+  double rate;
+};
+
+}  // namespace
+
+int lower_circuit(const char* text, size_t len, const double* rates, size_t n_rates,
+                  uint32_t obs_chunk_faults, Lowered& lw, LowerError& err) {
+  lw = Lowered();
+  std::vector<uint32_t> ready;
+  std::vector<uint32_t> op_layer;
+  std::vector<uint64_t> op_word;
+  std::vector<RawChan> chans;
+  std::vector<uint64_t> pairs;  // (m << 32) | code
+  uint32_t n_meas = 0, n_det = 0, n_obs = 0;
+  std::vector<uint32_t> targets;
+  std::vector<uint8_t> is_rec;
+
+  auto touch = [&](uint32_t q) {
+    if (q >= ready.size()) ready.resize(size_t(q) + 1, 0);
+  };
+
+  const char* p = text;
+  const char* end = text + len;
+  int line = 0;
+  while (p < end) {
+    line++;
+    const char* eol = static_cast<const char*>(std::memchr(p, '\n', size_t(end - p)));
+    if (!eol) eol = end;
+    const char* s = p;
+    p = eol + 1;
+    const char* hash = static_cast<const char*>(std::memchr(s, '#', size_t(eol - s)));
+    const char* e = hash ? hash : eol;
+    while (s < e && (*s == ' ' || *s == '\t' || *s == '\r')) s++;
+    if (s == e) continue;
+    char name[40];
+    size_t nl = 0;
+    while (s < e && *s != '(' && *s != ' ' && *s != '\t' && *s != '\r') {
+      if (nl >= sizeof(name) - 1) return set_err(err, GP_E_UNSUPPORTED, line, "unknown instruction %s", "(too long)");
+      char c = *s++;
+      name[nl++] = (c >= 'a' && c <= 'z') ? char(c - 32) : c;
+    }
+    name[nl] = 0;
+    if (!std::strcmp(name, "REPEAT") || name[0] == '{' || name[0] == '}')
+      return set_err(err, GP_E_UNSUPPORTED, line, "%s blocks are not supported", "REPEAT");
+    const Gate* g = nullptr;
+    for (const Gate& cand : kGates)
+      if (!std::strcmp(cand.name, name)) { g = &cand; break; }
+    if (!g) return set_err(err, GP_E_UNSUPPORTED, line, "unsupported instruction %s", name);
+    double args[8];
+    int nargs = 0;
+    if (s < e && *s == '(') {
+      s++;
+      for (;;) {
+        while (s < e && (*s == ' ' || *s == '\t')) s++;
+        if (s < e && *s == ')') { s++; break; }
+        char buf[64];
+        size_t bl = 0;
+        while (s < e && *s != ',' && *s != ')' && bl < sizeof(buf) - 1) buf[bl++] = *s++;
+        buf[bl] = 0;
+        char* ep;
+        double v = std::strtod(buf, &ep);
+        if (ep == buf) return set_err(err, GP_E_PARSE, line, "bad argument in %s", name);
+        if (nargs < 8) args[nargs] = v;
+        nargs++;
+        if (s < e && *s == ',') s++;
+        else if (s >= e) return set_err(err, GP_E_PARSE, line, "unterminated arguments in %s", name);
+      }
+    }
+    targets.clear();
+    is_rec.clear();
+    while (s < e) {
+      while (s < e && (*s == ' ' || *s == '\t' || *s == '\r')) s++;
+      if (s >= e) break;
+      if (*s >= '0' && *s <= '9') {
+        uint64_t v = 0;
+        while (s < e && *s >= '0' && *s <= '9') {
+          v = v * 10 + uint64_t(*s - '0');
+          if (v > kMaxIndex) return set_err(err, GP_E_BOUNDS, line, "target index too large in %s", name);
+          s++;
+        }
+        if (s < e && *s != ' ' && *s != '\t' && *s != '\r')
+          return set_err(err, GP_E_UNSUPPORTED, line, "unsupported target in %s", name);
+        targets.push_back(uint32_t(v));
+        is_rec.push_back(0);
+      } else if (e - s >= 6 && !std::strncmp(s, "rec[-", 5)) {
+        s += 5;
+        uint64_t v = 0;
+        int nd = 0;
+        while (s < e && *s >= '0' && *s <= '9') {
+          v = v * 10 + uint64_t(*s - '0');
+          if (v > kMaxIndex) return set_err(err, GP_E_PARSE, line, "record offset too large in %s", name);
+          s++;
+          nd++;
+        }
+        if (!nd || s >= e || *s != ']' || v == 0) return set_err(err, GP_E_PARSE, line, "bad record target in %s", name);
+        s++;
+        targets.push_back(uint32_t(v));
+        is_rec.push_back(1);
+      } else {
+        return set_err(err, GP_E_UNSUPPORTED, line, "unsupported target in %s", name);
+      }
+    }
+    const size_t nt = targets.size();
+    const bool qubit_targets = g->cls != G_DET && g->cls != G_OBS && g->cls != G_IGNORE;
+    if (qubit_targets) {
+      for (size_t k = 0; k < nt; k++)
+        if (is_rec[k]) return set_err(err, GP_E_PARSE, line, "record target on %s", name);
+      if (nargs && g->cls != G_N1 && g->cls != G_N2)
+        return set_err(err, GP_E_UNSUPPORTED, line, "arguments on %s are not supported", name);
+    }
+    switch (g->cls) {
+      case G_PAULI:
+        for (size_t k = 0; k < nt; k++) touch(targets[k]);
+        break;
+      case G_1Q:
+      case G_RESET:
+        for (size_t k = 0; k < nt; k++) {
+          uint32_t q = targets[k];
+          touch(q);
+          op_layer.push_back(ready[q]);
+          op_word.push_back(pack_op(g->kind, q, 0));
+          ready[q]++;
+        }
+        break;
+      case G_2Q:
+        if (nt % 2) return set_err(err, GP_E_PARSE, line, "odd number of targets in %s", name);
+        for (size_t k = 0; k < nt; k += 2) {
+          uint32_t a = targets[k], b = targets[k + 1];
+          if (a == b) return set_err(err, GP_E_PARSE, line, "repeated qubit in %s", name);
+          touch(a);
+          touch(b);
+          uint32_t l = std::max(ready[a], ready[b]);
+          op_layer.push_back(l);
+          op_word.push_back(pack_op(g->kind, a, b));
+          ready[a] = ready[b] = l + 1;
+        }
+        break;
+      case G_MEAS:
+        for (size_t k = 0; k < nt; k++) {
+          uint32_t q = targets[k];
+          touch(q);
+          if (n_meas > kMaxIndex) return set_err(err, GP_E_BOUNDS, line, "too many measurements at %s", name);
+          op_layer.push_back(ready[q]);
+          op_word.push_back(pack_op(g->kind, q, n_meas));
+          lw.meas_layer.push_back(ready[q]);
+          ready[q]++;
+          n_meas++;
+        }
+        break;
+      case G_N1:
+      case G_N2: {
+        if (nargs != 1) return set_err(err, GP_E_PARSE, line, "%s takes one probability", name);
+        double r = args[0];
+        if (!(r >= 0.0 && r <= rate_limit(g->kind)))
+          return set_err(err, GP_E_NOISE, line, "rate out of range in %s", name);
+        if (g->cls == G_N1) {
+          for (size_t k = 0; k < nt; k++) {
+            uint32_t q = targets[k];
+            touch(q);
+            chans.push_back(RawChan{ready[q], q, UINT32_MAX, g->kind, r});
+          }
+        } else {
+          if (nt % 2) return set_err(err, GP_E_PARSE, line, "odd number of targets in %s", name);
+          for (size_t k = 0; k < nt; k += 2) {
+            uint32_t a = targets[k], b = targets[k + 1];
+            if (a == b) return set_err(err, GP_E_PARSE, line, "repeated qubit in %s", name);
+            touch(a);
+            touch(b);
+            // both halves of the fault must sit at one boundary: later
+            // operations on either qubit may not be scheduled before it
+            uint32_t bnd = std::max(ready[a], ready[b]);
+            ready[a] = ready[b] = bnd;
+            chans.push_back(RawChan{bnd, a, b, g->kind, r});
+          }
+        }
+        break;
+      }
+      case G_DET:
+      case G_OBS: {
+        uint32_t code;
+        if (g->cls == G_DET) {
+          code = n_det++;
+          if (n_det > kMaxIndex) return set_err(err, GP_E_BOUNDS, line, "too many %s", "detectors");
+        } else {
+          if (nargs != 1 || args[0] < 0 || args[0] != std::floor(args[0]) || args[0] > 65535)
+            return set_err(err, GP_E_PARSE, line, "%s needs one observable index", name);
+          uint32_t k = uint32_t(args[0]);
+          n_obs = std::max(n_obs, k + 1);
+          code = kObsFlag | k;
+        }
+        for (size_t k = 0; k < nt; k++) {
+          if (!is_rec[k]) return set_err(err, GP_E_PARSE, line, "%s takes record targets", name);
+          if (targets[k] > n_meas) return set_err(err, GP_E_PARSE, line, "record looks back too far in %s", name);
+          uint32_t m = n_meas - targets[k];
+          pairs.push_back((uint64_t(m) << 32) | code);
+        }
+        break;
+      }
+      default:
+        break;
+    }
+  }
+
+  // ---- sizes
+  lw.n_qubits = uint32_t(ready.size());
+  uint32_t L = 0;
+  for (uint32_t r : ready) L = std::max(L, r);
+  lw.n_layers = L;
+  lw.n_meas = n_meas;
+  lw.n_det = n_det;
+  lw.n_obs = n_obs;
+  lw.wd = (n_det + 63) / 64;
+  lw.wo = (n_obs + 63) / 64;
+  lw.w = lw.wd + lw.wo;
+
+  // ---- operations sorted by layer (counting sort keeps program order)
+  lw.layer_off.assign(size_t(L) + 1, 0);
+  for (uint32_t l : op_layer) lw.layer_off[l + 1]++;
+  for (uint32_t l = 0; l < L; l++) lw.layer_off[l + 1] += lw.layer_off[l];
+  lw.ops.resize(op_word.size());
+  {
+    std::vector<uint32_t> fill(lw.layer_off.begin(), lw.layer_off.end() - 1);
+    for (size_t k = 0; k < op_word.size(); k++) lw.ops[fill[op_layer[k]]++] = op_word[k];
+  }
+
+  // ---- leaves (Eq. 2), XOR semantics for repeated memberships
+  std::sort(pairs.begin(), pairs.end());
+  lw.leaf_off.assign(size_t(n_meas) + 1, 0);
+  lw.leaf_bits.clear();
+  for (size_t i = 0; i < pairs.size();) {
+    size_t j = i;
+    while (j < pairs.size() && pairs[j] == pairs[i]) j++;
+    if ((j - i) & 1) {
+      uint32_t m = uint32_t(pairs[i] >> 32);
+      uint32_t code = uint32_t(pairs[i]);
+      uint32_t bit = (code & kObsFlag) ? lw.wd * 64 + (code & ~kObsFlag) : code;
+      lw.leaf_off[m + 1]++;
+      lw.leaf_bits.push_back(bit);
+    }
+    i = j;
+  }
+  for (uint32_t m = 0; m < n_meas; m++) lw.leaf_off[m + 1] += lw.leaf_off[m];
+
+  // ---- channels sorted by boundary (stable), fault positions
+  const size_t C = chans.size();
+  if (rates) {
+    if (n_rates != C) {
+      char buf[128];
+      std::snprintf(buf, sizeof buf, "rate array has %zu entries, circuit has %zu channels", n_rates, C);
+      return set_err(err, GP_E_NOISE, 0, "%s", buf);
+    }
+    for (size_t k = 0; k < C; k++) {
+      double r = rates[k];
+      if (!(r >= 0.0 && r <= rate_limit(chans[k].kind))) return set_err(err, GP_E_NOISE, 0, "%s", "rate out of range");
+      chans[k].rate = r;
+    }
+  }
+  lw.bnd_chan_off.assign(size_t(L) + 2, 0);
+  for (const RawChan& c : chans) lw.bnd_chan_off[c.boundary + 1]++;
+  for (uint32_t b = 0; b <= L; b++) lw.bnd_chan_off[b + 1] += lw.bnd_chan_off[b];
+  lw.chan_qa.resize(C);
+  lw.chan_qb.resize(C);
+  lw.chan_kind.resize(C);
+  lw.chan_rate.resize(C);
+  lw.chan_src.resize(C);
+  {
+    std::vector<uint32_t> fill(lw.bnd_chan_off.begin(), lw.bnd_chan_off.end() - 1);
+    for (size_t k = 0; k < C; k++) {
+      uint32_t d = fill[chans[k].boundary]++;
+      lw.chan_qa[d] = chans[k].qa;
+      lw.chan_qb[d] = chans[k].qb;
+      lw.chan_kind[d] = chans[k].kind;
+      lw.chan_rate[d] = chans[k].rate;
+      lw.chan_src[d] = uint32_t(k);
+    }
+  }
+  uint64_t total_faults = 0;
+  for (size_t c = 0; c < C; c++) total_faults += faults_of(lw.chan_kind[c]);
+  if (total_faults >= (1ull << 32)) return set_err(err, GP_E_BOUNDS, 0, "%s", "more than 2^32 - 1 faults");
+  lw.chan_foff.assign(C + 1, 0);
+  for (size_t c = 0; c < C; c++) lw.chan_foff[c + 1] = lw.chan_foff[c] + faults_of(lw.chan_kind[c]);
+  lw.n_faults = total_faults;
+  lw.bnd_fault_off.assign(size_t(L) + 2, 0);
+  for (uint32_t b = 0; b <= L + 1; b++) lw.bnd_fault_off[b] = lw.chan_foff[lw.bnd_chan_off[b]];
+
+  // ---- word columns: static live range from the layers of their leaves
+  lw.col_top.assign(lw.w, -1);
+  lw.col_lo.assign(lw.w, INT32_MAX);
+  for (uint32_t m = 0; m < n_meas; m++) {
+    for (uint32_t k = lw.leaf_off[m]; k < lw.leaf_off[m + 1]; k++) {
+      uint32_t w = lw.leaf_bits[k] >> 6;
+      lw.col_top[w] = std::max<int32_t>(lw.col_top[w], int32_t(lw.meas_layer[m]));
+      lw.col_lo[w] = std::min<int32_t>(lw.col_lo[w], int32_t(lw.meas_layer[m]));
+    }
+  }
+  lw.col_base.assign(lw.w, 0);
+  uint64_t base = 0;
+  for (uint32_t w = 0; w < lw.w; w++) {
+    lw.col_base[w] = base;
+    if (lw.col_top[w] >= 0) base += lw.bnd_fault_off[lw.col_top[w] + 1];
+    else lw.col_lo[w] = -1;
+  }
+  lw.slab_words = base;
+
+  // ---- sweep items: one per detector column; observable columns, which stay
+  // live over the whole circuit, are cut into chunks of about
+  // obs_chunk_faults emitted faults so that their emission spreads over CUs
+  const uint32_t chunk = std::max<uint32_t>(obs_chunk_faults, 1);
+  for (uint32_t w = 0; w < lw.w; w++) {
+    int32_t top = lw.col_top[w];
+    if (top < 0) continue;
+    if (w < lw.wd) {
+      lw.item_col.push_back(w);
+      lw.item_blo.push_back(0);
+      lw.item_bhi.push_back(uint32_t(top));
+      continue;
+    }
+    int32_t hi = top;
+    while (hi >= 0) {
+      int32_t lo = hi;
+      while (lo > 0 && lw.bnd_fault_off[hi + 1] - lw.bnd_fault_off[lo - 1] <= chunk) lo--;
+      lw.item_col.push_back(w);
+      lw.item_blo.push_back(uint32_t(lo));
+      lw.item_bhi.push_back(uint32_t(hi));
+      hi = lo - 1;
+    }
+  }
+
+  // ---- FNV-1a over the 8W octets of a signature: a run of k zero words
+  // multiplies the state by prime^(8k)
+  uint64_t p8 = 1;
+  for (int k = 0; k < 8; k++) p8 *= kFnvPrime;
+  lw.fnv_pow.assign(size_t(lw.w) + 1, 1);
+  for (uint32_t k = 1; k <= lw.w; k++) lw.fnv_pow[k] = lw.fnv_pow[k - 1] * p8;
+  return 0;
+}
+
+int apply_rates(Lowered& lw, const double* rates, size_t n_rates, LowerError& err) {
+  const size_t C = lw.chan_kind.size();
+  if (n_rates != C) return set_err(err, GP_E_NOISE, 0, "%s", "rate array length differs from the channel count");
+  for (size_t d = 0; d < C; d++) {
+    double r = rates[lw.chan_src[d]];
+    if (!(r >= 0.0 && r <= rate_limit(lw.chan_kind[d]))) return set_err(err, GP_E_NOISE, 0, "%s", "rate out of range");
+    lw.chan_rate[d] = r;
+  }
+  return 0;
+}
+
+}  // namespace gp

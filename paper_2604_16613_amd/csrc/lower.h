@@ -1,0 +1,87 @@
+// Host lowering: realised circuit text -> the tables the device stages consume.
+//
+// The circuit is lowered to the space-time error propagation graph of paper
+// Sec. 2.3.1 in an implicit form: operations are scheduled as soon as possible
+// into layers in which every qubit is touched at most once, and a boundary b
+// (0 <= b <= L) sits before layer b. Each (boundary, qubit) owns an X and a Z
+// vertex (symplectic doubling, Sec. 2.3.4). Instead of storing two successor
+// indices per vertex, a layer is stored as its list of operations; the device
+// applies each operation's successor rule to the X/Z vertices of its qubits
+// (identity for idle qubits), which is the same straight-line program (Eq. 1)
+// with the identity edges left implicit.
+//
+// Measurement leaves (Eq. 2): every measurement m owns the set of signature
+// bits (detectors, then observables) whose definitions list m an odd number of
+// times. Signature bits are packed into 64-bit words; detector bits occupy
+// words [0, WD) and observable bits words [WD, WD + WO), so the long-lived
+// observable columns are separate from the short-lived detector columns.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace gp {
+
+enum OpKind : uint8_t {
+  OP_H = 1, OP_S, OP_SQRTX, OP_CX, OP_CZ, OP_SWAP,
+  OP_R, OP_RX, OP_M, OP_MX, OP_MR, OP_MRX
+};
+
+enum ChanKind : uint8_t { CH_X = 1, CH_Y, CH_Z, CH_DEP1, CH_DEP2 };
+
+// op word: kind in bits 56..63, a in bits 28..55, b in bits 0..27.
+// a = qubit (control for CX); b = second qubit, or the measurement index.
+constexpr uint64_t kField = (1ull << 28) - 1;
+inline uint64_t pack_op(uint32_t kind, uint32_t a, uint32_t b) {
+  return (uint64_t(kind) << 56) | (uint64_t(a & kField) << 28) | uint64_t(b & kField);
+}
+
+struct Lowered {
+  uint32_t n_qubits = 0, n_layers = 0, n_meas = 0, n_det = 0, n_obs = 0;
+  uint32_t wd = 0, wo = 0, w = 0;     // word columns: detector, observable, total
+  uint64_t n_faults = 0;
+
+  std::vector<uint64_t> ops;          // sorted by layer
+  std::vector<uint32_t> layer_off;    // L + 1
+  std::vector<uint32_t> leaf_off;     // n_meas + 1
+  std::vector<uint32_t> leaf_bits;    // internal bit index, sorted per measurement
+  std::vector<uint32_t> meas_layer;   // n_meas
+
+  // channels, sorted by (boundary, program order)
+  std::vector<uint32_t> chan_qa, chan_qb;   // qb = UINT32_MAX for one-qubit channels
+  std::vector<uint8_t> chan_kind;
+  std::vector<double> chan_rate;            // rate in sorted order
+  std::vector<uint32_t> chan_src;           // program-order channel index
+  std::vector<uint32_t> chan_foff;          // C + 1: first fault position of each channel
+  std::vector<uint32_t> bnd_chan_off;       // L + 2: channels at boundary b
+  std::vector<uint32_t> bnd_fault_off;      // L + 2: fault positions at boundary b
+
+  // word columns and sweep work items
+  std::vector<int32_t> col_top;             // highest layer holding a leaf bit of the column (-1: none)
+  std::vector<int32_t> col_lo;              // lowest such layer
+  std::vector<uint64_t> col_base;           // slab offset: word of (column w, position p) at base[w] + p
+  uint64_t slab_words = 0;
+  std::vector<uint32_t> item_col, item_blo, item_bhi;  // emission boundaries [blo, bhi]
+
+  std::vector<uint64_t> fnv_pow;            // w + 1 entries: FNV prime^(8k) mod 2^64
+};
+
+struct LowerError {
+  int code;
+  std::string msg;
+};
+
+// Lower `text`; `rates` (if non-null) overrides the channel rates in program
+// order. `obs_chunk_faults` bounds the fault positions one sweep item of an
+// observable column emits. Returns 0 or a negative GP_E_* status with err set.
+int lower_circuit(const char* text, size_t len, const double* rates, size_t n_rates,
+                  uint32_t obs_chunk_faults, Lowered& out, LowerError& err);
+
+// Re-apply a rate array to an already lowered circuit (same structure).
+int apply_rates(Lowered& lw, const double* rates, size_t n_rates, LowerError& err);
+
+constexpr uint64_t kFnvOffset = 14695981039346656037ull;
+constexpr uint64_t kFnvPrime = 1099511628211ull;
+
+}  // namespace gp

@@ -1,0 +1,207 @@
+// Test-only CPU interpreter of the lowered tables produced by the compiler's
+// host lowering (paper_2604_16613_amd/csrc/lower.cpp). It replays the stage-1
+// work items exactly as the device sweep schedules them -- same tables, same
+// per-column slab addressing, same early stop -- with every table and slab
+// access bounds-checked, and returns each fault's signature. Tests compare
+// those signatures with the oracle's before any kernel runs on a GPU.
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gp.h"
+#include "lower.h"
+
+using namespace gp;
+
+namespace {
+std::string g_msg;
+int bad(const char* what) {
+  g_msg = what;
+  return -100;
+}
+}  // namespace
+
+extern "C" const char* hc_error() { return g_msg.c_str(); }
+
+// stats: [0] faults, [1] items, [2] slab words, [3] layers, [4] gauge flag,
+//        [5] words written, [6] columns, [7] qubits
+extern "C" int hc_run(const char* text, size_t len, const double* rates, size_t n_rates, uint64_t* off,
+                      uint32_t* bits, uint64_t bits_cap, uint32_t* src, uint32_t* code, uint64_t* stats,
+                      uint64_t max_faults) {
+  Lowered lw;
+  LowerError err{};
+  int rc = lower_circuit(text, len, rates, n_rates, 65536, lw, err);
+  if (rc) {
+    g_msg = err.msg;
+    return rc;
+  }
+  const uint32_t n = lw.n_qubits, L = lw.n_layers, W = lw.w;
+  const uint64_t F = lw.n_faults;
+  if (F > max_faults) return bad("fault capacity too small");
+  // structural checks of the tables
+  if (lw.layer_off.size() != L + 1u || lw.layer_off[L] != lw.ops.size()) return bad("layer_off");
+  for (uint32_t t = 0; t < L; t++) {
+    std::vector<char> seen(n, 0);
+    for (uint32_t o = lw.layer_off[t]; o < lw.layer_off[t + 1]; o++) {
+      uint64_t op = lw.ops[o];
+      uint32_t kind = uint32_t(op >> 56), a = uint32_t(op >> 28) & kField, b = uint32_t(op) & kField;
+      if (a >= n || seen[a]++) return bad("layer touches a qubit twice or out of range");
+      if (kind == OP_CX || kind == OP_CZ || kind == OP_SWAP) {
+        if (b >= n || seen[b]++) return bad("layer touches a qubit twice (pair)");
+      } else if (kind >= OP_M) {
+        if (b >= lw.n_meas) return bad("measurement index");
+      }
+    }
+  }
+  if (lw.bnd_fault_off.size() != L + 2u || lw.bnd_fault_off[L + 1] != F) return bad("bnd_fault_off");
+  for (size_t c = 0; c < lw.chan_kind.size(); c++) {
+    if (lw.chan_qa[c] >= n) return bad("channel qubit");
+    if (lw.chan_kind[c] == CH_DEP2 && lw.chan_qb[c] >= n) return bad("channel qubit b");
+  }
+  std::vector<uint64_t> slab(lw.slab_words, 0);
+  std::vector<char> written(lw.slab_words, 0);
+  std::vector<int32_t> cover_lo(W, 0);
+  uint64_t nwritten = 0;
+  int gauge = 0;
+  for (size_t it = 0; it < lw.item_col.size(); it++) {
+    const uint32_t w = lw.item_col[it];
+    if (w >= W) return bad("item column");
+    const int top = lw.col_top[w], clo = lw.col_lo[w];
+    const int blo = int(lw.item_blo[it]), bhi = int(lw.item_bhi[it]);
+    if (top < 0 || top >= int(L) || bhi > top || blo > bhi) return bad("item range");
+    const uint64_t base = lw.col_base[w];
+    const uint64_t cap = lw.bnd_fault_off[top + 1];
+    std::vector<uint64_t> fr(2 * size_t(n), 0);
+    int nz = 0;
+    bool dead = false;
+    for (int t = top; t >= blo; --t) {
+      int dnz = 0;
+      auto nzd = [](uint64_t a, uint64_t b) { return int(a != 0) - int(b != 0); };
+      for (uint32_t o = lw.layer_off[t]; o < lw.layer_off[t + 1]; o++) {
+        uint64_t op = lw.ops[o];
+        uint32_t kind = uint32_t(op >> 56), a = uint32_t(op >> 28) & kField, b = uint32_t(op) & kField;
+        uint64_t& xa = fr[2 * a];
+        uint64_t& za = fr[2 * a + 1];
+        const uint64_t x0 = xa, z0 = za;
+        auto leaf = [&](uint32_t m) {
+          uint64_t v = 0;
+          if (m + 1 >= lw.leaf_off.size()) return v;
+          for (uint32_t k = lw.leaf_off[m]; k < lw.leaf_off[m + 1]; k++)
+            if ((lw.leaf_bits[k] >> 6) == w) v |= 1ull << (lw.leaf_bits[k] & 63);
+          return v;
+        };
+        switch (kind) {
+          case OP_H: xa = z0; za = x0; break;
+          case OP_S: xa = x0 ^ z0; dnz += nzd(xa, x0); break;
+          case OP_SQRTX: za = x0 ^ z0; dnz += nzd(za, z0); break;
+          case OP_CX: {
+            uint64_t& xb = fr[2 * b]; uint64_t& zb = fr[2 * b + 1];
+            uint64_t x1 = xb, z1 = zb;
+            xa = x0 ^ x1; zb = z1 ^ z0;
+            dnz += nzd(xa, x0) + nzd(zb, z1);
+            break;
+          }
+          case OP_CZ: {
+            uint64_t& xb = fr[2 * b]; uint64_t& zb = fr[2 * b + 1];
+            uint64_t x1 = xb, z1 = zb;
+            xa = x0 ^ z1; xb = x1 ^ z0;
+            dnz += nzd(xa, x0) + nzd(xb, x1);
+            break;
+          }
+          case OP_SWAP: {
+            uint64_t& xb = fr[2 * b]; uint64_t& zb = fr[2 * b + 1];
+            std::swap(xa, xb); std::swap(za, zb);
+            break;
+          }
+          case OP_R: gauge |= z0 != 0; xa = 0; za = 0; dnz -= int(x0 != 0) + int(z0 != 0); break;
+          case OP_RX: gauge |= x0 != 0; xa = 0; za = 0; dnz -= int(x0 != 0) + int(z0 != 0); break;
+          case OP_M: gauge |= z0 != 0; xa = x0 ^ leaf(b); dnz += nzd(xa, x0); break;
+          case OP_MX: gauge |= x0 != 0; za = z0 ^ leaf(b); dnz += nzd(za, z0); break;
+          case OP_MR: gauge |= z0 != 0; xa = leaf(b); za = 0; dnz += nzd(xa, x0) - int(z0 != 0); break;
+          case OP_MRX: gauge |= x0 != 0; za = leaf(b); xa = 0; dnz += nzd(za, z0) - int(x0 != 0); break;
+          default: return bad("op kind");
+        }
+      }
+      nz += dnz;
+      int full = 0;
+      for (uint64_t v : fr) full += v != 0;
+      if (full != nz) return bad("incremental non-zero count disagrees with a full count");
+      if (t <= bhi) {
+        for (uint32_t c = lw.bnd_chan_off[t]; c < lw.bnd_chan_off[t + 1]; c++) {
+          const uint64_t x0 = fr[2 * lw.chan_qa[c]], z0 = fr[2 * lw.chan_qa[c] + 1];
+          uint64_t words[15];
+          int nwd = 0;
+          switch (lw.chan_kind[c]) {
+            case CH_X: words[nwd++] = x0; break;
+            case CH_Y: words[nwd++] = x0 ^ z0; break;
+            case CH_Z: words[nwd++] = z0; break;
+            case CH_DEP1: words[nwd++] = x0; words[nwd++] = x0 ^ z0; words[nwd++] = z0; break;
+            case CH_DEP2: {
+              const uint64_t x1 = fr[2 * lw.chan_qb[c]], z1 = fr[2 * lw.chan_qb[c] + 1];
+              const uint64_t A[4] = {0, x0, z0, x0 ^ z0}, B[4] = {0, x1, z1, x1 ^ z1};
+              for (int k = 1; k < 16; k++) words[nwd++] = A[k & 3] ^ B[k >> 2];
+              break;
+            }
+            default: return bad("channel kind");
+          }
+          for (int k = 0; k < nwd; k++) {
+            uint64_t pos = lw.chan_foff[c] + k;
+            if (pos >= cap) return bad("emission beyond the column's slab");
+            uint64_t idx = base + pos;
+            if (idx >= lw.slab_words) return bad("slab index out of range");
+            if (written[idx]) return bad("slab word written twice");
+            written[idx] = 1;
+            slab[idx] = words[k];
+            nwritten++;
+          }
+        }
+      }
+      if (nz == 0 && t <= clo) {
+        if (t <= bhi) cover_lo[w] = t;
+        dead = true;
+        break;
+      }
+    }
+    if (!dead && blo == 0)
+      for (uint32_t q = 0; q < n; q++) gauge |= fr[2 * q + 1] != 0;
+  }
+  // signatures of every fault position from the covered columns
+  uint64_t nb = 0;
+  off[0] = 0;
+  for (uint32_t b = 0; b <= L; b++) {
+    for (uint32_t c = lw.bnd_chan_off[b]; c < lw.bnd_chan_off[b + 1]; c++) {
+      for (uint32_t pos = lw.chan_foff[c]; pos < lw.chan_foff[c + 1]; pos++) {
+        for (uint32_t w = 0; w < W; w++) {
+          const int top = lw.col_top[w];
+          if (top < 0 || int(b) > top || int(b) < cover_lo[w]) continue;
+          uint64_t idx = lw.col_base[w] + pos;
+          if (!written[idx]) return bad("covered slab word never written");
+          uint64_t v = slab[idx];
+          while (v) {
+            uint32_t bit = w * 64 + uint32_t(__builtin_ctzll(v));
+            if (nb >= bits_cap) return bad("bit capacity");
+            bits[nb++] = bit < lw.wd * 64 ? bit : lw.n_det + (bit - lw.wd * 64);
+            v &= v - 1;
+          }
+        }
+        off[pos + 1] = nb;
+        src[pos] = lw.chan_src[c];
+        uint32_t k = pos - lw.chan_foff[c];
+        uint8_t kind = lw.chan_kind[c];
+        code[pos] = kind == CH_DEP2 ? k + 1 : kind == CH_DEP1 ? (k == 0 ? 1u : k == 1 ? 3u : 2u)
+                    : kind == CH_X ? 1u : kind == CH_Y ? 3u : 2u;
+      }
+    }
+  }
+  stats[0] = F;
+  stats[1] = lw.item_col.size();
+  stats[2] = lw.slab_words;
+  stats[3] = L;
+  stats[4] = uint64_t(gauge);
+  stats[5] = nwritten;
+  stats[6] = W;
+  stats[7] = n;
+  return 0;
+}

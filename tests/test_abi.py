@@ -1,0 +1,74 @@
+"""C-ABI library checks that need no GPU: every symbol include/gp.h declares is
+exported, host-only entry points work, errors come back as documented codes."""
+
+import os
+import re
+
+import pytest
+
+from paper_2604_16613_amd import _gp
+from workloads import bivariate_bicycle_memory, rotated_surface_code_memory
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "gp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _gp.load()
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_gp.EXPORTS)
+
+
+def test_bounds_from_circuit_sizes():
+    c = rotated_surface_code_memory(3, 3)
+    b = _gp.gp_bounds_from_circuit(c.text)
+    assert (b.max_qubits, b.max_detectors, b.max_observables, b.max_channels, b.max_faults) == (17, 24, 1, 170, 1308)
+    assert b.max_measurements == 33
+    c = rotated_surface_code_memory(25, 25)
+    b = _gp.gp_bounds_from_circuit(c.text)
+    assert (b.max_qubits, b.max_faults, b.max_channels, b.max_detectors) == (1249, 1013572, 108674, 15600)
+    c = bivariate_bicycle_memory()
+    b = _gp.gp_bounds_from_circuit(c.text)
+    assert (b.max_qubits, b.max_faults, b.max_detectors, b.max_observables) == (288, 168624, 1728, 12)
+
+
+@pytest.mark.parametrize("text,code", [
+    ("REPEAT 2 {\nH 0\n}\n", -3),
+    ("R 0\nT 0\n", -3),
+    ("R 0\nM(0.01) 0\n", -3),
+    ("R 0\nM !0\n", -3),
+    ("CX 0\n", -2),
+    ("CX 1 1\n", -2),
+    ("M 0\nDETECTOR rec[-2]\n", -2),
+    ("M 0\nDETECTOR 0\n", -2),
+    ("R 0\nX_ERROR(0.6) 0\n", -6),
+    ("R 0\nDEPOLARIZE1(0.8) 0\n", -6),
+    ("R 0 1\nDEPOLARIZE2(0.95) 0 1\n", -6),
+    ("R 0\nX_ERROR 0\n", -2),
+    ("OBSERVABLE_INCLUDE rec[-1]\n", -2),
+])
+def test_host_errors(text, code):
+    with pytest.raises(_gp.GpError) as e:
+        _gp.gp_bounds_from_circuit(text)
+    assert e.value.code == code
+    assert _gp.gp_last_error()
+
+
+def test_driver_without_gpu_fails_loudly():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    with pytest.raises(_gp.GpError) as e:
+        _gp.gp_driver_create_from_circuit(rotated_surface_code_memory(3, 3).text)
+    assert e.value.code == -7

@@ -1,0 +1,238 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Signatures must match exactly (same set of hyperedges, same bits) and
+probabilities to 1e-12 relative, on every workload: the d = 3 surface code,
+d = 11 / 17 / 25 with uniform and seeded log-uniform rates, the [[144,12,12]]
+bivariate bicycle code, d = 9 with per-channel rates, plus small circuits that
+exercise every gate kind, the empty and degenerate cases, and error paths.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_16613_amd import Driver, GpError, get_driver
+from paper_2604_16613_amd import _gp
+from workloads import (bit_flip_code_fig1, bivariate_bicycle_memory, log_uniform_rates, mirror_circuit,
+                       repetition_code_memory, rotated_surface_code_memory)
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-12
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def assert_parity(hg, ref, label=""):
+    g = hg.edges()
+    assert len(g) == len(hg), "duplicate hyperedges in the GPU output"
+    o = ref.edges()
+    missing = set(o) - set(g)
+    extra = set(g) - set(o)
+    assert not missing and not extra, f"{label}: {len(missing)} missing, {len(extra)} extra hyperedges"
+    worst = 0.0
+    for k, qo in o.items():
+        qg = g[k]
+        rel = abs(qg - qo) / qo if qo > 0 else abs(qg)
+        worst = max(worst, rel)
+    assert worst <= REL_TOL, f"{label}: worst relative error {worst:.3e}"
+    for e in range(len(hg)):
+        seg = hg.bits[hg.offsets[e]:hg.offsets[e + 1]]
+        assert np.all(np.diff(seg.astype(np.int64)) > 0)
+    return worst
+
+
+def merged_bounds(texts):
+    """Element-wise maximum of the bounds of several circuits; the derived
+    sizes (signature slab, sweep items) are left for the driver to compute."""
+    out = _gp.GpBounds()
+    for t in texts:
+        b = _gp.gp_bounds_from_circuit(t)
+        for k, _ in b._fields_:
+            setattr(out, k, max(getattr(out, k), getattr(b, k)))
+    out.max_observables = max(out.max_observables, 16)
+    out.max_slab_words = 0
+    out.max_items = 0
+    return out
+
+
+@pytest.fixture(scope="module")
+def drv25():
+    say("creating a driver for d=25 r=25 and the [[144,12,12]] code")
+    d = Driver(merged_bounds([rotated_surface_code_memory(25, 25).text, bivariate_bicycle_memory().text]))
+    yield d
+    d.close()
+
+
+def check(drv, text, rates=None, label=""):
+    say("case", label)
+    hg = drv.compile_hypergraph(text, rates)
+    ref = oracle.run(text, rates=rates)
+    return assert_parity(hg, ref, label)
+
+
+def test_small_circuits(drv25):
+    check(drv25, bit_flip_code_fig1().text, label="fig1")
+    check(drv25, repetition_code_memory(3, 2, p_data=0.01, p_meas=0.02, p2=0.03, p1=0.04).text, label="rep3")
+    check(drv25, repetition_code_memory(7, 5, p_data=0.01, p_meas=0.02, p2=0.03, p1=0.04,
+                                        data_noise="DEPOLARIZE1").text, label="rep7")
+    for s in range(6):
+        check(drv25, mirror_circuit(5, 6, s, x_basis=[s % 5, (s + 1) % 5]).text, label=f"mirror{s}")
+
+
+def test_surface_code_d3(drv25):
+    """The d = 3, 3-round surface code with uniform p = 1e-3."""
+    c = rotated_surface_code_memory(3, 3)
+    check(drv25, c.text, label="sc3")
+    info = drv25.info()
+    assert info["n_faults"] == 1308 and info["n_channels"] == 170
+
+
+@pytest.mark.parametrize("d,r", [(5, 5), (7, 7), (5, 2)])
+def test_surface_code_small(drv25, d, r):
+    check(drv25, rotated_surface_code_memory(d, r).text, label=f"sc{d}r{r}")
+
+
+def test_surface_code_d9_rates(drv25):
+    """d = 9, 9 rounds, per-channel log-uniform rates (seed 0)."""
+    c = rotated_surface_code_memory(9, 9)
+    check(drv25, c.text, log_uniform_rates(c.n_channels, 0), label="sc9 seed0")
+
+
+@pytest.mark.parametrize("seed", [None, 0, 1, 2])
+def test_surface_code_d11(drv25, seed):
+    c = rotated_surface_code_memory(11, 11)
+    rates = None if seed is None else log_uniform_rates(c.n_channels, seed)
+    check(drv25, c.text, rates, label=f"sc11 seed{seed}")
+
+
+def test_bivariate_bicycle(drv25):
+    c = bivariate_bicycle_memory()
+    check(drv25, c.text, label="bb144")
+    assert drv25.info()["n_observables"] == 12
+
+
+@pytest.mark.parametrize("seed", [None, 0])
+def test_surface_code_d17(drv25, seed):
+    c = rotated_surface_code_memory(17, 17)
+    rates = None if seed is None else log_uniform_rates(c.n_channels, seed)
+    check(drv25, c.text, rates, label=f"sc17 seed{seed}")
+
+
+@pytest.mark.parametrize("seed", [None, 1])
+def test_surface_code_d25(drv25, seed):
+    """The largest workload at full size, every hyperedge compared."""
+    c = rotated_surface_code_memory(25, 25)
+    rates = None if seed is None else log_uniform_rates(c.n_channels, seed)
+    check(drv25, c.text, rates, label=f"sc25 seed{seed}")
+    assert drv25.info()["n_faults"] == 1013572
+
+
+def test_deterministic_and_split_path(drv25):
+    c = rotated_surface_code_memory(11, 11)
+    a = drv25.compile_hypergraph(c.text)
+    drv25.lower(c.text)
+    for _ in range(3):
+        drv25.run()
+    b = drv25.fetch()
+    assert np.array_equal(a.offsets, b.offsets)
+    assert np.array_equal(a.bits, b.bits)
+    assert np.array_equal(a.q.view(np.uint64), b.q.view(np.uint64))
+
+
+def test_driver_reuse_and_bounds():
+    say("case reuse")
+    with get_driver(rotated_surface_code_memory(5, 5).text) as drv:
+        for d, r in ((3, 3), (5, 5), (3, 1), (5, 2)):
+            c = rotated_surface_code_memory(d, r)
+            assert_parity(drv.compile_hypergraph(c.text), oracle.run(c.text), f"reuse d{d}r{r}")
+        with pytest.raises(GpError) as e:
+            drv.compile_hypergraph(rotated_surface_code_memory(7, 7).text)
+        assert e.value.code == -4
+        # the driver still works after a refused circuit
+        c = rotated_surface_code_memory(3, 3)
+        assert_parity(drv.compile_hypergraph(c.text), oracle.run(c.text), "after refusal")
+
+
+def test_degenerate_circuits(drv25):
+    say("case degenerate")
+    # no noise at all
+    hg = drv25.compile_hypergraph("R 0 1\nCX 0 1\nM 0 1\nDETECTOR rec[-1] rec[-2]\n")
+    assert len(hg) == 0
+    # only undetectable faults
+    hg = drv25.compile_hypergraph("R 0\nZ_ERROR(0.1) 0\nM 0\nDETECTOR rec[-1]\n")
+    assert len(hg) == 0
+    # no detectors or observables at all: every fault is empty
+    hg = drv25.compile_hypergraph("R 0\nX_ERROR(0.1) 0\nM 0\n")
+    assert len(hg) == 0
+    # empty circuit
+    hg = drv25.compile_hypergraph("")
+    assert len(hg) == 0
+    # a single fault; observable only
+    hg = drv25.compile_hypergraph("R 0\nX_ERROR(0.25) 0\nM 0\nOBSERVABLE_INCLUDE(3) rec[-1]\n")
+    assert hg.edges() == {(3,): 0.25}
+    # DEPOLARIZE1 merges X and Y: q = 2r/3
+    hg = drv25.compile_hypergraph("R 0\nDEPOLARIZE1(0.003) 0\nM 0\nDETECTOR rec[-1]\n")
+    assert math.isclose(hg.edges()[(0,)], 0.002, rel_tol=1e-14)
+    # rate 0 keeps the structure with q = 0
+    text = "R 0 1\nX_ERROR(0) 0\nCX 0 1\nM 0 1\nDETECTOR rec[-1]\nDETECTOR rec[-2]\n"
+    assert_parity(drv25.compile_hypergraph(text), oracle.run(text), "zero rate")
+
+
+def test_error_paths(drv25):
+    say("case errors")
+    with pytest.raises(GpError) as e:
+        drv25.compile_hypergraph("R 0\nH 0\nM 0\nDETECTOR rec[-1]\n")
+    assert e.value.code == -5
+    with pytest.raises(GpError) as e:
+        drv25.compile_hypergraph("H 0\nM 0\nOBSERVABLE_INCLUDE(0) rec[-1]\n")
+    assert e.value.code == -5
+    c = rotated_surface_code_memory(3, 3)
+    with pytest.raises(GpError) as e:
+        drv25.compile_hypergraph(c.text, [1e-3] * (c.n_channels - 1))
+    assert e.value.code == -6
+    with pytest.raises(GpError) as e:
+        drv25.compile_hypergraph(c.text, [0.9] * c.n_channels)
+    assert e.value.code == -6
+    # still healthy afterwards
+    check(drv25, c.text, label="after errors")
+
+
+def test_dem_text_round_trip(drv25):
+    say("case dem")
+    c = rotated_surface_code_memory(3, 3)
+    dem = drv25.compile_detector_error_model(c.text)
+    ref = oracle.run(c.text).edges()
+    got = {}
+    D = 24
+    for line in dem.strip().splitlines():
+        head, *targets = line.split()
+        q = float(head[len("error("):-1])
+        bits = tuple(int(t[1:]) if t[0] == "D" else D + int(t[1:]) for t in targets)
+        got[bits] = q
+    assert set(got) == set(ref)
+    for k in ref:
+        assert math.isclose(got[k], ref[k], rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("bits", [8, 1])
+def test_forced_key_collisions(drv25, bits):
+    """Class keys cut to a few bits collide massively; the device detects it
+    through the check hash and the compile re-runs keyed on both hashes, so the
+    hypergraph is unchanged."""
+    c = rotated_surface_code_memory(7, 7)
+    _gp.gp_debug_set_key_bits(drv25.handle, bits)
+    try:
+        before = _gp.gp_debug_collision_retries(drv25.handle)
+        check(drv25, c.text, label=f"key bits {bits}")
+        assert _gp.gp_debug_collision_retries(drv25.handle) == before + 1
+    finally:
+        _gp.gp_debug_set_key_bits(drv25.handle, 64)
+    before = _gp.gp_debug_collision_retries(drv25.handle)
+    check(drv25, c.text, label="full keys again")
+    assert _gp.gp_debug_collision_retries(drv25.handle) == before

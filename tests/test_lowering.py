@@ -1,0 +1,52 @@
+"""The compiler's host lowering, replayed on the CPU by tests/host_check.cpp
+(same tables, same work items, same slab addressing, every access bounds
+checked), must give every fault the oracle's signature. No GPU needed."""
+
+import numpy as np
+import pytest
+
+import host_check
+import oracle
+from workloads import (bit_flip_code_fig1, bivariate_bicycle_memory, log_uniform_rates, mirror_circuit,
+                       repetition_code_memory, rotated_surface_code_memory)
+
+
+def compare(text, rates=None):
+    st, sigs = host_check.run(text, rates)
+    res = oracle.run(text, rates=rates, keep_faults=True)
+    osig = {(ch, code): sig for ch, code, sig, _ in res.fault_signatures()}
+    assert st["faults"] == res.n_faults == len(sigs)
+    assert sigs == osig
+    assert st["gauge"] == 0
+    return st
+
+
+def test_small_circuits():
+    compare(bit_flip_code_fig1().text)
+    compare(repetition_code_memory(5, 4, p_data=0.01, p_meas=0.01, p2=0.01, p1=0.01).text)
+    for s in range(6):
+        compare(mirror_circuit(5, 6, s, x_basis=[s % 5]).text)
+
+
+@pytest.mark.parametrize("d,r", [(3, 3), (5, 5), (7, 4), (9, 9)])
+def test_surface_code(d, r):
+    st = compare(rotated_surface_code_memory(d, r).text)
+    assert st["qubits"] == 2 * d * d - 1
+
+
+def test_surface_code_rates():
+    c = rotated_surface_code_memory(5, 3)
+    compare(c.text, log_uniform_rates(c.n_channels, 3))
+
+
+def test_bivariate_bicycle_short():
+    compare(bivariate_bicycle_memory(rounds=3).text)
+
+
+def test_gauge_flagged():
+    st, _ = host_check.run("R 0\nH 0\nM 0\nDETECTOR rec[-1]\n")
+    assert st["gauge"] == 1
+    st, _ = host_check.run("H 0\nM 0\nDETECTOR rec[-1]\n")
+    assert st["gauge"] == 1
+    st, _ = host_check.run("R 0\nM 0\nDETECTOR rec[-1]\n")
+    assert st["gauge"] == 0
