@@ -267,9 +267,9 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   gp_bounds& b = d->bounds;
   b.max_layers = std::max<uint32_t>(b.max_layers, 1);
   b.max_faults = std::max<uint64_t>(b.max_faults, 1);
-  if (b.max_faults >= (1ull << 32)) {
+  if (b.max_faults >= (1ull << 30)) {
     delete d;
-    return fail(GP_E_BOUNDS, "at most 2^32 - 1 faults per circuit");
+    return fail(GP_E_BOUNDS, "at most 2^30 - 1 faults per circuit");
   }
   d->max_w = std::max<uint32_t>(words_for(b.max_detectors, b.max_observables), 1);
   if (!b.max_slab_words) b.max_slab_words = b.max_faults * d->max_w;
@@ -308,8 +308,17 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
     if ((rc = dev_alloc(d, &st.val[k], F, "values"))) return cleanup(rc);
   }
   if ((rc = dev_alloc(d, &st.chk, F, "check hashes"))) return cleanup(rc);
-  if ((rc = dev_alloc(d, &st.hist, size_t(256) * d->max_tiles, "histograms"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.popc, F, "signature weights"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.nzm, F, "non-zero word masks"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.tile_cnt, size_t(d->max_tiles) + 1, "tile counts"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.part_hist, size_t(d->max_tiles) * gp::kMaxPasses * 256, "digit counts")))
+    return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.digit_off, size_t(gp::kMaxPasses) * 256, "digit offsets"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.lookback, size_t(gp::kMaxPasses) * d->max_tiles * 256, "look-back words")))
+    return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.tile_ctr, gp::kMaxPasses, "tile tickets"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.tile_sum, size_t(d->max_tiles) + 1, "tile sums"))) return cleanup(rc);
+  st.max_tiles = d->max_tiles;
   if ((rc = dev_alloc(d, &st.segstart, F, "class starts"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.seg_q, F, "class probabilities"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.seg_rep, F, "class representatives"))) return cleanup(rc);
@@ -515,6 +524,7 @@ int gp_circuit_info_get(const gp_driver* d, gp_circuit_info* out) {
     i.n_edges = d->h_hdr->n_edges;
     i.n_edge_bits = d->h_hdr->n_bits;
     i.n_live_words = d->h_hdr->n_words;
+    i.n_live_faults = d->h_hdr->n_live;
   }
   *out = i;
   return GP_OK;

@@ -10,21 +10,26 @@ namespace gp {
 
 // Device-side status block shared by the kernels of one compile.
 struct DevHeader {
-  uint32_t n_seg;      // classes found after sorting (incl. the empty one)
-  uint32_t empty_seg;  // class index of the empty signature, or 0xFFFFFFFF
-  uint32_t n_edges;    // hyperedges = classes minus the empty one
+  uint32_t n_seg;      // classes found after sorting
+  uint32_t empty_seg;  // class index of an empty signature, or 0xFFFFFFFF (none after compaction)
+  uint32_t n_edges;    // hyperedges
   uint32_t flags;      // FLAG_* bits
   uint64_t n_bits;     // total signature bits over all hyperedges
   uint64_t n_words;    // stage-1 signature words written (= words the hash reads)
+  uint32_t n_live;     // faults with a non-empty signature (the sorted ones)
+  uint32_t pad;
 };
 
 enum : uint32_t {
   FLAG_GAUGE = 1u,      // a detector/observable is sensitive right after a reset/measurement
-  FLAG_COLLISION = 2u,  // equal 64-bit keys with different check hashes
+  FLAG_COLLISION = 2u,  // equal class keys with different check hashes
   FLAG_OVERFLOW = 4u,   // output signature bits exceed the reserved capacity
+  FLAG_LOOKBACK = 8u,   // a sort tile gave up waiting for its predecessor (never expected)
 };
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr int kTile = 4096;       // items per tile in the sort, scan and compaction kernels
+constexpr int kMaxPasses = 8;     // 8-bit digits of a 64-bit key
 
 // Everything one compile reads or writes on the device.
 struct DevState {
@@ -56,6 +61,8 @@ struct DevState {
   // 1 = FNV-1a mixed with the check hash (used after a key collision)
   uint32_t key_mode;
   uint32_t key_bits;
+  uint32_t n_pass;      // radix passes (8-bit digits) over the class key
+  uint32_t max_tiles;   // tiles the sort/compaction scratch is sized for
 
   // work buffers
   uint64_t* slab;        // stage-1 signature words, column slabs
@@ -63,15 +70,21 @@ struct DevState {
   uint32_t* cov;         // per boundary: covered columns, ascending ((L+1) x W)
   uint32_t* ncov;        // per boundary: number of covered columns
   double* pfault;        // per fault position: probability
-  uint64_t* key[2];      // class key (FNV-1a), ping-pong for the sort
-  uint32_t* val[2];      // fault position, ping-pong for the sort
+  uint64_t* key[2];      // class keys: per position (key[1]) then compacted, ping-pong in the sort
+  uint32_t* val[2];      // fault positions riding with the keys
   uint64_t* chk;         // per fault position: check hash
-  uint32_t* hist;        // radix digit counts (256 x tiles)
+  uint32_t* popc;        // per fault position: signature weight
+  uint64_t* nzm;         // per fault position: which covered columns hold non-zero words
+  uint32_t* tile_cnt;    // per compaction tile: live faults, then their exclusive prefix
+  uint32_t* part_hist;   // per compaction tile: digit counts of every pass
+  uint32_t* digit_off;   // per pass: exclusive prefix of the digit counts
+  uint32_t* lookback;    // per pass, tile and digit: published count with status bits
+  uint32_t* tile_ctr;    // per pass: tile ticket counter
   uint32_t* tile_sum;    // scan tile sums
   uint32_t* segstart;    // first sorted index of each class
   double* seg_q;         // merged probability per class
   uint32_t* seg_rep;     // representative fault position per class
-  uint32_t* seg_cnt;     // signature bits per class (0 for the empty class)
+  uint32_t* seg_cnt;     // signature bits per class
   uint32_t* seg_off;     // exclusive prefix of seg_cnt
   uint32_t* edge_off32;  // per hyperedge: first bit (n_edges + 1)
   uint32_t* edge_bits;   // output signature bits (external numbering)
@@ -80,10 +93,10 @@ struct DevState {
   DevHeader* hdr;
 };
 
-// Names of the kernels, in launch order of one compile (for timing tables).
+// Names of the kernels (for timing tables).
 enum KernelId : int {
-  K_PREPARE = 0, K_SWEEP, K_COVER, K_HASH, K_RADIX_HIST, K_SCAN_SINGLE, K_RADIX_SCATTER,
-  K_HEADS_COUNT, K_HEADS_APPLY, K_REDUCE, K_SCAN_TILES, K_SCAN_APPLY, K_EDGE_WRITE, K_COUNT
+  K_PREPARE = 0, K_SWEEP, K_COVER, K_HASH, K_SCAN_SINGLE, K_COMPACT, K_DIGIT_OFFSETS, K_ONESWEEP,
+  K_HEADS_COUNT, K_HEADS_APPLY, K_REDUCE, K_REDUCE_BIG, K_SCAN_TILES, K_SCAN_APPLY, K_EDGE_WRITE, K_COUNT
 };
 const char* kernel_name(int id);
 
@@ -93,6 +106,10 @@ struct LaunchHook {
   void (*after)(void* ctx, int kernel_id) = nullptr;
   void* ctx = nullptr;
 };
+
+// Radix passes needed for `n` keys: enough key bits that two distinct classes
+// share them with probability below about 2^-12 (collisions are still caught).
+uint32_t sort_passes(uint64_t n);
 
 // Enqueue both stages for the lowered circuit described by `st`.
 hipError_t enqueue_compile(const DevState& st, hipStream_t stream, const LaunchHook& hook);

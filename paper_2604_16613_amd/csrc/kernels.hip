@@ -4,20 +4,25 @@
 // of the circuit backwards for one 64-bit word column of the class bit
 // vectors. The column's X/Z vertex words of all qubits live in LDS; a layer
 // is applied in place, one thread per operation (the operations of a layer
-// touch disjoint qubits, so their updates are independent). After each layer
-// the faults placed at that boundary read their qubits' words and write their
-// signature word (composite Paulis are XORs of the X and Z words, Sec. 2.3.4)
-// into the column's slab. A column's sweep starts at the highest layer that
-// holds one of its leaves and stops once its frame is all zero below its last
-// leaf: every lower boundary is then zero in that column and is not written.
+// touch disjoint qubits, so their updates are independent), while the next
+// layer's operations are already being fetched. After each layer the faults
+// placed at that boundary read their qubits' words and write their signature
+// word (composite Paulis are XORs of the X and Z words, Sec. 2.3.4) into the
+// column's slab. A column's sweep starts at the highest layer that holds one of
+// its leaves and stops once its frame is all zero below its last leaf: every
+// lower boundary is then zero in that column and is not written.
 //
 // Stage 2 (Sec. 3.2, Eq. 3): per fault, the 64-bit FNV-1a hash of its
-// signature's 8W octets (zero words only multiply by prime^8) as class key and
-// an independent check hash; a stable LSD radix sort of (key, fault) pairs;
-// class heads; merged probabilities q <- q + p(1 - 2q) per class in sorted
-// order; the class with the empty signature is dropped; the remaining classes
-// are written as bit lists. If two faults share a key but not a check hash,
-// the host re-runs the compile keyed on both hashes.
+// signature's 8W octets (zero words only multiply by prime^8) as class key, an
+// independent check hash, the signature weight and a mask of its non-zero
+// words. Faults with an empty signature are dropped by a stable compaction
+// (their class is never output). The rest are sorted by key with a stable LSD
+// radix sort: one histogram for all passes, then one kernel per 8-bit pass
+// that ranks a tile in LDS, finds its global offsets by looking back at the
+// tiles before it, and writes runs of equal digits contiguously. Class heads,
+// merged probabilities q <- q + p(1 - 2q) in sorted (fault) order, and the
+// hyperedges' bit lists follow. If two faults share a key but not a check
+// hash, the host re-runs the compile keyed on both hashes.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -30,11 +35,24 @@ namespace gp {
 namespace {
 
 constexpr int kSweepBlock = 256;
+constexpr int kSweepOps = 4;           // operations per thread held ahead in registers
 constexpr int kBlock = 256;
-constexpr int kTile = 4096;          // items per block in sort / scan kernels
 constexpr int kPerThread = kTile / kBlock;
 constexpr int kScanSingleBlock = 1024;
-constexpr uint32_t kBigSegment = 64;  // classes with more faults reduce in a whole block
+constexpr uint32_t kBigSegment = 64;   // classes with more faults reduce in a whole block
+constexpr int kHashLds = 512;          // cover-list entries a hash block stages in LDS
+constexpr uint32_t kLbAgg = 1u << 30;  // look-back status: tile aggregate published
+constexpr uint32_t kLbPre = 2u << 30;  // look-back status: inclusive prefix published
+constexpr uint32_t kLbMask = (1u << 30) - 1;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+// Barrier that orders LDS only: global loads issued before it (prefetches)
+// stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
   const int lane = threadIdx.x & 63;
@@ -43,6 +61,12 @@ __device__ __forceinline__ uint32_t wave_inclusive_scan(uint32_t v) {
     uint32_t t = __shfl_up(v, o, 64);
     if (lane >= o) v += t;
   }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   return v;
 }
 
@@ -110,16 +134,26 @@ __device__ __forceinline__ uint64_t leaf_word(const uint32_t* leaf_off, const ui
   return v;
 }
 
+__device__ __forceinline__ uint32_t digit_of(uint64_t k, uint32_t pass) { return uint32_t(k >> (8 * pass)) & 255u; }
+
 // ------------------------------------------------------------------ prepare
 
 __global__ void k_prepare(DevState st) {
   const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid < st.n_chan) {
-    const double p = fault_probability(st.chan_kind[gid], st.chan_rate[gid]);
-    const uint32_t f1 = st.chan_foff[gid + 1];
-    for (uint32_t f = st.chan_foff[gid]; f < f1; ++f) st.pfault[f] = p;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t c = gid; c < st.n_chan; c += stride) {
+    const double p = fault_probability(st.chan_kind[c], st.chan_rate[c]);
+    const uint32_t f1 = st.chan_foff[c + 1];
+    for (uint32_t f = st.chan_foff[c]; f < f1; ++f) st.pfault[f] = p;
   }
-  if (gid < st.w) st.cover_lo[gid] = 0;
+  for (uint32_t w = gid; w < st.w; w += stride) st.cover_lo[w] = 0;
+  const uint32_t ntiles = (st.n_faults + kTile - 1) / kTile;
+  for (uint32_t t = gid; t < ntiles + 1; t += stride) st.tile_cnt[t] = 0;
+  // look-back words of every pass (each pass owns max_tiles * 256 of them)
+  const uint32_t per_pass = ntiles * 256;
+  for (uint32_t i = gid; i < st.n_pass * per_pass; i += stride)
+    st.lookback[size_t(i / per_pass) * st.max_tiles * 256 + i % per_pass] = 0;
+  if (gid < kMaxPasses) st.tile_ctr[gid] = 0;
   if (gid == 0) {
     st.hdr->n_seg = 0;
     st.hdr->empty_seg = kNone;
@@ -127,12 +161,112 @@ __global__ void k_prepare(DevState st) {
     st.hdr->flags = 0;
     st.hdr->n_bits = 0;
     st.hdr->n_words = 0;
+    st.hdr->n_live = 0;
   }
 }
 
 // ------------------------------------------------------------------ stage 1
 
 __device__ __forceinline__ int nzd(uint64_t nv, uint64_t ov) { return int(nv != 0) - int(ov != 0); }
+
+// Apply one operation backwards to the frame (X_q at 2q, Z_q at 2q+1).
+__device__ __forceinline__ void apply_op(uint64_t op, uint64_t* frame, const DevState& st, uint32_t w, int& dnz,
+                                         int& gauge) {
+  const uint32_t kind = uint32_t(op >> 56);
+  const uint32_t a = uint32_t(op >> 28) & uint32_t(kField);
+  const uint32_t b = uint32_t(op) & uint32_t(kField);
+  uint64_t* fa = frame + 2 * a;
+  const uint64_t xa = fa[0], za = fa[1];
+  switch (kind) {
+    case OP_H:
+      fa[0] = za;
+      fa[1] = xa;
+      break;
+    case OP_S: {  // X -> XZ
+      const uint64_t n = xa ^ za;
+      fa[0] = n;
+      dnz += nzd(n, xa);
+      break;
+    }
+    case OP_SQRTX: {  // Z -> XZ
+      const uint64_t n = xa ^ za;
+      fa[1] = n;
+      dnz += nzd(n, za);
+      break;
+    }
+    case OP_CX: {  // X_c -> X_c X_t, Z_t -> Z_t Z_c
+      uint64_t* fb = frame + 2 * b;
+      const uint64_t xb = fb[0], zb = fb[1];
+      const uint64_t nxa = xa ^ xb, nzb = zb ^ za;
+      fa[0] = nxa;
+      fb[1] = nzb;
+      dnz += nzd(nxa, xa) + nzd(nzb, zb);
+      break;
+    }
+    case OP_CZ: {  // X_a -> X_a Z_b, X_b -> X_b Z_a
+      uint64_t* fb = frame + 2 * b;
+      const uint64_t xb = fb[0], zb = fb[1];
+      const uint64_t nxa = xa ^ zb, nxb = xb ^ za;
+      fa[0] = nxa;
+      fb[0] = nxb;
+      dnz += nzd(nxa, xa) + nzd(nxb, xb);
+      break;
+    }
+    case OP_SWAP: {
+      uint64_t* fb = frame + 2 * b;
+      const uint64_t xb = fb[0], zb = fb[1];
+      fa[0] = xb;
+      fa[1] = zb;
+      fb[0] = xa;
+      fb[1] = za;
+      break;
+    }
+    case OP_R:  // a Z error right after a Z reset must be invisible
+      gauge |= za != 0;
+      fa[0] = 0;
+      fa[1] = 0;
+      dnz -= int(xa != 0) + int(za != 0);
+      break;
+    case OP_RX:
+      gauge |= xa != 0;
+      fa[0] = 0;
+      fa[1] = 0;
+      dnz -= int(xa != 0) + int(za != 0);
+      break;
+    case OP_M: {  // X before the measurement flips it (leaf) and persists
+      gauge |= za != 0;
+      const uint64_t n = xa ^ leaf_word(st.leaf_off, st.leaf_bits, b, w);
+      fa[0] = n;
+      dnz += nzd(n, xa);
+      break;
+    }
+    case OP_MX: {
+      gauge |= xa != 0;
+      const uint64_t n = za ^ leaf_word(st.leaf_off, st.leaf_bits, b, w);
+      fa[1] = n;
+      dnz += nzd(n, za);
+      break;
+    }
+    case OP_MR: {  // the reset erases what the measurement did not see
+      gauge |= za != 0;
+      const uint64_t n = leaf_word(st.leaf_off, st.leaf_bits, b, w);
+      fa[0] = n;
+      fa[1] = 0;
+      dnz += nzd(n, xa) - int(za != 0);
+      break;
+    }
+    case OP_MRX: {
+      gauge |= xa != 0;
+      const uint64_t n = leaf_word(st.leaf_off, st.leaf_bits, b, w);
+      fa[1] = n;
+      fa[0] = 0;
+      dnz += nzd(n, za) - int(xa != 0);
+      break;
+    }
+    default:
+      break;
+  }
+}
 
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   extern __shared__ uint64_t frame[];  // X_q at 2q, Z_q at 2q+1
@@ -148,112 +282,39 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   const uint32_t nv = 2 * st.n_qubits;
   for (uint32_t i = tid; i < nv; i += kSweepBlock) frame[i] = 0;
   if (tid == 0) s_nz = 0;
-  __syncthreads();
   int gauge = 0;
   bool dead = false;
+  // operations of layer t held in registers; kind 0 marks an empty slot
+  uint64_t cur[kSweepOps];
+  {
+    const uint32_t o0 = st.layer_off[top] + tid, o1 = st.layer_off[top + 1];
+#pragma unroll
+    for (int k = 0; k < kSweepOps; ++k) cur[k] = (o0 + k * kSweepBlock < o1) ? st.ops[o0 + k * kSweepBlock] : 0;
+  }
+  __syncthreads();
   for (int t = top; t >= blo; --t) {
+    // fetch layer t-1 while layer t is applied
+    uint64_t nxt[kSweepOps];
+    if (t - 1 >= blo) {
+      const uint32_t o0 = st.layer_off[t - 1] + tid, o1 = st.layer_off[t];
+#pragma unroll
+      for (int k = 0; k < kSweepOps; ++k) nxt[k] = (o0 + k * kSweepBlock < o1) ? st.ops[o0 + k * kSweepBlock] : 0;
+    } else {
+#pragma unroll
+      for (int k = 0; k < kSweepOps; ++k) nxt[k] = 0;
+    }
     // transform the frame from boundary t+1 to boundary t (one layer, in place)
     int dnz = 0;
-    const uint32_t o1 = st.layer_off[t + 1];
-    for (uint32_t o = st.layer_off[t] + tid; o < o1; o += kSweepBlock) {
-      const uint64_t op = st.ops[o];
-      const uint32_t kind = uint32_t(op >> 56);
-      const uint32_t a = uint32_t(op >> 28) & uint32_t(kField);
-      const uint32_t b = uint32_t(op) & uint32_t(kField);
-      uint64_t* fa = frame + 2 * a;
-      const uint64_t xa = fa[0], za = fa[1];
-      switch (kind) {
-        case OP_H:
-          fa[0] = za;
-          fa[1] = xa;
-          break;
-        case OP_S: {  // X -> XZ
-          const uint64_t n = xa ^ za;
-          fa[0] = n;
-          dnz += nzd(n, xa);
-          break;
-        }
-        case OP_SQRTX: {  // Z -> XZ
-          const uint64_t n = xa ^ za;
-          fa[1] = n;
-          dnz += nzd(n, za);
-          break;
-        }
-        case OP_CX: {  // X_c -> X_c X_t, Z_t -> Z_t Z_c
-          uint64_t* fb = frame + 2 * b;
-          const uint64_t xb = fb[0], zb = fb[1];
-          const uint64_t nxa = xa ^ xb, nzb = zb ^ za;
-          fa[0] = nxa;
-          fb[1] = nzb;
-          dnz += nzd(nxa, xa) + nzd(nzb, zb);
-          break;
-        }
-        case OP_CZ: {  // X_a -> X_a Z_b, X_b -> X_b Z_a
-          uint64_t* fb = frame + 2 * b;
-          const uint64_t xb = fb[0], zb = fb[1];
-          const uint64_t nxa = xa ^ zb, nxb = xb ^ za;
-          fa[0] = nxa;
-          fb[0] = nxb;
-          dnz += nzd(nxa, xa) + nzd(nxb, xb);
-          break;
-        }
-        case OP_SWAP: {
-          uint64_t* fb = frame + 2 * b;
-          const uint64_t xb = fb[0], zb = fb[1];
-          fa[0] = xb;
-          fa[1] = zb;
-          fb[0] = xa;
-          fb[1] = za;
-          break;
-        }
-        case OP_R:  // a Z error right after a Z reset must be invisible
-          gauge |= za != 0;
-          fa[0] = 0;
-          fa[1] = 0;
-          dnz -= int(xa != 0) + int(za != 0);
-          break;
-        case OP_RX:
-          gauge |= xa != 0;
-          fa[0] = 0;
-          fa[1] = 0;
-          dnz -= int(xa != 0) + int(za != 0);
-          break;
-        case OP_M: {  // X before the measurement flips it (leaf) and persists
-          gauge |= za != 0;
-          const uint64_t n = xa ^ leaf_word(st.leaf_off, st.leaf_bits, b, w);
-          fa[0] = n;
-          dnz += nzd(n, xa);
-          break;
-        }
-        case OP_MX: {
-          gauge |= xa != 0;
-          const uint64_t n = za ^ leaf_word(st.leaf_off, st.leaf_bits, b, w);
-          fa[1] = n;
-          dnz += nzd(n, za);
-          break;
-        }
-        case OP_MR: {  // the reset erases what the measurement did not see
-          gauge |= za != 0;
-          const uint64_t n = leaf_word(st.leaf_off, st.leaf_bits, b, w);
-          fa[0] = n;
-          fa[1] = 0;
-          dnz += nzd(n, xa) - int(za != 0);
-          break;
-        }
-        case OP_MRX: {
-          gauge |= xa != 0;
-          const uint64_t n = leaf_word(st.leaf_off, st.leaf_bits, b, w);
-          fa[1] = n;
-          fa[0] = 0;
-          dnz += nzd(n, za) - int(xa != 0);
-          break;
-        }
-        default:
-          break;
-      }
+#pragma unroll
+    for (int k = 0; k < kSweepOps; ++k)
+      if (cur[k]) apply_op(cur[k], frame, st, w, dnz, gauge);
+    {
+      const uint32_t o1 = st.layer_off[t + 1];
+      for (uint32_t o = st.layer_off[t] + tid + kSweepOps * kSweepBlock; o < o1; o += kSweepBlock)
+        apply_op(st.ops[o], frame, st, w, dnz, gauge);
     }
     if (dnz) atomicAdd(&s_nz, dnz);
-    __syncthreads();
+    lds_barrier();
     const int nz = s_nz;
     // faults at boundary t: signature word = XOR of their Pauli's X/Z words
     if (t <= bhi) {
@@ -293,7 +354,9 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
       dead = true;
       break;
     }
-    __syncthreads();
+    lds_barrier();
+#pragma unroll
+    for (int k = 0; k < kSweepOps; ++k) cur[k] = nxt[k];
   }
   if (!dead && blo == 0) {
     // every qubit starts in |0>: a Z error at the very start must be invisible
@@ -302,131 +365,88 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   if (gauge) atomicOr(&st.hdr->flags, FLAG_GAUGE);
 }
 
-// Per boundary, the ascending list of columns whose word there may be non-zero.
-__global__ void k_cover(DevState st) {
-  const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b > st.n_layers) return;
-  uint32_t n = 0;
+// Per boundary (one block each), the ascending list of columns whose word there
+// may be non-zero.
+__global__ __launch_bounds__(kBlock) void k_cover(DevState st) {
+  __shared__ uint32_t s_wave[kBlock / 64 + 1];
+  const uint32_t b = blockIdx.x;
   uint32_t* dst = st.cov + size_t(b) * st.w;
-  for (uint32_t w = 0; w < st.w; ++w) {
-    const int top = st.col_top[w];
-    if (top >= 0 && int(b) <= top && int(b) >= st.cover_lo[w]) dst[n++] = w;
+  uint32_t n = 0;
+  for (uint32_t w0 = 0; w0 < st.w; w0 += kBlock) {
+    const uint32_t w = w0 + threadIdx.x;
+    uint32_t f = 0;
+    if (w < st.w) {
+      const int top = st.col_top[w];
+      f = (top >= 0 && int(b) <= top && int(b) >= st.cover_lo[w]) ? 1u : 0u;
+    }
+    const uint32_t at = block_exclusive_scan<kBlock>(f, s_wave);
+    if (f) dst[n + at] = w;
+    n += s_wave[kBlock / 64];
+    __syncthreads();
   }
-  st.ncov[b] = n;
+  if (threadIdx.x == 0) st.ncov[b] = n;
 }
 
 // ------------------------------------------------------------------ stage 2
 
-// FNV-1a over the W words of each fault's signature, word-wise
-// (h <- (h ^ word) * prime); a run of k zero words multiplies by prime^k.
+// FNV-1a over the 8W octets of each fault's signature (h <- (h ^ octet) *
+// prime), a run of k zero words multiplying by prime^(8k); the check hash, the
+// weight and the non-zero-word mask; live-fault counts per compaction tile.
 __global__ __launch_bounds__(kBlock) void k_hash(DevState st) {
+  __shared__ uint32_t s_w[kHashLds];
+  __shared__ uint64_t s_base[kHashLds];
+  __shared__ uint32_t s_b0, s_n0;
   const uint32_t pos = blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = pos < st.n_faults;
   const uint32_t b = valid ? boundary_of(st.bnd_fault_off, st.n_layers + 1, pos) : 0;
   const uint32_t n = valid ? st.ncov[b] : 0;
-  {
-    // words read here = words stage 1 wrote; one atomic per wave (all lanes
-    // take part in the sum, lanes past the end contribute 0)
-    uint32_t t = n;
+  // stage the cover list of the block's first boundary
+  if (threadIdx.x == 0) {
+    s_b0 = b;
+    s_n0 = n;
+  }
+  __syncthreads();
+  const uint32_t b0 = s_b0, n0 = s_n0 < kHashLds ? s_n0 : 0;
+  for (uint32_t k = threadIdx.x; k < n0; k += kBlock) {
+    const uint32_t w = st.cov[size_t(b0) * st.w + k];
+    s_w[k] = w;
+    s_base[k] = st.col_base[w];
+  }
+  __syncthreads();
+  uint64_t h1 = kFnvOffset, h2 = 0, mask = 0;
+  uint32_t wn = 0, weight = 0;
+  if (valid) {
+    const bool staged = (b == b0) && n0 == n;
+    const uint32_t* cl = st.cov + size_t(b) * st.w;
+    for (uint32_t k = 0; k < n; ++k) {
+      const uint32_t w = staged ? s_w[k] : cl[k];
+      const uint64_t base = staged ? s_base[k] : st.col_base[w];
+      const uint64_t v = st.slab[base + pos];
+      if (v) {
+        h1 *= st.fnv_pow[w - wn];
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
-    if ((threadIdx.x & 63) == 0 && t)
-      atomicAdd(reinterpret_cast<unsigned long long*>(&st.hdr->n_words), static_cast<unsigned long long>(t));
-  }
-  if (!valid) return;
-  const uint32_t* cl = st.cov + size_t(b) * st.w;
-  uint64_t h1 = kFnvOffset, h2 = 0;
-  uint32_t wn = 0;
-  for (uint32_t k = 0; k < n; ++k) {
-    const uint32_t w = cl[k];
-    const uint64_t v = st.slab[st.col_base[w] + pos];
-    if (v) {
-      h1 *= st.fnv_pow[w - wn];
-#pragma unroll
-      for (int o = 0; o < 8; ++o) h1 = (h1 ^ ((v >> (8 * o)) & 0xffu)) * kFnvPrime;
-      wn = w + 1;
-      h2 += check_term(w, v);
+        for (int o = 0; o < 8; ++o) h1 = (h1 ^ ((v >> (8 * o)) & 0xffu)) * kFnvPrime;
+        wn = w + 1;
+        h2 += check_term(w, v);
+        weight += __popcll(v);
+        if (k < 64) mask |= 1ull << k;
+      }
     }
+    h1 *= st.fnv_pow[st.w - wn];
+    uint64_t key = h1;
+    if (st.key_mode == 1) key = h1 ^ fmix64(h2 ^ 0x5851f42d4c957f2dull);
+    if (st.key_bits < 64) key &= (1ull << st.key_bits) - 1;
+    st.key[1][pos] = key;
+    st.chk[pos] = h2;
+    st.popc[pos] = weight;
+    st.nzm[pos] = mask;
   }
-  h1 *= st.fnv_pow[st.w - wn];
-  uint64_t key = h1;
-  if (st.key_mode == 1) key = h1 ^ fmix64(h2 ^ 0x5851f42d4c957f2dull);
-  else if (st.key_bits < 64) key &= (1ull << st.key_bits) - 1;
-  st.key[0][pos] = key;
-  st.chk[pos] = h2;
-  st.val[0][pos] = pos;
-}
-
-__global__ __launch_bounds__(kBlock) void k_radix_hist(const uint64_t* __restrict__ keys, uint32_t n, int shift,
-                                                       uint32_t* __restrict__ hist, uint32_t ntiles) {
-  __shared__ uint32_t h[256];
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const uint32_t base = blockIdx.x * kTile;
-#pragma unroll 4
-  for (int r = 0; r < kPerThread; ++r) {
-    const uint32_t i = base + r * kBlock + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1u);
-  }
-  __syncthreads();
-  hist[threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
-}
-
-// Stable scatter of one 8-bit digit. Wave v of the block owns items
-// [v*1024, (v+1)*1024) of the tile and ranks them in order, 64 at a time.
-__global__ __launch_bounds__(kBlock) void k_radix_scatter(const uint64_t* __restrict__ kin,
-                                                          const uint32_t* __restrict__ vin,
-                                                          uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                          uint32_t n, int shift, const uint32_t* __restrict__ offs,
-                                                          uint32_t ntiles) {
-  __shared__ uint32_t cnt[kBlock / 64][256];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int k = tid; k < (kBlock / 64) * 256; k += kBlock) (&cnt[0][0])[k] = 0;
-  __syncthreads();
-  const uint32_t base = blockIdx.x * kTile + wv * (kTile / (kBlock / 64));
-  constexpr int kRounds = kTile / kBlock;
-  for (int r = 0; r < kRounds; ++r) {
-    const uint32_t i = base + r * 64 + lane;
-    if (i < n) atomicAdd(&cnt[wv][(kin[i] >> shift) & 255], 1u);
-  }
-  __syncthreads();
-  {
-    uint32_t run = offs[tid * ntiles + blockIdx.x];
-    for (int v = 0; v < kBlock / 64; ++v) {
-      const uint32_t c = cnt[v][tid];
-      cnt[v][tid] = run;
-      run += c;
-    }
-  }
-  __syncthreads();
-  const uint64_t lt = (1ull << lane) - 1;
-  for (int r = 0; r < kRounds; ++r) {
-    const uint32_t i = base + r * 64 + lane;
-    const bool valid = i < n;
-    uint64_t k = 0;
-    uint32_t v = 0, d = 0;
-    if (valid) {
-      k = kin[i];
-      v = vin[i];
-      d = uint32_t(k >> shift) & 255u;
-    }
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
-      const bool on = (d >> bit) & 1u;
-      const uint64_t m = __ballot(on);
-      peers &= on ? m : ~m;
-    }
-    const uint32_t rank = __popcll(peers & lt);
-    uint32_t dst = 0;
-    if (valid) dst = cnt[wv][d] + rank;
-    __builtin_amdgcn_wave_barrier();
-    if (valid && rank == 0) cnt[wv][d] += __popcll(peers);
-    __builtin_amdgcn_wave_barrier();
-    if (valid) {
-      kout[dst] = k;
-      vout[dst] = v;
-    }
+  // words read here = words stage 1 wrote; live faults per compaction tile
+  const uint32_t t_words = wave_sum(n);
+  const uint32_t t_live = wave_sum(weight ? 1u : 0u);
+  if ((threadIdx.x & 63) == 0) {
+    if (t_words) atomicAdd(reinterpret_cast<unsigned long long*>(&st.hdr->n_words), (unsigned long long)t_words);
+    if (t_live) atomicAdd(&st.tile_cnt[(blockIdx.x * blockDim.x) / kTile], t_live);
   }
 }
 
@@ -448,6 +468,164 @@ __global__ __launch_bounds__(kScanSingleBlock) void k_scan_single(uint32_t* data
     run += v;
   }
   if (threadIdx.x == 0 && total) *total = TotalT(s_wave[kScanSingleBlock / 64]);
+}
+
+// Stable compaction of the live faults (non-empty signatures) into (key,
+// position) pairs, with the digit counts of every radix pass for this tile.
+__global__ __launch_bounds__(kBlock) void k_compact(DevState st) {
+  __shared__ uint32_t s_wave[kBlock / 64 + 1];
+  __shared__ uint32_t s_hist[kMaxPasses][256];
+  const uint32_t tile = blockIdx.x;
+  for (uint32_t i = threadIdx.x; i < kMaxPasses * 256; i += kBlock) (&s_hist[0][0])[i] = 0;
+  const uint32_t i0 = tile * kTile + threadIdx.x * kPerThread;
+  uint32_t flags = 0, s = 0;
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    const uint32_t i = i0 + k;
+    const bool live = i < st.n_faults && st.popc[i] != 0;
+    flags |= uint32_t(live) << k;
+    s += live;
+  }
+  uint32_t run = block_exclusive_scan<kBlock>(s, s_wave) + st.tile_cnt[tile];
+  const uint32_t P = st.n_pass;
+#pragma unroll
+  for (int k = 0; k < kPerThread; ++k) {
+    if ((flags >> k) & 1u) {
+      const uint32_t i = i0 + k;
+      const uint64_t key = st.key[1][i];
+      st.key[0][run] = key;
+      st.val[0][run] = i;
+      run++;
+      for (uint32_t p = 0; p < P; ++p) atomicAdd(&s_hist[p][digit_of(key, p)], 1u);
+    }
+  }
+  __syncthreads();
+  uint32_t* part = st.part_hist + size_t(tile) * kMaxPasses * 256;
+  for (uint32_t p = 0; p < P; ++p) part[p * 256 + threadIdx.x] = s_hist[p][threadIdx.x];
+}
+
+// Per pass (one block each): total digit counts over all tiles, exclusive prefix.
+__global__ __launch_bounds__(256) void k_digit_offsets(DevState st, uint32_t ntiles) {
+  __shared__ uint32_t s_wave[256 / 64 + 1];
+  const uint32_t p = blockIdx.x, d = threadIdx.x;
+  uint32_t tot = 0;
+  for (uint32_t t = 0; t < ntiles; ++t) tot += st.part_hist[(size_t(t) * kMaxPasses + p) * 256 + d];
+  const uint32_t ex = block_exclusive_scan<256>(tot, s_wave);
+  st.digit_off[p * 256 + d] = ex;
+}
+
+// One stable pass of 8-bit digits over the live keys (n = hdr->n_live). Tiles
+// are taken in ticket order, so every tile a block waits for is already
+// running. Wave v ranks tile items [v*1024, (v+1)*1024) in order, 64 at a time.
+__global__ __launch_bounds__(kBlock) void k_onesweep(DevState st, uint32_t pass, const uint64_t* __restrict__ kin,
+                                                     const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
+                                                     uint32_t* __restrict__ vout) {
+  __shared__ uint64_t s_key[kTile];
+  __shared__ uint32_t s_val[kTile];
+  __shared__ uint32_t s_cnt[kBlock / 64][256];
+  __shared__ uint32_t s_start[256];
+  __shared__ uint32_t s_gbase[256];
+  __shared__ uint32_t s_wave[kBlock / 64 + 1];
+  __shared__ uint32_t s_tile;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint32_t n = st.hdr->n_live;
+  const uint32_t ntiles = (n + kTile - 1) / kTile;
+  if (tid == 0) s_tile = atomicAdd(&st.tile_ctr[pass], 1u);
+  for (int k = tid; k < (kBlock / 64) * 256; k += kBlock) (&s_cnt[0][0])[k] = 0;
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  if (tile >= ntiles) return;
+  const uint32_t base = tile * kTile + wv * (kTile / (kBlock / 64));
+  constexpr int kRounds = kTile / kBlock;
+  uint64_t k[kRounds];
+  uint32_t v[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const uint32_t i = base + r * 64 + lane;
+    k[r] = i < n ? kin[i] : 0;
+    v[r] = i < n ? vin[i] : 0;
+  }
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r)
+    if (base + r * 64 + lane < n) atomicAdd(&s_cnt[wv][digit_of(k[r], pass)], 1u);
+  __syncthreads();
+  // thread d: tile count of digit d, publish, look back for the tiles before
+  {
+    const uint32_t d = tid;
+    uint32_t tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) tot += s_cnt[w][d];
+    uint32_t* lb = st.lookback + size_t(pass) * st.max_tiles * 256;
+    uint32_t excl = 0;
+    if (tile == 0) {
+      __hip_atomic_store(&lb[d], kLbPre | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      __hip_atomic_store(&lb[size_t(tile) * 256 + d], kLbAgg | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int j = int(tile) - 1;
+      uint32_t spins = 0;
+      while (j >= 0) {
+        const uint32_t x = __hip_atomic_load(&lb[size_t(j) * 256 + d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((x & ~kLbMask) == 0) {
+          if (++spins > kSpinLimit) {
+            atomicOr(&st.hdr->flags, FLAG_LOOKBACK);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+          continue;
+        }
+        excl += x & kLbMask;
+        if (x & kLbPre) break;
+        --j;
+      }
+      __hip_atomic_store(&lb[size_t(tile) * 256 + d], kLbPre | (excl + tot), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_gbase[d] = st.digit_off[pass * 256 + d] + excl;
+    const uint32_t start = block_exclusive_scan<kBlock>(tot, s_wave);
+    s_start[d] = start;
+    uint32_t run = start;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+      const uint32_t c = s_cnt[w][d];
+      s_cnt[w][d] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  // rank in order and place into LDS sorted by digit
+  const uint64_t lt = (1ull << lane) - 1;
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const bool valid = base + r * 64 + lane < n;
+    const uint32_t d = valid ? digit_of(k[r], pass) : 0u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool on = (d >> bit) & 1u;
+      const uint64_t m = __ballot(on);
+      peers &= on ? m : ~m;
+    }
+    const uint32_t rank = __popcll(peers & lt);
+    uint32_t li = 0;
+    if (valid) li = s_cnt[wv][d] + rank;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && rank == 0) s_cnt[wv][d] += __popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    if (valid) {
+      s_key[li] = k[r];
+      s_val[li] = v[r];
+    }
+  }
+  __syncthreads();
+  // write runs of equal digits to consecutive global positions
+  const uint32_t cnt = min(uint32_t(kTile), n - tile * kTile);
+  for (uint32_t li = tid; li < cnt; li += kBlock) {
+    const uint64_t key = s_key[li];
+    const uint32_t d = digit_of(key, pass);
+    const uint32_t dst = s_gbase[d] + (li - s_start[d]);
+    kout[dst] = key;
+    vout[dst] = s_val[li];
+  }
 }
 
 // Tile sums of n words (n = *n_dev when given).
@@ -493,10 +671,11 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const uint32_t* __restric
   }
 }
 
-// Class heads in the sorted key array: counts per tile.
-__global__ __launch_bounds__(kBlock) void k_heads_count(const uint64_t* __restrict__ keys, uint32_t n,
+// Class heads in the sorted key array (n = hdr->n_live): counts per tile.
+__global__ __launch_bounds__(kBlock) void k_heads_count(const uint64_t* __restrict__ keys, const DevHeader* hdr,
                                                         uint32_t* __restrict__ tile_sum) {
   __shared__ uint32_t s_wave[kBlock / 64 + 1];
+  const uint32_t n = hdr->n_live;
   const uint32_t base = blockIdx.x * kTile;
   uint32_t s = 0;
   for (int r = 0; r < kPerThread; ++r) {
@@ -508,10 +687,11 @@ __global__ __launch_bounds__(kBlock) void k_heads_count(const uint64_t* __restri
 }
 
 // segstart[class] = first sorted index of the class.
-__global__ __launch_bounds__(kBlock) void k_heads_apply(const uint64_t* __restrict__ keys, uint32_t n,
+__global__ __launch_bounds__(kBlock) void k_heads_apply(const uint64_t* __restrict__ keys, const DevHeader* hdr,
                                                         const uint32_t* __restrict__ tile_off,
                                                         uint32_t* __restrict__ segstart) {
   __shared__ uint32_t s_wave[kBlock / 64 + 1];
+  const uint32_t n = hdr->n_live;
   const uint32_t i0 = blockIdx.x * kTile + threadIdx.x * kPerThread;
   uint32_t flags = 0, s = 0;
 #pragma unroll
@@ -527,25 +707,16 @@ __global__ __launch_bounds__(kBlock) void k_heads_apply(const uint64_t* __restri
     if ((flags >> k) & 1u) segstart[run++] = i0 + k;
 }
 
-__device__ __forceinline__ uint32_t signature_popcount(const DevState& st, uint32_t pos) {
-  const uint32_t b = boundary_of(st.bnd_fault_off, st.n_layers + 1, pos);
-  const uint32_t n = st.ncov[b];
-  const uint32_t* cl = st.cov + size_t(b) * st.w;
-  uint32_t c = 0;
-  for (uint32_t k = 0; k < n; ++k) c += __popcll(st.slab[st.col_base[cl[k]] + pos]);
-  return c;
-}
-
 // One thread per class of at most kBigSegment faults: merge probabilities in
-// sorted (fault position) order, check the check hashes agree, count bits.
-__global__ __launch_bounds__(kBlock) void k_reduce(DevState st, uint32_t n) {
+// sorted (fault position) order and check that the check hashes agree.
+__global__ __launch_bounds__(kBlock) void k_reduce(DevState st, const uint32_t* __restrict__ vals) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t S = st.hdr->n_seg;
   if (s >= S) return;
+  const uint32_t n = st.hdr->n_live;
   const uint32_t i0 = st.segstart[s];
   const uint32_t i1 = (s + 1 < S) ? st.segstart[s + 1] : n;
   if (i1 - i0 > kBigSegment) return;  // handled by k_reduce_big
-  const uint32_t* vals = st.val[0];
   const uint32_t rep = vals[i0];
   const uint64_t c0 = st.chk[rep];
   bool bad = false;
@@ -557,21 +728,19 @@ __global__ __launch_bounds__(kBlock) void k_reduce(DevState st, uint32_t n) {
     q = fma(p, 1.0 - 2.0 * q, q);  // Eq. 3: q(1-p) + p(1-q)
   }
   if (bad) atomicOr(&st.hdr->flags, FLAG_COLLISION);
-  const uint32_t cnt = signature_popcount(st, rep);
   st.seg_q[s] = q;
   st.seg_rep[s] = rep;
-  if (cnt == 0) st.hdr->empty_seg = s;
-  st.seg_cnt[s] = cnt;
+  st.seg_cnt[s] = st.popc[rep];
 }
 
-// One block per class of more than kBigSegment faults (grid-stride over classes):
-// strided partial merges per thread, then a fixed-shape tree, so the result is
-// the same on every run.
-__global__ __launch_bounds__(kBlock) void k_reduce_big(DevState st, uint32_t n) {
+// One block per class of more than kBigSegment faults (grid-stride over
+// classes): strided partial merges per thread, then a fixed-shape tree, so the
+// result is the same on every run.
+__global__ __launch_bounds__(kBlock) void k_reduce_big(DevState st, const uint32_t* __restrict__ vals) {
   __shared__ double s_q[kBlock];
   __shared__ int s_bad;
   const uint32_t S = st.hdr->n_seg;
-  const uint32_t* vals = st.val[0];
+  const uint32_t n = st.hdr->n_live;
   for (uint32_t s = blockIdx.x; s < S; s += gridDim.x) {
     const uint32_t i0 = st.segstart[s];
     const uint32_t i1 = (s + 1 < S) ? st.segstart[s + 1] : n;
@@ -598,33 +767,28 @@ __global__ __launch_bounds__(kBlock) void k_reduce_big(DevState st, uint32_t n) 
     }
     if (threadIdx.x == 0) {
       if (s_bad) atomicOr(&st.hdr->flags, FLAG_COLLISION);
-      const uint32_t cnt = signature_popcount(st, rep);
       st.seg_q[s] = s_q[0];
       st.seg_rep[s] = rep;
-      if (cnt == 0) st.hdr->empty_seg = s;
-      st.seg_cnt[s] = cnt;
+      st.seg_cnt[s] = st.popc[rep];
     }
     __syncthreads();
   }
 }
 
-// Hyperedge e (class s without the empty one): bits in external numbering
-// (detector d -> d, observable k -> D + k) and its probability.
+// Hyperedge e = class s: bits in external numbering (detector d -> d,
+// observable k -> D + k) and its probability.
 __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t S = st.hdr->n_seg;
-  const uint32_t empty = st.hdr->empty_seg;
-  const uint32_t U = S - (empty != kNone ? 1u : 0u);
   if (s == 0) {
-    st.hdr->n_edges = U;
-    st.edge_off32[U] = uint32_t(st.hdr->n_bits);
+    st.hdr->n_edges = S;
+    st.edge_off32[S] = uint32_t(st.hdr->n_bits);
     if (st.hdr->n_bits > st.bits_cap) atomicOr(&st.hdr->flags, FLAG_OVERFLOW);
   }
-  if (s >= S || s == empty) return;
-  const uint32_t e = s - ((empty != kNone && s > empty) ? 1u : 0u);
+  if (s >= S) return;
   const uint32_t o0 = st.seg_off[s];
-  st.edge_off32[e] = o0;
-  st.edge_q[e] = st.seg_q[s];
+  st.edge_off32[s] = o0;
+  st.edge_q[s] = st.seg_q[s];
   if (uint64_t(o0) + st.seg_cnt[s] > st.bits_cap) return;
   const uint32_t pos = st.seg_rep[s];
   const uint32_t b = boundary_of(st.bnd_fault_off, st.n_layers + 1, pos);
@@ -632,14 +796,24 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
   const uint32_t* cl = st.cov + size_t(b) * st.w;
   uint32_t o = o0;
   const uint32_t obs0 = st.wd * 64;
-  for (uint32_t k = 0; k < n; ++k) {
-    const uint32_t w = cl[k];
+  auto emit = [&](uint32_t w) {
     uint64_t v = st.slab[st.col_base[w] + pos];
     while (v) {
       const uint32_t bit = w * 64 + uint32_t(__builtin_ctzll(v));
       st.edge_bits[o++] = bit < obs0 ? bit : st.n_det + (bit - obs0);
       v &= v - 1;
     }
+  };
+  if (n <= 64) {
+    // the mask names the covered columns that hold non-zero words
+    uint64_t mask = st.nzm[pos];
+    while (mask) {
+      const uint32_t k = uint32_t(__builtin_ctzll(mask));
+      mask &= mask - 1;
+      emit(cl[k]);
+    }
+  } else {
+    for (uint32_t k = 0; k < n; ++k) emit(cl[k]);
   }
 }
 
@@ -648,11 +822,20 @@ inline uint32_t cdiv(uint64_t a, uint64_t b) { return uint32_t((a + b - 1) / b);
 }  // namespace
 
 const char* kernel_name(int id) {
-  static const char* names[K_COUNT] = {"k_prepare",      "k_sweep",       "k_cover",        "k_hash",
-                                       "k_radix_hist",   "k_scan_single", "k_radix_scatter", "k_heads_count",
-                                       "k_heads_apply",  "k_reduce",      "k_scan_tiles",   "k_scan_apply",
-                                       "k_edge_write"};
+  static const char* names[K_COUNT] = {"k_prepare",     "k_sweep",      "k_cover",      "k_hash",
+                                       "k_scan_single", "k_compact",    "k_digit_offsets", "k_onesweep",
+                                       "k_heads_count", "k_heads_apply", "k_reduce",     "k_reduce_big",
+                                       "k_scan_tiles",  "k_scan_apply", "k_edge_write"};
   return (id >= 0 && id < K_COUNT) ? names[id] : "?";
+}
+
+uint32_t sort_passes(uint64_t n) {
+  uint32_t lg = 1;
+  while ((1ull << lg) < n && lg < 40) lg++;
+  uint32_t bits = 2 * lg + 12;
+  if (bits < 16) bits = 16;
+  uint32_t p = (bits + 7) / 8;
+  return p > uint32_t(kMaxPasses) ? uint32_t(kMaxPasses) : p;
 }
 
 size_t sweep_lds_bytes(uint32_t n_qubits) { return size_t(2) * n_qubits * sizeof(uint64_t); }
@@ -682,46 +865,59 @@ hipError_t configure_kernels() {
   return hipSuccess;
 }
 
-#define GP_LAUNCH(id, ...)                     \
-  do {                                         \
+#define GP_LAUNCH(id, ...)                      \
+  do {                                          \
     if (hook.before) hook.before(hook.ctx, id); \
-    __VA_ARGS__;                               \
-    if (hook.after) hook.after(hook.ctx, id);  \
-    hipError_t _e = hipGetLastError();         \
-    if (_e != hipSuccess) return _e;           \
+    __VA_ARGS__;                                \
+    if (hook.after) hook.after(hook.ctx, id);   \
+    hipError_t _e = hipGetLastError();          \
+    if (_e != hipSuccess) return _e;            \
   } while (0)
 
-hipError_t enqueue_compile(const DevState& st, hipStream_t stream, const LaunchHook& hook) {
+hipError_t enqueue_compile(const DevState& st_in, hipStream_t stream, const LaunchHook& hook) {
+  DevState st = st_in;
   const uint32_t n = st.n_faults;
+  const uint32_t ntiles = cdiv(n ? n : 1, kTile);
+  // passes: enough key bits for the faults; every bit after a collision
+  if (st.key_mode == 1) {
+    st.n_pass = kMaxPasses;
+    st.key_bits = 64;
+  } else {
+    st.n_pass = sort_passes(n);
+    if (8 * st.n_pass < st.key_bits) st.key_bits = 8 * st.n_pass;
+  }
   {
-    const uint32_t m = st.n_chan > st.w ? st.n_chan : st.w;
-    GP_LAUNCH(K_PREPARE, k_prepare<<<cdiv(m ? m : 1, kBlock), kBlock, 0, stream>>>(st));
+    const uint32_t m = st.n_chan > st.n_pass * ntiles * 256 ? st.n_chan : st.n_pass * ntiles * 256;
+    uint32_t g = cdiv(m ? m : 1, kBlock);
+    if (g > 4096) g = 4096;
+    GP_LAUNCH(K_PREPARE, k_prepare<<<g, kBlock, 0, stream>>>(st));
   }
   if (st.n_items) {
     GP_LAUNCH(K_SWEEP, k_sweep<<<st.n_items, kSweepBlock, sweep_lds_bytes(st.n_qubits), stream>>>(st));
   }
-  GP_LAUNCH(K_COVER, k_cover<<<cdiv(st.n_layers + 1, 64), 64, 0, stream>>>(st));
+  GP_LAUNCH(K_COVER, k_cover<<<st.n_layers + 1, kBlock, 0, stream>>>(st));
   if (n == 0) {
     GP_LAUNCH(K_EDGE_WRITE, k_edge_write<<<1, kBlock, 0, stream>>>(st));
     return hipSuccess;
   }
   GP_LAUNCH(K_HASH, k_hash<<<cdiv(n, kBlock), kBlock, 0, stream>>>(st));
-  const uint32_t ntiles = cdiv(n, kTile);
-  for (int pass = 0; pass < 8; ++pass) {
-    const int shift = 8 * pass;
+  GP_LAUNCH(K_SCAN_SINGLE, k_scan_single<uint32_t><<<1, kScanSingleBlock, 0, stream>>>(st.tile_cnt, ntiles, nullptr,
+                                                                                      &st.hdr->n_live));
+  GP_LAUNCH(K_COMPACT, k_compact<<<ntiles, kBlock, 0, stream>>>(st));
+  GP_LAUNCH(K_DIGIT_OFFSETS, k_digit_offsets<<<st.n_pass, 256, 0, stream>>>(st, ntiles));
+  for (uint32_t pass = 0; pass < st.n_pass; ++pass) {
     const int src = pass & 1, dst = src ^ 1;
-    GP_LAUNCH(K_RADIX_HIST, k_radix_hist<<<ntiles, kBlock, 0, stream>>>(st.key[src], n, shift, st.hist, ntiles));
-    GP_LAUNCH(K_SCAN_SINGLE, k_scan_single<uint32_t><<<1, kScanSingleBlock, 0, stream>>>(
-                                 st.hist, 256 * ntiles, nullptr, static_cast<uint32_t*>(nullptr)));
-    GP_LAUNCH(K_RADIX_SCATTER, k_radix_scatter<<<ntiles, kBlock, 0, stream>>>(
-                                   st.key[src], st.val[src], st.key[dst], st.val[dst], n, shift, st.hist, ntiles));
+    GP_LAUNCH(K_ONESWEEP, k_onesweep<<<ntiles, kBlock, 0, stream>>>(st, pass, st.key[src], st.val[src], st.key[dst],
+                                                                     st.val[dst]));
   }
-  GP_LAUNCH(K_HEADS_COUNT, k_heads_count<<<ntiles, kBlock, 0, stream>>>(st.key[0], n, st.tile_sum));
+  const int fin = st.n_pass & 1;
+  GP_LAUNCH(K_HEADS_COUNT, k_heads_count<<<ntiles, kBlock, 0, stream>>>(st.key[fin], st.hdr, st.tile_sum));
   GP_LAUNCH(K_SCAN_SINGLE,
             k_scan_single<uint32_t><<<1, kScanSingleBlock, 0, stream>>>(st.tile_sum, ntiles, nullptr, &st.hdr->n_seg));
-  GP_LAUNCH(K_HEADS_APPLY, k_heads_apply<<<ntiles, kBlock, 0, stream>>>(st.key[0], n, st.tile_sum, st.segstart));
-  GP_LAUNCH(K_REDUCE, k_reduce<<<cdiv(n, kBlock), kBlock, 0, stream>>>(st, n));
-  GP_LAUNCH(K_REDUCE, k_reduce_big<<<cdiv(n, kBigSegment * 64) + 1, kBlock, 0, stream>>>(st, n));
+  GP_LAUNCH(K_HEADS_APPLY, k_heads_apply<<<ntiles, kBlock, 0, stream>>>(st.key[fin], st.hdr, st.tile_sum,
+                                                                         st.segstart));
+  GP_LAUNCH(K_REDUCE, k_reduce<<<cdiv(n, kBlock), kBlock, 0, stream>>>(st, st.val[fin]));
+  GP_LAUNCH(K_REDUCE_BIG, k_reduce_big<<<cdiv(n, kBigSegment * 64) + 1, kBlock, 0, stream>>>(st, st.val[fin]));
   GP_LAUNCH(K_SCAN_TILES,
             k_scan_tiles<<<ntiles, kBlock, 0, stream>>>(st.seg_cnt, n, &st.hdr->n_seg, st.tile_sum));
   GP_LAUNCH(K_SCAN_SINGLE, k_scan_single<uint64_t><<<1, kScanSingleBlock, 0, stream>>>(st.tile_sum, ntiles, nullptr,
