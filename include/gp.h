@@ -155,6 +155,11 @@ int gp_timing_entry(const gp_driver* drv, int index, const char** name,
 int gp_debug_set_key_bits(gp_driver* drv, int bits);
 uint64_t gp_debug_collision_retries(const gp_driver* drv);
 
+/* Profiling hook: device wall-clock stamps of every stage-1 sweep item of the
+ * last gp_run (start, end pairs; `cap` entries at most), the item count, and
+ * the clock rate in Hz. Synchronises the driver's stream. */
+int gp_debug_sweep_times(gp_driver* drv, uint64_t* out, uint64_t cap, uint64_t* n_items, double* clock_hz);
+
 /* Result accessors. Hyperedge e has signature bits
  *   bits[offsets[e]] ... bits[offsets[e+1]-1]   (strictly increasing),
  * where bit b < n_detectors is detector b and bit n_detectors + k is

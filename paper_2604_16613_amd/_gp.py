@@ -29,6 +29,7 @@ EXPORTS = (
     "gp_timing_entry", "gp_edges_count", "gp_edges_detectors", "gp_edges_observables",
     "gp_edges_offsets", "gp_edges_bits", "gp_edges_probabilities", "gp_edges_to_dem_text",
     "gp_edges_free", "gp_free", "gp_debug_set_key_bits", "gp_debug_collision_retries",
+    "gp_debug_sweep_times",
 )
 
 
@@ -115,6 +116,8 @@ def load():
         "gp_free": ([_vp], None),
         "gp_debug_set_key_bits": ([_vp, ctypes.c_int], ctypes.c_int),
         "gp_debug_collision_retries": ([_vp], _u64),
+        "gp_debug_sweep_times": ([_vp, ctypes.POINTER(_u64), _u64, ctypes.POINTER(_u64),
+                                  ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -276,3 +279,14 @@ def gp_debug_set_key_bits(drv: int, bits: int) -> None:
 
 def gp_debug_collision_retries(drv: int) -> int:
     return int(load().gp_debug_collision_retries(drv))
+
+
+def gp_debug_sweep_times(drv: int, cap: int = 1 << 16):
+    """-> (array of (start, end) device clock stamps per sweep item, clock Hz)."""
+    buf = np.zeros(cap, dtype=np.uint64)
+    n = _u64()
+    hz = ctypes.c_double()
+    _check(load().gp_debug_sweep_times(drv, buf.ctypes.data_as(ctypes.POINTER(_u64)), cap, ctypes.byref(n),
+                                       ctypes.byref(hz)))
+    m = min(int(n.value), cap // 2)
+    return buf[:2 * m].reshape(-1, 2), hz.value

@@ -44,11 +44,12 @@ uint32_t words_for(uint32_t det, uint32_t obs) { return (det + 63) / 64 + (obs +
 // pinned host buffer of the same shape, so one copy uploads them all.
 struct TableLayout {
   size_t ops, layer_off, leaf_off, leaf_bits, chan_qa, chan_qb, chan_kind, chan_rate, chan_foff, bnd_chan_off,
-      bnd_fault_off, col_top, col_lo, col_base, item_col, item_blo, item_bhi, fnv_pow, total;
+      bnd_fault_off, col_top, col_lo, col_base, item_col, item_blo, item_bhi, fnv_pow, ops32, inj_off, inj_layer,
+      inj_qubit, inj_word, inj_next, hchunk_pos, hchunk_bnd, total;
 };
 
 TableLayout layout_for(uint64_t ops, uint32_t layers, uint32_t meas, uint64_t leaf_bits, uint64_t chans, uint32_t w,
-                       uint64_t items) {
+                       uint64_t items, uint64_t hchunks) {
   TableLayout t{};
   size_t o = 0;
   auto take = [&](size_t& f, size_t bytes) {
@@ -73,6 +74,14 @@ TableLayout layout_for(uint64_t ops, uint32_t layers, uint32_t meas, uint64_t le
   take(t.item_blo, items * 4);
   take(t.item_bhi, items * 4);
   take(t.fnv_pow, (size_t(w) + 1) * 8);
+  take(t.ops32, ops * 4);
+  take(t.inj_off, (size_t(w) + 1) * 4);
+  take(t.inj_layer, leaf_bits * 4);
+  take(t.inj_qubit, leaf_bits * 4);
+  take(t.inj_word, leaf_bits * 8);
+  take(t.inj_next, leaf_bits * 4);
+  take(t.hchunk_pos, hchunks * 4);
+  take(t.hchunk_bnd, hchunks * 4);
   t.total = o;
   return t;
 }
@@ -171,6 +180,8 @@ void collect_timing(gp_driver* d) {
   d->pending.clear();
 }
 
+uint64_t hash_chunk_cap(const gp_bounds& b) { return b.max_faults / 256 + uint64_t(b.max_layers) + 2; }
+
 int check_bounds(const gp_driver* d, const gp::Lowered& lw) {
   const gp_bounds& b = d->bounds;
   char msg[256];
@@ -190,6 +201,9 @@ int check_bounds(const gp_driver* d, const gp::Lowered& lw) {
   if (lw.slab_words > b.max_slab_words) return over("slab words", lw.slab_words, b.max_slab_words);
   if (lw.item_col.size() > b.max_items) return over("sweep items", lw.item_col.size(), b.max_items);
   if (lw.w > d->max_w) return over("signature words", lw.w, d->max_w);
+  if (lw.w > gp::kMaxHashWords) return over("signature words for the hash kernel", lw.w, gp::kMaxHashWords);
+  if (lw.n_qubits > gp::kMaxSweepQubits) return over("qubits for the compact op words", lw.n_qubits, gp::kMaxSweepQubits);
+  if (lw.hchunk_pos.size() > hash_chunk_cap(b)) return over("hash chunks", lw.hchunk_pos.size(), hash_chunk_cap(b));
   if (gp::sweep_lds_bytes(lw.n_qubits) > gp::sweep_lds_limit())
     return over("LDS bytes for the qubit frame", gp::sweep_lds_bytes(lw.n_qubits), gp::sweep_lds_limit());
   return GP_OK;
@@ -286,7 +300,7 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
     return cleanup(hip_fail(hipGetLastError(), "hipStreamCreate"));
 
   TableLayout tl = layout_for(b.max_ops, b.max_layers, b.max_measurements, b.max_leaf_bits, b.max_channels, d->max_w,
-                              b.max_items);
+                              b.max_items, hash_chunk_cap(b));
   d->tables_cap = tl.total;
   if ((rc = dev_alloc(d, &d->d_tables, d->tables_cap, "tables"))) return cleanup(rc);
   if (hipHostMalloc(reinterpret_cast<void**>(&d->h_tables), d->tables_cap, hipHostMallocDefault) != hipSuccess)
@@ -303,6 +317,7 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   if ((rc = dev_alloc(d, &st.cov, (size_t(b.max_layers) + 1) * d->max_w, "cover lists"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.ncov, size_t(b.max_layers) + 1, "cover counts"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.pfault, F, "fault probabilities"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.frec, F, "fault records"))) return cleanup(rc);
   for (int k = 0; k < 2; k++) {
     if ((rc = dev_alloc(d, &st.key[k], F, "keys"))) return cleanup(rc);
     if ((rc = dev_alloc(d, &st.val[k], F, "values"))) return cleanup(rc);
@@ -313,13 +328,14 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   if ((rc = dev_alloc(d, &st.tile_cnt, size_t(d->max_tiles) + 1, "tile counts"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.part_hist, size_t(d->max_tiles) * gp::kMaxPasses * 256, "digit counts")))
     return cleanup(rc);
-  if ((rc = dev_alloc(d, &st.digit_off, size_t(gp::kMaxPasses) * 256, "digit offsets"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.digit_tot, size_t(gp::kMaxPasses) * 256, "digit totals"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.lookback, size_t(gp::kMaxPasses) * d->max_tiles * 256, "look-back words")))
     return cleanup(rc);
   if ((rc = dev_alloc(d, &st.tile_ctr, gp::kMaxPasses, "tile tickets"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.tile_sum, size_t(d->max_tiles) + 1, "tile sums"))) return cleanup(rc);
   st.max_tiles = d->max_tiles;
   if ((rc = dev_alloc(d, &st.segstart, F, "class starts"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.big, F / 64 + 1, "large classes"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.seg_q, F, "class probabilities"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.seg_rep, F, "class representatives"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.seg_cnt, F, "class bit counts"))) return cleanup(rc);
@@ -328,6 +344,7 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   if ((rc = dev_alloc(d, &st.edge_bits, d->bits_cap, "edge bits"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.edge_q, F, "edge probabilities"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.hdr, 1, "header"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.item_clock, 2 * b.max_items, "item clocks"))) return cleanup(rc);
   st.bits_cap = d->bits_cap;
   // download staging: offsets + bits + probabilities of the largest result
   d->h_out_cap = (F + 1) * 4 + d->bits_cap * 4 + F * 8 + 3 * kAlign;
@@ -357,7 +374,7 @@ int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, si
   // the previous compile may still read the pinned buffer
   HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
   TableLayout tl = layout_for(lw.ops.size(), lw.n_layers, lw.n_meas, lw.leaf_bits.size(), lw.chan_kind.size(), lw.w,
-                              lw.item_col.size());
+                              lw.item_col.size(), lw.hchunk_pos.size());
   if (tl.total > d->tables_cap) return fail(GP_E_BOUNDS, "lowered tables exceed the driver's table arena");
   char* h = d->h_tables;
   auto put = [&](size_t off, const void* src, size_t bytes) {
@@ -381,6 +398,14 @@ int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, si
   put(tl.item_blo, lw.item_blo.data(), lw.item_blo.size() * 4);
   put(tl.item_bhi, lw.item_bhi.data(), lw.item_bhi.size() * 4);
   put(tl.fnv_pow, lw.fnv_pow.data(), lw.fnv_pow.size() * 8);
+  put(tl.ops32, lw.ops32.data(), lw.ops32.size() * 4);
+  put(tl.inj_off, lw.inj_off.data(), lw.inj_off.size() * 4);
+  put(tl.inj_layer, lw.inj_layer.data(), lw.inj_layer.size() * 4);
+  put(tl.inj_qubit, lw.inj_qubit.data(), lw.inj_qubit.size() * 4);
+  put(tl.inj_word, lw.inj_word.data(), lw.inj_word.size() * 8);
+  put(tl.inj_next, lw.inj_next.data(), lw.inj_next.size() * 4);
+  put(tl.hchunk_pos, lw.hchunk_pos.data(), lw.hchunk_pos.size() * 4);
+  put(tl.hchunk_bnd, lw.hchunk_bnd.data(), lw.hchunk_bnd.size() * 4);
   HIP_TRY(hipMemcpyAsync(d->d_tables, d->h_tables, tl.total, hipMemcpyHostToDevice, d->stream), "upload tables");
 
   gp::DevState& st = d->st;
@@ -403,6 +428,18 @@ int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, si
   st.item_blo = reinterpret_cast<const uint32_t*>(D + tl.item_blo);
   st.item_bhi = reinterpret_cast<const uint32_t*>(D + tl.item_bhi);
   st.fnv_pow = reinterpret_cast<const uint64_t*>(D + tl.fnv_pow);
+  st.ops32 = reinterpret_cast<const uint32_t*>(D + tl.ops32);
+  st.inj_off = reinterpret_cast<const uint32_t*>(D + tl.inj_off);
+  st.inj_layer = reinterpret_cast<const uint32_t*>(D + tl.inj_layer);
+  st.inj_qubit = reinterpret_cast<const uint32_t*>(D + tl.inj_qubit);
+  st.inj_word = reinterpret_cast<const uint64_t*>(D + tl.inj_word);
+  st.inj_next = reinterpret_cast<const uint32_t*>(D + tl.inj_next);
+  st.hchunk_pos = reinterpret_cast<const uint32_t*>(D + tl.hchunk_pos);
+  st.hchunk_bnd = reinterpret_cast<const uint32_t*>(D + tl.hchunk_bnd);
+  st.n_hchunks = uint32_t(lw.hchunk_pos.size());
+  st.max_col_inj = 0;
+  for (uint32_t w = 0; w < lw.w; w++)
+    st.max_col_inj = std::max(st.max_col_inj, lw.inj_off[w + 1] - lw.inj_off[w]);
   st.n_qubits = lw.n_qubits;
   st.n_layers = lw.n_layers;
   st.n_det = lw.n_det;
@@ -554,6 +591,23 @@ int gp_debug_set_key_bits(gp_driver* d, int bits) {
 }
 
 uint64_t gp_debug_collision_retries(const gp_driver* d) { return d ? d->collision_retries : 0; }
+
+int gp_debug_sweep_times(gp_driver* d, uint64_t* out, uint64_t cap, uint64_t* n_items, double* clock_hz) {
+  if (!d || !out || !n_items) return fail(GP_E_ARG, "null argument");
+  if (!d->ran) return fail(GP_E_STATE, "no compile has run");
+  HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
+  HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
+  const uint64_t n = d->lw.item_col.size();
+  *n_items = n;
+  const uint64_t m = std::min<uint64_t>(cap, 2 * n);
+  if (m) HIP_TRY(hipMemcpy(out, d->st.item_clock, m * 8, hipMemcpyDeviceToHost), "download item clocks");
+  if (clock_hz) {
+    int khz = 0;
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, d->device), "clock rate");
+    *clock_hz = double(khz) * 1e3;
+  }
+  return GP_OK;
+}
 
 int gp_timing_entry(const gp_driver* d, int index, const char** name, double* total_ms, uint64_t* launches) {
   if (!d || index < 0 || index >= gp::K_COUNT) return fail(GP_E_ARG, "bad timing index");

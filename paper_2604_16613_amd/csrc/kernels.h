@@ -17,7 +17,7 @@ struct DevHeader {
   uint64_t n_bits;     // total signature bits over all hyperedges
   uint64_t n_words;    // stage-1 signature words written (= words the hash reads)
   uint32_t n_live;     // faults with a non-empty signature (the sorted ones)
-  uint32_t pad;
+  uint32_t n_big;      // classes with more faults than one thread merges
 };
 
 enum : uint32_t {
@@ -52,11 +52,21 @@ struct DevState {
   const uint32_t* item_blo;
   const uint32_t* item_bhi;
   const uint64_t* fnv_pow;
+  const uint32_t* ops32;       // compact op words for the sweep
+  const uint32_t* inj_off;     // per column: injection entries
+  const uint32_t* inj_layer;
+  const uint32_t* inj_qubit;
+  const uint64_t* inj_word;
+  const uint32_t* inj_next;
+  const uint32_t* hchunk_pos;  // hash chunks: first position, boundary
+  const uint32_t* hchunk_bnd;
 
   // sizes
   uint32_t n_qubits, n_layers, n_det, wd, w;
   uint32_t n_chan, n_items;
   uint32_t n_faults;
+  uint32_t n_hchunks;
+  uint32_t max_col_inj;  // most injection entries of any one column
   // class key: 0 = FNV-1a of the signature (kept to its low key_bits bits);
   // 1 = FNV-1a mixed with the check hash (used after a key collision)
   uint32_t key_mode;
@@ -70,6 +80,7 @@ struct DevState {
   uint32_t* cov;         // per boundary: covered columns, ascending ((L+1) x W)
   uint32_t* ncov;        // per boundary: number of covered columns
   double* pfault;        // per fault position: probability
+  uint32_t* frec;        // per fault position: qubit a | qubit b << 14 | Pauli code << 28
   uint64_t* key[2];      // class keys: per position (key[1]) then compacted, ping-pong in the sort
   uint32_t* val[2];      // fault positions riding with the keys
   uint64_t* chk;         // per fault position: check hash
@@ -77,11 +88,12 @@ struct DevState {
   uint64_t* nzm;         // per fault position: which covered columns hold non-zero words
   uint32_t* tile_cnt;    // per compaction tile: live faults, then their exclusive prefix
   uint32_t* part_hist;   // per compaction tile: digit counts of every pass
-  uint32_t* digit_off;   // per pass: exclusive prefix of the digit counts
+  uint32_t* digit_tot;   // per pass: total count of each digit value
   uint32_t* lookback;    // per pass, tile and digit: published count with status bits
   uint32_t* tile_ctr;    // per pass: tile ticket counter
   uint32_t* tile_sum;    // scan tile sums
   uint32_t* segstart;    // first sorted index of each class
+  uint32_t* big;         // classes too large for one thread
   double* seg_q;         // merged probability per class
   uint32_t* seg_rep;     // representative fault position per class
   uint32_t* seg_cnt;     // signature bits per class
@@ -91,6 +103,7 @@ struct DevState {
   double* edge_q;        // output probabilities
   uint64_t bits_cap;
   DevHeader* hdr;
+  uint64_t* item_clock;  // per sweep item: device wall clock at start and end (profiling)
 };
 
 // Names of the kernels (for timing tables).
@@ -116,6 +129,8 @@ hipError_t enqueue_compile(const DevState& st, hipStream_t stream, const LaunchH
 
 // Dynamic LDS the sweep needs for n qubits, and the largest it may use.
 size_t sweep_lds_bytes(uint32_t n_qubits);
+// Largest word-column count the hash kernel stages in LDS.
+constexpr uint32_t kMaxHashWords = 1024;
 size_t sweep_lds_limit();
 hipError_t configure_kernels();
 

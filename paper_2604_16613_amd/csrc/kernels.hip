@@ -34,13 +34,16 @@ namespace gp {
 
 namespace {
 
-constexpr int kSweepBlock = 256;
-constexpr int kSweepOps = 4;           // operations per thread held ahead in registers
+constexpr int kSweepBlock = 1024;
+constexpr int kWinOps = 4096;          // compact ops per LDS window buffer (two buffers)
+constexpr int kEmitPre = 8;            // fault records per thread fetched during the op phase
+constexpr int kPre = kWinOps / kSweepBlock;
+constexpr int kLofsMax = 2048;         // layer offsets staged in LDS when the circuit has fewer layers
+constexpr int kInjLds = 512;           // a column's injections staged in LDS when it has at most this many
 constexpr int kBlock = 256;
 constexpr int kPerThread = kTile / kBlock;
 constexpr int kScanSingleBlock = 1024;
 constexpr uint32_t kBigSegment = 64;   // classes with more faults reduce in a whole block
-constexpr int kHashLds = 512;          // cover-list entries a hash block stages in LDS
 constexpr uint32_t kLbAgg = 1u << 30;  // look-back status: tile aggregate published
 constexpr uint32_t kLbPre = 2u << 30;  // look-back status: inclusive prefix published
 constexpr uint32_t kLbMask = (1u << 30) - 1;
@@ -123,17 +126,6 @@ __device__ __forceinline__ uint32_t boundary_of(const uint32_t* off, uint32_t n_
   return lo;
 }
 
-__device__ __forceinline__ uint64_t leaf_word(const uint32_t* leaf_off, const uint32_t* leaf_bits, uint32_t m,
-                                              uint32_t w) {
-  uint64_t v = 0;
-  const uint32_t k1 = leaf_off[m + 1];
-  for (uint32_t k = leaf_off[m]; k < k1; ++k) {
-    const uint32_t b = leaf_bits[k];
-    if ((b >> 6) == w) v |= 1ull << (b & 63);
-  }
-  return v;
-}
-
 __device__ __forceinline__ uint32_t digit_of(uint64_t k, uint32_t pass) { return uint32_t(k >> (8 * pass)) & 255u; }
 
 // ------------------------------------------------------------------ prepare
@@ -142,9 +134,20 @@ __global__ void k_prepare(DevState st) {
   const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t stride = gridDim.x * blockDim.x;
   for (uint32_t c = gid; c < st.n_chan; c += stride) {
-    const double p = fault_probability(st.chan_kind[c], st.chan_rate[c]);
-    const uint32_t f1 = st.chan_foff[c + 1];
-    for (uint32_t f = st.chan_foff[c]; f < f1; ++f) st.pfault[f] = p;
+    const uint32_t kind = st.chan_kind[c];
+    const double p = fault_probability(kind, st.chan_rate[c]);
+    const uint32_t f0 = st.chan_foff[c], f1 = st.chan_foff[c + 1];
+    const uint32_t qa = st.chan_qa[c] & kQField;
+    const uint32_t qb = kind == CH_DEP2 ? (st.chan_qb[c] & kQField) : 0u;
+    for (uint32_t f = f0; f < f1; ++f) {
+      st.pfault[f] = p;
+      // Pauli code: x on a | z on a << 1 | x on b << 2 | z on b << 3
+      const uint32_t k = f - f0;
+      const uint32_t code = kind == CH_DEP2 ? k + 1
+                          : kind == CH_DEP1 ? (k == 0 ? 1u : k == 1 ? 3u : 2u)
+                          : kind == CH_X ? 1u : kind == CH_Y ? 3u : 2u;
+      st.frec[f] = qa | (qb << kQubitBits) | (code << 28);
+    }
   }
   for (uint32_t w = gid; w < st.w; w += stride) st.cover_lo[w] = 0;
   const uint32_t ntiles = (st.n_faults + kTile - 1) / kTile;
@@ -162,6 +165,7 @@ __global__ void k_prepare(DevState st) {
     st.hdr->n_bits = 0;
     st.hdr->n_words = 0;
     st.hdr->n_live = 0;
+    st.hdr->n_big = 0;
   }
 }
 
@@ -169,12 +173,13 @@ __global__ void k_prepare(DevState st) {
 
 __device__ __forceinline__ int nzd(uint64_t nv, uint64_t ov) { return int(nv != 0) - int(ov != 0); }
 
-// Apply one operation backwards to the frame (X_q at 2q, Z_q at 2q+1).
-__device__ __forceinline__ void apply_op(uint64_t op, uint64_t* frame, const DevState& st, uint32_t w, int& dnz,
-                                         int& gauge) {
-  const uint32_t kind = uint32_t(op >> 56);
-  const uint32_t a = uint32_t(op >> 28) & uint32_t(kField);
-  const uint32_t b = uint32_t(op) & uint32_t(kField);
+// Apply one compact operation backwards to the frame (X_q at 2q, Z_q at
+// 2q+1). A measurement takes its leaf word for this column from pend[q]
+// (scattered there from the column's injection list) and clears it.
+__device__ __forceinline__ void apply_op(uint32_t op, uint64_t* frame, uint64_t* pend, int& dnz, int& gauge) {
+  const uint32_t kind = op >> 28;
+  const uint32_t a = (op >> kQubitBits) & kQField;
+  const uint32_t b = op & kQField;
   uint64_t* fa = frame + 2 * a;
   const uint64_t xa = fa[0], za = fa[1];
   switch (kind) {
@@ -235,21 +240,24 @@ __device__ __forceinline__ void apply_op(uint64_t op, uint64_t* frame, const Dev
       break;
     case OP_M: {  // X before the measurement flips it (leaf) and persists
       gauge |= za != 0;
-      const uint64_t n = xa ^ leaf_word(st.leaf_off, st.leaf_bits, b, w);
+      const uint64_t n = xa ^ pend[a];
+      pend[a] = 0;
       fa[0] = n;
       dnz += nzd(n, xa);
       break;
     }
     case OP_MX: {
       gauge |= xa != 0;
-      const uint64_t n = za ^ leaf_word(st.leaf_off, st.leaf_bits, b, w);
+      const uint64_t n = za ^ pend[a];
+      pend[a] = 0;
       fa[1] = n;
       dnz += nzd(n, za);
       break;
     }
     case OP_MR: {  // the reset erases what the measurement did not see
       gauge |= za != 0;
-      const uint64_t n = leaf_word(st.leaf_off, st.leaf_bits, b, w);
+      const uint64_t n = pend[a];
+      pend[a] = 0;
       fa[0] = n;
       fa[1] = 0;
       dnz += nzd(n, xa) - int(za != 0);
@@ -257,7 +265,8 @@ __device__ __forceinline__ void apply_op(uint64_t op, uint64_t* frame, const Dev
     }
     case OP_MRX: {
       gauge |= xa != 0;
-      const uint64_t n = leaf_word(st.leaf_off, st.leaf_bits, b, w);
+      const uint64_t n = pend[a];
+      pend[a] = 0;
       fa[1] = n;
       fa[0] = 0;
       dnz += nzd(n, za) - int(xa != 0);
@@ -268,85 +277,155 @@ __device__ __forceinline__ void apply_op(uint64_t op, uint64_t* frame, const Dev
   }
 }
 
+// One work item = one word column (or one boundary range of an observable
+// column). LDS holds the column's frame, the pending leaf words, two windows of
+// compact ops (the next window is fetched into registers while the current one
+// is applied), the layer and fault offsets and the column's injection list.
+// Per layer: fetch the new boundary's fault records and apply the ops (one
+// thread per op); then emit one signature word per fault (one thread per
+// fault, coalesced) and scatter the next layer's leaf words.
+template <bool kStaged>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
-  extern __shared__ uint64_t frame[];  // X_q at 2q, Z_q at 2q+1
+  extern __shared__ uint64_t lds[];
   __shared__ int s_nz;
   const int tid = threadIdx.x;
+  const uint32_t n = st.n_qubits;
+  uint64_t* frame = lds;
+  uint64_t* pend = frame + 2 * size_t(n);
+  uint64_t* sinj_w = pend + n;
+  uint32_t* opbuf = reinterpret_cast<uint32_t*>(sinj_w + kInjLds);
+  uint32_t* slofs = opbuf + 2 * kWinOps;
+  uint32_t* sbfo = slofs + kLofsMax;
+  uint32_t* sinj_l = sbfo + kLofsMax + 1;
+  uint32_t* sinj_q = sinj_l + kInjLds;
+  uint32_t* sinj_n = sinj_q + kInjLds;
+
   const uint32_t item = blockIdx.x;
+  if (tid == 0) st.item_clock[2 * item] = wall_clock64();
   const uint32_t w = st.item_col[item];
   const int top = st.col_top[w];
   const int clo = st.col_lo[w];
   const int blo = int(st.item_blo[item]);
   const int bhi = int(st.item_bhi[item]);
   uint64_t* out = st.slab + st.col_base[w];
-  const uint32_t nv = 2 * st.n_qubits;
-  for (uint32_t i = tid; i < nv; i += kSweepBlock) frame[i] = 0;
+  // kStaged: the layer offsets and every column's injections fit in LDS, so
+  // the layer loop reads no global memory besides the window prefetch and
+  // the emission's channel tables
+  constexpr bool lofs_lds = kStaged;
+  constexpr bool inj_lds = kStaged;
+  const uint32_t i0 = st.inj_off[w];
+  const uint32_t ni = st.inj_off[w + 1] - i0;
+
+  for (uint32_t i = tid; i < 3 * n; i += kSweepBlock) frame[i] = 0;  // frame and pend
+  if (lofs_lds)
+    for (uint32_t k = tid; k <= st.n_layers + 1; k += kSweepBlock) {
+      if (k <= st.n_layers) slofs[k] = st.layer_off[k];
+      sbfo[k] = st.bnd_fault_off[k];
+    }
+  if (inj_lds)
+    for (uint32_t k = tid; k < ni; k += kSweepBlock) {
+      sinj_w[k] = st.inj_word[i0 + k];
+      sinj_l[k] = st.inj_layer[i0 + k];
+      sinj_q[k] = st.inj_qubit[i0 + k];
+      sinj_n[k] = st.inj_next[i0 + k];
+    }
   if (tid == 0) s_nz = 0;
-  int gauge = 0;
-  bool dead = false;
-  // operations of layer t held in registers; kind 0 marks an empty slot
-  uint64_t cur[kSweepOps];
+  __syncthreads();
+  auto LO = [&](int t) -> uint32_t { return lofs_lds ? slofs[t] : st.layer_off[t]; };
+  auto BFO = [&](int t) -> uint32_t { return lofs_lds ? sbfo[t] : st.bnd_fault_off[t]; };
+  auto INJ_L = [&](uint32_t k) -> int { return int(inj_lds ? sinj_l[k] : st.inj_layer[i0 + k]); };
+  auto INJ_Q = [&](uint32_t k) -> uint32_t { return inj_lds ? sinj_q[k] : st.inj_qubit[i0 + k]; };
+  auto INJ_W = [&](uint32_t k) -> uint64_t { return inj_lds ? sinj_w[k] : st.inj_word[i0 + k]; };
+  auto INJ_N = [&](uint32_t k) -> uint32_t { return inj_lds ? sinj_n[k] : st.inj_next[i0 + k]; };
+  // lowest layer of the window that starts at layer hi (every thread computes the same)
+  auto window_lo = [&](int hi) -> int {
+    int lo = hi;
+    const uint32_t end = LO(hi + 1);
+    while (lo - 1 >= blo && end - LO(lo - 1) <= uint32_t(kWinOps)) lo--;
+    return lo;
+  };
+  // scatter the leaf words of layer t into pend
+  uint32_t ip = 0;
+  auto scatter = [&](int t) {
+    if (ip < ni && INJ_L(ip) == t) {
+      const uint32_t ie = INJ_N(ip);
+      for (uint32_t k = ip + tid; k < ie; k += kSweepBlock) pend[INJ_Q(k)] = INJ_W(k);
+      ip = ie;
+    }
+  };
+
+  // first window, loaded directly; the top layer's leaf words
+  int wlo = window_lo(top);
+  uint32_t o_base = LO(wlo);
   {
-    const uint32_t o0 = st.layer_off[top] + tid, o1 = st.layer_off[top + 1];
+    const uint32_t cnt = min(LO(top + 1) - o_base, uint32_t(kWinOps));
+    for (uint32_t i = tid; i < cnt; i += kSweepBlock) opbuf[i] = st.ops32[o_base + i];
+  }
+  scatter(top);
+  // next window into registers
+  int nhi = wlo - 1;
+  int nlo = nhi >= blo ? window_lo(nhi) : nhi + 1;
+  uint32_t nbase = nhi >= blo ? LO(nlo) : 0;
+  uint32_t pre[kPre];
+  {
+    const uint32_t cnt = nhi >= blo ? min(LO(nhi + 1) - nbase, uint32_t(kWinOps)) : 0;
 #pragma unroll
-    for (int k = 0; k < kSweepOps; ++k) cur[k] = (o0 + k * kSweepBlock < o1) ? st.ops[o0 + k * kSweepBlock] : 0;
+    for (int k = 0; k < kPre; ++k) {
+      const uint32_t i = tid + k * kSweepBlock;
+      pre[k] = i < cnt ? st.ops32[nbase + i] : 0u;
+    }
   }
   __syncthreads();
+  int cur = 0;
+  int gauge = 0;
+  bool dead = false;
   for (int t = top; t >= blo; --t) {
-    // fetch layer t-1 while layer t is applied
-    uint64_t nxt[kSweepOps];
-    if (t - 1 >= blo) {
-      const uint32_t o0 = st.layer_off[t - 1] + tid, o1 = st.layer_off[t];
+    // A: fetch the records of the faults at boundary t (used in B), then
+    // transform the frame from boundary t+1 to boundary t, in place
+    const bool emit = t <= bhi;
+    const uint32_t f0 = emit ? BFO(t) : 0u, nf = emit ? BFO(t + 1) - f0 : 0u;
+    uint32_t rec[kEmitPre];
 #pragma unroll
-      for (int k = 0; k < kSweepOps; ++k) nxt[k] = (o0 + k * kSweepBlock < o1) ? st.ops[o0 + k * kSweepBlock] : 0;
-    } else {
-#pragma unroll
-      for (int k = 0; k < kSweepOps; ++k) nxt[k] = 0;
+    for (int k = 0; k < kEmitPre; ++k) {
+      const uint32_t i = tid + k * kSweepBlock;
+      rec[k] = i < nf ? st.frec[f0 + i] : 0u;
     }
-    // transform the frame from boundary t+1 to boundary t (one layer, in place)
     int dnz = 0;
-#pragma unroll
-    for (int k = 0; k < kSweepOps; ++k)
-      if (cur[k]) apply_op(cur[k], frame, st, w, dnz, gauge);
     {
-      const uint32_t o1 = st.layer_off[t + 1];
-      for (uint32_t o = st.layer_off[t] + tid + kSweepOps * kSweepBlock; o < o1; o += kSweepBlock)
-        apply_op(st.ops[o], frame, st, w, dnz, gauge);
+      // a layer never exceeds a window: it has at most n ops and n fits LDS
+      const uint32_t ob = LO(t) - o_base, oe = LO(t + 1) - o_base;
+      const uint32_t* buf = opbuf + cur * kWinOps;
+      for (uint32_t i = ob + tid; i < oe; i += kSweepBlock) apply_op(buf[i], frame, pend, dnz, gauge);
     }
-    if (dnz) atomicAdd(&s_nz, dnz);
+    {
+      // one LDS atomic per wave: a single shared counter serialises atomics
+      const uint32_t wd = wave_sum(uint32_t(dnz));
+      if ((tid & 63) == 0 && wd) atomicAdd(&s_nz, int(wd));
+    }
     lds_barrier();
     const int nz = s_nz;
-    // faults at boundary t: signature word = XOR of their Pauli's X/Z words
-    if (t <= bhi) {
-      const uint32_t c1 = st.bnd_chan_off[t + 1];
-      for (uint32_t c = st.bnd_chan_off[t] + tid; c < c1; c += kSweepBlock) {
-        const uint32_t qa = st.chan_qa[c];
-        const uint64_t x0 = frame[2 * qa], z0 = frame[2 * qa + 1];
-        uint64_t* o = out + st.chan_foff[c];
-        switch (st.chan_kind[c]) {
-          case CH_X: o[0] = x0; break;
-          case CH_Y: o[0] = x0 ^ z0; break;
-          case CH_Z: o[0] = z0; break;
-          case CH_DEP1:
-            o[0] = x0;
-            o[1] = x0 ^ z0;
-            o[2] = z0;
-            break;
-          case CH_DEP2: {
-            const uint32_t qb = st.chan_qb[c];
-            const uint64_t x1 = frame[2 * qb], z1 = frame[2 * qb + 1];
-            // Pauli code k = xa | za<<1 | xb<<2 | zb<<3, k = 1..15
-            const uint64_t A[4] = {0, x0, z0, x0 ^ z0};
-            const uint64_t B[4] = {0, x1, z1, x1 ^ z1};
+    // B: faults at boundary t, one per thread: signature word = XOR of the X/Z
+    // words their Pauli selects (composite Paulis, Sec. 2.3.4); consecutive
+    // threads store consecutive positions
+    auto word_of = [&](uint32_t r) -> uint64_t {
+      const uint32_t qa = r & kQField, qb = (r >> kQubitBits) & kQField, code = r >> 28;
+      const uint64_t x0 = frame[2 * qa], z0 = frame[2 * qa + 1];
+      const uint64_t x1 = frame[2 * qb], z1 = frame[2 * qb + 1];
+      return (x0 & (0ull - (code & 1u))) ^ (z0 & (0ull - ((code >> 1) & 1u))) ^
+             (x1 & (0ull - ((code >> 2) & 1u))) ^ (z1 & (0ull - ((code >> 3) & 1u)));
+    };
+    // all words first, then all stores: a store in flight makes the compiler
+    // wait for every outstanding memory operation before the next use of a
+    // loaded register
+    uint64_t wv[kEmitPre];
 #pragma unroll
-            for (int k = 1; k < 16; ++k) o[k - 1] = A[k & 3] ^ B[k >> 2];
-            break;
-          }
-          default:
-            break;
-        }
-      }
+    for (int k = 0; k < kEmitPre; ++k) wv[k] = (tid + k * kSweepBlock < nf) ? word_of(rec[k]) : 0ull;
+#pragma unroll
+    for (int k = 0; k < kEmitPre; ++k) {
+      const uint32_t i = tid + k * kSweepBlock;
+      if (i < nf) out[f0 + i] = wv[k];
     }
+    for (uint32_t i = tid + kEmitPre * kSweepBlock; i < nf; i += kSweepBlock) out[f0 + i] = word_of(st.frec[f0 + i]);
     if (nz == 0 && t <= clo) {
       // no leaf of this column lies below t and the frame is zero: every lower
       // boundary is zero in this column
@@ -354,15 +433,38 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
       dead = true;
       break;
     }
-    lds_barrier();
+    if (t - 1 >= blo) scatter(t - 1);
+    if (t == wlo && nhi >= blo) {
+      // the window is used up: the prefetched one becomes current, and the
+      // window after it is fetched into registers
+      const uint32_t cnt = min(LO(nhi + 1) - nbase, uint32_t(kWinOps));
+      uint32_t* nb = opbuf + (cur ^ 1) * kWinOps;
 #pragma unroll
-    for (int k = 0; k < kSweepOps; ++k) cur[k] = nxt[k];
+      for (int k = 0; k < kPre; ++k) {
+        const uint32_t i = tid + k * kSweepBlock;
+        if (i < cnt) nb[i] = pre[k];
+      }
+      cur ^= 1;
+      wlo = nlo;
+      o_base = nbase;
+      nhi = wlo - 1;
+      nlo = nhi >= blo ? window_lo(nhi) : nhi + 1;
+      nbase = nhi >= blo ? LO(nlo) : 0;
+      const uint32_t cnt2 = nhi >= blo ? min(LO(nhi + 1) - nbase, uint32_t(kWinOps)) : 0;
+#pragma unroll
+      for (int k = 0; k < kPre; ++k) {
+        const uint32_t i = tid + k * kSweepBlock;
+        pre[k] = i < cnt2 ? st.ops32[nbase + i] : 0u;
+      }
+    }
+    lds_barrier();
   }
   if (!dead && blo == 0) {
     // every qubit starts in |0>: a Z error at the very start must be invisible
-    for (uint32_t q = tid; q < st.n_qubits; q += kSweepBlock) gauge |= frame[2 * q + 1] != 0;
+    for (uint32_t q = tid; q < n; q += kSweepBlock) gauge |= frame[2 * q + 1] != 0;
   }
   if (gauge) atomicOr(&st.hdr->flags, FLAG_GAUGE);
+  if (tid == 0) st.item_clock[2 * item + 1] = wall_clock64();
 }
 
 // Per boundary (one block each), the ascending list of columns whose word there
@@ -384,7 +486,12 @@ __global__ __launch_bounds__(kBlock) void k_cover(DevState st) {
     n += s_wave[kBlock / 64];
     __syncthreads();
   }
-  if (threadIdx.x == 0) st.ncov[b] = n;
+  if (threadIdx.x == 0) {
+    st.ncov[b] = n;
+    // signature words stage 1 wrote at this boundary (= words the hash reads)
+    const uint64_t words = uint64_t(n) * (st.bnd_fault_off[b + 1] - st.bnd_fault_off[b]);
+    if (words) atomicAdd(reinterpret_cast<unsigned long long*>(&st.hdr->n_words), (unsigned long long)words);
+  }
 }
 
 // ------------------------------------------------------------------ stage 2
@@ -392,62 +499,76 @@ __global__ __launch_bounds__(kBlock) void k_cover(DevState st) {
 // FNV-1a over the 8W octets of each fault's signature (h <- (h ^ octet) *
 // prime), a run of k zero words multiplying by prime^(8k); the check hash, the
 // weight and the non-zero-word mask; live-fault counts per compaction tile.
+// One block = at most 256 positions of one boundary, so the boundary's cover
+// list and the prime powers sit in LDS and the word loads carry no branches.
 __global__ __launch_bounds__(kBlock) void k_hash(DevState st) {
-  __shared__ uint32_t s_w[kHashLds];
-  __shared__ uint64_t s_base[kHashLds];
-  __shared__ uint32_t s_b0, s_n0;
-  const uint32_t pos = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool valid = pos < st.n_faults;
-  const uint32_t b = valid ? boundary_of(st.bnd_fault_off, st.n_layers + 1, pos) : 0;
-  const uint32_t n = valid ? st.ncov[b] : 0;
-  // stage the cover list of the block's first boundary
-  if (threadIdx.x == 0) {
-    s_b0 = b;
-    s_n0 = n;
-  }
-  __syncthreads();
-  const uint32_t b0 = s_b0, n0 = s_n0 < kHashLds ? s_n0 : 0;
-  for (uint32_t k = threadIdx.x; k < n0; k += kBlock) {
-    const uint32_t w = st.cov[size_t(b0) * st.w + k];
+  __shared__ uint32_t s_w[kMaxHashWords];
+  __shared__ uint64_t s_base[kMaxHashWords];
+  __shared__ uint64_t s_pow[kMaxHashWords + 1];
+  const uint32_t b = st.hchunk_bnd[blockIdx.x];
+  const uint32_t p0 = st.hchunk_pos[blockIdx.x];
+  const uint32_t p1 = min(p0 + uint32_t(kBlock), st.bnd_fault_off[b + 1]);
+  const uint32_t n = st.ncov[b];
+  for (uint32_t k = threadIdx.x; k < n; k += kBlock) {
+    const uint32_t w = st.cov[size_t(b) * st.w + k];
     s_w[k] = w;
     s_base[k] = st.col_base[w];
   }
+  for (uint32_t k = threadIdx.x; k <= st.w; k += kBlock) s_pow[k] = st.fnv_pow[k];
   __syncthreads();
+  const uint32_t pos = p0 + threadIdx.x;
+  const bool valid = pos < p1;
+  const uint32_t lpos = valid ? pos : p0;  // lanes past the chunk read a valid word and drop it
   uint64_t h1 = kFnvOffset, h2 = 0, mask = 0;
   uint32_t wn = 0, weight = 0;
-  if (valid) {
-    const bool staged = (b == b0) && n0 == n;
-    const uint32_t* cl = st.cov + size_t(b) * st.w;
-    for (uint32_t k = 0; k < n; ++k) {
-      const uint32_t w = staged ? s_w[k] : cl[k];
-      const uint64_t base = staged ? s_base[k] : st.col_base[w];
-      const uint64_t v = st.slab[base + pos];
+  for (uint32_t k0 = 0; k0 < n; k0 += 8) {
+    uint64_t vv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint32_t k = min(k0 + j, n - 1);
+      vv[j] = st.slab[s_base[k] + lpos];
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const uint64_t v = (k0 + j < n) ? vv[j] : 0;
       if (v) {
-        h1 *= st.fnv_pow[w - wn];
+        const uint32_t w = s_w[k0 + j];
+        h1 *= s_pow[w - wn];
 #pragma unroll
         for (int o = 0; o < 8; ++o) h1 = (h1 ^ ((v >> (8 * o)) & 0xffu)) * kFnvPrime;
         wn = w + 1;
         h2 += check_term(w, v);
         weight += __popcll(v);
-        if (k < 64) mask |= 1ull << k;
+        if (k0 + j < 64) mask |= 1ull << (k0 + j);
       }
     }
-    h1 *= st.fnv_pow[st.w - wn];
-    uint64_t key = h1;
-    if (st.key_mode == 1) key = h1 ^ fmix64(h2 ^ 0x5851f42d4c957f2dull);
-    if (st.key_bits < 64) key &= (1ull << st.key_bits) - 1;
+  }
+  h1 *= s_pow[st.w - wn];
+  uint64_t key = h1;
+  if (st.key_mode == 1) key = h1 ^ fmix64(h2 ^ 0x5851f42d4c957f2dull);
+  if (st.key_bits < 64) key &= (1ull << st.key_bits) - 1;
+  if (valid) {
     st.key[1][pos] = key;
     st.chk[pos] = h2;
     st.popc[pos] = weight;
     st.nzm[pos] = mask;
   }
-  // words read here = words stage 1 wrote; live faults per compaction tile
-  const uint32_t t_words = wave_sum(n);
-  const uint32_t t_live = wave_sum(weight ? 1u : 0u);
+  // live faults per compaction tile: the chunk's positions span at most two
+  // tiles; reduce over the block, then at most two global atomics
+  __shared__ uint32_t s_cnt[2];
+  if (threadIdx.x < 2) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t ta = p0 / kTile;
+  const bool live = valid && weight != 0;
+  const uint32_t c_a = wave_sum((live && pos / kTile == ta) ? 1u : 0u);
+  const uint32_t c_b = wave_sum((live && pos / kTile != ta) ? 1u : 0u);
   if ((threadIdx.x & 63) == 0) {
-    if (t_words) atomicAdd(reinterpret_cast<unsigned long long*>(&st.hdr->n_words), (unsigned long long)t_words);
-    if (t_live) atomicAdd(&st.tile_cnt[(blockIdx.x * blockDim.x) / kTile], t_live);
+    if (c_a) atomicAdd(&s_cnt[0], c_a);
+    if (c_b) atomicAdd(&s_cnt[1], c_b);
   }
+  __syncthreads();
+  if (threadIdx.x == 0 && s_cnt[0]) atomicAdd(&st.tile_cnt[ta], s_cnt[0]);
+  if (threadIdx.x == 1 && s_cnt[1]) atomicAdd(&st.tile_cnt[ta + 1], s_cnt[1]);
 }
 
 // In-place exclusive scan of n (host value, or *n_dev when given) words by one
@@ -504,19 +625,27 @@ __global__ __launch_bounds__(kBlock) void k_compact(DevState st) {
   for (uint32_t p = 0; p < P; ++p) part[p * 256 + threadIdx.x] = s_hist[p][threadIdx.x];
 }
 
-// Per pass (one block each): total digit counts over all tiles, exclusive prefix.
-__global__ __launch_bounds__(256) void k_digit_offsets(DevState st, uint32_t ntiles) {
-  __shared__ uint32_t s_wave[256 / 64 + 1];
-  const uint32_t p = blockIdx.x, d = threadIdx.x;
+// Total count of digit d in pass p over all compaction tiles (block p*256 + d).
+__global__ __launch_bounds__(kBlock) void k_digit_totals(DevState st, uint32_t ntiles) {
+  __shared__ uint32_t s_red[kBlock / 64];
+  const uint32_t p = blockIdx.x >> 8, d = blockIdx.x & 255u;
   uint32_t tot = 0;
-  for (uint32_t t = 0; t < ntiles; ++t) tot += st.part_hist[(size_t(t) * kMaxPasses + p) * 256 + d];
-  const uint32_t ex = block_exclusive_scan<256>(tot, s_wave);
-  st.digit_off[p * 256 + d] = ex;
+  for (uint32_t t = threadIdx.x; t < ntiles; t += kBlock) tot += st.part_hist[(size_t(t) * kMaxPasses + p) * 256 + d];
+  tot = wave_sum(tot);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = tot;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t a = 0;
+    for (int k = 0; k < kBlock / 64; ++k) a += s_red[k];
+    st.digit_tot[p * 256 + d] = a;
+  }
 }
 
 // One stable pass of 8-bit digits over the live keys (n = hdr->n_live). Tiles
 // are taken in ticket order, so every tile a block waits for is already
 // running. Wave v ranks tile items [v*1024, (v+1)*1024) in order, 64 at a time.
+// The tile publishes its digit counts first, ranks its items into LDS, and
+// only then looks back for the counts of the tiles before it.
 __global__ __launch_bounds__(kBlock) void k_onesweep(DevState st, uint32_t pass, const uint64_t* __restrict__ kin,
                                                      const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
                                                      uint32_t* __restrict__ vout) {
@@ -545,42 +674,21 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(DevState st, uint32_t pass,
     k[r] = i < n ? kin[i] : 0;
     v[r] = i < n ? vin[i] : 0;
   }
+  // global start of every digit value: exclusive prefix of the digit totals
+  const uint32_t digit_base = block_exclusive_scan<kBlock>(st.digit_tot[pass * 256 + tid], s_wave);
 #pragma unroll
   for (int r = 0; r < kRounds; ++r)
     if (base + r * 64 + lane < n) atomicAdd(&s_cnt[wv][digit_of(k[r], pass)], 1u);
   __syncthreads();
-  // thread d: tile count of digit d, publish, look back for the tiles before
+  uint32_t* lb = st.lookback + size_t(pass) * st.max_tiles * 256;
+  uint32_t tot = 0;
   {
+    // thread d: tile count of digit d; publish it; local start of digit d
     const uint32_t d = tid;
-    uint32_t tot = 0;
 #pragma unroll
     for (int w = 0; w < kBlock / 64; ++w) tot += s_cnt[w][d];
-    uint32_t* lb = st.lookback + size_t(pass) * st.max_tiles * 256;
-    uint32_t excl = 0;
-    if (tile == 0) {
-      __hip_atomic_store(&lb[d], kLbPre | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      __hip_atomic_store(&lb[size_t(tile) * 256 + d], kLbAgg | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      int j = int(tile) - 1;
-      uint32_t spins = 0;
-      while (j >= 0) {
-        const uint32_t x = __hip_atomic_load(&lb[size_t(j) * 256 + d], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if ((x & ~kLbMask) == 0) {
-          if (++spins > kSpinLimit) {
-            atomicOr(&st.hdr->flags, FLAG_LOOKBACK);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-          continue;
-        }
-        excl += x & kLbMask;
-        if (x & kLbPre) break;
-        --j;
-      }
-      __hip_atomic_store(&lb[size_t(tile) * 256 + d], kLbPre | (excl + tot), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    }
-    s_gbase[d] = st.digit_off[pass * 256 + d] + excl;
+    __hip_atomic_store(&lb[size_t(tile) * 256 + d], (tile == 0 ? kLbPre : kLbAgg) | tot, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t start = block_exclusive_scan<kBlock>(tot, s_wave);
     s_start[d] = start;
     uint32_t run = start;
@@ -615,6 +723,47 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(DevState st, uint32_t pass,
       s_key[li] = k[r];
       s_val[li] = v[r];
     }
+  }
+  {
+    // thread d: counts of digit d in the tiles before this one, read four at
+    // a time, until a tile that already published its inclusive prefix
+    const uint32_t d = tid;
+    uint32_t excl = 0;
+    if (tile > 0) {
+      int j = int(tile) - 1;
+      uint32_t spins = 0;
+      bool done = false;
+      while (!done) {
+        uint32_t x[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          x[q] = (j - q >= 0) ? __hip_atomic_load(&lb[size_t(j - q) * 256 + d], __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT)
+                              : kLbPre;
+        bool stalled = false;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (done || stalled) continue;
+          if ((x[q] & ~kLbMask) == 0) {
+            stalled = true;
+            continue;
+          }
+          if (j >= 0) excl += x[q] & kLbMask;
+          if (x[q] & kLbPre) done = true;
+          else --j;
+        }
+        if (stalled && !done) {
+          if (++spins > kSpinLimit) {
+            atomicOr(&st.hdr->flags, FLAG_LOOKBACK);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+      __hip_atomic_store(&lb[size_t(tile) * 256 + d], kLbPre | (excl + tot), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+    s_gbase[d] = digit_base + excl;
   }
   __syncthreads();
   // write runs of equal digits to consecutive global positions
@@ -716,7 +865,10 @@ __global__ __launch_bounds__(kBlock) void k_reduce(DevState st, const uint32_t* 
   const uint32_t n = st.hdr->n_live;
   const uint32_t i0 = st.segstart[s];
   const uint32_t i1 = (s + 1 < S) ? st.segstart[s + 1] : n;
-  if (i1 - i0 > kBigSegment) return;  // handled by k_reduce_big
+  if (i1 - i0 > kBigSegment) {  // merged by a whole block in k_reduce_big
+    st.big[atomicAdd(&st.hdr->n_big, 1u)] = s;
+    return;
+  }
   const uint32_t rep = vals[i0];
   const uint64_t c0 = st.chk[rep];
   bool bad = false;
@@ -733,18 +885,19 @@ __global__ __launch_bounds__(kBlock) void k_reduce(DevState st, const uint32_t* 
   st.seg_cnt[s] = st.popc[rep];
 }
 
-// One block per class of more than kBigSegment faults (grid-stride over
-// classes): strided partial merges per thread, then a fixed-shape tree, so the
-// result is the same on every run.
+// One block per class of more than kBigSegment faults (the list k_reduce
+// built; its order does not matter): strided partial merges per thread, then
+// a fixed-shape tree, so the result is the same on every run.
 __global__ __launch_bounds__(kBlock) void k_reduce_big(DevState st, const uint32_t* __restrict__ vals) {
   __shared__ double s_q[kBlock];
   __shared__ int s_bad;
   const uint32_t S = st.hdr->n_seg;
   const uint32_t n = st.hdr->n_live;
-  for (uint32_t s = blockIdx.x; s < S; s += gridDim.x) {
+  const uint32_t nb = st.hdr->n_big;
+  for (uint32_t g = blockIdx.x; g < nb; g += gridDim.x) {
+    const uint32_t s = st.big[g];
     const uint32_t i0 = st.segstart[s];
     const uint32_t i1 = (s + 1 < S) ? st.segstart[s + 1] : n;
-    if (i1 - i0 <= kBigSegment) continue;
     if (threadIdx.x == 0) s_bad = 0;
     const uint32_t rep = vals[i0];
     const uint64_t c0 = st.chk[rep];
@@ -823,7 +976,7 @@ inline uint32_t cdiv(uint64_t a, uint64_t b) { return uint32_t((a + b - 1) / b);
 
 const char* kernel_name(int id) {
   static const char* names[K_COUNT] = {"k_prepare",     "k_sweep",      "k_cover",      "k_hash",
-                                       "k_scan_single", "k_compact",    "k_digit_offsets", "k_onesweep",
+                                       "k_scan_single", "k_compact",    "k_digit_totals", "k_onesweep",
                                        "k_heads_count", "k_heads_apply", "k_reduce",     "k_reduce_big",
                                        "k_scan_tiles",  "k_scan_apply", "k_edge_write"};
   return (id >= 0 && id < K_COUNT) ? names[id] : "?";
@@ -838,7 +991,10 @@ uint32_t sort_passes(uint64_t n) {
   return p > uint32_t(kMaxPasses) ? uint32_t(kMaxPasses) : p;
 }
 
-size_t sweep_lds_bytes(uint32_t n_qubits) { return size_t(2) * n_qubits * sizeof(uint64_t); }
+size_t sweep_lds_bytes(uint32_t n_qubits) {
+  return (size_t(3) * n_qubits + kInjLds) * sizeof(uint64_t) +
+         (size_t(2) * kWinOps + 2 * kLofsMax + 1 + 3 * kInjLds) * sizeof(uint32_t);
+}
 
 static size_t g_lds_limit = 64 * 1024;
 
@@ -854,8 +1010,11 @@ hipError_t configure_kernels() {
   // leave room for the sweep's static shared words
   size_t lim = size_t(lds) > 1024 ? size_t(lds) - 1024 : size_t(lds);
   if (lim > 64 * 1024) {
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            int(lim));
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep<true>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lim));
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep<false>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lim));
     if (e != hipSuccess) {
       (void)hipGetLastError();
       lim = 64 * 1024 - 1024;
@@ -893,18 +1052,22 @@ hipError_t enqueue_compile(const DevState& st_in, hipStream_t stream, const Laun
     GP_LAUNCH(K_PREPARE, k_prepare<<<g, kBlock, 0, stream>>>(st));
   }
   if (st.n_items) {
-    GP_LAUNCH(K_SWEEP, k_sweep<<<st.n_items, kSweepBlock, sweep_lds_bytes(st.n_qubits), stream>>>(st));
+    if (st.n_layers + 2 <= uint32_t(kLofsMax) && st.max_col_inj <= uint32_t(kInjLds)) {
+      GP_LAUNCH(K_SWEEP, k_sweep<true><<<st.n_items, kSweepBlock, sweep_lds_bytes(st.n_qubits), stream>>>(st));
+    } else {
+      GP_LAUNCH(K_SWEEP, k_sweep<false><<<st.n_items, kSweepBlock, sweep_lds_bytes(st.n_qubits), stream>>>(st));
+    }
   }
   GP_LAUNCH(K_COVER, k_cover<<<st.n_layers + 1, kBlock, 0, stream>>>(st));
   if (n == 0) {
     GP_LAUNCH(K_EDGE_WRITE, k_edge_write<<<1, kBlock, 0, stream>>>(st));
     return hipSuccess;
   }
-  GP_LAUNCH(K_HASH, k_hash<<<cdiv(n, kBlock), kBlock, 0, stream>>>(st));
+  GP_LAUNCH(K_HASH, k_hash<<<st.n_hchunks, kBlock, 0, stream>>>(st));
   GP_LAUNCH(K_SCAN_SINGLE, k_scan_single<uint32_t><<<1, kScanSingleBlock, 0, stream>>>(st.tile_cnt, ntiles, nullptr,
                                                                                       &st.hdr->n_live));
   GP_LAUNCH(K_COMPACT, k_compact<<<ntiles, kBlock, 0, stream>>>(st));
-  GP_LAUNCH(K_DIGIT_OFFSETS, k_digit_offsets<<<st.n_pass, 256, 0, stream>>>(st, ntiles));
+  GP_LAUNCH(K_DIGIT_OFFSETS, k_digit_totals<<<st.n_pass * 256, kBlock, 0, stream>>>(st, ntiles));
   for (uint32_t pass = 0; pass < st.n_pass; ++pass) {
     const int src = pass & 1, dst = src ^ 1;
     GP_LAUNCH(K_ONESWEEP, k_onesweep<<<ntiles, kBlock, 0, stream>>>(st, pass, st.key[src], st.val[src], st.key[dst],
@@ -917,7 +1080,7 @@ hipError_t enqueue_compile(const DevState& st_in, hipStream_t stream, const Laun
   GP_LAUNCH(K_HEADS_APPLY, k_heads_apply<<<ntiles, kBlock, 0, stream>>>(st.key[fin], st.hdr, st.tile_sum,
                                                                          st.segstart));
   GP_LAUNCH(K_REDUCE, k_reduce<<<cdiv(n, kBlock), kBlock, 0, stream>>>(st, st.val[fin]));
-  GP_LAUNCH(K_REDUCE_BIG, k_reduce_big<<<cdiv(n, kBigSegment * 64) + 1, kBlock, 0, stream>>>(st, st.val[fin]));
+  GP_LAUNCH(K_REDUCE_BIG, k_reduce_big<<<256, kBlock, 0, stream>>>(st, st.val[fin]));
   GP_LAUNCH(K_SCAN_TILES,
             k_scan_tiles<<<ntiles, kBlock, 0, stream>>>(st.seg_cnt, n, &st.hdr->n_seg, st.tile_sum));
   GP_LAUNCH(K_SCAN_SINGLE, k_scan_single<uint64_t><<<1, kScanSingleBlock, 0, stream>>>(st.tile_sum, ntiles, nullptr,

@@ -367,27 +367,99 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
 
   // ---- sweep items: one per detector column; observable columns, which stay
   // live over the whole circuit, are cut into chunks of about
-  // obs_chunk_faults emitted faults so that their emission spreads over CUs
+  // obs_chunk_faults emitted faults so that their emission spreads over CUs.
+  // Each chunk re-sweeps from the column's top, so the lowest chunks run
+  // longest; they are listed first so that they start first.
   const uint32_t chunk = std::max<uint32_t>(obs_chunk_faults, 1);
-  for (uint32_t w = 0; w < lw.w; w++) {
+  for (uint32_t w = lw.wd; w < lw.w; w++) {
     int32_t top = lw.col_top[w];
     if (top < 0) continue;
-    if (w < lw.wd) {
-      lw.item_col.push_back(w);
-      lw.item_blo.push_back(0);
-      lw.item_bhi.push_back(uint32_t(top));
-      continue;
-    }
+    std::vector<std::pair<uint32_t, uint32_t>> ranges;
     int32_t hi = top;
     while (hi >= 0) {
       int32_t lo = hi;
       while (lo > 0 && lw.bnd_fault_off[hi + 1] - lw.bnd_fault_off[lo - 1] <= chunk) lo--;
-      lw.item_col.push_back(w);
-      lw.item_blo.push_back(uint32_t(lo));
-      lw.item_bhi.push_back(uint32_t(hi));
+      ranges.emplace_back(uint32_t(lo), uint32_t(hi));
       hi = lo - 1;
     }
+    for (size_t k = ranges.size(); k-- > 0;) {
+      lw.item_col.push_back(w);
+      lw.item_blo.push_back(ranges[k].first);
+      lw.item_bhi.push_back(ranges[k].second);
+    }
   }
+  for (uint32_t w = 0; w < lw.wd; w++) {
+    if (lw.col_top[w] < 0) continue;
+    lw.item_col.push_back(w);
+    lw.item_blo.push_back(0);
+    lw.item_bhi.push_back(uint32_t(lw.col_top[w]));
+  }
+
+  // ---- compact sweep ops (qubit indices must fit the compact word)
+  lw.ops32.resize(lw.ops.size());
+  for (size_t k = 0; k < lw.ops.size(); k++) {
+    const uint64_t op = lw.ops[k];
+    const uint32_t kind = uint32_t(op >> 56), a = uint32_t(op >> 28) & kField, b = uint32_t(op) & kField;
+    const bool two = kind == OP_CX || kind == OP_CZ || kind == OP_SWAP;
+    lw.ops32[k] = (a < kMaxSweepQubits && (!two || b < kMaxSweepQubits)) ? pack_op32(kind, a, two ? b : 0)
+                                                                         : 0xFFFFFFFFu;
+  }
+
+  // ---- per-column leaf injections, top layer first
+  {
+    std::vector<uint32_t> meas_qubit(n_meas, 0);
+    for (uint64_t op : lw.ops) {
+      const uint32_t kind = uint32_t(op >> 56);
+      if (kind >= OP_M) meas_qubit[uint32_t(op) & kField] = uint32_t(op >> 28) & kField;
+    }
+    struct Inj {
+      uint32_t w, layer, qubit, m;
+      uint64_t word;
+    };
+    std::vector<Inj> inj;
+    for (uint32_t m = 0; m < n_meas; m++) {
+      for (uint32_t k = lw.leaf_off[m]; k < lw.leaf_off[m + 1]; k++) {
+        const uint32_t bit = lw.leaf_bits[k];
+        const uint32_t w = bit >> 6;
+        if (!inj.empty() && inj.back().m == m && inj.back().w == w) {
+          inj.back().word |= 1ull << (bit & 63);
+        } else {
+          inj.push_back(Inj{w, lw.meas_layer[m], meas_qubit[m], m, 1ull << (bit & 63)});
+        }
+      }
+    }
+    std::stable_sort(inj.begin(), inj.end(), [](const Inj& x, const Inj& y) {
+      if (x.w != y.w) return x.w < y.w;
+      return x.layer > y.layer;
+    });
+    lw.inj_off.assign(size_t(lw.w) + 1, 0);
+    for (const Inj& e : inj) lw.inj_off[e.w + 1]++;
+    for (uint32_t w = 0; w < lw.w; w++) lw.inj_off[w + 1] += lw.inj_off[w];
+    lw.inj_layer.resize(inj.size());
+    lw.inj_qubit.resize(inj.size());
+    lw.inj_word.resize(inj.size());
+    for (size_t k = 0; k < inj.size(); k++) {
+      lw.inj_layer[k] = inj[k].layer;
+      lw.inj_qubit[k] = inj[k].qubit;
+      lw.inj_word[k] = inj[k].word;
+    }
+    lw.inj_next.resize(inj.size());
+    for (uint32_t w = 0; w < lw.w; w++) {
+      const uint32_t a = lw.inj_off[w], e = lw.inj_off[w + 1];
+      uint32_t next = e - a;
+      for (uint32_t k = e; k-- > a;) {
+        if (k + 1 < e && lw.inj_layer[k + 1] != lw.inj_layer[k]) next = k + 1 - a;
+        lw.inj_next[k] = next;
+      }
+    }
+  }
+
+  // ---- hash chunks: 256 positions of one boundary at most
+  for (uint32_t b = 0; b <= L; b++)
+    for (uint32_t p0 = lw.bnd_fault_off[b]; p0 < lw.bnd_fault_off[b + 1]; p0 += 256) {
+      lw.hchunk_pos.push_back(p0);
+      lw.hchunk_bnd.push_back(b);
+    }
 
   // ---- FNV-1a over the 8W octets of a signature: a run of k zero words
   // multiplies the state by prime^(8k)

@@ -37,6 +37,16 @@ inline uint64_t pack_op(uint32_t kind, uint32_t a, uint32_t b) {
   return (uint64_t(kind) << 56) | (uint64_t(a & kField) << 28) | uint64_t(b & kField);
 }
 
+// Compact op word for the device sweep: kind in bits 28..31, a in bits 14..27,
+// b (second qubit, unused for one-qubit operations) in bits 0..13. Leaves
+// reach the sweep through the per-column injection lists instead.
+constexpr uint32_t kQubitBits = 14;
+constexpr uint32_t kMaxSweepQubits = 1u << kQubitBits;
+constexpr uint32_t kQField = kMaxSweepQubits - 1;
+inline uint32_t pack_op32(uint32_t kind, uint32_t a, uint32_t b) {
+  return (kind << 28) | ((a & kQField) << kQubitBits) | (b & kQField);
+}
+
 struct Lowered {
   uint32_t n_qubits = 0, n_layers = 0, n_meas = 0, n_det = 0, n_obs = 0;
   uint32_t wd = 0, wo = 0, w = 0;     // word columns: detector, observable, total
@@ -65,6 +75,19 @@ struct Lowered {
   std::vector<uint32_t> item_col, item_blo, item_bhi;  // emission boundaries [blo, bhi]
 
   std::vector<uint64_t> fnv_pow;            // w + 1 entries: FNV prime^(8k) mod 2^64
+
+  // device sweep inputs
+  std::vector<uint32_t> ops32;              // compact op words, same order as ops
+  // per column: the leaf words it receives (Eq. 2), one entry per (column,
+  // measurement), ordered by layer from the top down: the measurement's layer,
+  // its qubit, and the 64-bit word of leaf bits that fall in this column
+  std::vector<uint32_t> inj_off;            // w + 1
+  std::vector<uint32_t> inj_layer, inj_qubit;
+  std::vector<uint64_t> inj_word;
+  std::vector<uint32_t> inj_next;           // per entry: first entry (column-relative) of a lower layer
+
+  // hash work chunks: at most 256 consecutive fault positions of one boundary
+  std::vector<uint32_t> hchunk_pos, hchunk_bnd;
 };
 
 struct LowerError {

@@ -6,6 +6,7 @@
 // those signatures with the oracle's before any kernel runs on a GPU.
 #include <cstdint>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -24,6 +25,13 @@ int bad(const char* what) {
 }  // namespace
 
 extern "C" const char* hc_error() { return g_msg.c_str(); }
+
+// per work item of the last hc_run: layers swept, words emitted
+static std::vector<uint64_t> g_item_stats;
+extern "C" uint64_t hc_item_stats(uint64_t* out, uint64_t cap) {
+  for (size_t i = 0; i < g_item_stats.size() && i < cap; i++) out[i] = g_item_stats[i];
+  return g_item_stats.size();
+}
 
 // stats: [0] faults, [1] items, [2] slab words, [3] layers, [4] gauge flag,
 //        [5] words written, [6] columns, [7] qubits
@@ -65,6 +73,8 @@ extern "C" int hc_run(const char* text, size_t len, const double* rates, size_t 
   std::vector<int32_t> cover_lo(W, 0);
   uint64_t nwritten = 0;
   int gauge = 0;
+  if (lw.ops32.size() != lw.ops.size() || lw.inj_off.size() != W + 1u) return bad("device tables missing");
+  g_item_stats.assign(2 * lw.item_col.size(), 0);
   for (size_t it = 0; it < lw.item_col.size(); it++) {
     const uint32_t w = lw.item_col[it];
     if (w >= W) return bad("item column");
@@ -74,24 +84,36 @@ extern "C" int hc_run(const char* text, size_t len, const double* rates, size_t 
     const uint64_t base = lw.col_base[w];
     const uint64_t cap = lw.bnd_fault_off[top + 1];
     std::vector<uint64_t> fr(2 * size_t(n), 0);
+    std::vector<uint64_t> pend(n, 0);
+    uint32_t ip = lw.inj_off[w];
+    const uint32_t ip_end = lw.inj_off[w + 1];
+    auto scatter = [&](int layer) -> int {
+      while (ip < ip_end && int(lw.inj_layer[ip]) == layer) {
+        const uint32_t q = lw.inj_qubit[ip];
+        if (q >= n) return bad("injection qubit");
+        if (pend[q]) return bad("two injections for one qubit in one layer");
+        pend[q] = lw.inj_word[ip];
+        ip++;
+      }
+      if (ip < ip_end && int(lw.inj_layer[ip]) > layer) return bad("injections out of order");
+      return 0;
+    };
+    if (ip < ip_end && int(lw.inj_layer[ip]) != top) return bad("first injection is not at the top layer");
+    if (scatter(top)) return -100;
     int nz = 0;
     bool dead = false;
     for (int t = top; t >= blo; --t) {
+      g_item_stats[2 * it]++;
       int dnz = 0;
       auto nzd = [](uint64_t a, uint64_t b) { return int(a != 0) - int(b != 0); };
       for (uint32_t o = lw.layer_off[t]; o < lw.layer_off[t + 1]; o++) {
-        uint64_t op = lw.ops[o];
-        uint32_t kind = uint32_t(op >> 56), a = uint32_t(op >> 28) & kField, b = uint32_t(op) & kField;
+        const uint32_t op = lw.ops32[o];
+        if (op == 0xFFFFFFFFu) return bad("qubit index too large for the compact op word");
+        const uint32_t kind = op >> 28, a = (op >> kQubitBits) & kQField, b = op & kQField;
+        if ((lw.ops[o] >> 56) != kind) return bad("compact op kind differs");
         uint64_t& xa = fr[2 * a];
         uint64_t& za = fr[2 * a + 1];
         const uint64_t x0 = xa, z0 = za;
-        auto leaf = [&](uint32_t m) {
-          uint64_t v = 0;
-          if (m + 1 >= lw.leaf_off.size()) return v;
-          for (uint32_t k = lw.leaf_off[m]; k < lw.leaf_off[m + 1]; k++)
-            if ((lw.leaf_bits[k] >> 6) == w) v |= 1ull << (lw.leaf_bits[k] & 63);
-          return v;
-        };
         switch (kind) {
           case OP_H: xa = z0; za = x0; break;
           case OP_S: xa = x0 ^ z0; dnz += nzd(xa, x0); break;
@@ -117,13 +139,15 @@ extern "C" int hc_run(const char* text, size_t len, const double* rates, size_t 
           }
           case OP_R: gauge |= z0 != 0; xa = 0; za = 0; dnz -= int(x0 != 0) + int(z0 != 0); break;
           case OP_RX: gauge |= x0 != 0; xa = 0; za = 0; dnz -= int(x0 != 0) + int(z0 != 0); break;
-          case OP_M: gauge |= z0 != 0; xa = x0 ^ leaf(b); dnz += nzd(xa, x0); break;
-          case OP_MX: gauge |= x0 != 0; za = z0 ^ leaf(b); dnz += nzd(za, z0); break;
-          case OP_MR: gauge |= z0 != 0; xa = leaf(b); za = 0; dnz += nzd(xa, x0) - int(z0 != 0); break;
-          case OP_MRX: gauge |= x0 != 0; za = leaf(b); xa = 0; dnz += nzd(za, z0) - int(x0 != 0); break;
+          case OP_M: gauge |= z0 != 0; xa = x0 ^ pend[a]; pend[a] = 0; dnz += nzd(xa, x0); break;
+          case OP_MX: gauge |= x0 != 0; za = z0 ^ pend[a]; pend[a] = 0; dnz += nzd(za, z0); break;
+          case OP_MR: gauge |= z0 != 0; xa = pend[a]; za = 0; pend[a] = 0; dnz += nzd(xa, x0) - int(z0 != 0); break;
+          case OP_MRX: gauge |= x0 != 0; za = pend[a]; xa = 0; pend[a] = 0; dnz += nzd(za, z0) - int(x0 != 0); break;
           default: return bad("op kind");
         }
       }
+      for (uint32_t q = 0; q < n; q++)
+        if (pend[q]) return bad("an injection was not consumed by a measurement of its layer");
       nz += dnz;
       int full = 0;
       for (uint64_t v : fr) full += v != 0;
@@ -155,9 +179,11 @@ extern "C" int hc_run(const char* text, size_t len, const double* rates, size_t 
             written[idx] = 1;
             slab[idx] = words[k];
             nwritten++;
+            g_item_stats[2 * it + 1]++;
           }
         }
       }
+      if (t > 0 && scatter(t - 1)) return -100;
       if (nz == 0 && t <= clo) {
         if (t <= bhi) cover_lo[w] = t;
         dead = true;
@@ -166,6 +192,22 @@ extern "C" int hc_run(const char* text, size_t len, const double* rates, size_t 
     }
     if (!dead && blo == 0)
       for (uint32_t q = 0; q < n; q++) gauge |= fr[2 * q + 1] != 0;
+  }
+  // hash chunks cover every position once, each inside one boundary
+  {
+    std::vector<char> seen(F, 0);
+    if (lw.hchunk_pos.size() != lw.hchunk_bnd.size()) return bad("hash chunk arrays");
+    for (size_t k = 0; k < lw.hchunk_pos.size(); k++) {
+      const uint32_t b = lw.hchunk_bnd[k], p0 = lw.hchunk_pos[k];
+      if (b > L || p0 < lw.bnd_fault_off[b] || p0 >= lw.bnd_fault_off[b + 1]) return bad("hash chunk boundary");
+      const uint32_t p1 = std::min<uint32_t>(p0 + 256, lw.bnd_fault_off[b + 1]);
+      for (uint32_t p = p0; p < p1; p++) {
+        if (seen[p]) return bad("hash chunks overlap");
+        seen[p] = 1;
+      }
+    }
+    for (uint64_t p = 0; p < F; p++)
+      if (!seen[p]) return bad("hash chunks miss a position");
   }
   // signatures of every fault position from the covered columns
   uint64_t nb = 0;
