@@ -155,6 +155,15 @@ int gp_timing_entry(const gp_driver* drv, int index, const char** name,
 int gp_debug_set_key_bits(gp_driver* drv, int bits);
 uint64_t gp_debug_collision_retries(const gp_driver* drv);
 
+/* Test hook: stage-2 grouping method for later gp_run calls. 0 (default):
+ * where the circuit allows it, one stable radix pass on the top 8-bit key
+ * digit splits the faults into 256 buckets and each bucket is sorted and
+ * merged in LDS (a bucket over its LDS capacity makes gp_fetch redo the
+ * grouping with the full sort); 1: always the full LSD radix sort over every
+ * key digit. Both give the same hyperedges (same classes, same merge order
+ * within a class; the edge order may differ). GP_E_ARG for other values. */
+int gp_debug_set_sort_mode(gp_driver* drv, int mode);
+
 /* Profiling hook: device wall-clock stamps of every stage-1 sweep item of the
  * last gp_run (start, end pairs; `cap` entries at most), the item count, and
  * the clock rate in Hz. Synchronises the driver's stream. */

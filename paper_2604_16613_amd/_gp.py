@@ -29,7 +29,7 @@ EXPORTS = (
     "gp_timing_entry", "gp_edges_count", "gp_edges_detectors", "gp_edges_observables",
     "gp_edges_offsets", "gp_edges_bits", "gp_edges_probabilities", "gp_edges_to_dem_text",
     "gp_edges_free", "gp_free", "gp_debug_set_key_bits", "gp_debug_collision_retries",
-    "gp_debug_sweep_times",
+    "gp_debug_sweep_times", "gp_debug_set_sort_mode",
 )
 
 
@@ -116,6 +116,7 @@ def load():
         "gp_free": ([_vp], None),
         "gp_debug_set_key_bits": ([_vp, ctypes.c_int], ctypes.c_int),
         "gp_debug_collision_retries": ([_vp], _u64),
+        "gp_debug_set_sort_mode": ([_vp, ctypes.c_int], ctypes.c_int),
         "gp_debug_sweep_times": ([_vp, ctypes.POINTER(_u64), _u64, ctypes.POINTER(_u64),
                                   ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     }
@@ -275,6 +276,10 @@ def gp_edges_free(e: int) -> None:
 
 def gp_debug_set_key_bits(drv: int, bits: int) -> None:
     _check(load().gp_debug_set_key_bits(drv, bits))
+
+
+def gp_debug_set_sort_mode(drv: int, mode: int) -> None:
+    _check(load().gp_debug_set_sort_mode(drv, mode))
 
 
 def gp_debug_collision_retries(drv: int) -> int:

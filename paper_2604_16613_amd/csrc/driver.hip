@@ -33,7 +33,6 @@ int hip_fail(hipError_t e, const char* what) {
     if (_e != hipSuccess) return hip_fail(_e, what); \
   } while (0)
 
-constexpr uint32_t kObsChunkFaults = 65536;
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -122,6 +121,7 @@ struct gp_driver {
   gp::DevState st{};
 
   uint32_t key_bits = 64;      // test hook: class keys cut to this many bits
+  uint32_t sort_mode = gp::SORT_AUTO;  // test hook: force the full radix sort
   uint64_t collision_retries = 0;
 
   bool timing = false;
@@ -222,7 +222,8 @@ void fill_bounds(const gp::Lowered& lw, gp_bounds* out) {
   b.max_leaf_bits = lw.leaf_bits.size();
   // any circuit within these bounds needs at most one word per (fault, column)
   b.max_slab_words = std::max<uint64_t>(lw.slab_words, lw.n_faults * uint64_t(lw.w));
-  b.max_items = uint64_t(lw.w) + (lw.n_faults / kObsChunkFaults + 2) * uint64_t((lw.n_obs + 63) / 64) + 16;
+  // detector columns one item each; observable ranges fill the slots left
+  b.max_items = std::max<uint64_t>(gp::kSweepSlots, lw.w) + 16;
   *out = b;
 }
 
@@ -236,7 +237,7 @@ int gp_bounds_from_circuit(const char* text, size_t len, gp_bounds* out) {
   if (!text || !out) return fail(GP_E_ARG, "null argument");
   gp::Lowered lw;
   gp::LowerError err{};
-  int rc = gp::lower_circuit(text, len, nullptr, 0, kObsChunkFaults, lw, err);
+  int rc = gp::lower_circuit(text, len, nullptr, 0, gp::kSweepSlots, lw, err);
   if (rc) return fail(rc, err.msg);
   fill_bounds(lw, out);
   return GP_OK;
@@ -287,7 +288,7 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   }
   d->max_w = std::max<uint32_t>(words_for(b.max_detectors, b.max_observables), 1);
   if (!b.max_slab_words) b.max_slab_words = b.max_faults * d->max_w;
-  if (!b.max_items) b.max_items = uint64_t(d->max_w) + (b.max_faults / kObsChunkFaults + 2) * ((b.max_observables + 63) / 64) + 16;
+  if (!b.max_items) b.max_items = std::max<uint64_t>(gp::kSweepSlots, d->max_w) + 16;
   d->bits_cap = std::max<uint64_t>(b.max_faults * 8, 1u << 20);
   d->max_tiles = uint32_t((b.max_faults + 4095) / 4096) + 1;
 
@@ -316,13 +317,12 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   if ((rc = dev_alloc(d, &st.cover_lo, d->max_w, "cover_lo"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.cov, (size_t(b.max_layers) + 1) * d->max_w, "cover lists"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.ncov, size_t(b.max_layers) + 1, "cover counts"))) return cleanup(rc);
-  if ((rc = dev_alloc(d, &st.pfault, F, "fault probabilities"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.frp, F, "fault probabilities and check hashes"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.frec, F, "fault records"))) return cleanup(rc);
   for (int k = 0; k < 2; k++) {
     if ((rc = dev_alloc(d, &st.key[k], F, "keys"))) return cleanup(rc);
     if ((rc = dev_alloc(d, &st.val[k], F, "values"))) return cleanup(rc);
   }
-  if ((rc = dev_alloc(d, &st.chk, F, "check hashes"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.popc, F, "signature weights"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.nzm, F, "non-zero word masks"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.tile_cnt, size_t(d->max_tiles) + 1, "tile counts"))) return cleanup(rc);
@@ -336,6 +336,7 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   st.max_tiles = d->max_tiles;
   if ((rc = dev_alloc(d, &st.segstart, F, "class starts"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.big, F / 64 + 1, "large classes"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.bkt, 3 * size_t(gp::kBuckets + 1), "bucket offsets"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.seg_q, F, "class probabilities"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.seg_rep, F, "class representatives"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.seg_cnt, F, "class bit counts"))) return cleanup(rc);
@@ -366,7 +367,7 @@ int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, si
   gp::LowerError err{};
   d->lowered = false;
   d->ran = false;
-  int rc = gp::lower_circuit(text, len, rates, n_rates, kObsChunkFaults, d->lw, err);
+  int rc = gp::lower_circuit(text, len, rates, n_rates, gp::kSweepSlots, d->lw, err);
   if (rc) return fail(rc, err.msg);
   if ((rc = check_bounds(d, d->lw))) return rc;
   const gp::Lowered& lw = d->lw;
@@ -464,6 +465,7 @@ int gp_run(gp_driver* d) {
   }
   d->st.key_mode = 0;
   d->st.key_bits = d->key_bits;
+  d->st.sort_mode = d->sort_mode;
   hipError_t e = gp::enqueue_compile(d->st, d->stream, hook);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   d->ran = true;
@@ -488,19 +490,33 @@ int gp_fetch(gp_driver* d, gp_edges** out) {
   HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
   collect_timing(d);
   gp::DevHeader hdr = *d->h_hdr;
-  if ((hdr.flags & gp::FLAG_COLLISION) && !(hdr.flags & gp::FLAG_GAUGE)) {
-    // two signatures met under one key: compile again keyed on both hashes
-    d->collision_retries++;
-    d->st.key_mode = 1;
+  // at most two more compiles: a bucket too large for LDS redoes the grouping
+  // with the full radix sort; two signatures under one key redo it keyed on
+  // both hashes (which always takes the full sort)
+  for (int attempt = 0; attempt < 2 && !(hdr.flags & gp::FLAG_GAUGE); attempt++) {
+    if (hdr.flags & gp::FLAG_BUCKET) {
+      d->st.sort_mode = gp::SORT_FULL;
+    } else if ((hdr.flags & gp::FLAG_COLLISION) && d->st.key_mode == 0) {
+      d->collision_retries++;
+      d->st.key_mode = 1;
+    } else {
+      break;
+    }
     gp::LaunchHook none;
     hipError_t e = gp::enqueue_compile(d->st, d->stream, none);
-    d->st.key_mode = 0;
-    if (e != hipSuccess) return hip_fail(e, "kernel launch");
+    if (e != hipSuccess) {
+      d->st.key_mode = 0;
+      d->st.sort_mode = d->sort_mode;
+      return hip_fail(e, "kernel launch");
+    }
     HIP_TRY(hipMemcpyAsync(d->h_hdr, d->st.hdr, sizeof(gp::DevHeader), hipMemcpyDeviceToHost, d->stream),
             "download header");
     HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
     hdr = *d->h_hdr;
   }
+  d->st.key_mode = 0;
+  d->st.sort_mode = d->sort_mode;
+  if (hdr.flags & gp::FLAG_BUCKET) return fail(GP_E_HIP, "bucket grouping overflow after the full-sort retry");
   if (hdr.flags & gp::FLAG_GAUGE)
     return fail(GP_E_NONDETERMINISTIC,
                 "a detector or observable is sensitive to an error right after a reset or measurement "
@@ -591,6 +607,13 @@ int gp_debug_set_key_bits(gp_driver* d, int bits) {
 }
 
 uint64_t gp_debug_collision_retries(const gp_driver* d) { return d ? d->collision_retries : 0; }
+
+int gp_debug_set_sort_mode(gp_driver* d, int mode) {
+  if (!d) return fail(GP_E_ARG, "null driver");
+  if (mode != int(gp::SORT_AUTO) && mode != int(gp::SORT_FULL)) return fail(GP_E_ARG, "sort mode must be 0 or 1");
+  d->sort_mode = uint32_t(mode);
+  return GP_OK;
+}
 
 int gp_debug_sweep_times(gp_driver* d, uint64_t* out, uint64_t cap, uint64_t* n_items, double* clock_hz) {
   if (!d || !out || !n_items) return fail(GP_E_ARG, "null argument");

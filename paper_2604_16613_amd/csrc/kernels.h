@@ -25,11 +25,28 @@ enum : uint32_t {
   FLAG_COLLISION = 2u,  // equal class keys with different check hashes
   FLAG_OVERFLOW = 4u,   // output signature bits exceed the reserved capacity
   FLAG_LOOKBACK = 8u,   // a sort tile gave up waiting for its predecessor (never expected)
+  FLAG_BUCKET = 16u,    // a bucket of the bucket grouping exceeded its LDS capacity (redo with the full sort)
 };
+
+// Stage-2 grouping: 0 = buckets (one stable pass on the top key digit, then
+// every bucket sorted and merged in LDS) where they apply, else the full
+// radix sort; 1 = always the full radix sort.
+enum : uint32_t { SORT_AUTO = 0, SORT_FULL = 1 };
+constexpr uint32_t kBuckets = 256;         // buckets = values of the top 8-bit digit
+constexpr uint32_t kBucketCap = 8192;      // faults one bucket sorts in LDS
+// bucket grouping is used up to this many faults (mean bucket <= 6144)
+constexpr uint64_t kBucketMaxFaults = uint64_t(kBuckets) * 6144;
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kTile = 4096;       // items per tile in the sort, scan and compaction kernels
 constexpr int kMaxPasses = 8;     // 8-bit digits of a 64-bit key
+
+// Per fault position: what the merge gathers for each class member, in one
+// 16-byte record (one random sector per member instead of two).
+struct __align__(16) FaultRec {
+  double p;      // fault probability
+  uint64_t chk;  // check hash of the signature
+};
 
 // Everything one compile reads or writes on the device.
 struct DevState {
@@ -72,6 +89,7 @@ struct DevState {
   uint32_t key_mode;
   uint32_t key_bits;
   uint32_t n_pass;      // radix passes (8-bit digits) over the class key
+  uint32_t sort_mode;   // SORT_*
   uint32_t max_tiles;   // tiles the sort/compaction scratch is sized for
 
   // work buffers
@@ -79,11 +97,10 @@ struct DevState {
   int32_t* cover_lo;     // per column: lowest boundary written
   uint32_t* cov;         // per boundary: covered columns, ascending ((L+1) x W)
   uint32_t* ncov;        // per boundary: number of covered columns
-  double* pfault;        // per fault position: probability
+  FaultRec* frp;         // per fault position: probability and check hash
   uint32_t* frec;        // per fault position: qubit a | qubit b << 14 | Pauli code << 28
   uint64_t* key[2];      // class keys: per position (key[1]) then compacted, ping-pong in the sort
   uint32_t* val[2];      // fault positions riding with the keys
-  uint64_t* chk;         // per fault position: check hash
   uint32_t* popc;        // per fault position: signature weight
   uint64_t* nzm;         // per fault position: which covered columns hold non-zero words
   uint32_t* tile_cnt;    // per compaction tile: live faults, then their exclusive prefix
@@ -94,6 +111,7 @@ struct DevState {
   uint32_t* tile_sum;    // scan tile sums
   uint32_t* segstart;    // first sorted index of each class
   uint32_t* big;         // classes too large for one thread
+  uint32_t* bkt;         // per bucket (kBuckets + 1 each): class, bit and fault offsets
   double* seg_q;         // merged probability per class
   uint32_t* seg_rep;     // representative fault position per class
   uint32_t* seg_cnt;     // signature bits per class
@@ -109,7 +127,8 @@ struct DevState {
 // Names of the kernels (for timing tables).
 enum KernelId : int {
   K_PREPARE = 0, K_SWEEP, K_COVER, K_HASH, K_SCAN_SINGLE, K_COMPACT, K_DIGIT_OFFSETS, K_ONESWEEP,
-  K_HEADS_COUNT, K_HEADS_APPLY, K_REDUCE, K_REDUCE_BIG, K_SCAN_TILES, K_SCAN_APPLY, K_EDGE_WRITE, K_COUNT
+  K_HEADS_COUNT, K_HEADS_APPLY, K_REDUCE, K_REDUCE_BIG, K_SCAN_TILES, K_SCAN_APPLY, K_EDGE_WRITE, K_BUCKET,
+  K_BUCKET_SCAN, K_COUNT
 };
 const char* kernel_name(int id);
 
@@ -129,6 +148,8 @@ hipError_t enqueue_compile(const DevState& st, hipStream_t stream, const LaunchH
 
 // Dynamic LDS the sweep needs for n qubits, and the largest it may use.
 size_t sweep_lds_bytes(uint32_t n_qubits);
+// Whether the bucket grouping's LDS fits this device (set by configure_kernels).
+bool bucket_grouping_available();
 // Largest word-column count the hash kernel stages in LDS.
 constexpr uint32_t kMaxHashWords = 1024;
 size_t sweep_lds_limit();

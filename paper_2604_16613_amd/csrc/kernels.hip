@@ -42,12 +42,14 @@ constexpr int kLofsMax = 2048;         // layer offsets staged in LDS when the c
 constexpr int kInjLds = 512;           // a column's injections staged in LDS when it has at most this many
 constexpr int kBlock = 256;
 constexpr int kPerThread = kTile / kBlock;
+static_assert(kPerThread * (kBlock / 64) == 64, "compaction offsets are scanned by one wave");
 constexpr int kScanSingleBlock = 1024;
 constexpr uint32_t kBigSegment = 64;   // classes with more faults reduce in a whole block
 constexpr uint32_t kLbAgg = 1u << 30;  // look-back status: tile aggregate published
 constexpr uint32_t kLbPre = 2u << 30;  // look-back status: inclusive prefix published
 constexpr uint32_t kLbMask = (1u << 30) - 1;
 constexpr uint32_t kSpinLimit = 1u << 22;
+constexpr int kLookWin = 16;            // look-back: predecessor tiles read per round
 
 // Barrier that orders LDS only: global loads issued before it (prefetches)
 // stay in flight across it.
@@ -140,7 +142,7 @@ __global__ void k_prepare(DevState st) {
     const uint32_t qa = st.chan_qa[c] & kQField;
     const uint32_t qb = kind == CH_DEP2 ? (st.chan_qb[c] & kQField) : 0u;
     for (uint32_t f = f0; f < f1; ++f) {
-      st.pfault[f] = p;
+      st.frp[f].p = p;
       // Pauli code: x on a | z on a << 1 | x on b << 2 | z on b << 3
       const uint32_t k = f - f0;
       const uint32_t code = kind == CH_DEP2 ? k + 1
@@ -173,76 +175,66 @@ __global__ void k_prepare(DevState st) {
 
 __device__ __forceinline__ int nzd(uint64_t nv, uint64_t ov) { return int(nv != 0) - int(ov != 0); }
 
-// Apply one compact operation backwards to the frame (X_q at 2q, Z_q at
-// 2q+1). A measurement takes its leaf word for this column from pend[q]
-// (scattered there from the column's injection list) and clears it.
-__device__ __forceinline__ void apply_op(uint32_t op, uint64_t* frame, uint64_t* pend, int& dnz, int& gauge) {
+// Apply one compact operation backwards to the frame (the (X_q, Z_q) pair of
+// qubit q at frame[q]). Both qubits' pairs are read up front (a one-qubit op
+// reads qubit 0's and ignores it). A measurement takes its leaf word for this
+// column from pend[q] (scattered there from the column's injection list) and
+// clears it.
+__device__ __forceinline__ void apply_op(uint32_t op, ulonglong2* frame, uint64_t* pend, int& dnz, int& gauge) {
   const uint32_t kind = op >> 28;
   const uint32_t a = (op >> kQubitBits) & kQField;
   const uint32_t b = op & kQField;
-  uint64_t* fa = frame + 2 * a;
-  const uint64_t xa = fa[0], za = fa[1];
+  const ulonglong2 pa = frame[a], pb = frame[b];
+  const uint64_t xa = pa.x, za = pa.y, xb = pb.x, zb = pb.y;
   switch (kind) {
     case OP_H:
-      fa[0] = za;
-      fa[1] = xa;
+      frame[a] = make_ulonglong2(za, xa);
       break;
     case OP_S: {  // X -> XZ
       const uint64_t n = xa ^ za;
-      fa[0] = n;
+      frame[a].x = n;
       dnz += nzd(n, xa);
       break;
     }
     case OP_SQRTX: {  // Z -> XZ
       const uint64_t n = xa ^ za;
-      fa[1] = n;
+      frame[a].y = n;
       dnz += nzd(n, za);
       break;
     }
     case OP_CX: {  // X_c -> X_c X_t, Z_t -> Z_t Z_c
-      uint64_t* fb = frame + 2 * b;
-      const uint64_t xb = fb[0], zb = fb[1];
       const uint64_t nxa = xa ^ xb, nzb = zb ^ za;
-      fa[0] = nxa;
-      fb[1] = nzb;
+      frame[a].x = nxa;
+      frame[b].y = nzb;
       dnz += nzd(nxa, xa) + nzd(nzb, zb);
       break;
     }
     case OP_CZ: {  // X_a -> X_a Z_b, X_b -> X_b Z_a
-      uint64_t* fb = frame + 2 * b;
-      const uint64_t xb = fb[0], zb = fb[1];
       const uint64_t nxa = xa ^ zb, nxb = xb ^ za;
-      fa[0] = nxa;
-      fb[0] = nxb;
+      frame[a].x = nxa;
+      frame[b].x = nxb;
       dnz += nzd(nxa, xa) + nzd(nxb, xb);
       break;
     }
-    case OP_SWAP: {
-      uint64_t* fb = frame + 2 * b;
-      const uint64_t xb = fb[0], zb = fb[1];
-      fa[0] = xb;
-      fa[1] = zb;
-      fb[0] = xa;
-      fb[1] = za;
+    case OP_SWAP:
+      frame[a] = pb;
+      frame[b] = pa;
       break;
-    }
     case OP_R:  // a Z error right after a Z reset must be invisible
       gauge |= za != 0;
-      fa[0] = 0;
-      fa[1] = 0;
+      frame[a] = make_ulonglong2(0, 0);
       dnz -= int(xa != 0) + int(za != 0);
       break;
     case OP_RX:
       gauge |= xa != 0;
-      fa[0] = 0;
-      fa[1] = 0;
+      frame[a] = make_ulonglong2(0, 0);
       dnz -= int(xa != 0) + int(za != 0);
       break;
     case OP_M: {  // X before the measurement flips it (leaf) and persists
       gauge |= za != 0;
       const uint64_t n = xa ^ pend[a];
       pend[a] = 0;
-      fa[0] = n;
+      frame[a].x = n;
       dnz += nzd(n, xa);
       break;
     }
@@ -250,7 +242,7 @@ __device__ __forceinline__ void apply_op(uint32_t op, uint64_t* frame, uint64_t*
       gauge |= xa != 0;
       const uint64_t n = za ^ pend[a];
       pend[a] = 0;
-      fa[1] = n;
+      frame[a].y = n;
       dnz += nzd(n, za);
       break;
     }
@@ -258,8 +250,7 @@ __device__ __forceinline__ void apply_op(uint32_t op, uint64_t* frame, uint64_t*
       gauge |= za != 0;
       const uint64_t n = pend[a];
       pend[a] = 0;
-      fa[0] = n;
-      fa[1] = 0;
+      frame[a] = make_ulonglong2(n, 0);
       dnz += nzd(n, xa) - int(za != 0);
       break;
     }
@@ -267,8 +258,7 @@ __device__ __forceinline__ void apply_op(uint32_t op, uint64_t* frame, uint64_t*
       gauge |= xa != 0;
       const uint64_t n = pend[a];
       pend[a] = 0;
-      fa[1] = n;
-      fa[0] = 0;
+      frame[a] = make_ulonglong2(0, n);
       dnz += nzd(n, za) - int(xa != 0);
       break;
     }
@@ -277,22 +267,39 @@ __device__ __forceinline__ void apply_op(uint32_t op, uint64_t* frame, uint64_t*
   }
 }
 
+// Sum over the wave of small per-lane values (|v| < 64) with seven ballots:
+// scalar popcounts instead of a chain of cross-lane LDS permutes. Every lane
+// of the wave must be active.
+__device__ __forceinline__ int wave_total_small(int v) {
+  const uint32_t u = uint32_t(v + 64);
+  int s = 0;
+#pragma unroll
+  for (int bit = 0; bit < 7; ++bit) s += int(__popcll(__ballot((u >> bit) & 1u))) << bit;
+  return s - 64 * 64;
+}
+
 // One work item = one word column (or one boundary range of an observable
-// column). LDS holds the column's frame, the pending leaf words, two windows of
-// compact ops (the next window is fetched into registers while the current one
-// is applied), the layer and fault offsets and the column's injection list.
-// Per layer: fetch the new boundary's fault records and apply the ops (one
-// thread per op); then emit one signature word per fault (one thread per
-// fault, coalesced) and scatter the next layer's leaf words.
+// column). LDS holds the column's frame, two parity buffers of pending leaf
+// words, two windows of compact ops (the next window is fetched into
+// registers while the current one is applied), the layer and fault offsets
+// and the column's injection list.
+// Layers above the item's emission range only transform the frame: one
+// barrier each, and no global memory access besides the window prefetch.
+// Layers in the range fetch the new boundary's fault records, apply the ops
+// (one thread per op), then emit one signature word per fault (one thread
+// per fault, coalesced).
+// The count of non-zero frame words (for the early exit) is kept per wave as
+// a running sum and published in a per-wave LDS slot.
 template <bool kStaged>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
-  extern __shared__ uint64_t lds[];
-  __shared__ int s_nz;
+  extern __shared__ __align__(16) uint64_t lds[];
+  __shared__ int s_wnz[2][kSweepBlock / 64];
   const int tid = threadIdx.x;
+  const int wave = tid >> 6;
   const uint32_t n = st.n_qubits;
   uint64_t* frame = lds;
-  uint64_t* pend = frame + 2 * size_t(n);
-  uint64_t* sinj_w = pend + n;
+  uint64_t* pend = frame + 2 * size_t(n);  // two buffers, by layer parity
+  uint64_t* sinj_w = pend + 2 * size_t(n);
   uint32_t* opbuf = reinterpret_cast<uint32_t*>(sinj_w + kInjLds);
   uint32_t* slofs = opbuf + 2 * kWinOps;
   uint32_t* sbfo = slofs + kLofsMax;
@@ -310,13 +317,13 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   uint64_t* out = st.slab + st.col_base[w];
   // kStaged: the layer offsets and every column's injections fit in LDS, so
   // the layer loop reads no global memory besides the window prefetch and
-  // the emission's channel tables
+  // the emission's fault records
   constexpr bool lofs_lds = kStaged;
   constexpr bool inj_lds = kStaged;
   const uint32_t i0 = st.inj_off[w];
   const uint32_t ni = st.inj_off[w + 1] - i0;
 
-  for (uint32_t i = tid; i < 3 * n; i += kSweepBlock) frame[i] = 0;  // frame and pend
+  for (uint32_t i = tid; i < 4 * n; i += kSweepBlock) frame[i] = 0;  // frame and both pend buffers
   if (lofs_lds)
     for (uint32_t k = tid; k <= st.n_layers + 1; k += kSweepBlock) {
       if (k <= st.n_layers) slofs[k] = st.layer_off[k];
@@ -329,7 +336,6 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
       sinj_q[k] = st.inj_qubit[i0 + k];
       sinj_n[k] = st.inj_next[i0 + k];
     }
-  if (tid == 0) s_nz = 0;
   __syncthreads();
   auto LO = [&](int t) -> uint32_t { return lofs_lds ? slofs[t] : st.layer_off[t]; };
   auto BFO = [&](int t) -> uint32_t { return lofs_lds ? sbfo[t] : st.bnd_fault_off[t]; };
@@ -344,13 +350,18 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
     while (lo - 1 >= blo && end - LO(lo - 1) <= uint32_t(kWinOps)) lo--;
     return lo;
   };
-  // scatter the leaf words of layer t into pend
+  // scatter the leaf words of layer t into its pend buffer; the layer of the
+  // next injection group is kept in a register
   uint32_t ip = 0;
+  int inj_t = ni ? INJ_L(0) : -1;
+  uint32_t inj_e = ni ? INJ_N(0) : 0;
   auto scatter = [&](int t) {
-    if (ip < ni && INJ_L(ip) == t) {
-      const uint32_t ie = INJ_N(ip);
-      for (uint32_t k = ip + tid; k < ie; k += kSweepBlock) pend[INJ_Q(k)] = INJ_W(k);
-      ip = ie;
+    if (inj_t == t) {
+      uint64_t* pb = pend + size_t(t & 1) * n;
+      for (uint32_t k = ip + tid; k < inj_e; k += kSweepBlock) pb[INJ_Q(k)] = INJ_W(k);
+      ip = inj_e;
+      inj_t = ip < ni ? INJ_L(ip) : -1;
+      inj_e = ip < ni ? INJ_N(ip) : 0;
     }
   };
 
@@ -378,65 +389,33 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   __syncthreads();
   int cur = 0;
   int gauge = 0;
-  bool dead = false;
-  for (int t = top; t >= blo; --t) {
-    // A: fetch the records of the faults at boundary t (used in B), then
-    // transform the frame from boundary t+1 to boundary t, in place
-    const bool emit = t <= bhi;
-    const uint32_t f0 = emit ? BFO(t) : 0u, nf = emit ? BFO(t + 1) - f0 : 0u;
-    uint32_t rec[kEmitPre];
-#pragma unroll
-    for (int k = 0; k < kEmitPre; ++k) {
-      const uint32_t i = tid + k * kSweepBlock;
-      rec[k] = i < nf ? st.frec[f0 + i] : 0u;
-    }
+  int wave_nz = 0;     // this wave's running share of the non-zero word count
+  uint32_t lo_hi = LO(top + 1);
+
+  // the ops of layer t, then this wave's count published in slot (t & 1)
+  auto apply_layer = [&](int t, uint32_t lo_t) {
     int dnz = 0;
-    {
-      // a layer never exceeds a window: it has at most n ops and n fits LDS
-      const uint32_t ob = LO(t) - o_base, oe = LO(t + 1) - o_base;
-      const uint32_t* buf = opbuf + cur * kWinOps;
-      for (uint32_t i = ob + tid; i < oe; i += kSweepBlock) apply_op(buf[i], frame, pend, dnz, gauge);
-    }
-    {
-      // one LDS atomic per wave: a single shared counter serialises atomics
-      const uint32_t wd = wave_sum(uint32_t(dnz));
-      if ((tid & 63) == 0 && wd) atomicAdd(&s_nz, int(wd));
-    }
-    lds_barrier();
-    const int nz = s_nz;
-    // B: faults at boundary t, one per thread: signature word = XOR of the X/Z
-    // words their Pauli selects (composite Paulis, Sec. 2.3.4); consecutive
-    // threads store consecutive positions
-    auto word_of = [&](uint32_t r) -> uint64_t {
-      const uint32_t qa = r & kQField, qb = (r >> kQubitBits) & kQField, code = r >> 28;
-      const uint64_t x0 = frame[2 * qa], z0 = frame[2 * qa + 1];
-      const uint64_t x1 = frame[2 * qb], z1 = frame[2 * qb + 1];
-      return (x0 & (0ull - (code & 1u))) ^ (z0 & (0ull - ((code >> 1) & 1u))) ^
-             (x1 & (0ull - ((code >> 2) & 1u))) ^ (z1 & (0ull - ((code >> 3) & 1u)));
-    };
-    // all words first, then all stores: a store in flight makes the compiler
-    // wait for every outstanding memory operation before the next use of a
-    // loaded register
-    uint64_t wv[kEmitPre];
+    const uint32_t* buf = opbuf + cur * kWinOps;
+    uint64_t* pb = pend + size_t(t & 1) * n;
+    // a layer never exceeds a window: it has at most n ops and n fits LDS
+    for (uint32_t i = lo_t - o_base + tid; i < lo_hi - o_base; i += kSweepBlock)
+      apply_op(buf[i], reinterpret_cast<ulonglong2*>(frame), pb, dnz, gauge);
+    wave_nz += wave_total_small(dnz);
+    if ((tid & 63) == 0) s_wnz[t & 1][wave] = wave_nz;
+  };
+  // the non-zero frame words after layer t (read after the barrier)
+  auto count_after = [&](int t) -> int {
+    int nz = 0;
 #pragma unroll
-    for (int k = 0; k < kEmitPre; ++k) wv[k] = (tid + k * kSweepBlock < nf) ? word_of(rec[k]) : 0ull;
-#pragma unroll
-    for (int k = 0; k < kEmitPre; ++k) {
-      const uint32_t i = tid + k * kSweepBlock;
-      if (i < nf) out[f0 + i] = wv[k];
-    }
-    for (uint32_t i = tid + kEmitPre * kSweepBlock; i < nf; i += kSweepBlock) out[f0 + i] = word_of(st.frec[f0 + i]);
-    if (nz == 0 && t <= clo) {
-      // no leaf of this column lies below t and the frame is zero: every lower
-      // boundary is zero in this column
-      if (t <= bhi && tid == 0) st.cover_lo[w] = t;
-      dead = true;
-      break;
-    }
+    for (int k = 0; k < kSweepBlock / 64; ++k) nz += s_wnz[t & 1][k];
+    return nz;
+  };
+  // the next layer's leaf words, and the window swap when layer t ends it
+  auto advance = [&](int t) {
     if (t - 1 >= blo) scatter(t - 1);
     if (t == wlo && nhi >= blo) {
-      // the window is used up: the prefetched one becomes current, and the
-      // window after it is fetched into registers
+      // the prefetched window becomes current (the other buffer is no longer
+      // read), and the window after it is fetched into registers
       const uint32_t cnt = min(LO(nhi + 1) - nbase, uint32_t(kWinOps));
       uint32_t* nb = opbuf + (cur ^ 1) * kWinOps;
 #pragma unroll
@@ -457,7 +436,74 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
         pre[k] = i < cnt2 ? st.ops32[nbase + i] : 0u;
       }
     }
+  };
+
+  bool dead = false;
+  int t = top;
+  // the next layer's offsets are read before each barrier
+  uint32_t lo_t = LO(top);
+  // layers above the emission range: transform only
+  for (; t > bhi; --t) {
+    apply_layer(t, lo_t);
+    advance(t);
+    const uint32_t lo_n = LO(t > 0 ? t - 1 : 0);
     lds_barrier();
+    lo_hi = lo_t;
+    lo_t = lo_n;
+    if (t <= clo && count_after(t) == 0) {
+      // the frame is zero and no leaf lies below: this column is zero on
+      // every boundary of this item's range (the item that holds this
+      // boundary records it)
+      dead = true;
+      break;
+    }
+  }
+  if (!dead) {
+    uint32_t f_hi = BFO(t + 1), f0 = BFO(t);
+    for (; t >= blo; --t) {
+      // A: fetch the records of the faults at boundary t (used in B), then
+      // transform the frame from boundary t+1 to boundary t, in place
+      const uint32_t nf = f_hi - f0;
+      uint32_t rec[kEmitPre];
+#pragma unroll
+      for (int k = 0; k < kEmitPre; ++k) {
+        const uint32_t i = tid + k * kSweepBlock;
+        rec[k] = i < nf ? st.frec[f0 + i] : 0u;
+      }
+      apply_layer(t, lo_t);
+      advance(t);
+      const uint32_t lo_n = LO(t > 0 ? t - 1 : 0), f_n = BFO(t > 0 ? t - 1 : 0);
+      lds_barrier();
+      lo_hi = lo_t;
+      const bool zero = t <= clo && count_after(t) == 0;
+      // B: faults at boundary t, one per thread: signature word = XOR of the
+      // X/Z words their Pauli selects (composite Paulis, Sec. 2.3.4);
+      // consecutive threads store consecutive positions
+      auto word_of = [&](uint32_t r) -> uint64_t {
+        const uint32_t qa = r & kQField, qb = (r >> kQubitBits) & kQField, code = r >> 28;
+        const ulonglong2 p0 = reinterpret_cast<const ulonglong2*>(frame)[qa];
+        const ulonglong2 p1 = reinterpret_cast<const ulonglong2*>(frame)[qb];
+        return (p0.x & (0ull - (code & 1u))) ^ (p0.y & (0ull - ((code >> 1) & 1u))) ^
+               (p1.x & (0ull - ((code >> 2) & 1u))) ^ (p1.y & (0ull - ((code >> 3) & 1u)));
+      };
+#pragma unroll
+      for (int k = 0; k < kEmitPre; ++k) {
+        const uint32_t i = tid + k * kSweepBlock;
+        if (i < nf) out[f0 + i] = word_of(rec[k]);
+      }
+      for (uint32_t i = tid + kEmitPre * kSweepBlock; i < nf; i += kSweepBlock) out[f0 + i] = word_of(st.frec[f0 + i]);
+      if (zero) {
+        // no leaf of this column lies below t and the frame is zero: every
+        // lower boundary is zero in this column
+        if (tid == 0) st.cover_lo[w] = t;
+        dead = true;
+        break;
+      }
+      lo_t = lo_n;
+      f_hi = f0;
+      f0 = f_n;
+      lds_barrier();
+    }
   }
   if (!dead && blo == 0) {
     // every qubit starts in |0>: a Z error at the very start must be invisible
@@ -549,7 +595,7 @@ __global__ __launch_bounds__(kBlock) void k_hash(DevState st) {
   if (st.key_bits < 64) key &= (1ull << st.key_bits) - 1;
   if (valid) {
     st.key[1][pos] = key;
-    st.chk[pos] = h2;
+    st.frp[pos].chk = h2;
     st.popc[pos] = weight;
     st.nzm[pos] = mask;
   }
@@ -591,44 +637,64 @@ __global__ __launch_bounds__(kScanSingleBlock) void k_scan_single(uint32_t* data
   if (threadIdx.x == 0 && total) *total = TotalT(s_wave[kScanSingleBlock / 64]);
 }
 
+// Lanes of the wave below this one whose bit is set in m.
+__device__ __forceinline__ uint32_t lane_rank(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+}
+
 // Stable compaction of the live faults (non-empty signatures) into (key,
-// position) pairs, with the digit counts of every radix pass for this tile.
-__global__ __launch_bounds__(kBlock) void k_compact(DevState st) {
-  __shared__ uint32_t s_wave[kBlock / 64 + 1];
+// position) pairs, with the digit counts of radix passes [p0, n_pass) for
+// this tile.
+// Round k of the tile covers positions [k*256, k*256+256): consecutive lanes
+// read consecutive positions and write consecutive compacted slots.
+__global__ __launch_bounds__(kBlock) void k_compact(DevState st, uint32_t p0) {
+  constexpr int kWaves = kBlock / 64;
+  __shared__ uint32_t s_off[kPerThread * kWaves];  // per (round, wave): first slot in the tile
   __shared__ uint32_t s_hist[kMaxPasses][256];
   const uint32_t tile = blockIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (uint32_t i = threadIdx.x; i < kMaxPasses * 256; i += kBlock) (&s_hist[0][0])[i] = 0;
-  const uint32_t i0 = tile * kTile + threadIdx.x * kPerThread;
-  uint32_t flags = 0, s = 0;
+  const uint32_t base = tile * kTile + threadIdx.x;
+  uint32_t flags = 0;
 #pragma unroll
   for (int k = 0; k < kPerThread; ++k) {
-    const uint32_t i = i0 + k;
+    const uint32_t i = base + k * kBlock;
     const bool live = i < st.n_faults && st.popc[i] != 0;
     flags |= uint32_t(live) << k;
-    s += live;
+    const uint64_t m = __ballot(live);
+    if (lane == 0) s_off[k * kWaves + wv] = uint32_t(__popcll(m));
   }
-  uint32_t run = block_exclusive_scan<kBlock>(s, s_wave) + st.tile_cnt[tile];
+  __syncthreads();
+  if (threadIdx.x < kPerThread * kWaves) {
+    const uint32_t v = s_off[threadIdx.x];
+    s_off[threadIdx.x] = wave_inclusive_scan(v) - v;
+  }
+  __syncthreads();
+  const uint32_t tb = st.tile_cnt[tile];
   const uint32_t P = st.n_pass;
 #pragma unroll
   for (int k = 0; k < kPerThread; ++k) {
-    if ((flags >> k) & 1u) {
-      const uint32_t i = i0 + k;
+    const bool live = (flags >> k) & 1u;
+    const uint64_t m = __ballot(live);
+    if (live) {
+      const uint32_t i = base + k * kBlock;
+      const uint32_t slot = tb + s_off[k * kWaves + wv] + lane_rank(m);
       const uint64_t key = st.key[1][i];
-      st.key[0][run] = key;
-      st.val[0][run] = i;
-      run++;
-      for (uint32_t p = 0; p < P; ++p) atomicAdd(&s_hist[p][digit_of(key, p)], 1u);
+      st.key[0][slot] = key;
+      st.val[0][slot] = i;
+      for (uint32_t p = p0; p < P; ++p) atomicAdd(&s_hist[p][digit_of(key, p)], 1u);
     }
   }
   __syncthreads();
   uint32_t* part = st.part_hist + size_t(tile) * kMaxPasses * 256;
-  for (uint32_t p = 0; p < P; ++p) part[p * 256 + threadIdx.x] = s_hist[p][threadIdx.x];
+  for (uint32_t p = p0; p < P; ++p) part[p * 256 + threadIdx.x] = s_hist[p][threadIdx.x];
 }
 
-// Total count of digit d in pass p over all compaction tiles (block p*256 + d).
-__global__ __launch_bounds__(kBlock) void k_digit_totals(DevState st, uint32_t ntiles) {
+// Total count of digit d in pass p over all compaction tiles (block
+// (p - p0)*256 + d).
+__global__ __launch_bounds__(kBlock) void k_digit_totals(DevState st, uint32_t ntiles, uint32_t p0) {
   __shared__ uint32_t s_red[kBlock / 64];
-  const uint32_t p = blockIdx.x >> 8, d = blockIdx.x & 255u;
+  const uint32_t p = p0 + (blockIdx.x >> 8), d = blockIdx.x & 255u;
   uint32_t tot = 0;
   for (uint32_t t = threadIdx.x; t < ntiles; t += kBlock) tot += st.part_hist[(size_t(t) * kMaxPasses + p) * 256 + d];
   tot = wave_sum(tot);
@@ -639,6 +705,19 @@ __global__ __launch_bounds__(kBlock) void k_digit_totals(DevState st, uint32_t n
     for (int k = 0; k < kBlock / 64; ++k) a += s_red[k];
     st.digit_tot[p * 256 + d] = a;
   }
+}
+
+// Lanes of the wave (among the valid ones) whose 8-bit digit equals this
+// lane's: eight ballots, one per digit bit.
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
+  uint64_t peers = __ballot(valid);
+#pragma unroll
+  for (int bit = 0; bit < 8; ++bit) {
+    const bool on = (d >> bit) & 1u;
+    const uint64_t m = __ballot(on);
+    peers &= on ? m : ~m;
+  }
+  return peers;
 }
 
 // One stable pass of 8-bit digits over the live keys (n = hdr->n_live). Tiles
@@ -706,13 +785,7 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(DevState st, uint32_t pass,
   for (int r = 0; r < kRounds; ++r) {
     const bool valid = base + r * 64 + lane < n;
     const uint32_t d = valid ? digit_of(k[r], pass) : 0u;
-    uint64_t peers = __ballot(valid);
-#pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
-      const bool on = (d >> bit) & 1u;
-      const uint64_t m = __ballot(on);
-      peers &= on ? m : ~m;
-    }
+    const uint64_t peers = digit_peers(d, valid);
     const uint32_t rank = __popcll(peers & lt);
     uint32_t li = 0;
     if (valid) li = s_cnt[wv][d] + rank;
@@ -725,8 +798,11 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(DevState st, uint32_t pass,
     }
   }
   {
-    // thread d: counts of digit d in the tiles before this one, read four at
-    // a time, until a tile that already published its inclusive prefix
+    // thread d: counts of digit d in the tiles before this one, kLookWin at a
+    // time, until a tile that already published its inclusive prefix. Every
+    // tile runs at once, so the inclusive prefixes spread from tile 0 while
+    // all tiles walk back; a wide window keeps the number of (cross-XCD
+    // latency) rounds small.
     const uint32_t d = tid;
     uint32_t excl = 0;
     if (tile > 0) {
@@ -734,15 +810,15 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(DevState st, uint32_t pass,
       uint32_t spins = 0;
       bool done = false;
       while (!done) {
-        uint32_t x[4];
+        uint32_t x[kLookWin];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < kLookWin; ++q)
           x[q] = (j - q >= 0) ? __hip_atomic_load(&lb[size_t(j - q) * 256 + d], __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT)
                               : kLbPre;
         bool stalled = false;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < kLookWin; ++q) {
           if (done || stalled) continue;
           if ((x[q] & ~kLbMask) == 0) {
             stalled = true;
@@ -870,14 +946,13 @@ __global__ __launch_bounds__(kBlock) void k_reduce(DevState st, const uint32_t* 
     return;
   }
   const uint32_t rep = vals[i0];
-  const uint64_t c0 = st.chk[rep];
+  const FaultRec r0 = st.frp[rep];
   bool bad = false;
-  double q = 0.0;
-  for (uint32_t i = i0; i < i1; ++i) {
-    const uint32_t pos = vals[i];
-    bad |= st.chk[pos] != c0;
-    const double p = st.pfault[pos];
-    q = fma(p, 1.0 - 2.0 * q, q);  // Eq. 3: q(1-p) + p(1-q)
+  double q = r0.p;
+  for (uint32_t i = i0 + 1; i < i1; ++i) {
+    const FaultRec r = st.frp[vals[i]];
+    bad |= r.chk != r0.chk;
+    q = fma(r.p, 1.0 - 2.0 * q, q);  // Eq. 3: q(1-p) + p(1-q)
   }
   if (bad) atomicOr(&st.hdr->flags, FLAG_COLLISION);
   st.seg_q[s] = q;
@@ -900,13 +975,13 @@ __global__ __launch_bounds__(kBlock) void k_reduce_big(DevState st, const uint32
     const uint32_t i1 = (s + 1 < S) ? st.segstart[s + 1] : n;
     if (threadIdx.x == 0) s_bad = 0;
     const uint32_t rep = vals[i0];
-    const uint64_t c0 = st.chk[rep];
+    const uint64_t c0 = st.frp[rep].chk;
     bool bad = false;
     double q = 0.0;
     for (uint32_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
-      const uint32_t pos = vals[i];
-      bad |= st.chk[pos] != c0;
-      q = fma(st.pfault[pos], 1.0 - 2.0 * q, q);
+      const FaultRec r = st.frp[vals[i]];
+      bad |= r.chk != c0;
+      q = fma(r.p, 1.0 - 2.0 * q, q);
     }
     s_q[threadIdx.x] = q;
     __syncthreads();
@@ -928,22 +1003,265 @@ __global__ __launch_bounds__(kBlock) void k_reduce_big(DevState st, const uint32
   }
 }
 
+// ------------------------------------------------------------------ buckets
+
+constexpr int kBucketBlock = 1024;
+constexpr int kBucketWaves = kBucketBlock / 64;
+
+// Grouping inside one bucket: the live faults whose key has top digit d,
+// which the stable partition pass left in position order at
+// [bkt_start, bkt_start + m). Values (key bits below the top digit << 16 |
+// index in the bucket) are sorted in LDS by stable 8-bit LSD passes over the
+// key bits, so each class is a run of equal key bits whose members are in
+// position order. Per class: Eq. 3 merge in that order (one thread, or the
+// whole block for classes of more than kBigSegment faults), the check-hash
+// comparison, the representative (first member), its bit count and the
+// class's bit offset within the bucket. Class c of the bucket is stored at
+// slot bkt_start + c; k_bucket_scan turns the per-bucket counts into offsets.
+__global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint64_t* __restrict__ keys,
+                                                         const uint32_t* __restrict__ vals) {
+  extern __shared__ __align__(16) uint64_t s_buf[];  // two buffers of kBucketCap values
+  __shared__ uint32_t s_cnt[kBucketWaves][256];
+  __shared__ uint32_t s_wave[kBucketWaves + 1];
+  __shared__ uint32_t s_big[kBucketCap / (kBigSegment + 1) + 1];
+  __shared__ uint32_t s_nbig;
+  __shared__ uint32_t s_start;
+  __shared__ double s_q[kBucketBlock];
+  __shared__ int s_bad;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint32_t d = blockIdx.x;
+  const uint32_t msd = st.n_pass - 1;
+  const uint32_t* tot = st.digit_tot + msd * 256;
+  uint32_t* b_cls = st.bkt;                  // per bucket: classes (then offsets)
+  uint32_t* b_bits = st.bkt + (kBuckets + 1);  // per bucket: signature bits (then offsets)
+  {
+    const uint32_t v = tid < int(kBuckets) ? tot[tid] : 0u;
+    const uint32_t ex = block_exclusive_scan<kBucketBlock>(v, s_wave);
+    if (uint32_t(tid) == d) s_start = ex;
+    if (tid == 0) {
+      s_nbig = 0;
+      s_bad = 0;
+    }
+  }
+  __syncthreads();
+  const uint32_t start = s_start;
+  const uint32_t m = tot[d];
+  if (m == 0 || m > kBucketCap) {
+    if (tid == 0) {
+      b_cls[d] = 0;
+      b_bits[d] = 0;
+      if (m) atomicOr(&st.hdr->flags, FLAG_BUCKET);
+    }
+    return;
+  }
+  const uint32_t lbits = 8 * msd;  // key bits below the top digit (at most 48)
+  const uint64_t lmask = (1ull << lbits) - 1;
+  uint64_t* a = s_buf;
+  uint64_t* b = s_buf + kBucketCap;
+  for (uint32_t i = tid; i < m; i += kBucketBlock) a[i] = ((keys[start + i] & lmask) << 16) | i;
+  // wave wv owns the contiguous values [wv*chunk, (wv+1)*chunk), 64 per round
+  const uint32_t rounds = (m + kBucketBlock - 1) / kBucketBlock;
+  const uint32_t chunk = rounds * 64;
+  const uint64_t lt = (1ull << lane) - 1;
+  for (uint32_t pass = 0; pass < msd; ++pass) {
+    const uint32_t sh = 16 + 8 * pass;
+    for (int k = tid; k < kBucketWaves * 256; k += kBucketBlock) (&s_cnt[0][0])[k] = 0;
+    __syncthreads();
+    for (uint32_t r = 0; r < rounds; ++r) {
+      const uint32_t i = wv * chunk + r * 64 + lane;
+      const bool valid = i < m;
+      const uint32_t dg = valid ? uint32_t(a[i] >> sh) & 255u : 0u;
+      const uint64_t peers = digit_peers(dg, valid);
+      if (valid && (peers & lt) == 0) s_cnt[wv][dg] += uint32_t(__popcll(peers));
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    {
+      // exclusive scan in (digit, wave) order: thread t owns digit t/4, waves 4(t%4)..4(t%4)+3
+      const uint32_t dg = tid >> 2, w0 = (tid & 3) * 4;
+      uint32_t c[4], sum = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        c[j] = s_cnt[w0 + j][dg];
+        sum += c[j];
+      }
+      uint32_t run = block_exclusive_scan<kBucketBlock>(sum, s_wave);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        s_cnt[w0 + j][dg] = run;
+        run += c[j];
+      }
+    }
+    __syncthreads();
+    for (uint32_t r = 0; r < rounds; ++r) {
+      const uint32_t i = wv * chunk + r * 64 + lane;
+      const bool valid = i < m;
+      const uint64_t v = valid ? a[i] : 0ull;
+      const uint32_t dg = uint32_t(v >> sh) & 255u;
+      const uint64_t peers = digit_peers(dg, valid);
+      const uint32_t rank = uint32_t(__popcll(peers & lt));
+      const uint32_t base = valid ? s_cnt[wv][dg] : 0u;
+      __builtin_amdgcn_wave_barrier();
+      if (valid && rank == 0) s_cnt[wv][dg] = base + uint32_t(__popcll(peers));
+      __builtin_amdgcn_wave_barrier();
+      if (valid) b[base + rank] = v;
+    }
+    __syncthreads();
+    uint64_t* t = a;
+    a = b;
+    b = t;
+  }
+  // class heads; thread t owns the sorted values [t*per, (t+1)*per)
+  uint32_t* hpos = reinterpret_cast<uint32_t*>(b);  // first sorted index of each class
+  uint32_t* hcnt = hpos + kBucketCap;              // signature bits of each class
+  const uint32_t per = rounds;
+  const uint32_t j0 = min(m, tid * per), j1 = min(m, j0 + per);
+  auto is_head = [&](uint32_t j) { return j == 0 || (a[j] >> 16) != (a[j - 1] >> 16); };
+  uint32_t nh = 0;
+  for (uint32_t j = j0; j < j1; ++j) nh += is_head(j);
+  uint32_t c = block_exclusive_scan<kBucketBlock>(nh, s_wave);
+  const uint32_t ncls = s_wave[kBucketWaves];
+  for (uint32_t j = j0; j < j1; ++j)
+    if (is_head(j)) hpos[c++] = j;
+  __syncthreads();
+  // small classes: one thread each, members in position order
+  for (uint32_t k = tid; k < ncls; k += kBucketBlock) {
+    const uint32_t i0 = hpos[k], i1 = k + 1 < ncls ? hpos[k + 1] : m;
+    if (i1 - i0 > kBigSegment) {
+      s_big[atomicAdd(&s_nbig, 1u)] = k;
+      continue;
+    }
+    const uint32_t rep = vals[start + uint32_t(a[i0] & 0xFFFFu)];
+    const FaultRec r0 = st.frp[rep];
+    bool bad = false;
+    double q = r0.p;
+    for (uint32_t i = i0 + 1; i < i1; ++i) {
+      const FaultRec r = st.frp[vals[start + uint32_t(a[i] & 0xFFFFu)]];
+      bad |= r.chk != r0.chk;
+      q = fma(r.p, 1.0 - 2.0 * q, q);  // Eq. 3: q(1-p) + p(1-q)
+    }
+    if (bad) s_bad = 1;
+    const uint32_t bits = st.popc[rep];
+    st.seg_q[start + k] = q;
+    st.seg_rep[start + k] = rep;
+    hcnt[k] = bits;
+  }
+  __syncthreads();
+  // large classes: strided partial merges, then a fixed-shape tree
+  const uint32_t nbig = s_nbig;
+  for (uint32_t g = 0; g < nbig; ++g) {
+    const uint32_t k = s_big[g];
+    const uint32_t i0 = hpos[k], i1 = k + 1 < ncls ? hpos[k + 1] : m;
+    const uint32_t rep = vals[start + uint32_t(a[i0] & 0xFFFFu)];
+    const uint64_t c0 = st.frp[rep].chk;
+    bool bad = false;
+    double q = 0.0;
+    for (uint32_t i = i0 + tid; i < i1; i += kBucketBlock) {
+      const FaultRec r = st.frp[vals[start + uint32_t(a[i] & 0xFFFFu)]];
+      bad |= r.chk != c0;
+      q = fma(r.p, 1.0 - 2.0 * q, q);
+    }
+    if (bad) s_bad = 1;
+    s_q[tid] = q;
+    __syncthreads();
+    for (int h = kBucketBlock / 2; h > 0; h >>= 1) {
+      if (tid < h) {
+        const double x = s_q[tid], y = s_q[tid + h];
+        s_q[tid] = fma(y, 1.0 - 2.0 * x, x);
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      st.seg_q[start + k] = s_q[0];
+      st.seg_rep[start + k] = rep;
+      hcnt[k] = st.popc[rep];
+    }
+    __syncthreads();
+  }
+  // bit offsets of the classes within the bucket
+  const uint32_t pc = (ncls + kBucketBlock - 1) / kBucketBlock;
+  const uint32_t k0 = min(ncls, tid * pc), k1 = min(ncls, k0 + pc);
+  uint32_t nb = 0;
+  for (uint32_t k = k0; k < k1; ++k) nb += hcnt[k];
+  uint32_t o = block_exclusive_scan<kBucketBlock>(nb, s_wave);
+  for (uint32_t k = k0; k < k1; ++k) {
+    st.seg_off[start + k] = o;
+    o += hcnt[k];
+  }
+  if (tid == 0) {
+    b_cls[d] = ncls;
+    b_bits[d] = s_wave[kBucketWaves];
+    if (s_bad) atomicOr(&st.hdr->flags, FLAG_COLLISION);
+  }
+}
+
+// Per-bucket class, bit and fault counts -> exclusive offsets (entry
+// kBuckets holds the totals); the header's class and bit totals.
+__global__ __launch_bounds__(kBuckets) void k_bucket_scan(DevState st) {
+  __shared__ uint32_t s_wave[kBuckets / 64 + 1];
+  const uint32_t t = threadIdx.x;
+  uint32_t* b_cls = st.bkt;
+  uint32_t* b_bits = st.bkt + (kBuckets + 1);
+  uint32_t* b_start = st.bkt + 2 * (kBuckets + 1);
+  const uint32_t nc = b_cls[t], nb = b_bits[t], nf = st.digit_tot[(st.n_pass - 1) * 256 + t];
+  const uint32_t oc = block_exclusive_scan<kBuckets>(nc, s_wave);
+  const uint32_t tc = s_wave[kBuckets / 64];
+  __syncthreads();
+  const uint32_t ob = block_exclusive_scan<kBuckets>(nb, s_wave);
+  const uint32_t tb = s_wave[kBuckets / 64];
+  __syncthreads();
+  const uint32_t of = block_exclusive_scan<kBuckets>(nf, s_wave);
+  const uint32_t tf = s_wave[kBuckets / 64];
+  b_cls[t] = oc;
+  b_bits[t] = ob;
+  b_start[t] = of;
+  if (t == 0) {
+    b_cls[kBuckets] = tc;
+    b_bits[kBuckets] = tb;
+    b_start[kBuckets] = tf;
+    st.hdr->n_seg = tc;
+    st.hdr->n_bits = tb;
+  }
+}
+
 // Hyperedge e = class s: bits in external numbering (detector d -> d,
 // observable k -> D + k) and its probability.
+// With kBuckets, class e lives at slot bucket_start + (e - bucket_class_offset)
+// and its bit offset is the bucket's plus the class's within the bucket.
+template <bool kBucketed>
 __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
-  const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ uint32_t s_cls[kBuckets + 1];
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t S = st.hdr->n_seg;
-  if (s == 0) {
+  if (kBucketed) {
+    for (uint32_t k = threadIdx.x; k <= kBuckets; k += blockDim.x) s_cls[k] = st.bkt[k];
+    __syncthreads();
+  }
+  if (e == 0) {
     st.hdr->n_edges = S;
     st.edge_off32[S] = uint32_t(st.hdr->n_bits);
     if (st.hdr->n_bits > st.bits_cap) atomicOr(&st.hdr->flags, FLAG_OVERFLOW);
   }
-  if (s >= S) return;
-  const uint32_t o0 = st.seg_off[s];
-  st.edge_off32[s] = o0;
-  st.edge_q[s] = st.seg_q[s];
-  if (uint64_t(o0) + st.seg_cnt[s] > st.bits_cap) return;
+  if (e >= S) return;
+  uint32_t s = e, o0;
+  if (kBucketed) {
+    // the bucket holding class e: last bucket whose class offset is <= e
+    uint32_t lo = 0, hi = kBuckets;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) / 2;
+      if (s_cls[mid] <= e) lo = mid;
+      else hi = mid;
+    }
+    s = st.bkt[2 * (kBuckets + 1) + lo] + (e - s_cls[lo]);
+    o0 = st.bkt[(kBuckets + 1) + lo] + st.seg_off[s];
+  } else {
+    o0 = st.seg_off[s];
+  }
+  st.edge_off32[e] = o0;
+  st.edge_q[e] = st.seg_q[s];
   const uint32_t pos = st.seg_rep[s];
+  const uint32_t cnt = kBucketed ? st.popc[pos] : st.seg_cnt[s];
+  if (uint64_t(o0) + cnt > st.bits_cap) return;
   const uint32_t b = boundary_of(st.bnd_fault_off, st.n_layers + 1, pos);
   const uint32_t n = st.ncov[b];
   const uint32_t* cl = st.cov + size_t(b) * st.w;
@@ -978,7 +1296,8 @@ const char* kernel_name(int id) {
   static const char* names[K_COUNT] = {"k_prepare",     "k_sweep",      "k_cover",      "k_hash",
                                        "k_scan_single", "k_compact",    "k_digit_totals", "k_onesweep",
                                        "k_heads_count", "k_heads_apply", "k_reduce",     "k_reduce_big",
-                                       "k_scan_tiles",  "k_scan_apply", "k_edge_write"};
+                                       "k_scan_tiles",  "k_scan_apply", "k_edge_write", "k_bucket",
+                                       "k_bucket_scan"};
   return (id >= 0 && id < K_COUNT) ? names[id] : "?";
 }
 
@@ -992,13 +1311,16 @@ uint32_t sort_passes(uint64_t n) {
 }
 
 size_t sweep_lds_bytes(uint32_t n_qubits) {
-  return (size_t(3) * n_qubits + kInjLds) * sizeof(uint64_t) +
+  return (size_t(5) * n_qubits + kInjLds) * sizeof(uint64_t) +
          (size_t(2) * kWinOps + 2 * kLofsMax + 1 + 3 * kInjLds) * sizeof(uint32_t);
 }
 
 static size_t g_lds_limit = 64 * 1024;
+static bool g_bucket_ok = false;
 
 size_t sweep_lds_limit() { return g_lds_limit; }
+bool bucket_grouping_available() { return g_bucket_ok; }
+static constexpr size_t kBucketDynLds = 2 * size_t(kBucketCap) * sizeof(uint64_t);
 
 hipError_t configure_kernels() {
   int dev = 0;
@@ -1021,6 +1343,15 @@ hipError_t configure_kernels() {
     }
   }
   g_lds_limit = lim;
+  // the bucket grouping needs its two sort buffers next to its static arrays
+  g_bucket_ok = false;
+  hipFuncAttributes fa{};
+  if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_bucket)) == hipSuccess &&
+      fa.sharedSizeBytes + kBucketDynLds <= size_t(lds)) {
+    g_bucket_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bucket),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(kBucketDynLds)) == hipSuccess;
+  }
+  (void)hipGetLastError();
   return hipSuccess;
 }
 
@@ -1060,14 +1391,28 @@ hipError_t enqueue_compile(const DevState& st_in, hipStream_t stream, const Laun
   }
   GP_LAUNCH(K_COVER, k_cover<<<st.n_layers + 1, kBlock, 0, stream>>>(st));
   if (n == 0) {
-    GP_LAUNCH(K_EDGE_WRITE, k_edge_write<<<1, kBlock, 0, stream>>>(st));
+    GP_LAUNCH(K_EDGE_WRITE, k_edge_write<false><<<1, kBlock, 0, stream>>>(st));
     return hipSuccess;
   }
   GP_LAUNCH(K_HASH, k_hash<<<st.n_hchunks, kBlock, 0, stream>>>(st));
   GP_LAUNCH(K_SCAN_SINGLE, k_scan_single<uint32_t><<<1, kScanSingleBlock, 0, stream>>>(st.tile_cnt, ntiles, nullptr,
                                                                                       &st.hdr->n_live));
-  GP_LAUNCH(K_COMPACT, k_compact<<<ntiles, kBlock, 0, stream>>>(st));
-  GP_LAUNCH(K_DIGIT_OFFSETS, k_digit_totals<<<st.n_pass * 256, kBlock, 0, stream>>>(st, ntiles));
+  // buckets: one stable pass on the top digit, then each bucket in LDS
+  const bool bucketed = st.sort_mode == SORT_AUTO && st.key_mode == 0 && g_bucket_ok && n <= kBucketMaxFaults &&
+                        st.n_pass >= 2 && st.n_pass <= 7;
+  if (bucketed) {
+    const uint32_t msd = st.n_pass - 1;
+    GP_LAUNCH(K_COMPACT, k_compact<<<ntiles, kBlock, 0, stream>>>(st, msd));
+    GP_LAUNCH(K_DIGIT_OFFSETS, k_digit_totals<<<256, kBlock, 0, stream>>>(st, ntiles, msd));
+    GP_LAUNCH(K_ONESWEEP, k_onesweep<<<ntiles, kBlock, 0, stream>>>(st, msd, st.key[0], st.val[0], st.key[1],
+                                                                     st.val[1]));
+    GP_LAUNCH(K_BUCKET, k_bucket<<<kBuckets, kBucketBlock, kBucketDynLds, stream>>>(st, st.key[1], st.val[1]));
+    GP_LAUNCH(K_BUCKET_SCAN, k_bucket_scan<<<1, kBuckets, 0, stream>>>(st));
+    GP_LAUNCH(K_EDGE_WRITE, k_edge_write<true><<<cdiv(n, kBlock), kBlock, 0, stream>>>(st));
+    return hipSuccess;
+  }
+  GP_LAUNCH(K_COMPACT, k_compact<<<ntiles, kBlock, 0, stream>>>(st, 0));
+  GP_LAUNCH(K_DIGIT_OFFSETS, k_digit_totals<<<st.n_pass * 256, kBlock, 0, stream>>>(st, ntiles, 0));
   for (uint32_t pass = 0; pass < st.n_pass; ++pass) {
     const int src = pass & 1, dst = src ^ 1;
     GP_LAUNCH(K_ONESWEEP, k_onesweep<<<ntiles, kBlock, 0, stream>>>(st, pass, st.key[src], st.val[src], st.key[dst],
@@ -1087,7 +1432,7 @@ hipError_t enqueue_compile(const DevState& st_in, hipStream_t stream, const Laun
                                                                                       &st.hdr->n_bits));
   GP_LAUNCH(K_SCAN_APPLY,
             k_scan_apply<<<ntiles, kBlock, 0, stream>>>(st.seg_cnt, st.seg_off, n, &st.hdr->n_seg, st.tile_sum));
-  GP_LAUNCH(K_EDGE_WRITE, k_edge_write<<<cdiv(n, kBlock), kBlock, 0, stream>>>(st));
+  GP_LAUNCH(K_EDGE_WRITE, k_edge_write<false><<<cdiv(n, kBlock), kBlock, 0, stream>>>(st));
   return hipSuccess;
 }
 

@@ -67,7 +67,7 @@ struct RawChan {
 }  // namespace
 
 int lower_circuit(const char* text, size_t len, const double* rates, size_t n_rates,
-                  uint32_t obs_chunk_faults, Lowered& lw, LowerError& err) {
+                  uint32_t sweep_slots, Lowered& lw, LowerError& err) {
   lw = Lowered();
   std::vector<uint32_t> ready;
   std::vector<uint32_t> op_layer;
@@ -366,26 +366,38 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
   lw.slab_words = base;
 
   // ---- sweep items: one per detector column; observable columns, which stay
-  // live over the whole circuit, are cut into chunks of about
-  // obs_chunk_faults emitted faults so that their emission spreads over CUs.
-  // Each chunk re-sweeps from the column's top, so the lowest chunks run
-  // longest; they are listed first so that they start first.
-  const uint32_t chunk = std::max<uint32_t>(obs_chunk_faults, 1);
-  for (uint32_t w = lw.wd; w < lw.w; w++) {
-    int32_t top = lw.col_top[w];
-    if (top < 0) continue;
-    std::vector<std::pair<uint32_t, uint32_t>> ranges;
-    int32_t hi = top;
-    while (hi >= 0) {
-      int32_t lo = hi;
-      while (lo > 0 && lw.bnd_fault_off[hi + 1] - lw.bnd_fault_off[lo - 1] <= chunk) lo--;
-      ranges.emplace_back(uint32_t(lo), uint32_t(hi));
-      hi = lo - 1;
-    }
-    for (size_t k = ranges.size(); k-- > 0;) {
-      lw.item_col.push_back(w);
-      lw.item_blo.push_back(ranges[k].first);
-      lw.item_bhi.push_back(ranges[k].second);
+  // live over the whole circuit, are cut into boundary ranges so that their
+  // emission spreads over the slots left after the detector columns (one
+  // slot = one CU running one item). Each range re-sweeps from the column's
+  // top, so the lowest ranges run longest; they are listed first so that
+  // they start first.
+  {
+    uint32_t n_det_items = 0, n_obs_live = 0;
+    for (uint32_t w = 0; w < lw.w; w++)
+      if (lw.col_top[w] >= 0) (w < lw.wd ? n_det_items : n_obs_live)++;
+    const uint32_t slots = std::max<uint32_t>(sweep_slots, 1);
+    const uint32_t per_obs =
+        n_obs_live && slots > n_det_items ? std::max<uint32_t>((slots - n_det_items) / n_obs_live, 1) : 1;
+    for (uint32_t w = lw.wd; w < lw.w; w++) {
+      const int32_t top = lw.col_top[w];
+      if (top < 0) continue;
+      const uint64_t total = lw.bnd_fault_off[top + 1];
+      const uint64_t chunk = std::max<uint64_t>((total + per_obs - 1) / per_obs, kMinObsChunkFaults);
+      // every range but the lowest holds at least `chunk` faults, so there
+      // are at most per_obs of them
+      std::vector<std::pair<uint32_t, uint32_t>> ranges;
+      int32_t hi = top;
+      while (hi >= 0) {
+        int32_t lo = hi;
+        while (lo > 0 && uint64_t(lw.bnd_fault_off[hi + 1] - lw.bnd_fault_off[lo]) < chunk) lo--;
+        ranges.emplace_back(uint32_t(lo), uint32_t(hi));
+        hi = lo - 1;
+      }
+      for (size_t k = ranges.size(); k-- > 0;) {
+        lw.item_col.push_back(w);
+        lw.item_blo.push_back(ranges[k].first);
+        lw.item_bhi.push_back(ranges[k].second);
+      }
     }
   }
   for (uint32_t w = 0; w < lw.wd; w++) {

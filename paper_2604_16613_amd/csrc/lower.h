@@ -43,6 +43,10 @@ inline uint64_t pack_op(uint32_t kind, uint32_t a, uint32_t b) {
 constexpr uint32_t kQubitBits = 14;
 constexpr uint32_t kMaxSweepQubits = 1u << kQubitBits;
 constexpr uint32_t kQField = kMaxSweepQubits - 1;
+// Sweep items that run at once: one per CU of the target GPU (256 on gfx950).
+constexpr uint32_t kSweepSlots = 256;
+// An observable column is not cut into ranges of fewer faults than this.
+constexpr uint64_t kMinObsChunkFaults = 8192;
 inline uint32_t pack_op32(uint32_t kind, uint32_t a, uint32_t b) {
   return (kind << 28) | ((a & kQField) << kQubitBits) | (b & kQField);
 }
@@ -96,10 +100,11 @@ struct LowerError {
 };
 
 // Lower `text`; `rates` (if non-null) overrides the channel rates in program
-// order. `obs_chunk_faults` bounds the fault positions one sweep item of an
-// observable column emits. Returns 0 or a negative GP_E_* status with err set.
+// order. `sweep_slots` is the number of sweep items that run at once (one per
+// CU); observable columns are cut into ranges that fill the slots the
+// detector columns leave. Returns 0 or a negative GP_E_* status with err set.
 int lower_circuit(const char* text, size_t len, const double* rates, size_t n_rates,
-                  uint32_t obs_chunk_faults, Lowered& out, LowerError& err);
+                  uint32_t sweep_slots, Lowered& out, LowerError& err);
 
 // Re-apply a rate array to an already lowered circuit (same structure).
 int apply_rates(Lowered& lw, const double* rates, size_t n_rates, LowerError& err);

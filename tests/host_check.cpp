@@ -40,7 +40,7 @@ extern "C" int hc_run(const char* text, size_t len, const double* rates, size_t 
                       uint64_t max_faults) {
   Lowered lw;
   LowerError err{};
-  int rc = lower_circuit(text, len, rates, n_rates, 65536, lw, err);
+  int rc = lower_circuit(text, len, rates, n_rates, kSweepSlots, lw, err);
   if (rc) {
     g_msg = err.msg;
     return rc;

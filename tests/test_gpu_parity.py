@@ -236,3 +236,29 @@ def test_forced_key_collisions(drv25, bits):
     before = _gp.gp_debug_collision_retries(drv25.handle)
     check(drv25, c.text, label="full keys again")
     assert _gp.gp_debug_collision_retries(drv25.handle) == before
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_grouping_paths(drv25, mode):
+    """Both stage-2 groupings (256 buckets sorted and merged in LDS, and the
+    full LSD radix sort) against the oracle on the same workloads."""
+    _gp.gp_debug_set_sort_mode(drv25.handle, mode)
+    try:
+        c = rotated_surface_code_memory(11, 11)
+        check(drv25, c.text, log_uniform_rates(c.n_channels, 2), label=f"sort mode {mode} sc11")
+        check(drv25, bivariate_bicycle_memory().text, label=f"sort mode {mode} bb")
+        c = rotated_surface_code_memory(25, 25)
+        check(drv25, c.text, log_uniform_rates(c.n_channels, 0), label=f"sort mode {mode} sc25")
+    finally:
+        _gp.gp_debug_set_sort_mode(drv25.handle, 0)
+
+
+@pytest.mark.parametrize("copies", [3000, 9000])
+def test_large_classes(drv25, copies):
+    """Thousands of faults with one signature: a class merged by a whole
+    block (3000 members), and one larger than a bucket's LDS capacity (9000),
+    which makes the compile redo the grouping with the full sort."""
+    rates = np.linspace(1e-7, 2e-5, copies)
+    lines = [f"X_ERROR({r:.17g}) 0" for r in rates]
+    lines += ["X_ERROR(0.01) 1", "M 0 1", "DETECTOR rec[-2]", "DETECTOR rec[-1]", "OBSERVABLE_INCLUDE(0) rec[-1]"]
+    check(drv25, "\n".join(lines) + "\n", label=f"{copies} copies")
