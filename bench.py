@@ -78,12 +78,15 @@ def kernel_bytes(name: str, info: dict) -> float:
     listed with the kernels in the design doc)."""
     F = info["n_faults"]
     live = info["n_live_faults"]
-    words = info["n_live_words"]
+    words = info["n_live_words"]     # (fault, column) pairs in the swept windows
+    nz = info["n_nonzero_words"]     # of which non-zero (the only words stored)
     U = info["n_edges"]
     if name == "k_sweep":
-        return 8.0 * words                      # signature words written
+        return 8.0 * nz + words / 8.0           # non-zero words + one bitmap bit per word
     if name == "k_hash":
-        return 8.0 * words + F * (8 + 8 + 4 + 8)  # words read; key, check, weight, mask written
+        return 8.0 * nz + words / 8.0 + F * (8 + 8 + 4 + 8)  # read both; key, check, weight, mask written
+    if name == "k_bucket":
+        return live * (8 + 4 + 4 + 16) + U * (8 + 4 + 4)     # keys, positions, gathers; class records
     if name == "k_compact":
         return F * 4.0 + live * (8 + 8 + 4)     # weights read; live keys read, (key, pos) written
     if name == "k_onesweep":

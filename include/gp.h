@@ -91,8 +91,9 @@ typedef struct gp_circuit_info {
   uint64_t n_classes;         /* equivalence classes incl. the empty one (valid after fetch) */
   uint64_t n_edges;           /* hyperedges = non-empty classes (valid after fetch) */
   uint64_t n_edge_bits;       /* total signature bits over all hyperedges (valid after fetch) */
-  uint64_t n_live_words;      /* stage-1 signature words written (valid after fetch) */
+  uint64_t n_live_words;      /* stage-1 signature words in the swept windows (valid after fetch) */
   uint64_t n_live_faults;     /* faults with a non-empty signature (valid after fetch) */
+  uint64_t n_nonzero_words;   /* non-zero stage-1 signature words stored (valid after fetch) */
 } gp_circuit_info;
 
 /* Thread-local description of the last non-zero status. Never NULL. */

@@ -63,6 +63,7 @@ class GpCircuitInfo(ctypes.Structure):
         ("n_items", ctypes.c_uint64), ("slab_words", ctypes.c_uint64),
         ("n_classes", ctypes.c_uint64), ("n_edges", ctypes.c_uint64), ("n_edge_bits", ctypes.c_uint64),
         ("n_live_words", ctypes.c_uint64), ("n_live_faults", ctypes.c_uint64),
+        ("n_nonzero_words", ctypes.c_uint64),
     ]
 
     def as_dict(self):

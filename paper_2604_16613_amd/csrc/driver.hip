@@ -44,7 +44,8 @@ uint32_t words_for(uint32_t det, uint32_t obs) { return (det + 63) / 64 + (obs +
 struct TableLayout {
   size_t ops, layer_off, leaf_off, leaf_bits, chan_qa, chan_qb, chan_kind, chan_rate, chan_foff, bnd_chan_off,
       bnd_fault_off, col_top, col_lo, col_base, item_col, item_blo, item_bhi, fnv_pow, ops32, inj_off, inj_layer,
-      inj_qubit, inj_word, inj_next, hchunk_pos, hchunk_bnd, total;
+      inj_qubit, inj_word, inj_next, hchunk_pos, hchunk_bnd, bnd_bm_off, col_bm_base, layer_win, win_lo, win_obase,
+      win_cnt, total;
 };
 
 TableLayout layout_for(uint64_t ops, uint32_t layers, uint32_t meas, uint64_t leaf_bits, uint64_t chans, uint32_t w,
@@ -81,6 +82,12 @@ TableLayout layout_for(uint64_t ops, uint32_t layers, uint32_t meas, uint64_t le
   take(t.inj_next, leaf_bits * 4);
   take(t.hchunk_pos, hchunks * 4);
   take(t.hchunk_bnd, hchunks * 4);
+  take(t.bnd_bm_off, (size_t(layers) + 2) * 4);
+  take(t.col_bm_base, size_t(w) * 8);
+  take(t.layer_win, (size_t(layers) + 1) * 4);
+  take(t.win_lo, (size_t(layers) + 1) * 4);
+  take(t.win_obase, (size_t(layers) + 1) * 4);
+  take(t.win_cnt, (size_t(layers) + 1) * 4);
   t.total = o;
   return t;
 }
@@ -122,6 +129,7 @@ struct gp_driver {
 
   uint32_t key_bits = 64;      // test hook: class keys cut to this many bits
   uint32_t sort_mode = gp::SORT_AUTO;  // test hook: force the full radix sort
+  uint64_t bm_cap = 0;                 // non-zero-word bitmap words allocated
   uint64_t collision_retries = 0;
 
   bool timing = false;
@@ -200,6 +208,9 @@ int check_bounds(const gp_driver* d, const gp::Lowered& lw) {
   if (lw.leaf_bits.size() > b.max_leaf_bits) return over("leaf bits", lw.leaf_bits.size(), b.max_leaf_bits);
   if (lw.slab_words > b.max_slab_words) return over("slab words", lw.slab_words, b.max_slab_words);
   if (lw.item_col.size() > b.max_items) return over("sweep items", lw.item_col.size(), b.max_items);
+  if (lw.bm_words > d->bm_cap) return over("non-zero-word bitmap words", lw.bm_words, d->bm_cap);
+  for (uint32_t c : lw.win_cnt)
+    if (c > gp::kSweepWinOps) return over("operations in one layer (sweep op window)", c, gp::kSweepWinOps);
   if (lw.w > d->max_w) return over("signature words", lw.w, d->max_w);
   if (lw.w > gp::kMaxHashWords) return over("signature words for the hash kernel", lw.w, gp::kMaxHashWords);
   if (lw.n_qubits > gp::kMaxSweepQubits) return over("qubits for the compact op words", lw.n_qubits, gp::kMaxSweepQubits);
@@ -314,6 +325,9 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   uint64_t* slab = nullptr;
   if ((rc = dev_alloc(d, &slab, b.max_slab_words, "signature slab"))) return cleanup(rc);
   st.slab = slab;
+  // a column's bitmaps take at most (its slab words) / 64 + (boundaries) words
+  d->bm_cap = b.max_slab_words / 64 + uint64_t(d->max_w) * (uint64_t(b.max_layers) + 2);
+  if ((rc = dev_alloc(d, &st.bm, d->bm_cap, "non-zero-word bitmaps"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.cover_lo, d->max_w, "cover_lo"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.cov, (size_t(b.max_layers) + 1) * d->max_w, "cover lists"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.ncov, size_t(b.max_layers) + 1, "cover counts"))) return cleanup(rc);
@@ -326,6 +340,7 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   if ((rc = dev_alloc(d, &st.popc, F, "signature weights"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.nzm, F, "non-zero word masks"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.tile_cnt, size_t(d->max_tiles) + 1, "tile counts"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.tile_nz, size_t(d->max_tiles) + 1, "tile non-zero word counts"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.part_hist, size_t(d->max_tiles) * gp::kMaxPasses * 256, "digit counts")))
     return cleanup(rc);
   if ((rc = dev_alloc(d, &st.digit_tot, size_t(gp::kMaxPasses) * 256, "digit totals"))) return cleanup(rc);
@@ -407,6 +422,12 @@ int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, si
   put(tl.inj_next, lw.inj_next.data(), lw.inj_next.size() * 4);
   put(tl.hchunk_pos, lw.hchunk_pos.data(), lw.hchunk_pos.size() * 4);
   put(tl.hchunk_bnd, lw.hchunk_bnd.data(), lw.hchunk_bnd.size() * 4);
+  put(tl.bnd_bm_off, lw.bnd_bm_off.data(), lw.bnd_bm_off.size() * 4);
+  put(tl.col_bm_base, lw.col_bm_base.data(), lw.col_bm_base.size() * 8);
+  put(tl.layer_win, lw.layer_win.data(), lw.layer_win.size() * 4);
+  put(tl.win_lo, lw.win_lo.data(), lw.win_lo.size() * 4);
+  put(tl.win_obase, lw.win_obase.data(), lw.win_obase.size() * 4);
+  put(tl.win_cnt, lw.win_cnt.data(), lw.win_cnt.size() * 4);
   HIP_TRY(hipMemcpyAsync(d->d_tables, d->h_tables, tl.total, hipMemcpyHostToDevice, d->stream), "upload tables");
 
   gp::DevState& st = d->st;
@@ -438,6 +459,13 @@ int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, si
   st.hchunk_pos = reinterpret_cast<const uint32_t*>(D + tl.hchunk_pos);
   st.hchunk_bnd = reinterpret_cast<const uint32_t*>(D + tl.hchunk_bnd);
   st.n_hchunks = uint32_t(lw.hchunk_pos.size());
+  st.bnd_bm_off = reinterpret_cast<const uint32_t*>(D + tl.bnd_bm_off);
+  st.col_bm_base = reinterpret_cast<const uint64_t*>(D + tl.col_bm_base);
+  st.layer_win = reinterpret_cast<const uint32_t*>(D + tl.layer_win);
+  st.win_lo = reinterpret_cast<const uint32_t*>(D + tl.win_lo);
+  st.win_obase = reinterpret_cast<const uint32_t*>(D + tl.win_obase);
+  st.win_cnt = reinterpret_cast<const uint32_t*>(D + tl.win_cnt);
+  st.n_win = uint32_t(lw.win_lo.size());
   st.max_col_inj = 0;
   for (uint32_t w = 0; w < lw.w; w++)
     st.max_col_inj = std::max(st.max_col_inj, lw.inj_off[w + 1] - lw.inj_off[w]);
@@ -578,6 +606,7 @@ int gp_circuit_info_get(const gp_driver* d, gp_circuit_info* out) {
     i.n_edge_bits = d->h_hdr->n_bits;
     i.n_live_words = d->h_hdr->n_words;
     i.n_live_faults = d->h_hdr->n_live;
+    i.n_nonzero_words = d->h_hdr->n_nz_words;
   }
   *out = i;
   return GP_OK;

@@ -18,6 +18,7 @@ struct DevHeader {
   uint64_t n_words;    // stage-1 signature words written (= words the hash reads)
   uint32_t n_live;     // faults with a non-empty signature (the sorted ones)
   uint32_t n_big;      // classes with more faults than one thread merges
+  uint64_t n_nz_words; // non-zero signature words stored by stage 1
 };
 
 enum : uint32_t {
@@ -77,12 +78,19 @@ struct DevState {
   const uint32_t* inj_next;
   const uint32_t* hchunk_pos;  // hash chunks: first position, boundary
   const uint32_t* hchunk_bnd;
+  const uint32_t* bnd_bm_off;  // per boundary: first word of its bitmap within a column's bitmaps
+  const uint64_t* col_bm_base; // per column: first word of its bitmaps
+  const uint32_t* layer_win;   // per layer: its op window
+  const uint32_t* win_lo;      // per op window: lowest layer, first op, op count
+  const uint32_t* win_obase;
+  const uint32_t* win_cnt;
 
   // sizes
   uint32_t n_qubits, n_layers, n_det, wd, w;
   uint32_t n_chan, n_items;
   uint32_t n_faults;
   uint32_t n_hchunks;
+  uint32_t n_win;
   uint32_t max_col_inj;  // most injection entries of any one column
   // class key: 0 = FNV-1a of the signature (kept to its low key_bits bits);
   // 1 = FNV-1a mixed with the check hash (used after a key collision)
@@ -93,7 +101,8 @@ struct DevState {
   uint32_t max_tiles;   // tiles the sort/compaction scratch is sized for
 
   // work buffers
-  uint64_t* slab;        // stage-1 signature words, column slabs
+  uint64_t* slab;        // stage-1 signature words, column slabs (only non-zero words are stored)
+  uint64_t* bm;          // per (column, boundary): one bit per fault position, set where the word is non-zero
   int32_t* cover_lo;     // per column: lowest boundary written
   uint32_t* cov;         // per boundary: covered columns, ascending ((L+1) x W)
   uint32_t* ncov;        // per boundary: number of covered columns
@@ -104,6 +113,7 @@ struct DevState {
   uint32_t* popc;        // per fault position: signature weight
   uint64_t* nzm;         // per fault position: which covered columns hold non-zero words
   uint32_t* tile_cnt;    // per compaction tile: live faults, then their exclusive prefix
+  uint32_t* tile_nz;     // per compaction tile: non-zero signature words
   uint32_t* part_hist;   // per compaction tile: digit counts of every pass
   uint32_t* digit_tot;   // per pass: total count of each digit value
   uint32_t* lookback;    // per pass, tile and digit: published count with status bits

@@ -35,14 +35,13 @@ namespace gp {
 namespace {
 
 constexpr int kSweepBlock = 1024;
-constexpr int kWinOps = 4096;          // compact ops per LDS window buffer (two buffers)
+constexpr int kWinOps = int(kSweepWinOps);  // compact ops per LDS window buffer (two buffers)
 constexpr int kEmitPre = 8;            // fault records per thread fetched during the op phase
 constexpr int kPre = kWinOps / kSweepBlock;
 constexpr int kLofsMax = 2048;         // layer offsets staged in LDS when the circuit has fewer layers
 constexpr int kInjLds = 512;           // a column's injections staged in LDS when it has at most this many
 constexpr int kBlock = 256;
 constexpr int kPerThread = kTile / kBlock;
-static_assert(kPerThread * (kBlock / 64) == 64, "compaction offsets are scanned by one wave");
 constexpr int kScanSingleBlock = 1024;
 constexpr uint32_t kBigSegment = 64;   // classes with more faults reduce in a whole block
 constexpr uint32_t kLbAgg = 1u << 30;  // look-back status: tile aggregate published
@@ -153,7 +152,10 @@ __global__ void k_prepare(DevState st) {
   }
   for (uint32_t w = gid; w < st.w; w += stride) st.cover_lo[w] = 0;
   const uint32_t ntiles = (st.n_faults + kTile - 1) / kTile;
-  for (uint32_t t = gid; t < ntiles + 1; t += stride) st.tile_cnt[t] = 0;
+  for (uint32_t t = gid; t < ntiles + 1; t += stride) {
+    st.tile_cnt[t] = 0;
+    st.tile_nz[t] = 0;
+  }
   // look-back words of every pass (each pass owns max_tiles * 256 of them)
   const uint32_t per_pass = ntiles * 256;
   for (uint32_t i = gid; i < st.n_pass * per_pass; i += stride)
@@ -168,6 +170,7 @@ __global__ void k_prepare(DevState st) {
     st.hdr->n_words = 0;
     st.hdr->n_live = 0;
     st.hdr->n_big = 0;
+    st.hdr->n_nz_words = 0;
   }
 }
 
@@ -267,35 +270,41 @@ __device__ __forceinline__ void apply_op(uint32_t op, ulonglong2* frame, uint64_
   }
 }
 
-// Sum over the wave of small per-lane values (|v| < 64) with seven ballots:
+// Sum over the wave of per-lane values with |v| < 2^(BITS-1), by BITS ballots:
 // scalar popcounts instead of a chain of cross-lane LDS permutes. Every lane
 // of the wave must be active.
-__device__ __forceinline__ int wave_total_small(int v) {
-  const uint32_t u = uint32_t(v + 64);
+template <int BITS>
+__device__ __forceinline__ int wave_total(int v) {
+  const uint32_t u = uint32_t(v + (1 << (BITS - 1)));
   int s = 0;
 #pragma unroll
-  for (int bit = 0; bit < 7; ++bit) s += int(__popcll(__ballot((u >> bit) & 1u))) << bit;
-  return s - 64 * 64;
+  for (int bit = 0; bit < BITS; ++bit) s += int(__popcll(__ballot((u >> bit) & 1u))) << bit;
+  return s - 64 * (1 << (BITS - 1));
 }
 
 // One work item = one word column (or one boundary range of an observable
 // column). LDS holds the column's frame, two parity buffers of pending leaf
-// words, two windows of compact ops (the next window is fetched into
-// registers while the current one is applied), the layer and fault offsets
-// and the column's injection list.
+// words, two op windows (the circuit's layers cut from the top into ranges of
+// at most kWinOps ops; the next window is fetched into registers while the
+// current one is applied), the layer, fault and bitmap offsets and the
+// column's injection list.
 // Layers above the item's emission range only transform the frame: one
-// barrier each, and no global memory access besides the window prefetch.
+// barrier each, and no global memory access besides the window prefetch;
+// their count of non-zero frame words is published every kCountEvery layers.
 // Layers in the range fetch the new boundary's fault records, apply the ops
-// (one thread per op), then emit one signature word per fault (one thread
-// per fault, coalesced).
+// (one thread per op), then emit the non-zero signature words of the
+// boundary's faults (one thread per fault, coalesced) with a ballot bitmap of
+// which words are non-zero.
 // The count of non-zero frame words (for the early exit) is kept per wave as
-// a running sum and published in a per-wave LDS slot.
+// a running sum and published in per-wave LDS slots (two sets, alternating).
+constexpr int kCountEvery = 4;
+
 template <bool kStaged>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   extern __shared__ __align__(16) uint64_t lds[];
   __shared__ int s_wnz[2][kSweepBlock / 64];
   const int tid = threadIdx.x;
-  const int wave = tid >> 6;
+  const int wave = tid >> 6, lane = tid & 63;
   const uint32_t n = st.n_qubits;
   uint64_t* frame = lds;
   uint64_t* pend = frame + 2 * size_t(n);  // two buffers, by layer parity
@@ -303,7 +312,8 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   uint32_t* opbuf = reinterpret_cast<uint32_t*>(sinj_w + kInjLds);
   uint32_t* slofs = opbuf + 2 * kWinOps;
   uint32_t* sbfo = slofs + kLofsMax;
-  uint32_t* sinj_l = sbfo + kLofsMax + 1;
+  uint32_t* sbmo = sbfo + kLofsMax + 1;
+  uint32_t* sinj_l = sbmo + kLofsMax + 1;
   uint32_t* sinj_q = sinj_l + kInjLds;
   uint32_t* sinj_n = sinj_q + kInjLds;
 
@@ -315,6 +325,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   const int blo = int(st.item_blo[item]);
   const int bhi = int(st.item_bhi[item]);
   uint64_t* out = st.slab + st.col_base[w];
+  uint64_t* obm = st.bm + st.col_bm_base[w];
   // kStaged: the layer offsets and every column's injections fit in LDS, so
   // the layer loop reads no global memory besides the window prefetch and
   // the emission's fault records
@@ -328,6 +339,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
     for (uint32_t k = tid; k <= st.n_layers + 1; k += kSweepBlock) {
       if (k <= st.n_layers) slofs[k] = st.layer_off[k];
       sbfo[k] = st.bnd_fault_off[k];
+      sbmo[k] = st.bnd_bm_off[k];
     }
   if (inj_lds)
     for (uint32_t k = tid; k < ni; k += kSweepBlock) {
@@ -336,20 +348,22 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
       sinj_q[k] = st.inj_qubit[i0 + k];
       sinj_n[k] = st.inj_next[i0 + k];
     }
+  // the op window holding the top layer, loaded directly
+  int wid = int(st.layer_win[top]);
+  uint32_t o_base = st.win_obase[wid];
+  int wlo = int(st.win_lo[wid]);
+  {
+    const uint32_t cnt = st.win_cnt[wid];
+    for (uint32_t i = tid; i < cnt; i += kSweepBlock) opbuf[i] = st.ops32[o_base + i];
+  }
   __syncthreads();
   auto LO = [&](int t) -> uint32_t { return lofs_lds ? slofs[t] : st.layer_off[t]; };
   auto BFO = [&](int t) -> uint32_t { return lofs_lds ? sbfo[t] : st.bnd_fault_off[t]; };
+  auto BMO = [&](int t) -> uint32_t { return lofs_lds ? sbmo[t] : st.bnd_bm_off[t]; };
   auto INJ_L = [&](uint32_t k) -> int { return int(inj_lds ? sinj_l[k] : st.inj_layer[i0 + k]); };
   auto INJ_Q = [&](uint32_t k) -> uint32_t { return inj_lds ? sinj_q[k] : st.inj_qubit[i0 + k]; };
   auto INJ_W = [&](uint32_t k) -> uint64_t { return inj_lds ? sinj_w[k] : st.inj_word[i0 + k]; };
   auto INJ_N = [&](uint32_t k) -> uint32_t { return inj_lds ? sinj_n[k] : st.inj_next[i0 + k]; };
-  // lowest layer of the window that starts at layer hi (every thread computes the same)
-  auto window_lo = [&](int hi) -> int {
-    int lo = hi;
-    const uint32_t end = LO(hi + 1);
-    while (lo - 1 >= blo && end - LO(lo - 1) <= uint32_t(kWinOps)) lo--;
-    return lo;
-  };
   // scatter the leaf words of layer t into its pend buffer; the layer of the
   // next injection group is kept in a register
   uint32_t ip = 0;
@@ -364,59 +378,54 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
       inj_e = ip < ni ? INJ_N(ip) : 0;
     }
   };
-
-  // first window, loaded directly; the top layer's leaf words
-  int wlo = window_lo(top);
-  uint32_t o_base = LO(wlo);
-  {
-    const uint32_t cnt = min(LO(top + 1) - o_base, uint32_t(kWinOps));
-    for (uint32_t i = tid; i < cnt; i += kSweepBlock) opbuf[i] = st.ops32[o_base + i];
-  }
   scatter(top);
-  // next window into registers
-  int nhi = wlo - 1;
-  int nlo = nhi >= blo ? window_lo(nhi) : nhi + 1;
-  uint32_t nbase = nhi >= blo ? LO(nlo) : 0;
+  // the next window (layers below wlo) into registers, if the item needs it
   uint32_t pre[kPre];
-  {
-    const uint32_t cnt = nhi >= blo ? min(LO(nhi + 1) - nbase, uint32_t(kWinOps)) : 0;
+  uint32_t nbase = 0;
+  auto prefetch = [&]() {
+    const bool need = wlo - 1 >= blo;
+    const uint32_t cnt = need ? st.win_cnt[wid + 1] : 0u;
+    nbase = need ? st.win_obase[wid + 1] : 0u;
 #pragma unroll
     for (int k = 0; k < kPre; ++k) {
       const uint32_t i = tid + k * kSweepBlock;
       pre[k] = i < cnt ? st.ops32[nbase + i] : 0u;
     }
-  }
+  };
+  prefetch();
   __syncthreads();
   int cur = 0;
   int gauge = 0;
-  int wave_nz = 0;     // this wave's running share of the non-zero word count
+  int wave_nz = 0;   // this wave's running share of the non-zero word count
+  uint32_t ck = 0;   // count publications so far (slot set ck & 1)
   uint32_t lo_hi = LO(top + 1);
 
-  // the ops of layer t, then this wave's count published in slot (t & 1)
-  auto apply_layer = [&](int t, uint32_t lo_t) {
-    int dnz = 0;
+  // the ops of layer t; dnz accumulates the change in non-zero frame words
+  auto apply_layer = [&](int t, uint32_t lo_t, int& dnz) {
     const uint32_t* buf = opbuf + cur * kWinOps;
     uint64_t* pb = pend + size_t(t & 1) * n;
-    // a layer never exceeds a window: it has at most n ops and n fits LDS
+    // a layer never exceeds a window
     for (uint32_t i = lo_t - o_base + tid; i < lo_hi - o_base; i += kSweepBlock)
       apply_op(buf[i], reinterpret_cast<ulonglong2*>(frame), pb, dnz, gauge);
-    wave_nz += wave_total_small(dnz);
-    if ((tid & 63) == 0) s_wnz[t & 1][wave] = wave_nz;
   };
-  // the non-zero frame words after layer t (read after the barrier)
-  auto count_after = [&](int t) -> int {
+  // publish this wave's running count in slot set ck & 1 (read after a barrier)
+  auto publish = [&](int dnz) {
+    wave_nz += wave_total<10>(dnz);
+    if (lane == 0) s_wnz[ck & 1][wave] = wave_nz;
+  };
+  auto count_published = [&]() -> int {
     int nz = 0;
 #pragma unroll
-    for (int k = 0; k < kSweepBlock / 64; ++k) nz += s_wnz[t & 1][k];
+    for (int k = 0; k < kSweepBlock / 64; ++k) nz += s_wnz[ck & 1][k];
     return nz;
   };
   // the next layer's leaf words, and the window swap when layer t ends it
   auto advance = [&](int t) {
     if (t - 1 >= blo) scatter(t - 1);
-    if (t == wlo && nhi >= blo) {
+    if (t == wlo && t - 1 >= blo) {
       // the prefetched window becomes current (the other buffer is no longer
       // read), and the window after it is fetched into registers
-      const uint32_t cnt = min(LO(nhi + 1) - nbase, uint32_t(kWinOps));
+      const uint32_t cnt = st.win_cnt[wid + 1];
       uint32_t* nb = opbuf + (cur ^ 1) * kWinOps;
 #pragma unroll
       for (int k = 0; k < kPre; ++k) {
@@ -424,17 +433,10 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
         if (i < cnt) nb[i] = pre[k];
       }
       cur ^= 1;
-      wlo = nlo;
+      wid++;
       o_base = nbase;
-      nhi = wlo - 1;
-      nlo = nhi >= blo ? window_lo(nhi) : nhi + 1;
-      nbase = nhi >= blo ? LO(nlo) : 0;
-      const uint32_t cnt2 = nhi >= blo ? min(LO(nhi + 1) - nbase, uint32_t(kWinOps)) : 0;
-#pragma unroll
-      for (int k = 0; k < kPre; ++k) {
-        const uint32_t i = tid + k * kSweepBlock;
-        pre[k] = i < cnt2 ? st.ops32[nbase + i] : 0u;
-      }
+      wlo = int(st.win_lo[wid]);
+      prefetch();
     }
   };
 
@@ -442,20 +444,30 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   int t = top;
   // the next layer's offsets are read before each barrier
   uint32_t lo_t = LO(top);
+  int acc = 0;  // change in non-zero words not yet published
   // layers above the emission range: transform only
   for (; t > bhi; --t) {
-    apply_layer(t, lo_t);
+    apply_layer(t, lo_t, acc);
     advance(t);
+    const bool pub = ((top - t) % kCountEvery) == kCountEvery - 1 || t == bhi + 1;
+    if (pub) {
+      publish(acc);
+      acc = 0;
+    }
     const uint32_t lo_n = LO(t > 0 ? t - 1 : 0);
     lds_barrier();
     lo_hi = lo_t;
     lo_t = lo_n;
-    if (t <= clo && count_after(t) == 0) {
-      // the frame is zero and no leaf lies below: this column is zero on
-      // every boundary of this item's range (the item that holds this
-      // boundary records it)
-      dead = true;
-      break;
+    if (pub) {
+      const bool zero = t <= clo && count_published() == 0;
+      ck++;
+      if (zero) {
+        // the frame is zero and no leaf lies below: this column is zero on
+        // every boundary of this item's range (the item that holds this
+        // boundary records it)
+        dead = true;
+        break;
+      }
     }
   }
   if (!dead) {
@@ -470,12 +482,15 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
         const uint32_t i = tid + k * kSweepBlock;
         rec[k] = i < nf ? st.frec[f0 + i] : 0u;
       }
-      apply_layer(t, lo_t);
+      int dnz = 0;
+      apply_layer(t, lo_t, dnz);
       advance(t);
+      publish(dnz);
       const uint32_t lo_n = LO(t > 0 ? t - 1 : 0), f_n = BFO(t > 0 ? t - 1 : 0);
       lds_barrier();
       lo_hi = lo_t;
-      const bool zero = t <= clo && count_after(t) == 0;
+      const bool zero = t <= clo && count_published() == 0;
+      ck++;
       // B: faults at boundary t, one per thread: signature word = XOR of the
       // X/Z words their Pauli selects (composite Paulis, Sec. 2.3.4);
       // consecutive threads store consecutive positions
@@ -486,12 +501,24 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
         return (p0.x & (0ull - (code & 1u))) ^ (p0.y & (0ull - ((code >> 1) & 1u))) ^
                (p1.x & (0ull - ((code >> 2) & 1u))) ^ (p1.y & (0ull - ((code >> 3) & 1u)));
       };
+      // only non-zero words are stored; a ballot per wave records which
+      // (bit i of bitmap word i / 64 of this boundary)
+      uint64_t* bmp = obm + BMO(t);
 #pragma unroll
       for (int k = 0; k < kEmitPre; ++k) {
         const uint32_t i = tid + k * kSweepBlock;
-        if (i < nf) out[f0 + i] = word_of(rec[k]);
+        const uint64_t v = i < nf ? word_of(rec[k]) : 0ull;
+        if (v) out[f0 + i] = v;
+        const uint64_t msk = __ballot(v != 0);
+        if (lane == 0 && i < nf) bmp[i >> 6] = msk;
       }
-      for (uint32_t i = tid + kEmitPre * kSweepBlock; i < nf; i += kSweepBlock) out[f0 + i] = word_of(st.frec[f0 + i]);
+      for (uint32_t k = kEmitPre; k * kSweepBlock < nf; ++k) {
+        const uint32_t i = tid + k * kSweepBlock;
+        const uint64_t v = i < nf ? word_of(st.frec[f0 + i]) : 0ull;
+        if (v) out[f0 + i] = v;
+        const uint64_t msk = __ballot(v != 0);
+        if (lane == 0 && i < nf) bmp[i >> 6] = msk;
+      }
       if (zero) {
         // no leaf of this column lies below t and the frame is zero: every
         // lower boundary is zero in this column
@@ -550,39 +577,52 @@ __global__ __launch_bounds__(kBlock) void k_cover(DevState st) {
 __global__ __launch_bounds__(kBlock) void k_hash(DevState st) {
   __shared__ uint32_t s_w[kMaxHashWords];
   __shared__ uint64_t s_base[kMaxHashWords];
+  __shared__ uint64_t s_bmb[kMaxHashWords];
   __shared__ uint64_t s_pow[kMaxHashWords + 1];
   const uint32_t b = st.hchunk_bnd[blockIdx.x];
   const uint32_t p0 = st.hchunk_pos[blockIdx.x];
+  const uint32_t fb = st.bnd_fault_off[b];
   const uint32_t p1 = min(p0 + uint32_t(kBlock), st.bnd_fault_off[b + 1]);
   const uint32_t n = st.ncov[b];
+  const uint32_t bmo = st.bnd_bm_off[b];
   for (uint32_t k = threadIdx.x; k < n; k += kBlock) {
     const uint32_t w = st.cov[size_t(b) * st.w + k];
     s_w[k] = w;
     s_base[k] = st.col_base[w];
+    s_bmb[k] = st.col_bm_base[w] + bmo;
   }
   for (uint32_t k = threadIdx.x; k <= st.w; k += kBlock) s_pow[k] = st.fnv_pow[k];
   __syncthreads();
   const uint32_t pos = p0 + threadIdx.x;
   const bool valid = pos < p1;
-  const uint32_t lpos = valid ? pos : p0;  // lanes past the chunk read a valid word and drop it
+  const uint32_t lpos = valid ? pos : p0;  // lanes past the chunk read a valid bitmap word and drop it
+  const uint32_t ib = lpos - fb;           // index within the boundary: bit ib of bitmap word ib / 64
   uint64_t h1 = kFnvOffset, h2 = 0, mask = 0;
-  uint32_t wn = 0, weight = 0;
+  uint32_t wn = 0, weight = 0, nzw = 0;
   for (uint32_t k0 = 0; k0 < n; k0 += 8) {
-    uint64_t vv[8];
+    // which of the next eight covered words are non-zero, then only those words
+    uint64_t mw[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const uint32_t k = min(k0 + j, n - 1);
-      vv[j] = st.slab[s_base[k] + lpos];
+      mw[j] = st.bm[s_bmb[k] + (ib >> 6)];
+    }
+    uint64_t vv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const bool nz = valid && k0 + j < n && ((mw[j] >> (ib & 63)) & 1ull);
+      vv[j] = nz ? st.slab[s_base[k0 + j] + lpos] : 0ull;
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const uint64_t v = (k0 + j < n) ? vv[j] : 0;
+      const uint64_t v = vv[j];
       if (v) {
         const uint32_t w = s_w[k0 + j];
         h1 *= s_pow[w - wn];
 #pragma unroll
         for (int o = 0; o < 8; ++o) h1 = (h1 ^ ((v >> (8 * o)) & 0xffu)) * kFnvPrime;
         wn = w + 1;
+        nzw++;
         h2 += check_term(w, v);
         weight += __popcll(v);
         if (k0 + j < 64) mask |= 1ull << (k0 + j);
@@ -599,22 +639,30 @@ __global__ __launch_bounds__(kBlock) void k_hash(DevState st) {
     st.popc[pos] = weight;
     st.nzm[pos] = mask;
   }
-  // live faults per compaction tile: the chunk's positions span at most two
-  // tiles; reduce over the block, then at most two global atomics
-  __shared__ uint32_t s_cnt[2];
-  if (threadIdx.x < 2) s_cnt[threadIdx.x] = 0;
+  // live faults and non-zero words per compaction tile: the chunk's
+  // positions span at most two tiles; reduce over the block, then at most
+  // four global atomics
+  __shared__ uint32_t s_cnt[4];
+  if (threadIdx.x < 4) s_cnt[threadIdx.x] = 0;
   __syncthreads();
   const uint32_t ta = p0 / kTile;
   const bool live = valid && weight != 0;
-  const uint32_t c_a = wave_sum((live && pos / kTile == ta) ? 1u : 0u);
-  const uint32_t c_b = wave_sum((live && pos / kTile != ta) ? 1u : 0u);
+  const bool in_a = pos / kTile == ta;
+  const uint32_t c_a = wave_sum((live && in_a) ? 1u : 0u);
+  const uint32_t c_b = wave_sum((live && !in_a) ? 1u : 0u);
+  const uint32_t z_a = wave_sum(valid && in_a ? nzw : 0u);
+  const uint32_t z_b = wave_sum(valid && !in_a ? nzw : 0u);
   if ((threadIdx.x & 63) == 0) {
     if (c_a) atomicAdd(&s_cnt[0], c_a);
     if (c_b) atomicAdd(&s_cnt[1], c_b);
+    if (z_a) atomicAdd(&s_cnt[2], z_a);
+    if (z_b) atomicAdd(&s_cnt[3], z_b);
   }
   __syncthreads();
   if (threadIdx.x == 0 && s_cnt[0]) atomicAdd(&st.tile_cnt[ta], s_cnt[0]);
   if (threadIdx.x == 1 && s_cnt[1]) atomicAdd(&st.tile_cnt[ta + 1], s_cnt[1]);
+  if (threadIdx.x == 2 && s_cnt[2]) atomicAdd(&st.tile_nz[ta], s_cnt[2]);
+  if (threadIdx.x == 3 && s_cnt[3]) atomicAdd(&st.tile_nz[ta + 1], s_cnt[3]);
 }
 
 // In-place exclusive scan of n (host value, or *n_dev when given) words by one
@@ -644,40 +692,46 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t m) {
 
 // Stable compaction of the live faults (non-empty signatures) into (key,
 // position) pairs, with the digit counts of radix passes [p0, n_pass) for
-// this tile.
-// Round k of the tile covers positions [k*256, k*256+256): consecutive lanes
-// read consecutive positions and write consecutive compacted slots.
-__global__ __launch_bounds__(kBlock) void k_compact(DevState st, uint32_t p0) {
-  constexpr int kWaves = kBlock / 64;
-  __shared__ uint32_t s_off[kPerThread * kWaves];  // per (round, wave): first slot in the tile
+// this tile. Round k of the tile covers positions [k*1024, k*1024+1024):
+// consecutive lanes read consecutive positions and write consecutive
+// compacted slots.
+constexpr int kCompactBlock = 1024;
+constexpr int kCompactRounds = kTile / kCompactBlock;
+static_assert(kCompactRounds * (kCompactBlock / 64) == 64, "compaction offsets are scanned by one wave");
+
+__global__ __launch_bounds__(kCompactBlock) void k_compact(DevState st, uint32_t p0) {
+  constexpr int kWaves = kCompactBlock / 64;
+  __shared__ uint32_t s_off[kCompactRounds * kWaves];  // per (round, wave): first slot in the tile
   __shared__ uint32_t s_hist[kMaxPasses][256];
   const uint32_t tile = blockIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (uint32_t i = threadIdx.x; i < kMaxPasses * 256; i += kBlock) (&s_hist[0][0])[i] = 0;
+  for (uint32_t i = threadIdx.x; i < kMaxPasses * 256; i += kCompactBlock) (&s_hist[0][0])[i] = 0;
   const uint32_t base = tile * kTile + threadIdx.x;
   uint32_t flags = 0;
 #pragma unroll
-  for (int k = 0; k < kPerThread; ++k) {
-    const uint32_t i = base + k * kBlock;
+  for (int k = 0; k < kCompactRounds; ++k) {
+    const uint32_t i = base + k * kCompactBlock;
     const bool live = i < st.n_faults && st.popc[i] != 0;
     flags |= uint32_t(live) << k;
     const uint64_t m = __ballot(live);
     if (lane == 0) s_off[k * kWaves + wv] = uint32_t(__popcll(m));
   }
   __syncthreads();
-  if (threadIdx.x < kPerThread * kWaves) {
+  if (threadIdx.x < kCompactRounds * kWaves) {
     const uint32_t v = s_off[threadIdx.x];
     s_off[threadIdx.x] = wave_inclusive_scan(v) - v;
   }
   __syncthreads();
   const uint32_t tb = st.tile_cnt[tile];
   const uint32_t P = st.n_pass;
+  if (threadIdx.x == 0 && st.tile_nz[tile])
+    atomicAdd(reinterpret_cast<unsigned long long*>(&st.hdr->n_nz_words), (unsigned long long)st.tile_nz[tile]);
 #pragma unroll
-  for (int k = 0; k < kPerThread; ++k) {
+  for (int k = 0; k < kCompactRounds; ++k) {
     const bool live = (flags >> k) & 1u;
     const uint64_t m = __ballot(live);
     if (live) {
-      const uint32_t i = base + k * kBlock;
+      const uint32_t i = base + k * kCompactBlock;
       const uint32_t slot = tb + s_off[k * kWaves + wv] + lane_rank(m);
       const uint64_t key = st.key[1][i];
       st.key[0][slot] = key;
@@ -687,7 +741,10 @@ __global__ __launch_bounds__(kBlock) void k_compact(DevState st, uint32_t p0) {
   }
   __syncthreads();
   uint32_t* part = st.part_hist + size_t(tile) * kMaxPasses * 256;
-  for (uint32_t p = p0; p < P; ++p) part[p * 256 + threadIdx.x] = s_hist[p][threadIdx.x];
+  for (uint32_t i = threadIdx.x; i < (P - p0) * 256; i += kCompactBlock) {
+    const uint32_t p = p0 + i / 256, dg = i % 256;
+    part[p * 256 + dg] = s_hist[p][dg];
+  }
 }
 
 // Total count of digit d in pass p over all compaction tiles (block
@@ -722,82 +779,96 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
 
 // One stable pass of 8-bit digits over the live keys (n = hdr->n_live). Tiles
 // are taken in ticket order, so every tile a block waits for is already
-// running. Wave v ranks tile items [v*1024, (v+1)*1024) in order, 64 at a time.
-// The tile publishes its digit counts first, ranks its items into LDS, and
-// only then looks back for the counts of the tiles before it.
-__global__ __launch_bounds__(kBlock) void k_onesweep(DevState st, uint32_t pass, const uint64_t* __restrict__ kin,
-                                                     const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
-                                                     uint32_t* __restrict__ vout) {
+// running. Wave v ranks tile items [v*256, (v+1)*256) in order, 64 at a time;
+// each round's digit-peer masks serve both the wave's histogram and the
+// placement. The tile publishes its digit counts first, ranks its items into
+// LDS, and only then looks back for the counts of the tiles before it.
+constexpr int kSortBlock = 1024;
+constexpr int kSortWaves = kSortBlock / 64;
+constexpr int kSortRounds = kTile / kSortBlock;
+
+__global__ __launch_bounds__(kSortBlock) void k_onesweep(DevState st, uint32_t pass, const uint64_t* __restrict__ kin,
+                                                         const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
+                                                         uint32_t* __restrict__ vout) {
   __shared__ uint64_t s_key[kTile];
   __shared__ uint32_t s_val[kTile];
-  __shared__ uint32_t s_cnt[kBlock / 64][256];
+  __shared__ uint32_t s_cnt[kSortWaves][256];
   __shared__ uint32_t s_start[256];
   __shared__ uint32_t s_gbase[256];
-  __shared__ uint32_t s_wave[kBlock / 64 + 1];
+  __shared__ uint32_t s_wave[kSortWaves + 1];
   __shared__ uint32_t s_tile;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const uint32_t n = st.hdr->n_live;
   const uint32_t ntiles = (n + kTile - 1) / kTile;
   if (tid == 0) s_tile = atomicAdd(&st.tile_ctr[pass], 1u);
-  for (int k = tid; k < (kBlock / 64) * 256; k += kBlock) (&s_cnt[0][0])[k] = 0;
+  for (int k = tid; k < kSortWaves * 256; k += kSortBlock) (&s_cnt[0][0])[k] = 0;
   __syncthreads();
   const uint32_t tile = s_tile;
   if (tile >= ntiles) return;
-  const uint32_t base = tile * kTile + wv * (kTile / (kBlock / 64));
-  constexpr int kRounds = kTile / kBlock;
-  uint64_t k[kRounds];
-  uint32_t v[kRounds];
+  const uint32_t base = tile * kTile + wv * (kTile / kSortWaves);
+  uint64_t k[kSortRounds];
+  uint32_t v[kSortRounds];
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
+  for (int r = 0; r < kSortRounds; ++r) {
     const uint32_t i = base + r * 64 + lane;
     k[r] = i < n ? kin[i] : 0;
     v[r] = i < n ? vin[i] : 0;
   }
   // global start of every digit value: exclusive prefix of the digit totals
-  const uint32_t digit_base = block_exclusive_scan<kBlock>(st.digit_tot[pass * 256 + tid], s_wave);
+  const uint32_t digit_base =
+      block_exclusive_scan<kSortBlock>(tid < 256 ? st.digit_tot[pass * 256 + tid] : 0u, s_wave);
+  const uint64_t lt = (1ull << lane) - 1;
+  uint64_t peers[kSortRounds];
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r)
-    if (base + r * 64 + lane < n) atomicAdd(&s_cnt[wv][digit_of(k[r], pass)], 1u);
+  for (int r = 0; r < kSortRounds; ++r) {
+    const bool valid = base + r * 64 + lane < n;
+    const uint32_t d = valid ? digit_of(k[r], pass) : 0u;
+    peers[r] = digit_peers(d, valid);
+    if (valid && (peers[r] & lt) == 0) s_cnt[wv][d] += uint32_t(__popcll(peers[r]));
+    __builtin_amdgcn_wave_barrier();
+  }
   __syncthreads();
   uint32_t* lb = st.lookback + size_t(pass) * st.max_tiles * 256;
   uint32_t tot = 0;
-  {
-    // thread d: tile count of digit d; publish it; local start of digit d
-    const uint32_t d = tid;
+  if (tid < 256) {
+    // thread d: tile count of digit d; publish it
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) tot += s_cnt[w][d];
-    __hip_atomic_store(&lb[size_t(tile) * 256 + d], (tile == 0 ? kLbPre : kLbAgg) | tot, __ATOMIC_RELAXED,
+    for (int w = 0; w < kSortWaves; ++w) tot += s_cnt[w][tid];
+    __hip_atomic_store(&lb[size_t(tile) * 256 + tid], (tile == 0 ? kLbPre : kLbAgg) | tot, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t start = block_exclusive_scan<kBlock>(tot, s_wave);
-    s_start[d] = start;
-    uint32_t run = start;
+  }
+  {
+    // local start of digit d, then of each wave's share of it
+    const uint32_t start = block_exclusive_scan<kSortBlock>(tot, s_wave);
+    if (tid < 256) {
+      s_start[tid] = start;
+      uint32_t run = start;
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) {
-      const uint32_t c = s_cnt[w][d];
-      s_cnt[w][d] = run;
-      run += c;
+      for (int w = 0; w < kSortWaves; ++w) {
+        const uint32_t c = s_cnt[w][tid];
+        s_cnt[w][tid] = run;
+        run += c;
+      }
     }
   }
   __syncthreads();
   // rank in order and place into LDS sorted by digit
-  const uint64_t lt = (1ull << lane) - 1;
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
+  for (int r = 0; r < kSortRounds; ++r) {
     const bool valid = base + r * 64 + lane < n;
     const uint32_t d = valid ? digit_of(k[r], pass) : 0u;
-    const uint64_t peers = digit_peers(d, valid);
-    const uint32_t rank = __popcll(peers & lt);
+    const uint32_t rank = uint32_t(__popcll(peers[r] & lt));
     uint32_t li = 0;
     if (valid) li = s_cnt[wv][d] + rank;
     __builtin_amdgcn_wave_barrier();
-    if (valid && rank == 0) s_cnt[wv][d] += __popcll(peers);
+    if (valid && rank == 0) s_cnt[wv][d] += uint32_t(__popcll(peers[r]));
     __builtin_amdgcn_wave_barrier();
     if (valid) {
       s_key[li] = k[r];
       s_val[li] = v[r];
     }
   }
-  {
+  if (tid < 256) {
     // thread d: counts of digit d in the tiles before this one, kLookWin at a
     // time, until a tile that already published its inclusive prefix. Every
     // tile runs at once, so the inclusive prefixes spread from tile 0 while
@@ -844,7 +915,7 @@ __global__ __launch_bounds__(kBlock) void k_onesweep(DevState st, uint32_t pass,
   __syncthreads();
   // write runs of equal digits to consecutive global positions
   const uint32_t cnt = min(uint32_t(kTile), n - tile * kTile);
-  for (uint32_t li = tid; li < cnt; li += kBlock) {
+  for (uint32_t li = tid; li < cnt; li += kSortBlock) {
     const uint64_t key = s_key[li];
     const uint32_t d = digit_of(key, pass);
     const uint32_t dst = s_gbase[d] + (li - s_start[d]);
@@ -1023,8 +1094,10 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
   extern __shared__ __align__(16) uint64_t s_buf[];  // two buffers of kBucketCap values
   __shared__ uint32_t s_cnt[kBucketWaves][256];
   __shared__ uint32_t s_wave[kBucketWaves + 1];
-  __shared__ uint32_t s_big[kBucketCap / (kBigSegment + 1) + 1];
+  __shared__ uint32_t s_big[2 * (kBucketCap / (kBigSegment + 1) + 1)];  // (class, first sorted index)
+  __shared__ uint64_t s_hb[kBucketCap / 64];                            // class heads, one bit per value
   __shared__ uint32_t s_nbig;
+  __shared__ uint32_t s_big_end;
   __shared__ uint32_t s_start;
   __shared__ double s_q[kBucketBlock];
   __shared__ int s_bad;
@@ -1042,6 +1115,7 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
       s_nbig = 0;
       s_bad = 0;
     }
+    for (uint32_t k = tid; k < kBucketCap / 64; k += kBucketBlock) s_hb[k] = 0;
   }
   __syncthreads();
   const uint32_t start = s_start;
@@ -1111,55 +1185,107 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
     a = b;
     b = t;
   }
-  // class heads; thread t owns the sorted values [t*per, (t+1)*per)
-  uint32_t* hpos = reinterpret_cast<uint32_t*>(b);  // first sorted index of each class
-  uint32_t* hcnt = hpos + kBucketCap;              // signature bits of each class
-  const uint32_t per = rounds;
-  const uint32_t j0 = min(m, tid * per), j1 = min(m, j0 + per);
-  auto is_head = [&](uint32_t j) { return j == 0 || (a[j] >> 16) != (a[j - 1] >> 16); };
-  uint32_t nh = 0;
-  for (uint32_t j = j0; j < j1; ++j) nh += is_head(j);
-  uint32_t c = block_exclusive_scan<kBucketBlock>(nh, s_wave);
-  const uint32_t ncls = s_wave[kBucketWaves];
-  for (uint32_t j = j0; j < j1; ++j)
-    if (is_head(j)) hpos[c++] = j;
-  __syncthreads();
-  // small classes: one thread each, members in position order
-  for (uint32_t k = tid; k < ncls; k += kBucketBlock) {
-    const uint32_t i0 = hpos[k], i1 = k + 1 < ncls ? hpos[k + 1] : m;
-    if (i1 - i0 > kBigSegment) {
-      s_big[atomicAdd(&s_nbig, 1u)] = k;
-      continue;
+  // Each thread owns the sorted values [j0, j0 + per): their head flags
+  // (first of a run of equal key bits) go to an LDS bitmask, and their
+  // probability and check hash are gathered at once (independent loads)
+  // into the two sort buffers, now free: p over a, check hash over b.
+  const uint32_t per = rounds;  // at most kBucketCap / kBucketBlock
+  const uint32_t j0 = tid * per;
+  uint32_t hmask = 0;
+  uint32_t pos[kBucketCap / kBucketBlock];
+#pragma unroll
+  for (int k = 0; k < int(kBucketCap / kBucketBlock); ++k) {
+    const uint32_t j = j0 + k;
+    pos[k] = 0;
+    if (uint32_t(k) < per && j < m) {
+      const uint64_t v = a[j];
+      if (j == 0 || (v >> 16) != (a[j - 1] >> 16)) hmask |= 1u << k;
+      pos[k] = vals[start + uint32_t(v & 0xFFFFu)];
     }
-    const uint32_t rep = vals[start + uint32_t(a[i0] & 0xFFFFu)];
-    const FaultRec r0 = st.frp[rep];
-    bool bad = false;
-    double q = r0.p;
-    for (uint32_t i = i0 + 1; i < i1; ++i) {
-      const FaultRec r = st.frp[vals[start + uint32_t(a[i] & 0xFFFFu)]];
-      bad |= r.chk != r0.chk;
-      q = fma(r.p, 1.0 - 2.0 * q, q);  // Eq. 3: q(1-p) + p(1-q)
-    }
-    if (bad) s_bad = 1;
-    const uint32_t bits = st.popc[rep];
-    st.seg_q[start + k] = q;
-    st.seg_rep[start + k] = rep;
-    hcnt[k] = bits;
   }
+  if (hmask) {
+    const uint32_t wd = j0 >> 6, sh = j0 & 63;
+    atomicOr(&s_hb[wd], uint64_t(hmask) << sh);
+    if (sh + per > 64) atomicOr(&s_hb[wd + 1], uint64_t(hmask) >> (64 - sh));
+  }
+  FaultRec rec[kBucketCap / kBucketBlock];
+#pragma unroll
+  for (int k = 0; k < int(kBucketCap / kBucketBlock); ++k)
+    if (uint32_t(k) < per && j0 + k < m) rec[k] = st.frp[pos[k]];
+  const uint32_t nh = uint32_t(__popc(hmask));
+  uint32_t c = block_exclusive_scan<kBucketBlock>(nh, s_wave);  // barrier: every a[j] has been read
+  const uint32_t ncls = s_wave[kBucketWaves];
+  double* sp = reinterpret_cast<double*>(a);
+  uint64_t* sc = b;
+#pragma unroll
+  for (int k = 0; k < int(kBucketCap / kBucketBlock); ++k)
+    if (uint32_t(k) < per && j0 + k < m) {
+      sp[j0 + k] = rec[k].p;
+      sc[j0 + k] = rec[k].chk;
+    }
   __syncthreads();
-  // large classes: strided partial merges, then a fixed-shape tree
+  auto head_at = [&](uint32_t j) -> bool { return (s_hb[j >> 6] >> (j & 63)) & 1ull; };
+  // classes whose head this thread owns, in order: Eq. 3 over the members
+  // in position order (runs longer than kBigSegment go to the block below)
+  uint32_t nbits = 0;
+  uint32_t cbits[kBucketCap / kBucketBlock];
+#pragma unroll
+  for (int k = 0; k < int(kBucketCap / kBucketBlock); ++k) {
+    cbits[k] = 0;
+    if (!((hmask >> k) & 1u)) continue;
+    const uint32_t j = j0 + k;
+    const uint32_t cls = c + uint32_t(__popc(hmask & ((1u << k) - 1)));
+    const uint32_t rep = pos[k];
+    cbits[k] = st.popc[rep];
+    nbits += cbits[k];
+    st.seg_rep[start + cls] = rep;
+    double q = sp[j];
+    const uint64_t c0 = sc[j];
+    bool bad = false;
+    uint32_t i = j + 1;
+    for (; i < m && i - j <= kBigSegment && !head_at(i); ++i) {
+      bad |= sc[i] != c0;
+      q = fma(sp[i], 1.0 - 2.0 * q, q);  // Eq. 3: q(1-p) + p(1-q)
+    }
+    if (i < m && i - j > kBigSegment && !head_at(i)) {
+      const uint32_t g = atomicAdd(&s_nbig, 1u);
+      s_big[2 * g] = cls;
+      s_big[2 * g + 1] = j;
+    } else {
+      st.seg_q[start + cls] = q;
+      if (bad) s_bad = 1;
+    }
+  }
+  // bit offsets of the classes within the bucket (class order = thread order)
+  uint32_t o = block_exclusive_scan<kBucketBlock>(nbits, s_wave);
+  {
+    uint32_t k2 = 0;
+#pragma unroll
+    for (int k = 0; k < int(kBucketCap / kBucketBlock); ++k)
+      if ((hmask >> k) & 1u) {
+        st.seg_off[start + c + k2] = o;
+        o += cbits[k];
+        k2++;
+      }
+  }
+  // large classes: strided partial merges over the whole run, then a
+  // fixed-shape tree
   const uint32_t nbig = s_nbig;
   for (uint32_t g = 0; g < nbig; ++g) {
-    const uint32_t k = s_big[g];
-    const uint32_t i0 = hpos[k], i1 = k + 1 < ncls ? hpos[k + 1] : m;
-    const uint32_t rep = vals[start + uint32_t(a[i0] & 0xFFFFu)];
-    const uint64_t c0 = st.frp[rep].chk;
+    const uint32_t cls = s_big[2 * g], j = s_big[2 * g + 1];
+    if (tid == 0) {
+      uint32_t e = j + 1;
+      while (e < m && !head_at(e)) ++e;
+      s_big_end = e;
+    }
+    __syncthreads();
+    const uint32_t e = s_big_end;
+    const uint64_t c0 = sc[j];
     bool bad = false;
     double q = 0.0;
-    for (uint32_t i = i0 + tid; i < i1; i += kBucketBlock) {
-      const FaultRec r = st.frp[vals[start + uint32_t(a[i] & 0xFFFFu)]];
-      bad |= r.chk != c0;
-      q = fma(r.p, 1.0 - 2.0 * q, q);
+    for (uint32_t i = j + tid; i < e; i += kBucketBlock) {
+      bad |= sc[i] != c0;
+      q = fma(sp[i], 1.0 - 2.0 * q, q);
     }
     if (bad) s_bad = 1;
     s_q[tid] = q;
@@ -1171,22 +1297,8 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
       }
       __syncthreads();
     }
-    if (tid == 0) {
-      st.seg_q[start + k] = s_q[0];
-      st.seg_rep[start + k] = rep;
-      hcnt[k] = st.popc[rep];
-    }
+    if (tid == 0) st.seg_q[start + cls] = s_q[0];
     __syncthreads();
-  }
-  // bit offsets of the classes within the bucket
-  const uint32_t pc = (ncls + kBucketBlock - 1) / kBucketBlock;
-  const uint32_t k0 = min(ncls, tid * pc), k1 = min(ncls, k0 + pc);
-  uint32_t nb = 0;
-  for (uint32_t k = k0; k < k1; ++k) nb += hcnt[k];
-  uint32_t o = block_exclusive_scan<kBucketBlock>(nb, s_wave);
-  for (uint32_t k = k0; k < k1; ++k) {
-    st.seg_off[start + k] = o;
-    o += hcnt[k];
   }
   if (tid == 0) {
     b_cls[d] = ncls;
@@ -1228,15 +1340,19 @@ __global__ __launch_bounds__(kBuckets) void k_bucket_scan(DevState st) {
 // observable k -> D + k) and its probability.
 // With kBuckets, class e lives at slot bucket_start + (e - bucket_class_offset)
 // and its bit offset is the bucket's plus the class's within the bucket.
+// The boundary fault offsets are searched in LDS when they fit.
 template <bool kBucketed>
 __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
   __shared__ uint32_t s_cls[kBuckets + 1];
+  __shared__ uint32_t s_bfo[kLofsMax];
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t S = st.hdr->n_seg;
-  if (kBucketed) {
+  const bool bfo_lds = st.n_layers + 2 <= uint32_t(kLofsMax);
+  if (kBucketed)
     for (uint32_t k = threadIdx.x; k <= kBuckets; k += blockDim.x) s_cls[k] = st.bkt[k];
-    __syncthreads();
-  }
+  if (bfo_lds)
+    for (uint32_t k = threadIdx.x; k < st.n_layers + 2; k += blockDim.x) s_bfo[k] = st.bnd_fault_off[k];
+  __syncthreads();
   if (e == 0) {
     st.hdr->n_edges = S;
     st.edge_off32[S] = uint32_t(st.hdr->n_bits);
@@ -1262,7 +1378,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
   const uint32_t pos = st.seg_rep[s];
   const uint32_t cnt = kBucketed ? st.popc[pos] : st.seg_cnt[s];
   if (uint64_t(o0) + cnt > st.bits_cap) return;
-  const uint32_t b = boundary_of(st.bnd_fault_off, st.n_layers + 1, pos);
+  const uint32_t b = boundary_of(bfo_lds ? s_bfo : st.bnd_fault_off, st.n_layers + 1, pos);
   const uint32_t n = st.ncov[b];
   const uint32_t* cl = st.cov + size_t(b) * st.w;
   uint32_t o = o0;
@@ -1284,7 +1400,11 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
       emit(cl[k]);
     }
   } else {
-    for (uint32_t k = 0; k < n; ++k) emit(cl[k]);
+    // more covered columns than mask bits: the bitmaps say which words are stored
+    const uint32_t ib = pos - st.bnd_fault_off[b];
+    const uint64_t* bm = st.bm + st.bnd_bm_off[b] + (ib >> 6);
+    for (uint32_t k = 0; k < n; ++k)
+      if ((bm[st.col_bm_base[cl[k]]] >> (ib & 63)) & 1ull) emit(cl[k]);
   }
 }
 
@@ -1312,7 +1432,7 @@ uint32_t sort_passes(uint64_t n) {
 
 size_t sweep_lds_bytes(uint32_t n_qubits) {
   return (size_t(5) * n_qubits + kInjLds) * sizeof(uint64_t) +
-         (size_t(2) * kWinOps + 2 * kLofsMax + 1 + 3 * kInjLds) * sizeof(uint32_t);
+         (size_t(2) * kWinOps + 3 * kLofsMax + 2 + 3 * kInjLds) * sizeof(uint32_t);
 }
 
 static size_t g_lds_limit = 64 * 1024;
@@ -1402,20 +1522,20 @@ hipError_t enqueue_compile(const DevState& st_in, hipStream_t stream, const Laun
                         st.n_pass >= 2 && st.n_pass <= 7;
   if (bucketed) {
     const uint32_t msd = st.n_pass - 1;
-    GP_LAUNCH(K_COMPACT, k_compact<<<ntiles, kBlock, 0, stream>>>(st, msd));
+    GP_LAUNCH(K_COMPACT, k_compact<<<ntiles, kCompactBlock, 0, stream>>>(st, msd));
     GP_LAUNCH(K_DIGIT_OFFSETS, k_digit_totals<<<256, kBlock, 0, stream>>>(st, ntiles, msd));
-    GP_LAUNCH(K_ONESWEEP, k_onesweep<<<ntiles, kBlock, 0, stream>>>(st, msd, st.key[0], st.val[0], st.key[1],
+    GP_LAUNCH(K_ONESWEEP, k_onesweep<<<ntiles, kSortBlock, 0, stream>>>(st, msd, st.key[0], st.val[0], st.key[1],
                                                                      st.val[1]));
     GP_LAUNCH(K_BUCKET, k_bucket<<<kBuckets, kBucketBlock, kBucketDynLds, stream>>>(st, st.key[1], st.val[1]));
     GP_LAUNCH(K_BUCKET_SCAN, k_bucket_scan<<<1, kBuckets, 0, stream>>>(st));
     GP_LAUNCH(K_EDGE_WRITE, k_edge_write<true><<<cdiv(n, kBlock), kBlock, 0, stream>>>(st));
     return hipSuccess;
   }
-  GP_LAUNCH(K_COMPACT, k_compact<<<ntiles, kBlock, 0, stream>>>(st, 0));
+  GP_LAUNCH(K_COMPACT, k_compact<<<ntiles, kCompactBlock, 0, stream>>>(st, 0));
   GP_LAUNCH(K_DIGIT_OFFSETS, k_digit_totals<<<st.n_pass * 256, kBlock, 0, stream>>>(st, ntiles, 0));
   for (uint32_t pass = 0; pass < st.n_pass; ++pass) {
     const int src = pass & 1, dst = src ^ 1;
-    GP_LAUNCH(K_ONESWEEP, k_onesweep<<<ntiles, kBlock, 0, stream>>>(st, pass, st.key[src], st.val[src], st.key[dst],
+    GP_LAUNCH(K_ONESWEEP, k_onesweep<<<ntiles, kSortBlock, 0, stream>>>(st, pass, st.key[src], st.val[src], st.key[dst],
                                                                      st.val[dst]));
   }
   const int fin = st.n_pass & 1;

@@ -364,6 +364,16 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
     else lw.col_lo[w] = -1;
   }
   lw.slab_words = base;
+  lw.bnd_bm_off.assign(size_t(L) + 2, 0);
+  for (uint32_t b = 0; b <= L; b++)
+    lw.bnd_bm_off[b + 1] = lw.bnd_bm_off[b] + (lw.bnd_fault_off[b + 1] - lw.bnd_fault_off[b] + 63) / 64;
+  lw.col_bm_base.assign(lw.w, 0);
+  uint64_t bm = 0;
+  for (uint32_t w = 0; w < lw.w; w++) {
+    lw.col_bm_base[w] = bm;
+    if (lw.col_top[w] >= 0) bm += lw.bnd_bm_off[lw.col_top[w] + 1];
+  }
+  lw.bm_words = bm;
 
   // ---- sweep items: one per detector column; observable columns, which stay
   // live over the whole circuit, are cut into boundary ranges so that their
@@ -405,6 +415,20 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
     lw.item_col.push_back(w);
     lw.item_blo.push_back(0);
     lw.item_bhi.push_back(uint32_t(lw.col_top[w]));
+  }
+
+  // ---- op windows (a layer has at most n ops; the driver rejects circuits
+  // whose largest layer exceeds a window)
+  lw.layer_win.assign(L, 0);
+  for (int32_t hi = int32_t(L) - 1; hi >= 0;) {
+    int32_t lo = hi;
+    while (lo > 0 && lw.layer_off[hi + 1] - lw.layer_off[lo - 1] <= kSweepWinOps) lo--;
+    const uint32_t id = uint32_t(lw.win_lo.size());
+    lw.win_lo.push_back(uint32_t(lo));
+    lw.win_obase.push_back(lw.layer_off[lo]);
+    lw.win_cnt.push_back(lw.layer_off[hi + 1] - lw.layer_off[lo]);
+    for (int32_t t = lo; t <= hi; t++) lw.layer_win[t] = id;
+    hi = lo - 1;
   }
 
   // ---- compact sweep ops (qubit indices must fit the compact word)

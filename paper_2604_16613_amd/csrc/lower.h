@@ -43,6 +43,8 @@ inline uint64_t pack_op(uint32_t kind, uint32_t a, uint32_t b) {
 constexpr uint32_t kQubitBits = 14;
 constexpr uint32_t kMaxSweepQubits = 1u << kQubitBits;
 constexpr uint32_t kQField = kMaxSweepQubits - 1;
+// Compact ops one LDS op window of the sweep holds.
+constexpr uint32_t kSweepWinOps = 4096;
 // Sweep items that run at once: one per CU of the target GPU (256 on gfx950).
 constexpr uint32_t kSweepSlots = 256;
 // An observable column is not cut into ranges of fewer faults than this.
@@ -92,6 +94,19 @@ struct Lowered {
 
   // hash work chunks: at most 256 consecutive fault positions of one boundary
   std::vector<uint32_t> hchunk_pos, hchunk_bnd;
+
+  // op windows of the sweep: layers cut from the top down into ranges of at
+  // most kSweepWinOps ops; window k (k grows downward) holds layers
+  // [win_lo[k], win_lo[k-1]) and its ops start at win_obase[k]
+  std::vector<uint32_t> layer_win;          // per layer: its window
+  std::vector<uint32_t> win_lo, win_obase, win_cnt;
+
+  // non-zero-word bitmaps: per boundary b, ceil(faults at b / 64) words
+  // starting at bnd_bm_off[b] (L + 2 entries); column w's bitmaps start at
+  // col_bm_base[w] (boundaries 0 .. its top leaf layer)
+  std::vector<uint32_t> bnd_bm_off;
+  std::vector<uint64_t> col_bm_base;
+  uint64_t bm_words = 0;
 };
 
 struct LowerError {
