@@ -388,25 +388,54 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
     const uint32_t slots = std::max<uint32_t>(sweep_slots, 1);
     const uint32_t per_obs =
         n_obs_live && slots > n_det_items ? std::max<uint32_t>((slots - n_det_items) / n_obs_live, 1) : 1;
+    // A range [lo, hi] costs (top - hi) transform-only layers plus its own
+    // layers with their faults (relative weights of a transform-only layer
+    // and of one emitted fault, measured on gfx950). Every range re-sweeps
+    // from the top, so the lowest ranges get few boundaries and the upper
+    // ones many: the smallest makespan T that the greedy cut from the
+    // bottom fits into per_obs ranges is found by bisection.
+    constexpr double kLayerCost = 1.0, kFaultCost = 5.2e-4;
     for (uint32_t w = lw.wd; w < lw.w; w++) {
       const int32_t top = lw.col_top[w];
       if (top < 0) continue;
-      const uint64_t total = lw.bnd_fault_off[top + 1];
-      const uint64_t chunk = std::max<uint64_t>((total + per_obs - 1) / per_obs, kMinObsChunkFaults);
-      // every range but the lowest holds at least `chunk` faults, so there
-      // are at most per_obs of them
+      auto emit_cost = [&](int32_t t) {
+        return kLayerCost + kFaultCost * double(lw.bnd_fault_off[t + 1] - lw.bnd_fault_off[t]);
+      };
+      // greedy cut for makespan T: ranges from the bottom up, or empty if a
+      // range would exceed per_obs
+      auto cut = [&](double T, std::vector<std::pair<uint32_t, uint32_t>>& out) {
+        out.clear();
+        int32_t lo = 0;
+        while (lo <= top) {
+          if (out.size() == per_obs) return false;
+          double c = kLayerCost * double(top - lo) + emit_cost(lo);
+          int32_t hi = lo;
+          while (hi < top) {
+            const double nc = c - kLayerCost + emit_cost(hi + 1);
+            if (nc > T) break;
+            c = nc;
+            hi++;
+          }
+          out.emplace_back(uint32_t(lo), uint32_t(hi));
+          lo = hi + 1;
+        }
+        return true;
+      };
+      double total = 0;
+      for (int32_t t = 0; t <= top; t++) total += emit_cost(t);
+      double lo_T = 0, hi_T = total + kLayerCost * double(top + 1);
       std::vector<std::pair<uint32_t, uint32_t>> ranges;
-      int32_t hi = top;
-      while (hi >= 0) {
-        int32_t lo = hi;
-        while (lo > 0 && uint64_t(lw.bnd_fault_off[hi + 1] - lw.bnd_fault_off[lo]) < chunk) lo--;
-        ranges.emplace_back(uint32_t(lo), uint32_t(hi));
-        hi = lo - 1;
+      for (int it = 0; it < 60; it++) {
+        const double mid = 0.5 * (lo_T + hi_T);
+        if (cut(mid, ranges)) hi_T = mid;
+        else lo_T = mid;
       }
-      for (size_t k = ranges.size(); k-- > 0;) {
+      cut(hi_T, ranges);
+      // ranges are bottom-up: the lowest (longest-running) first
+      for (const auto& r : ranges) {
         lw.item_col.push_back(w);
-        lw.item_blo.push_back(ranges[k].first);
-        lw.item_bhi.push_back(ranges[k].second);
+        lw.item_blo.push_back(r.first);
+        lw.item_bhi.push_back(r.second);
       }
     }
   }
