@@ -74,6 +74,26 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
   return v;
 }
 
+// Exclusive scan over a block with one barrier: every thread sums the wave
+// totals itself. s_wave needs BLOCK/64 entries; callers barrier before the
+// next use of s_wave.
+template <int BLOCK>
+__device__ __forceinline__ uint32_t block_scan_1sync(uint32_t v, uint32_t* s_wave, uint32_t& total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const uint32_t inc = wave_inclusive_scan(v);
+  if (lane == 63) s_wave[wv] = inc;
+  __syncthreads();
+  uint32_t off = 0, tot = 0;
+#pragma unroll
+  for (int k = 0; k < BLOCK / 64; ++k) {
+    const uint32_t x = s_wave[k];
+    off += k < wv ? x : 0u;
+    tot += x;
+  }
+  total = tot;
+  return off + inc - v;
+}
+
 // Exclusive scan over a block; s_wave needs BLOCK/64 + 1 entries and holds the
 // block total in s_wave[BLOCK/64] on return. Callers barrier before reuse.
 template <int BLOCK>
@@ -1078,6 +1098,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_big(DevState st, const uint32
 
 constexpr int kBucketBlock = 1024;
 constexpr int kBucketWaves = kBucketBlock / 64;
+constexpr uint32_t kBucketSortBits = 24;  // key bits a bucket sorts in LDS; longer runs of equal bits are rare
 
 // Grouping inside one bucket: the live faults whose key has top digit d,
 // which the stable partition pass left in position order at
@@ -1096,6 +1117,9 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
   __shared__ uint32_t s_wave[kBucketWaves + 1];
   __shared__ uint32_t s_big[2 * (kBucketCap / (kBigSegment + 1) + 1)];  // (class, first sorted index)
   __shared__ uint64_t s_hb[kBucketCap / 64];                            // class heads, one bit per value
+  __shared__ uint64_t s_rb[kBucketCap / 64];                            // starts of runs of equal sorted bits
+  __shared__ uint64_t s_mb[kBucketCap / 64];                            // run members whose key differs
+  __shared__ int s_bad_bucket;
   __shared__ uint32_t s_nbig;
   __shared__ uint32_t s_big_end;
   __shared__ uint32_t s_start;
@@ -1114,6 +1138,7 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
     if (tid == 0) {
       s_nbig = 0;
       s_bad = 0;
+      s_bad_bucket = 0;
     }
     for (uint32_t k = tid; k < kBucketCap / 64; k += kBucketBlock) s_hb[k] = 0;
   }
@@ -1137,17 +1162,24 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
   const uint32_t rounds = (m + kBucketBlock - 1) / kBucketBlock;
   const uint32_t chunk = rounds * 64;
   const uint64_t lt = (1ull << lane) - 1;
-  for (uint32_t pass = 0; pass < msd; ++pass) {
+  // stable LSD passes over the lowest kBucketSortBits key bits (fewer when
+  // the key has fewer); equal keys then sit in runs of equal sorted bits
+  const uint32_t npass = min(msd, kBucketSortBits / 8);
+  for (uint32_t pass = 0; pass < npass; ++pass) {
     const uint32_t sh = 16 + 8 * pass;
     for (int k = tid; k < kBucketWaves * 256; k += kBucketBlock) (&s_cnt[0][0])[k] = 0;
     __syncthreads();
-    for (uint32_t r = 0; r < rounds; ++r) {
-      const uint32_t i = wv * chunk + r * 64 + lane;
-      const bool valid = i < m;
-      const uint32_t dg = valid ? uint32_t(a[i] >> sh) & 255u : 0u;
-      const uint64_t peers = digit_peers(dg, valid);
-      if (valid && (peers & lt) == 0) s_cnt[wv][dg] += uint32_t(__popcll(peers));
-      __builtin_amdgcn_wave_barrier();
+    uint64_t val[kBucketCap / kBucketBlock], pe[kBucketCap / kBucketBlock];
+#pragma unroll
+    for (int r = 0; r < int(kBucketCap / kBucketBlock); ++r) {
+      if (uint32_t(r) < rounds) {
+        const uint32_t i = wv * chunk + r * 64 + lane;
+        const bool valid = i < m;
+        val[r] = valid ? a[i] : 0ull;
+        const uint32_t dg = uint32_t(val[r] >> sh) & 255u;
+        pe[r] = digit_peers(dg, valid);
+        if (valid && (pe[r] & lt) == 0) atomicAdd(&s_cnt[wv][dg], uint32_t(__popcll(pe[r])));
+      }
     }
     __syncthreads();
     {
@@ -1159,7 +1191,8 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
         c[j] = s_cnt[w0 + j][dg];
         sum += c[j];
       }
-      uint32_t run = block_exclusive_scan<kBucketBlock>(sum, s_wave);
+      uint32_t total;
+      uint32_t run = block_scan_1sync<kBucketBlock>(sum, s_wave, total);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         s_cnt[w0 + j][dg] = run;
@@ -1167,23 +1200,88 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
       }
     }
     __syncthreads();
-    for (uint32_t r = 0; r < rounds; ++r) {
-      const uint32_t i = wv * chunk + r * 64 + lane;
-      const bool valid = i < m;
-      const uint64_t v = valid ? a[i] : 0ull;
-      const uint32_t dg = uint32_t(v >> sh) & 255u;
-      const uint64_t peers = digit_peers(dg, valid);
-      const uint32_t rank = uint32_t(__popcll(peers & lt));
-      const uint32_t base = valid ? s_cnt[wv][dg] : 0u;
-      __builtin_amdgcn_wave_barrier();
-      if (valid && rank == 0) s_cnt[wv][dg] = base + uint32_t(__popcll(peers));
-      __builtin_amdgcn_wave_barrier();
-      if (valid) b[base + rank] = v;
+#pragma unroll
+    for (int r = 0; r < int(kBucketCap / kBucketBlock); ++r) {
+      if (uint32_t(r) < rounds) {
+        const uint32_t i = wv * chunk + r * 64 + lane;
+        const bool valid = i < m;
+        const uint32_t dg = uint32_t(val[r] >> sh) & 255u;
+        const uint32_t rank = uint32_t(__popcll(pe[r] & lt));
+        const uint32_t base = valid ? s_cnt[wv][dg] : 0u;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && rank == 0) s_cnt[wv][dg] = base + uint32_t(__popcll(pe[r]));
+        __builtin_amdgcn_wave_barrier();
+        if (valid) b[base + rank] = val[r];
+      }
     }
     __syncthreads();
     uint64_t* t = a;
     a = b;
     b = t;
+  }
+  if (8 * npass < lbits) {
+    // Runs of equal sorted bits that hold more than one key (rare: the keys
+    // are hashes) are sorted by the whole value (key bits, then index) by
+    // one thread; a longer such run hands the bucket to the full sort.
+    // run starts and mixed elements (key bits differ from the previous
+    // value's inside a run) as bitmasks, read-only while runs are sorted
+    const uint64_t smask = (1ull << (16 + 8 * npass)) - 1;
+    for (uint32_t k = tid; k < kBucketCap / 64; k += kBucketBlock) {
+      s_rb[k] = 0;
+      s_mb[k] = 0;
+    }
+    __syncthreads();
+    const uint32_t j0 = tid * rounds;
+    uint32_t mixed = 0;
+    for (uint32_t k = 0; k < rounds; ++k) {
+      const uint32_t j = j0 + k;
+      if (j >= m) break;
+      const uint64_t v = a[j], u = j ? a[j - 1] : 0ull;
+      const bool run_start = j == 0 || ((v ^ u) & smask & ~0xFFFFull) != 0;
+      if (run_start) {
+        atomicOr(&s_rb[j >> 6], 1ull << (j & 63));
+      } else if ((v >> 16) != (u >> 16)) {
+        mixed |= 1u << k;
+        atomicOr(&s_mb[j >> 6], 1ull << (j & 63));
+      }
+    }
+    __syncthreads();
+    auto run_start_at = [&](uint32_t j) -> bool { return (s_rb[j >> 6] >> (j & 63)) & 1ull; };
+    auto mixed_at = [&](uint32_t j) -> bool { return (s_mb[j >> 6] >> (j & 63)) & 1ull; };
+    for (uint32_t k = 0; k < rounds; ++k) {
+      if (!((mixed >> k) & 1u)) continue;
+      const uint32_t j = j0 + k;
+      uint32_t rs = j;
+      while (!run_start_at(rs)) --rs;
+      // the first mixed element of the run sorts it
+      bool first = true;
+      for (uint32_t x = rs + 1; x < j && first; ++x) first = !mixed_at(x);
+      if (!first) continue;
+      uint32_t re = j + 1;
+      while (re < m && !run_start_at(re)) ++re;
+      if (re - rs > 64) {
+        s_bad_bucket = 1;
+        continue;
+      }
+      for (uint32_t x = rs + 1; x < re; ++x) {
+        const uint64_t v = a[x];
+        uint32_t y = x;
+        while (y > rs && a[y - 1] > v) {
+          a[y] = a[y - 1];
+          --y;
+        }
+        a[y] = v;
+      }
+    }
+    __syncthreads();
+    if (s_bad_bucket) {
+      if (tid == 0) {
+        b_cls[d] = 0;
+        b_bits[d] = 0;
+        atomicOr(&st.hdr->flags, FLAG_BUCKET);
+      }
+      return;
+    }
   }
   // Each thread owns the sorted values [j0, j0 + per): their head flags
   // (first of a run of equal key bits) go to an LDS bitmask, and their
