@@ -341,8 +341,6 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   if ((rc = dev_alloc(d, &st.nzm, F, "non-zero word masks"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.tile_cnt, size_t(d->max_tiles) + 1, "tile counts"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.tile_nz, size_t(d->max_tiles) + 1, "tile non-zero word counts"))) return cleanup(rc);
-  if ((rc = dev_alloc(d, &st.part_hist, size_t(d->max_tiles) * gp::kMaxPasses * 256, "digit counts")))
-    return cleanup(rc);
   if ((rc = dev_alloc(d, &st.digit_tot, size_t(gp::kMaxPasses) * 256, "digit totals"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.lookback, size_t(gp::kMaxPasses) * d->max_tiles * 256, "look-back words")))
     return cleanup(rc);
@@ -351,7 +349,7 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   st.max_tiles = d->max_tiles;
   if ((rc = dev_alloc(d, &st.segstart, F, "class starts"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.big, F / 64 + 1, "large classes"))) return cleanup(rc);
-  if ((rc = dev_alloc(d, &st.bkt, 3 * size_t(gp::kBuckets + 1), "bucket offsets"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.bkt, 2 * size_t(gp::kBuckets + 1), "bucket counts"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.seg_q, F, "class probabilities"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.seg_rep, F, "class representatives"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.seg_cnt, F, "class bit counts"))) return cleanup(rc);

@@ -114,14 +114,13 @@ struct DevState {
   uint64_t* nzm;         // per fault position: which covered columns hold non-zero words
   uint32_t* tile_cnt;    // per compaction tile: live faults, then their exclusive prefix
   uint32_t* tile_nz;     // per compaction tile: non-zero signature words
-  uint32_t* part_hist;   // per compaction tile: digit counts of every pass
-  uint32_t* digit_tot;   // per pass: total count of each digit value
+  uint32_t* digit_tot;   // per pass: total count of each digit value (summed by the compaction tiles)
   uint32_t* lookback;    // per pass, tile and digit: published count with status bits
   uint32_t* tile_ctr;    // per pass: tile ticket counter
   uint32_t* tile_sum;    // scan tile sums
   uint32_t* segstart;    // first sorted index of each class
   uint32_t* big;         // classes too large for one thread
-  uint32_t* bkt;         // per bucket (kBuckets + 1 each): class, bit and fault offsets
+  uint32_t* bkt;         // per bucket: classes, then signature bits (kBuckets + 1 each)
   double* seg_q;         // merged probability per class
   uint32_t* seg_rep;     // representative fault position per class
   uint32_t* seg_cnt;     // signature bits per class
@@ -136,9 +135,8 @@ struct DevState {
 
 // Names of the kernels (for timing tables).
 enum KernelId : int {
-  K_PREPARE = 0, K_SWEEP, K_COVER, K_HASH, K_SCAN_SINGLE, K_COMPACT, K_DIGIT_OFFSETS, K_ONESWEEP,
-  K_HEADS_COUNT, K_HEADS_APPLY, K_REDUCE, K_REDUCE_BIG, K_SCAN_TILES, K_SCAN_APPLY, K_EDGE_WRITE, K_BUCKET,
-  K_BUCKET_SCAN, K_COUNT
+  K_PREPARE = 0, K_SWEEP, K_HASH, K_SCAN_SINGLE, K_COMPACT, K_ONESWEEP, K_HEADS_COUNT, K_HEADS_APPLY, K_REDUCE,
+  K_REDUCE_BIG, K_SCAN_TILES, K_SCAN_APPLY, K_EDGE_WRITE, K_BUCKET, K_COUNT
 };
 const char* kernel_name(int id);
 

@@ -181,6 +181,7 @@ __global__ void k_prepare(DevState st) {
   for (uint32_t i = gid; i < st.n_pass * per_pass; i += stride)
     st.lookback[size_t(i / per_pass) * st.max_tiles * 256 + i % per_pass] = 0;
   if (gid < kMaxPasses) st.tile_ctr[gid] = 0;
+  for (uint32_t i = gid; i < st.n_pass * 256; i += stride) st.digit_tot[i] = 0;
   if (gid == 0) {
     st.hdr->n_seg = 0;
     st.hdr->empty_seg = kNone;
@@ -560,12 +561,28 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   if (tid == 0) st.item_clock[2 * item + 1] = wall_clock64();
 }
 
-// Per boundary (one block each), the ascending list of columns whose word there
-// may be non-zero.
-__global__ __launch_bounds__(kBlock) void k_cover(DevState st) {
+// ------------------------------------------------------------------ stage 2
+
+// FNV-1a over the 8W octets of each fault's signature (h <- (h ^ octet) *
+// prime), a run of k zero words multiplying by prime^(8k); the check hash, the
+// weight and the non-zero-word mask; live-fault and non-zero-word counts per
+// compaction tile. One block = at most 256 positions of one boundary: it
+// lists the columns that cover the boundary (top leaf layer >= b >= the
+// column's lowest written boundary) in LDS with their slab and bitmap bases,
+// so the word loads carry no branches; the boundary's first chunk also
+// stores the list for the edge writer and counts the boundary's words.
+__global__ __launch_bounds__(kBlock) void k_hash(DevState st) {
+  __shared__ uint32_t s_w[kMaxHashWords];
+  __shared__ uint64_t s_base[kMaxHashWords];
+  __shared__ uint64_t s_bmb[kMaxHashWords];
+  __shared__ uint64_t s_pow[kMaxHashWords + 1];
   __shared__ uint32_t s_wave[kBlock / 64 + 1];
-  const uint32_t b = blockIdx.x;
-  uint32_t* dst = st.cov + size_t(b) * st.w;
+  const uint32_t b = st.hchunk_bnd[blockIdx.x];
+  const uint32_t p0 = st.hchunk_pos[blockIdx.x];
+  const uint32_t fb = st.bnd_fault_off[b];
+  const uint32_t p1 = min(p0 + uint32_t(kBlock), st.bnd_fault_off[b + 1]);
+  const uint32_t bmo = st.bnd_bm_off[b];
+  const bool first_chunk = p0 == fb;
   uint32_t n = 0;
   for (uint32_t w0 = 0; w0 < st.w; w0 += kBlock) {
     const uint32_t w = w0 + threadIdx.x;
@@ -575,41 +592,20 @@ __global__ __launch_bounds__(kBlock) void k_cover(DevState st) {
       f = (top >= 0 && int(b) <= top && int(b) >= st.cover_lo[w]) ? 1u : 0u;
     }
     const uint32_t at = block_exclusive_scan<kBlock>(f, s_wave);
-    if (f) dst[n + at] = w;
+    if (f) {
+      s_w[n + at] = w;
+      s_base[n + at] = st.col_base[w];
+      s_bmb[n + at] = st.col_bm_base[w] + bmo;
+      if (first_chunk) st.cov[size_t(b) * st.w + n + at] = w;
+    }
     n += s_wave[kBlock / 64];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
+  if (first_chunk && threadIdx.x == 0) {
     st.ncov[b] = n;
-    // signature words stage 1 wrote at this boundary (= words the hash reads)
-    const uint64_t words = uint64_t(n) * (st.bnd_fault_off[b + 1] - st.bnd_fault_off[b]);
+    // (fault, column) pairs of this boundary in the swept windows
+    const uint64_t words = uint64_t(n) * (st.bnd_fault_off[b + 1] - fb);
     if (words) atomicAdd(reinterpret_cast<unsigned long long*>(&st.hdr->n_words), (unsigned long long)words);
-  }
-}
-
-// ------------------------------------------------------------------ stage 2
-
-// FNV-1a over the 8W octets of each fault's signature (h <- (h ^ octet) *
-// prime), a run of k zero words multiplying by prime^(8k); the check hash, the
-// weight and the non-zero-word mask; live-fault counts per compaction tile.
-// One block = at most 256 positions of one boundary, so the boundary's cover
-// list and the prime powers sit in LDS and the word loads carry no branches.
-__global__ __launch_bounds__(kBlock) void k_hash(DevState st) {
-  __shared__ uint32_t s_w[kMaxHashWords];
-  __shared__ uint64_t s_base[kMaxHashWords];
-  __shared__ uint64_t s_bmb[kMaxHashWords];
-  __shared__ uint64_t s_pow[kMaxHashWords + 1];
-  const uint32_t b = st.hchunk_bnd[blockIdx.x];
-  const uint32_t p0 = st.hchunk_pos[blockIdx.x];
-  const uint32_t fb = st.bnd_fault_off[b];
-  const uint32_t p1 = min(p0 + uint32_t(kBlock), st.bnd_fault_off[b + 1]);
-  const uint32_t n = st.ncov[b];
-  const uint32_t bmo = st.bnd_bm_off[b];
-  for (uint32_t k = threadIdx.x; k < n; k += kBlock) {
-    const uint32_t w = st.cov[size_t(b) * st.w + k];
-    s_w[k] = w;
-    s_base[k] = st.col_base[w];
-    s_bmb[k] = st.col_bm_base[w] + bmo;
   }
   for (uint32_t k = threadIdx.x; k <= st.w; k += kBlock) s_pow[k] = st.fnv_pow[k];
   __syncthreads();
@@ -711,8 +707,8 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t m) {
 }
 
 // Stable compaction of the live faults (non-empty signatures) into (key,
-// position) pairs, with the digit counts of radix passes [p0, n_pass) for
-// this tile. Round k of the tile covers positions [k*1024, k*1024+1024):
+// position) pairs, adding this tile's digit counts of radix passes
+// [p0, n_pass) to the totals. Round k of the tile covers positions [k*1024, k*1024+1024):
 // consecutive lanes read consecutive positions and write consecutive
 // compacted slots.
 constexpr int kCompactBlock = 1024;
@@ -723,6 +719,7 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(DevState st, uint32_t
   constexpr int kWaves = kCompactBlock / 64;
   __shared__ uint32_t s_off[kCompactRounds * kWaves];  // per (round, wave): first slot in the tile
   __shared__ uint32_t s_hist[kMaxPasses][256];
+  __shared__ uint32_t s_red[kWaves];
   const uint32_t tile = blockIdx.x;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (uint32_t i = threadIdx.x; i < kMaxPasses * 256; i += kCompactBlock) (&s_hist[0][0])[i] = 0;
@@ -742,7 +739,19 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(DevState st, uint32_t
     s_off[threadIdx.x] = wave_inclusive_scan(v) - v;
   }
   __syncthreads();
-  const uint32_t tb = st.tile_cnt[tile];
+  // live faults before this tile (the hash counted them per tile); the last
+  // tile also records the total
+  uint32_t tb = 0;
+  {
+    uint32_t part = 0;
+    for (uint32_t t2 = threadIdx.x; t2 < tile; t2 += kCompactBlock) part += st.tile_cnt[t2];
+    part = wave_sum(part);
+    if (lane == 0) s_red[wv] = part;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) tb += s_red[k];
+    if (threadIdx.x == 0 && tile + 1 == gridDim.x) st.hdr->n_live = tb + st.tile_cnt[tile];
+  }
   const uint32_t P = st.n_pass;
   if (threadIdx.x == 0 && st.tile_nz[tile])
     atomicAdd(reinterpret_cast<unsigned long long*>(&st.hdr->n_nz_words), (unsigned long long)st.tile_nz[tile]);
@@ -760,27 +769,10 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(DevState st, uint32_t
     }
   }
   __syncthreads();
-  uint32_t* part = st.part_hist + size_t(tile) * kMaxPasses * 256;
+  // digit totals over all tiles
   for (uint32_t i = threadIdx.x; i < (P - p0) * 256; i += kCompactBlock) {
     const uint32_t p = p0 + i / 256, dg = i % 256;
-    part[p * 256 + dg] = s_hist[p][dg];
-  }
-}
-
-// Total count of digit d in pass p over all compaction tiles (block
-// (p - p0)*256 + d).
-__global__ __launch_bounds__(kBlock) void k_digit_totals(DevState st, uint32_t ntiles, uint32_t p0) {
-  __shared__ uint32_t s_red[kBlock / 64];
-  const uint32_t p = p0 + (blockIdx.x >> 8), d = blockIdx.x & 255u;
-  uint32_t tot = 0;
-  for (uint32_t t = threadIdx.x; t < ntiles; t += kBlock) tot += st.part_hist[(size_t(t) * kMaxPasses + p) * 256 + d];
-  tot = wave_sum(tot);
-  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = tot;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t a = 0;
-    for (int k = 0; k < kBlock / 64; ++k) a += s_red[k];
-    st.digit_tot[p * 256 + d] = a;
+    if (s_hist[p][dg]) atomicAdd(&st.digit_tot[p * 256 + dg], s_hist[p][dg]);
   }
 }
 
@@ -1405,56 +1397,51 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
   }
 }
 
-// Per-bucket class, bit and fault counts -> exclusive offsets (entry
-// kBuckets holds the totals); the header's class and bit totals.
-__global__ __launch_bounds__(kBuckets) void k_bucket_scan(DevState st) {
-  __shared__ uint32_t s_wave[kBuckets / 64 + 1];
-  const uint32_t t = threadIdx.x;
-  uint32_t* b_cls = st.bkt;
-  uint32_t* b_bits = st.bkt + (kBuckets + 1);
-  uint32_t* b_start = st.bkt + 2 * (kBuckets + 1);
-  const uint32_t nc = b_cls[t], nb = b_bits[t], nf = st.digit_tot[(st.n_pass - 1) * 256 + t];
-  const uint32_t oc = block_exclusive_scan<kBuckets>(nc, s_wave);
-  const uint32_t tc = s_wave[kBuckets / 64];
-  __syncthreads();
-  const uint32_t ob = block_exclusive_scan<kBuckets>(nb, s_wave);
-  const uint32_t tb = s_wave[kBuckets / 64];
-  __syncthreads();
-  const uint32_t of = block_exclusive_scan<kBuckets>(nf, s_wave);
-  const uint32_t tf = s_wave[kBuckets / 64];
-  b_cls[t] = oc;
-  b_bits[t] = ob;
-  b_start[t] = of;
-  if (t == 0) {
-    b_cls[kBuckets] = tc;
-    b_bits[kBuckets] = tb;
-    b_start[kBuckets] = tf;
-    st.hdr->n_seg = tc;
-    st.hdr->n_bits = tb;
-  }
-}
-
 // Hyperedge e = class s: bits in external numbering (detector d -> d,
 // observable k -> D + k) and its probability.
 // With kBuckets, class e lives at slot bucket_start + (e - bucket_class_offset)
 // and its bit offset is the bucket's plus the class's within the bucket.
 // The boundary fault offsets are searched in LDS when they fit.
+// With kBucketed every block turns the per-bucket class, bit and fault counts
+// into offsets itself (thread t: bucket t).
 template <bool kBucketed>
 __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
+  static_assert(kBlock == int(kBuckets), "one thread per bucket");
   __shared__ uint32_t s_cls[kBuckets + 1];
+  __shared__ uint32_t s_bit[kBuckets];
+  __shared__ uint32_t s_fst[kBuckets];
   __shared__ uint32_t s_bfo[kLofsMax];
+  __shared__ uint32_t s_wave[kBlock / 64];
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  const uint32_t S = st.hdr->n_seg;
+  uint32_t S;
+  uint64_t NB;
+  if (kBucketed) {
+    const uint32_t t = threadIdx.x;
+    uint32_t tc, tb, tf;
+    s_cls[t] = block_scan_1sync<kBlock>(st.bkt[t], s_wave, tc);
+    __syncthreads();
+    s_bit[t] = block_scan_1sync<kBlock>(st.bkt[kBuckets + 1 + t], s_wave, tb);
+    __syncthreads();
+    s_fst[t] = block_scan_1sync<kBlock>(st.digit_tot[(st.n_pass - 1) * 256 + t], s_wave, tf);
+    if (t == 0) s_cls[kBuckets] = tc;
+    S = tc;
+    NB = tb;
+  } else {
+    S = st.hdr->n_seg;
+    NB = st.hdr->n_bits;
+  }
   const bool bfo_lds = st.n_layers + 2 <= uint32_t(kLofsMax);
-  if (kBucketed)
-    for (uint32_t k = threadIdx.x; k <= kBuckets; k += blockDim.x) s_cls[k] = st.bkt[k];
   if (bfo_lds)
     for (uint32_t k = threadIdx.x; k < st.n_layers + 2; k += blockDim.x) s_bfo[k] = st.bnd_fault_off[k];
   __syncthreads();
   if (e == 0) {
     st.hdr->n_edges = S;
-    st.edge_off32[S] = uint32_t(st.hdr->n_bits);
-    if (st.hdr->n_bits > st.bits_cap) atomicOr(&st.hdr->flags, FLAG_OVERFLOW);
+    if (kBucketed) {
+      st.hdr->n_seg = S;
+      st.hdr->n_bits = NB;
+    }
+    st.edge_off32[S] = uint32_t(NB);
+    if (NB > st.bits_cap) atomicOr(&st.hdr->flags, FLAG_OVERFLOW);
   }
   if (e >= S) return;
   uint32_t s = e, o0;
@@ -1466,8 +1453,8 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
       if (s_cls[mid] <= e) lo = mid;
       else hi = mid;
     }
-    s = st.bkt[2 * (kBuckets + 1) + lo] + (e - s_cls[lo]);
-    o0 = st.bkt[(kBuckets + 1) + lo] + st.seg_off[s];
+    s = s_fst[lo] + (e - s_cls[lo]);
+    o0 = s_bit[lo] + st.seg_off[s];
   } else {
     o0 = st.seg_off[s];
   }
@@ -1511,11 +1498,9 @@ inline uint32_t cdiv(uint64_t a, uint64_t b) { return uint32_t((a + b - 1) / b);
 }  // namespace
 
 const char* kernel_name(int id) {
-  static const char* names[K_COUNT] = {"k_prepare",     "k_sweep",      "k_cover",      "k_hash",
-                                       "k_scan_single", "k_compact",    "k_digit_totals", "k_onesweep",
-                                       "k_heads_count", "k_heads_apply", "k_reduce",     "k_reduce_big",
-                                       "k_scan_tiles",  "k_scan_apply", "k_edge_write", "k_bucket",
-                                       "k_bucket_scan"};
+  static const char* names[K_COUNT] = {"k_prepare",    "k_sweep",       "k_hash",   "k_scan_single", "k_compact",
+                                       "k_onesweep",   "k_heads_count", "k_heads_apply", "k_reduce",  "k_reduce_big",
+                                       "k_scan_tiles", "k_scan_apply",  "k_edge_write",  "k_bucket"};
   return (id >= 0 && id < K_COUNT) ? names[id] : "?";
 }
 
@@ -1607,30 +1592,24 @@ hipError_t enqueue_compile(const DevState& st_in, hipStream_t stream, const Laun
       GP_LAUNCH(K_SWEEP, k_sweep<false><<<st.n_items, kSweepBlock, sweep_lds_bytes(st.n_qubits), stream>>>(st));
     }
   }
-  GP_LAUNCH(K_COVER, k_cover<<<st.n_layers + 1, kBlock, 0, stream>>>(st));
   if (n == 0) {
     GP_LAUNCH(K_EDGE_WRITE, k_edge_write<false><<<1, kBlock, 0, stream>>>(st));
     return hipSuccess;
   }
   GP_LAUNCH(K_HASH, k_hash<<<st.n_hchunks, kBlock, 0, stream>>>(st));
-  GP_LAUNCH(K_SCAN_SINGLE, k_scan_single<uint32_t><<<1, kScanSingleBlock, 0, stream>>>(st.tile_cnt, ntiles, nullptr,
-                                                                                      &st.hdr->n_live));
   // buckets: one stable pass on the top digit, then each bucket in LDS
   const bool bucketed = st.sort_mode == SORT_AUTO && st.key_mode == 0 && g_bucket_ok && n <= kBucketMaxFaults &&
                         st.n_pass >= 2 && st.n_pass <= 7;
   if (bucketed) {
     const uint32_t msd = st.n_pass - 1;
     GP_LAUNCH(K_COMPACT, k_compact<<<ntiles, kCompactBlock, 0, stream>>>(st, msd));
-    GP_LAUNCH(K_DIGIT_OFFSETS, k_digit_totals<<<256, kBlock, 0, stream>>>(st, ntiles, msd));
     GP_LAUNCH(K_ONESWEEP, k_onesweep<<<ntiles, kSortBlock, 0, stream>>>(st, msd, st.key[0], st.val[0], st.key[1],
                                                                      st.val[1]));
     GP_LAUNCH(K_BUCKET, k_bucket<<<kBuckets, kBucketBlock, kBucketDynLds, stream>>>(st, st.key[1], st.val[1]));
-    GP_LAUNCH(K_BUCKET_SCAN, k_bucket_scan<<<1, kBuckets, 0, stream>>>(st));
     GP_LAUNCH(K_EDGE_WRITE, k_edge_write<true><<<cdiv(n, kBlock), kBlock, 0, stream>>>(st));
     return hipSuccess;
   }
   GP_LAUNCH(K_COMPACT, k_compact<<<ntiles, kCompactBlock, 0, stream>>>(st, 0));
-  GP_LAUNCH(K_DIGIT_OFFSETS, k_digit_totals<<<st.n_pass * 256, kBlock, 0, stream>>>(st, ntiles, 0));
   for (uint32_t pass = 0; pass < st.n_pass; ++pass) {
     const int src = pass & 1, dst = src ^ 1;
     GP_LAUNCH(K_ONESWEEP, k_onesweep<<<ntiles, kSortBlock, 0, stream>>>(st, pass, st.key[src], st.val[src], st.key[dst],
