@@ -156,6 +156,8 @@ hipError_t enqueue_compile(const DevState& st, hipStream_t stream, const LaunchH
 
 // Dynamic LDS the sweep needs for n qubits, and the largest it may use.
 size_t sweep_lds_bytes(uint32_t n_qubits);
+// Dynamic LDS the hash needs for w signature words.
+size_t hash_lds_bytes(uint32_t w);
 // Whether the bucket grouping's LDS fits this device (set by configure_kernels).
 bool bucket_grouping_available();
 // Largest word-column count the hash kernel stages in LDS.

@@ -49,6 +49,7 @@ constexpr uint32_t kLbPre = 2u << 30;  // look-back status: inclusive prefix pub
 constexpr uint32_t kLbMask = (1u << 30) - 1;
 constexpr uint32_t kSpinLimit = 1u << 22;
 constexpr int kLookWin = 16;            // look-back: predecessor tiles read per round
+constexpr uint32_t kHashBmw = 5;        // bitmap words 256 consecutive positions span at most
 
 // Barrier that orders LDS only: global loads issued before it (prefetches)
 // stay in flight across it.
@@ -568,26 +569,33 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
 // weight and the non-zero-word mask; live-fault and non-zero-word counts per
 // compaction tile. One block = at most 256 positions of one boundary: it
 // lists the columns that cover the boundary (top leaf layer >= b >= the
-// column's lowest written boundary) in LDS with their slab and bitmap bases,
-// so the word loads carry no branches; the boundary's first chunk also
-// stores the list for the edge writer and counts the boundary's words.
+// column's lowest written boundary) in LDS with their slab bases and the
+// bitmap words its positions span; the boundary's first chunk also stores
+// the list for the edge writer and counts the boundary's words. Each thread
+// then loads only its fault's non-zero words, up to eight at once.
 __global__ __launch_bounds__(kBlock) void k_hash(DevState st) {
-  __shared__ uint32_t s_w[kMaxHashWords];
-  __shared__ uint64_t s_base[kMaxHashWords];
-  __shared__ uint64_t s_bmb[kMaxHashWords];
-  __shared__ uint64_t s_pow[kMaxHashWords + 1];
+  extern __shared__ __align__(16) uint64_t hlds[];
+  const uint32_t W = st.w;
+  uint64_t* s_pow = hlds;                  // W + 1
+  uint64_t* s_base = s_pow + W + 1;        // W: slab base of each covered column
+  uint64_t* s_bmb = s_base + W;            // W: bitmap base of each covered column at this boundary
+  uint64_t* s_bm = s_bmb + W;              // W * kHashBmw: the bitmap words this chunk spans
+  uint32_t* s_w = reinterpret_cast<uint32_t*>(s_bm + size_t(W) * kHashBmw);  // W: covered columns
   __shared__ uint32_t s_wave[kBlock / 64 + 1];
   const uint32_t b = st.hchunk_bnd[blockIdx.x];
   const uint32_t p0 = st.hchunk_pos[blockIdx.x];
   const uint32_t fb = st.bnd_fault_off[b];
   const uint32_t p1 = min(p0 + uint32_t(kBlock), st.bnd_fault_off[b + 1]);
   const uint32_t bmo = st.bnd_bm_off[b];
+  const uint32_t nwb = st.bnd_bm_off[b + 1] - bmo;  // bitmap words of this boundary
+  const uint32_t wb0 = (p0 - fb) >> 6;              // first of them this chunk touches
   const bool first_chunk = p0 == fb;
+  for (uint32_t k = threadIdx.x; k <= W; k += kBlock) s_pow[k] = st.fnv_pow[k];
   uint32_t n = 0;
-  for (uint32_t w0 = 0; w0 < st.w; w0 += kBlock) {
+  for (uint32_t w0 = 0; w0 < W; w0 += kBlock) {
     const uint32_t w = w0 + threadIdx.x;
     uint32_t f = 0;
-    if (w < st.w) {
+    if (w < W) {
       const int top = st.col_top[w];
       f = (top >= 0 && int(b) <= top && int(b) >= st.cover_lo[w]) ? 1u : 0u;
     }
@@ -596,7 +604,7 @@ __global__ __launch_bounds__(kBlock) void k_hash(DevState st) {
       s_w[n + at] = w;
       s_base[n + at] = st.col_base[w];
       s_bmb[n + at] = st.col_bm_base[w] + bmo;
-      if (first_chunk) st.cov[size_t(b) * st.w + n + at] = w;
+      if (first_chunk) st.cov[size_t(b) * W + n + at] = w;
     }
     n += s_wave[kBlock / 64];
     __syncthreads();
@@ -607,33 +615,41 @@ __global__ __launch_bounds__(kBlock) void k_hash(DevState st) {
     const uint64_t words = uint64_t(n) * (st.bnd_fault_off[b + 1] - fb);
     if (words) atomicAdd(reinterpret_cast<unsigned long long*>(&st.hdr->n_words), (unsigned long long)words);
   }
-  for (uint32_t k = threadIdx.x; k <= st.w; k += kBlock) s_pow[k] = st.fnv_pow[k];
+  for (uint32_t i = threadIdx.x; i < n * kHashBmw; i += kBlock) {
+    const uint32_t k = i / kHashBmw, j = i % kHashBmw;
+    s_bm[i] = wb0 + j < nwb ? st.bm[s_bmb[k] + wb0 + j] : 0ull;
+  }
   __syncthreads();
   const uint32_t pos = p0 + threadIdx.x;
   const bool valid = pos < p1;
-  const uint32_t lpos = valid ? pos : p0;  // lanes past the chunk read a valid bitmap word and drop it
-  const uint32_t ib = lpos - fb;           // index within the boundary: bit ib of bitmap word ib / 64
+  const uint32_t ib = (valid ? pos : p0) - fb;  // bit ib & 63 of bitmap word ib / 64 of the boundary
+  const uint32_t wj = (ib >> 6) - wb0, bit = ib & 63;
   uint64_t h1 = kFnvOffset, h2 = 0, mask = 0;
   uint32_t wn = 0, weight = 0, nzw = 0;
-  for (uint32_t k0 = 0; k0 < n; k0 += 8) {
-    // which of the next eight covered words are non-zero, then only those words
-    uint64_t mw[8];
+  for (uint32_t seg = 0; seg < n; seg += 64) {
+    // this fault's non-zero words among covered columns seg .. seg + 63
+    const uint32_t cnt = min(64u, n - seg);
+    uint64_t msk = 0;
+    for (uint32_t q = 0; q < cnt; ++q) msk |= ((s_bm[(seg + q) * kHashBmw + wj] >> bit) & 1ull) << q;
+    if (!valid) msk = 0;
+    if (seg == 0) mask = msk;
+    while (msk) {
+      uint32_t kk[8];
+      bool on[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const uint32_t k = min(k0 + j, n - 1);
-      mw[j] = st.bm[s_bmb[k] + (ib >> 6)];
-    }
-    uint64_t vv[8];
+      for (int j = 0; j < 8; ++j) {
+        on[j] = msk != 0;
+        kk[j] = on[j] ? seg + uint32_t(__builtin_ctzll(msk)) : 0u;
+        msk &= msk - 1;
+      }
+      uint64_t vv[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const bool nz = valid && k0 + j < n && ((mw[j] >> (ib & 63)) & 1ull);
-      vv[j] = nz ? st.slab[s_base[k0 + j] + lpos] : 0ull;
-    }
+      for (int j = 0; j < 8; ++j) vv[j] = on[j] ? st.slab[s_base[kk[j]] + pos] : 0ull;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const uint64_t v = vv[j];
-      if (v) {
-        const uint32_t w = s_w[k0 + j];
+      for (int j = 0; j < 8; ++j) {
+        if (!on[j]) continue;
+        const uint64_t v = vv[j];
+        const uint32_t w = s_w[kk[j]];
         h1 *= s_pow[w - wn];
 #pragma unroll
         for (int o = 0; o < 8; ++o) h1 = (h1 ^ ((v >> (8 * o)) & 0xffu)) * kFnvPrime;
@@ -641,7 +657,6 @@ __global__ __launch_bounds__(kBlock) void k_hash(DevState st) {
         nzw++;
         h2 += check_term(w, v);
         weight += __popcll(v);
-        if (k0 + j < 64) mask |= 1ull << (k0 + j);
       }
     }
   }
@@ -1513,6 +1528,8 @@ uint32_t sort_passes(uint64_t n) {
   return p > uint32_t(kMaxPasses) ? uint32_t(kMaxPasses) : p;
 }
 
+size_t hash_lds_bytes(uint32_t w) { return (size_t(w) + 1) * 8 + size_t(w) * (8 + 8 + 8 * kHashBmw + 4); }
+
 size_t sweep_lds_bytes(uint32_t n_qubits) {
   return (size_t(5) * n_qubits + kInjLds) * sizeof(uint64_t) +
          (size_t(2) * kWinOps + 3 * kLofsMax + 2 + 3 * kInjLds) * sizeof(uint32_t);
@@ -1546,6 +1563,10 @@ hipError_t configure_kernels() {
     }
   }
   g_lds_limit = lim;
+  // the hash stages its cover list and bitmap words (at most kMaxHashWords columns)
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_hash), hipFuncAttributeMaxDynamicSharedMemorySize,
+                          int(hash_lds_bytes(kMaxHashWords))) != hipSuccess)
+    (void)hipGetLastError();
   // the bucket grouping needs its two sort buffers next to its static arrays
   g_bucket_ok = false;
   hipFuncAttributes fa{};
@@ -1596,7 +1617,7 @@ hipError_t enqueue_compile(const DevState& st_in, hipStream_t stream, const Laun
     GP_LAUNCH(K_EDGE_WRITE, k_edge_write<false><<<1, kBlock, 0, stream>>>(st));
     return hipSuccess;
   }
-  GP_LAUNCH(K_HASH, k_hash<<<st.n_hchunks, kBlock, 0, stream>>>(st));
+  GP_LAUNCH(K_HASH, k_hash<<<st.n_hchunks, kBlock, hash_lds_bytes(st.w), stream>>>(st));
   // buckets: one stable pass on the top digit, then each bucket in LDS
   const bool bucketed = st.sort_mode == SORT_AUTO && st.key_mode == 0 && g_bucket_ok && n <= kBucketMaxFaults &&
                         st.n_pass >= 2 && st.n_pass <= 7;
