@@ -40,6 +40,7 @@ constexpr int kEmitPre = 8;            // fault records per thread fetched durin
 constexpr int kPre = kWinOps / kSweepBlock;
 constexpr int kLofsMax = 2048;         // layer offsets staged in LDS when the circuit has fewer layers
 constexpr int kInjLds = 512;           // a column's injections staged in LDS when it has at most this many
+constexpr int kWinTableLds = 512;      // op windows whose table is staged in LDS
 constexpr int kBlock = 256;
 constexpr int kPerThread = kTile / kBlock;
 constexpr int kScanSingleBlock = 1024;
@@ -319,7 +320,7 @@ __device__ __forceinline__ int wave_total(int v) {
 // which words are non-zero.
 // The count of non-zero frame words (for the early exit) is kept per wave as
 // a running sum and published in per-wave LDS slots (two sets, alternating).
-constexpr int kCountEvery = 4;
+constexpr int kCountEvery = 8;
 
 template <bool kStaged>
 __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
@@ -338,6 +339,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   uint32_t* sinj_l = sbmo + kLofsMax + 1;
   uint32_t* sinj_q = sinj_l + kInjLds;
   uint32_t* sinj_n = sinj_q + kInjLds;
+  uint32_t* swin = sinj_n + kInjLds;  // per op window: lowest layer, first op, op count
 
   const uint32_t item = blockIdx.x;
   if (tid == 0) st.item_clock[2 * item] = wall_clock64();
@@ -370,6 +372,17 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
       sinj_q[k] = st.inj_qubit[i0 + k];
       sinj_n[k] = st.inj_next[i0 + k];
     }
+  // the window table sits in LDS (kStaged): reading it from global memory with
+  // scalar loads would make the next LDS wait also wait for them
+  if (lofs_lds)
+    for (uint32_t k = tid; k < st.n_win; k += kSweepBlock) {
+      swin[3 * k] = st.win_lo[k];
+      swin[3 * k + 1] = st.win_obase[k];
+      swin[3 * k + 2] = st.win_cnt[k];
+    }
+  auto WLO = [&](int k) -> uint32_t { return lofs_lds ? swin[3 * k] : st.win_lo[k]; };
+  auto WOB = [&](int k) -> uint32_t { return lofs_lds ? swin[3 * k + 1] : st.win_obase[k]; };
+  auto WCN = [&](int k) -> uint32_t { return lofs_lds ? swin[3 * k + 2] : st.win_cnt[k]; };
   // the op window holding the top layer, loaded directly
   int wid = int(st.layer_win[top]);
   uint32_t o_base = st.win_obase[wid];
@@ -406,8 +419,8 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   uint32_t nbase = 0;
   auto prefetch = [&]() {
     const bool need = wlo - 1 >= blo;
-    const uint32_t cnt = need ? st.win_cnt[wid + 1] : 0u;
-    nbase = need ? st.win_obase[wid + 1] : 0u;
+    const uint32_t cnt = need ? WCN(wid + 1) : 0u;
+    nbase = need ? WOB(wid + 1) : 0u;
 #pragma unroll
     for (int k = 0; k < kPre; ++k) {
       const uint32_t i = tid + k * kSweepBlock;
@@ -447,7 +460,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
     if (t == wlo && t - 1 >= blo) {
       // the prefetched window becomes current (the other buffer is no longer
       // read), and the window after it is fetched into registers
-      const uint32_t cnt = st.win_cnt[wid + 1];
+      const uint32_t cnt = WCN(wid + 1);
       uint32_t* nb = opbuf + (cur ^ 1) * kWinOps;
 #pragma unroll
       for (int k = 0; k < kPre; ++k) {
@@ -457,7 +470,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
       cur ^= 1;
       wid++;
       o_base = nbase;
-      wlo = int(st.win_lo[wid]);
+      wlo = int(WLO(wid));
       prefetch();
     }
   };
@@ -1532,7 +1545,7 @@ size_t hash_lds_bytes(uint32_t w) { return (size_t(w) + 1) * 8 + size_t(w) * (8 
 
 size_t sweep_lds_bytes(uint32_t n_qubits) {
   return (size_t(5) * n_qubits + kInjLds) * sizeof(uint64_t) +
-         (size_t(2) * kWinOps + 3 * kLofsMax + 2 + 3 * kInjLds) * sizeof(uint32_t);
+         (size_t(2) * kWinOps + 3 * kLofsMax + 2 + 3 * kInjLds + 3 * kWinTableLds) * sizeof(uint32_t);
 }
 
 static size_t g_lds_limit = 64 * 1024;
@@ -1607,7 +1620,8 @@ hipError_t enqueue_compile(const DevState& st_in, hipStream_t stream, const Laun
     GP_LAUNCH(K_PREPARE, k_prepare<<<g, kBlock, 0, stream>>>(st));
   }
   if (st.n_items) {
-    if (st.n_layers + 2 <= uint32_t(kLofsMax) && st.max_col_inj <= uint32_t(kInjLds)) {
+    if (st.n_layers + 2 <= uint32_t(kLofsMax) && st.max_col_inj <= uint32_t(kInjLds) &&
+        st.n_win <= uint32_t(kWinTableLds)) {
       GP_LAUNCH(K_SWEEP, k_sweep<true><<<st.n_items, kSweepBlock, sweep_lds_bytes(st.n_qubits), stream>>>(st));
     } else {
       GP_LAUNCH(K_SWEEP, k_sweep<false><<<st.n_items, kSweepBlock, sweep_lds_bytes(st.n_qubits), stream>>>(st));

@@ -394,7 +394,7 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
     // from the top, so the lowest ranges get few boundaries and the upper
     // ones many: the smallest makespan T that the greedy cut from the
     // bottom fits into per_obs ranges is found by bisection.
-    constexpr double kLayerCost = 1.0, kFaultCost = 5.2e-4;
+    constexpr double kLayerCost = 1.0, kFaultCost = 6.2e-4;
     for (uint32_t w = lw.wd; w < lw.w; w++) {
       const int32_t top = lw.col_top[w];
       if (top < 0) continue;
