@@ -132,6 +132,29 @@ int gp_lower(gp_driver* drv, const char* text, size_t len, const double* rates, 
 int gp_run(gp_driver* drv);
 int gp_fetch(gp_driver* drv, gp_edges** out);
 
+/* Fixed structure, new rates (Eq. 3 over cached classes). After a gp_fetch,
+ * the driver keeps each hyperedge's member faults (in fault order) on the
+ * device. gp_refresh_rates replaces the channel rates (`rates`: host,
+ * n_rates = channel count, program order, each within its channel's range)
+ * and enqueues the per-fault probabilities and the merge of every hyperedge
+ * again -- no stage-1 sweep, no grouping; the next gp_fetch returns the same
+ * hyperedges in the same order with the new probabilities (bitwise what a full
+ * compile gives, except classes of more than 65 faults compiled by the full
+ * radix sort, which agree to rounding). GP_E_STATE if no fetched compile of
+ * the lowered circuit exists; GP_E_NOISE for a bad rate array (the previous
+ * rates stay). */
+int gp_refresh_rates(gp_driver* drv, const double* rates, size_t n_rates);
+
+/* Adjoint of stage 2 for the current rates (those of the last compile or
+ * refresh). Input dl_dq: host, one dL/dq per hyperedge in the order of the
+ * last gp_fetch. Output dl_dr: host, one dL/d(rate) per channel in program
+ * order. With q_k = 1/2 (1 - prod_{i in k} (1 - 2 p_i)) (Eq. 3 unrolled),
+ * dq_k/dp_i = prod_{j in k, j != i} (1 - 2 p_j); dp_i/dr is the derivative of
+ * the per-fault split of the fault's channel; faults with an empty signature
+ * contribute nothing. Synchronous. GP_E_STATE without a fetched compile,
+ * GP_E_ARG for wrong lengths. */
+int gp_rates_gradient(gp_driver* drv, const double* dl_dq, size_t n_edges, double* dl_dr, size_t n_rates);
+
 /* Wait for every operation enqueued on the driver's stream. */
 int gp_sync(gp_driver* drv);
 

@@ -75,6 +75,10 @@ def _load():
         lib.oracle_last_error.restype = ctypes.c_char_p
         lib.oracle_fault_probability.argtypes = [ctypes.c_int, ctypes.c_double]
         lib.oracle_fault_probability.restype = ctypes.c_double
+        lib.oracle_gradient.argtypes = [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.c_int64,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.c_int64]
+        lib.oracle_gradient.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -168,6 +172,35 @@ def run(text: str, rates: Optional[Sequence[float]] = None, keep_faults: bool = 
     finally:
         lib.oracle_free(out)
     return res
+
+
+def gradient(text: str, dl_dq: Sequence[float], rates: Optional[Sequence[float]] = None) -> np.ndarray:
+    """dL/d(rate) per channel (program order) given dL/dq per hyperedge in the
+    order `run` returns the hyperedges (explicit products over each class's
+    other members, chain rule through the per-fault split)."""
+    lib = _load()
+    raw = text.encode()
+    g = np.ascontiguousarray(dl_dq, dtype=np.float64)
+    if rates is not None:
+        r = np.ascontiguousarray(rates, dtype=np.float64)
+        rp, nr = r.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(r)
+        nch = nr
+    else:
+        rp, nr = None, 0
+        nch = run(text).n_channels
+    out = np.zeros(nch, dtype=np.float64)
+    rc = lib.oracle_gradient(raw, len(raw), rp, nr, g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(g),
+                             out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nch)
+    if rc != 0:
+        raise OracleError(rc, lib.oracle_last_error().decode())
+    return out
+
+
+def loss_and_dl_dq(q: np.ndarray, w: np.ndarray):
+    """The differentiation workload's loss L = sum_k w_k log(q_k / (1 - q_k))
+    and its derivative w_k / (q_k (1 - q_k))."""
+    q = np.asarray(q, dtype=np.float64)
+    return float(np.sum(w * np.log(q / (1.0 - q)))), w / (q * (1.0 - q))
 
 
 def fault_probability(kind: str, rate: float) -> float:

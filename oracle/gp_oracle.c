@@ -798,6 +798,89 @@ fin:
   return ORC_OK;
 }
 
+/* --------------------------------------------------------------- gradient */
+
+/* Derivative of the per-fault probability with respect to the channel rate,
+ * from the split above: (1-2p)^k = 1 - x with x = a r gives
+ * dp/dr = (a / (2k)) (1 - x)^(1/k - 1): DEPOLARIZE1 (k = 2, a = 4/3):
+ * (1/3)(1 - 4r/3)^(-1/2); DEPOLARIZE2 (k = 8, a = 16/15):
+ * (1/15)(1 - 16r/15)^(-7/8); a Pauli flip channel: 1. */
+static double fault_dp_dr(int kind, double r) {
+  switch (kind) {
+    case N_DEP1: return (1.0 / 3.0) / sqrt(1.0 - 4.0 * r / 3.0);
+    case N_DEP2: return (1.0 / 15.0) * pow(1.0 - 16.0 * r / 15.0, -7.0 / 8.0);
+    default: return 1.0;
+  }
+}
+
+/*
+ * oracle_gradient: dL/d(rate) of every channel (program order) for a loss
+ * whose derivative with respect to each hyperedge probability is given:
+ * dl_dq[e] for the hyperedges in the order oracle_run returns them. With
+ * q = 1/2 (1 - prod_j (1 - 2 p_j)) over the class members (Eq. 3 unrolled),
+ * dq/dp_i = prod_{j != i} (1 - 2 p_j), evaluated here as that explicit
+ * product; the chain rule then goes through dp_i/dr of the fault's channel.
+ * Faults with an empty signature do not contribute.
+ */
+int oracle_gradient(const char *text, size_t len, const double *rates, int64_t n_rates, const double *dl_dq,
+                    int64_t n_edges, double *dl_dr, int64_t n_out) {
+  oracle_result *r = NULL;
+  int rc = oracle_run(text, len, rates, n_rates, 1, 1, &r);
+  if (rc) return rc;
+  if (n_edges != r->n_edges) {
+    int64_t ne = r->n_edges;
+    oracle_free(r);
+    return fail(ORC_E_ARG, "dl_dq has %lld entries, the hypergraph has %lld edges", (long long)n_edges,
+                (long long)ne);
+  }
+  if (n_out != r->n_channels) {
+    int64_t nc = r->n_channels;
+    oracle_free(r);
+    return fail(ORC_E_ARG, "dl_dr has %lld entries, the circuit has %lld channels", (long long)n_out, (long long)nc);
+  }
+  /* the channels' kinds and rates, as the forward pass used them */
+  circ_t c;
+  memset(&c, 0, sizeof c);
+  if ((rc = parse(text, len, &c))) { oracle_free(r); circ_free(&c); return rc; }
+  if (rates)
+    for (int64_t k = 0; k < c.nch; k++) c.ch[k].rate = rates[k];
+  for (int64_t k = 0; k < n_out; k++) dl_dr[k] = 0.0;
+  const int64_t nf = r->n_faults;
+  int64_t *ord = (int64_t *)malloc((size_t)(nf ? nf : 1) * sizeof(int64_t));
+  if (!ord) { oracle_free(r); circ_free(&c); return fail(ORC_E_OOM, "out of memory"); }
+  for (int64_t i = 0; i < nf; i++) ord[i] = i;
+  sigctx_t g = {r->fault_off, r->fault_bits};
+  qsort_r(ord, (size_t)nf, sizeof(int64_t), cmp_fault, &g);
+  /* walk the classes in the order oracle_run emitted them */
+  int64_t e = 0, i = 0;
+  while (i < nf) {
+    int64_t j = i + 1;
+    const int64_t li = r->fault_off[ord[i] + 1] - r->fault_off[ord[i]];
+    while (j < nf) {
+      const int64_t lj = r->fault_off[ord[j] + 1] - r->fault_off[ord[j]];
+      if (lj != li || memcmp(r->fault_bits + r->fault_off[ord[i]], r->fault_bits + r->fault_off[ord[j]],
+                             (size_t)li * sizeof(int32_t)))
+        break;
+      j++;
+    }
+    if (li != 0) {
+      for (int64_t a = i; a < j; a++) {
+        double prod = 1.0;
+        for (int64_t b = i; b < j; b++)
+          if (b != a) prod *= 1.0 - 2.0 * r->fault_p[ord[b]];
+        const int32_t ch = r->fault_channel[ord[a]];
+        dl_dr[ch] += dl_dq[e] * prod * fault_dp_dr(c.ch[ch].kind, c.ch[ch].rate);
+      }
+      e++;
+    }
+    i = j;
+  }
+  free(ord);
+  oracle_free(r);
+  circ_free(&c);
+  return ORC_OK;
+}
+
 /* Per-fault probability for a channel kind name, exposed so tests can pin the
  * split against closed forms. kind: 1 X_ERROR, 2 Y_ERROR, 3 Z_ERROR,
  * 4 DEPOLARIZE1, 5 DEPOLARIZE2. */

@@ -29,7 +29,7 @@ EXPORTS = (
     "gp_timing_entry", "gp_edges_count", "gp_edges_detectors", "gp_edges_observables",
     "gp_edges_offsets", "gp_edges_bits", "gp_edges_probabilities", "gp_edges_to_dem_text",
     "gp_edges_free", "gp_free", "gp_debug_set_key_bits", "gp_debug_collision_retries",
-    "gp_debug_sweep_times", "gp_debug_set_sort_mode",
+    "gp_debug_sweep_times", "gp_debug_set_sort_mode", "gp_refresh_rates", "gp_rates_gradient",
 )
 
 
@@ -118,6 +118,9 @@ def load():
         "gp_debug_set_key_bits": ([_vp, ctypes.c_int], ctypes.c_int),
         "gp_debug_collision_retries": ([_vp], _u64),
         "gp_debug_set_sort_mode": ([_vp, ctypes.c_int], ctypes.c_int),
+        "gp_refresh_rates": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t], ctypes.c_int),
+        "gp_rates_gradient": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t,
+                               ctypes.POINTER(ctypes.c_double), ctypes.c_size_t], ctypes.c_int),
         "gp_debug_sweep_times": ([_vp, ctypes.POINTER(_u64), _u64, ctypes.POINTER(_u64),
                                   ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     }
@@ -277,6 +280,19 @@ def gp_edges_free(e: int) -> None:
 
 def gp_debug_set_key_bits(drv: int, bits: int) -> None:
     _check(load().gp_debug_set_key_bits(drv, bits))
+
+
+def gp_refresh_rates(drv: int, rates: Sequence[float]) -> None:
+    r = np.ascontiguousarray(rates, dtype=np.float64)
+    _check(load().gp_refresh_rates(drv, r.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(r)))
+
+
+def gp_rates_gradient(drv: int, dl_dq: Sequence[float], n_rates: int) -> np.ndarray:
+    g = np.ascontiguousarray(dl_dq, dtype=np.float64)
+    out = np.zeros(n_rates, dtype=np.float64)
+    _check(load().gp_rates_gradient(drv, g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(g),
+                                    out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n_rates))
+    return out
 
 
 def gp_debug_set_sort_mode(drv: int, mode: int) -> None:

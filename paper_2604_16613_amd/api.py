@@ -105,6 +105,18 @@ class Driver:
     def info(self) -> dict:
         return _gp.gp_circuit_info_get(self.handle).as_dict()
 
+    # fixed structure: new rates, and the adjoint of stage 2
+    def refresh_rates(self, rates: Sequence[float]) -> Hypergraph:
+        """Same hyperedges (same order) as the last fetched compile, with the
+        probabilities for `rates` (per channel, program order)."""
+        _gp.gp_refresh_rates(self.handle, rates)
+        return self.fetch()
+
+    def rates_gradient(self, dl_dq: Sequence[float]) -> np.ndarray:
+        """dL/d(rate) per channel (program order) from dL/dq per hyperedge
+        (order of the last fetch), at the current rates."""
+        return _gp.gp_rates_gradient(self.handle, dl_dq, int(self.info()["n_channels"]))
+
     def set_timing(self, enable: bool) -> None:
         _gp.gp_set_timing(self.handle, enable)
 

@@ -125,6 +125,8 @@ struct gp_driver {
   gp::Lowered lw;
   bool lowered = false;
   bool ran = false;
+  bool structured = false;     // a fetched compile left its class structure on the device
+  uint64_t struct_edges = 0;   // hyperedges of that compile
   gp::DevState st{};
 
   uint32_t key_bits = 64;      // test hook: class keys cut to this many bits
@@ -350,6 +352,13 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   if ((rc = dev_alloc(d, &st.segstart, F, "class starts"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.big, F / 64 + 1, "large classes"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.bkt, 2 * size_t(gp::kBuckets + 1), "bucket counts"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.seg_first, F, "class member offsets"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.seg_mem, F, "class member counts"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.e_first, F, "hyperedge member offsets"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.e_cnt, F, "hyperedge member counts"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.gfault, F, "fault gradients"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.gq, F, "hyperedge gradients"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.gr, std::max<uint64_t>(b.max_channels, 1), "channel gradients"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.seg_q, F, "class probabilities"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.seg_rep, F, "class representatives"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.seg_cnt, F, "class bit counts"))) return cleanup(rc);
@@ -380,6 +389,7 @@ int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, si
   gp::LowerError err{};
   d->lowered = false;
   d->ran = false;
+  d->structured = false;
   int rc = gp::lower_circuit(text, len, rates, n_rates, gp::kSweepSlots, d->lw, err);
   if (rc) return fail(rc, err.msg);
   if ((rc = check_bounds(d, d->lw))) return rc;
@@ -492,6 +502,7 @@ int gp_run(gp_driver* d) {
   d->st.key_mode = 0;
   d->st.key_bits = d->key_bits;
   d->st.sort_mode = d->sort_mode;
+  d->structured = false;
   hipError_t e = gp::enqueue_compile(d->st, d->stream, hook);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   d->ran = true;
@@ -569,6 +580,54 @@ int gp_fetch(gp_driver* d, gp_edges** out) {
   e->bits.assign(reinterpret_cast<const uint32_t*>(h + o_bits), reinterpret_cast<const uint32_t*>(h + o_bits) + nb);
   e->q.assign(reinterpret_cast<const double*>(h + o_q), reinterpret_cast<const double*>(h + o_q) + U);
   *out = e;
+  d->structured = true;
+  d->struct_edges = U;
+  return GP_OK;
+}
+
+int gp_refresh_rates(gp_driver* d, const double* rates, size_t n_rates) {
+  if (!d || !rates) return fail(GP_E_ARG, "null argument");
+  if (!d->structured) return fail(GP_E_STATE, "gp_refresh_rates before a fetched compile of this circuit");
+  HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
+  // the pinned table buffer may still be read by an earlier upload
+  HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
+  gp::Lowered& lw = d->lw;
+  const std::vector<double> old = lw.chan_rate;
+  gp::LowerError err{};
+  int rc = gp::apply_rates(lw, rates, n_rates, err);
+  if (rc) {
+    lw.chan_rate = old;
+    return fail(rc, err.msg);
+  }
+  TableLayout tl = layout_for(lw.ops.size(), lw.n_layers, lw.n_meas, lw.leaf_bits.size(), lw.chan_kind.size(), lw.w,
+                              lw.item_col.size(), lw.hchunk_pos.size());
+  const size_t bytes = lw.chan_rate.size() * 8;
+  if (bytes) {
+    std::memcpy(d->h_tables + tl.chan_rate, lw.chan_rate.data(), bytes);
+    HIP_TRY(hipMemcpyAsync(d->d_tables + tl.chan_rate, d->h_tables + tl.chan_rate, bytes, hipMemcpyHostToDevice,
+                           d->stream),
+            "upload rates");
+  }
+  HIP_TRY(gp::enqueue_refresh(d->st, uint32_t(d->struct_edges), d->stream), "kernel launch");
+  return GP_OK;
+}
+
+int gp_rates_gradient(gp_driver* d, const double* dl_dq, size_t n_edges, double* dl_dr, size_t n_rates) {
+  if (!d || (!dl_dq && n_edges) || (!dl_dr && n_rates)) return fail(GP_E_ARG, "null argument");
+  if (!d->structured) return fail(GP_E_STATE, "gp_rates_gradient before a fetched compile of this circuit");
+  if (n_edges != d->struct_edges) return fail(GP_E_ARG, "dl_dq length differs from the hyperedge count");
+  const gp::Lowered& lw = d->lw;
+  const size_t C = lw.chan_kind.size();
+  if (n_rates != C) return fail(GP_E_ARG, "dl_dr length differs from the channel count");
+  HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
+  if (n_edges)
+    HIP_TRY(hipMemcpyAsync(d->st.gq, dl_dq, n_edges * 8, hipMemcpyHostToDevice, d->stream), "upload dL/dq");
+  HIP_TRY(gp::enqueue_rates_gradient(d->st, uint32_t(n_edges), d->stream), "kernel launch");
+  std::vector<double> g(C);
+  if (C) HIP_TRY(hipMemcpyAsync(g.data(), d->st.gr, C * 8, hipMemcpyDeviceToHost, d->stream), "download dL/dr");
+  HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
+  // lowered channel order -> program order
+  for (size_t c = 0; c < C; c++) dl_dr[lw.chan_src[c]] = g[c];
   return GP_OK;
 }
 

@@ -121,6 +121,15 @@ struct DevState {
   uint32_t* segstart;    // first sorted index of each class
   uint32_t* big;         // classes too large for one thread
   uint32_t* bkt;         // per bucket: classes, then signature bits (kBuckets + 1 each)
+  // the class structure a compile leaves for rate refreshes and the adjoint:
+  uint32_t* ord;         // fault positions, classes contiguous, members in position order (set by enqueue_compile)
+  uint32_t* seg_first;   // per class slot (bucket grouping): first index into ord, member count
+  uint32_t* seg_mem;
+  uint32_t* e_first;     // per hyperedge: first index into ord, member count
+  uint32_t* e_cnt;
+  double* gfault;        // per fault position: dL/dp (adjoint)
+  double* gq;            // per hyperedge: dL/dq (adjoint input)
+  double* gr;            // per channel (lowered order): dL/d(rate) (adjoint output)
   double* seg_q;         // merged probability per class
   uint32_t* seg_rep;     // representative fault position per class
   uint32_t* seg_cnt;     // signature bits per class
@@ -151,8 +160,18 @@ struct LaunchHook {
 // share them with probability below about 2^-12 (collisions are still caught).
 uint32_t sort_passes(uint64_t n);
 
-// Enqueue both stages for the lowered circuit described by `st`.
-hipError_t enqueue_compile(const DevState& st, hipStream_t stream, const LaunchHook& hook);
+// Enqueue both stages for the lowered circuit described by `st`; st.ord is
+// set to the buffer that then holds the class members.
+hipError_t enqueue_compile(DevState& st, hipStream_t stream, const LaunchHook& hook);
+
+// After a compile (and its fetch): per-fault probabilities from the channel
+// rates now in the tables, then every hyperedge re-merged over the cached
+// members with the compile's merge shape; n_edges hyperedges.
+hipError_t enqueue_refresh(const DevState& st, uint32_t n_edges, hipStream_t stream);
+
+// Adjoint of stage 2: with dL/dq per hyperedge in st.gq, dL/d(rate) per
+// channel (lowered order) into st.gr.
+hipError_t enqueue_rates_gradient(const DevState& st, uint32_t n_edges, hipStream_t stream);
 
 // Dynamic LDS the sweep needs for n qubits, and the largest it may use.
 size_t sweep_lds_bytes(uint32_t n_qubits);

@@ -1329,7 +1329,10 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
   FaultRec rec[kBucketCap / kBucketBlock];
 #pragma unroll
   for (int k = 0; k < int(kBucketCap / kBucketBlock); ++k)
-    if (uint32_t(k) < per && j0 + k < m) rec[k] = st.frp[pos[k]];
+    if (uint32_t(k) < per && j0 + k < m) {
+      rec[k] = st.frp[pos[k]];
+      st.val[0][start + j0 + k] = pos[k];  // the class members, kept for refreshes and the adjoint
+    }
   const uint32_t nh = uint32_t(__popc(hmask));
   uint32_t c = block_exclusive_scan<kBucketBlock>(nh, s_wave);  // barrier: every a[j] has been read
   const uint32_t ncls = s_wave[kBucketWaves];
@@ -1365,12 +1368,14 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
       bad |= sc[i] != c0;
       q = fma(sp[i], 1.0 - 2.0 * q, q);  // Eq. 3: q(1-p) + p(1-q)
     }
+    st.seg_first[start + cls] = start + j;
     if (i < m && i - j > kBigSegment && !head_at(i)) {
       const uint32_t g = atomicAdd(&s_nbig, 1u);
       s_big[2 * g] = cls;
       s_big[2 * g + 1] = j;
     } else {
       st.seg_q[start + cls] = q;
+      st.seg_mem[start + cls] = i - j;
       if (bad) s_bad = 1;
     }
   }
@@ -1415,7 +1420,10 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
       }
       __syncthreads();
     }
-    if (tid == 0) st.seg_q[start + cls] = s_q[0];
+    if (tid == 0) {
+      st.seg_q[start + cls] = s_q[0];
+      st.seg_mem[start + cls] = e - j;
+    }
     __syncthreads();
   }
   if (tid == 0) {
@@ -1488,6 +1496,13 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
   }
   st.edge_off32[e] = o0;
   st.edge_q[e] = st.seg_q[s];
+  if (kBucketed) {
+    st.e_first[e] = st.seg_first[s];
+    st.e_cnt[e] = st.seg_mem[s];
+  } else {
+    st.e_first[e] = st.segstart[e];
+    st.e_cnt[e] = (e + 1 < S ? st.segstart[e + 1] : st.hdr->n_live) - st.segstart[e];
+  }
   const uint32_t pos = st.seg_rep[s];
   const uint32_t cnt = kBucketed ? st.popc[pos] : st.seg_cnt[s];
   if (uint64_t(o0) + cnt > st.bits_cap) return;
@@ -1519,6 +1534,108 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
     for (uint32_t k = 0; k < n; ++k)
       if ((bm[st.col_bm_base[cl[k]]] >> (ib & 63)) & 1ull) emit(cl[k]);
   }
+}
+
+// ------------------------------------------------------------------ rates
+
+// Per-fault probabilities from the channel rates now in the tables.
+__global__ __launch_bounds__(kBlock) void k_fault_p(DevState st) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= st.n_chan) return;
+  const double p = fault_probability(st.chan_kind[c], st.chan_rate[c]);
+  for (uint32_t f = st.chan_foff[c]; f < st.chan_foff[c + 1]; ++f) st.frp[f].p = p;
+}
+
+// Eq. 3 again over each hyperedge's cached members (position order), with the
+// compile's shape: up to kBigSegment + 1 members one thread folds them in
+// order; larger classes are listed for k_remerge_big.
+__global__ __launch_bounds__(kBlock) void k_remerge(DevState st, const uint32_t* __restrict__ ord, uint32_t n_edges) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_edges) return;
+  const uint32_t i0 = st.e_first[e], cnt = st.e_cnt[e];
+  if (cnt > kBigSegment + 1) {
+    st.big[atomicAdd(&st.hdr->n_big, 1u)] = e;
+    return;
+  }
+  double q = st.frp[ord[i0]].p;
+  for (uint32_t i = 1; i < cnt; ++i) q = fma(st.frp[ord[i0 + i]].p, 1.0 - 2.0 * q, q);
+  st.edge_q[e] = q;
+}
+
+// One block of kBucketBlock threads per listed hyperedge: strided partial
+// merges, then the fixed tree the bucket grouping uses.
+__global__ __launch_bounds__(kBucketBlock) void k_remerge_big(DevState st, const uint32_t* __restrict__ ord) {
+  __shared__ double s_q[kBucketBlock];
+  const int tid = threadIdx.x;
+  const uint32_t nb = st.hdr->n_big;
+  for (uint32_t g = blockIdx.x; g < nb; g += gridDim.x) {
+    const uint32_t e = st.big[g];
+    const uint32_t i0 = st.e_first[e], cnt = st.e_cnt[e];
+    double q = 0.0;
+    for (uint32_t i = tid; i < cnt; i += kBucketBlock) q = fma(st.frp[ord[i0 + i]].p, 1.0 - 2.0 * q, q);
+    s_q[tid] = q;
+    __syncthreads();
+    for (int h = kBucketBlock / 2; h > 0; h >>= 1) {
+      if (tid < h) {
+        const double x = s_q[tid], y = s_q[tid + h];
+        s_q[tid] = fma(y, 1.0 - 2.0 * x, x);
+      }
+      __syncthreads();
+    }
+    if (tid == 0) st.edge_q[e] = s_q[0];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_clear_big(DevState st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) st.hdr->n_big = 0;
+}
+
+// Adjoint, per hyperedge: q = 1/2 (1 - prod_j (1 - 2 p_j)) over the members,
+// so dq/dp_i = prod_{j != i} (1 - 2 p_j): the product of the members other
+// than those with p = 1/2, divided by (1 - 2 p_i); with one member at p = 1/2
+// only that member's derivative is non-zero, with two or more none is.
+__global__ __launch_bounds__(kBlock) void k_adj_edges(DevState st, const uint32_t* __restrict__ ord,
+                                                      uint32_t n_edges) {
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_edges) return;
+  const uint32_t i0 = st.e_first[e], cnt = st.e_cnt[e];
+  uint32_t half = 0;
+  double prod = 1.0;
+  for (uint32_t i = 0; i < cnt; ++i) {
+    const double p = st.frp[ord[i0 + i]].p;
+    if (p == 0.5) half++;
+    else prod *= 1.0 - 2.0 * p;
+  }
+  const double g = st.gq[e];
+  for (uint32_t i = 0; i < cnt; ++i) {
+    const uint32_t pos = ord[i0 + i];
+    const double p = st.frp[pos].p;
+    const double d = half == 0 ? prod / (1.0 - 2.0 * p) : (half == 1 && p == 0.5 ? prod : 0.0);
+    st.gfault[pos] = g * d;
+  }
+}
+
+// dp/dr of a fault's split: (1-2p)^k = 1 - x, x = a r, so dp/dr =
+// (a / 2k)(1 - x)^(1/k - 1): DEPOLARIZE1 (1/3)(1 - 4r/3)^(-1/2), DEPOLARIZE2
+// (1/15)(1 - 16r/15)^(-7/8), a Pauli flip 1.
+__device__ __forceinline__ double fault_dp_dr(uint32_t kind, double r) {
+  if (kind == CH_DEP1) return (1.0 / 3.0) / sqrt(1.0 - 4.0 * r / 3.0);
+  if (kind == CH_DEP2) return (1.0 / 15.0) * exp(-0.875 * log1p(-16.0 * r / 15.0));
+  return 1.0;
+}
+
+// Per channel: its faults' dL/dp summed in fault order, times dp/dr.
+__global__ __launch_bounds__(kBlock) void k_adj_channels(DevState st) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= st.n_chan) return;
+  double sum = 0.0;
+  for (uint32_t f = st.chan_foff[c]; f < st.chan_foff[c + 1]; ++f) sum += st.gfault[f];
+  st.gr[c] = sum * fault_dp_dr(st.chan_kind[c], st.chan_rate[c]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_f64(double* __restrict__ a, uint32_t n) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) a[i] = 0.0;
 }
 
 inline uint32_t cdiv(uint64_t a, uint64_t b) { return uint32_t((a + b - 1) / b); }
@@ -1601,8 +1718,9 @@ hipError_t configure_kernels() {
     if (_e != hipSuccess) return _e;            \
   } while (0)
 
-hipError_t enqueue_compile(const DevState& st_in, hipStream_t stream, const LaunchHook& hook) {
-  DevState st = st_in;
+hipError_t enqueue_compile(DevState& st_io, hipStream_t stream, const LaunchHook& hook) {
+  DevState st = st_io;
+  st_io.ord = st.val[0];
   const uint32_t n = st.n_faults;
   const uint32_t ntiles = cdiv(n ? n : 1, kTile);
   // passes: enough key bits for the faults; every bit after a collision
@@ -1651,6 +1769,7 @@ hipError_t enqueue_compile(const DevState& st_in, hipStream_t stream, const Laun
                                                                      st.val[dst]));
   }
   const int fin = st.n_pass & 1;
+  st_io.ord = st.val[fin];
   GP_LAUNCH(K_HEADS_COUNT, k_heads_count<<<ntiles, kBlock, 0, stream>>>(st.key[fin], st.hdr, st.tile_sum));
   GP_LAUNCH(K_SCAN_SINGLE,
             k_scan_single<uint32_t><<<1, kScanSingleBlock, 0, stream>>>(st.tile_sum, ntiles, nullptr, &st.hdr->n_seg));
@@ -1666,6 +1785,23 @@ hipError_t enqueue_compile(const DevState& st_in, hipStream_t stream, const Laun
             k_scan_apply<<<ntiles, kBlock, 0, stream>>>(st.seg_cnt, st.seg_off, n, &st.hdr->n_seg, st.tile_sum));
   GP_LAUNCH(K_EDGE_WRITE, k_edge_write<false><<<cdiv(n, kBlock), kBlock, 0, stream>>>(st));
   return hipSuccess;
+}
+
+hipError_t enqueue_refresh(const DevState& st, uint32_t n_edges, hipStream_t stream) {
+  if (st.n_chan) k_fault_p<<<cdiv(st.n_chan, kBlock), kBlock, 0, stream>>>(st);
+  k_clear_big<<<1, kBlock, 0, stream>>>(st);
+  if (n_edges) {
+    k_remerge<<<cdiv(n_edges, kBlock), kBlock, 0, stream>>>(st, st.ord, n_edges);
+    k_remerge_big<<<64, kBucketBlock, 0, stream>>>(st, st.ord);
+  }
+  return hipGetLastError();
+}
+
+hipError_t enqueue_rates_gradient(const DevState& st, uint32_t n_edges, hipStream_t stream) {
+  if (st.n_faults) k_zero_f64<<<min(cdiv(st.n_faults, kBlock), 4096u), kBlock, 0, stream>>>(st.gfault, st.n_faults);
+  if (n_edges) k_adj_edges<<<cdiv(n_edges, kBlock), kBlock, 0, stream>>>(st, st.ord, n_edges);
+  if (st.n_chan) k_adj_channels<<<cdiv(st.n_chan, kBlock), kBlock, 0, stream>>>(st);
+  return hipGetLastError();
 }
 
 }  // namespace gp

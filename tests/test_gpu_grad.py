@@ -1,0 +1,172 @@
+"""GPU parity of the fixed-structure rate refresh and of the stage-2 adjoint
+(through the C ABI), against the oracle.
+
+Workload of the differentiation row: rotated surface code d = 9, 9 rounds,
+per-channel rates log-uniform in [1e-4, 5e-3) (seed 0); loss
+L = sum_k w_k log(q_k / (1 - q_k)) with w_k ~ U[-1, 1] (seed 1) assigned to
+the hyperedges in sorted-signature order. The gradient must match the
+oracle's to 1e-9 relative and central differences of the device forward
+pass within their error.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_16613_amd import GpError, get_driver
+from paper_2604_16613_amd import _gp
+from workloads import log_uniform_rates, rotated_surface_code_memory
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _weights(sigs, seed=1):
+    """w per signature, drawn in sorted-signature order."""
+    order = sorted(sigs)
+    w = np.random.default_rng(seed).uniform(-1.0, 1.0, len(order))
+    return dict(zip(order, w))
+
+
+def _gpu_dl_dq(hg, wmap):
+    sigs = [tuple(int(b) for b in hg.bits[hg.offsets[e]:hg.offsets[e + 1]]) for e in range(len(hg))]
+    w = np.array([wmap[s] for s in sigs])
+    return oracle.loss_and_dl_dq(hg.q, w)
+
+
+def _oracle_dl_dq(res, wmap):
+    sigs = [tuple(int(b) for b in res.edge_bits[res.edge_off[e]:res.edge_off[e + 1]]) for e in range(res.n_edges)]
+    w = np.array([wmap[s] for s in sigs])
+    return oracle.loss_and_dl_dq(res.edge_q, w)
+
+
+@pytest.fixture(scope="module")
+def c5():
+    c = rotated_surface_code_memory(9, 9)
+    rates = log_uniform_rates(c.n_channels, 0)
+    drv = get_driver(c.text)
+    yield c, rates, drv
+    drv.close()
+
+
+def test_gradient_matches_oracle_c5(c5):
+    c, rates, drv = c5
+    say("case c5 gradient vs oracle")
+    hg = drv.compile_hypergraph(c.text, rates)
+    res = oracle.run(c.text, rates=rates)
+    wmap = _weights(hg.edges().keys())
+    _, g_gpu_q = _gpu_dl_dq(hg, wmap)
+    _, g_orc_q = _oracle_dl_dq(res, wmap)
+    g_gpu = drv.rates_gradient(g_gpu_q)
+    g_orc = oracle.gradient(c.text, g_orc_q, rates=rates)
+    assert g_gpu.shape == (c.n_channels,)
+    scale = np.abs(g_orc)
+    err = np.abs(g_gpu - g_orc)
+    assert np.all(err <= 1e-9 * scale + 1e-300), float(np.max(err / np.maximum(scale, 1e-300)))
+
+
+def test_refresh_equals_full_compile(c5):
+    c, rates, drv = c5
+    say("case refresh vs compile")
+    drv.compile_hypergraph(c.text, rates)
+    r2 = log_uniform_rates(c.n_channels, 7)
+    refreshed = drv.refresh_rates(r2)
+    full = drv.compile_hypergraph(c.text, r2)
+    assert np.array_equal(refreshed.offsets, full.offsets)
+    assert np.array_equal(refreshed.bits, full.bits)
+    assert np.array_equal(refreshed.q.view(np.uint64), full.q.view(np.uint64))
+
+
+def test_gradient_matches_device_finite_differences(c5):
+    c, rates, drv = c5
+    say("case c5 gradient vs central differences")
+    hg = drv.compile_hypergraph(c.text, rates)
+    wmap = _weights(hg.edges().keys())
+    _, g_q = _gpu_dl_dq(hg, wmap)
+    grad = drv.rates_gradient(g_q)
+    h = 1e-7
+    rng = np.random.default_rng(3)
+    for ch in rng.choice(c.n_channels, 24, replace=False):
+        rp, rm = rates.copy(), rates.copy()
+        rp[ch] += h
+        rm[ch] -= h
+        lp = _gpu_dl_dq(drv.refresh_rates(rp), wmap)[0]
+        lm = _gpu_dl_dq(drv.refresh_rates(rm), wmap)[0]
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - grad[ch]) <= 1e-5 * abs(grad[ch]) + 1e-5, (int(ch), fd, grad[ch])
+    drv.refresh_rates(rates)
+
+
+def test_gradient_with_half_probability_members(c5):
+    _, _, drv = c5
+    say("case p = 1/2 members")
+    text = ("X_ERROR(0.5) 0\nX_ERROR(0.1) 0\nX_ERROR(0.2) 1\nX_ERROR(0.5) 1\nX_ERROR(0.5) 1\n"
+            "DEPOLARIZE1(0.75) 2\nM 0 1 2\nDETECTOR rec[-3]\nDETECTOR rec[-2]\nDETECTOR rec[-1]\n")
+    hg = drv.compile_hypergraph(text)
+    res = oracle.run(text)
+    wmap = _weights(hg.edges().keys(), seed=5)
+    g_gpu = drv.rates_gradient(_gpu_dl_dq(hg, wmap)[1])
+    g_orc = oracle.gradient(text, _oracle_dl_dq(res, wmap)[1])
+    finite = np.isfinite(g_orc)
+    assert np.array_equal(finite, np.isfinite(g_gpu))
+    assert np.allclose(g_gpu[finite], g_orc[finite], rtol=1e-12, atol=1e-300)
+
+
+def test_gradient_through_the_bucket_overflow_path(c5):
+    _, _, drv = c5
+    say("case gradient, class larger than a bucket")
+    rates = np.linspace(1e-7, 2e-5, 9000)
+    text = "\n".join(f"X_ERROR({r:.17g}) 0" for r in rates) + "\nX_ERROR(0.01) 1\nM 0 1\nDETECTOR rec[-2]\nDETECTOR rec[-1]\n"
+    with get_driver(text) as big:
+        hg = big.compile_hypergraph(text)
+        res = oracle.run(text)
+        wmap = _weights(hg.edges().keys(), seed=2)
+        g_gpu = big.rates_gradient(_gpu_dl_dq(hg, wmap)[1])
+        g_orc = oracle.gradient(text, _oracle_dl_dq(res, wmap)[1])
+    assert np.allclose(g_gpu, g_orc, rtol=1e-9, atol=0)
+
+
+def test_state_and_argument_errors(c5):
+    c, rates, drv = c5
+    say("case adjoint error paths")
+    drv.lower(c.text, rates)
+    with pytest.raises(GpError) as e:
+        drv.rates_gradient(np.zeros(3))
+    assert e.value.code == -10  # GP_E_STATE: no fetched compile of this lowering
+    hg = drv.compile_hypergraph(c.text, rates)
+    with pytest.raises(GpError) as e:
+        _gp.gp_rates_gradient(drv.handle, np.zeros(len(hg) + 1), c.n_channels)
+    assert e.value.code == -1
+    with pytest.raises(GpError) as e:
+        drv.refresh_rates(np.full(c.n_channels, 2.0))
+    assert e.value.code == -6
+    # the failed refresh left the rates alone
+    again = drv.refresh_rates(rates)
+    assert np.array_equal(again.q.view(np.uint64), hg.q.view(np.uint64))
+
+
+def test_torch_autograd_wrapper(c5):
+    torch = pytest.importorskip("torch")
+    from paper_2604_16613_amd.autograd import HypergraphFunction
+    c, rates, drv = c5
+    say("case torch autograd")
+    f = HypergraphFunction(drv, c.text)
+    f.compile(rates)
+    wmap = _weights(f.structure.edges().keys())
+    sigs = [tuple(int(b) for b in f.structure.bits[f.structure.offsets[e]:f.structure.offsets[e + 1]])
+            for e in range(len(f.structure))]
+    w = torch.tensor([wmap[s] for s in sigs], dtype=torch.float64)
+    r = torch.tensor(rates, dtype=torch.float64, requires_grad=True)
+    q = f(r)
+    loss = torch.sum(w * torch.log(q / (1 - q)))
+    loss.backward()
+    _, g_q = _gpu_dl_dq(f.structure, wmap)
+    expect = drv.rates_gradient(g_q)
+    # torch differentiates log(q / (1 - q)) through the division: dL/dq agrees to rounding
+    assert np.allclose(r.grad.numpy(), expect, rtol=1e-10, atol=0)
