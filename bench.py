@@ -109,6 +109,7 @@ def main() -> int:
     ap.add_argument("--latency-iters", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-grad", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain streaming copy of MIB MiB five times (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -198,6 +199,9 @@ def main() -> int:
                      "bytes_per_launch": dom_bytes, "avg_launch_ms": dom_avg_ms, "launches_per_step": dom_launches},
     }
 
+    if not args.no_grad:
+        out["differentiation"] = bench_differentiation(get_driver)
+
     if not args.no_cpu_baseline:
         # the oracle on the whole workload, repeated until about cpu_seconds of
         # host time have passed (one run of the largest circuit takes a few s)
@@ -216,6 +220,54 @@ def main() -> int:
     print(json.dumps(out), flush=True)
     drv.close()
     return 0
+
+
+def bench_differentiation(get_driver, iters: int = 50) -> dict:
+    """The differentiation workload: rotated surface code d = 9, 9 rounds,
+    per-channel rates log-uniform in [1e-4, 5e-3) (seed 0). Times one device
+    compile, one rate refresh over the fixed structure (per-fault
+    probabilities + Eq. 3 over every hyperedge) and one adjoint (dL/dq up,
+    dL/d(rate) down), and checks the adjoint against the oracle."""
+    from paper_2604_16613_amd import _gp
+    from workloads import log_uniform_rates, rotated_surface_code_memory
+    import oracle
+    c = rotated_surface_code_memory(9, 9)
+    rates = log_uniform_rates(c.n_channels, 0)
+    drv = get_driver(c.text)
+    hg = drv.compile_hypergraph(c.text, rates)
+    F = drv.info()["n_faults"]
+    sigs = [tuple(int(b) for b in hg.bits[hg.offsets[e]:hg.offsets[e + 1]]) for e in range(len(hg))]
+    wmap = dict(zip(sorted(sigs), np.random.default_rng(1).uniform(-1.0, 1.0, len(sigs))))
+    w = np.array([wmap[k] for k in sigs])
+    _, dl_dq = oracle.loss_and_dl_dq(hg.q, w)
+
+    def timed(fn):
+        fn()
+        drv.sync()
+        t = []
+        for _ in range(iters):
+            s0 = time.perf_counter()
+            fn()
+            drv.sync()
+            t.append((time.perf_counter() - s0) * 1e3)
+        return float(np.median(t))
+
+    compile_ms = timed(drv.run)
+    drv.fetch()
+    refresh_ms = timed(lambda: _gp.gp_refresh_rates(drv.handle, rates))
+    grad_ms = timed(lambda: drv.rates_gradient(dl_dq))
+    g = drv.rates_gradient(dl_dq)
+    res = oracle.run(c.text, rates=rates)
+    osigs = [tuple(int(b) for b in res.edge_bits[res.edge_off[e]:res.edge_off[e + 1]]) for e in range(res.n_edges)]
+    _, odl = oracle.loss_and_dl_dq(res.edge_q, np.array([wmap[k] for k in osigs]))
+    go = oracle.gradient(c.text, odl, rates=rates)
+    drv.close()
+    return {"workload": "sc_d9_r9 log-uniform rates seed 0, loss sum_k w_k log(q_k/(1-q_k)), w ~ U[-1,1] seed 1",
+            "faults": int(F), "channels": int(c.n_channels), "hyperedges": len(hg),
+            "compile_ms_median": compile_ms, "refresh_ms_median": refresh_ms,
+            "gradient_ms_median": grad_ms, "refresh_faults_per_s": F / (refresh_ms * 1e-3),
+            "gradient_max_rel_err_vs_oracle": float(np.max(np.abs(g - go) / np.maximum(np.abs(go), 1e-300))),
+            "timing": "host wall clock around each call + stream sync, median of %d" % iters}
 
 
 def copy_calibration(mib: int) -> int:
