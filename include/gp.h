@@ -132,6 +132,13 @@ int gp_lower(gp_driver* drv, const char* text, size_t len, const double* rates, 
 int gp_run(gp_driver* drv);
 int gp_fetch(gp_driver* drv, gp_edges** out);
 
+/* Correlation level (Table 1) for the following lowerings: which Paulis of
+ * each noise channel become faults. 0: products of X's or of Z's (IX, IZ, XI,
+ * XX, ZI, ZZ; one-qubit X, Z); 1 adds a Y next to the identity and mixed X/Z
+ * pairs (IY, YI, XZ, ZX; one-qubit Y); 2 (default): every Pauli. A kept fault
+ * keeps the probability it has at level 2. GP_E_ARG for other values. */
+int gp_set_correlation_level(gp_driver* drv, int level);
+
 /* Fixed structure, new rates (Eq. 3 over cached classes). After a gp_fetch,
  * the driver keeps each hyperedge's member faults (in fault order) on the
  * device. gp_refresh_rates replaces the channel rates (`rates`: host,

@@ -79,6 +79,8 @@ def _load():
                                         ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.c_int64,
                                         ctypes.POINTER(ctypes.c_double), ctypes.c_int64]
         lib.oracle_gradient.restype = ctypes.c_int
+        lib.oracle_set_level.argtypes = [ctypes.c_int]
+        lib.oracle_set_level.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -136,10 +138,17 @@ def _arr(ptr, n, dtype):
     return np.ctypeslib.as_array(ptr, shape=(n,)).astype(dtype, copy=True)
 
 
+def _level(lib, level: int) -> None:
+    if lib.oracle_set_level(int(level)) != 0:
+        raise OracleError(-1, lib.oracle_last_error().decode())
+
+
 def run(text: str, rates: Optional[Sequence[float]] = None, keep_faults: bool = False,
-        fault_stride: int = 1) -> OracleResult:
-    """Compile `text` with the oracle. `rates`: optional per-channel rate array."""
+        fault_stride: int = 1, level: int = 2) -> OracleResult:
+    """Compile `text` with the oracle. `rates`: optional per-channel rate array;
+    `level`: correlation level (Table 1), 2 = every Pauli."""
     lib = _load()
+    _level(lib, level)
     raw = text.encode()
     out = ctypes.POINTER(_Result)()
     if rates is not None:
@@ -174,7 +183,8 @@ def run(text: str, rates: Optional[Sequence[float]] = None, keep_faults: bool = 
     return res
 
 
-def gradient(text: str, dl_dq: Sequence[float], rates: Optional[Sequence[float]] = None) -> np.ndarray:
+def gradient(text: str, dl_dq: Sequence[float], rates: Optional[Sequence[float]] = None,
+             level: int = 2) -> np.ndarray:
     """dL/d(rate) per channel (program order) given dL/dq per hyperedge in the
     order `run` returns the hyperedges (explicit products over each class's
     other members, chain rule through the per-fault split)."""
@@ -188,6 +198,7 @@ def gradient(text: str, dl_dq: Sequence[float], rates: Optional[Sequence[float]]
     else:
         rp, nr = None, 0
         nch = run(text).n_channels
+    _level(lib, level)
     out = np.zeros(nch, dtype=np.float64)
     rc = lib.oracle_gradient(raw, len(raw), rp, nr, g.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), len(g),
                              out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), nch)

@@ -453,6 +453,35 @@ static int chan_faults(int kind, int codes[15]) {
   return 0;
 }
 
+/* Correlation levels, Table 1: the two-qubit Paulis each level adds, by name
+ * (first letter = first target). One-qubit channels follow the same split:
+ * X and Z at level 0, Y from level 1. */
+static const char *const LEVEL_NAMES[3][6] = {
+    {"IX", "IZ", "XI", "XX", "ZI", "ZZ"},
+    {"IY", "XZ", "YI", "ZX", NULL, NULL},
+    {"XY", "YX", "YY", "YZ", "ZY", NULL},
+};
+
+static char pauli_letter(int xz) { return "IXZY"[xz & 3]; }
+
+static int pauli_level_of(int kind, int code) {
+  char name[3] = {0, 0, 0};
+  if (kind == N_DEP2) {
+    name[0] = pauli_letter(code & 3);
+    name[1] = pauli_letter((code >> 2) & 3);
+  } else {
+    /* a one-qubit Pauli P is ranked like IP */
+    name[0] = 'I';
+    name[1] = pauli_letter(code & 3);
+  }
+  for (int l = 0; l < 3; l++)
+    for (int k = 0; k < 6 && LEVEL_NAMES[l][k]; k++)
+      if (!strcmp(name, LEVEL_NAMES[l][k])) return l;
+  return 3;
+}
+
+static int g_level = 2;
+
 static double fault_p(int kind, double r) {
   switch (kind) {
     case N_DEP1: return split_dep1(r);
@@ -706,8 +735,10 @@ int oracle_run(const char *text, size_t len, const double *rates, int64_t n_rate
   for (int64_t k = 0; k < c.nch; k++) {
     int nfc = chan_faults(c.ch[k].kind, codes);
     double p = fault_p(c.ch[k].kind, c.ch[k].rate);
-    for (int j = 0; j < nfc; j++, fid++) {
-      if (fid % fault_stride) continue;
+    for (int j = 0; j < nfc; j++) {
+      /* faults above the correlation level are not part of the model */
+      if (pauli_level_of(c.ch[k].kind, codes[j]) > g_level) continue;
+      if ((fid++) % fault_stride) continue;
       if ((rc = track_fault(&c, &c.ch[k], codes[j], &s))) goto fin;
       if (nf == capf) {
         capf = capf ? capf * 2 : 1024;
@@ -878,6 +909,14 @@ int oracle_gradient(const char *text, size_t len, const double *rates, int64_t n
   free(ord);
   oracle_free(r);
   circ_free(&c);
+  return ORC_OK;
+}
+
+/* Correlation level used by the following oracle_run / oracle_gradient calls
+ * (0, 1 or 2 = every Pauli). */
+int oracle_set_level(int level) {
+  if (level < 0 || level > 2) return fail(ORC_E_ARG, "correlation level must be 0, 1 or 2");
+  g_level = level;
   return ORC_OK;
 }
 

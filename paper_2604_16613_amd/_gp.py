@@ -30,6 +30,7 @@ EXPORTS = (
     "gp_edges_offsets", "gp_edges_bits", "gp_edges_probabilities", "gp_edges_to_dem_text",
     "gp_edges_free", "gp_free", "gp_debug_set_key_bits", "gp_debug_collision_retries",
     "gp_debug_sweep_times", "gp_debug_set_sort_mode", "gp_refresh_rates", "gp_rates_gradient",
+    "gp_set_correlation_level",
 )
 
 
@@ -119,6 +120,7 @@ def load():
         "gp_debug_collision_retries": ([_vp], _u64),
         "gp_debug_set_sort_mode": ([_vp, ctypes.c_int], ctypes.c_int),
         "gp_refresh_rates": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t], ctypes.c_int),
+        "gp_set_correlation_level": ([_vp, ctypes.c_int], ctypes.c_int),
         "gp_rates_gradient": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t,
                                ctypes.POINTER(ctypes.c_double), ctypes.c_size_t], ctypes.c_int),
         "gp_debug_sweep_times": ([_vp, ctypes.POINTER(_u64), _u64, ctypes.POINTER(_u64),
@@ -280,6 +282,10 @@ def gp_edges_free(e: int) -> None:
 
 def gp_debug_set_key_bits(drv: int, bits: int) -> None:
     _check(load().gp_debug_set_key_bits(drv, bits))
+
+
+def gp_set_correlation_level(drv: int, level: int) -> None:
+    _check(load().gp_set_correlation_level(drv, level))
 
 
 def gp_refresh_rates(drv: int, rates: Sequence[float]) -> None:

@@ -105,6 +105,10 @@ class Driver:
     def info(self) -> dict:
         return _gp.gp_circuit_info_get(self.handle).as_dict()
 
+    def set_correlation_level(self, level: int) -> None:
+        """Table 1 level (0, 1 or 2 = every Pauli) for the following compiles."""
+        _gp.gp_set_correlation_level(self.handle, level)
+
     # fixed structure: new rates, and the adjoint of stage 2
     def refresh_rates(self, rates: Sequence[float]) -> Hypergraph:
         """Same hyperedges (same order) as the last fetched compile, with the

@@ -132,6 +132,7 @@ struct gp_driver {
   uint32_t key_bits = 64;      // test hook: class keys cut to this many bits
   uint32_t sort_mode = gp::SORT_AUTO;  // test hook: force the full radix sort
   uint64_t bm_cap = 0;                 // non-zero-word bitmap words allocated
+  uint32_t level = 2;                  // correlation level for the next lowering
   uint64_t collision_retries = 0;
 
   bool timing = false;
@@ -390,7 +391,7 @@ int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, si
   d->lowered = false;
   d->ran = false;
   d->structured = false;
-  int rc = gp::lower_circuit(text, len, rates, n_rates, gp::kSweepSlots, d->lw, err);
+  int rc = gp::lower_circuit(text, len, rates, n_rates, gp::kSweepSlots, d->lw, err, d->level);
   if (rc) return fail(rc, err.msg);
   if ((rc = check_bounds(d, d->lw))) return rc;
   const gp::Lowered& lw = d->lw;
@@ -485,6 +486,7 @@ int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, si
   st.n_chan = uint32_t(lw.chan_kind.size());
   st.n_items = uint32_t(lw.item_col.size());
   st.n_faults = uint32_t(lw.n_faults);
+  st.level = lw.level;
   d->lowered = true;
   return GP_OK;
 }
@@ -693,6 +695,13 @@ int gp_debug_set_key_bits(gp_driver* d, int bits) {
 }
 
 uint64_t gp_debug_collision_retries(const gp_driver* d) { return d ? d->collision_retries : 0; }
+
+int gp_set_correlation_level(gp_driver* d, int level) {
+  if (!d) return fail(GP_E_ARG, "null driver");
+  if (level < 0 || level > 2) return fail(GP_E_ARG, "correlation level must be 0, 1 or 2");
+  d->level = uint32_t(level);
+  return GP_OK;
+}
 
 int gp_debug_set_sort_mode(gp_driver* d, int mode) {
   if (!d) return fail(GP_E_ARG, "null driver");

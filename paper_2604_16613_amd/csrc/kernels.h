@@ -91,6 +91,7 @@ struct DevState {
   uint32_t n_faults;
   uint32_t n_hchunks;
   uint32_t n_win;
+  uint32_t level;       // correlation level (Table 1) the faults were kept at
   uint32_t max_col_inj;  // most injection entries of any one column
   // class key: 0 = FNV-1a of the signature (kept to its low key_bits bits);
   // 1 = FNV-1a mixed with the check hash (used after a key collision)

@@ -165,10 +165,7 @@ __global__ void k_prepare(DevState st) {
     for (uint32_t f = f0; f < f1; ++f) {
       st.frp[f].p = p;
       // Pauli code: x on a | z on a << 1 | x on b << 2 | z on b << 3
-      const uint32_t k = f - f0;
-      const uint32_t code = kind == CH_DEP2 ? k + 1
-                          : kind == CH_DEP1 ? (k == 0 ? 1u : k == 1 ? 3u : 2u)
-                          : kind == CH_X ? 1u : kind == CH_Y ? 3u : 2u;
+      const uint32_t code = kept_code(kind, st.level, f - f0);
       st.frec[f] = qa | (qb << kQubitBits) | (code << 28);
     }
   }

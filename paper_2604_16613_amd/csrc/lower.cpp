@@ -43,7 +43,7 @@ double rate_limit(uint8_t kind) {
   return kind == CH_DEP1 ? 0.75 : kind == CH_DEP2 ? 15.0 / 16.0 : 0.5;
 }
 
-uint32_t faults_of(uint8_t kind) { return kind == CH_DEP2 ? 15u : kind == CH_DEP1 ? 3u : 1u; }
+
 
 int set_err(LowerError& err, int code, int line, const char* fmt, const char* what) {
   char buf[256];
@@ -67,8 +67,10 @@ struct RawChan {
 }  // namespace
 
 int lower_circuit(const char* text, size_t len, const double* rates, size_t n_rates,
-                  uint32_t sweep_slots, Lowered& lw, LowerError& err) {
+                  uint32_t sweep_slots, Lowered& lw, LowerError& err, uint32_t level) {
   lw = Lowered();
+  if (level > 2) return set_err(err, GP_E_ARG, 0, "%s", "correlation level must be 0, 1 or 2");
+  lw.level = level;
   std::vector<uint32_t> ready;
   std::vector<uint32_t> op_layer;
   std::vector<uint64_t> op_word;
@@ -338,10 +340,10 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
     }
   }
   uint64_t total_faults = 0;
-  for (size_t c = 0; c < C; c++) total_faults += faults_of(lw.chan_kind[c]);
+  for (size_t c = 0; c < C; c++) total_faults += kept_faults(lw.chan_kind[c], lw.level);
   if (total_faults >= (1ull << 32)) return set_err(err, GP_E_BOUNDS, 0, "%s", "more than 2^32 - 1 faults");
   lw.chan_foff.assign(C + 1, 0);
-  for (size_t c = 0; c < C; c++) lw.chan_foff[c + 1] = lw.chan_foff[c] + faults_of(lw.chan_kind[c]);
+  for (size_t c = 0; c < C; c++) lw.chan_foff[c + 1] = lw.chan_foff[c] + kept_faults(lw.chan_kind[c], lw.level);
   lw.n_faults = total_faults;
   lw.bnd_fault_off.assign(size_t(L) + 2, 0);
   for (uint32_t b = 0; b <= L + 1; b++) lw.bnd_fault_off[b] = lw.chan_foff[lw.bnd_chan_off[b]];

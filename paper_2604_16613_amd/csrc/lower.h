@@ -43,6 +43,36 @@ inline uint64_t pack_op(uint32_t kind, uint32_t a, uint32_t b) {
 constexpr uint32_t kQubitBits = 14;
 constexpr uint32_t kMaxSweepQubits = 1u << kQubitBits;
 constexpr uint32_t kQField = kMaxSweepQubits - 1;
+// Correlation level of a fault's Pauli (code: x on a | z on a << 1 | x on b <<
+// 2 | z on b << 3), Table 1: 0 for products of X's or of Z's (IX, IZ, XI, XX,
+// ZI, ZZ; one-qubit X, Z), 1 for a Y next to the identity or a mixed X/Z pair
+// (IY, YI, XZ, ZX; one-qubit Y), 2 for a Y next to X, Y or Z. Level L keeps
+// the faults of level <= L (L0 in L1 in L2 = every Pauli).
+constexpr uint32_t pauli_level(uint32_t code) {
+  const uint32_t a = code & 3u, b = (code >> 2) & 3u;  // per qubit: 0 I, 1 X, 2 Z, 3 Y
+  if (a != 3u && b != 3u) return (a == 0u || b == 0u || a == b) ? 0u : 1u;
+  return (a == 0u || b == 0u) ? 1u : 2u;
+}
+
+// The Pauli codes of a channel, in fault order: a DEPOLARIZE1 gives X, Y, Z; a
+// DEPOLARIZE2 the fifteen non-identity codes in ascending order.
+constexpr uint32_t channel_code(uint32_t kind, uint32_t k) {
+  return kind == 5u ? k + 1u : kind == 4u ? (k == 0u ? 1u : k == 1u ? 3u : 2u) : kind == 1u ? 1u : kind == 2u ? 3u : 2u;
+}
+constexpr uint32_t channel_codes(uint32_t kind) { return kind == 5u ? 15u : kind == 4u ? 3u : 1u; }
+
+// Faults a channel keeps at a correlation level, and the code of its k-th kept fault.
+constexpr uint32_t kept_faults(uint32_t kind, uint32_t level) {
+  uint32_t n = 0;
+  for (uint32_t k = 0; k < channel_codes(kind); k++) n += pauli_level(channel_code(kind, k)) <= level;
+  return n;
+}
+constexpr uint32_t kept_code(uint32_t kind, uint32_t level, uint32_t j) {
+  for (uint32_t k = 0; k < channel_codes(kind); k++)
+    if (pauli_level(channel_code(kind, k)) <= level && j-- == 0u) return channel_code(kind, k);
+  return 0u;
+}
+
 // Compact ops one LDS op window of the sweep holds.
 constexpr uint32_t kSweepWinOps = 4096;
 // Sweep items that run at once: one per CU of the target GPU (256 on gfx950).
@@ -78,6 +108,7 @@ struct Lowered {
   std::vector<int32_t> col_lo;              // lowest such layer
   std::vector<uint64_t> col_base;           // slab offset: word of (column w, position p) at base[w] + p
   uint64_t slab_words = 0;
+  uint32_t level = 2;                       // correlation level the faults were kept at
   std::vector<uint32_t> item_col, item_blo, item_bhi;  // emission boundaries [blo, bhi]
 
   std::vector<uint64_t> fnv_pow;            // w + 1 entries: FNV prime^(8k) mod 2^64
@@ -119,7 +150,7 @@ struct LowerError {
 // CU); observable columns are cut into ranges that fill the slots the
 // detector columns leave. Returns 0 or a negative GP_E_* status with err set.
 int lower_circuit(const char* text, size_t len, const double* rates, size_t n_rates,
-                  uint32_t sweep_slots, Lowered& out, LowerError& err);
+                  uint32_t sweep_slots, Lowered& out, LowerError& err, uint32_t level = 2);
 
 // Re-apply a rate array to an already lowered circuit (same structure).
 int apply_rates(Lowered& lw, const double* rates, size_t n_rates, LowerError& err);

@@ -262,3 +262,26 @@ def test_large_classes(drv25, copies):
     lines = [f"X_ERROR({r:.17g}) 0" for r in rates]
     lines += ["X_ERROR(0.01) 1", "M 0 1", "DETECTOR rec[-2]", "DETECTOR rec[-1]", "OBSERVABLE_INCLUDE(0) rec[-1]"]
     check(drv25, "\n".join(lines) + "\n", label=f"{copies} copies")
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_correlation_levels(drv25, level):
+    """Table 1 levels: the device keeps the same Paulis as the oracle."""
+    from workloads import paper_noise
+    drv25.set_correlation_level(level)
+    try:
+        c = rotated_surface_code_memory(11, 11)
+        hg = drv25.compile_hypergraph(c.text, log_uniform_rates(c.n_channels, 0))
+        assert_parity(hg, oracle.run(c.text, rates=log_uniform_rates(c.n_channels, 0), level=level),
+                      f"level {level} sc11")
+        c = bivariate_bicycle_memory()
+        assert_parity(drv25.compile_hypergraph(c.text), oracle.run(c.text, level=level), f"level {level} bb")
+        c = rotated_surface_code_memory(7, 7, p=1e-3, x_detectors=False, **paper_noise(1e-3))
+        assert_parity(drv25.compile_hypergraph(c.text), oracle.run(c.text, level=level), f"level {level} preset")
+        c = rotated_surface_code_memory(25, 25)
+        assert_parity(drv25.compile_hypergraph(c.text), oracle.run(c.text, level=level), f"level {level} sc25")
+    finally:
+        drv25.set_correlation_level(2)
+    with pytest.raises(GpError) as e:
+        drv25.set_correlation_level(3)
+    assert e.value.code == -1

@@ -8,6 +8,7 @@ CPU oracle may consume what it generates without sharing any method code.
 from .circuits import (  # noqa: F401
     Circuit,
     rotated_surface_code_memory,
+    paper_noise,
     repetition_code_memory,
     bivariate_bicycle_memory,
     bit_flip_code_fig1,

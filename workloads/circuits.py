@@ -156,17 +156,27 @@ def _rotated_layout(d: int):
     return plaqs
 
 
+def paper_noise(p: float) -> Dict[str, object]:
+    """The paper's hardware-inspired preset (Sec. 4): p1 = pi = p/10 and
+    p2 = pr = pm = p, with idle noise and resets that fail by a bit flip."""
+    return {"p1": p / 10, "pi": p / 10, "p2": p, "pr": p, "pm": p, "reset_noise": "X_ERROR"}
+
+
 def rotated_surface_code_memory(d: int, rounds: int, p: float = 1e-3,
                                 p1: Optional[float] = None, p2: Optional[float] = None,
                                 pm: Optional[float] = None, pr: Optional[float] = None,
-                                ticks: bool = True) -> Circuit:
+                                pi: float = 0.0, reset_noise: str = "DEPOLARIZE1",
+                                x_detectors: bool = True, ticks: bool = True) -> Circuit:
     """Z-basis memory of the distance-d rotated surface code, `rounds` rounds.
 
     CX order: X checks visit (TL, TR, BL, BR) ("Z" shape), Z checks visit
     (TL, BL, TR, BR) ("N" shape), so that hook errors of each type run
     perpendicular to the logical operator of the same type. Detectors: first
-    round Z checks, consecutive-round parity of every check, final data parity of
-    every Z check. Observable 0: Z on data row 0.
+    round Z checks, consecutive-round parity of every check (X checks only if
+    `x_detectors`), final data parity of every Z check. Observable 0: Z on data
+    row 0. Noise: DEPOLARIZE1(p1) after one-qubit gates, DEPOLARIZE2(p2) after
+    CX, X_ERROR(pm) before measurements, `reset_noise`(pr) after resets, and
+    DEPOLARIZE1(pi) on the qubits idle in a gate layer when pi > 0.
     """
     p1 = p if p1 is None else p1
     p2 = p if p2 is None else p2
@@ -182,14 +192,22 @@ def rotated_surface_code_memory(d: int, rounds: int, p: float = 1e-3,
     order_x = (0, 1, 2, 3)
     order_z = (0, 2, 1, 3)
     b = _Builder()
+    busy_h = set(xanc)
+    idle_h = [q for q in allq if q not in busy_h]
+
+    def idle(qs):
+        if pi > 0 and qs:
+            b.noise1("DEPOLARIZE1", pi, qs)
+
     b.gate("R", allq)
-    b.noise1("DEPOLARIZE1", pr, allq)
+    b.noise1(reset_noise, pr, allq)
     if ticks:
         b.tick()
     last: Dict[int, int] = {}
     for rnd in range(rounds):
         b.gate("H", xanc)
         b.noise1("DEPOLARIZE1", p1, xanc)
+        idle(idle_h)
         if ticks:
             b.tick()
         for layer in range(4):
@@ -202,22 +220,26 @@ def rotated_surface_code_memory(d: int, rounds: int, p: float = 1e-3,
                 pairs.append((anc[k], q) if typ == "X" else (q, anc[k]))
             b.pairs("CX", pairs)
             b.noise2(p2, pairs)
+            busy = {q for pr_ in pairs for q in pr_}
+            idle([q for q in allq if q not in busy])
             if ticks:
                 b.tick()
         b.gate("H", xanc)
         b.noise1("DEPOLARIZE1", p1, xanc)
+        idle(idle_h)
         if ticks:
             b.tick()
         b.noise1("X_ERROR", pm, anc)
         ms = b.measure("MR", anc)
-        b.noise1("DEPOLARIZE1", pr, anc)
+        b.noise1(reset_noise, pr, anc)
+        idle(data)
         cur = dict(zip(anc, ms))
         for k, (typ, _) in enumerate(plaqs):
             a = anc[k]
             if rnd == 0:
                 if typ == "Z":
                     b.detector([cur[a]])
-            else:
+            elif typ == "Z" or x_detectors:
                 b.detector([cur[a], last[a]])
         last = cur
         if ticks:
