@@ -68,7 +68,9 @@ typedef struct gp_driver gp_driver;
 typedef struct gp_edges gp_edges;
 
 /* Size bounds of a driver; every device buffer is allocated once from these
- * (paper Sec. 3.4, buffer reuse). Circuits within the bounds reuse the buffers. */
+ * (paper Sec. 3.4, buffer reuse). Circuits within the bounds reuse the buffers.
+ * For a batch (gp_lower_batch), qubits, layers, detectors and observables
+ * bound each circuit; every other field bounds the sum over the batch. */
 typedef struct gp_bounds {
   uint32_t max_qubits;
   uint32_t max_layers;        /* gate layers after as-soon-as-possible scheduling */
@@ -76,11 +78,12 @@ typedef struct gp_bounds {
   uint32_t max_detectors;
   uint32_t max_observables;
   uint32_t max_channels;
-  uint64_t max_faults;
+  uint64_t max_faults;        /* at most 2^30 - 1 */
   uint64_t max_ops;           /* elementary gate/measurement/reset operations */
   uint64_t max_leaf_bits;     /* total (measurement, detector-or-observable) memberships */
-  uint64_t max_slab_words;    /* 64-bit words of stage-1 signature storage */
-  uint64_t max_items;         /* stage-1 sweep work items */
+  uint64_t max_slab_words;    /* 64-bit words of stage-1 signature storage (0: max_faults words per column) */
+  uint64_t max_items;         /* stage-1 sweep work items (0: enough for any circuit within the bounds) */
+  uint32_t max_branches;      /* circuits one batch may hold (0 means 1) */
 } gp_bounds;
 
 /* Sizes of the most recently lowered circuit (and, after a fetch, its result). */
@@ -94,6 +97,7 @@ typedef struct gp_circuit_info {
   uint64_t n_live_words;      /* stage-1 signature words in the swept windows (valid after fetch) */
   uint64_t n_live_faults;     /* faults with a non-empty signature (valid after fetch) */
   uint64_t n_nonzero_words;   /* non-zero stage-1 signature words stored (valid after fetch) */
+  uint32_t n_circuits;        /* circuits lowered together (1 after gp_lower) */
 } gp_circuit_info;
 
 /* Thread-local description of the last non-zero status. Never NULL. */
@@ -109,6 +113,14 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out);
 
 /* Listing 1 of the paper: a driver whose bounds are those of a maximum circuit. */
 int gp_driver_create_from_circuit(const char* text, size_t len, int device, gp_driver** out);
+
+/* Batch forms (Sec. 3.4 compiles many circuit instances; here several are
+ * compiled by one launch of each stage). `texts[k]`, `lens[k]`: host circuit
+ * texts, k < n. gp_bounds_from_batch reports the bounds the batch needs (no
+ * GPU use); gp_driver_create_from_batch creates a driver from them. */
+int gp_bounds_from_batch(const char* const* texts, const size_t* lens, size_t n, gp_bounds* out);
+int gp_driver_create_from_batch(const char* const* texts, const size_t* lens, size_t n, int device,
+                                gp_driver** out);
 
 /* Waits for outstanding work, frees device and host buffers. NULL is ignored. */
 void gp_driver_destroy(gp_driver* drv);
@@ -131,6 +143,21 @@ int gp_compile_hypergraph(gp_driver* drv, const char* text, size_t len,
 int gp_lower(gp_driver* drv, const char* text, size_t len, const double* rates, size_t n_rates);
 int gp_run(gp_driver* drv);
 int gp_fetch(gp_driver* drv, gp_edges** out);
+
+/* Lower n independent circuits as one batch; gp_run then compiles them all in
+ * one pass of each stage and gp_fetch returns every circuit's hyperedges in
+ * one gp_edges, tagged by circuit (gp_edges_circuit_ids). Each circuit is
+ * grouped on its own: a hyperedge never merges faults of two circuits, and
+ * circuit k's hyperedges are those a compile of circuit k alone gives (same
+ * bits; the same probabilities, bitwise when both compiles take the same
+ * stage-2 grouping; the order may differ). `rates` (host,
+ * may be NULL) holds one rate array per circuit (rates[k] NULL = the rates in
+ * texts[k]) of n_rates[k] entries. For gp_refresh_rates and gp_rates_gradient
+ * the channels of a batch are numbered circuit by circuit: circuit 0's in
+ * program order, then circuit 1's, and so on. A failing circuit reports its
+ * index in gp_last_error. */
+int gp_lower_batch(gp_driver* drv, const char* const* texts, const size_t* lens, const double* const* rates,
+                   const size_t* n_rates, size_t n);
 
 /* Correlation level (Table 1) for the following lowerings: which Paulis of
  * each noise channel become faults. 0: products of X's or of Z's (IX, IZ, XI,
@@ -204,16 +231,24 @@ int gp_debug_sweep_times(gp_driver* drv, uint64_t* out, uint64_t cap, uint64_t* 
  *   bits[offsets[e]] ... bits[offsets[e+1]-1]   (strictly increasing),
  * where bit b < n_detectors is detector b and bit n_detectors + k is
  * observable k, and probability probabilities[e]. Edge order is unspecified
- * (deterministic for a given circuit). Pointers stay valid until gp_edges_free. */
+ * (deterministic for a given circuit). Pointers stay valid until gp_edges_free.
+ * In a batch result, n_detectors is that of hyperedge e's own circuit
+ * (circuit_ids[e], with its shape from gp_edges_circuit_shape), and
+ * gp_edges_detectors / gp_edges_observables give the largest of any circuit. */
 uint64_t gp_edges_count(const gp_edges* e);
 uint32_t gp_edges_detectors(const gp_edges* e);
 uint32_t gp_edges_observables(const gp_edges* e);
 const uint64_t* gp_edges_offsets(const gp_edges* e);
 const uint32_t* gp_edges_bits(const gp_edges* e);
 const double* gp_edges_probabilities(const gp_edges* e);
+uint32_t gp_edges_circuits(const gp_edges* e);            /* circuits in the compile (1 without a batch) */
+const uint32_t* gp_edges_circuit_ids(const gp_edges* e);  /* per hyperedge: its circuit */
+int gp_edges_circuit_shape(const gp_edges* e, uint32_t circuit, uint32_t* n_det, uint32_t* n_obs);
 /* Detector error model text, one "error(q) D.. L.." line per hyperedge. The
- * caller releases *text with gp_free. */
+ * caller releases *text with gp_free. GP_E_STATE for a batch result, whose
+ * circuits each have their own text (gp_edges_circuit_dem_text). */
 int gp_edges_to_dem_text(const gp_edges* e, char** text, size_t* len);
+int gp_edges_circuit_dem_text(const gp_edges* e, uint32_t circuit, char** text, size_t* len);
 void gp_edges_free(gp_edges* e);
 void gp_free(void* p);
 

@@ -30,7 +30,8 @@ EXPORTS = (
     "gp_edges_offsets", "gp_edges_bits", "gp_edges_probabilities", "gp_edges_to_dem_text",
     "gp_edges_free", "gp_free", "gp_debug_set_key_bits", "gp_debug_collision_retries",
     "gp_debug_sweep_times", "gp_debug_set_sort_mode", "gp_refresh_rates", "gp_rates_gradient",
-    "gp_set_correlation_level",
+    "gp_set_correlation_level", "gp_bounds_from_batch", "gp_driver_create_from_batch", "gp_lower_batch",
+    "gp_edges_circuits", "gp_edges_circuit_ids", "gp_edges_circuit_shape", "gp_edges_circuit_dem_text",
 )
 
 
@@ -48,7 +49,7 @@ class GpBounds(ctypes.Structure):
         ("max_observables", ctypes.c_uint32), ("max_channels", ctypes.c_uint32),
         ("max_faults", ctypes.c_uint64), ("max_ops", ctypes.c_uint64),
         ("max_leaf_bits", ctypes.c_uint64), ("max_slab_words", ctypes.c_uint64),
-        ("max_items", ctypes.c_uint64),
+        ("max_items", ctypes.c_uint64), ("max_branches", ctypes.c_uint32),
     ]
 
     def as_dict(self):
@@ -64,7 +65,7 @@ class GpCircuitInfo(ctypes.Structure):
         ("n_items", ctypes.c_uint64), ("slab_words", ctypes.c_uint64),
         ("n_classes", ctypes.c_uint64), ("n_edges", ctypes.c_uint64), ("n_edge_bits", ctypes.c_uint64),
         ("n_live_words", ctypes.c_uint64), ("n_live_faults", ctypes.c_uint64),
-        ("n_nonzero_words", ctypes.c_uint64),
+        ("n_nonzero_words", ctypes.c_uint64), ("n_circuits", ctypes.c_uint32),
     ]
 
     def as_dict(self):
@@ -125,6 +126,19 @@ def load():
                                ctypes.POINTER(ctypes.c_double), ctypes.c_size_t], ctypes.c_int),
         "gp_debug_sweep_times": ([_vp, ctypes.POINTER(_u64), _u64, ctypes.POINTER(_u64),
                                   ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "gp_bounds_from_batch": ([ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_size_t), ctypes.c_size_t,
+                                  ctypes.POINTER(GpBounds)], ctypes.c_int),
+        "gp_driver_create_from_batch": ([ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_size_t),
+                                         ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_vp)], ctypes.c_int),
+        "gp_lower_batch": ([_vp, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_size_t),
+                            ctypes.POINTER(ctypes.POINTER(ctypes.c_double)), ctypes.POINTER(ctypes.c_size_t),
+                            ctypes.c_size_t], ctypes.c_int),
+        "gp_edges_circuits": ([_vp], ctypes.c_uint32),
+        "gp_edges_circuit_ids": ([_vp], ctypes.POINTER(ctypes.c_uint32)),
+        "gp_edges_circuit_shape": ([_vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
+                                    ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
+        "gp_edges_circuit_dem_text": ([_vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -170,6 +184,42 @@ def gp_driver_create_from_circuit(text: str, device: int = 0) -> int:
     h = _vp()
     _check(load().gp_driver_create_from_circuit(raw, len(raw), device, ctypes.byref(h)))
     return h.value
+
+
+def _texts(texts: Sequence[str]):
+    raw = [t.encode() for t in texts]
+    arr = (ctypes.c_char_p * max(len(raw), 1))(*raw)
+    lens = (ctypes.c_size_t * max(len(raw), 1))(*[len(r) for r in raw])
+    return arr, lens, raw
+
+
+def gp_bounds_from_batch(texts: Sequence[str]) -> GpBounds:
+    arr, lens, _keep = _texts(texts)
+    b = GpBounds()
+    _check(load().gp_bounds_from_batch(arr, lens, len(texts), ctypes.byref(b)))
+    return b
+
+
+def gp_driver_create_from_batch(texts: Sequence[str], device: int = 0) -> int:
+    arr, lens, _keep = _texts(texts)
+    h = _vp()
+    _check(load().gp_driver_create_from_batch(arr, lens, len(texts), device, ctypes.byref(h)))
+    return h.value
+
+
+def gp_lower_batch(drv: int, texts: Sequence[str], rates: Optional[Sequence[Optional[Sequence[float]]]] = None) -> None:
+    arr, lens, _keep = _texts(texts)
+    n = len(texts)
+    if rates is None:
+        _check(load().gp_lower_batch(drv, arr, lens, None, None, n))
+        return
+    if len(rates) != n:
+        raise ValueError("one rate array (or None) per circuit")
+    dp = ctypes.POINTER(ctypes.c_double)
+    keep = [None if r is None else np.ascontiguousarray(r, dtype=np.float64) for r in rates]
+    ptrs = (dp * max(n, 1))(*[dp() if r is None else r.ctypes.data_as(dp) for r in keep])
+    nr = (ctypes.c_size_t * max(n, 1))(*[0 if r is None else len(r) for r in keep])
+    _check(load().gp_lower_batch(drv, arr, lens, ptrs, nr, n))
 
 
 def gp_driver_destroy(drv: int) -> None:
@@ -270,6 +320,34 @@ def gp_edges_to_dem_text(e: int) -> str:
     p = ctypes.c_void_p()
     n = ctypes.c_size_t()
     _check(load().gp_edges_to_dem_text(e, ctypes.byref(p), ctypes.byref(n)))
+    try:
+        return ctypes.string_at(p.value, n.value).decode() if n.value else ""
+    finally:
+        load().gp_free(p)
+
+
+def gp_edges_circuits(e: int) -> int:
+    return int(load().gp_edges_circuits(e))
+
+
+def gp_edges_circuit_ids(e: int) -> np.ndarray:
+    n = gp_edges_count(e)
+    if n == 0:
+        return np.zeros(0, dtype=np.uint32)
+    return np.ctypeslib.as_array(load().gp_edges_circuit_ids(e), shape=(n,)).copy()
+
+
+def gp_edges_circuit_shape(e: int, circuit: int) -> Tuple[int, int]:
+    d = ctypes.c_uint32()
+    o = ctypes.c_uint32()
+    _check(load().gp_edges_circuit_shape(e, circuit, ctypes.byref(d), ctypes.byref(o)))
+    return d.value, o.value
+
+
+def gp_edges_circuit_dem_text(e: int, circuit: int) -> str:
+    p = ctypes.c_void_p()
+    n = ctypes.c_size_t()
+    _check(load().gp_edges_circuit_dem_text(e, circuit, ctypes.byref(p), ctypes.byref(n)))
     try:
         return ctypes.string_at(p.value, n.value).decode() if n.value else ""
     finally:

@@ -10,7 +10,7 @@ circuit within those bounds.
 from __future__ import annotations
 
 import dataclasses
-from typing import Dict, Optional, Sequence, Tuple
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -50,6 +50,35 @@ def _take(handle: int) -> Hypergraph:
         _gp.gp_edges_free(handle)
 
 
+def _take_batch(handle: int) -> List[Hypergraph]:
+    """Split a batch result into one Hypergraph per circuit (each keeps the
+    relative order its hyperedges had in the result)."""
+    try:
+        off = _gp.gp_edges_offsets(handle)
+        bits = _gp.gp_edges_bits(handle)
+        q = _gp.gp_edges_probabilities(handle)
+        ids = _gp.gp_edges_circuit_ids(handle)
+        shapes = [_gp.gp_edges_circuit_shape(handle, k) for k in range(_gp.gp_edges_circuits(handle))]
+    finally:
+        _gp.gp_edges_free(handle)
+    order = np.argsort(ids, kind="stable")
+    cnt = np.diff(off).astype(np.int64)[order]
+    start = off[:-1].astype(np.int64)[order]
+    new_off = np.zeros(len(order) + 1, dtype=np.int64)
+    np.cumsum(cnt, out=new_off[1:])
+    gather = np.repeat(start - new_off[:-1], cnt) + np.arange(int(new_off[-1]), dtype=np.int64)
+    bits_s = bits[gather]
+    q_s = q[order]
+    cut = np.searchsorted(ids[order], np.arange(len(shapes) + 1))
+    out = []
+    for k, (nd, no) in enumerate(shapes):
+        a, b = int(cut[k]), int(cut[k + 1])
+        o = new_off[a:b + 1]
+        out.append(Hypergraph(n_detectors=nd, n_observables=no, offsets=(o - o[0]).astype(np.uint64),
+                              bits=bits_s[int(o[0]):int(o[-1])].copy(), q=q_s[a:b].copy()))
+    return out
+
+
 class Driver:
     """Owns one gp_driver (device buffers + stream) on one HIP device."""
 
@@ -60,6 +89,11 @@ class Driver:
     @classmethod
     def from_circuit(cls, max_circuit: str, device: int = 0) -> "Driver":
         return cls(_gp.gp_bounds_from_circuit(max_circuit), device)
+
+    @classmethod
+    def from_batch(cls, circuits: Sequence[str], device: int = 0) -> "Driver":
+        """A driver sized for compiling `circuits` together as one batch."""
+        return cls(_gp.gp_bounds_from_batch(circuits), device)
 
     def close(self) -> None:
         if self.handle:
@@ -89,9 +123,24 @@ class Driver:
         finally:
             _gp.gp_edges_free(h)
 
+    def compile_batch(self, circuits: Sequence[str],
+                      rates: Optional[Sequence[Optional[Sequence[float]]]] = None) -> List[Hypergraph]:
+        """Compile several circuits in one pass of each stage; one Hypergraph
+        per circuit, each equal to what compiling that circuit alone gives."""
+        self.lower_batch(circuits, rates)
+        self.run()
+        return self.fetch_batch()
+
     # split path
     def lower(self, circuit: str, rates: Optional[Sequence[float]] = None) -> None:
         _gp.gp_lower(self.handle, circuit, rates)
+
+    def lower_batch(self, circuits: Sequence[str],
+                    rates: Optional[Sequence[Optional[Sequence[float]]]] = None) -> None:
+        _gp.gp_lower_batch(self.handle, circuits, rates)
+
+    def fetch_batch(self) -> List[Hypergraph]:
+        return _take_batch(_gp.gp_fetch(self.handle))
 
     def run(self) -> None:
         _gp.gp_run(self.handle)

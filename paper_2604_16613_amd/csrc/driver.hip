@@ -39,55 +39,68 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 uint32_t words_for(uint32_t det, uint32_t obs) { return (det + 63) / 64 + (obs + 63) / 64; }
 
-// Layout of the per-circuit input tables inside one device arena and one
+// Layout of the per-compile input tables inside one device arena and one
 // pinned host buffer of the same shape, so one copy uploads them all.
 struct TableLayout {
   size_t ops, layer_off, leaf_off, leaf_bits, chan_qa, chan_qb, chan_kind, chan_rate, chan_foff, bnd_chan_off,
       bnd_fault_off, col_top, col_lo, col_base, item_col, item_blo, item_bhi, fnv_pow, ops32, inj_off, inj_layer,
       inj_qubit, inj_word, inj_next, hchunk_pos, hchunk_bnd, bnd_bm_off, col_bm_base, layer_win, win_lo, win_obase,
-      win_cnt, total;
+      win_cnt, branch, item_branch, hchunk_branch, total;
 };
 
-TableLayout layout_for(uint64_t ops, uint32_t layers, uint32_t meas, uint64_t leaf_bits, uint64_t chans, uint32_t w,
-                       uint64_t items, uint64_t hchunks) {
+// Entry counts of the tables: exact for a lowering, upper bounds for a driver.
+struct TableSizes {
+  uint64_t ops, layer_entries, leaf_offs, leaf_bits, chans, bnd_entries, cols, items, fnv, hchunks, windows, branches;
+};
+
+TableSizes sizes_of(const gp::Lowered& lw) {
+  return {lw.ops.size(), lw.layer_off.size(), lw.leaf_off.size(), lw.leaf_bits.size(), lw.chan_kind.size(),
+          lw.bnd_fault_off.size(), lw.col_top.size(), lw.item_col.size(), lw.fnv_pow.size(), lw.hchunk_pos.size(),
+          lw.win_lo.size(), lw.branches.size()};
+}
+
+TableLayout layout_for(const TableSizes& z) {
   TableLayout t{};
   size_t o = 0;
   auto take = [&](size_t& f, size_t bytes) {
     f = o;
     o += align_up(bytes ? bytes : 1);
   };
-  take(t.ops, ops * 8);
-  take(t.layer_off, (size_t(layers) + 1) * 4);
-  take(t.leaf_off, (size_t(meas) + 1) * 4);
-  take(t.leaf_bits, leaf_bits * 4);
-  take(t.chan_qa, chans * 4);
-  take(t.chan_qb, chans * 4);
-  take(t.chan_kind, chans);
-  take(t.chan_rate, chans * 8);
-  take(t.chan_foff, (chans + 1) * 4);
-  take(t.bnd_chan_off, (size_t(layers) + 2) * 4);
-  take(t.bnd_fault_off, (size_t(layers) + 2) * 4);
-  take(t.col_top, size_t(w) * 4);
-  take(t.col_lo, size_t(w) * 4);
-  take(t.col_base, size_t(w) * 8);
-  take(t.item_col, items * 4);
-  take(t.item_blo, items * 4);
-  take(t.item_bhi, items * 4);
-  take(t.fnv_pow, (size_t(w) + 1) * 8);
-  take(t.ops32, ops * 4);
-  take(t.inj_off, (size_t(w) + 1) * 4);
-  take(t.inj_layer, leaf_bits * 4);
-  take(t.inj_qubit, leaf_bits * 4);
-  take(t.inj_word, leaf_bits * 8);
-  take(t.inj_next, leaf_bits * 4);
-  take(t.hchunk_pos, hchunks * 4);
-  take(t.hchunk_bnd, hchunks * 4);
-  take(t.bnd_bm_off, (size_t(layers) + 2) * 4);
-  take(t.col_bm_base, size_t(w) * 8);
-  take(t.layer_win, (size_t(layers) + 1) * 4);
-  take(t.win_lo, (size_t(layers) + 1) * 4);
-  take(t.win_obase, (size_t(layers) + 1) * 4);
-  take(t.win_cnt, (size_t(layers) + 1) * 4);
+  take(t.ops, z.ops * 8);
+  take(t.layer_off, z.layer_entries * 4);
+  take(t.leaf_off, z.leaf_offs * 4);
+  take(t.leaf_bits, z.leaf_bits * 4);
+  take(t.chan_qa, z.chans * 4);
+  take(t.chan_qb, z.chans * 4);
+  take(t.chan_kind, z.chans);
+  take(t.chan_rate, z.chans * 8);
+  take(t.chan_foff, (z.chans + 1) * 4);
+  take(t.bnd_chan_off, z.bnd_entries * 4);
+  take(t.bnd_fault_off, z.bnd_entries * 4);
+  take(t.col_top, z.cols * 4);
+  take(t.col_lo, z.cols * 4);
+  take(t.col_base, z.cols * 8);
+  take(t.item_col, z.items * 4);
+  take(t.item_blo, z.items * 4);
+  take(t.item_bhi, z.items * 4);
+  take(t.fnv_pow, z.fnv * 8);
+  take(t.ops32, z.ops * 4);
+  take(t.inj_off, (z.cols + 1) * 4);
+  take(t.inj_layer, z.leaf_bits * 4);
+  take(t.inj_qubit, z.leaf_bits * 4);
+  take(t.inj_word, z.leaf_bits * 8);
+  take(t.inj_next, z.leaf_bits * 4);
+  take(t.hchunk_pos, z.hchunks * 4);
+  take(t.hchunk_bnd, z.hchunks * 4);
+  take(t.bnd_bm_off, z.bnd_entries * 4);
+  take(t.col_bm_base, z.cols * 8);
+  take(t.layer_win, z.layer_entries * 4);
+  take(t.win_lo, z.windows * 4);
+  take(t.win_obase, z.windows * 4);
+  take(t.win_cnt, z.windows * 4);
+  take(t.branch, z.branches * sizeof(gp::BranchDesc));
+  take(t.item_branch, z.items * 4);
+  take(t.hchunk_branch, z.hchunks * 4);
   t.total = o;
   return t;
 }
@@ -100,10 +113,12 @@ struct TimedLaunch {
 }  // namespace
 
 struct gp_edges {
-  uint32_t n_det = 0, n_obs = 0;
+  uint32_t n_det = 0, n_obs = 0;      // most detectors / observables of any circuit
   std::vector<uint64_t> off;
   std::vector<uint32_t> bits;
   std::vector<double> q;
+  std::vector<uint32_t> circuit;      // per hyperedge: its circuit in the batch
+  std::vector<uint32_t> c_det, c_obs; // per circuit: detectors, observables
 };
 
 struct gp_driver {
@@ -191,7 +206,18 @@ void collect_timing(gp_driver* d) {
   d->pending.clear();
 }
 
-uint64_t hash_chunk_cap(const gp_bounds& b) { return b.max_faults / 256 + uint64_t(b.max_layers) + 2; }
+uint32_t branches_of(const gp_bounds& b) { return std::max<uint32_t>(b.max_branches, 1); }
+
+uint64_t hash_chunk_cap(const gp_bounds& b) {
+  return b.max_faults / 256 + uint64_t(branches_of(b)) * (uint64_t(b.max_layers) + 2);
+}
+
+// Table capacities of a driver: per-circuit maxima times the circuits of a batch.
+TableSizes sizes_cap(const gp_bounds& b, uint32_t max_w) {
+  const uint64_t B = branches_of(b), L = b.max_layers;
+  return {b.max_ops, B * (L + 1), uint64_t(b.max_measurements) + B, b.max_leaf_bits, b.max_channels, B * (L + 2),
+          B * max_w, b.max_items, uint64_t(max_w) + 1, hash_chunk_cap(b), B * (L + 1), B};
+}
 
 int check_bounds(const gp_driver* d, const gp::Lowered& lw) {
   const gp_bounds& b = d->bounds;
@@ -200,6 +226,7 @@ int check_bounds(const gp_driver* d, const gp::Lowered& lw) {
     std::snprintf(msg, sizeof msg, "circuit exceeds the driver bounds: %s %" PRIu64 " > %" PRIu64, what, have, cap);
     return fail(GP_E_BOUNDS, msg);
   };
+  if (lw.branches.size() > branches_of(b)) return over("circuits in a batch", lw.branches.size(), branches_of(b));
   if (lw.n_qubits > b.max_qubits) return over("qubits", lw.n_qubits, b.max_qubits);
   if (lw.n_layers > b.max_layers) return over("layers", lw.n_layers, b.max_layers);
   if (lw.n_meas > b.max_measurements) return over("measurements", lw.n_meas, b.max_measurements);
@@ -214,10 +241,12 @@ int check_bounds(const gp_driver* d, const gp::Lowered& lw) {
   if (lw.bm_words > d->bm_cap) return over("non-zero-word bitmap words", lw.bm_words, d->bm_cap);
   for (uint32_t c : lw.win_cnt)
     if (c > gp::kSweepWinOps) return over("operations in one layer (sweep op window)", c, gp::kSweepWinOps);
-  if (lw.w > d->max_w) return over("signature words", lw.w, d->max_w);
-  if (lw.w > gp::kMaxHashWords) return over("signature words for the hash kernel", lw.w, gp::kMaxHashWords);
+  if (lw.w_max > d->max_w) return over("signature words", lw.w_max, d->max_w);
+  if (lw.w_max > gp::kMaxHashWords) return over("signature words for the hash kernel", lw.w_max, gp::kMaxHashWords);
   if (lw.n_qubits > gp::kMaxSweepQubits) return over("qubits for the compact op words", lw.n_qubits, gp::kMaxSweepQubits);
   if (lw.hchunk_pos.size() > hash_chunk_cap(b)) return over("hash chunks", lw.hchunk_pos.size(), hash_chunk_cap(b));
+  if (layout_for(sizes_of(lw)).total > d->tables_cap)
+    return over("table bytes", layout_for(sizes_of(lw)).total, d->tables_cap);
   if (gp::sweep_lds_bytes(lw.n_qubits) > gp::sweep_lds_limit())
     return over("LDS bytes for the qubit frame", gp::sweep_lds_bytes(lw.n_qubits), gp::sweep_lds_limit());
   return GP_OK;
@@ -234,11 +263,36 @@ void fill_bounds(const gp::Lowered& lw, gp_bounds* out) {
   b.max_faults = lw.n_faults;
   b.max_ops = lw.ops.size();
   b.max_leaf_bits = lw.leaf_bits.size();
+  b.max_branches = uint32_t(lw.branches.size());
   // any circuit within these bounds needs at most one word per (fault, column)
-  b.max_slab_words = std::max<uint64_t>(lw.slab_words, lw.n_faults * uint64_t(lw.w));
+  b.max_slab_words = std::max<uint64_t>(lw.slab_words, lw.n_faults * uint64_t(lw.w_max));
   // detector columns one item each; observable ranges fill the slots left
-  b.max_items = std::max<uint64_t>(gp::kSweepSlots, lw.w) + 16;
+  b.max_items = uint64_t(b.max_branches) * (std::max<uint64_t>(gp::kSweepSlots, lw.w_max) + 16);
   *out = b;
+}
+
+// Lower every circuit of a batch (each with its share of the sweep slots) and
+// merge them; `rates` may be null (rates written in the texts), as may any rates[k].
+int lower_batch(const char* const* texts, const size_t* lens, const double* const* rates, const size_t* n_rates,
+                size_t n, uint32_t level, gp::Lowered& out) {
+  if ((!texts || !lens) && n) return fail(GP_E_ARG, "null argument");
+  if (n == 0) return fail(GP_E_ARG, "a batch needs at least one circuit");
+  if (rates && !n_rates) return fail(GP_E_ARG, "rate arrays without their lengths");
+  if (n > (1u << 20)) return fail(GP_E_BOUNDS, "at most 2^20 circuits in one batch");
+  const uint32_t slots = std::max<uint32_t>(1, uint32_t((gp::kSweepSlots + n - 1) / n));
+  std::vector<gp::Lowered> parts(n);
+  for (size_t k = 0; k < n; k++) {
+    if (!texts[k]) return fail(GP_E_ARG, "null circuit text in the batch");
+    gp::LowerError err{};
+    const double* r = rates ? rates[k] : nullptr;
+    int rc = gp::lower_circuit(texts[k], lens[k], r, r ? n_rates[k] : 0, slots, parts[k], err, level);
+    if (rc) return fail(rc, "circuit " + std::to_string(k) + " of the batch: " + err.msg);
+  }
+  uint64_t faults = 0;
+  for (const gp::Lowered& a : parts) faults += a.n_faults;
+  if (faults >= (1ull << 30)) return fail(GP_E_BOUNDS, "at most 2^30 - 1 faults in one batch");
+  gp::merge_branches(parts, out);
+  return GP_OK;
 }
 
 }  // namespace
@@ -296,13 +350,14 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   gp_bounds& b = d->bounds;
   b.max_layers = std::max<uint32_t>(b.max_layers, 1);
   b.max_faults = std::max<uint64_t>(b.max_faults, 1);
+  b.max_branches = branches_of(b);
   if (b.max_faults >= (1ull << 30)) {
     delete d;
-    return fail(GP_E_BOUNDS, "at most 2^30 - 1 faults per circuit");
+    return fail(GP_E_BOUNDS, "at most 2^30 - 1 faults per compile");
   }
   d->max_w = std::max<uint32_t>(words_for(b.max_detectors, b.max_observables), 1);
   if (!b.max_slab_words) b.max_slab_words = b.max_faults * d->max_w;
-  if (!b.max_items) b.max_items = std::max<uint64_t>(gp::kSweepSlots, d->max_w) + 16;
+  if (!b.max_items) b.max_items = uint64_t(branches_of(b)) * (std::max<uint64_t>(gp::kSweepSlots, d->max_w) + 16);
   d->bits_cap = std::max<uint64_t>(b.max_faults * 8, 1u << 20);
   d->max_tiles = uint32_t((b.max_faults + 4095) / 4096) + 1;
 
@@ -314,8 +369,7 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   if (hipStreamCreateWithFlags(&d->stream, hipStreamNonBlocking) != hipSuccess)
     return cleanup(hip_fail(hipGetLastError(), "hipStreamCreate"));
 
-  TableLayout tl = layout_for(b.max_ops, b.max_layers, b.max_measurements, b.max_leaf_bits, b.max_channels, d->max_w,
-                              b.max_items, hash_chunk_cap(b));
+  TableLayout tl = layout_for(sizes_cap(b, d->max_w));
   d->tables_cap = tl.total;
   if ((rc = dev_alloc(d, &d->d_tables, d->tables_cap, "tables"))) return cleanup(rc);
   if (hipHostMalloc(reinterpret_cast<void**>(&d->h_tables), d->tables_cap, hipHostMallocDefault) != hipSuccess)
@@ -329,11 +383,12 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   if ((rc = dev_alloc(d, &slab, b.max_slab_words, "signature slab"))) return cleanup(rc);
   st.slab = slab;
   // a column's bitmaps take at most (its slab words) / 64 + (boundaries) words
-  d->bm_cap = b.max_slab_words / 64 + uint64_t(d->max_w) * (uint64_t(b.max_layers) + 2);
+  d->bm_cap = b.max_slab_words / 64 + uint64_t(branches_of(b)) * d->max_w * (uint64_t(b.max_layers) + 2);
   if ((rc = dev_alloc(d, &st.bm, d->bm_cap, "non-zero-word bitmaps"))) return cleanup(rc);
-  if ((rc = dev_alloc(d, &st.cover_lo, d->max_w, "cover_lo"))) return cleanup(rc);
-  if ((rc = dev_alloc(d, &st.cov, (size_t(b.max_layers) + 1) * d->max_w, "cover lists"))) return cleanup(rc);
-  if ((rc = dev_alloc(d, &st.ncov, size_t(b.max_layers) + 1, "cover counts"))) return cleanup(rc);
+  const size_t bnd_rows = size_t(branches_of(b)) * (size_t(b.max_layers) + 2);
+  if ((rc = dev_alloc(d, &st.cover_lo, size_t(branches_of(b)) * d->max_w, "cover_lo"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.cov, bnd_rows * d->max_w, "cover lists"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.ncov, bnd_rows, "cover counts"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.frp, F, "fault probabilities and check hashes"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.frec, F, "fault records"))) return cleanup(rc);
   for (int k = 0; k < 2; k++) {
@@ -367,11 +422,12 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   if ((rc = dev_alloc(d, &st.edge_off32, F + 1, "edge offsets"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.edge_bits, d->bits_cap, "edge bits"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.edge_q, F, "edge probabilities"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.edge_branch, F, "edge circuits"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.hdr, 1, "header"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.item_clock, 2 * b.max_items, "item clocks"))) return cleanup(rc);
   st.bits_cap = d->bits_cap;
-  // download staging: offsets + bits + probabilities of the largest result
-  d->h_out_cap = (F + 1) * 4 + d->bits_cap * 4 + F * 8 + 3 * kAlign;
+  // download staging: offsets + bits + probabilities + circuits of the largest result
+  d->h_out_cap = (F + 1) * 4 + d->bits_cap * 4 + F * 8 + F * 4 + 4 * kAlign;
   if (hipHostMalloc(&d->h_out, d->h_out_cap, hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(GP_E_OOM, "pinned host allocation failed"));
   *out = d;
@@ -385,21 +441,32 @@ int gp_driver_create_from_circuit(const char* text, size_t len, int device, gp_d
   return gp_driver_create(&b, device, out);
 }
 
-int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, size_t n_rates) {
-  if (!d || !text) return fail(GP_E_ARG, "null argument");
-  gp::LowerError err{};
-  d->lowered = false;
-  d->ran = false;
-  d->structured = false;
-  int rc = gp::lower_circuit(text, len, rates, n_rates, gp::kSweepSlots, d->lw, err, d->level);
-  if (rc) return fail(rc, err.msg);
+int gp_bounds_from_batch(const char* const* texts, const size_t* lens, size_t n, gp_bounds* out) {
+  if (!out) return fail(GP_E_ARG, "null argument");
+  gp::Lowered lw;
+  int rc = lower_batch(texts, lens, nullptr, nullptr, n, 2, lw);
+  if (rc) return rc;
+  fill_bounds(lw, out);
+  return GP_OK;
+}
+
+int gp_driver_create_from_batch(const char* const* texts, const size_t* lens, size_t n, int device,
+                                gp_driver** out) {
+  gp_bounds b;
+  int rc = gp_bounds_from_batch(texts, lens, n, &b);
+  if (rc) return rc;
+  return gp_driver_create(&b, device, out);
+}
+
+// Upload a lowering (one circuit, or a merged batch) and point the device state at it.
+static int upload_lowered(gp_driver* d) {
+  int rc;
   if ((rc = check_bounds(d, d->lw))) return rc;
   const gp::Lowered& lw = d->lw;
   HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
   // the previous compile may still read the pinned buffer
   HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
-  TableLayout tl = layout_for(lw.ops.size(), lw.n_layers, lw.n_meas, lw.leaf_bits.size(), lw.chan_kind.size(), lw.w,
-                              lw.item_col.size(), lw.hchunk_pos.size());
+  TableLayout tl = layout_for(sizes_of(lw));
   if (tl.total > d->tables_cap) return fail(GP_E_BOUNDS, "lowered tables exceed the driver's table arena");
   char* h = d->h_tables;
   auto put = [&](size_t off, const void* src, size_t bytes) {
@@ -437,6 +504,9 @@ int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, si
   put(tl.win_lo, lw.win_lo.data(), lw.win_lo.size() * 4);
   put(tl.win_obase, lw.win_obase.data(), lw.win_obase.size() * 4);
   put(tl.win_cnt, lw.win_cnt.data(), lw.win_cnt.size() * 4);
+  put(tl.branch, lw.branches.data(), lw.branches.size() * sizeof(gp::BranchDesc));
+  put(tl.item_branch, lw.item_branch.data(), lw.item_branch.size() * 4);
+  put(tl.hchunk_branch, lw.hchunk_branch.data(), lw.hchunk_branch.size() * 4);
   HIP_TRY(hipMemcpyAsync(d->d_tables, d->h_tables, tl.total, hipMemcpyHostToDevice, d->stream), "upload tables");
 
   gp::DevState& st = d->st;
@@ -474,7 +544,13 @@ int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, si
   st.win_lo = reinterpret_cast<const uint32_t*>(D + tl.win_lo);
   st.win_obase = reinterpret_cast<const uint32_t*>(D + tl.win_obase);
   st.win_cnt = reinterpret_cast<const uint32_t*>(D + tl.win_cnt);
-  st.n_win = uint32_t(lw.win_lo.size());
+  st.branch = reinterpret_cast<const gp::BranchDesc*>(D + tl.branch);
+  st.item_branch = reinterpret_cast<const uint32_t*>(D + tl.item_branch);
+  st.hchunk_branch = reinterpret_cast<const uint32_t*>(D + tl.hchunk_branch);
+  st.n_branch = uint32_t(lw.branches.size());
+  st.w_max = lw.w_max;
+  st.n_win = 0;
+  for (const gp::BranchDesc& bd : lw.branches) st.n_win = std::max(st.n_win, bd.n_win);
   st.max_col_inj = 0;
   for (uint32_t w = 0; w < lw.w; w++)
     st.max_col_inj = std::max(st.max_col_inj, lw.inj_off[w + 1] - lw.inj_off[w]);
@@ -489,6 +565,29 @@ int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, si
   st.level = lw.level;
   d->lowered = true;
   return GP_OK;
+}
+
+
+int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, size_t n_rates) {
+  if (!d || !text) return fail(GP_E_ARG, "null argument");
+  gp::LowerError err{};
+  d->lowered = false;
+  d->ran = false;
+  d->structured = false;
+  int rc = gp::lower_circuit(text, len, rates, n_rates, gp::kSweepSlots, d->lw, err, d->level);
+  if (rc) return fail(rc, err.msg);
+  return upload_lowered(d);
+}
+
+int gp_lower_batch(gp_driver* d, const char* const* texts, const size_t* lens, const double* const* rates,
+                   const size_t* n_rates, size_t n) {
+  if (!d) return fail(GP_E_ARG, "null driver");
+  d->lowered = false;
+  d->ran = false;
+  d->structured = false;
+  int rc = lower_batch(texts, lens, rates, n_rates, n, d->level, d->lw);
+  if (rc) return rc;
+  return upload_lowered(d);
 }
 
 int gp_run(gp_driver* d) {
@@ -568,10 +667,14 @@ int gp_fetch(gp_driver* d, gp_edges** out) {
   const uint64_t nb = hdr.n_bits;
   char* h = static_cast<char*>(d->h_out);
   const size_t o_off = 0, o_bits = align_up((U + 1) * 4), o_q = o_bits + align_up(nb * 4);
-  if (o_q + U * 8 > d->h_out_cap) return fail(GP_E_BOUNDS, "result exceeds the download staging buffer");
+  const size_t o_c = o_q + align_up(U * 8);
+  const bool batch = d->lw.branches.size() > 1;
+  if (o_c + U * 4 > d->h_out_cap) return fail(GP_E_BOUNDS, "result exceeds the download staging buffer");
   HIP_TRY(hipMemcpyAsync(h + o_off, d->st.edge_off32, (U + 1) * 4, hipMemcpyDeviceToHost, d->stream), "download");
   if (nb) HIP_TRY(hipMemcpyAsync(h + o_bits, d->st.edge_bits, nb * 4, hipMemcpyDeviceToHost, d->stream), "download");
   if (U) HIP_TRY(hipMemcpyAsync(h + o_q, d->st.edge_q, U * 8, hipMemcpyDeviceToHost, d->stream), "download");
+  if (U && batch)
+    HIP_TRY(hipMemcpyAsync(h + o_c, d->st.edge_branch, U * 4, hipMemcpyDeviceToHost, d->stream), "download");
   HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
   gp_edges* e = new gp_edges();
   e->n_det = d->lw.n_det;
@@ -581,6 +684,14 @@ int gp_fetch(gp_driver* d, gp_edges** out) {
   for (uint64_t i = 0; i <= U; i++) e->off[i] = off32[i];
   e->bits.assign(reinterpret_cast<const uint32_t*>(h + o_bits), reinterpret_cast<const uint32_t*>(h + o_bits) + nb);
   e->q.assign(reinterpret_cast<const double*>(h + o_q), reinterpret_cast<const double*>(h + o_q) + U);
+  if (batch)
+    e->circuit.assign(reinterpret_cast<const uint32_t*>(h + o_c), reinterpret_cast<const uint32_t*>(h + o_c) + U);
+  else
+    e->circuit.assign(U, 0u);
+  for (const gp::BranchDesc& bd : d->lw.branches) {
+    e->c_det.push_back(bd.n_det);
+    e->c_obs.push_back(bd.n_obs);
+  }
   *out = e;
   d->structured = true;
   d->struct_edges = U;
@@ -601,8 +712,7 @@ int gp_refresh_rates(gp_driver* d, const double* rates, size_t n_rates) {
     lw.chan_rate = old;
     return fail(rc, err.msg);
   }
-  TableLayout tl = layout_for(lw.ops.size(), lw.n_layers, lw.n_meas, lw.leaf_bits.size(), lw.chan_kind.size(), lw.w,
-                              lw.item_col.size(), lw.hchunk_pos.size());
+  TableLayout tl = layout_for(sizes_of(lw));
   const size_t bytes = lw.chan_rate.size() * 8;
   if (bytes) {
     std::memcpy(d->h_tables + tl.chan_rate, lw.chan_rate.data(), bytes);
@@ -659,6 +769,7 @@ int gp_circuit_info_get(const gp_driver* d, gp_circuit_info* out) {
   i.n_ops = lw.ops.size();
   i.n_items = lw.item_col.size();
   i.slab_words = lw.slab_words;
+  i.n_circuits = uint32_t(lw.branches.size());
   if (d->h_hdr) {
     i.n_classes = d->h_hdr->n_seg;
     i.n_edges = d->h_hdr->n_edges;
@@ -741,21 +852,40 @@ uint32_t gp_edges_observables(const gp_edges* e) { return e ? e->n_obs : 0; }
 const uint64_t* gp_edges_offsets(const gp_edges* e) { return e ? e->off.data() : nullptr; }
 const uint32_t* gp_edges_bits(const gp_edges* e) { return e ? e->bits.data() : nullptr; }
 const double* gp_edges_probabilities(const gp_edges* e) { return e ? e->q.data() : nullptr; }
+uint32_t gp_edges_circuits(const gp_edges* e) { return e ? uint32_t(e->c_det.size()) : 0; }
+const uint32_t* gp_edges_circuit_ids(const gp_edges* e) { return e ? e->circuit.data() : nullptr; }
+
+int gp_edges_circuit_shape(const gp_edges* e, uint32_t k, uint32_t* n_det, uint32_t* n_obs) {
+  if (!e) return fail(GP_E_ARG, "null argument");
+  if (k >= e->c_det.size()) return fail(GP_E_ARG, "circuit index out of range");
+  if (n_det) *n_det = e->c_det[k];
+  if (n_obs) *n_obs = e->c_obs[k];
+  return GP_OK;
+}
 
 int gp_edges_to_dem_text(const gp_edges* e, char** text, size_t* len) {
   if (!e || !text) return fail(GP_E_ARG, "null argument");
+  if (e->c_det.size() > 1) return fail(GP_E_STATE, "a batch result: use gp_edges_circuit_dem_text");
+  return gp_edges_circuit_dem_text(e, 0, text, len);
+}
+
+int gp_edges_circuit_dem_text(const gp_edges* e, uint32_t circuit, char** text, size_t* len) {
+  if (!e || !text) return fail(GP_E_ARG, "null argument");
+  if (circuit >= std::max<size_t>(e->c_det.size(), 1)) return fail(GP_E_ARG, "circuit index out of range");
+  const uint32_t n_det = e->c_det.empty() ? e->n_det : e->c_det[circuit];
   std::string s;
   s.reserve(e->q.size() * 32);
   char buf[64];
   for (size_t k = 0; k < e->q.size(); k++) {
+    if (e->circuit[k] != circuit) continue;
     std::snprintf(buf, sizeof buf, "error(%.17g)", e->q[k]);
     s += buf;
     for (uint64_t i = e->off[k]; i < e->off[k + 1]; i++) {
       uint32_t b = e->bits[i];
-      if (b < e->n_det)
+      if (b < n_det)
         std::snprintf(buf, sizeof buf, " D%u", b);
       else
-        std::snprintf(buf, sizeof buf, " L%u", b - e->n_det);
+        std::snprintf(buf, sizeof buf, " L%u", b - n_det);
       s += buf;
     }
     s += '\n';

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 
+#include "lower.h"
+
 namespace gp {
 
 // Device-side status block shared by the kernels of one compile.
@@ -80,13 +82,19 @@ struct DevState {
   const uint32_t* hchunk_bnd;
   const uint32_t* bnd_bm_off;  // per boundary: first word of its bitmap within a column's bitmaps
   const uint64_t* col_bm_base; // per column: first word of its bitmaps
+  const BranchDesc* branch;    // per circuit of the batch
+  const uint32_t* item_branch; // per sweep item / hash chunk: its circuit
+  const uint32_t* hchunk_branch;
   const uint32_t* layer_win;   // per layer: its op window
   const uint32_t* win_lo;      // per op window: lowest layer, first op, op count
   const uint32_t* win_obase;
   const uint32_t* win_cnt;
 
   // sizes
+  // most qubits / layers / op windows of any circuit; word columns in all and
+  // in the widest circuit; circuits in the batch
   uint32_t n_qubits, n_layers, n_det, wd, w;
+  uint32_t w_max, n_branch;
   uint32_t n_chan, n_items;
   uint32_t n_faults;
   uint32_t n_hchunks;
@@ -105,7 +113,7 @@ struct DevState {
   uint64_t* slab;        // stage-1 signature words, column slabs (only non-zero words are stored)
   uint64_t* bm;          // per (column, boundary): one bit per fault position, set where the word is non-zero
   int32_t* cover_lo;     // per column: lowest boundary written
-  uint32_t* cov;         // per boundary: covered columns, ascending ((L+1) x W)
+  uint32_t* cov;         // per boundary row: covered columns, ascending (rows of w_max)
   uint32_t* ncov;        // per boundary: number of covered columns
   FaultRec* frp;         // per fault position: probability and check hash
   uint32_t* frec;        // per fault position: qubit a | qubit b << 14 | Pauli code << 28
@@ -137,6 +145,7 @@ struct DevState {
   uint32_t* seg_off;     // exclusive prefix of seg_cnt
   uint32_t* edge_off32;  // per hyperedge: first bit (n_edges + 1)
   uint32_t* edge_bits;   // output signature bits (external numbering)
+  uint32_t* edge_branch; // output: circuit of each hyperedge
   double* edge_q;        // output probabilities
   uint64_t bits_cap;
   DevHeader* hdr;

@@ -41,6 +41,7 @@ constexpr int kPre = kWinOps / kSweepBlock;
 constexpr int kLofsMax = 2048;         // layer offsets staged in LDS when the circuit has fewer layers
 constexpr int kInjLds = 512;           // a column's injections staged in LDS when it has at most this many
 constexpr int kWinTableLds = 512;      // op windows whose table is staged in LDS
+constexpr int kBranchLds = 1024;       // circuits of a batch whose first fault the edge writer stages in LDS
 constexpr int kBlock = 256;
 constexpr int kPerThread = kTile / kBlock;
 constexpr int kScanSingleBlock = 1024;
@@ -325,7 +326,17 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   __shared__ int s_wnz[2][kSweepBlock / 64];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const uint32_t n = st.n_qubits;
+  const uint32_t item = blockIdx.x;
+  const BranchDesc br = st.branch[st.item_branch[item]];
+  const uint32_t n = br.n_qubits;
+  // this circuit's layer, boundary and window tables
+  const uint32_t* layer_off = st.layer_off + br.lob;
+  const uint32_t* layer_win = st.layer_win + br.lob;
+  const uint32_t* bnd_fault_off = st.bnd_fault_off + br.bb;
+  const uint32_t* bnd_bm_off = st.bnd_bm_off + br.bb;
+  const uint32_t* win_lo = st.win_lo + br.wib;
+  const uint32_t* win_obase = st.win_obase + br.wib;
+  const uint32_t* win_cnt = st.win_cnt + br.wib;
   uint64_t* frame = lds;
   uint64_t* pend = frame + 2 * size_t(n);  // two buffers, by layer parity
   uint64_t* sinj_w = pend + 2 * size_t(n);
@@ -338,7 +349,6 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   uint32_t* sinj_n = sinj_q + kInjLds;
   uint32_t* swin = sinj_n + kInjLds;  // per op window: lowest layer, first op, op count
 
-  const uint32_t item = blockIdx.x;
   if (tid == 0) st.item_clock[2 * item] = wall_clock64();
   const uint32_t w = st.item_col[item];
   const int top = st.col_top[w];
@@ -357,10 +367,10 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
 
   for (uint32_t i = tid; i < 4 * n; i += kSweepBlock) frame[i] = 0;  // frame and both pend buffers
   if (lofs_lds)
-    for (uint32_t k = tid; k <= st.n_layers + 1; k += kSweepBlock) {
-      if (k <= st.n_layers) slofs[k] = st.layer_off[k];
-      sbfo[k] = st.bnd_fault_off[k];
-      sbmo[k] = st.bnd_bm_off[k];
+    for (uint32_t k = tid; k <= br.n_layers + 1; k += kSweepBlock) {
+      if (k <= br.n_layers) slofs[k] = layer_off[k];
+      sbfo[k] = bnd_fault_off[k];
+      sbmo[k] = bnd_bm_off[k];
     }
   if (inj_lds)
     for (uint32_t k = tid; k < ni; k += kSweepBlock) {
@@ -372,26 +382,26 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   // the window table sits in LDS (kStaged): reading it from global memory with
   // scalar loads would make the next LDS wait also wait for them
   if (lofs_lds)
-    for (uint32_t k = tid; k < st.n_win; k += kSweepBlock) {
-      swin[3 * k] = st.win_lo[k];
-      swin[3 * k + 1] = st.win_obase[k];
-      swin[3 * k + 2] = st.win_cnt[k];
+    for (uint32_t k = tid; k < br.n_win; k += kSweepBlock) {
+      swin[3 * k] = win_lo[k];
+      swin[3 * k + 1] = win_obase[k];
+      swin[3 * k + 2] = win_cnt[k];
     }
-  auto WLO = [&](int k) -> uint32_t { return lofs_lds ? swin[3 * k] : st.win_lo[k]; };
-  auto WOB = [&](int k) -> uint32_t { return lofs_lds ? swin[3 * k + 1] : st.win_obase[k]; };
-  auto WCN = [&](int k) -> uint32_t { return lofs_lds ? swin[3 * k + 2] : st.win_cnt[k]; };
+  auto WLO = [&](int k) -> uint32_t { return lofs_lds ? swin[3 * k] : win_lo[k]; };
+  auto WOB = [&](int k) -> uint32_t { return lofs_lds ? swin[3 * k + 1] : win_obase[k]; };
+  auto WCN = [&](int k) -> uint32_t { return lofs_lds ? swin[3 * k + 2] : win_cnt[k]; };
   // the op window holding the top layer, loaded directly
-  int wid = int(st.layer_win[top]);
-  uint32_t o_base = st.win_obase[wid];
-  int wlo = int(st.win_lo[wid]);
+  int wid = int(layer_win[top]);
+  uint32_t o_base = win_obase[wid];
+  int wlo = int(win_lo[wid]);
   {
-    const uint32_t cnt = st.win_cnt[wid];
+    const uint32_t cnt = win_cnt[wid];
     for (uint32_t i = tid; i < cnt; i += kSweepBlock) opbuf[i] = st.ops32[o_base + i];
   }
   __syncthreads();
-  auto LO = [&](int t) -> uint32_t { return lofs_lds ? slofs[t] : st.layer_off[t]; };
-  auto BFO = [&](int t) -> uint32_t { return lofs_lds ? sbfo[t] : st.bnd_fault_off[t]; };
-  auto BMO = [&](int t) -> uint32_t { return lofs_lds ? sbmo[t] : st.bnd_bm_off[t]; };
+  auto LO = [&](int t) -> uint32_t { return lofs_lds ? slofs[t] : layer_off[t]; };
+  auto BFO = [&](int t) -> uint32_t { return lofs_lds ? sbfo[t] : bnd_fault_off[t]; };
+  auto BMO = [&](int t) -> uint32_t { return lofs_lds ? sbmo[t] : bnd_bm_off[t]; };
   auto INJ_L = [&](uint32_t k) -> int { return int(inj_lds ? sinj_l[k] : st.inj_layer[i0 + k]); };
   auto INJ_Q = [&](uint32_t k) -> uint32_t { return inj_lds ? sinj_q[k] : st.inj_qubit[i0 + k]; };
   auto INJ_W = [&](uint32_t k) -> uint64_t { return inj_lds ? sinj_w[k] : st.inj_word[i0 + k]; };
@@ -585,44 +595,47 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
 // then loads only its fault's non-zero words, up to eight at once.
 __global__ __launch_bounds__(kBlock) void k_hash(DevState st) {
   extern __shared__ __align__(16) uint64_t hlds[];
-  const uint32_t W = st.w;
+  const uint32_t bi = st.hchunk_branch[blockIdx.x];
+  const BranchDesc br = st.branch[bi];
+  const uint32_t W = br.nw;  // this circuit's word columns (the LDS holds the widest circuit's)
   uint64_t* s_pow = hlds;                  // W + 1
   uint64_t* s_base = s_pow + W + 1;        // W: slab base of each covered column
   uint64_t* s_bmb = s_base + W;            // W: bitmap base of each covered column at this boundary
   uint64_t* s_bm = s_bmb + W;              // W * kHashBmw: the bitmap words this chunk spans
   uint32_t* s_w = reinterpret_cast<uint32_t*>(s_bm + size_t(W) * kHashBmw);  // W: covered columns
   __shared__ uint32_t s_wave[kBlock / 64 + 1];
-  const uint32_t b = st.hchunk_bnd[blockIdx.x];
+  const uint32_t b = st.hchunk_bnd[blockIdx.x];  // the circuit's boundary
+  const uint32_t gb = br.bb + b;                  // its row in the batch's boundary tables
   const uint32_t p0 = st.hchunk_pos[blockIdx.x];
-  const uint32_t fb = st.bnd_fault_off[b];
-  const uint32_t p1 = min(p0 + uint32_t(kBlock), st.bnd_fault_off[b + 1]);
-  const uint32_t bmo = st.bnd_bm_off[b];
-  const uint32_t nwb = st.bnd_bm_off[b + 1] - bmo;  // bitmap words of this boundary
+  const uint32_t fb = st.bnd_fault_off[gb];
+  const uint32_t p1 = min(p0 + uint32_t(kBlock), st.bnd_fault_off[gb + 1]);
+  const uint32_t bmo = st.bnd_bm_off[gb];
+  const uint32_t nwb = st.bnd_bm_off[gb + 1] - bmo;  // bitmap words of this boundary
   const uint32_t wb0 = (p0 - fb) >> 6;              // first of them this chunk touches
   const bool first_chunk = p0 == fb;
   for (uint32_t k = threadIdx.x; k <= W; k += kBlock) s_pow[k] = st.fnv_pow[k];
   uint32_t n = 0;
   for (uint32_t w0 = 0; w0 < W; w0 += kBlock) {
-    const uint32_t w = w0 + threadIdx.x;
+    const uint32_t wl = w0 + threadIdx.x, w = br.wb + wl;  // the circuit's column, the batch's
     uint32_t f = 0;
-    if (w < W) {
+    if (wl < W) {
       const int top = st.col_top[w];
       f = (top >= 0 && int(b) <= top && int(b) >= st.cover_lo[w]) ? 1u : 0u;
     }
     const uint32_t at = block_exclusive_scan<kBlock>(f, s_wave);
     if (f) {
-      s_w[n + at] = w;
+      s_w[n + at] = wl;
       s_base[n + at] = st.col_base[w];
       s_bmb[n + at] = st.col_bm_base[w] + bmo;
-      if (first_chunk) st.cov[size_t(b) * W + n + at] = w;
+      if (first_chunk) st.cov[size_t(gb) * st.w_max + n + at] = w;
     }
     n += s_wave[kBlock / 64];
     __syncthreads();
   }
   if (first_chunk && threadIdx.x == 0) {
-    st.ncov[b] = n;
+    st.ncov[gb] = n;
     // (fault, column) pairs of this boundary in the swept windows
-    const uint64_t words = uint64_t(n) * (st.bnd_fault_off[b + 1] - fb);
+    const uint64_t words = uint64_t(n) * (st.bnd_fault_off[gb + 1] - fb);
     if (words) atomicAdd(reinterpret_cast<unsigned long long*>(&st.hdr->n_words), (unsigned long long)words);
   }
   for (uint32_t i = threadIdx.x; i < n * kHashBmw; i += kBlock) {
@@ -670,7 +683,13 @@ __global__ __launch_bounds__(kBlock) void k_hash(DevState st) {
       }
     }
   }
-  h1 *= s_pow[st.w - wn];
+  h1 *= s_pow[W - wn];
+  if (bi) {
+    // circuits of a batch share column numbers: a per-circuit salt keeps
+    // equal signatures of different circuits in different classes
+    h1 ^= fmix64(0x9e3779b97f4a7c15ull * bi);
+    h2 += fmix64(0xc2b2ae3d27d4eb4full * bi);
+  }
   uint64_t key = h1;
   if (st.key_mode == 1) key = h1 ^ fmix64(h2 ^ 0x5851f42d4c957f2dull);
   if (st.key_bits < 64) key &= (1ull << st.key_bits) - 1;
@@ -1445,6 +1464,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
   __shared__ uint32_t s_fst[kBuckets];
   __shared__ uint32_t s_bfo[kLofsMax];
   __shared__ uint32_t s_wave[kBlock / 64];
+  __shared__ uint32_t s_bfb[kBranchLds];  // first fault of each circuit of the batch
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t S;
   uint64_t NB;
@@ -1463,9 +1483,13 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
     S = st.hdr->n_seg;
     NB = st.hdr->n_bits;
   }
-  const bool bfo_lds = st.n_layers + 2 <= uint32_t(kLofsMax);
+  // a single circuit searches its boundary offsets in LDS when they fit
+  const bool bfo_lds = st.n_branch == 1 && st.n_layers + 2 <= uint32_t(kLofsMax);
   if (bfo_lds)
     for (uint32_t k = threadIdx.x; k < st.n_layers + 2; k += blockDim.x) s_bfo[k] = st.bnd_fault_off[k];
+  const bool bfb_lds = st.n_branch <= uint32_t(kBranchLds);
+  if (bfb_lds)
+    for (uint32_t k = threadIdx.x; k < st.n_branch; k += blockDim.x) s_bfb[k] = st.branch[k].fb;
   __syncthreads();
   if (e == 0) {
     st.hdr->n_edges = S;
@@ -1503,16 +1527,31 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
   const uint32_t pos = st.seg_rep[s];
   const uint32_t cnt = kBucketed ? st.popc[pos] : st.seg_cnt[s];
   if (uint64_t(o0) + cnt > st.bits_cap) return;
-  const uint32_t b = boundary_of(bfo_lds ? s_bfo : st.bnd_fault_off, st.n_layers + 1, pos);
+  // the representative's circuit (last one whose first fault is <= pos) and boundary
+  uint32_t bi = 0;
+  {
+    uint32_t lo = 0, hi = st.n_branch;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) / 2;
+      if ((bfb_lds ? s_bfb[mid] : st.branch[mid].fb) <= pos) lo = mid;
+      else hi = mid;
+    }
+    bi = lo;
+  }
+  const BranchDesc br = st.branch[bi];
+  st.edge_branch[e] = bi;
+  const uint32_t b =
+      br.bb + boundary_of(bfo_lds ? s_bfo : st.bnd_fault_off + br.bb, br.n_layers + 1, pos);
   const uint32_t n = st.ncov[b];
-  const uint32_t* cl = st.cov + size_t(b) * st.w;
+  const uint32_t* cl = st.cov + size_t(b) * st.w_max;
   uint32_t o = o0;
-  const uint32_t obs0 = st.wd * 64;
+  const uint32_t obs0 = br.wd * 64;
   auto emit = [&](uint32_t w) {
     uint64_t v = st.slab[st.col_base[w] + pos];
     while (v) {
-      const uint32_t bit = w * 64 + uint32_t(__builtin_ctzll(v));
-      st.edge_bits[o++] = bit < obs0 ? bit : st.n_det + (bit - obs0);
+      // the circuit's own bit numbering: detector d -> d, observable k -> D + k
+      const uint32_t bit = (w - br.wb) * 64 + uint32_t(__builtin_ctzll(v));
+      st.edge_bits[o++] = bit < obs0 ? bit : br.n_det + (bit - obs0);
       v &= v - 1;
     }
   };
@@ -1526,7 +1565,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
     }
   } else {
     // more covered columns than mask bits: the bitmaps say which words are stored
-    const uint32_t ib = pos - st.bnd_fault_off[b];
+    const uint32_t ib = pos - st.bnd_fault_off[b];  // b is the batch's boundary row
     const uint64_t* bm = st.bm + st.bnd_bm_off[b] + (ib >> 6);
     for (uint32_t k = 0; k < n; ++k)
       if ((bm[st.col_bm_base[cl[k]]] >> (ib & 63)) & 1ull) emit(cl[k]);
@@ -1746,7 +1785,7 @@ hipError_t enqueue_compile(DevState& st_io, hipStream_t stream, const LaunchHook
     GP_LAUNCH(K_EDGE_WRITE, k_edge_write<false><<<1, kBlock, 0, stream>>>(st));
     return hipSuccess;
   }
-  GP_LAUNCH(K_HASH, k_hash<<<st.n_hchunks, kBlock, hash_lds_bytes(st.w), stream>>>(st));
+  GP_LAUNCH(K_HASH, k_hash<<<st.n_hchunks, kBlock, hash_lds_bytes(st.w_max), stream>>>(st));
   // buckets: one stable pass on the top digit, then each bucket in LDS
   const bool bucketed = st.sort_mode == SORT_AUTO && st.key_mode == 0 && g_bucket_ok && n <= kBucketMaxFaults &&
                         st.n_pass >= 2 && st.n_pass <= 7;

@@ -534,7 +534,141 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
   for (int k = 0; k < 8; k++) p8 *= kFnvPrime;
   lw.fnv_pow.assign(size_t(lw.w) + 1, 1);
   for (uint32_t k = 1; k <= lw.w; k++) lw.fnv_pow[k] = lw.fnv_pow[k - 1] * p8;
+  // a single circuit is a batch of one
+  lw.w_max = lw.w;
+  BranchDesc bd{};
+  bd.n_qubits = lw.n_qubits;
+  bd.n_layers = lw.n_layers;
+  bd.lob = 0;
+  bd.bb = 0;
+  bd.wb = 0;
+  bd.nw = lw.w;
+  bd.wd = lw.wd;
+  bd.n_det = lw.n_det;
+  bd.n_obs = lw.n_obs;
+  bd.wib = 0;
+  bd.n_win = uint32_t(lw.win_lo.size());
+  bd.fb = 0;
+  bd.fe = uint32_t(lw.n_faults);
+  lw.branches.assign(1, bd);
+  lw.item_branch.assign(lw.item_col.size(), 0);
+  lw.hchunk_branch.assign(lw.hchunk_pos.size(), 0);
+  // layer windows share the layer-offset indexing (n_layers + 1 entries)
+  lw.layer_win.resize(size_t(lw.n_layers) + 1, 0);
   return 0;
+}
+
+void merge_branches(const std::vector<Lowered>& in, Lowered& out) {
+  out = Lowered();
+  uint32_t ob = 0, cb = 0, fb = 0, wb = 0, ib = 0, wib = 0, mb = 0;
+  uint64_t sb = 0, bmb = 0;
+  std::vector<uint32_t> item_order_span;
+  for (size_t k = 0; k < in.size(); k++) {
+    const Lowered& a = in[k];
+    out.n_qubits = std::max(out.n_qubits, a.n_qubits);
+    out.n_layers = std::max(out.n_layers, a.n_layers);
+    out.n_det = std::max(out.n_det, a.n_det);
+    out.n_obs = std::max(out.n_obs, a.n_obs);
+    out.w_max = std::max(out.w_max, a.w);
+    out.level = a.level;
+    BranchDesc bd{};
+    bd.n_qubits = a.n_qubits;
+    bd.n_layers = a.n_layers;
+    bd.lob = uint32_t(out.layer_off.size());
+    bd.bb = uint32_t(out.bnd_fault_off.size());
+    bd.wb = wb;
+    bd.nw = a.w;
+    bd.wd = a.wd;
+    bd.n_det = a.n_det;
+    bd.n_obs = a.n_obs;
+    bd.wib = wib;
+    bd.n_win = uint32_t(a.win_lo.size());
+    bd.fb = fb;
+    bd.fe = fb + uint32_t(a.n_faults);
+    out.branches.push_back(bd);
+    for (uint64_t o : a.ops) out.ops.push_back(o);
+    for (uint32_t o : a.ops32) out.ops32.push_back(o);
+    for (uint32_t v : a.layer_off) out.layer_off.push_back(v + ob);
+    for (uint32_t v : a.layer_win) out.layer_win.push_back(v);
+    for (uint32_t v : a.leaf_off) out.leaf_off.push_back(v);
+    for (uint32_t v : a.leaf_bits) out.leaf_bits.push_back(v);
+    for (uint32_t v : a.meas_layer) out.meas_layer.push_back(v);
+    const size_t C = a.chan_kind.size();
+    for (size_t c = 0; c < C; c++) {
+      out.chan_qa.push_back(a.chan_qa[c]);
+      out.chan_qb.push_back(a.chan_qb[c]);
+      out.chan_kind.push_back(a.chan_kind[c]);
+      out.chan_rate.push_back(a.chan_rate[c]);
+      out.chan_src.push_back(a.chan_src[c] + cb);
+      out.chan_foff.push_back(a.chan_foff[c] + fb);
+    }
+    for (uint32_t v : a.bnd_chan_off) out.bnd_chan_off.push_back(v + cb);
+    for (uint32_t v : a.bnd_fault_off) out.bnd_fault_off.push_back(v + fb);
+    for (uint32_t v : a.bnd_bm_off) out.bnd_bm_off.push_back(v);
+    // slab words are addressed by base + (batch) fault position: the circuit's
+    // slab starts at sb >= fb, so its bases (sb - fb + own base) stay >= 0
+    sb = std::max<uint64_t>(sb, fb);
+    for (uint32_t w = 0; w < a.w; w++) {
+      out.col_top.push_back(a.col_top[w]);
+      out.col_lo.push_back(a.col_lo[w]);
+      out.col_base.push_back(a.col_base[w] + sb - fb);
+      out.col_bm_base.push_back(a.col_bm_base[w] + bmb);
+      out.inj_off.push_back(a.inj_off[w] + ib);
+    }
+    for (size_t e = 0; e < a.inj_layer.size(); e++) {
+      out.inj_layer.push_back(a.inj_layer[e]);
+      out.inj_qubit.push_back(a.inj_qubit[e]);
+      out.inj_word.push_back(a.inj_word[e]);
+      out.inj_next.push_back(a.inj_next[e]);
+    }
+    for (size_t t = 0; t < a.item_col.size(); t++) {
+      out.item_col.push_back(a.item_col[t] + wb);
+      out.item_blo.push_back(a.item_blo[t]);
+      out.item_bhi.push_back(a.item_bhi[t]);
+      out.item_branch.push_back(uint32_t(k));
+      item_order_span.push_back(uint32_t(a.col_top[a.item_col[t]] - int32_t(a.item_blo[t]) + 1));
+    }
+    for (size_t h = 0; h < a.hchunk_pos.size(); h++) {
+      out.hchunk_pos.push_back(a.hchunk_pos[h] + fb);
+      out.hchunk_bnd.push_back(a.hchunk_bnd[h]);
+      out.hchunk_branch.push_back(uint32_t(k));
+    }
+    for (size_t x = 0; x < a.win_lo.size(); x++) {
+      out.win_lo.push_back(a.win_lo[x]);
+      out.win_obase.push_back(a.win_obase[x] + ob);
+      out.win_cnt.push_back(a.win_cnt[x]);
+    }
+    if (a.fnv_pow.size() > out.fnv_pow.size()) out.fnv_pow = a.fnv_pow;
+    ob += uint32_t(a.ops32.size());
+    cb += uint32_t(C);
+    fb += uint32_t(a.n_faults);
+    wb += a.w;
+    ib += uint32_t(a.inj_layer.size());
+    wib += uint32_t(a.win_lo.size());
+    mb += a.n_meas;
+    sb += a.slab_words;
+    bmb += a.bm_words;
+  }
+  out.chan_foff.push_back(fb);
+  out.inj_off.push_back(ib);
+  out.n_meas = mb;
+  out.n_faults = fb;
+  out.w = wb;
+  out.slab_words = sb;
+  out.bm_words = bmb;
+  // the longest sweeps first (stable: a circuit's own order is kept among equals)
+  std::vector<uint32_t> idx(out.item_col.size());
+  for (uint32_t i = 0; i < idx.size(); i++) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) { return item_order_span[x] > item_order_span[y]; });
+  auto permute = [&](std::vector<uint32_t>& v) {
+    std::vector<uint32_t> t(v.size());
+    for (size_t i = 0; i < idx.size(); i++) t[i] = v[idx[i]];
+    v.swap(t);
+  };
+  permute(out.item_col);
+  permute(out.item_blo);
+  permute(out.item_bhi);
+  permute(out.item_branch);
 }
 
 int apply_rates(Lowered& lw, const double* rates, size_t n_rates, LowerError& err) {

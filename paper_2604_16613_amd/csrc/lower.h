@@ -83,6 +83,21 @@ inline uint32_t pack_op32(uint32_t kind, uint32_t a, uint32_t b) {
   return (kind << 28) | ((a & kQField) << kQubitBits) | (b & kQField);
 }
 
+// One circuit of a batch, as the device sees it (a single compile is a batch
+// of one). Qubits, layers, boundaries and windows are the circuit's own; the
+// bases say where its entries start in the concatenated tables.
+struct BranchDesc {
+  uint32_t n_qubits, n_layers;
+  uint32_t lob;        // layer offsets and layer windows: entries [lob, lob + n_layers + 1)
+  uint32_t bb;         // boundary tables (channel, fault, bitmap offsets; cover rows): [bb, bb + n_layers + 2)
+  uint32_t wb, nw;     // word columns [wb, wb + nw)
+  uint32_t wd;         // of which detector columns
+  uint32_t n_det;      // detectors (observable k is output as bit n_det + k)
+  uint32_t n_obs;      // observables
+  uint32_t wib, n_win; // op windows [wib, wib + n_win)
+  uint32_t fb, fe;     // fault positions [fb, fe)
+};
+
 struct Lowered {
   uint32_t n_qubits = 0, n_layers = 0, n_meas = 0, n_det = 0, n_obs = 0;
   uint32_t wd = 0, wo = 0, w = 0;     // word columns: detector, observable, total
@@ -138,7 +153,20 @@ struct Lowered {
   std::vector<uint32_t> bnd_bm_off;
   std::vector<uint64_t> col_bm_base;
   uint64_t bm_words = 0;
+
+  // batch view: one descriptor per circuit, the circuit of every sweep item
+  // and hash chunk, and the most word columns of any circuit
+  std::vector<BranchDesc> branches;
+  std::vector<uint32_t> item_branch, hchunk_branch;
+  uint32_t w_max = 0;
 };
+
+// Concatenate independently lowered circuits into one batch: tables are
+// appended and rebased (operations, channels, fault positions, columns, slab
+// and bitmap words, injections, windows are global; qubits, layers and
+// boundaries stay per circuit, reached through the descriptors). Sweep items
+// are ordered by the number of layers they sweep, longest first.
+void merge_branches(const std::vector<Lowered>& in, Lowered& out);
 
 struct LowerError {
   int code;

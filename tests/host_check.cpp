@@ -33,40 +33,84 @@ extern "C" uint64_t hc_item_stats(uint64_t* out, uint64_t cap) {
   return g_item_stats.size();
 }
 
-// stats: [0] faults, [1] items, [2] slab words, [3] layers, [4] gauge flag,
-//        [5] words written, [6] columns, [7] qubits
-extern "C" int hc_run(const char* text, size_t len, const double* rates, size_t n_rates, uint64_t* off,
-                      uint32_t* bits, uint64_t bits_cap, uint32_t* src, uint32_t* code, uint64_t* stats,
-                      uint64_t max_faults) {
-  Lowered lw;
-  LowerError err{};
-  int rc = lower_circuit(text, len, rates, n_rates, kSweepSlots, lw, err);
-  if (rc) {
-    g_msg = err.msg;
-    return rc;
-  }
-  const uint32_t n = lw.n_qubits, L = lw.n_layers, W = lw.w;
+// Replay the lowered tables (one circuit, or a merged batch) as the device
+// addresses them: every circuit through its descriptor, every access checked.
+// Signature bits use each circuit's own numbering.
+// stats: [0] faults, [1] items, [2] slab words, [3] layers (most of any circuit),
+//        [4] gauge flag, [5] words written, [6] columns, [7] qubits (most)
+static int replay(const Lowered& lw, uint64_t* off, uint32_t* bits, uint64_t bits_cap, uint32_t* src,
+                  uint32_t* code, uint64_t* stats, uint64_t max_faults) {
+  const uint32_t W = lw.w;
   const uint64_t F = lw.n_faults;
   if (F > max_faults) return bad("fault capacity too small");
-  // structural checks of the tables
-  if (lw.layer_off.size() != L + 1u || lw.layer_off[L] != lw.ops.size()) return bad("layer_off");
-  for (uint32_t t = 0; t < L; t++) {
-    std::vector<char> seen(n, 0);
-    for (uint32_t o = lw.layer_off[t]; o < lw.layer_off[t + 1]; o++) {
-      uint64_t op = lw.ops[o];
-      uint32_t kind = uint32_t(op >> 56), a = uint32_t(op >> 28) & kField, b = uint32_t(op) & kField;
-      if (a >= n || seen[a]++) return bad("layer touches a qubit twice or out of range");
-      if (kind == OP_CX || kind == OP_CZ || kind == OP_SWAP) {
-        if (b >= n || seen[b]++) return bad("layer touches a qubit twice (pair)");
-      } else if (kind >= OP_M) {
-        if (b >= lw.n_meas) return bad("measurement index");
+  if (lw.branches.empty()) return bad("no circuit descriptor");
+  // descriptors tile the batch's tables in order
+  {
+    uint32_t lob = 0, bb = 0, wb = 0, wib = 0, fb = 0;
+    for (const BranchDesc& br : lw.branches) {
+      if (br.lob != lob || br.bb != bb || br.wb != wb || br.wib != wib || br.fb != fb || br.fe < br.fb)
+        return bad("descriptor bases do not tile the tables");
+      if (br.nw > lw.w_max || br.wd > br.nw) return bad("descriptor columns");
+      lob += br.n_layers + 1;
+      bb += br.n_layers + 2;
+      wb += br.nw;
+      wib += br.n_win;
+      fb = br.fe;
+    }
+    if (lob != lw.layer_off.size() || lob != lw.layer_win.size() || bb != lw.bnd_fault_off.size() ||
+        bb != lw.bnd_chan_off.size() || bb != lw.bnd_bm_off.size() || wb != W || wib != lw.win_lo.size() ||
+        fb != F)
+      return bad("descriptors do not cover the tables");
+  }
+  if (lw.item_branch.size() != lw.item_col.size() || lw.hchunk_branch.size() != lw.hchunk_pos.size())
+    return bad("per-item circuit tables");
+  if (lw.fnv_pow.size() < lw.w_max + 1u) return bad("fnv powers");
+  for (const BranchDesc& br : lw.branches) {
+    const uint32_t n = br.n_qubits, L = br.n_layers;
+    const uint32_t* layer_off = lw.layer_off.data() + br.lob;
+    if (layer_off[L] - layer_off[0] > lw.ops.size()) return bad("layer_off");
+    for (uint32_t t = 0; t < L; t++) {
+      // the layer lies inside its op window
+      const uint32_t k = lw.layer_win[br.lob + t];
+      if (k >= br.n_win) return bad("layer window index");
+      const uint32_t ob = lw.win_obase[br.wib + k], oc = lw.win_cnt[br.wib + k];
+      if (oc > kSweepWinOps || ob + oc > lw.ops32.size()) return bad("op window out of range");
+      if (layer_off[t] < ob || layer_off[t + 1] > ob + oc || lw.win_lo[br.wib + k] > t)
+        return bad("layer outside its op window");
+      std::vector<char> seen(n, 0);
+      for (uint32_t o = layer_off[t]; o < layer_off[t + 1]; o++) {
+        uint64_t op = lw.ops[o];
+        uint32_t kind = uint32_t(op >> 56), a = uint32_t(op >> 28) & kField, b = uint32_t(op) & kField;
+        if (a >= n || seen[a]++) return bad("layer touches a qubit twice or out of range");
+        if (kind == OP_CX || kind == OP_CZ || kind == OP_SWAP) {
+          if (b >= n || seen[b]++) return bad("layer touches a qubit twice (pair)");
+        }
       }
     }
+    if (lw.bnd_fault_off[br.bb] != br.fb || lw.bnd_fault_off[br.bb + L + 1] != br.fe) return bad("bnd_fault_off");
+    for (uint32_t c = lw.bnd_chan_off[br.bb]; c < lw.bnd_chan_off[br.bb + L + 1]; c++) {
+      if (lw.chan_qa[c] >= n) return bad("channel qubit");
+      if (lw.chan_kind[c] == CH_DEP2 && lw.chan_qb[c] >= n) return bad("channel qubit b");
+      if (lw.chan_foff[c] < br.fb || lw.chan_foff[c + 1] > br.fe) return bad("channel faults outside the circuit");
+    }
   }
-  if (lw.bnd_fault_off.size() != L + 2u || lw.bnd_fault_off[L + 1] != F) return bad("bnd_fault_off");
-  for (size_t c = 0; c < lw.chan_kind.size(); c++) {
-    if (lw.chan_qa[c] >= n) return bad("channel qubit");
-    if (lw.chan_kind[c] == CH_DEP2 && lw.chan_qb[c] >= n) return bad("channel qubit b");
+  // bitmap regions: column w at boundary b owns ceil(faults at b / 64) words
+  {
+    std::vector<char> owned(lw.bm_words, 0);
+    for (const BranchDesc& br : lw.branches)
+      for (uint32_t w = br.wb; w < br.wb + br.nw; w++) {
+        const int top = lw.col_top[w];
+        for (int b = 0; b <= top; b++) {
+          const uint32_t nf = lw.bnd_fault_off[br.bb + b + 1] - lw.bnd_fault_off[br.bb + b];
+          const uint64_t o = lw.col_bm_base[w] + lw.bnd_bm_off[br.bb + b];
+          if (lw.bnd_bm_off[br.bb + b + 1] - lw.bnd_bm_off[br.bb + b] != (nf + 63) / 64)
+            return bad("bitmap words of a boundary");
+          for (uint64_t i = o; i < o + (nf + 63) / 64; i++) {
+            if (i >= lw.bm_words) return bad("bitmap word out of range");
+            if (owned[i]++) return bad("bitmap regions overlap");
+          }
+        }
+      }
   }
   std::vector<uint64_t> slab(lw.slab_words, 0);
   std::vector<char> written(lw.slab_words, 0);
@@ -76,17 +120,23 @@ extern "C" int hc_run(const char* text, size_t len, const double* rates, size_t 
   if (lw.ops32.size() != lw.ops.size() || lw.inj_off.size() != W + 1u) return bad("device tables missing");
   g_item_stats.assign(2 * lw.item_col.size(), 0);
   for (size_t it = 0; it < lw.item_col.size(); it++) {
+    if (lw.item_branch[it] >= lw.branches.size()) return bad("item circuit");
+    const BranchDesc& br = lw.branches[lw.item_branch[it]];
+    const uint32_t n = br.n_qubits;
+    const uint32_t* layer_off = lw.layer_off.data() + br.lob;
+    const uint32_t* bnd_chan_off = lw.bnd_chan_off.data() + br.bb;
     const uint32_t w = lw.item_col[it];
-    if (w >= W) return bad("item column");
+    if (w < br.wb || w >= br.wb + br.nw) return bad("item column outside its circuit");
     const int top = lw.col_top[w], clo = lw.col_lo[w];
     const int blo = int(lw.item_blo[it]), bhi = int(lw.item_bhi[it]);
-    if (top < 0 || top >= int(L) || bhi > top || blo > bhi) return bad("item range");
+    if (top < 0 || top >= int(br.n_layers) || bhi > top || blo > bhi) return bad("item range");
     const uint64_t base = lw.col_base[w];
-    const uint64_t cap = lw.bnd_fault_off[top + 1];
+    const uint64_t cap = lw.bnd_fault_off[br.bb + top + 1];
     std::vector<uint64_t> fr(2 * size_t(n), 0);
     std::vector<uint64_t> pend(n, 0);
     uint32_t ip = lw.inj_off[w];
     const uint32_t ip_end = lw.inj_off[w + 1];
+    if (ip_end > lw.inj_layer.size()) return bad("injection range");
     auto scatter = [&](int layer) -> int {
       while (ip < ip_end && int(lw.inj_layer[ip]) == layer) {
         const uint32_t q = lw.inj_qubit[ip];
@@ -106,7 +156,7 @@ extern "C" int hc_run(const char* text, size_t len, const double* rates, size_t 
       g_item_stats[2 * it]++;
       int dnz = 0;
       auto nzd = [](uint64_t a, uint64_t b) { return int(a != 0) - int(b != 0); };
-      for (uint32_t o = lw.layer_off[t]; o < lw.layer_off[t + 1]; o++) {
+      for (uint32_t o = layer_off[t]; o < layer_off[t + 1]; o++) {
         const uint32_t op = lw.ops32[o];
         if (op == 0xFFFFFFFFu) return bad("qubit index too large for the compact op word");
         const uint32_t kind = op >> 28, a = (op >> kQubitBits) & kQField, b = op & kQField;
@@ -153,7 +203,7 @@ extern "C" int hc_run(const char* text, size_t len, const double* rates, size_t 
       for (uint64_t v : fr) full += v != 0;
       if (full != nz) return bad("incremental non-zero count disagrees with a full count");
       if (t <= bhi) {
-        for (uint32_t c = lw.bnd_chan_off[t]; c < lw.bnd_chan_off[t + 1]; c++) {
+        for (uint32_t c = bnd_chan_off[t]; c < bnd_chan_off[t + 1]; c++) {
           const uint64_t x0 = fr[2 * lw.chan_qa[c]], z0 = fr[2 * lw.chan_qa[c] + 1];
           uint64_t words[15];
           int nwd = 0;
@@ -193,14 +243,17 @@ extern "C" int hc_run(const char* text, size_t len, const double* rates, size_t 
     if (!dead && blo == 0)
       for (uint32_t q = 0; q < n; q++) gauge |= fr[2 * q + 1] != 0;
   }
-  // hash chunks cover every position once, each inside one boundary
+  // hash chunks cover every position once, each inside one boundary of its circuit
   {
     std::vector<char> seen(F, 0);
     if (lw.hchunk_pos.size() != lw.hchunk_bnd.size()) return bad("hash chunk arrays");
     for (size_t k = 0; k < lw.hchunk_pos.size(); k++) {
+      if (lw.hchunk_branch[k] >= lw.branches.size()) return bad("hash chunk circuit");
+      const BranchDesc& br = lw.branches[lw.hchunk_branch[k]];
       const uint32_t b = lw.hchunk_bnd[k], p0 = lw.hchunk_pos[k];
-      if (b > L || p0 < lw.bnd_fault_off[b] || p0 >= lw.bnd_fault_off[b + 1]) return bad("hash chunk boundary");
-      const uint32_t p1 = std::min<uint32_t>(p0 + 256, lw.bnd_fault_off[b + 1]);
+      if (b > br.n_layers || p0 < lw.bnd_fault_off[br.bb + b] || p0 >= lw.bnd_fault_off[br.bb + b + 1])
+        return bad("hash chunk boundary");
+      const uint32_t p1 = std::min<uint32_t>(p0 + 256, lw.bnd_fault_off[br.bb + b + 1]);
       for (uint32_t p = p0; p < p1; p++) {
         if (seen[p]) return bad("hash chunks overlap");
         seen[p] = 1;
@@ -209,33 +262,38 @@ extern "C" int hc_run(const char* text, size_t len, const double* rates, size_t 
     for (uint64_t p = 0; p < F; p++)
       if (!seen[p]) return bad("hash chunks miss a position");
   }
-  // signatures of every fault position from the covered columns
+  // signatures of every fault position from its circuit's covered columns
   uint64_t nb = 0;
   off[0] = 0;
-  for (uint32_t b = 0; b <= L; b++) {
-    for (uint32_t c = lw.bnd_chan_off[b]; c < lw.bnd_chan_off[b + 1]; c++) {
-      for (uint32_t pos = lw.chan_foff[c]; pos < lw.chan_foff[c + 1]; pos++) {
-        for (uint32_t w = 0; w < W; w++) {
-          const int top = lw.col_top[w];
-          if (top < 0 || int(b) > top || int(b) < cover_lo[w]) continue;
-          uint64_t idx = lw.col_base[w] + pos;
-          if (!written[idx]) return bad("covered slab word never written");
-          uint64_t v = slab[idx];
-          while (v) {
-            uint32_t bit = w * 64 + uint32_t(__builtin_ctzll(v));
-            if (nb >= bits_cap) return bad("bit capacity");
-            bits[nb++] = bit < lw.wd * 64 ? bit : lw.n_det + (bit - lw.wd * 64);
-            v &= v - 1;
+  for (const BranchDesc& br : lw.branches) {
+    for (uint32_t b = 0; b <= br.n_layers; b++) {
+      for (uint32_t c = lw.bnd_chan_off[br.bb + b]; c < lw.bnd_chan_off[br.bb + b + 1]; c++) {
+        for (uint32_t pos = lw.chan_foff[c]; pos < lw.chan_foff[c + 1]; pos++) {
+          for (uint32_t w = br.wb; w < br.wb + br.nw; w++) {
+            const int top = lw.col_top[w];
+            if (top < 0 || int(b) > top || int(b) < cover_lo[w]) continue;
+            uint64_t idx = lw.col_base[w] + pos;
+            if (!written[idx]) return bad("covered slab word never written");
+            uint64_t v = slab[idx];
+            while (v) {
+              uint32_t bit = (w - br.wb) * 64 + uint32_t(__builtin_ctzll(v));
+              if (nb >= bits_cap) return bad("bit capacity");
+              bits[nb++] = bit < br.wd * 64 ? bit : br.n_det + (bit - br.wd * 64);
+              v &= v - 1;
+            }
           }
+          off[pos + 1] = nb;
+          src[pos] = lw.chan_src[c];
+          uint32_t k = pos - lw.chan_foff[c];
+          code[pos] = kept_code(lw.chan_kind[c], lw.level, k);
         }
-        off[pos + 1] = nb;
-        src[pos] = lw.chan_src[c];
-        uint32_t k = pos - lw.chan_foff[c];
-        uint8_t kind = lw.chan_kind[c];
-        code[pos] = kind == CH_DEP2 ? k + 1 : kind == CH_DEP1 ? (k == 0 ? 1u : k == 1 ? 3u : 2u)
-                    : kind == CH_X ? 1u : kind == CH_Y ? 3u : 2u;
       }
     }
+  }
+  uint32_t L = 0, nq = 0;
+  for (const BranchDesc& br : lw.branches) {
+    L = std::max(L, br.n_layers);
+    nq = std::max(nq, br.n_qubits);
   }
   stats[0] = F;
   stats[1] = lw.item_col.size();
@@ -244,6 +302,42 @@ extern "C" int hc_run(const char* text, size_t len, const double* rates, size_t 
   stats[4] = uint64_t(gauge);
   stats[5] = nwritten;
   stats[6] = W;
-  stats[7] = n;
+  stats[7] = nq;
   return 0;
+}
+
+extern "C" int hc_run(const char* text, size_t len, const double* rates, size_t n_rates, uint64_t* off,
+                      uint32_t* bits, uint64_t bits_cap, uint32_t* src, uint32_t* code, uint64_t* stats,
+                      uint64_t max_faults) {
+  Lowered lw;
+  LowerError err{};
+  int rc = lower_circuit(text, len, rates, n_rates, kSweepSlots, lw, err);
+  if (rc) {
+    g_msg = err.msg;
+    return rc;
+  }
+  return replay(lw, off, bits, bits_cap, src, code, stats, max_faults);
+}
+
+// The same for a batch: each circuit lowered with `slots` sweep slots, then
+// merged. Positions (and so off, src, code) run over the batch in circuit order;
+// src is the batch's channel number.
+extern "C" int hc_run_batch(const char* const* texts, const size_t* lens, size_t n_texts, uint32_t slots,
+                            uint64_t* off, uint32_t* bits, uint64_t bits_cap, uint32_t* src, uint32_t* code,
+                            uint64_t* stats, uint64_t max_faults, uint32_t* fault_circuit) {
+  std::vector<Lowered> parts(n_texts);
+  for (size_t k = 0; k < n_texts; k++) {
+    LowerError err{};
+    int rc = lower_circuit(texts[k], lens[k], nullptr, 0, slots, parts[k], err);
+    if (rc) {
+      g_msg = err.msg;
+      return rc;
+    }
+  }
+  Lowered lw;
+  merge_branches(parts, lw);
+  if (lw.n_faults > max_faults) return bad("fault capacity too small");
+  for (size_t k = 0; k < lw.branches.size(); k++)
+    for (uint32_t p = lw.branches[k].fb; p < lw.branches[k].fe; p++) fault_circuit[p] = uint32_t(k);
+  return replay(lw, off, bits, bits_cap, src, code, stats, max_faults);
 }

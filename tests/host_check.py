@@ -64,3 +64,47 @@ def run(text, rates=None, max_faults=4_000_000, bits_per_fault=16):
     for p in range(F):
         sigs[(int(src[p]), int(code[p]))] = tuple(int(x) for x in bits[off[p]:off[p + 1]])
     return st, sigs
+
+
+def run_batch(texts, slots=None, max_faults=4_000_000, bits_per_fault=16):
+    """Replay a merged batch -> (stats, [per circuit {(channel, pauli code): signature}]).
+    Channels are numbered per circuit (program order), as in `run`."""
+    lib = _load()
+    P = ctypes.POINTER
+    lib.hc_run_batch.argtypes = [P(ctypes.c_char_p), P(ctypes.c_size_t), ctypes.c_size_t, ctypes.c_uint32,
+                                 P(ctypes.c_uint64), P(ctypes.c_uint32), ctypes.c_uint64, P(ctypes.c_uint32),
+                                 P(ctypes.c_uint32), P(ctypes.c_uint64), ctypes.c_uint64, P(ctypes.c_uint32)]
+    lib.hc_run_batch.restype = ctypes.c_int
+    n = len(texts)
+    if slots is None:
+        slots = max(1, -(-256 // n))
+    raw = [t.encode() for t in texts]
+    arr = (ctypes.c_char_p * n)(*raw)
+    lens = (ctypes.c_size_t * n)(*[len(r) for r in raw])
+    off = np.zeros(max_faults + 1, dtype=np.uint64)
+    bits = np.zeros(max_faults * bits_per_fault, dtype=np.uint32)
+    src = np.zeros(max_faults, dtype=np.uint32)
+    code = np.zeros(max_faults, dtype=np.uint32)
+    circ = np.zeros(max_faults, dtype=np.uint32)
+    stats = np.zeros(8, dtype=np.uint64)
+    rc = lib.hc_run_batch(arr, lens, n, slots, off.ctypes.data_as(P(ctypes.c_uint64)),
+                          bits.ctypes.data_as(P(ctypes.c_uint32)), len(bits), src.ctypes.data_as(P(ctypes.c_uint32)),
+                          code.ctypes.data_as(P(ctypes.c_uint32)), stats.ctypes.data_as(P(ctypes.c_uint64)),
+                          max_faults, circ.ctypes.data_as(P(ctypes.c_uint32)))
+    if rc != 0:
+        raise RuntimeError(f"host check failed ({rc}): {lib.hc_error().decode()}")
+    names = ["faults", "items", "slab_words", "layers", "gauge", "written", "words", "qubits"]
+    st = {k: int(v) for k, v in zip(names, stats)}
+    # channel numbers of the batch -> per circuit: subtract the channels of the circuits before
+    counts = [0] * n
+    for p in range(st["faults"]):
+        k = int(circ[p])
+        counts[k] = max(counts[k], int(src[p]) + 1)
+    base = [0] * n
+    for k in range(1, n):
+        base[k] = max(base[k - 1], counts[k - 1])
+    out = [dict() for _ in range(n)]
+    for p in range(st["faults"]):
+        k = int(circ[p])
+        out[k][(int(src[p]) - base[k], int(code[p]))] = tuple(int(x) for x in bits[off[p]:off[p + 1]])
+    return st, out

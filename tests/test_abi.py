@@ -40,6 +40,27 @@ def test_bounds_from_circuit_sizes():
     assert (b.max_qubits, b.max_faults, b.max_detectors, b.max_observables) == (288, 168624, 1728, 12)
 
 
+def test_bounds_from_batch_sizes():
+    """A batch bounds each circuit's qubits, layers, detectors and observables
+    and the sums of everything else."""
+    texts = [rotated_surface_code_memory(3, 3).text, rotated_surface_code_memory(5, 7).text,
+             bivariate_bicycle_memory(rounds=2).text, ""]
+    b = _gp.gp_bounds_from_batch(texts)
+    singles = [_gp.gp_bounds_from_circuit(t) for t in texts]
+    assert b.max_branches == 4
+    for f in ("max_qubits", "max_layers", "max_detectors", "max_observables"):
+        assert getattr(b, f) == max(getattr(s, f) for s in singles), f
+    for f in ("max_measurements", "max_channels", "max_faults", "max_ops", "max_leaf_bits"):
+        assert getattr(b, f) == sum(getattr(s, f) for s in singles), f
+    assert b.max_slab_words >= sum(s.max_faults for s in singles)
+    with pytest.raises(_gp.GpError) as e:
+        _gp.gp_bounds_from_batch([])
+    assert e.value.code == -1
+    with pytest.raises(_gp.GpError) as e:
+        _gp.gp_bounds_from_batch([texts[0], "CX 0\n"])
+    assert e.value.code == -2 and "circuit 1" in str(e.value)
+
+
 @pytest.mark.parametrize("text,code", [
     ("REPEAT 2 {\nH 0\n}\n", -3),
     ("R 0\nT 0\n", -3),

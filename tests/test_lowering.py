@@ -50,3 +50,27 @@ def test_gauge_flagged():
     assert st["gauge"] == 1
     st, _ = host_check.run("R 0\nM 0\nDETECTOR rec[-1]\n")
     assert st["gauge"] == 0
+
+
+def test_merged_batch_replays_like_each_circuit():
+    """A batch of mixed circuits, merged and replayed through the circuit
+    descriptors with every access checked, gives every circuit the signatures
+    its own lowering gives (and so the oracle's)."""
+    texts = [rotated_surface_code_memory(5, 5).text, bit_flip_code_fig1().text, "",
+             repetition_code_memory(7, 5, p_data=0.01, p_meas=0.02, p2=0.03, p1=0.04).text,
+             "R 0 1\nCX 0 1\nM 0 1\nDETECTOR rec[-1] rec[-2]\n", "R 0\nX_ERROR(0.1) 0\nM 0\n",
+             mirror_circuit(5, 6, 1, x_basis=[1, 2]).text, bivariate_bicycle_memory(rounds=2).text,
+             rotated_surface_code_memory(3, 3).text]
+    st, per = host_check.run_batch(texts)
+    assert st["gauge"] == 0
+    total = 0
+    for t, sigs in zip(texts, per):
+        _, single = host_check.run(t)
+        assert sigs == single
+        total += len(single)
+    assert st["faults"] == total
+    # the same circuit many times, each with a share of one slot
+    c = rotated_surface_code_memory(3, 3).text
+    st, per = host_check.run_batch([c] * 300)
+    _, single = host_check.run(c)
+    assert all(s == single for s in per)
