@@ -110,6 +110,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiation workload")
+    ap.add_argument("--batch-distances", default="3,5,7,10",
+                    help="outer distances of the batched [[4,2,2]]-concatenated workload ('' skips it)")
+    ap.add_argument("--batch-branches", type=int, default=256)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain streaming copy of MIB MiB five times (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -201,6 +204,9 @@ def main() -> int:
 
     if not args.no_grad:
         out["differentiation"] = bench_differentiation(get_driver)
+    if args.batch_distances:
+        out["batching"] = [bench_batched(int(d), args.batch_branches, args.steps)
+                           for d in args.batch_distances.split(",")]
 
     if not args.no_cpu_baseline:
         # the oracle on the whole workload, repeated until about cpu_seconds of
@@ -268,6 +274,76 @@ def bench_differentiation(get_driver, iters: int = 50) -> dict:
             "gradient_ms_median": grad_ms, "refresh_faults_per_s": F / (refresh_ms * 1e-3),
             "gradient_max_rel_err_vs_oracle": float(np.max(np.abs(g - go) / np.maximum(np.abs(go), 1e-300))),
             "timing": "host wall clock around each call + stream sync, median of %d" % iters}
+
+
+def bench_batched(d: int, n_branches: int, steps: int) -> dict:
+    """The batched workload: `n_branches` realised branches of the adaptive
+    [[4,2,2]]-concatenated surface code, outer distance d, d cycles (seeds
+    0 .. n_branches-1), uniform p = 1e-3. Device stages over the whole batch
+    in one launch of each kernel (tables resident) against the same branches
+    compiled one per launch (each branch's tables resident while it is timed),
+    plus the whole path for both (lowering, upload, stages, download)."""
+    from paper_2604_16613_amd import Driver
+    from workloads import iceberg_surface_batch
+    print(f"batched workload: generating {n_branches} branches at outer d={d}", file=sys.stderr, flush=True)
+    texts = [c.text for c in iceberg_surface_batch(d, n_branches=n_branches, seed=0)]
+    drv = Driver.from_batch(texts)
+    drv.lower_batch(texts)
+    F = drv.info()["n_faults"]
+    drv.run()
+    hgs = drv.fetch_batch()
+    U = sum(len(h) for h in hgs)
+    drv.sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        drv.run()
+    drv.sync()
+    batch_ms = (time.perf_counter() - t0) * 1e3 / steps
+    drv.reset_timing()
+    drv.set_timing(True)
+    drv.run()
+    drv.sync()
+    drv.set_timing(False)
+    kt = {k: round(ms, 4) for k, (ms, n) in sorted(drv.timing().items(), key=lambda x: -x[1][0])}
+    s = time.perf_counter()
+    drv.compile_batch(texts)
+    batch_e2e_ms = (time.perf_counter() - s) * 1e3
+    drv.close()
+    # one launch sequence per branch, on a driver sized for the largest branch
+    from paper_2604_16613_amd import _gp
+    sizes = [_gp.gp_bounds_from_circuit(t) for t in texts]
+    bounds = _gp.GpBounds()
+    for f, _ in bounds._fields_:
+        setattr(bounds, f, max(getattr(b, f) for b in sizes))
+    bounds.max_slab_words = 0   # derived by the driver from the other bounds
+    bounds.max_items = 0
+    single = Driver(bounds)
+    per_ms = 0.0
+    reps = max(2, steps // 4)
+    for t in texts:
+        single.lower(t)
+        single.run()
+        single.sync()
+        s = time.perf_counter()
+        for _ in range(reps):
+            single.run()
+        single.sync()
+        per_ms += (time.perf_counter() - s) * 1e3 / reps
+    s = time.perf_counter()
+    for t in texts:
+        single.compile_hypergraph(t)
+    per_e2e_ms = (time.perf_counter() - s) * 1e3
+    single.close()
+    return {"workload": f"iceberg_surface_d{d}: {n_branches} branches, d cycles, seeds 0..{n_branches - 1}, "
+                        "uniform p=1e-3, level 2",
+            "faults": int(F), "hyperedges": int(U),
+            "batched_ms": batch_ms, "batched_faults_per_s": F / (batch_ms * 1e-3),
+            "per_branch_ms_sum": per_ms, "per_branch_faults_per_s": F / (per_ms * 1e-3),
+            "speedup_batched_vs_per_branch": per_ms / batch_ms,
+            "batched_e2e_ms": batch_e2e_ms, "per_branch_e2e_ms_sum": per_e2e_ms,
+            "batched_kernels_ms": kt,
+            "timing": "device stages with tables resident (host wall clock over synced launches); "
+                      "e2e = host lowering + upload + stages + download"}
 
 
 def copy_calibration(mib: int) -> int:

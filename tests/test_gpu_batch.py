@@ -210,3 +210,30 @@ def test_batch_bounds_errors():
                 assert sorted(_gp.gp_edges_circuit_dem_text(h, k).splitlines()) == sorted(single.splitlines())
         finally:
             _gp.gp_edges_free(h)
+
+
+@pytest.mark.parametrize("d,n", [(3, 64), (5, 16)])
+def test_concatenated_branches_batch(d, n):
+    """Realised branches of the adaptive [[4,2,2]]-concatenated surface code
+    (uneven lengths), compiled as one batch, against the oracle per branch."""
+    from workloads import iceberg_surface_batch
+    texts = [c.text for c in iceberg_surface_batch(d, n_branches=n, seed=100)]
+    say("case concatenated batch", d, n)
+    with Driver.from_batch(texts) as drv:
+        got = drv.compile_batch(texts)
+        for k, (t, hg) in enumerate(zip(texts, got)):
+            assert_same(hg, oracle.run(t), f"d{d} branch {k}")
+
+
+def test_concatenated_d10_batch_samples():
+    """Outer distance 10: a batch of 12 branches; every branch equals its own
+    compile, two of them are checked against the oracle."""
+    from workloads import iceberg_surface_batch
+    texts = [c.text for c in iceberg_surface_batch(10, n_branches=12, seed=7)]
+    say("case concatenated d10 batch")
+    with Driver.from_batch(texts) as drv:
+        got = drv.compile_batch(texts)
+        for k in (0, 11):
+            assert_same(got[k], oracle.run(texts[k]), f"d10 branch {k} vs oracle")
+        for k, t in enumerate(texts):
+            assert_same(got[k], drv.compile_hypergraph(t), f"d10 branch {k} vs single", exact=True)

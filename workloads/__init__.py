@@ -14,4 +14,10 @@ from .circuits import (  # noqa: F401
     bit_flip_code_fig1,
     mirror_circuit,
 )
+from .concatenated import (  # noqa: F401
+    iceberg_pairing,
+    iceberg_pairing_violations,
+    iceberg_surface_branch,
+    iceberg_surface_batch,
+)
 from .rates import splitmix64_uniform, log_uniform_rates  # noqa: F401
