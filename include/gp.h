@@ -232,8 +232,10 @@ int gp_debug_sweep_times(gp_driver* drv, uint64_t* out, uint64_t cap, uint64_t* 
  * where bit b < n_detectors is detector b and bit n_detectors + k is
  * observable k, and probability probabilities[e]. Edge order is unspecified
  * (deterministic for a given circuit). Pointers stay valid until gp_edges_free.
- * In a batch result, n_detectors is that of hyperedge e's own circuit
- * (circuit_ids[e], with its shape from gp_edges_circuit_shape), and
+ * A batch result lists the hyperedges circuit by circuit: circuit k owns
+ * hyperedges circuit_offsets[k] .. circuit_offsets[k+1]-1 (n_circuits + 1
+ * offsets; circuit_ids[e] names the circuit of each hyperedge); bits use
+ * that circuit's numbering (its shape from gp_edges_circuit_shape), and
  * gp_edges_detectors / gp_edges_observables give the largest of any circuit. */
 uint64_t gp_edges_count(const gp_edges* e);
 uint32_t gp_edges_detectors(const gp_edges* e);
@@ -243,6 +245,7 @@ const uint32_t* gp_edges_bits(const gp_edges* e);
 const double* gp_edges_probabilities(const gp_edges* e);
 uint32_t gp_edges_circuits(const gp_edges* e);            /* circuits in the compile (1 without a batch) */
 const uint32_t* gp_edges_circuit_ids(const gp_edges* e);  /* per hyperedge: its circuit */
+const uint64_t* gp_edges_circuit_offsets(const gp_edges* e);  /* first hyperedge of each circuit, and the count */
 int gp_edges_circuit_shape(const gp_edges* e, uint32_t circuit, uint32_t* n_det, uint32_t* n_obs);
 /* Detector error model text, one "error(q) D.. L.." line per hyperedge. The
  * caller releases *text with gp_free. GP_E_STATE for a batch result, whose

@@ -32,6 +32,7 @@ EXPORTS = (
     "gp_debug_sweep_times", "gp_debug_set_sort_mode", "gp_refresh_rates", "gp_rates_gradient",
     "gp_set_correlation_level", "gp_bounds_from_batch", "gp_driver_create_from_batch", "gp_lower_batch",
     "gp_edges_circuits", "gp_edges_circuit_ids", "gp_edges_circuit_shape", "gp_edges_circuit_dem_text",
+    "gp_edges_circuit_offsets",
 )
 
 
@@ -135,6 +136,7 @@ def load():
                             ctypes.c_size_t], ctypes.c_int),
         "gp_edges_circuits": ([_vp], ctypes.c_uint32),
         "gp_edges_circuit_ids": ([_vp], ctypes.POINTER(ctypes.c_uint32)),
+        "gp_edges_circuit_offsets": ([_vp], ctypes.POINTER(_u64)),
         "gp_edges_circuit_shape": ([_vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
                                     ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
         "gp_edges_circuit_dem_text": ([_vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p),
@@ -335,6 +337,11 @@ def gp_edges_circuit_ids(e: int) -> np.ndarray:
     if n == 0:
         return np.zeros(0, dtype=np.uint32)
     return np.ctypeslib.as_array(load().gp_edges_circuit_ids(e), shape=(n,)).copy()
+
+
+def gp_edges_circuit_offsets(e: int) -> np.ndarray:
+    n = gp_edges_circuits(e) + 1
+    return np.ctypeslib.as_array(load().gp_edges_circuit_offsets(e), shape=(n,)).copy()
 
 
 def gp_edges_circuit_shape(e: int, circuit: int) -> Tuple[int, int]:

@@ -51,31 +51,21 @@ def _take(handle: int) -> Hypergraph:
 
 
 def _take_batch(handle: int) -> List[Hypergraph]:
-    """Split a batch result into one Hypergraph per circuit (each keeps the
-    relative order its hyperedges had in the result)."""
+    """Split a batch result (listed circuit by circuit) into one Hypergraph per circuit."""
     try:
         off = _gp.gp_edges_offsets(handle)
         bits = _gp.gp_edges_bits(handle)
         q = _gp.gp_edges_probabilities(handle)
-        ids = _gp.gp_edges_circuit_ids(handle)
-        shapes = [_gp.gp_edges_circuit_shape(handle, k) for k in range(_gp.gp_edges_circuits(handle))]
+        cut = _gp.gp_edges_circuit_offsets(handle)
+        shapes = [_gp.gp_edges_circuit_shape(handle, k) for k in range(len(cut) - 1)]
     finally:
         _gp.gp_edges_free(handle)
-    order = np.argsort(ids, kind="stable")
-    cnt = np.diff(off).astype(np.int64)[order]
-    start = off[:-1].astype(np.int64)[order]
-    new_off = np.zeros(len(order) + 1, dtype=np.int64)
-    np.cumsum(cnt, out=new_off[1:])
-    gather = np.repeat(start - new_off[:-1], cnt) + np.arange(int(new_off[-1]), dtype=np.int64)
-    bits_s = bits[gather]
-    q_s = q[order]
-    cut = np.searchsorted(ids[order], np.arange(len(shapes) + 1))
     out = []
     for k, (nd, no) in enumerate(shapes):
         a, b = int(cut[k]), int(cut[k + 1])
-        o = new_off[a:b + 1]
-        out.append(Hypergraph(n_detectors=nd, n_observables=no, offsets=(o - o[0]).astype(np.uint64),
-                              bits=bits_s[int(o[0]):int(o[-1])].copy(), q=q_s[a:b].copy()))
+        o = off[a:b + 1]
+        out.append(Hypergraph(n_detectors=nd, n_observables=no, offsets=o - o[0],
+                              bits=bits[int(o[0]):int(o[-1])], q=q[a:b]))
     return out
 
 

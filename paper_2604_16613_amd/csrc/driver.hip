@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "gp.h"
@@ -119,6 +120,7 @@ struct gp_edges {
   std::vector<double> q;
   std::vector<uint32_t> circuit;      // per hyperedge: its circuit in the batch
   std::vector<uint32_t> c_det, c_obs; // per circuit: detectors, observables
+  std::vector<uint64_t> c_off;        // per circuit: its hyperedges [c_off[k], c_off[k+1])
 };
 
 struct gp_driver {
@@ -142,6 +144,7 @@ struct gp_driver {
   bool ran = false;
   bool structured = false;     // a fetched compile left its class structure on the device
   uint64_t struct_edges = 0;   // hyperedges of that compile
+  std::vector<uint32_t> edge_perm;  // batch: device hyperedge of each fetched one (empty: same order)
   gp::DevState st{};
 
   uint32_t key_bits = 64;      // test hook: class keys cut to this many bits
@@ -280,14 +283,28 @@ int lower_batch(const char* const* texts, const size_t* lens, const double* cons
   if (rates && !n_rates) return fail(GP_E_ARG, "rate arrays without their lengths");
   if (n > (1u << 20)) return fail(GP_E_BOUNDS, "at most 2^20 circuits in one batch");
   const uint32_t slots = std::max<uint32_t>(1, uint32_t((gp::kSweepSlots + n - 1) / n));
-  std::vector<gp::Lowered> parts(n);
-  for (size_t k = 0; k < n; k++) {
+  for (size_t k = 0; k < n; k++)
     if (!texts[k]) return fail(GP_E_ARG, "null circuit text in the batch");
-    gp::LowerError err{};
-    const double* r = rates ? rates[k] : nullptr;
-    int rc = gp::lower_circuit(texts[k], lens[k], r, r ? n_rates[k] : 0, slots, parts[k], err, level);
-    if (rc) return fail(rc, "circuit " + std::to_string(k) + " of the batch: " + err.msg);
+  // the circuits are lowered independently, on up to 16 host threads
+  std::vector<gp::Lowered> parts(n);
+  std::vector<gp::LowerError> errs(n);
+  std::vector<int> rcs(n, 0);
+  auto lower_range = [&](size_t lo, size_t hi) {
+    for (size_t k = lo; k < hi; k++) {
+      const double* r = rates ? rates[k] : nullptr;
+      rcs[k] = gp::lower_circuit(texts[k], lens[k], r, r ? n_rates[k] : 0, slots, parts[k], errs[k], level);
+    }
+  };
+  const size_t n_threads = std::min<size_t>({n, 16, std::max<size_t>(1, std::thread::hardware_concurrency())});
+  if (n_threads <= 1) {
+    lower_range(0, n);
+  } else {
+    std::vector<std::thread> pool;
+    for (size_t t = 0; t < n_threads; t++) pool.emplace_back(lower_range, n * t / n_threads, n * (t + 1) / n_threads);
+    for (std::thread& th : pool) th.join();
   }
+  for (size_t k = 0; k < n; k++)
+    if (rcs[k]) return fail(rcs[k], "circuit " + std::to_string(k) + " of the batch: " + errs[k].msg);
   uint64_t faults = 0;
   for (const gp::Lowered& a : parts) faults += a.n_faults;
   if (faults >= (1ull << 30)) return fail(GP_E_BOUNDS, "at most 2^30 - 1 faults in one batch");
@@ -679,18 +696,58 @@ int gp_fetch(gp_driver* d, gp_edges** out) {
   gp_edges* e = new gp_edges();
   e->n_det = d->lw.n_det;
   e->n_obs = d->lw.n_obs;
-  e->off.resize(U + 1);
   const uint32_t* off32 = reinterpret_cast<const uint32_t*>(h + o_off);
-  for (uint64_t i = 0; i <= U; i++) e->off[i] = off32[i];
-  e->bits.assign(reinterpret_cast<const uint32_t*>(h + o_bits), reinterpret_cast<const uint32_t*>(h + o_bits) + nb);
-  e->q.assign(reinterpret_cast<const double*>(h + o_q), reinterpret_cast<const double*>(h + o_q) + U);
-  if (batch)
-    e->circuit.assign(reinterpret_cast<const uint32_t*>(h + o_c), reinterpret_cast<const uint32_t*>(h + o_c) + U);
-  else
-    e->circuit.assign(U, 0u);
+  const uint32_t* bits32 = reinterpret_cast<const uint32_t*>(h + o_bits);
+  const double* q64 = reinterpret_cast<const double*>(h + o_q);
+  const size_t B = d->lw.branches.size();
   for (const gp::BranchDesc& bd : d->lw.branches) {
     e->c_det.push_back(bd.n_det);
     e->c_obs.push_back(bd.n_obs);
+  }
+  e->c_off.assign(B + 1, 0);
+  d->edge_perm.clear();
+  if (!batch) {
+    e->off.resize(U + 1);
+    for (uint64_t i = 0; i <= U; i++) e->off[i] = off32[i];
+    e->bits.assign(bits32, bits32 + nb);
+    e->q.assign(q64, q64 + U);
+    e->circuit.assign(U, 0u);
+    e->c_off[1] = U;
+  } else {
+    // circuit by circuit (a stable counting sort), each circuit's hyperedges
+    // in the order the device wrote them
+    const uint32_t* cid = reinterpret_cast<const uint32_t*>(h + o_c);
+    std::vector<uint64_t> bit_off(B + 1, 0);
+    for (uint64_t i = 0; i < U; i++) {
+      if (cid[i] >= B) {
+        delete e;
+        return fail(GP_E_HIP, "a hyperedge names a circuit outside the batch");
+      }
+      e->c_off[cid[i] + 1]++;
+      bit_off[cid[i] + 1] += off32[i + 1] - off32[i];
+    }
+    for (size_t k = 0; k < B; k++) {
+      e->c_off[k + 1] += e->c_off[k];
+      bit_off[k + 1] += bit_off[k];
+    }
+    std::vector<uint64_t> at(e->c_off.begin(), e->c_off.end() - 1), bat(bit_off.begin(), bit_off.end() - 1);
+    e->off.resize(U + 1);
+    e->bits.resize(nb);
+    e->q.resize(U);
+    e->circuit.resize(U);
+    d->edge_perm.resize(U);
+    for (uint64_t i = 0; i < U; i++) {
+      const uint32_t k = cid[i];
+      const uint64_t j = at[k]++;
+      d->edge_perm[j] = uint32_t(i);
+      const uint32_t len = off32[i + 1] - off32[i];
+      e->q[j] = q64[i];
+      e->circuit[j] = k;
+      e->off[j] = bat[k];
+      if (len) std::memcpy(e->bits.data() + bat[k], bits32 + off32[i], size_t(len) * 4);
+      bat[k] += len;
+    }
+    e->off[U] = nb;
   }
   *out = e;
   d->structured = true;
@@ -732,6 +789,14 @@ int gp_rates_gradient(gp_driver* d, const double* dl_dq, size_t n_edges, double*
   const size_t C = lw.chan_kind.size();
   if (n_rates != C) return fail(GP_E_ARG, "dl_dr length differs from the channel count");
   HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
+  // a batch was fetched circuit by circuit: back to the device's hyperedge order
+  // (the buffer lives until the stream is synchronised below)
+  std::vector<double> dev_order;
+  if (!d->edge_perm.empty()) {
+    dev_order.resize(n_edges);
+    for (size_t j = 0; j < n_edges; j++) dev_order[d->edge_perm[j]] = dl_dq[j];
+    dl_dq = dev_order.data();
+  }
   if (n_edges)
     HIP_TRY(hipMemcpyAsync(d->st.gq, dl_dq, n_edges * 8, hipMemcpyHostToDevice, d->stream), "upload dL/dq");
   HIP_TRY(gp::enqueue_rates_gradient(d->st, uint32_t(n_edges), d->stream), "kernel launch");
@@ -854,6 +919,7 @@ const uint32_t* gp_edges_bits(const gp_edges* e) { return e ? e->bits.data() : n
 const double* gp_edges_probabilities(const gp_edges* e) { return e ? e->q.data() : nullptr; }
 uint32_t gp_edges_circuits(const gp_edges* e) { return e ? uint32_t(e->c_det.size()) : 0; }
 const uint32_t* gp_edges_circuit_ids(const gp_edges* e) { return e ? e->circuit.data() : nullptr; }
+const uint64_t* gp_edges_circuit_offsets(const gp_edges* e) { return e ? e->c_off.data() : nullptr; }
 
 int gp_edges_circuit_shape(const gp_edges* e, uint32_t k, uint32_t* n_det, uint32_t* n_obs) {
   if (!e) return fail(GP_E_ARG, "null argument");

@@ -237,3 +237,19 @@ def test_concatenated_d10_batch_samples():
             assert_same(got[k], oracle.run(texts[k]), f"d10 branch {k} vs oracle")
         for k, t in enumerate(texts):
             assert_same(got[k], drv.compile_hypergraph(t), f"d10 branch {k} vs single", exact=True)
+
+
+def test_batch_result_is_listed_circuit_by_circuit(batch_driver):
+    cs = mixed_batch()
+    batch_driver.lower_batch([t for _, t, _ in cs], [r for _, _, r in cs])
+    batch_driver.run()
+    h = _gp.gp_fetch(batch_driver.handle)
+    try:
+        ids = _gp.gp_edges_circuit_ids(h)
+        cut = _gp.gp_edges_circuit_offsets(h)
+        assert len(cut) == len(cs) + 1 and cut[0] == 0 and cut[-1] == len(ids)
+        assert np.all(np.diff(ids.astype(np.int64)) >= 0)
+        for k in range(len(cs)):
+            assert np.all(ids[cut[k]:cut[k + 1]] == k)
+    finally:
+        _gp.gp_edges_free(h)
