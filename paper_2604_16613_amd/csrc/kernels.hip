@@ -154,6 +154,9 @@ __device__ __forceinline__ uint32_t digit_of(uint64_t k, uint32_t pass) { return
 
 // ------------------------------------------------------------------ prepare
 
+// the Pauli codes each channel kind keeps at each correlation level
+__constant__ KeptCodes c_kept = make_kept_codes();
+
 __global__ void k_prepare(DevState st) {
   const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t stride = gridDim.x * blockDim.x;
@@ -166,7 +169,7 @@ __global__ void k_prepare(DevState st) {
     for (uint32_t f = f0; f < f1; ++f) {
       st.frp[f].p = p;
       // Pauli code: x on a | z on a << 1 | x on b << 2 | z on b << 3
-      const uint32_t code = kept_code(kind, st.level, f - f0);
+      const uint32_t code = c_kept.code[kind][st.level][f - f0];
       st.frec[f] = qa | (qb << kQubitBits) | (code << 28);
     }
   }

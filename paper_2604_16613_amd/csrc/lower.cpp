@@ -79,6 +79,12 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
   uint32_t n_meas = 0, n_det = 0, n_obs = 0;
   std::vector<uint32_t> targets;
   std::vector<uint8_t> is_rec;
+  // sized from the text (typical circuits spend about four characters per
+  // target) so that the vectors rarely regrow
+  op_layer.reserve(len / 4);
+  op_word.reserve(len / 4);
+  chans.reserve(len / 8);
+  pairs.reserve(len / 8);
 
   auto touch = [&](uint32_t q) {
     if (q >= ready.size()) ready.resize(size_t(q) + 1, 0);
@@ -340,10 +346,10 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
     }
   }
   uint64_t total_faults = 0;
-  for (size_t c = 0; c < C; c++) total_faults += kept_faults(lw.chan_kind[c], lw.level);
+  for (size_t c = 0; c < C; c++) total_faults += kKeptCodes.n[lw.chan_kind[c]][lw.level];
   if (total_faults >= (1ull << 32)) return set_err(err, GP_E_BOUNDS, 0, "%s", "more than 2^32 - 1 faults");
   lw.chan_foff.assign(C + 1, 0);
-  for (size_t c = 0; c < C; c++) lw.chan_foff[c + 1] = lw.chan_foff[c] + kept_faults(lw.chan_kind[c], lw.level);
+  for (size_t c = 0; c < C; c++) lw.chan_foff[c + 1] = lw.chan_foff[c] + kKeptCodes.n[lw.chan_kind[c]][lw.level];
   lw.n_faults = total_faults;
   lw.bnd_fault_off.assign(size_t(L) + 2, 0);
   for (uint32_t b = 0; b <= L + 1; b++) lw.bnd_fault_off[b] = lw.chan_foff[lw.bnd_chan_off[b]];

@@ -73,6 +73,23 @@ constexpr uint32_t kept_code(uint32_t kind, uint32_t level, uint32_t j) {
   return 0u;
 }
 
+// Both, tabulated once per (channel kind, level): n[kind][level] kept faults
+// with Pauli codes code[kind][level][0 ..).
+struct KeptCodes {
+  uint8_t n[6][3];
+  uint8_t code[6][3][15];
+};
+constexpr KeptCodes make_kept_codes() {
+  KeptCodes t{};
+  for (uint32_t kind = 1; kind <= 5; kind++)
+    for (uint32_t level = 0; level <= 2; level++) {
+      t.n[kind][level] = uint8_t(kept_faults(kind, level));
+      for (uint32_t j = 0; j < t.n[kind][level]; j++) t.code[kind][level][j] = uint8_t(kept_code(kind, level, j));
+    }
+  return t;
+}
+inline constexpr KeptCodes kKeptCodes = make_kept_codes();
+
 // Compact ops one LDS op window of the sweep holds.
 constexpr uint32_t kSweepWinOps = 4096;
 // Sweep items that run at once: one per CU of the target GPU (256 on gfx950).
