@@ -113,6 +113,9 @@ def main() -> int:
     ap.add_argument("--batch-distances", default="3,5,7,10",
                     help="outer distances of the batched [[4,2,2]]-concatenated workload ('' skips it)")
     ap.add_argument("--batch-branches", type=int, default=256)
+    ap.add_argument("--serve-distances", default="5,10",
+                    help="outer distances of the served workload ('' skips it)")
+    ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain streaming copy of MIB MiB five times (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -207,6 +210,8 @@ def main() -> int:
     if args.batch_distances:
         out["batching"] = [bench_batched(int(d), args.batch_branches, args.steps)
                            for d in args.batch_distances.split(",")]
+    if args.serve_distances:
+        out["serving"] = [bench_serving(int(d), args.serve_requests) for d in args.serve_distances.split(",")]
 
     if not args.no_cpu_baseline:
         # the oracle on the whole workload, repeated until about cpu_seconds of
@@ -344,6 +349,66 @@ def bench_batched(d: int, n_branches: int, steps: int) -> dict:
             "batched_kernels_ms": kt,
             "timing": "device stages with tables resident (host wall clock over synced launches); "
                       "e2e = host lowering + upload + stages + download"}
+
+
+def bench_serving(d: int, n_requests: int, rate_hz: float = 1000.0, pool: int = 64) -> dict:
+    """The served workload: requests arrive as a Poisson process (seeded
+    exponential gaps, mean 1/rate_hz), each one realised branch of the
+    adaptive [[4,2,2]]-concatenated surface code at outer distance d, d
+    cycles (a pool of `pool` seeded branches, cycled). The server batches
+    what has arrived (up to 16 circuits per batch) over two drivers. Latency
+    is submit -> hyperedges on the host for that request, taken by the
+    server; also divided by the cycles (the paper's per-cycle normalisation)."""
+    import threading
+    from paper_2604_16613_amd import Server, _gp
+    from workloads import iceberg_surface_batch
+    print(f"served workload: outer d={d}, {n_requests} requests at {rate_hz:g} Hz", file=sys.stderr, flush=True)
+    texts = [c.text for c in iceberg_surface_batch(d, n_branches=pool, seed=1000)]
+    faults = [_gp.gp_bounds_from_circuit(t).max_faults for t in texts]
+    srv = Server.for_circuits(texts, max_batch=16)
+    for t in texts[:4]:
+        srv.wait(srv.submit(t))   # warm-up
+    gaps = np.random.default_rng(42).exponential(1.0 / rate_hz, n_requests)
+    tickets = [None] * n_requests
+    lat = np.zeros(n_requests)
+    done = threading.Event()
+
+    def collect():
+        for i in range(n_requests):
+            while tickets[i] is None:
+                time.sleep(1e-5)
+            _, lat[i] = srv.wait(tickets[i])
+        done.set()
+
+    th = threading.Thread(target=collect)
+    th.start()
+    start = time.perf_counter()
+    t_next = start
+    for i in range(n_requests):
+        t_next += gaps[i]
+        while True:
+            now = time.perf_counter()
+            if now >= t_next:
+                break
+            time.sleep(min(t_next - now, 2e-4))
+        tickets[i] = srv.submit(texts[i % pool])
+    th.join()
+    wall = time.perf_counter() - start
+    st = srv.stats()
+    srv.close()
+    served_faults = sum(faults[i % pool] for i in range(n_requests))
+    return {"workload": f"iceberg_surface_d{d} served: {n_requests} requests, Poisson {rate_hz:g} Hz "
+                        f"(seed 42), {pool} seeded branches cycled, d cycles each, uniform p=1e-3, level 2",
+            "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                           "max": float(lat.max())},
+            "per_cycle_latency_ms": {"p50": float(np.percentile(lat, 50)) / d,
+                                     "p99": float(np.percentile(lat, 99)) / d},
+            "requests_per_s": n_requests / wall, "faults_per_s": served_faults / wall,
+            "batches": st["batches"], "mean_batch": st["requests"] / max(st["batches"], 1),
+            "max_batch": st["max_batch"],
+            "worker_ms": {"lower": st["worker_lower_ms"], "merge_upload_launch": st["worker_upload_ms"],
+                          "wait_download_split": st["worker_fetch_ms"], "wall": wall * 1e3},
+            "latency_includes": "host lowering + upload + device stages + download + per-request split"}
 
 
 def copy_calibration(mib: int) -> int:

@@ -66,6 +66,7 @@ enum {
 
 typedef struct gp_driver gp_driver;
 typedef struct gp_edges gp_edges;
+typedef struct gp_server gp_server;
 
 /* Size bounds of a driver; every device buffer is allocated once from these
  * (paper Sec. 3.4, buffer reuse). Circuits within the bounds reuse the buffers.
@@ -188,6 +189,38 @@ int gp_refresh_rates(gp_driver* drv, const double* rates, size_t n_rates);
  * contribute nothing. Synchronous. GP_E_STATE without a fetched compile,
  * GP_E_ARG for wrong lengths. */
 int gp_rates_gradient(gp_driver* drv, const double* dl_dq, size_t n_edges, double* dl_dr, size_t n_rates);
+
+/* Request server (continuous batching). A worker thread owns two drivers
+ * created with `batch_bounds` (the bounds of one batch: max_branches circuits
+ * at most, totals summed over them), each on its own HIP stream of default
+ * priority on `device`. Every pass it takes the requests that have arrived,
+ * lowers the new ones on host threads, uploads them as one batch to the free
+ * driver and launches both stages; while that batch runs, it downloads the
+ * other driver's batch and completes those requests. A batch that exceeds the
+ * bounds is split; a request that exceeds them alone fails with GP_E_BOUNDS.
+ * Each request gets exactly the hyperedges of its own circuit (a batch never
+ * merges faults of two circuits), whatever it was batched with.
+ *
+ * gp_server_submit copies `text` and `rates` (host; rates NULL = the rates in
+ * the text) and returns a ticket at once. gp_server_wait blocks until that
+ * request is done (timeout_us < 0: no limit; otherwise GP_E_STATE when the
+ * time runs out, and the ticket stays valid), then hands over its result
+ * (*out, released with gp_edges_free) or returns the request's own error
+ * status and message; latency_ns (may be NULL) receives the time from submit
+ * to completion. A ticket is collected once; GP_E_ARG for unknown tickets.
+ * gp_server_stats reports batches launched, requests batched and the largest
+ * batch. gp_server_destroy finishes every submitted request, frees the
+ * results nobody collected and the drivers. The functions may be called from
+ * several host threads. */
+int gp_server_create(const gp_bounds* batch_bounds, int device, gp_server** out);
+int gp_server_submit(gp_server* srv, const char* text, size_t len, const double* rates, size_t n_rates,
+                     uint64_t* ticket);
+int gp_server_wait(gp_server* srv, uint64_t ticket, int64_t timeout_us, gp_edges** out, uint64_t* latency_ns);
+int gp_server_stats(const gp_server* srv, uint64_t* batches, uint64_t* requests, uint64_t* max_batch);
+/* Worker time so far in host lowering, in merging + uploading + launching,
+ * and in waiting for + downloading + splitting results (milliseconds). */
+int gp_server_timing(const gp_server* srv, double* lower_ms, double* upload_ms, double* fetch_ms);
+void gp_server_destroy(gp_server* srv);
 
 /* Wait for every operation enqueued on the driver's stream. */
 int gp_sync(gp_driver* drv);

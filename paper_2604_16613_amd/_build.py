@@ -22,7 +22,7 @@ ARCH = "gfx950"
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wall", "-Wno-unused-function", "-I", INCLUDE, "-I", CSRC]
-CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra", "-I", INCLUDE, "-I", CSRC]
+CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-Wextra", "-I", INCLUDE, "-I", CSRC]
 
 
 def _run(cmds: List[List[str]], verbose: bool) -> None:
@@ -62,7 +62,7 @@ def build(verbose: bool = False) -> str:
         objs.append(obj)
     _run(cmds, verbose)
     tmp = LIB + ".tmp"
-    _run([[HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]], verbose)
+    _run([[HIPCC, "-shared", "-fPIC", "-pthread", f"--offload-arch={ARCH}", *objs, "-o", tmp]], verbose)
     os.replace(tmp, LIB)
     return LIB
 

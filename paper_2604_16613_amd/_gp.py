@@ -32,7 +32,8 @@ EXPORTS = (
     "gp_debug_sweep_times", "gp_debug_set_sort_mode", "gp_refresh_rates", "gp_rates_gradient",
     "gp_set_correlation_level", "gp_bounds_from_batch", "gp_driver_create_from_batch", "gp_lower_batch",
     "gp_edges_circuits", "gp_edges_circuit_ids", "gp_edges_circuit_shape", "gp_edges_circuit_dem_text",
-    "gp_edges_circuit_offsets",
+    "gp_edges_circuit_offsets", "gp_server_create", "gp_server_submit", "gp_server_wait", "gp_server_stats",
+    "gp_server_destroy", "gp_server_timing",
 )
 
 
@@ -137,6 +138,14 @@ def load():
         "gp_edges_circuits": ([_vp], ctypes.c_uint32),
         "gp_edges_circuit_ids": ([_vp], ctypes.POINTER(ctypes.c_uint32)),
         "gp_edges_circuit_offsets": ([_vp], ctypes.POINTER(_u64)),
+        "gp_server_create": ([ctypes.POINTER(GpBounds), ctypes.c_int, ctypes.POINTER(_vp)], ctypes.c_int),
+        "gp_server_submit": ([_vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t,
+                              ctypes.POINTER(_u64)], ctypes.c_int),
+        "gp_server_wait": ([_vp, _u64, ctypes.c_int64, ctypes.POINTER(_vp), ctypes.POINTER(_u64)], ctypes.c_int),
+        "gp_server_stats": ([_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(_u64)], ctypes.c_int),
+        "gp_server_destroy": ([_vp], None),
+        "gp_server_timing": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "gp_edges_circuit_shape": ([_vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
                                     ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
         "gp_edges_circuit_dem_text": ([_vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p),
@@ -403,3 +412,42 @@ def gp_debug_sweep_times(drv: int, cap: int = 1 << 16):
                                        ctypes.byref(hz)))
     m = min(int(n.value), cap // 2)
     return buf[:2 * m].reshape(-1, 2), hz.value
+
+
+def gp_server_create(bounds: GpBounds, device: int = 0) -> int:
+    h = _vp()
+    _check(load().gp_server_create(ctypes.byref(bounds), device, ctypes.byref(h)))
+    return h.value
+
+
+def gp_server_submit(srv: int, text: str, rates: Optional[Sequence[float]] = None) -> int:
+    raw = text.encode()
+    rp, nr, _keep = _rates(rates)
+    t = _u64()
+    _check(load().gp_server_submit(srv, raw, len(raw), rp, nr, ctypes.byref(t)))
+    return t.value
+
+
+def gp_server_wait(srv: int, ticket: int, timeout_us: int = -1) -> Tuple[int, int]:
+    """-> (gp_edges handle, latency in ns from submit to completion)."""
+    h = _vp()
+    lat = _u64()
+    _check(load().gp_server_wait(srv, ticket, timeout_us, ctypes.byref(h), ctypes.byref(lat)))
+    return h.value, lat.value
+
+
+def gp_server_stats(srv: int) -> Tuple[int, int, int]:
+    b, r, m = _u64(), _u64(), _u64()
+    _check(load().gp_server_stats(srv, ctypes.byref(b), ctypes.byref(r), ctypes.byref(m)))
+    return b.value, r.value, m.value
+
+
+def gp_server_destroy(srv: int) -> None:
+    load().gp_server_destroy(srv)
+
+
+def gp_server_timing(srv: int) -> Tuple[float, float, float]:
+    lo, up, fe = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(load().gp_server_timing(srv, ctypes.byref(lo), ctypes.byref(up), ctypes.byref(fe)))
+    return lo.value, up.value, fe.value
+

@@ -175,6 +175,57 @@ class Driver:
         return out
 
 
+class Server:
+    """Continuous-batching request server (gp_server): submit circuits as they
+    arrive, wait for each one's hypergraph. `batch_bounds` bound one batch
+    (see Driver.from_batch / gp_bounds_from_batch for a set of circuits that
+    must fit in one)."""
+
+    def __init__(self, batch_bounds: _gp.GpBounds, device: int = 0):
+        self.bounds = batch_bounds
+        self.handle = _gp.gp_server_create(batch_bounds, device)
+
+    @classmethod
+    def for_circuits(cls, circuits: Sequence[str], max_batch: Optional[int] = None, device: int = 0) -> "Server":
+        """A server sized so that a batch may hold all of `circuits` at once;
+        `max_batch` (if given) caps the circuits per batch."""
+        b = _gp.gp_bounds_from_batch(circuits)
+        if max_batch is not None:
+            b.max_branches = max(1, min(int(max_batch), b.max_branches))
+        return cls(b, device)
+
+    def submit(self, circuit: str, rates: Optional[Sequence[float]] = None) -> int:
+        return _gp.gp_server_submit(self.handle, circuit, rates)
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> Tuple[Hypergraph, float]:
+        """-> (hypergraph, latency in ms from submit to completion)."""
+        h, lat = _gp.gp_server_wait(self.handle, ticket, timeout_us)
+        return _take(h), lat * 1e-6
+
+    def stats(self) -> Dict[str, int]:
+        b, r, m = _gp.gp_server_stats(self.handle)
+        lo, up, fe = _gp.gp_server_timing(self.handle)
+        return {"batches": b, "requests": r, "max_batch": m, "worker_lower_ms": lo, "worker_upload_ms": up,
+                "worker_fetch_ms": fe}
+
+    def close(self) -> None:
+        if self.handle:
+            _gp.gp_server_destroy(self.handle)
+            self.handle = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def get_driver(max_circuit: str, device: int = 0) -> Driver:
     """Listing 1: a driver whose buffers are sized for `max_circuit`."""
     return Driver.from_circuit(max_circuit, device)

@@ -11,6 +11,7 @@
 #include <thread>
 #include <vector>
 
+#include "driver_internal.h"
 #include "gp.h"
 #include "kernels.h"
 #include "lower.h"
@@ -43,7 +44,7 @@ uint32_t words_for(uint32_t det, uint32_t obs) { return (det + 63) / 64 + (obs +
 // Layout of the per-compile input tables inside one device arena and one
 // pinned host buffer of the same shape, so one copy uploads them all.
 struct TableLayout {
-  size_t ops, layer_off, leaf_off, leaf_bits, chan_qa, chan_qb, chan_kind, chan_rate, chan_foff, bnd_chan_off,
+  size_t layer_off, chan_qa, chan_qb, chan_kind, chan_rate, chan_foff, bnd_chan_off,
       bnd_fault_off, col_top, col_lo, col_base, item_col, item_blo, item_bhi, fnv_pow, ops32, inj_off, inj_layer,
       inj_qubit, inj_word, inj_next, hchunk_pos, hchunk_bnd, bnd_bm_off, col_bm_base, layer_win, win_lo, win_obase,
       win_cnt, branch, item_branch, hchunk_branch, total;
@@ -51,13 +52,13 @@ struct TableLayout {
 
 // Entry counts of the tables: exact for a lowering, upper bounds for a driver.
 struct TableSizes {
-  uint64_t ops, layer_entries, leaf_offs, leaf_bits, chans, bnd_entries, cols, items, fnv, hchunks, windows, branches;
+  uint64_t ops, layer_entries, inj, chans, bnd_entries, cols, items, fnv, hchunks, windows, branches;
 };
 
 TableSizes sizes_of(const gp::Lowered& lw) {
-  return {lw.ops.size(), lw.layer_off.size(), lw.leaf_off.size(), lw.leaf_bits.size(), lw.chan_kind.size(),
-          lw.bnd_fault_off.size(), lw.col_top.size(), lw.item_col.size(), lw.fnv_pow.size(), lw.hchunk_pos.size(),
-          lw.win_lo.size(), lw.branches.size()};
+  return {lw.ops32.size(), lw.layer_off.size(), lw.inj_layer.size(), lw.chan_kind.size(), lw.bnd_fault_off.size(),
+          lw.col_top.size(), lw.item_col.size(), lw.fnv_pow.size(), lw.hchunk_pos.size(), lw.win_lo.size(),
+          lw.branches.size()};
 }
 
 TableLayout layout_for(const TableSizes& z) {
@@ -67,10 +68,7 @@ TableLayout layout_for(const TableSizes& z) {
     f = o;
     o += align_up(bytes ? bytes : 1);
   };
-  take(t.ops, z.ops * 8);
   take(t.layer_off, z.layer_entries * 4);
-  take(t.leaf_off, z.leaf_offs * 4);
-  take(t.leaf_bits, z.leaf_bits * 4);
   take(t.chan_qa, z.chans * 4);
   take(t.chan_qb, z.chans * 4);
   take(t.chan_kind, z.chans);
@@ -87,10 +85,10 @@ TableLayout layout_for(const TableSizes& z) {
   take(t.fnv_pow, z.fnv * 8);
   take(t.ops32, z.ops * 4);
   take(t.inj_off, (z.cols + 1) * 4);
-  take(t.inj_layer, z.leaf_bits * 4);
-  take(t.inj_qubit, z.leaf_bits * 4);
-  take(t.inj_word, z.leaf_bits * 8);
-  take(t.inj_next, z.leaf_bits * 4);
+  take(t.inj_layer, z.inj * 4);
+  take(t.inj_qubit, z.inj * 4);
+  take(t.inj_word, z.inj * 8);
+  take(t.inj_next, z.inj * 4);
   take(t.hchunk_pos, z.hchunks * 4);
   take(t.hchunk_bnd, z.hchunks * 4);
   take(t.bnd_bm_off, z.bnd_entries * 4);
@@ -218,8 +216,9 @@ uint64_t hash_chunk_cap(const gp_bounds& b) {
 // Table capacities of a driver: per-circuit maxima times the circuits of a batch.
 TableSizes sizes_cap(const gp_bounds& b, uint32_t max_w) {
   const uint64_t B = branches_of(b), L = b.max_layers;
-  return {b.max_ops, B * (L + 1), uint64_t(b.max_measurements) + B, b.max_leaf_bits, b.max_channels, B * (L + 2),
-          B * max_w, b.max_items, uint64_t(max_w) + 1, hash_chunk_cap(b), B * (L + 1), B};
+  // injection entries: one per (column, measurement) pair, so at most one per leaf bit
+  return {b.max_ops, B * (L + 1), b.max_leaf_bits, b.max_channels, B * (L + 2), B * max_w, b.max_items,
+          uint64_t(max_w) + 1, hash_chunk_cap(b), B * (L + 1), B};
 }
 
 int check_bounds(const gp_driver* d, const gp::Lowered& lw) {
@@ -489,10 +488,7 @@ static int upload_lowered(gp_driver* d) {
   auto put = [&](size_t off, const void* src, size_t bytes) {
     if (bytes) std::memcpy(h + off, src, bytes);
   };
-  put(tl.ops, lw.ops.data(), lw.ops.size() * 8);
   put(tl.layer_off, lw.layer_off.data(), lw.layer_off.size() * 4);
-  put(tl.leaf_off, lw.leaf_off.data(), lw.leaf_off.size() * 4);
-  put(tl.leaf_bits, lw.leaf_bits.data(), lw.leaf_bits.size() * 4);
   put(tl.chan_qa, lw.chan_qa.data(), lw.chan_qa.size() * 4);
   put(tl.chan_qb, lw.chan_qb.data(), lw.chan_qb.size() * 4);
   put(tl.chan_kind, lw.chan_kind.data(), lw.chan_kind.size());
@@ -528,10 +524,7 @@ static int upload_lowered(gp_driver* d) {
 
   gp::DevState& st = d->st;
   char* D = d->d_tables;
-  st.ops = reinterpret_cast<const uint64_t*>(D + tl.ops);
   st.layer_off = reinterpret_cast<const uint32_t*>(D + tl.layer_off);
-  st.leaf_off = reinterpret_cast<const uint32_t*>(D + tl.leaf_off);
-  st.leaf_bits = reinterpret_cast<const uint32_t*>(D + tl.leaf_bits);
   st.chan_qa = reinterpret_cast<const uint32_t*>(D + tl.chan_qa);
   st.chan_qb = reinterpret_cast<const uint32_t*>(D + tl.chan_qb);
   st.chan_kind = reinterpret_cast<const uint8_t*>(D + tl.chan_kind);
@@ -635,9 +628,18 @@ int gp_sync(gp_driver* d) {
   return GP_OK;
 }
 
-int gp_fetch(gp_driver* d, gp_edges** out) {
-  if (!d || !out) return fail(GP_E_ARG, "null argument");
-  *out = nullptr;
+// A fetched compile in the pinned staging buffer.
+struct Staged {
+  uint64_t U = 0, nb = 0;
+  const uint32_t* off32 = nullptr;
+  const uint32_t* bits32 = nullptr;
+  const double* q64 = nullptr;
+  const uint32_t* cid = nullptr;  // null unless a batch
+};
+
+// Wait for the compile (redoing it for the retry flags), check the device
+// flags and download the hyperedges into the pinned staging buffer.
+static int fetch_staged(gp_driver* d, Staged& out) {
   if (!d->ran) return fail(GP_E_STATE, "gp_fetch before gp_run");
   HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
   HIP_TRY(hipMemcpyAsync(d->h_hdr, d->st.hdr, sizeof(gp::DevHeader), hipMemcpyDeviceToHost, d->stream),
@@ -693,12 +695,29 @@ int gp_fetch(gp_driver* d, gp_edges** out) {
   if (U && batch)
     HIP_TRY(hipMemcpyAsync(h + o_c, d->st.edge_branch, U * 4, hipMemcpyDeviceToHost, d->stream), "download");
   HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
+  out.U = U;
+  out.nb = nb;
+  out.off32 = reinterpret_cast<const uint32_t*>(h + o_off);
+  out.bits32 = reinterpret_cast<const uint32_t*>(h + o_bits);
+  out.q64 = reinterpret_cast<const double*>(h + o_q);
+  out.cid = batch ? reinterpret_cast<const uint32_t*>(h + o_c) : nullptr;
+  return GP_OK;
+}
+
+int gp_fetch(gp_driver* d, gp_edges** out) {
+  if (!d || !out) return fail(GP_E_ARG, "null argument");
+  *out = nullptr;
+  Staged sg;
+  int rc = fetch_staged(d, sg);
+  if (rc) return rc;
+  const uint64_t U = sg.U, nb = sg.nb;
+  const uint32_t* off32 = sg.off32;
+  const uint32_t* bits32 = sg.bits32;
+  const double* q64 = sg.q64;
+  const bool batch = sg.cid != nullptr;
   gp_edges* e = new gp_edges();
   e->n_det = d->lw.n_det;
   e->n_obs = d->lw.n_obs;
-  const uint32_t* off32 = reinterpret_cast<const uint32_t*>(h + o_off);
-  const uint32_t* bits32 = reinterpret_cast<const uint32_t*>(h + o_bits);
-  const double* q64 = reinterpret_cast<const double*>(h + o_q);
   const size_t B = d->lw.branches.size();
   for (const gp::BranchDesc& bd : d->lw.branches) {
     e->c_det.push_back(bd.n_det);
@@ -716,7 +735,7 @@ int gp_fetch(gp_driver* d, gp_edges** out) {
   } else {
     // circuit by circuit (a stable counting sort), each circuit's hyperedges
     // in the order the device wrote them
-    const uint32_t* cid = reinterpret_cast<const uint32_t*>(h + o_c);
+    const uint32_t* cid = sg.cid;
     std::vector<uint64_t> bit_off(B + 1, 0);
     for (uint64_t i = 0; i < U; i++) {
       if (cid[i] >= B) {
@@ -968,3 +987,60 @@ void gp_edges_free(gp_edges* e) { delete e; }
 void gp_free(void* p) { std::free(p); }
 
 }  // extern "C"
+
+namespace gp {
+
+int driver_upload_parts(gp_driver* d, const std::vector<const Lowered*>& parts) {
+  if (!d || parts.empty()) return fail(GP_E_ARG, "a batch needs a driver and at least one circuit");
+  d->lowered = false;
+  d->ran = false;
+  d->structured = false;
+  merge_branches(parts, d->lw);
+  return upload_lowered(d);
+}
+
+uint32_t driver_level(const gp_driver* d) { return d ? d->level : 2u; }
+
+int driver_fetch_split(gp_driver* d, std::vector<gp_edges*>& out) {
+  out.clear();
+  if (!d) return fail(GP_E_ARG, "null driver");
+  Staged sg;
+  int rc = fetch_staged(d, sg);
+  if (rc) return rc;
+  // the split order is not the device's: no refresh or adjoint on this compile
+  d->structured = false;
+  const size_t B = d->lw.branches.size();
+  std::vector<uint64_t> ne(B, 0), nbits(B, 0);
+  for (uint64_t i = 0; i < sg.U; i++) {
+    const uint32_t k = sg.cid ? sg.cid[i] : 0u;
+    if (k >= B) return fail(GP_E_HIP, "a hyperedge names a circuit outside the batch");
+    ne[k]++;
+    nbits[k] += sg.off32[i + 1] - sg.off32[i];
+  }
+  out.resize(B);
+  for (size_t k = 0; k < B; k++) {
+    gp_edges* e = new gp_edges();
+    e->n_det = d->lw.branches[k].n_det;
+    e->n_obs = d->lw.branches[k].n_obs;
+    e->off.reserve(ne[k] + 1);
+    e->off.push_back(0);
+    e->bits.reserve(nbits[k]);
+    e->q.reserve(ne[k]);
+    e->circuit.assign(ne[k], 0u);
+    e->c_det.assign(1, e->n_det);
+    e->c_obs.assign(1, e->n_obs);
+    e->c_off = {0, ne[k]};
+    out[k] = e;
+  }
+  for (uint64_t i = 0; i < sg.U; i++) {
+    gp_edges* e = out[sg.cid ? sg.cid[i] : 0u];
+    e->bits.insert(e->bits.end(), sg.bits32 + sg.off32[i], sg.bits32 + sg.off32[i + 1]);
+    e->off.push_back(e->bits.size());
+    e->q.push_back(sg.q64[i]);
+  }
+  return GP_OK;
+}
+
+int set_last_error(int code, const std::string& msg) { return fail(code, msg); }
+
+}  // namespace gp

@@ -54,10 +54,7 @@ struct __align__(16) FaultRec {
 // Everything one compile reads or writes on the device.
 struct DevState {
   // lowered tables (inputs, uploaded per circuit)
-  const uint64_t* ops;
   const uint32_t* layer_off;
-  const uint32_t* leaf_off;
-  const uint32_t* leaf_bits;
   const uint32_t* chan_qa;
   const uint32_t* chan_qb;
   const uint8_t* chan_kind;

@@ -565,12 +565,77 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
 }
 
 void merge_branches(const std::vector<Lowered>& in, Lowered& out) {
+  std::vector<const Lowered*> ptrs;
+  for (const Lowered& a : in) ptrs.push_back(&a);
+  merge_branches(ptrs, out);
+}
+
+namespace {
+
+template <typename T>
+void append(std::vector<T>& dst, const std::vector<T>& src) {
+  dst.insert(dst.end(), src.begin(), src.end());
+}
+
+template <typename T, typename U>
+void append_plus(std::vector<T>& dst, const std::vector<T>& src, U add) {
+  const size_t n0 = dst.size();
+  dst.resize(n0 + src.size());
+  T* o = dst.data() + n0;
+  for (size_t i = 0; i < src.size(); i++) o[i] = T(src[i] + add);
+}
+
+}  // namespace
+
+void merge_branches(const std::vector<const Lowered*>& in, Lowered& out) {
   out = Lowered();
+  // every table is sized once, then filled by bulk appends
+  size_t n_ops = 0, n_lay = 0, n_leafo = 0, n_leaf = 0, n_meas = 0, n_ch = 0, n_bnd = 0, n_col = 0, n_inj = 0,
+         n_item = 0, n_hc = 0, n_win = 0;
+  for (const Lowered* a : in) {
+    n_ops += a->ops.size();
+    n_lay += a->layer_off.size();
+    n_leafo += a->leaf_off.size();
+    n_leaf += a->leaf_bits.size();
+    n_meas += a->meas_layer.size();
+    n_ch += a->chan_kind.size();
+    n_bnd += a->bnd_fault_off.size();
+    n_col += a->w;
+    n_inj += a->inj_layer.size();
+    n_item += a->item_col.size();
+    n_hc += a->hchunk_pos.size();
+    n_win += a->win_lo.size();
+  }
+  out.ops.reserve(n_ops);
+  out.ops32.reserve(n_ops);
+  out.layer_off.reserve(n_lay);
+  out.layer_win.reserve(n_lay);
+  out.leaf_off.reserve(n_leafo);
+  out.leaf_bits.reserve(n_leaf);
+  out.meas_layer.reserve(n_meas);
+  for (auto* v : {&out.chan_qa, &out.chan_qb, &out.chan_src}) v->reserve(n_ch);
+  out.chan_kind.reserve(n_ch);
+  out.chan_rate.reserve(n_ch);
+  out.chan_foff.reserve(n_ch + 1);
+  for (auto* v : {&out.bnd_chan_off, &out.bnd_fault_off, &out.bnd_bm_off}) v->reserve(n_bnd);
+  out.col_top.reserve(n_col);
+  out.col_lo.reserve(n_col);
+  out.col_base.reserve(n_col);
+  out.col_bm_base.reserve(n_col);
+  out.inj_off.reserve(n_col + 1);
+  for (auto* v : {&out.inj_layer, &out.inj_qubit, &out.inj_next}) v->reserve(n_inj);
+  out.inj_word.reserve(n_inj);
+  for (auto* v : {&out.item_col, &out.item_blo, &out.item_bhi, &out.item_branch}) v->reserve(n_item);
+  for (auto* v : {&out.hchunk_pos, &out.hchunk_bnd, &out.hchunk_branch}) v->reserve(n_hc);
+  for (auto* v : {&out.win_lo, &out.win_obase, &out.win_cnt}) v->reserve(n_win);
+  out.branches.reserve(in.size());
+
   uint32_t ob = 0, cb = 0, fb = 0, wb = 0, ib = 0, wib = 0, mb = 0;
   uint64_t sb = 0, bmb = 0;
   std::vector<uint32_t> item_order_span;
+  item_order_span.reserve(n_item);
   for (size_t k = 0; k < in.size(); k++) {
-    const Lowered& a = in[k];
+    const Lowered& a = *in[k];
     out.n_qubits = std::max(out.n_qubits, a.n_qubits);
     out.n_layers = std::max(out.n_layers, a.n_layers);
     out.n_det = std::max(out.n_det, a.n_det);
@@ -592,61 +657,59 @@ void merge_branches(const std::vector<Lowered>& in, Lowered& out) {
     bd.fb = fb;
     bd.fe = fb + uint32_t(a.n_faults);
     out.branches.push_back(bd);
-    for (uint64_t o : a.ops) out.ops.push_back(o);
-    for (uint32_t o : a.ops32) out.ops32.push_back(o);
-    for (uint32_t v : a.layer_off) out.layer_off.push_back(v + ob);
-    for (uint32_t v : a.layer_win) out.layer_win.push_back(v);
-    for (uint32_t v : a.leaf_off) out.leaf_off.push_back(v);
-    for (uint32_t v : a.leaf_bits) out.leaf_bits.push_back(v);
-    for (uint32_t v : a.meas_layer) out.meas_layer.push_back(v);
-    const size_t C = a.chan_kind.size();
-    for (size_t c = 0; c < C; c++) {
-      out.chan_qa.push_back(a.chan_qa[c]);
-      out.chan_qb.push_back(a.chan_qb[c]);
-      out.chan_kind.push_back(a.chan_kind[c]);
-      out.chan_rate.push_back(a.chan_rate[c]);
-      out.chan_src.push_back(a.chan_src[c] + cb);
-      out.chan_foff.push_back(a.chan_foff[c] + fb);
+    append(out.ops, a.ops);
+    append(out.ops32, a.ops32);
+    append_plus(out.layer_off, a.layer_off, ob);
+    append(out.layer_win, a.layer_win);
+    append(out.leaf_off, a.leaf_off);
+    append(out.leaf_bits, a.leaf_bits);
+    append(out.meas_layer, a.meas_layer);
+    append(out.chan_qa, a.chan_qa);
+    append(out.chan_qb, a.chan_qb);
+    append(out.chan_kind, a.chan_kind);
+    append(out.chan_rate, a.chan_rate);
+    append_plus(out.chan_src, a.chan_src, cb);
+    {
+      // chan_foff holds C + 1 entries per circuit; the batch keeps one closing entry
+      const size_t C = a.chan_kind.size();
+      const size_t n0 = out.chan_foff.size();
+      out.chan_foff.resize(n0 + C);
+      for (size_t c = 0; c < C; c++) out.chan_foff[n0 + c] = a.chan_foff[c] + fb;
     }
-    for (uint32_t v : a.bnd_chan_off) out.bnd_chan_off.push_back(v + cb);
-    for (uint32_t v : a.bnd_fault_off) out.bnd_fault_off.push_back(v + fb);
-    for (uint32_t v : a.bnd_bm_off) out.bnd_bm_off.push_back(v);
+    append_plus(out.bnd_chan_off, a.bnd_chan_off, cb);
+    append_plus(out.bnd_fault_off, a.bnd_fault_off, fb);
+    append(out.bnd_bm_off, a.bnd_bm_off);
     // slab words are addressed by base + (batch) fault position: the circuit's
     // slab starts at sb >= fb, so its bases (sb - fb + own base) stay >= 0
     sb = std::max<uint64_t>(sb, fb);
-    for (uint32_t w = 0; w < a.w; w++) {
-      out.col_top.push_back(a.col_top[w]);
-      out.col_lo.push_back(a.col_lo[w]);
-      out.col_base.push_back(a.col_base[w] + sb - fb);
-      out.col_bm_base.push_back(a.col_bm_base[w] + bmb);
-      out.inj_off.push_back(a.inj_off[w] + ib);
+    append(out.col_top, a.col_top);
+    append(out.col_lo, a.col_lo);
+    append_plus(out.col_base, a.col_base, sb - fb);
+    append_plus(out.col_bm_base, a.col_bm_base, bmb);
+    {
+      const size_t n0 = out.inj_off.size();
+      out.inj_off.resize(n0 + a.w);
+      for (uint32_t w = 0; w < a.w; w++) out.inj_off[n0 + w] = a.inj_off[w] + ib;
     }
-    for (size_t e = 0; e < a.inj_layer.size(); e++) {
-      out.inj_layer.push_back(a.inj_layer[e]);
-      out.inj_qubit.push_back(a.inj_qubit[e]);
-      out.inj_word.push_back(a.inj_word[e]);
-      out.inj_next.push_back(a.inj_next[e]);
-    }
-    for (size_t t = 0; t < a.item_col.size(); t++) {
-      out.item_col.push_back(a.item_col[t] + wb);
-      out.item_blo.push_back(a.item_blo[t]);
-      out.item_bhi.push_back(a.item_bhi[t]);
-      out.item_branch.push_back(uint32_t(k));
+    append(out.inj_layer, a.inj_layer);
+    append(out.inj_qubit, a.inj_qubit);
+    append(out.inj_word, a.inj_word);
+    append(out.inj_next, a.inj_next);
+    append_plus(out.item_col, a.item_col, wb);
+    append(out.item_blo, a.item_blo);
+    append(out.item_bhi, a.item_bhi);
+    out.item_branch.resize(out.item_branch.size() + a.item_col.size(), uint32_t(k));
+    for (size_t t = 0; t < a.item_col.size(); t++)
       item_order_span.push_back(uint32_t(a.col_top[a.item_col[t]] - int32_t(a.item_blo[t]) + 1));
-    }
-    for (size_t h = 0; h < a.hchunk_pos.size(); h++) {
-      out.hchunk_pos.push_back(a.hchunk_pos[h] + fb);
-      out.hchunk_bnd.push_back(a.hchunk_bnd[h]);
-      out.hchunk_branch.push_back(uint32_t(k));
-    }
-    for (size_t x = 0; x < a.win_lo.size(); x++) {
-      out.win_lo.push_back(a.win_lo[x]);
-      out.win_obase.push_back(a.win_obase[x] + ob);
-      out.win_cnt.push_back(a.win_cnt[x]);
-    }
+    append_plus(out.hchunk_pos, a.hchunk_pos, fb);
+    append(out.hchunk_bnd, a.hchunk_bnd);
+    out.hchunk_branch.resize(out.hchunk_branch.size() + a.hchunk_pos.size(), uint32_t(k));
+    append(out.win_lo, a.win_lo);
+    append_plus(out.win_obase, a.win_obase, ob);
+    append(out.win_cnt, a.win_cnt);
     if (a.fnv_pow.size() > out.fnv_pow.size()) out.fnv_pow = a.fnv_pow;
     ob += uint32_t(a.ops32.size());
-    cb += uint32_t(C);
+    cb += uint32_t(a.chan_kind.size());
     fb += uint32_t(a.n_faults);
     wb += a.w;
     ib += uint32_t(a.inj_layer.size());

@@ -184,6 +184,7 @@ struct Lowered {
 // boundaries stay per circuit, reached through the descriptors). Sweep items
 // are ordered by the number of layers they sweep, longest first.
 void merge_branches(const std::vector<Lowered>& in, Lowered& out);
+void merge_branches(const std::vector<const Lowered*>& in, Lowered& out);
 
 struct LowerError {
   int code;

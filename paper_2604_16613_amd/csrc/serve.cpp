@@ -1,0 +1,318 @@
+// Request server: continuous batching over two drivers (C ABI in gp.h).
+//
+// A worker thread owns two drivers of identical bounds, each with its own
+// HIP stream. Every pass it takes the requests that arrived (up to the
+// batch size the bounds allow), lowers the new ones on host threads, uploads
+// them as one batch to the free driver and launches both stages there; while
+// that batch runs on the device it downloads the other driver's finished
+// batch and completes its requests, each with its own circuit's hyperedges.
+// Requests never share a hyperedge (a batch groups every circuit on its own),
+// so a request's result does not depend on what it was batched with.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "driver_internal.h"
+#include "gp.h"
+#include "lower.h"
+
+namespace {
+
+uint64_t now_ns() {
+  return uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(
+                      std::chrono::steady_clock::now().time_since_epoch()).count());
+}
+
+struct Request {
+  uint64_t ticket = 0;
+  std::string text;
+  std::vector<double> rates;
+  bool has_rates = false;
+  uint64_t t_submit = 0, t_done = 0;
+  bool lowered = false;
+  bool solo = false;  // failed inside a batch: runs alone next, to find whose error it was
+  gp::Lowered lw;
+  bool done = false;
+  int rc = GP_OK;
+  std::string msg;
+  gp_edges* edges = nullptr;
+};
+
+using ReqPtr = std::shared_ptr<Request>;
+
+}  // namespace
+
+struct gp_server {
+  gp_bounds bounds{};
+  gp_driver* drv[2] = {nullptr, nullptr};
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<ReqPtr> pending;
+  std::unordered_map<uint64_t, ReqPtr> live;  // submitted and not yet collected
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  std::thread worker;
+  uint64_t n_batches = 0, n_requests = 0, max_batch = 0;
+  uint64_t ns_lower = 0, ns_upload = 0, ns_fetch = 0;  // worker time in each phase
+};
+
+namespace {
+
+void complete(gp_server* s, const ReqPtr& r, int rc, const std::string& msg, gp_edges* e) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  r->rc = rc;
+  r->msg = msg;
+  r->edges = e;
+  r->t_done = now_ns();
+  r->done = true;
+  r->lw = gp::Lowered();  // the tables are no longer needed
+  s->cv_done.notify_all();
+}
+
+// Lower the requests that are not lowered yet, on up to 16 host threads.
+void lower_new(gp_server* s, const std::vector<ReqPtr>& reqs, uint32_t level) {
+  std::vector<ReqPtr> todo;
+  for (const ReqPtr& r : reqs)
+    if (!r->lowered) todo.push_back(r);
+  if (todo.empty()) return;
+  const uint32_t slots = std::max<uint32_t>(1, gp::kSweepSlots / uint32_t(std::max<size_t>(reqs.size(), 1)));
+  std::vector<int> rcs(todo.size());
+  std::vector<gp::LowerError> errs(todo.size());
+  auto run = [&](size_t lo, size_t hi) {
+    for (size_t k = lo; k < hi; k++) {
+      Request& r = *todo[k];
+      rcs[k] = gp::lower_circuit(r.text.data(), r.text.size(), r.has_rates ? r.rates.data() : nullptr,
+                                 r.has_rates ? r.rates.size() : 0, slots, r.lw, errs[k], level);
+    }
+  };
+  const size_t n = todo.size();
+  const size_t nt = std::min<size_t>({n, 16, std::max<size_t>(1, std::thread::hardware_concurrency())});
+  if (nt <= 1) {
+    run(0, n);
+  } else {
+    std::vector<std::thread> pool;
+    for (size_t t = 0; t < nt; t++) pool.emplace_back(run, n * t / nt, n * (t + 1) / nt);
+    for (std::thread& th : pool) th.join();
+  }
+  for (size_t k = 0; k < n; k++) {
+    todo[k]->lowered = true;
+    if (rcs[k]) complete(s, todo[k], rcs[k], errs[k].msg, nullptr);
+  }
+}
+
+// Download a driver's finished batch and complete its requests.
+void finish(gp_server* s, int slot, std::vector<ReqPtr>& batch) {
+  if (batch.empty()) return;
+  const uint64_t t0 = now_ns();
+  std::vector<gp_edges*> parts;
+  int rc = gp::driver_fetch_split(s->drv[slot], parts);
+  if (rc && batch.size() > 1) {
+    // a device-side error (e.g. a non-deterministic detector) names no
+    // circuit: every request of the batch runs again on its own
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (size_t k = batch.size(); k-- > 0;) {
+      batch[k]->solo = true;
+      s->pending.push_front(batch[k]);
+    }
+  } else if (rc) {
+    const std::string msg = gp_last_error();
+    for (const ReqPtr& r : batch) complete(s, r, rc, msg, nullptr);
+  } else {
+    for (size_t k = 0; k < batch.size(); k++) {
+      if (k < parts.size())
+        complete(s, batch[k], GP_OK, "", parts[k]);
+      else
+        complete(s, batch[k], GP_E_STATE, "result missing for a circuit of the batch", nullptr);
+    }
+    for (size_t k = batch.size(); k < parts.size(); k++) gp_edges_free(parts[k]);
+  }
+  batch.clear();
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->ns_fetch += now_ns() - t0;
+}
+
+void worker_loop(gp_server* s) {
+  const size_t max_batch = std::max<uint32_t>(s->bounds.max_branches, 1);
+  const uint32_t level = gp::driver_level(s->drv[0]);
+  std::vector<ReqPtr> inflight[2];
+  int cur = 0;
+  for (;;) {
+    std::vector<ReqPtr> take;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      const bool busy = !inflight[0].empty() || !inflight[1].empty();
+      if (!busy) s->cv_work.wait(lk, [&] { return s->stop || !s->pending.empty(); });
+      if (s->pending.empty() && !busy && s->stop) break;
+      while (!s->pending.empty() && take.size() < max_batch) {
+        const bool solo = s->pending.front()->solo;
+        if (solo && !take.empty()) break;
+        take.push_back(s->pending.front());
+        s->pending.pop_front();
+        if (solo) break;
+      }
+    }
+    const uint64_t t0 = now_ns();
+    lower_new(s, take, level);
+    const uint64_t t1 = now_ns();
+    std::vector<ReqPtr> batch;
+    for (const ReqPtr& r : take)
+      if (!r->done) batch.push_back(r);
+    // upload the largest prefix that fits the bounds; the rest waits
+    while (!batch.empty()) {
+      if (!inflight[cur].empty()) finish(s, cur, inflight[cur]);
+      std::vector<const gp::Lowered*> parts;
+      for (const ReqPtr& r : batch) parts.push_back(&r->lw);
+      const uint64_t u0 = now_ns();
+      int rc = gp::driver_upload_parts(s->drv[cur], parts);
+      if (rc == GP_OK) rc = gp_run(s->drv[cur]);
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->ns_upload += now_ns() - u0;
+      }
+      if (rc == GP_OK) break;
+      const std::string msg = gp_last_error();
+      if (rc != GP_E_BOUNDS || batch.size() == 1) {
+        for (const ReqPtr& r : batch) complete(s, r, rc, msg, nullptr);
+        batch.clear();
+        break;
+      }
+      const size_t keep = batch.size() / 2;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (size_t k = batch.size(); k-- > keep;) s->pending.push_front(batch[k]);
+      }
+      batch.resize(keep);
+    }
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->ns_lower += t1 - t0;
+    }
+    if (!batch.empty()) {
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->n_batches++;
+        s->n_requests += batch.size();
+        s->max_batch = std::max<uint64_t>(s->max_batch, batch.size());
+      }
+      inflight[cur] = std::move(batch);
+      // the new batch runs while the older one is downloaded
+      finish(s, cur ^ 1, inflight[cur ^ 1]);
+      cur ^= 1;
+    } else {
+      finish(s, cur ^ 1, inflight[cur ^ 1]);
+      finish(s, cur, inflight[cur]);
+    }
+  }
+  finish(s, 0, inflight[0]);
+  finish(s, 1, inflight[1]);
+}
+
+}  // namespace
+
+extern "C" {
+
+int gp_server_create(const gp_bounds* bounds, int device, gp_server** out) {
+  if (!bounds || !out) return gp::set_last_error(GP_E_ARG, "null argument");
+  *out = nullptr;
+  gp_server* s = new gp_server();
+  s->bounds = *bounds;
+  for (int k = 0; k < 2; k++) {
+    int rc = gp_driver_create(bounds, device, &s->drv[k]);
+    if (rc) {
+      const std::string msg = gp_last_error();
+      if (s->drv[0]) gp_driver_destroy(s->drv[0]);
+      delete s;
+      return gp::set_last_error(rc, msg);
+    }
+  }
+  s->worker = std::thread(worker_loop, s);
+  *out = s;
+  return GP_OK;
+}
+
+int gp_server_submit(gp_server* s, const char* text, size_t len, const double* rates, size_t n_rates,
+                     uint64_t* ticket) {
+  if (!s || !text || !ticket || (!rates && n_rates)) return gp::set_last_error(GP_E_ARG, "null argument");
+  ReqPtr r = std::make_shared<Request>();
+  r->text.assign(text, len);
+  if (rates) {
+    r->rates.assign(rates, rates + n_rates);
+    r->has_rates = true;
+  }
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return gp::set_last_error(GP_E_STATE, "the server is shutting down");
+    r->ticket = s->next_ticket++;
+    r->t_submit = now_ns();
+    s->pending.push_back(r);
+    s->live[r->ticket] = r;
+  }
+  s->cv_work.notify_one();
+  *ticket = r->ticket;
+  return GP_OK;
+}
+
+int gp_server_wait(gp_server* s, uint64_t ticket, int64_t timeout_us, gp_edges** out, uint64_t* latency_ns) {
+  if (!s || !out) return gp::set_last_error(GP_E_ARG, "null argument");
+  *out = nullptr;
+  std::unique_lock<std::mutex> lk(s->mu);
+  auto it = s->live.find(ticket);
+  if (it == s->live.end()) return gp::set_last_error(GP_E_ARG, "unknown ticket (never issued or already collected)");
+  ReqPtr r = it->second;
+  if (timeout_us < 0) {
+    s->cv_done.wait(lk, [&] { return r->done; });
+  } else if (!s->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), [&] { return r->done; })) {
+    return gp::set_last_error(GP_E_STATE, "the request has not finished yet");
+  }
+  s->live.erase(ticket);
+  if (latency_ns) *latency_ns = r->t_done - r->t_submit;
+  if (r->rc) return gp::set_last_error(r->rc, r->msg);
+  *out = r->edges;
+  r->edges = nullptr;
+  return GP_OK;
+}
+
+int gp_server_stats(const gp_server* s, uint64_t* batches, uint64_t* requests, uint64_t* max_batch) {
+  if (!s) return gp::set_last_error(GP_E_ARG, "null server");
+  gp_server* m = const_cast<gp_server*>(s);
+  std::lock_guard<std::mutex> lk(m->mu);
+  if (batches) *batches = s->n_batches;
+  if (requests) *requests = s->n_requests;
+  if (max_batch) *max_batch = s->max_batch;
+  return GP_OK;
+}
+
+int gp_server_timing(const gp_server* s, double* lower_ms, double* upload_ms, double* fetch_ms) {
+  if (!s) return gp::set_last_error(GP_E_ARG, "null server");
+  gp_server* m = const_cast<gp_server*>(s);
+  std::lock_guard<std::mutex> lk(m->mu);
+  if (lower_ms) *lower_ms = s->ns_lower * 1e-6;
+  if (upload_ms) *upload_ms = s->ns_upload * 1e-6;
+  if (fetch_ms) *fetch_ms = s->ns_fetch * 1e-6;
+  return GP_OK;
+}
+
+void gp_server_destroy(gp_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  for (auto& kv : s->live)
+    if (kv.second->edges) gp_edges_free(kv.second->edges);
+  for (gp_driver* d : s->drv)
+    if (d) gp_driver_destroy(d);
+  delete s;
+}
+
+}  // extern "C"

@@ -93,3 +93,15 @@ def test_driver_without_gpu_fails_loudly():
     with pytest.raises(_gp.GpError) as e:
         _gp.gp_driver_create_from_circuit(rotated_surface_code_memory(3, 3).text)
     assert e.value.code == -7
+
+
+def test_server_without_a_device_fails_cleanly():
+    """gp_server_create needs a gfx950 device; without one it reports GP_E_HIP
+    (or GP_E_ARG for null bounds) and allocates nothing."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present; the server is covered by the GPU tests")
+    b = _gp.gp_bounds_from_circuit(rotated_surface_code_memory(3, 3).text)
+    with pytest.raises(_gp.GpError) as e:
+        _gp.gp_server_create(b, 0)
+    assert e.value.code == -7
