@@ -407,7 +407,9 @@ def bench_serving(d: int, n_requests: int, rate_hz: float = 1000.0, pool: int = 
             "batches": st["batches"], "mean_batch": st["requests"] / max(st["batches"], 1),
             "max_batch": st["max_batch"],
             "worker_ms": {"lower": st["worker_lower_ms"], "merge_upload_launch": st["worker_upload_ms"],
-                          "wait_download_split": st["worker_fetch_ms"], "wall": wall * 1e3},
+                          "fetch": st["worker_fetch_ms"], "of_which_device_wait": st["worker_wait_ms"],
+                          "of_which_download": st["worker_download_ms"],
+                          "wall": wall * 1e3},
             "latency_includes": "host lowering + upload + device stages + download + per-request split"}
 
 

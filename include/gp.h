@@ -193,10 +193,11 @@ int gp_rates_gradient(gp_driver* drv, const double* dl_dq, size_t n_edges, doubl
 /* Request server (continuous batching). A worker thread owns two drivers
  * created with `batch_bounds` (the bounds of one batch: max_branches circuits
  * at most, totals summed over them), each on its own HIP stream of default
- * priority on `device`. Every pass it takes the requests that have arrived,
- * lowers the new ones on host threads, uploads them as one batch to the free
- * driver and launches both stages; while that batch runs, it downloads the
- * other driver's batch and completes those requests. A batch that exceeds the
+ * priority on `device`; a pool of host threads lowers every submitted circuit
+ * as soon as it arrives. Every pass the worker takes the lowered requests,
+ * uploads them as one batch to the free driver and launches both stages;
+ * while that batch runs, it downloads the other driver's batch and completes
+ * those requests. A batch that exceeds the
  * bounds is split; a request that exceeds them alone fails with GP_E_BOUNDS.
  * Each request gets exactly the hyperedges of its own circuit (a batch never
  * merges faults of two circuits), whatever it was batched with.
@@ -217,9 +218,12 @@ int gp_server_submit(gp_server* srv, const char* text, size_t len, const double*
                      uint64_t* ticket);
 int gp_server_wait(gp_server* srv, uint64_t ticket, int64_t timeout_us, gp_edges** out, uint64_t* latency_ns);
 int gp_server_stats(const gp_server* srv, uint64_t* batches, uint64_t* requests, uint64_t* max_batch);
-/* Worker time so far in host lowering, in merging + uploading + launching,
- * and in waiting for + downloading + splitting results (milliseconds). */
-int gp_server_timing(const gp_server* srv, double* lower_ms, double* upload_ms, double* fetch_ms);
+/* Worker time so far (milliseconds) in host lowering, in merging +
+ * uploading + launching, and in fetching results (waiting for the device,
+ * downloading, splitting per request), with the waiting and the downloading
+ * parts of the latter. Any output may be NULL. */
+int gp_server_timing(const gp_server* srv, double* lower_ms, double* upload_ms, double* fetch_ms, double* wait_ms,
+                     double* download_ms);
 void gp_server_destroy(gp_server* srv);
 
 /* Wait for every operation enqueued on the driver's stream. */

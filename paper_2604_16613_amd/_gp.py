@@ -145,6 +145,7 @@ def load():
         "gp_server_stats": ([_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(_u64)], ctypes.c_int),
         "gp_server_destroy": ([_vp], None),
         "gp_server_timing": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "gp_edges_circuit_shape": ([_vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
                                     ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
@@ -446,8 +447,8 @@ def gp_server_destroy(srv: int) -> None:
     load().gp_server_destroy(srv)
 
 
-def gp_server_timing(srv: int) -> Tuple[float, float, float]:
-    lo, up, fe = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-    _check(load().gp_server_timing(srv, ctypes.byref(lo), ctypes.byref(up), ctypes.byref(fe)))
-    return lo.value, up.value, fe.value
+def gp_server_timing(srv: int) -> Tuple[float, float, float, float, float]:
+    v = [ctypes.c_double() for _ in range(5)]
+    _check(load().gp_server_timing(srv, *[ctypes.byref(x) for x in v]))
+    return tuple(x.value for x in v)
 

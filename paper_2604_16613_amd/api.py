@@ -204,9 +204,9 @@ class Server:
 
     def stats(self) -> Dict[str, int]:
         b, r, m = _gp.gp_server_stats(self.handle)
-        lo, up, fe = _gp.gp_server_timing(self.handle)
+        lo, up, fe, wa, dl = _gp.gp_server_timing(self.handle)
         return {"batches": b, "requests": r, "max_batch": m, "worker_lower_ms": lo, "worker_upload_ms": up,
-                "worker_fetch_ms": fe}
+                "worker_fetch_ms": fe, "worker_wait_ms": wa, "worker_download_ms": dl}
 
     def close(self) -> None:
         if self.handle:

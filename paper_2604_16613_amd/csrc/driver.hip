@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cinttypes>
 #include <cstdio>
 #include <cstdlib>
@@ -635,6 +636,8 @@ struct Staged {
   const uint32_t* bits32 = nullptr;
   const double* q64 = nullptr;
   const uint32_t* cid = nullptr;  // null unless a batch
+  std::chrono::steady_clock::time_point t_ready;   // when the compile was seen finished
+  std::chrono::steady_clock::time_point t_loaded;  // when the download had finished
 };
 
 // Wait for the compile (redoing it for the retry flags), check the device
@@ -647,6 +650,7 @@ static int fetch_staged(gp_driver* d, Staged& out) {
   HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
   collect_timing(d);
   gp::DevHeader hdr = *d->h_hdr;
+  out.t_ready = std::chrono::steady_clock::now();
   // at most two more compiles: a bucket too large for LDS redoes the grouping
   // with the full radix sort; two signatures under one key redo it keyed on
   // both hashes (which always takes the full sort)
@@ -695,6 +699,7 @@ static int fetch_staged(gp_driver* d, Staged& out) {
   if (U && batch)
     HIP_TRY(hipMemcpyAsync(h + o_c, d->st.edge_branch, U * 4, hipMemcpyDeviceToHost, d->stream), "download");
   HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
+  out.t_loaded = std::chrono::steady_clock::now();
   out.U = U;
   out.nb = nb;
   out.off32 = reinterpret_cast<const uint32_t*>(h + o_off);
@@ -1001,43 +1006,101 @@ int driver_upload_parts(gp_driver* d, const std::vector<const Lowered*>& parts) 
 
 uint32_t driver_level(const gp_driver* d) { return d ? d->level : 2u; }
 
-int driver_fetch_split(gp_driver* d, std::vector<gp_edges*>& out) {
+int driver_fetch_split(gp_driver* d, std::vector<gp_edges*>& out, uint64_t* wait_ns) {
   out.clear();
   if (!d) return fail(GP_E_ARG, "null driver");
+  const auto t0 = std::chrono::steady_clock::now();
   Staged sg;
+  sg.t_ready = sg.t_loaded = t0;
   int rc = fetch_staged(d, sg);
+  if (wait_ns) {
+    wait_ns[0] = uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(sg.t_ready - t0).count());
+    wait_ns[1] = uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(sg.t_loaded - sg.t_ready).count());
+  }
   if (rc) return rc;
   // the split order is not the device's: no refresh or adjoint on this compile
   d->structured = false;
   const size_t B = d->lw.branches.size();
-  std::vector<uint64_t> ne(B, 0), nbits(B, 0);
-  for (uint64_t i = 0; i < sg.U; i++) {
-    const uint32_t k = sg.cid ? sg.cid[i] : 0u;
-    if (k >= B) return fail(GP_E_HIP, "a hyperedge names a circuit outside the batch");
-    ne[k]++;
-    nbits[k] += sg.off32[i + 1] - sg.off32[i];
-  }
+  const uint64_t U = sg.U;
+  // a parallel counting sort by circuit: chunk t of the hyperedges counts,
+  // then writes at its own offsets within every circuit
+  const size_t T = std::min<size_t>({16, std::max<size_t>(1, std::thread::hardware_concurrency()),
+                                     std::max<uint64_t>(1, U / 65536)});
+  std::vector<uint64_t> ce(T * B, 0), cb(T * B, 0);
+  std::vector<int> bad(T, 0);
+  auto parallel = [&](auto&& fn) {
+    if (T == 1) {
+      fn(size_t(0));
+      return;
+    }
+    std::vector<std::thread> pool;
+    for (size_t t = 0; t < T; t++) pool.emplace_back(fn, t);
+    for (std::thread& th : pool) th.join();
+  };
+  // (each thread counts in its own vectors: rows of one shared array would
+  // share cache lines between threads)
+  parallel([&](size_t t) {
+    std::vector<uint64_t> le(B, 0), lb(B, 0);
+    for (uint64_t i = U * t / T; i < U * (t + 1) / T; i++) {
+      const uint32_t k = sg.cid ? sg.cid[i] : 0u;
+      if (k >= B) {
+        bad[t] = 1;
+        return;
+      }
+      le[k]++;
+      lb[k] += sg.off32[i + 1] - sg.off32[i];
+    }
+    std::copy(le.begin(), le.end(), ce.begin() + t * B);
+    std::copy(lb.begin(), lb.end(), cb.begin() + t * B);
+  });
+  for (int v : bad)
+    if (v) return fail(GP_E_HIP, "a hyperedge names a circuit outside the batch");
   out.resize(B);
+  std::vector<uint64_t> tot_e(B), tot_b(B);
   for (size_t k = 0; k < B; k++) {
-    gp_edges* e = new gp_edges();
-    e->n_det = d->lw.branches[k].n_det;
-    e->n_obs = d->lw.branches[k].n_obs;
-    e->off.reserve(ne[k] + 1);
-    e->off.push_back(0);
-    e->bits.reserve(nbits[k]);
-    e->q.reserve(ne[k]);
-    e->circuit.assign(ne[k], 0u);
-    e->c_det.assign(1, e->n_det);
-    e->c_obs.assign(1, e->n_obs);
-    e->c_off = {0, ne[k]};
-    out[k] = e;
+    uint64_t ne = 0, nb = 0;
+    for (size_t t = 0; t < T; t++) {
+      const uint64_t a = ce[t * B + k], b = cb[t * B + k];
+      ce[t * B + k] = ne;  // now: this chunk's first hyperedge / bit in circuit k
+      cb[t * B + k] = nb;
+      ne += a;
+      nb += b;
+    }
+    tot_e[k] = ne;
+    tot_b[k] = nb;
   }
-  for (uint64_t i = 0; i < sg.U; i++) {
-    gp_edges* e = out[sg.cid ? sg.cid[i] : 0u];
-    e->bits.insert(e->bits.end(), sg.bits32 + sg.off32[i], sg.bits32 + sg.off32[i + 1]);
-    e->off.push_back(e->bits.size());
-    e->q.push_back(sg.q64[i]);
-  }
+  // the results are allocated (and first touched) in parallel too
+  parallel([&](size_t t) {
+    for (size_t k = t; k < B; k += T) {
+      gp_edges* e = new gp_edges();
+      e->n_det = d->lw.branches[k].n_det;
+      e->n_obs = d->lw.branches[k].n_obs;
+      e->off.resize(tot_e[k] + 1);
+      e->off[0] = 0;
+      e->bits.resize(tot_b[k]);
+      e->q.resize(tot_e[k]);
+      e->circuit.assign(tot_e[k], 0u);
+      e->c_det.assign(1, e->n_det);
+      e->c_obs.assign(1, e->n_obs);
+      e->c_off = {0, tot_e[k]};
+      out[k] = e;
+    }
+  });
+  parallel([&](size_t t) {
+    std::vector<uint64_t> je(ce.begin() + t * B, ce.begin() + (t + 1) * B);
+    std::vector<uint64_t> jb(cb.begin() + t * B, cb.begin() + (t + 1) * B);
+    for (uint64_t i = U * t / T; i < U * (t + 1) / T; i++) {
+      const uint32_t k = sg.cid ? sg.cid[i] : 0u;
+      gp_edges* e = out[k];
+      const uint64_t j = je[k]++;
+      const uint32_t len = sg.off32[i + 1] - sg.off32[i];
+      const uint64_t b = jb[k];
+      jb[k] = b + len;
+      e->q[j] = sg.q64[i];
+      e->off[j + 1] = b + len;
+      if (len) std::memcpy(e->bits.data() + b, sg.bits32 + sg.off32[i], size_t(len) * 4);
+    }
+  });
   return GP_OK;
 }
 

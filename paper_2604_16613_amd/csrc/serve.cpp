@@ -1,11 +1,12 @@
 // Request server: continuous batching over two drivers (C ABI in gp.h).
 //
-// A worker thread owns two drivers of identical bounds, each with its own
-// HIP stream. Every pass it takes the requests that arrived (up to the
-// batch size the bounds allow), lowers the new ones on host threads, uploads
-// them as one batch to the free driver and launches both stages there; while
-// that batch runs on the device it downloads the other driver's finished
-// batch and completes its requests, each with its own circuit's hyperedges.
+// Submitted circuits are lowered at once by a pool of host threads. A worker
+// thread owns two drivers of identical bounds, each with its own HIP stream.
+// Every pass it takes the lowered requests (up to the batch size the bounds
+// allow), uploads them as one batch to the free driver and launches both
+// stages there; while that batch runs on the device it downloads the other
+// driver's finished batch and completes its requests, each with its own
+// circuit's hyperedges.
 // Requests never share a hyperedge (a batch groups every circuit on its own),
 // so a request's result does not depend on what it was batched with.
 #include <algorithm>
@@ -55,13 +56,17 @@ struct gp_server {
   gp_driver* drv[2] = {nullptr, nullptr};
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
-  std::deque<ReqPtr> pending;
+  std::deque<ReqPtr> to_lower;  // submitted, waiting for a lowering thread
+  std::condition_variable cv_lower;
+  std::vector<std::thread> lowerers;
+  bool lowerers_done = false;
+  std::deque<ReqPtr> pending;   // lowered, waiting for a batch
   std::unordered_map<uint64_t, ReqPtr> live;  // submitted and not yet collected
   uint64_t next_ticket = 1;
   bool stop = false;
   std::thread worker;
   uint64_t n_batches = 0, n_requests = 0, max_batch = 0;
-  uint64_t ns_lower = 0, ns_upload = 0, ns_fetch = 0;  // worker time in each phase
+  uint64_t ns_lower = 0, ns_upload = 0, ns_fetch = 0, ns_wait = 0, ns_download = 0;  // worker time per phase
 };
 
 namespace {
@@ -77,34 +82,36 @@ void complete(gp_server* s, const ReqPtr& r, int rc, const std::string& msg, gp_
   s->cv_done.notify_all();
 }
 
-// Lower the requests that are not lowered yet, on up to 16 host threads.
-void lower_new(gp_server* s, const std::vector<ReqPtr>& reqs, uint32_t level) {
-  std::vector<ReqPtr> todo;
-  for (const ReqPtr& r : reqs)
-    if (!r->lowered) todo.push_back(r);
-  if (todo.empty()) return;
-  const uint32_t slots = std::max<uint32_t>(1, gp::kSweepSlots / uint32_t(std::max<size_t>(reqs.size(), 1)));
-  std::vector<int> rcs(todo.size());
-  std::vector<gp::LowerError> errs(todo.size());
-  auto run = [&](size_t lo, size_t hi) {
-    for (size_t k = lo; k < hi; k++) {
-      Request& r = *todo[k];
-      rcs[k] = gp::lower_circuit(r.text.data(), r.text.size(), r.has_rates ? r.rates.data() : nullptr,
-                                 r.has_rates ? r.rates.size() : 0, slots, r.lw, errs[k], level);
+// A lowering thread: lowers submitted requests one at a time and hands them
+// to the worker.
+void lower_loop(gp_server* s, uint32_t level) {
+  // sweep slots per circuit: batches under load hold a few circuits
+  const uint32_t slots = std::max<uint32_t>(1, gp::kSweepSlots / 4);
+  for (;;) {
+    ReqPtr r;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      s->cv_lower.wait(lk, [&] { return s->stop || !s->to_lower.empty(); });
+      if (s->to_lower.empty()) return;  // stopping, and nothing left
+      r = s->to_lower.front();
+      s->to_lower.pop_front();
     }
-  };
-  const size_t n = todo.size();
-  const size_t nt = std::min<size_t>({n, 16, std::max<size_t>(1, std::thread::hardware_concurrency())});
-  if (nt <= 1) {
-    run(0, n);
-  } else {
-    std::vector<std::thread> pool;
-    for (size_t t = 0; t < nt; t++) pool.emplace_back(run, n * t / nt, n * (t + 1) / nt);
-    for (std::thread& th : pool) th.join();
-  }
-  for (size_t k = 0; k < n; k++) {
-    todo[k]->lowered = true;
-    if (rcs[k]) complete(s, todo[k], rcs[k], errs[k].msg, nullptr);
+    const uint64_t t0 = now_ns();
+    gp::LowerError err{};
+    const int rc = gp::lower_circuit(r->text.data(), r->text.size(), r->has_rates ? r->rates.data() : nullptr,
+                                     r->has_rates ? r->rates.size() : 0, slots, r->lw, err, level);
+    r->lowered = true;
+    if (rc) {
+      complete(s, r, rc, err.msg, nullptr);
+    } else {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->pending.push_back(r);
+    }
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->ns_lower += now_ns() - t0;
+    }
+    s->cv_work.notify_one();
   }
 }
 
@@ -113,7 +120,8 @@ void finish(gp_server* s, int slot, std::vector<ReqPtr>& batch) {
   if (batch.empty()) return;
   const uint64_t t0 = now_ns();
   std::vector<gp_edges*> parts;
-  int rc = gp::driver_fetch_split(s->drv[slot], parts);
+  uint64_t wait[2] = {0, 0};
+  int rc = gp::driver_fetch_split(s->drv[slot], parts, wait);
   if (rc && batch.size() > 1) {
     // a device-side error (e.g. a non-deterministic detector) names no
     // circuit: every request of the batch runs again on its own
@@ -137,11 +145,12 @@ void finish(gp_server* s, int slot, std::vector<ReqPtr>& batch) {
   batch.clear();
   std::lock_guard<std::mutex> lk(s->mu);
   s->ns_fetch += now_ns() - t0;
+  s->ns_wait += wait[0];
+  s->ns_download += wait[1];
 }
 
 void worker_loop(gp_server* s) {
   const size_t max_batch = std::max<uint32_t>(s->bounds.max_branches, 1);
-  const uint32_t level = gp::driver_level(s->drv[0]);
   std::vector<ReqPtr> inflight[2];
   int cur = 0;
   for (;;) {
@@ -149,8 +158,8 @@ void worker_loop(gp_server* s) {
     {
       std::unique_lock<std::mutex> lk(s->mu);
       const bool busy = !inflight[0].empty() || !inflight[1].empty();
-      if (!busy) s->cv_work.wait(lk, [&] { return s->stop || !s->pending.empty(); });
-      if (s->pending.empty() && !busy && s->stop) break;
+      if (!busy) s->cv_work.wait(lk, [&] { return s->lowerers_done || !s->pending.empty(); });
+      if (s->pending.empty() && !busy && s->lowerers_done) break;
       while (!s->pending.empty() && take.size() < max_batch) {
         const bool solo = s->pending.front()->solo;
         if (solo && !take.empty()) break;
@@ -159,12 +168,7 @@ void worker_loop(gp_server* s) {
         if (solo) break;
       }
     }
-    const uint64_t t0 = now_ns();
-    lower_new(s, take, level);
-    const uint64_t t1 = now_ns();
-    std::vector<ReqPtr> batch;
-    for (const ReqPtr& r : take)
-      if (!r->done) batch.push_back(r);
+    std::vector<ReqPtr> batch = std::move(take);
     // upload the largest prefix that fits the bounds; the rest waits
     while (!batch.empty()) {
       if (!inflight[cur].empty()) finish(s, cur, inflight[cur]);
@@ -190,10 +194,6 @@ void worker_loop(gp_server* s) {
         for (size_t k = batch.size(); k-- > keep;) s->pending.push_front(batch[k]);
       }
       batch.resize(keep);
-    }
-    {
-      std::lock_guard<std::mutex> lk(s->mu);
-      s->ns_lower += t1 - t0;
     }
     if (!batch.empty()) {
       {
@@ -233,6 +233,9 @@ int gp_server_create(const gp_bounds* bounds, int device, gp_server** out) {
       return gp::set_last_error(rc, msg);
     }
   }
+  const uint32_t level = gp::driver_level(s->drv[0]);
+  const size_t n_lower = std::min<size_t>(8, std::max<size_t>(1, std::thread::hardware_concurrency()));
+  for (size_t k = 0; k < n_lower; k++) s->lowerers.emplace_back(lower_loop, s, level);
   s->worker = std::thread(worker_loop, s);
   *out = s;
   return GP_OK;
@@ -252,10 +255,10 @@ int gp_server_submit(gp_server* s, const char* text, size_t len, const double* r
     if (s->stop) return gp::set_last_error(GP_E_STATE, "the server is shutting down");
     r->ticket = s->next_ticket++;
     r->t_submit = now_ns();
-    s->pending.push_back(r);
+    s->to_lower.push_back(r);
     s->live[r->ticket] = r;
   }
-  s->cv_work.notify_one();
+  s->cv_lower.notify_one();
   *ticket = r->ticket;
   return GP_OK;
 }
@@ -290,13 +293,16 @@ int gp_server_stats(const gp_server* s, uint64_t* batches, uint64_t* requests, u
   return GP_OK;
 }
 
-int gp_server_timing(const gp_server* s, double* lower_ms, double* upload_ms, double* fetch_ms) {
+int gp_server_timing(const gp_server* s, double* lower_ms, double* upload_ms, double* fetch_ms, double* wait_ms,
+                     double* download_ms) {
   if (!s) return gp::set_last_error(GP_E_ARG, "null server");
   gp_server* m = const_cast<gp_server*>(s);
   std::lock_guard<std::mutex> lk(m->mu);
   if (lower_ms) *lower_ms = s->ns_lower * 1e-6;
   if (upload_ms) *upload_ms = s->ns_upload * 1e-6;
   if (fetch_ms) *fetch_ms = s->ns_fetch * 1e-6;
+  if (wait_ms) *wait_ms = s->ns_wait * 1e-6;
+  if (download_ms) *download_ms = s->ns_download * 1e-6;
   return GP_OK;
 }
 
@@ -305,6 +311,12 @@ void gp_server_destroy(gp_server* s) {
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop = true;
+  }
+  s->cv_lower.notify_all();
+  for (std::thread& th : s->lowerers) th.join();
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->lowerers_done = true;
   }
   s->cv_work.notify_all();
   if (s->worker.joinable()) s->worker.join();
