@@ -110,6 +110,25 @@ struct TimedLaunch {
   hipEvent_t a, b;
 };
 
+// Host threads for splitting a result of U hyperedges (one per 64 Ki, at most 16).
+size_t split_threads(uint64_t U) {
+  return std::min<size_t>({16, std::max<size_t>(1, std::thread::hardware_concurrency()),
+                           std::max<uint64_t>(1, U / 65536)});
+}
+
+// Run fn(0 .. T-1) on T threads (inline when T is 1) and wait for all.
+template <typename F>
+void run_threads(size_t T, F&& fn) {
+  if (T <= 1) {
+    fn(size_t(0));
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (size_t t = 0; t < T; t++) pool.emplace_back(fn, t);
+  for (std::thread& th : pool) th.join();
+}
+
+
 }  // namespace
 
 struct gp_edges {
@@ -738,39 +757,62 @@ int gp_fetch(gp_driver* d, gp_edges** out) {
     e->circuit.assign(U, 0u);
     e->c_off[1] = U;
   } else {
-    // circuit by circuit (a stable counting sort), each circuit's hyperedges
-    // in the order the device wrote them
+    // circuit by circuit (a stable counting sort on host threads), each
+    // circuit's hyperedges in the order the device wrote them
     const uint32_t* cid = sg.cid;
-    std::vector<uint64_t> bit_off(B + 1, 0);
-    for (uint64_t i = 0; i < U; i++) {
-      if (cid[i] >= B) {
+    const size_t T = split_threads(U);
+    std::vector<uint64_t> ce(T * B, 0), cb(T * B, 0);
+    std::vector<int> bad(T, 0);
+    run_threads(T, [&](size_t t) {
+      std::vector<uint64_t> le(B, 0), lb(B, 0);  // own counters: no shared cache lines
+      for (uint64_t i = U * t / T; i < U * (t + 1) / T; i++) {
+        if (cid[i] >= B) {
+          bad[t] = 1;
+          return;
+        }
+        le[cid[i]]++;
+        lb[cid[i]] += off32[i + 1] - off32[i];
+      }
+      std::copy(le.begin(), le.end(), ce.begin() + t * B);
+      std::copy(lb.begin(), lb.end(), cb.begin() + t * B);
+    });
+    for (int v : bad)
+      if (v) {
         delete e;
         return fail(GP_E_HIP, "a hyperedge names a circuit outside the batch");
       }
-      e->c_off[cid[i] + 1]++;
-      bit_off[cid[i] + 1] += off32[i + 1] - off32[i];
-    }
+    uint64_t ne = 0, nbits = 0;
     for (size_t k = 0; k < B; k++) {
-      e->c_off[k + 1] += e->c_off[k];
-      bit_off[k + 1] += bit_off[k];
+      e->c_off[k] = ne;
+      for (size_t t = 0; t < T; t++) {
+        const uint64_t a = ce[t * B + k], b = cb[t * B + k];
+        ce[t * B + k] = ne;  // now: chunk t's first slot and bit within the result
+        cb[t * B + k] = nbits;
+        ne += a;
+        nbits += b;
+      }
     }
-    std::vector<uint64_t> at(e->c_off.begin(), e->c_off.end() - 1), bat(bit_off.begin(), bit_off.end() - 1);
+    e->c_off[B] = ne;
     e->off.resize(U + 1);
     e->bits.resize(nb);
     e->q.resize(U);
     e->circuit.resize(U);
     d->edge_perm.resize(U);
-    for (uint64_t i = 0; i < U; i++) {
-      const uint32_t k = cid[i];
-      const uint64_t j = at[k]++;
-      d->edge_perm[j] = uint32_t(i);
-      const uint32_t len = off32[i + 1] - off32[i];
-      e->q[j] = q64[i];
-      e->circuit[j] = k;
-      e->off[j] = bat[k];
-      if (len) std::memcpy(e->bits.data() + bat[k], bits32 + off32[i], size_t(len) * 4);
-      bat[k] += len;
-    }
+    run_threads(T, [&](size_t t) {
+      std::vector<uint64_t> je(ce.begin() + t * B, ce.begin() + (t + 1) * B);
+      std::vector<uint64_t> jb(cb.begin() + t * B, cb.begin() + (t + 1) * B);
+      for (uint64_t i = U * t / T; i < U * (t + 1) / T; i++) {
+        const uint32_t k = cid[i];
+        const uint64_t j = je[k]++;
+        const uint32_t len = off32[i + 1] - off32[i];
+        d->edge_perm[j] = uint32_t(i);
+        e->q[j] = q64[i];
+        e->circuit[j] = k;
+        e->off[j] = jb[k];
+        if (len) std::memcpy(e->bits.data() + jb[k], bits32 + off32[i], size_t(len) * 4);
+        jb[k] += len;
+      }
+    });
     e->off[U] = nb;
   }
   *out = e;
@@ -1024,19 +1066,10 @@ int driver_fetch_split(gp_driver* d, std::vector<gp_edges*>& out, uint64_t* wait
   const uint64_t U = sg.U;
   // a parallel counting sort by circuit: chunk t of the hyperedges counts,
   // then writes at its own offsets within every circuit
-  const size_t T = std::min<size_t>({16, std::max<size_t>(1, std::thread::hardware_concurrency()),
-                                     std::max<uint64_t>(1, U / 65536)});
+  const size_t T = split_threads(U);
   std::vector<uint64_t> ce(T * B, 0), cb(T * B, 0);
   std::vector<int> bad(T, 0);
-  auto parallel = [&](auto&& fn) {
-    if (T == 1) {
-      fn(size_t(0));
-      return;
-    }
-    std::vector<std::thread> pool;
-    for (size_t t = 0; t < T; t++) pool.emplace_back(fn, t);
-    for (std::thread& th : pool) th.join();
-  };
+  auto parallel = [&](auto&& fn) { run_threads(T, fn); };
   // (each thread counts in its own vectors: rows of one shared array would
   // share cache lines between threads)
   parallel([&](size_t t) {
