@@ -157,21 +157,47 @@ __device__ __forceinline__ uint32_t digit_of(uint64_t k, uint32_t pass) { return
 // the Pauli codes each channel kind keeps at each correlation level
 __constant__ KeptCodes c_kept = make_kept_codes();
 
-__global__ void k_prepare(DevState st) {
+// A block takes 256 consecutive channels: one thread per channel computes the
+// per-fault probability and the qubits, then the block writes the faults of
+// those channels (consecutive positions) one thread per fault, coalesced.
+__global__ __launch_bounds__(kBlock) void k_prepare(DevState st) {
+  __shared__ double s_p[kBlock];
+  __shared__ uint32_t s_q[kBlock];          // qubit a | qubit b << 14 | kind << 28
+  __shared__ uint32_t s_off[kBlock + 1];    // first fault of each channel, from the block's first
   const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t c = gid; c < st.n_chan; c += stride) {
-    const uint32_t kind = st.chan_kind[c];
-    const double p = fault_probability(kind, st.chan_rate[c]);
-    const uint32_t f0 = st.chan_foff[c], f1 = st.chan_foff[c + 1];
-    const uint32_t qa = st.chan_qa[c] & kQField;
-    const uint32_t qb = kind == CH_DEP2 ? (st.chan_qb[c] & kQField) : 0u;
-    for (uint32_t f = f0; f < f1; ++f) {
-      st.frp[f].p = p;
-      // Pauli code: x on a | z on a << 1 | x on b << 2 | z on b << 3
-      const uint32_t code = c_kept.code[kind][st.level][f - f0];
-      st.frec[f] = qa | (qb << kQubitBits) | (code << 28);
+  const uint32_t n_blk = (st.n_chan + kBlock - 1) / kBlock;
+  for (uint32_t cb = blockIdx.x; cb < n_blk; cb += gridDim.x) {
+    const uint32_t c0 = cb * kBlock, nc = min(uint32_t(kBlock), st.n_chan - c0);
+    const uint32_t f_lo = st.chan_foff[c0];
+    if (threadIdx.x < nc) {
+      const uint32_t c = c0 + threadIdx.x;
+      const uint32_t kind = st.chan_kind[c];
+      const uint32_t qa = st.chan_qa[c] & kQField;
+      // a one-qubit channel names its qubit twice, so that "both qubits'
+      // frame words are zero" is the test for an empty word (see k_sweep)
+      const uint32_t qb = kind == CH_DEP2 ? (st.chan_qb[c] & kQField) : qa;
+      s_p[threadIdx.x] = fault_probability(kind, st.chan_rate[c]);
+      s_q[threadIdx.x] = qa | (qb << kQubitBits) | (kind << 28);
+      s_off[threadIdx.x] = st.chan_foff[c] - f_lo;
     }
+    if (threadIdx.x == 0) s_off[nc] = st.chan_foff[c0 + nc] - f_lo;
+    __syncthreads();
+    const uint32_t nf = s_off[nc];
+    for (uint32_t i = threadIdx.x; i < nf; i += kBlock) {
+      // the channel holding fault i: the last j with s_off[j] <= i
+      uint32_t lo = 0, hi = nc;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (s_off[mid] <= i) lo = mid; else hi = mid;
+      }
+      const uint32_t q = s_q[lo], kind = q >> 28;
+      st.frp[f_lo + i].p = s_p[lo];
+      // Pauli code: x on a | z on a << 1 | x on b << 2 | z on b << 3
+      const uint32_t code = c_kept.code[kind][st.level][i - s_off[lo]];
+      st.frec[f_lo + i] = (q & ((1u << 28) - 1u)) | (code << 28);
+    }
+    __syncthreads();
   }
   for (uint32_t w = gid; w < st.w; w += stride) st.cover_lo[w] = 0;
   const uint32_t ntiles = (st.n_faults + kTile - 1) / kTile;
@@ -543,6 +569,9 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
         const uint32_t qa = r & kQField, qb = (r >> kQubitBits) & kQField, code = r >> 28;
         const ulonglong2 p0 = reinterpret_cast<const ulonglong2*>(frame)[qa];
         const ulonglong2 p1 = reinterpret_cast<const ulonglong2*>(frame)[qb];
+        // most faults sit on qubits whose frame words are all zero (a
+        // one-qubit fault names its qubit twice): skip the selection then
+        if (((p0.x | p0.y) | (p1.x | p1.y)) == 0ull) return 0ull;
         return (p0.x & (0ull - (code & 1u))) ^ (p0.y & (0ull - ((code >> 1) & 1u))) ^
                (p1.x & (0ull - ((code >> 2) & 1u))) ^ (p1.y & (0ull - ((code >> 3) & 1u)));
       };
