@@ -426,6 +426,7 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   if ((rc = dev_alloc(d, &st.cov, bnd_rows * d->max_w, "cover lists"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.ncov, bnd_rows, "cover counts"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.frp, F, "fault probabilities and check hashes"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.crp, F, "partitioned fault records"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.frec, F, "fault records"))) return cleanup(rc);
   for (int k = 0; k < 2; k++) {
     if ((rc = dev_alloc(d, &st.key[k], F, "keys"))) return cleanup(rc);

@@ -113,6 +113,7 @@ struct DevState {
   uint32_t* cov;         // per boundary row: covered columns, ascending (rows of w_max)
   uint32_t* ncov;        // per boundary: number of covered columns
   FaultRec* frp;         // per fault position: probability and check hash
+  FaultRec* crp;         // bucket grouping: the records of the partitioned pairs, in pair order
   uint32_t* frec;        // per fault position: qubit a | qubit b << 14 | Pauli code << 28 (b = a for one-qubit faults)
   uint64_t* key[2];      // class keys: per position (key[1]) then compacted, ping-pong in the sort
   uint32_t* val[2];      // fault positions riding with the keys

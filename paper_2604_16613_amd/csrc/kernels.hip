@@ -875,9 +875,12 @@ constexpr int kSortBlock = 1024;
 constexpr int kSortWaves = kSortBlock / 64;
 constexpr int kSortRounds = kTile / kSortBlock;
 
+// With pout set, each pair's FaultRec (gathered from pin by its position)
+// moves along with it, so that a later kernel reads it in pair order.
 __global__ __launch_bounds__(kSortBlock) void k_onesweep(DevState st, uint32_t pass, const uint64_t* __restrict__ kin,
                                                          const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
-                                                         uint32_t* __restrict__ vout) {
+                                                         uint32_t* __restrict__ vout, const FaultRec* __restrict__ pin,
+                                                         FaultRec* __restrict__ pout) {
   __shared__ uint64_t s_key[kTile];
   __shared__ uint32_t s_val[kTile];
   __shared__ uint32_t s_cnt[kSortWaves][256];
@@ -1003,6 +1006,35 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(DevState st, uint32_t p
   __syncthreads();
   // write runs of equal digits to consecutive global positions
   const uint32_t cnt = min(uint32_t(kTile), n - tile * kTile);
+  if (pout) {
+    // the records are read first (independent loads), then written
+    double pp[kSortRounds];
+    uint64_t pc[kSortRounds];
+    uint32_t pd[kSortRounds];
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r) {
+      const uint32_t li = tid + r * kSortBlock;
+      const bool ok = li < cnt;
+      const uint64_t key = ok ? s_key[li] : 0ull;
+      const uint32_t d = digit_of(key, pass);
+      const uint32_t dst = ok ? s_gbase[d] + (li - s_start[d]) : 0u;
+      const uint32_t v = ok ? s_val[li] : 0u;
+      if (ok) {
+        kout[dst] = key;
+        vout[dst] = v;
+      }
+      pp[r] = ok ? pin[v].p : 0.0;
+      pc[r] = ok ? pin[v].chk : 0ull;
+      pd[r] = dst;
+    }
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r)
+      if (tid + r * kSortBlock < cnt) {
+        pout[pd[r]].p = pp[r];
+        pout[pd[r]].chk = pc[r];
+      }
+    return;
+  }
   for (uint32_t li = tid; li < cnt; li += kSortBlock) {
     const uint64_t key = s_key[li];
     const uint32_t d = digit_of(key, pass);
@@ -1359,14 +1391,17 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
   const uint32_t j0 = tid * per;
   uint32_t hmask = 0;
   uint32_t pos[kBucketCap / kBucketBlock];
+  uint32_t idx[kBucketCap / kBucketBlock];  // index within the bucket (the pair's slot)
 #pragma unroll
   for (int k = 0; k < int(kBucketCap / kBucketBlock); ++k) {
     const uint32_t j = j0 + k;
     pos[k] = 0;
+    idx[k] = 0;
     if (uint32_t(k) < per && j < m) {
       const uint64_t v = a[j];
       if (j == 0 || (v >> 16) != (a[j - 1] >> 16)) hmask |= 1u << k;
-      pos[k] = vals[start + uint32_t(v & 0xFFFFu)];
+      idx[k] = uint32_t(v & 0xFFFFu);
+      pos[k] = vals[start + idx[k]];
     }
   }
   if (hmask) {
@@ -1374,11 +1409,13 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
     atomicOr(&s_hb[wd], uint64_t(hmask) << sh);
     if (sh + per > 64) atomicOr(&s_hb[wd + 1], uint64_t(hmask) >> (64 - sh));
   }
+  // each pair's record was moved into the bucket's range by the partition
+  // pass: read within the bucket instead of gathered across all faults
   FaultRec rec[kBucketCap / kBucketBlock];
 #pragma unroll
   for (int k = 0; k < int(kBucketCap / kBucketBlock); ++k)
     if (uint32_t(k) < per && j0 + k < m) {
-      rec[k] = st.frp[pos[k]];
+      rec[k] = st.crp[start + idx[k]];
       st.val[0][start + j0 + k] = pos[k];  // the class members, kept for refreshes and the adjoint
     }
   const uint32_t nh = uint32_t(__popc(hmask));
@@ -1825,7 +1862,7 @@ hipError_t enqueue_compile(DevState& st_io, hipStream_t stream, const LaunchHook
     const uint32_t msd = st.n_pass - 1;
     GP_LAUNCH(K_COMPACT, k_compact<<<ntiles, kCompactBlock, 0, stream>>>(st, msd));
     GP_LAUNCH(K_ONESWEEP, k_onesweep<<<ntiles, kSortBlock, 0, stream>>>(st, msd, st.key[0], st.val[0], st.key[1],
-                                                                     st.val[1]));
+                                                                     st.val[1], st.frp, st.crp));
     GP_LAUNCH(K_BUCKET, k_bucket<<<kBuckets, kBucketBlock, kBucketDynLds, stream>>>(st, st.key[1], st.val[1]));
     GP_LAUNCH(K_EDGE_WRITE, k_edge_write<true><<<cdiv(n, kBlock), kBlock, 0, stream>>>(st));
     return hipSuccess;
@@ -1834,7 +1871,7 @@ hipError_t enqueue_compile(DevState& st_io, hipStream_t stream, const LaunchHook
   for (uint32_t pass = 0; pass < st.n_pass; ++pass) {
     const int src = pass & 1, dst = src ^ 1;
     GP_LAUNCH(K_ONESWEEP, k_onesweep<<<ntiles, kSortBlock, 0, stream>>>(st, pass, st.key[src], st.val[src], st.key[dst],
-                                                                     st.val[dst]));
+                                                                     st.val[dst], nullptr, nullptr));
   }
   const int fin = st.n_pass & 1;
   st_io.ord = st.val[fin];
