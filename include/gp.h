@@ -259,6 +259,13 @@ uint64_t gp_debug_collision_retries(const gp_driver* drv);
  * within a class; the edge order may differ). GP_E_ARG for other values. */
 int gp_debug_set_sort_mode(gp_driver* drv, int mode);
 
+/* Launch mode: with enable = 1, gp_run replays the compile's kernel launches as
+ * one HIP graph, captured at the first gp_run after each lowering (and after a
+ * change of the test modes above); 0 (default) launches every kernel on its
+ * own. Worth it only when one lowering is run many times; runs with timing
+ * enabled (gp_set_timing) are never captured. */
+int gp_debug_set_graph(gp_driver* drv, int enable);
+
 /* Profiling hook: device wall-clock stamps of every stage-1 sweep item of the
  * last gp_run (start, end pairs; `cap` entries at most), the item count, and
  * the clock rate in Hz. Synchronises the driver's stream. */

@@ -33,7 +33,7 @@ EXPORTS = (
     "gp_set_correlation_level", "gp_bounds_from_batch", "gp_driver_create_from_batch", "gp_lower_batch",
     "gp_edges_circuits", "gp_edges_circuit_ids", "gp_edges_circuit_shape", "gp_edges_circuit_dem_text",
     "gp_edges_circuit_offsets", "gp_server_create", "gp_server_submit", "gp_server_wait", "gp_server_stats",
-    "gp_server_destroy", "gp_server_timing",
+    "gp_server_destroy", "gp_server_timing", "gp_debug_set_graph",
 )
 
 
@@ -122,6 +122,7 @@ def load():
         "gp_debug_set_key_bits": ([_vp, ctypes.c_int], ctypes.c_int),
         "gp_debug_collision_retries": ([_vp], _u64),
         "gp_debug_set_sort_mode": ([_vp, ctypes.c_int], ctypes.c_int),
+        "gp_debug_set_graph": ([_vp, ctypes.c_int], ctypes.c_int),
         "gp_refresh_rates": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t], ctypes.c_int),
         "gp_set_correlation_level": ([_vp, ctypes.c_int], ctypes.c_int),
         "gp_rates_gradient": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t,
@@ -398,6 +399,10 @@ def gp_rates_gradient(drv: int, dl_dq: Sequence[float], n_rates: int) -> np.ndar
 
 def gp_debug_set_sort_mode(drv: int, mode: int) -> None:
     _check(load().gp_debug_set_sort_mode(drv, mode))
+
+
+def gp_debug_set_graph(drv: int, enable: bool) -> None:
+    _check(load().gp_debug_set_graph(drv, int(enable)))
 
 
 def gp_debug_collision_retries(drv: int) -> int:

@@ -171,6 +171,14 @@ struct gp_driver {
   uint32_t level = 2;                  // correlation level for the next lowering
   uint64_t collision_retries = 0;
 
+  // optionally, the compile's launch sequence captured as a HIP graph and
+  // replayed while the lowering and the modes it was captured with stay the same
+  bool use_graph = false;
+  hipGraphExec_t gexec = nullptr;
+  uint64_t lower_gen = 0;      // bumped by every upload of a lowering
+  uint64_t graph_gen = ~0ull;  // the lowering generation the graph was captured for
+  uint32_t graph_key_bits = 0, graph_sort_mode = 0;
+
   bool timing = false;
   std::vector<hipEvent_t> ev_free;
   std::vector<TimedLaunch> pending;
@@ -355,6 +363,7 @@ void gp_driver_destroy(gp_driver* d) {
   if (d->h_tables) (void)hipHostFree(d->h_tables);
   if (d->h_out) (void)hipHostFree(d->h_out);
   if (d->h_hdr) (void)hipHostFree(d->h_hdr);
+  if (d->gexec) (void)hipGraphExecDestroy(d->gexec);
   for (TimedLaunch& t : d->pending) {
     if (t.a) (void)hipEventDestroy(t.a);
     if (t.b) (void)hipEventDestroy(t.b);
@@ -595,6 +604,7 @@ static int upload_lowered(gp_driver* d) {
   st.n_faults = uint32_t(lw.n_faults);
   st.level = lw.level;
   d->lowered = true;
+  d->lower_gen++;
   return GP_OK;
 }
 
@@ -635,9 +645,45 @@ int gp_run(gp_driver* d) {
   d->st.key_bits = d->key_bits;
   d->st.sort_mode = d->sort_mode;
   d->structured = false;
+  if (d->use_graph && !d->timing) {
+    // replay the captured launch sequence; capture it first if the lowering
+    // or a mode changed since
+    if (!d->gexec || d->graph_gen != d->lower_gen || d->graph_key_bits != d->key_bits ||
+        d->graph_sort_mode != d->sort_mode) {
+      if (d->gexec) {
+        (void)hipGraphExecDestroy(d->gexec);
+        d->gexec = nullptr;
+      }
+      hipGraph_t g = nullptr;
+      gp::LaunchHook none;
+      HIP_TRY(hipStreamBeginCapture(d->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+      const hipError_t ce = gp::enqueue_compile(d->st, d->stream, none);
+      const hipError_t ee = hipStreamEndCapture(d->stream, &g);
+      hipError_t ie = hipSuccess;
+      if (ce == hipSuccess && ee == hipSuccess) ie = hipGraphInstantiate(&d->gexec, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      if (ce != hipSuccess || ee != hipSuccess || ie != hipSuccess) {
+        (void)hipGetLastError();
+        d->gexec = nullptr;
+        return hip_fail(ce != hipSuccess ? ce : ee != hipSuccess ? ee : ie, "capturing the compile as a graph");
+      }
+      d->graph_gen = d->lower_gen;
+      d->graph_key_bits = d->key_bits;
+      d->graph_sort_mode = d->sort_mode;
+    }
+    HIP_TRY(hipGraphLaunch(d->gexec, d->stream), "hipGraphLaunch");
+    d->ran = true;
+    return GP_OK;
+  }
   hipError_t e = gp::enqueue_compile(d->st, d->stream, hook);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   d->ran = true;
+  return GP_OK;
+}
+
+int gp_debug_set_graph(gp_driver* d, int enable) {
+  if (!d) return fail(GP_E_ARG, "null driver");
+  d->use_graph = enable != 0;
   return GP_OK;
 }
 

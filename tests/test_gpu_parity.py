@@ -285,3 +285,39 @@ def test_correlation_levels(drv25, level):
     with pytest.raises(GpError) as e:
         drv25.set_correlation_level(3)
     assert e.value.code == -1
+
+
+def test_graph_replays_match_eager_launches(drv25):
+    """gp_run replays the compile as a captured HIP graph. Every replay, with
+    eager launches, other circuits and rate changes in between, gives exactly
+    the eagerly launched result."""
+    say("case graph replays")
+    ca = rotated_surface_code_memory(9, 9)
+    cb = bivariate_bicycle_memory(rounds=3)
+    ra = log_uniform_rates(ca.n_channels, 5)
+
+    def compile_with(graph, text, rates=None):
+        _gp.gp_debug_set_graph(drv25.handle, graph)
+        try:
+            return drv25.compile_hypergraph(text, rates).edges()
+        finally:
+            _gp.gp_debug_set_graph(drv25.handle, 1)
+
+    try:
+        eager_a = compile_with(0, ca.text)
+        eager_b = compile_with(0, cb.text)
+        eager_ar = compile_with(0, ca.text, ra)
+        with Driver.from_circuit(ca.text) as other:
+            for rep in range(3):
+                assert compile_with(1, ca.text) == eager_a, f"replay {rep} a"
+                # one lowering replayed several times, with eager work (another
+                # driver, synchronised) in between
+                drv25.lower(cb.text)
+                for k in range(3):
+                    drv25.run()
+                    assert drv25.fetch().edges() == eager_b, f"replay {rep}.{k} b"
+                    assert other.compile_hypergraph(ca.text, ra).edges() == eager_ar
+                assert compile_with(1, ca.text, ra) == eager_ar, f"replay {rep} a rates"
+    finally:
+        _gp.gp_debug_set_graph(drv25.handle, 0)
+    assert oracle.run(ca.text).edges().keys() == eager_a.keys()
