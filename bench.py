@@ -110,6 +110,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiation workload")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default stage-1 work split")
     ap.add_argument("--batch-distances", default="3,5,7,10",
                     help="outer distances of the batched [[4,2,2]]-concatenated workload ('' skips it)")
     ap.add_argument("--batch-branches", type=int, default=256)
@@ -131,6 +132,8 @@ def main() -> int:
 
     circuit, rates, cfg = workload(args.workload)
     drv = get_driver(circuit.text)
+    # the stage-1 work split measured for this circuit (untimed)
+    tuned = drv.autotune(circuit.text, iters=5) if not args.no_autotune else None
     drv.lower(circuit.text, rates)
     info = drv.info()
     F = info["n_faults"]
@@ -193,6 +196,7 @@ def main() -> int:
                    "qubits": info["n_qubits"], "layers": info["n_layers"], "detectors": info["n_detectors"],
                    "observables": info["n_observables"], "hyperedges": info["n_edges"], "mode": "plain"},
         "hyperedges_per_s": info["n_edges"] / (ms_per_step * 1e-3),
+        "autotune": tuned,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "per_cycle_p50": float(np.percentile(lat, 50)) / rounds,
                        "per_cycle_p99": float(np.percentile(lat, 99)) / rounds,

@@ -160,6 +160,18 @@ int gp_fetch(gp_driver* drv, gp_edges** out);
 int gp_lower_batch(gp_driver* drv, const char* const* texts, const size_t* lens, const double* const* rates,
                    const size_t* n_rates, size_t n);
 
+/* Autotuner for the stage-1 work split. An observable column stays live over
+ * the whole circuit, so it is cut into boundary ranges swept by separate work
+ * items; the cut balances estimated item times in which a layer costs 1 and
+ * emitting a boundary 1 + fault_cost per fault there. gp_autotune compiles
+ * `text` with each of a few fault costs, times `iters` device runs of each
+ * (HIP events on the driver's stream), keeps the fastest for the following
+ * lowerings of this driver and returns it (*best_cost, *best_ms: may be NULL).
+ * The driver must be sized for `text`. Afterwards no lowering is current
+ * (gp_lower again). gp_set_fault_cost sets the value directly (0 < c < 1). */
+int gp_autotune(gp_driver* drv, const char* text, size_t len, int iters, double* best_cost, double* best_ms);
+int gp_set_fault_cost(gp_driver* drv, double fault_cost);
+
 /* Correlation level (Table 1) for the following lowerings: which Paulis of
  * each noise channel become faults. 0: products of X's or of Z's (IX, IZ, XI,
  * XX, ZI, ZZ; one-qubit X, Z); 1 adds a Y next to the identity and mixed X/Z

@@ -33,7 +33,7 @@ EXPORTS = (
     "gp_set_correlation_level", "gp_bounds_from_batch", "gp_driver_create_from_batch", "gp_lower_batch",
     "gp_edges_circuits", "gp_edges_circuit_ids", "gp_edges_circuit_shape", "gp_edges_circuit_dem_text",
     "gp_edges_circuit_offsets", "gp_server_create", "gp_server_submit", "gp_server_wait", "gp_server_stats",
-    "gp_server_destroy", "gp_server_timing", "gp_debug_set_graph",
+    "gp_server_destroy", "gp_server_timing", "gp_debug_set_graph", "gp_autotune", "gp_set_fault_cost",
 )
 
 
@@ -123,6 +123,9 @@ def load():
         "gp_debug_collision_retries": ([_vp], _u64),
         "gp_debug_set_sort_mode": ([_vp, ctypes.c_int], ctypes.c_int),
         "gp_debug_set_graph": ([_vp, ctypes.c_int], ctypes.c_int),
+        "gp_autotune": ([_vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                         ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "gp_set_fault_cost": ([_vp, ctypes.c_double], ctypes.c_int),
         "gp_refresh_rates": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t], ctypes.c_int),
         "gp_set_correlation_level": ([_vp, ctypes.c_int], ctypes.c_int),
         "gp_rates_gradient": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t,
@@ -403,6 +406,18 @@ def gp_debug_set_sort_mode(drv: int, mode: int) -> None:
 
 def gp_debug_set_graph(drv: int, enable: bool) -> None:
     _check(load().gp_debug_set_graph(drv, int(enable)))
+
+
+def gp_autotune(drv: int, text: str, iters: int = 10) -> Tuple[float, float]:
+    """-> (chosen fault cost, its mean device time in ms)."""
+    raw = text.encode()
+    c, ms = ctypes.c_double(), ctypes.c_double()
+    _check(load().gp_autotune(drv, raw, len(raw), iters, ctypes.byref(c), ctypes.byref(ms)))
+    return c.value, ms.value
+
+
+def gp_set_fault_cost(drv: int, fault_cost: float) -> None:
+    _check(load().gp_set_fault_cost(drv, fault_cost))
 
 
 def gp_debug_collision_retries(drv: int) -> int:

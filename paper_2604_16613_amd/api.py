@@ -144,6 +144,12 @@ class Driver:
     def info(self) -> dict:
         return _gp.gp_circuit_info_get(self.handle).as_dict()
 
+    def autotune(self, circuit: str, iters: int = 10) -> Dict[str, float]:
+        """Measure the stage-1 work split for `circuit` and keep the fastest
+        for the following compiles (see gp_autotune)."""
+        c, ms = _gp.gp_autotune(self.handle, circuit, iters)
+        return {"fault_cost": c, "ms": ms}
+
     def set_correlation_level(self, level: int) -> None:
         """Table 1 level (0, 1 or 2 = every Pauli) for the following compiles."""
         _gp.gp_set_correlation_level(self.handle, level)

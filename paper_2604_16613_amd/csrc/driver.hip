@@ -169,6 +169,7 @@ struct gp_driver {
   uint32_t sort_mode = gp::SORT_AUTO;  // test hook: force the full radix sort
   uint64_t bm_cap = 0;                 // non-zero-word bitmap words allocated
   uint32_t level = 2;                  // correlation level for the next lowering
+  double fault_cost = gp::kDefaultFaultCost;  // observable range cut (set by gp_autotune)
   uint64_t collision_retries = 0;
 
   // optionally, the compile's launch sequence captured as a HIP graph and
@@ -304,7 +305,7 @@ void fill_bounds(const gp::Lowered& lw, gp_bounds* out) {
 // Lower every circuit of a batch (each with its share of the sweep slots) and
 // merge them; `rates` may be null (rates written in the texts), as may any rates[k].
 int lower_batch(const char* const* texts, const size_t* lens, const double* const* rates, const size_t* n_rates,
-                size_t n, uint32_t level, gp::Lowered& out) {
+                size_t n, uint32_t level, gp::Lowered& out, double fault_cost = gp::kDefaultFaultCost) {
   if ((!texts || !lens) && n) return fail(GP_E_ARG, "null argument");
   if (n == 0) return fail(GP_E_ARG, "a batch needs at least one circuit");
   if (rates && !n_rates) return fail(GP_E_ARG, "rate arrays without their lengths");
@@ -319,7 +320,8 @@ int lower_batch(const char* const* texts, const size_t* lens, const double* cons
   auto lower_range = [&](size_t lo, size_t hi) {
     for (size_t k = lo; k < hi; k++) {
       const double* r = rates ? rates[k] : nullptr;
-      rcs[k] = gp::lower_circuit(texts[k], lens[k], r, r ? n_rates[k] : 0, slots, parts[k], errs[k], level);
+      rcs[k] = gp::lower_circuit(texts[k], lens[k], r, r ? n_rates[k] : 0, slots, parts[k], errs[k], level,
+                                 fault_cost);
     }
   };
   const size_t n_threads = std::min<size_t>({n, 16, std::max<size_t>(1, std::thread::hardware_concurrency())});
@@ -615,7 +617,7 @@ int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, si
   d->lowered = false;
   d->ran = false;
   d->structured = false;
-  int rc = gp::lower_circuit(text, len, rates, n_rates, gp::kSweepSlots, d->lw, err, d->level);
+  int rc = gp::lower_circuit(text, len, rates, n_rates, gp::kSweepSlots, d->lw, err, d->level, d->fault_cost);
   if (rc) return fail(rc, err.msg);
   return upload_lowered(d);
 }
@@ -626,7 +628,7 @@ int gp_lower_batch(gp_driver* d, const char* const* texts, const size_t* lens, c
   d->lowered = false;
   d->ran = false;
   d->structured = false;
-  int rc = lower_batch(texts, lens, rates, n_rates, n, d->level, d->lw);
+  int rc = lower_batch(texts, lens, rates, n_rates, n, d->level, d->lw, d->fault_cost);
   if (rc) return rc;
   return upload_lowered(d);
 }
@@ -678,6 +680,63 @@ int gp_run(gp_driver* d) {
   hipError_t e = gp::enqueue_compile(d->st, d->stream, hook);
   if (e != hipSuccess) return hip_fail(e, "kernel launch");
   d->ran = true;
+  return GP_OK;
+}
+
+int gp_set_fault_cost(gp_driver* d, double fault_cost) {
+  if (!d) return fail(GP_E_ARG, "null driver");
+  if (!(fault_cost > 0.0 && fault_cost < 1.0)) return fail(GP_E_ARG, "fault cost must be in (0, 1)");
+  d->fault_cost = fault_cost;
+  return GP_OK;
+}
+
+int gp_autotune(gp_driver* d, const char* text, size_t len, int iters, double* best_cost, double* best_ms) {
+  if (!d || !text) return fail(GP_E_ARG, "null argument");
+  if (iters < 1) return fail(GP_E_ARG, "iters must be at least 1");
+  static const double kCandidates[] = {2.5e-4, 4.0e-4, 6.2e-4, 9.0e-4, 1.4e-3};
+  HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
+  hipEvent_t a = nullptr, b = nullptr;
+  HIP_TRY(hipEventCreate(&a), "hipEventCreate");
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return hip_fail(hipGetLastError(), "hipEventCreate");
+  }
+  const double saved = d->fault_cost;
+  double bc = saved, bms = -1.0;
+  int rc = GP_OK;
+  for (double c : kCandidates) {
+    d->fault_cost = c;
+    if ((rc = gp_lower(d, text, len, nullptr, 0)) || (rc = gp_run(d))) break;
+    float ms = 0.f;
+    if (hipEventRecord(a, d->stream) != hipSuccess) {
+      rc = hip_fail(hipGetLastError(), "hipEventRecord");
+      break;
+    }
+    for (int k = 0; k < iters && rc == GP_OK; k++) rc = gp_run(d);
+    if (rc) break;
+    if (hipEventRecord(b, d->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+        hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+      rc = hip_fail(hipGetLastError(), "timing the candidates");
+      break;
+    }
+    const double per = double(ms) / iters;
+    if (bms < 0 || per < bms) {
+      bms = per;
+      bc = c;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  d->lowered = false;  // the tables hold the last candidate's lowering
+  d->ran = false;
+  d->structured = false;
+  if (rc) {
+    d->fault_cost = saved;
+    return rc;
+  }
+  d->fault_cost = bc;
+  if (best_cost) *best_cost = bc;
+  if (best_ms) *best_ms = bms;
   return GP_OK;
 }
 

@@ -67,9 +67,10 @@ struct RawChan {
 }  // namespace
 
 int lower_circuit(const char* text, size_t len, const double* rates, size_t n_rates,
-                  uint32_t sweep_slots, Lowered& lw, LowerError& err, uint32_t level) {
+                  uint32_t sweep_slots, Lowered& lw, LowerError& err, uint32_t level, double fault_cost) {
   lw = Lowered();
   if (level > 2) return set_err(err, GP_E_ARG, 0, "%s", "correlation level must be 0, 1 or 2");
+  if (!(fault_cost >= 0.0 && fault_cost < 1.0)) return set_err(err, GP_E_ARG, 0, "%s", "fault cost must be in [0, 1)");
   lw.level = level;
   std::vector<uint32_t> ready;
   std::vector<uint32_t> op_layer;
@@ -402,7 +403,8 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
     // from the top, so the lowest ranges get few boundaries and the upper
     // ones many: the smallest makespan T that the greedy cut from the
     // bottom fits into per_obs ranges is found by bisection.
-    constexpr double kLayerCost = 1.0, kFaultCost = 6.2e-4;
+    constexpr double kLayerCost = 1.0;
+    const double kFaultCost = fault_cost > 0 ? fault_cost : kDefaultFaultCost;
     for (uint32_t w = lw.wd; w < lw.w; w++) {
       const int32_t top = lw.col_top[w];
       if (top < 0) continue;

@@ -195,8 +195,14 @@ struct LowerError {
 // order. `sweep_slots` is the number of sweep items that run at once (one per
 // CU); observable columns are cut into ranges that fill the slots the
 // detector columns leave. Returns 0 or a negative GP_E_* status with err set.
+// Observable columns are cut into boundary ranges of equal estimated sweep
+// time: a layer costs 1, emitting a boundary costs 1 + fault_cost per fault
+// there (the default was measured at d = 25; gp_autotune measures others).
+constexpr double kDefaultFaultCost = 6.2e-4;
+
 int lower_circuit(const char* text, size_t len, const double* rates, size_t n_rates,
-                  uint32_t sweep_slots, Lowered& out, LowerError& err, uint32_t level = 2);
+                  uint32_t sweep_slots, Lowered& out, LowerError& err, uint32_t level = 2,
+                  double fault_cost = kDefaultFaultCost);
 
 // Re-apply a rate array to an already lowered circuit (same structure).
 int apply_rates(Lowered& lw, const double* rates, size_t n_rates, LowerError& err);

@@ -306,12 +306,16 @@ static int replay(const Lowered& lw, uint64_t* off, uint32_t* bits, uint64_t bit
   return 0;
 }
 
+// the observable range cut used by hc_run (the lowering's cost per fault)
+static double g_fault_cost = kDefaultFaultCost;
+extern "C" void hc_set_fault_cost(double c) { g_fault_cost = c; }
+
 extern "C" int hc_run(const char* text, size_t len, const double* rates, size_t n_rates, uint64_t* off,
                       uint32_t* bits, uint64_t bits_cap, uint32_t* src, uint32_t* code, uint64_t* stats,
                       uint64_t max_faults) {
   Lowered lw;
   LowerError err{};
-  int rc = lower_circuit(text, len, rates, n_rates, kSweepSlots, lw, err);
+  int rc = lower_circuit(text, len, rates, n_rates, kSweepSlots, lw, err, 2, g_fault_cost);
   if (rc) {
     g_msg = err.msg;
     return rc;

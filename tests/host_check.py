@@ -108,3 +108,11 @@ def run_batch(texts, slots=None, max_faults=4_000_000, bits_per_fault=16):
         k = int(circ[p])
         out[k][(int(src[p]) - base[k], int(code[p]))] = tuple(int(x) for x in bits[off[p]:off[p + 1]])
     return st, out
+
+
+def set_fault_cost(c: float) -> None:
+    lib = _load()
+    lib.hc_set_fault_cost.argtypes = [ctypes.c_double]
+    lib.hc_set_fault_cost.restype = None
+    lib.hc_set_fault_cost(c)
+

@@ -321,3 +321,19 @@ def test_graph_replays_match_eager_launches(drv25):
     finally:
         _gp.gp_debug_set_graph(drv25.handle, 0)
     assert oracle.run(ca.text).edges().keys() == eager_a.keys()
+
+
+def test_autotune_keeps_results(drv25):
+    """The autotuner picks one of its fault costs and the compiles after it
+    still match the oracle."""
+    say("case autotune")
+    c = rotated_surface_code_memory(11, 11)
+    try:
+        res = drv25.autotune(c.text, iters=3)
+        assert res["fault_cost"] in (2.5e-4, 4.0e-4, 6.2e-4, 9.0e-4, 1.4e-3) and res["ms"] > 0
+        with pytest.raises(GpError):
+            drv25.run()  # no lowering is current after tuning
+        check(drv25, c.text, label="after autotune")
+        check(drv25, bivariate_bicycle_memory().text, label="bb after autotune")
+    finally:
+        _gp.gp_set_fault_cost(drv25.handle, 6.2e-4)

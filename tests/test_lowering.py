@@ -74,3 +74,18 @@ def test_merged_batch_replays_like_each_circuit():
     st, per = host_check.run_batch([c] * 300)
     _, single = host_check.run(c)
     assert all(s == single for s in per)
+
+
+@pytest.mark.parametrize("cost", [2.5e-4, 1.4e-3, 0.02])
+def test_observable_cut_does_not_change_signatures(cost):
+    """The autotuner's knob (cost per fault when cutting observable columns
+    into ranges) moves item boundaries only: every fault keeps its signature."""
+    texts = [rotated_surface_code_memory(5, 5).text, bivariate_bicycle_memory(rounds=2).text]
+    ref = [host_check.run(t)[1] for t in texts]
+    host_check.set_fault_cost(cost)
+    try:
+        for t, r in zip(texts, ref):
+            st, sigs = host_check.run(t)
+            assert sigs == r
+    finally:
+        host_check.set_fault_cost(6.2e-4)
