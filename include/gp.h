@@ -271,6 +271,14 @@ uint64_t gp_debug_collision_retries(const gp_driver* drv);
  * within a class; the edge order may differ). GP_E_ARG for other values. */
 int gp_debug_set_sort_mode(gp_driver* drv, int mode);
 
+/* Test hook: stage-1 work-group shape for later gp_run calls. 0 (default):
+ * automatic (work-groups of 256 threads with smaller LDS tables, several per
+ * CU, when a compile has at least 512 sweep items of a circuit small enough;
+ * otherwise one work-group of 1024 threads per item); 1: always 1024 threads;
+ * 2: 256 threads wherever the circuit fits them. Same signatures either way.
+ * GP_E_ARG for other values. */
+int gp_debug_set_sweep_shape(gp_driver* drv, int shape);
+
 /* Launch mode: with enable = 1, gp_run replays the compile's kernel launches as
  * one HIP graph, captured at the first gp_run after each lowering (and after a
  * change of the test modes above); 0 (default) launches every kernel on its

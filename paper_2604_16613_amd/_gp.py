@@ -34,6 +34,7 @@ EXPORTS = (
     "gp_edges_circuits", "gp_edges_circuit_ids", "gp_edges_circuit_shape", "gp_edges_circuit_dem_text",
     "gp_edges_circuit_offsets", "gp_server_create", "gp_server_submit", "gp_server_wait", "gp_server_stats",
     "gp_server_destroy", "gp_server_timing", "gp_debug_set_graph", "gp_autotune", "gp_set_fault_cost",
+    "gp_debug_set_sweep_shape",
 )
 
 
@@ -123,6 +124,7 @@ def load():
         "gp_debug_collision_retries": ([_vp], _u64),
         "gp_debug_set_sort_mode": ([_vp, ctypes.c_int], ctypes.c_int),
         "gp_debug_set_graph": ([_vp, ctypes.c_int], ctypes.c_int),
+        "gp_debug_set_sweep_shape": ([_vp, ctypes.c_int], ctypes.c_int),
         "gp_autotune": ([_vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
                          ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "gp_set_fault_cost": ([_vp, ctypes.c_double], ctypes.c_int),
@@ -418,6 +420,10 @@ def gp_autotune(drv: int, text: str, iters: int = 10) -> Tuple[float, float]:
 
 def gp_set_fault_cost(drv: int, fault_cost: float) -> None:
     _check(load().gp_set_fault_cost(drv, fault_cost))
+
+
+def gp_debug_set_sweep_shape(drv: int, shape: int) -> None:
+    _check(load().gp_debug_set_sweep_shape(drv, shape))
 
 
 def gp_debug_collision_retries(drv: int) -> int:

@@ -167,6 +167,7 @@ struct gp_driver {
 
   uint32_t key_bits = 64;      // test hook: class keys cut to this many bits
   uint32_t sort_mode = gp::SORT_AUTO;  // test hook: force the full radix sort
+  uint32_t sweep_shape = 0;            // test hook: force a stage-1 work-group shape
   uint64_t bm_cap = 0;                 // non-zero-word bitmap words allocated
   uint32_t level = 2;                  // correlation level for the next lowering
   double fault_cost = gp::kDefaultFaultCost;  // observable range cut (set by gp_autotune)
@@ -178,7 +179,7 @@ struct gp_driver {
   hipGraphExec_t gexec = nullptr;
   uint64_t lower_gen = 0;      // bumped by every upload of a lowering
   uint64_t graph_gen = ~0ull;  // the lowering generation the graph was captured for
-  uint32_t graph_key_bits = 0, graph_sort_mode = 0;
+  uint32_t graph_key_bits = 0, graph_sort_mode = 0, graph_shape = 0;
 
   bool timing = false;
   std::vector<hipEvent_t> ev_free;
@@ -593,9 +594,8 @@ static int upload_lowered(gp_driver* d) {
   st.w_max = lw.w_max;
   st.n_win = 0;
   for (const gp::BranchDesc& bd : lw.branches) st.n_win = std::max(st.n_win, bd.n_win);
-  st.max_col_inj = 0;
-  for (uint32_t w = 0; w < lw.w; w++)
-    st.max_col_inj = std::max(st.max_col_inj, lw.inj_off[w + 1] - lw.inj_off[w]);
+  st.max_win_ops = 0;
+  for (uint32_t c : lw.win_cnt) st.max_win_ops = std::max(st.max_win_ops, c);
   st.n_qubits = lw.n_qubits;
   st.n_layers = lw.n_layers;
   st.n_det = lw.n_det;
@@ -646,12 +646,13 @@ int gp_run(gp_driver* d) {
   d->st.key_mode = 0;
   d->st.key_bits = d->key_bits;
   d->st.sort_mode = d->sort_mode;
+  d->st.sweep_shape = d->sweep_shape;
   d->structured = false;
   if (d->use_graph && !d->timing) {
     // replay the captured launch sequence; capture it first if the lowering
     // or a mode changed since
     if (!d->gexec || d->graph_gen != d->lower_gen || d->graph_key_bits != d->key_bits ||
-        d->graph_sort_mode != d->sort_mode) {
+        d->graph_sort_mode != d->sort_mode || d->graph_shape != d->sweep_shape) {
       if (d->gexec) {
         (void)hipGraphExecDestroy(d->gexec);
         d->gexec = nullptr;
@@ -672,6 +673,7 @@ int gp_run(gp_driver* d) {
       d->graph_gen = d->lower_gen;
       d->graph_key_bits = d->key_bits;
       d->graph_sort_mode = d->sort_mode;
+      d->graph_shape = d->sweep_shape;
     }
     HIP_TRY(hipGraphLaunch(d->gexec, d->stream), "hipGraphLaunch");
     d->ran = true;
@@ -737,6 +739,13 @@ int gp_autotune(gp_driver* d, const char* text, size_t len, int iters, double* b
   d->fault_cost = bc;
   if (best_cost) *best_cost = bc;
   if (best_ms) *best_ms = bms;
+  return GP_OK;
+}
+
+int gp_debug_set_sweep_shape(gp_driver* d, int shape) {
+  if (!d) return fail(GP_E_ARG, "null driver");
+  if (shape < 0 || shape > 2) return fail(GP_E_ARG, "sweep shape must be 0, 1 or 2");
+  d->sweep_shape = uint32_t(shape);
   return GP_OK;
 }
 

@@ -97,13 +97,14 @@ struct DevState {
   uint32_t n_hchunks;
   uint32_t n_win;
   uint32_t level;       // correlation level (Table 1) the faults were kept at
-  uint32_t max_col_inj;  // most injection entries of any one column
+  uint32_t max_win_ops;  // most ops in one op window
   // class key: 0 = FNV-1a of the signature (kept to its low key_bits bits);
   // 1 = FNV-1a mixed with the check hash (used after a key collision)
   uint32_t key_mode;
   uint32_t key_bits;
   uint32_t n_pass;      // radix passes (8-bit digits) over the class key
   uint32_t sort_mode;   // SORT_*
+  uint32_t sweep_shape; // stage-1 work-group shape: 0 automatic, 1 = 1024 threads, 2 = 256 threads
   uint32_t max_tiles;   // tiles the sort/compaction scratch is sized for
 
   // work buffers

@@ -37,11 +37,18 @@ namespace {
 constexpr int kSweepBlock = 1024;
 constexpr int kWinOps = int(kSweepWinOps);  // compact ops per LDS window buffer (two buffers)
 constexpr int kEmitPre = 8;            // fault records per thread fetched during the op phase
-constexpr int kPre = kWinOps / kSweepBlock;
 constexpr int kLofsMax = 2048;         // layer offsets staged in LDS when the circuit has fewer layers
 constexpr int kInjLds = 512;           // a column's injections staged in LDS when it has at most this many
 constexpr int kWinTableLds = 512;      // op windows whose table is staged in LDS
-constexpr int kBranchLds = 1024;       // circuits of a batch whose first fault the edge writer stages in LDS
+constexpr int kBranchLds = 1024;
+// LDS table sizes of the two sweep shapes (work-group size kBlk)
+template <int kBlk> struct SweepShape;
+template <> struct SweepShape<1024> {
+  static constexpr int kLofs = kLofsMax, kInj = kInjLds, kWinTab = kWinTableLds, kWin = kWinOps;
+};
+template <> struct SweepShape<256> {
+  static constexpr int kLofs = 512, kInj = 256, kWinTab = 128, kWin = int(kSmallWinOps);
+};       // circuits of a batch whose first fault the edge writer stages in LDS
 constexpr int kBlock = 256;
 constexpr int kPerThread = kTile / kBlock;
 constexpr int kScanSingleBlock = 1024;
@@ -349,10 +356,16 @@ __device__ __forceinline__ int wave_total(int v) {
 // a running sum and published in per-wave LDS slots (two sets, alternating).
 constexpr int kCountEvery = 8;
 
-template <bool kStaged>
-__global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
+template <bool kStaged, int kBlk>
+__global__ __launch_bounds__(kBlk) void k_sweep(DevState st) {
+  // kBlk = 1024: one item per CU (large circuits); 256: a smaller LDS
+  // footprint so that several items share a CU (many items of small circuits)
+  constexpr int kLofs = SweepShape<kBlk>::kLofs;
+  constexpr int kInj = SweepShape<kBlk>::kInj;
+  constexpr int kWinN = SweepShape<kBlk>::kWin;  // ops per window buffer
+  constexpr int kPreN = kWinN / kBlk;
   extern __shared__ __align__(16) uint64_t lds[];
-  __shared__ int s_wnz[2][kSweepBlock / 64];
+  __shared__ int s_wnz[2][kBlk / 64];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const uint32_t item = blockIdx.x;
@@ -369,14 +382,14 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   uint64_t* frame = lds;
   uint64_t* pend = frame + 2 * size_t(n);  // two buffers, by layer parity
   uint64_t* sinj_w = pend + 2 * size_t(n);
-  uint32_t* opbuf = reinterpret_cast<uint32_t*>(sinj_w + kInjLds);
-  uint32_t* slofs = opbuf + 2 * kWinOps;
-  uint32_t* sbfo = slofs + kLofsMax;
-  uint32_t* sbmo = sbfo + kLofsMax + 1;
-  uint32_t* sinj_l = sbmo + kLofsMax + 1;
-  uint32_t* sinj_q = sinj_l + kInjLds;
-  uint32_t* sinj_n = sinj_q + kInjLds;
-  uint32_t* swin = sinj_n + kInjLds;  // per op window: lowest layer, first op, op count
+  uint32_t* opbuf = reinterpret_cast<uint32_t*>(sinj_w + kInj);
+  uint32_t* slofs = opbuf + 2 * kWinN;
+  uint32_t* sbfo = slofs + kLofs;
+  uint32_t* sbmo = sbfo + kLofs + 1;
+  uint32_t* sinj_l = sbmo + kLofs + 1;
+  uint32_t* sinj_q = sinj_l + kInj;
+  uint32_t* sinj_n = sinj_q + kInj;
+  uint32_t* swin = sinj_n + kInj;  // per op window: lowest layer, first op, op count
 
   if (tid == 0) st.item_clock[2 * item] = wall_clock64();
   const uint32_t w = st.item_col[item];
@@ -386,23 +399,25 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   const int bhi = int(st.item_bhi[item]);
   uint64_t* out = st.slab + st.col_base[w];
   uint64_t* obm = st.bm + st.col_bm_base[w];
-  // kStaged: the layer offsets and every column's injections fit in LDS, so
-  // the layer loop reads no global memory besides the window prefetch and
-  // the emission's fault records
+  // kStaged: the layer offsets (and the column's injections, where they fit)
+  // sit in LDS, so the layer loop reads no global memory besides the window
+  // prefetch and the emission's fault records
   constexpr bool lofs_lds = kStaged;
-  constexpr bool inj_lds = kStaged;
   const uint32_t i0 = st.inj_off[w];
   const uint32_t ni = st.inj_off[w + 1] - i0;
+  // a column with more injections than the LDS list holds reads them from
+  // global memory (the same for every thread of the item)
+  const bool inj_lds = kStaged && ni <= uint32_t(kInj);
 
-  for (uint32_t i = tid; i < 4 * n; i += kSweepBlock) frame[i] = 0;  // frame and both pend buffers
+  for (uint32_t i = tid; i < 4 * n; i += kBlk) frame[i] = 0;  // frame and both pend buffers
   if (lofs_lds)
-    for (uint32_t k = tid; k <= br.n_layers + 1; k += kSweepBlock) {
+    for (uint32_t k = tid; k <= br.n_layers + 1; k += kBlk) {
       if (k <= br.n_layers) slofs[k] = layer_off[k];
       sbfo[k] = bnd_fault_off[k];
       sbmo[k] = bnd_bm_off[k];
     }
   if (inj_lds)
-    for (uint32_t k = tid; k < ni; k += kSweepBlock) {
+    for (uint32_t k = tid; k < ni; k += kBlk) {
       sinj_w[k] = st.inj_word[i0 + k];
       sinj_l[k] = st.inj_layer[i0 + k];
       sinj_q[k] = st.inj_qubit[i0 + k];
@@ -411,7 +426,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   // the window table sits in LDS (kStaged): reading it from global memory with
   // scalar loads would make the next LDS wait also wait for them
   if (lofs_lds)
-    for (uint32_t k = tid; k < br.n_win; k += kSweepBlock) {
+    for (uint32_t k = tid; k < br.n_win; k += kBlk) {
       swin[3 * k] = win_lo[k];
       swin[3 * k + 1] = win_obase[k];
       swin[3 * k + 2] = win_cnt[k];
@@ -425,7 +440,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   int wlo = int(win_lo[wid]);
   {
     const uint32_t cnt = win_cnt[wid];
-    for (uint32_t i = tid; i < cnt; i += kSweepBlock) opbuf[i] = st.ops32[o_base + i];
+    for (uint32_t i = tid; i < cnt; i += kBlk) opbuf[i] = st.ops32[o_base + i];
   }
   __syncthreads();
   auto LO = [&](int t) -> uint32_t { return lofs_lds ? slofs[t] : layer_off[t]; };
@@ -443,7 +458,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   auto scatter = [&](int t) {
     if (inj_t == t) {
       uint64_t* pb = pend + size_t(t & 1) * n;
-      for (uint32_t k = ip + tid; k < inj_e; k += kSweepBlock) pb[INJ_Q(k)] = INJ_W(k);
+      for (uint32_t k = ip + tid; k < inj_e; k += kBlk) pb[INJ_Q(k)] = INJ_W(k);
       ip = inj_e;
       inj_t = ip < ni ? INJ_L(ip) : -1;
       inj_e = ip < ni ? INJ_N(ip) : 0;
@@ -451,15 +466,15 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   };
   scatter(top);
   // the next window (layers below wlo) into registers, if the item needs it
-  uint32_t pre[kPre];
+  uint32_t pre[kPreN];
   uint32_t nbase = 0;
   auto prefetch = [&]() {
     const bool need = wlo - 1 >= blo;
     const uint32_t cnt = need ? WCN(wid + 1) : 0u;
     nbase = need ? WOB(wid + 1) : 0u;
 #pragma unroll
-    for (int k = 0; k < kPre; ++k) {
-      const uint32_t i = tid + k * kSweepBlock;
+    for (int k = 0; k < kPreN; ++k) {
+      const uint32_t i = tid + k * kBlk;
       pre[k] = i < cnt ? st.ops32[nbase + i] : 0u;
     }
   };
@@ -473,10 +488,10 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
 
   // the ops of layer t; dnz accumulates the change in non-zero frame words
   auto apply_layer = [&](int t, uint32_t lo_t, int& dnz) {
-    const uint32_t* buf = opbuf + cur * kWinOps;
+    const uint32_t* buf = opbuf + cur * kWinN;
     uint64_t* pb = pend + size_t(t & 1) * n;
     // a layer never exceeds a window
-    for (uint32_t i = lo_t - o_base + tid; i < lo_hi - o_base; i += kSweepBlock)
+    for (uint32_t i = lo_t - o_base + tid; i < lo_hi - o_base; i += kBlk)
       apply_op(buf[i], reinterpret_cast<ulonglong2*>(frame), pb, dnz, gauge);
   };
   // publish this wave's running count in slot set ck & 1 (read after a barrier)
@@ -487,7 +502,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   auto count_published = [&]() -> int {
     int nz = 0;
 #pragma unroll
-    for (int k = 0; k < kSweepBlock / 64; ++k) nz += s_wnz[ck & 1][k];
+    for (int k = 0; k < kBlk / 64; ++k) nz += s_wnz[ck & 1][k];
     return nz;
   };
   // the next layer's leaf words, and the window swap when layer t ends it
@@ -497,10 +512,10 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
       // the prefetched window becomes current (the other buffer is no longer
       // read), and the window after it is fetched into registers
       const uint32_t cnt = WCN(wid + 1);
-      uint32_t* nb = opbuf + (cur ^ 1) * kWinOps;
+      uint32_t* nb = opbuf + (cur ^ 1) * kWinN;
 #pragma unroll
-      for (int k = 0; k < kPre; ++k) {
-        const uint32_t i = tid + k * kSweepBlock;
+      for (int k = 0; k < kPreN; ++k) {
+        const uint32_t i = tid + k * kBlk;
         if (i < cnt) nb[i] = pre[k];
       }
       cur ^= 1;
@@ -550,7 +565,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
       uint32_t rec[kEmitPre];
 #pragma unroll
       for (int k = 0; k < kEmitPre; ++k) {
-        const uint32_t i = tid + k * kSweepBlock;
+        const uint32_t i = tid + k * kBlk;
         rec[k] = i < nf ? st.frec[f0 + i] : 0u;
       }
       int dnz = 0;
@@ -580,14 +595,14 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
       uint64_t* bmp = obm + BMO(t);
 #pragma unroll
       for (int k = 0; k < kEmitPre; ++k) {
-        const uint32_t i = tid + k * kSweepBlock;
+        const uint32_t i = tid + k * kBlk;
         const uint64_t v = i < nf ? word_of(rec[k]) : 0ull;
         if (v) out[f0 + i] = v;
         const uint64_t msk = __ballot(v != 0);
         if (lane == 0 && i < nf) bmp[i >> 6] = msk;
       }
-      for (uint32_t k = kEmitPre; k * kSweepBlock < nf; ++k) {
-        const uint32_t i = tid + k * kSweepBlock;
+      for (uint32_t k = kEmitPre; k * kBlk < nf; ++k) {
+        const uint32_t i = tid + k * kBlk;
         const uint64_t v = i < nf ? word_of(st.frec[f0 + i]) : 0ull;
         if (v) out[f0 + i] = v;
         const uint64_t msk = __ballot(v != 0);
@@ -608,7 +623,7 @@ __global__ __launch_bounds__(kSweepBlock) void k_sweep(DevState st) {
   }
   if (!dead && blo == 0) {
     // every qubit starts in |0>: a Z error at the very start must be invisible
-    for (uint32_t q = tid; q < n; q += kSweepBlock) gauge |= frame[2 * q + 1] != 0;
+    for (uint32_t q = tid; q < n; q += kBlk) gauge |= frame[2 * q + 1] != 0;
   }
   if (gauge) atomicOr(&st.hdr->flags, FLAG_GAUGE);
   if (tid == 0) st.item_clock[2 * item + 1] = wall_clock64();
@@ -1765,9 +1780,23 @@ uint32_t sort_passes(uint64_t n) {
 
 size_t hash_lds_bytes(uint32_t w) { return (size_t(w) + 1) * 8 + size_t(w) * (8 + 8 + 8 * kHashBmw + 4); }
 
-size_t sweep_lds_bytes(uint32_t n_qubits) {
-  return (size_t(5) * n_qubits + kInjLds) * sizeof(uint64_t) +
-         (size_t(2) * kWinOps + 3 * kLofsMax + 2 + 3 * kInjLds + 3 * kWinTableLds) * sizeof(uint32_t);
+template <int kBlk>
+static size_t sweep_lds_shape(uint32_t n_qubits) {
+  using S = SweepShape<kBlk>;
+  return (size_t(5) * n_qubits + S::kInj) * sizeof(uint64_t) +
+         (size_t(2) * S::kWin + 3 * S::kLofs + 2 + 3 * S::kInj + 3 * S::kWinTab) * sizeof(uint32_t);
+}
+
+size_t sweep_lds_bytes(uint32_t n_qubits) { return sweep_lds_shape<1024>(n_qubits); }
+
+// The small shape is used when there are enough items to give each CU
+// several, its tables hold the circuit and two of its work-groups fit in one
+// CU's LDS.
+static bool small_sweep_fits(const DevState& st) {
+  using S = SweepShape<256>;
+  return st.n_layers + 2 <= uint32_t(S::kLofs) && st.n_win <= uint32_t(S::kWinTab) &&
+         st.max_win_ops <= uint32_t(S::kWin) &&
+         2 * (sweep_lds_shape<256>(st.n_qubits) + 1024) <= 160 * 1024;
 }
 
 static size_t g_lds_limit = 64 * 1024;
@@ -1787,11 +1816,11 @@ hipError_t configure_kernels() {
   // leave room for the sweep's static shared words
   size_t lim = size_t(lds) > 1024 ? size_t(lds) - 1024 : size_t(lds);
   if (lim > 64 * 1024) {
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep<true>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lim));
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sweep<false>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lim));
+    const void* variants[3] = {reinterpret_cast<const void*>(&k_sweep<true, 1024>),
+                               reinterpret_cast<const void*>(&k_sweep<false, 1024>),
+                               reinterpret_cast<const void*>(&k_sweep<true, 256>)};
+    for (const void* f : variants)
+      if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, int(lim));
     if (e != hipSuccess) {
       (void)hipGetLastError();
       lim = 64 * 1024 - 1024;
@@ -1843,11 +1872,16 @@ hipError_t enqueue_compile(DevState& st_io, hipStream_t stream, const LaunchHook
     GP_LAUNCH(K_PREPARE, k_prepare<<<g, kBlock, 0, stream>>>(st));
   }
   if (st.n_items) {
-    if (st.n_layers + 2 <= uint32_t(kLofsMax) && st.max_col_inj <= uint32_t(kInjLds) &&
-        st.n_win <= uint32_t(kWinTableLds)) {
-      GP_LAUNCH(K_SWEEP, k_sweep<true><<<st.n_items, kSweepBlock, sweep_lds_bytes(st.n_qubits), stream>>>(st));
+    // the small shape for many items of small circuits (several per CU)
+    const bool small = st.sweep_shape == 2 || (st.sweep_shape == 0 && st.n_items >= 512 && small_sweep_fits(st));
+    if (small && small_sweep_fits(st)) {
+      GP_LAUNCH(K_SWEEP, k_sweep<true, 256><<<st.n_items, 256, sweep_lds_shape<256>(st.n_qubits), stream>>>(st));
+    } else if (st.n_layers + 2 <= uint32_t(kLofsMax) && st.n_win <= uint32_t(kWinTableLds)) {
+      GP_LAUNCH(K_SWEEP,
+                k_sweep<true, 1024><<<st.n_items, kSweepBlock, sweep_lds_bytes(st.n_qubits), stream>>>(st));
     } else {
-      GP_LAUNCH(K_SWEEP, k_sweep<false><<<st.n_items, kSweepBlock, sweep_lds_bytes(st.n_qubits), stream>>>(st));
+      GP_LAUNCH(K_SWEEP,
+                k_sweep<false, 1024><<<st.n_items, kSweepBlock, sweep_lds_bytes(st.n_qubits), stream>>>(st));
     }
   }
   if (n == 0) {

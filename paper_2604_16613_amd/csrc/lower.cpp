@@ -459,9 +459,10 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
   // ---- op windows (a layer has at most n ops; the driver rejects circuits
   // whose largest layer exceeds a window)
   lw.layer_win.assign(L, 0);
+  const uint32_t win_ops = lw.n_qubits <= kSmallWinOps ? kSmallWinOps : kSweepWinOps;
   for (int32_t hi = int32_t(L) - 1; hi >= 0;) {
     int32_t lo = hi;
-    while (lo > 0 && lw.layer_off[hi + 1] - lw.layer_off[lo - 1] <= kSweepWinOps) lo--;
+    while (lo > 0 && lw.layer_off[hi + 1] - lw.layer_off[lo - 1] <= win_ops) lo--;
     const uint32_t id = uint32_t(lw.win_lo.size());
     lw.win_lo.push_back(uint32_t(lo));
     lw.win_obase.push_back(lw.layer_off[lo]);

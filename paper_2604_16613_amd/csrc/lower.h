@@ -92,6 +92,9 @@ inline constexpr KeptCodes kKeptCodes = make_kept_codes();
 
 // Compact ops one LDS op window of the sweep holds.
 constexpr uint32_t kSweepWinOps = 4096;
+// Circuits of at most this many qubits (so at most this many ops in a layer)
+// get windows of this many ops: small enough for the sweep's small shape.
+constexpr uint32_t kSmallWinOps = 1024;
 // Sweep items that run at once: one per CU of the target GPU (256 on gfx950).
 constexpr uint32_t kSweepSlots = 256;
 // An observable column is not cut into ranges of fewer faults than this.

@@ -37,7 +37,8 @@ extern "C" uint64_t hc_item_stats(uint64_t* out, uint64_t cap) {
 // addresses them: every circuit through its descriptor, every access checked.
 // Signature bits use each circuit's own numbering.
 // stats: [0] faults, [1] items, [2] slab words, [3] layers (most of any circuit),
-//        [4] gauge flag, [5] words written, [6] columns, [7] qubits (most)
+//        [4] gauge flag, [5] words written, [6] columns, [7] qubits (most),
+//        [8] injection entries of the longest column list
 static int replay(const Lowered& lw, uint64_t* off, uint32_t* bits, uint64_t bits_cap, uint32_t* src,
                   uint32_t* code, uint64_t* stats, uint64_t max_faults) {
   const uint32_t W = lw.w;
@@ -303,6 +304,9 @@ static int replay(const Lowered& lw, uint64_t* off, uint32_t* bits, uint64_t bit
   stats[5] = nwritten;
   stats[6] = W;
   stats[7] = nq;
+  uint64_t mi = 0;
+  for (size_t w = 0; w + 1 < lw.inj_off.size(); w++) mi = std::max<uint64_t>(mi, lw.inj_off[w + 1] - lw.inj_off[w]);
+  stats[8] = mi;
   return 0;
 }
 

@@ -45,7 +45,7 @@ def run(text, rates=None, max_faults=4_000_000, bits_per_fault=16):
     bits = np.zeros(max_faults * bits_per_fault, dtype=np.uint32)
     src = np.zeros(max_faults, dtype=np.uint32)
     code = np.zeros(max_faults, dtype=np.uint32)
-    stats = np.zeros(8, dtype=np.uint64)
+    stats = np.zeros(9, dtype=np.uint64)
     P = ctypes.POINTER
     if rates is not None:
         r = np.ascontiguousarray(rates, dtype=np.float64)
@@ -57,7 +57,7 @@ def run(text, rates=None, max_faults=4_000_000, bits_per_fault=16):
                     code.ctypes.data_as(P(ctypes.c_uint32)), stats.ctypes.data_as(P(ctypes.c_uint64)), max_faults)
     if rc != 0:
         raise RuntimeError(f"host check failed ({rc}): {lib.hc_error().decode()}")
-    names = ["faults", "items", "slab_words", "layers", "gauge", "written", "words", "qubits"]
+    names = ["faults", "items", "slab_words", "layers", "gauge", "written", "words", "qubits", "max_col_inj"]
     st = {k: int(v) for k, v in zip(names, stats)}
     F = st["faults"]
     sigs = {}
@@ -86,14 +86,14 @@ def run_batch(texts, slots=None, max_faults=4_000_000, bits_per_fault=16):
     src = np.zeros(max_faults, dtype=np.uint32)
     code = np.zeros(max_faults, dtype=np.uint32)
     circ = np.zeros(max_faults, dtype=np.uint32)
-    stats = np.zeros(8, dtype=np.uint64)
+    stats = np.zeros(9, dtype=np.uint64)
     rc = lib.hc_run_batch(arr, lens, n, slots, off.ctypes.data_as(P(ctypes.c_uint64)),
                           bits.ctypes.data_as(P(ctypes.c_uint32)), len(bits), src.ctypes.data_as(P(ctypes.c_uint32)),
                           code.ctypes.data_as(P(ctypes.c_uint32)), stats.ctypes.data_as(P(ctypes.c_uint64)),
                           max_faults, circ.ctypes.data_as(P(ctypes.c_uint32)))
     if rc != 0:
         raise RuntimeError(f"host check failed ({rc}): {lib.hc_error().decode()}")
-    names = ["faults", "items", "slab_words", "layers", "gauge", "written", "words", "qubits"]
+    names = ["faults", "items", "slab_words", "layers", "gauge", "written", "words", "qubits", "max_col_inj"]
     st = {k: int(v) for k, v in zip(names, stats)}
     # channel numbers of the batch -> per circuit: subtract the channels of the circuits before
     counts = [0] * n

@@ -74,3 +74,12 @@ def test_outer_checks_follow_the_refresh_rule():
     busy = iceberg_surface_branch(d, 0, cycles=cycles, p_excite=1.0, gamma=100)
     n_outer = d * d - 1
     assert busy.n_detectors - quiet.n_detectors == (cycles - 2) * n_outer
+
+
+def test_d10_batch_has_columns_longer_than_the_small_injection_list():
+    """The 256-thread stage-1 shape keeps up to 256 injection entries per column
+    in LDS; the distance-10 GPU case must include longer lists so that the
+    global-memory path is exercised there."""
+    texts = [c.text for c in iceberg_surface_batch(10, n_branches=6, seed=3)]
+    st, _ = host_check.run_batch(texts)
+    assert st["max_col_inj"] > 256

@@ -253,3 +253,37 @@ def test_batch_result_is_listed_circuit_by_circuit(batch_driver):
             assert np.all(ids[cut[k]:cut[k + 1]] == k)
     finally:
         _gp.gp_edges_free(h)
+
+
+@pytest.mark.parametrize("shape", [1, 2])
+def test_forced_sweep_shapes_match_oracle(batch_driver, shape):
+    """Both stage-1 work-group shapes (1024 threads with the large LDS tables,
+    256 threads with the small ones) give the oracle's hypergraphs on the mixed
+    batch; the automatic choice only picks the small one for large batches."""
+    cs = mixed_batch()
+    say("case forced sweep shape", shape)
+    _gp.gp_debug_set_sweep_shape(batch_driver.handle, shape)
+    try:
+        got = batch_driver.compile_batch([t for _, t, _ in cs], [r for _, _, r in cs])
+    finally:
+        _gp.gp_debug_set_sweep_shape(batch_driver.handle, 0)
+    for (name, t, r), hg in zip(cs, got):
+        assert_same(hg, oracle.run(t, r), f"{name} shape {shape}")
+
+
+def test_small_shape_with_long_injection_lists():
+    """Outer distance 10 branches under the 256-thread shape: some columns carry
+    more injections than its LDS list holds, so they are read from global
+    memory. Equal to the 1024-thread shape bit for bit, and to the oracle on one
+    branch."""
+    from workloads import iceberg_surface_batch
+    texts = [c.text for c in iceberg_surface_batch(10, n_branches=6, seed=3)]
+    say("case small shape d10")
+    with Driver.from_batch(texts) as drv:
+        _gp.gp_debug_set_sweep_shape(drv.handle, 1)
+        big = drv.compile_batch(texts)
+        _gp.gp_debug_set_sweep_shape(drv.handle, 2)
+        small = drv.compile_batch(texts)
+    for k in range(len(texts)):
+        assert_same(small[k], big[k], f"d10 branch {k} small vs big", exact=True)
+    assert_same(small[5], oracle.run(texts[5]), "d10 branch 5 vs oracle")
