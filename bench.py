@@ -54,7 +54,8 @@ def profiled_traffic(kernel: str, workload_name: str):
                 row = line.split()
     if digest != kernel_digest() or row is None:
         return None
-    return float(row[4]) + float(row[5])
+    # the last two columns are fetch and write bytes (kernel names may hold spaces)
+    return float(row[-2]) + float(row[-1])
 
 
 def workload(name: str):
