@@ -134,7 +134,10 @@ def main() -> int:
     circuit, rates, cfg = workload(args.workload)
     drv = get_driver(circuit.text)
     # the stage-1 work split measured for this circuit (untimed)
-    tuned = drv.autotune(circuit.text, iters=5) if not args.no_autotune else None
+    tuned = None
+    if not args.no_autotune:
+        t = drv.autotune(circuit.text, iters=5)
+        tuned = {k: t[k] for k in ("fault_cost", "sweep_block", "ms", "cached")}
     drv.lower(circuit.text, rates)
     info = drv.info()
     F = info["n_faults"]
@@ -298,6 +301,8 @@ def bench_batched(d: int, n_branches: int, steps: int) -> dict:
     print(f"batched workload: generating {n_branches} branches at outer d={d}", file=sys.stderr, flush=True)
     texts = [c.text for c in iceberg_surface_batch(d, n_branches=n_branches, seed=0)]
     drv = Driver.from_batch(texts)
+    t = drv.autotune_batch(texts, iters=3)
+    tuned = {k: t[k] for k in ("fault_cost", "sweep_block", "ms", "cached")}
     drv.lower_batch(texts)
     F = drv.info()["n_faults"]
     drv.run()
@@ -351,7 +356,7 @@ def bench_batched(d: int, n_branches: int, steps: int) -> dict:
             "per_branch_ms_sum": per_ms, "per_branch_faults_per_s": F / (per_ms * 1e-3),
             "speedup_batched_vs_per_branch": per_ms / batch_ms,
             "batched_e2e_ms": batch_e2e_ms, "per_branch_e2e_ms_sum": per_e2e_ms,
-            "batched_kernels_ms": kt,
+            "batched_kernels_ms": kt, "autotune": tuned,
             "timing": "device stages with tables resident (host wall clock over synced launches); "
                       "e2e = host lowering + upload + stages + download"}
 

@@ -160,16 +160,42 @@ int gp_fetch(gp_driver* drv, gp_edges** out);
 int gp_lower_batch(gp_driver* drv, const char* const* texts, const size_t* lens, const double* const* rates,
                    const size_t* n_rates, size_t n);
 
-/* Autotuner for the stage-1 work split. An observable column stays live over
- * the whole circuit, so it is cut into boundary ranges swept by separate work
- * items; the cut balances estimated item times in which a layer costs 1 and
- * emitting a boundary 1 + fault_cost per fault there. gp_autotune compiles
- * `text` with each of a few fault costs, times `iters` device runs of each
- * (HIP events on the driver's stream), keeps the fastest for the following
- * lowerings of this driver and returns it (*best_cost, *best_ms: may be NULL).
- * The driver must be sized for `text`. Afterwards no lowering is current
- * (gp_lower again). gp_set_fault_cost sets the value directly (0 < c < 1). */
-int gp_autotune(gp_driver* drv, const char* text, size_t len, int iters, double* best_cost, double* best_ms);
+/* Autotuner for stage 1. An observable column stays live over the whole
+ * circuit, so it is cut into boundary ranges swept by separate work items;
+ * the cut balances estimated item times in which a layer costs 1 and emitting
+ * a boundary 1 + fault_cost per fault there. The sweep runs one work-group of
+ * 1024 threads per item, or of 256 threads with smaller LDS tables (two per
+ * CU) when the circuit fits them. gp_autotune compiles `text` (gp_autotune_batch:
+ * the batch, as gp_lower_batch with the rates in the texts) with each of a few
+ * fault costs and each work-group size that fits, times `iters` device runs
+ * of each (HIP events on the driver's stream) and keeps the fastest pair for
+ * the following lowerings of this driver. Results are cached per process by
+ * the lowered shape (the key fields below): a shape already tuned is lowered
+ * once to read its key and not timed again (cached = 1). *out (may be NULL)
+ * receives the choice. The driver must be sized for the input. Afterwards no
+ * lowering is current (gp_lower again). gp_set_fault_cost sets the cut
+ * directly (0 < c < 1). Neither changes any signature or probability. */
+typedef struct gp_tuning {
+  double fault_cost; /* cost per fault of an observable range, relative to a layer */
+  int32_t sweep_block; /* stage-1 work-group size: 1024 or 256 */
+  int32_t cached;    /* 1: taken from the cache */
+  double ms;         /* mean device time per run when it was tuned */
+  /* the shape key: circuits, most qubits and layers of one circuit, faults,
+   * most detectors and observables of one circuit, correlation level */
+  uint32_t n_circuits, n_qubits, n_layers, n_det;
+  uint64_t n_faults;
+  uint32_t n_obs, level;
+} gp_tuning;
+int gp_autotune(gp_driver* drv, const char* text, size_t len, int iters, gp_tuning* out);
+int gp_autotune_batch(gp_driver* drv, const char* const* texts, const size_t* lens, size_t n, int iters,
+                      gp_tuning* out);
+/* The process-wide tuning cache, for saving and restoring it: the number of
+ * entries, entry i (in key order; GP_E_ARG past the end), and inserting or
+ * replacing an entry by its key (GP_E_ARG for a fault cost outside (0, 1), a
+ * work-group size other than 256 or 1024, or a level above 2). */
+size_t gp_tuning_cache_size(void);
+int gp_tuning_cache_get(size_t i, gp_tuning* out);
+int gp_tuning_cache_put(const gp_tuning* t);
 int gp_set_fault_cost(gp_driver* drv, double fault_cost);
 
 /* Correlation level (Table 1) for the following lowerings: which Paulis of

@@ -7,4 +7,4 @@ its binding. Build it with ``paper_2604_16613_amd._build.build()``.
 
 from . import _gp  # noqa: F401
 from ._gp import GpError, GpBounds, GpCircuitInfo  # noqa: F401
-from .api import Driver, Hypergraph, Server, get_driver  # noqa: F401
+from .api import Driver, Hypergraph, Server, get_driver, load_tuning, save_tuning  # noqa: F401

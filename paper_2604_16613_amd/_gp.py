@@ -34,7 +34,8 @@ EXPORTS = (
     "gp_edges_circuits", "gp_edges_circuit_ids", "gp_edges_circuit_shape", "gp_edges_circuit_dem_text",
     "gp_edges_circuit_offsets", "gp_server_create", "gp_server_submit", "gp_server_wait", "gp_server_stats",
     "gp_server_destroy", "gp_server_timing", "gp_debug_set_graph", "gp_autotune", "gp_set_fault_cost",
-    "gp_debug_set_sweep_shape",
+    "gp_debug_set_sweep_shape", "gp_autotune_batch", "gp_tuning_cache_size", "gp_tuning_cache_get",
+    "gp_tuning_cache_put",
 )
 
 
@@ -69,6 +70,19 @@ class GpCircuitInfo(ctypes.Structure):
         ("n_classes", ctypes.c_uint64), ("n_edges", ctypes.c_uint64), ("n_edge_bits", ctypes.c_uint64),
         ("n_live_words", ctypes.c_uint64), ("n_live_faults", ctypes.c_uint64),
         ("n_nonzero_words", ctypes.c_uint64), ("n_circuits", ctypes.c_uint32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class GpTuning(ctypes.Structure):
+    _fields_ = [
+        ("fault_cost", ctypes.c_double), ("sweep_block", ctypes.c_int32), ("cached", ctypes.c_int32),
+        ("ms", ctypes.c_double),
+        ("n_circuits", ctypes.c_uint32), ("n_qubits", ctypes.c_uint32), ("n_layers", ctypes.c_uint32),
+        ("n_det", ctypes.c_uint32), ("n_faults", ctypes.c_uint64),
+        ("n_obs", ctypes.c_uint32), ("level", ctypes.c_uint32),
     ]
 
     def as_dict(self):
@@ -125,8 +139,13 @@ def load():
         "gp_debug_set_sort_mode": ([_vp, ctypes.c_int], ctypes.c_int),
         "gp_debug_set_graph": ([_vp, ctypes.c_int], ctypes.c_int),
         "gp_debug_set_sweep_shape": ([_vp, ctypes.c_int], ctypes.c_int),
-        "gp_autotune": ([_vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
-                         ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "gp_autotune": ([_vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(GpTuning)],
+                        ctypes.c_int),
+        "gp_autotune_batch": ([_vp, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_size_t),
+                               ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(GpTuning)], ctypes.c_int),
+        "gp_tuning_cache_size": ([], ctypes.c_size_t),
+        "gp_tuning_cache_get": ([ctypes.c_size_t, ctypes.POINTER(GpTuning)], ctypes.c_int),
+        "gp_tuning_cache_put": ([ctypes.POINTER(GpTuning)], ctypes.c_int),
         "gp_set_fault_cost": ([_vp, ctypes.c_double], ctypes.c_int),
         "gp_refresh_rates": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t], ctypes.c_int),
         "gp_set_correlation_level": ([_vp, ctypes.c_int], ctypes.c_int),
@@ -410,12 +429,38 @@ def gp_debug_set_graph(drv: int, enable: bool) -> None:
     _check(load().gp_debug_set_graph(drv, int(enable)))
 
 
-def gp_autotune(drv: int, text: str, iters: int = 10) -> Tuple[float, float]:
-    """-> (chosen fault cost, its mean device time in ms)."""
+def gp_autotune(drv: int, text: str, iters: int = 10) -> dict:
+    """-> the chosen tuning (fault cost, sweep work-group, ms, cached, shape key)."""
     raw = text.encode()
-    c, ms = ctypes.c_double(), ctypes.c_double()
-    _check(load().gp_autotune(drv, raw, len(raw), iters, ctypes.byref(c), ctypes.byref(ms)))
-    return c.value, ms.value
+    t = GpTuning()
+    _check(load().gp_autotune(drv, raw, len(raw), iters, ctypes.byref(t)))
+    return t.as_dict()
+
+
+def gp_autotune_batch(drv: int, texts: Sequence[str], iters: int = 10) -> dict:
+    arr, lens, _keep = _texts(texts)
+    t = GpTuning()
+    _check(load().gp_autotune_batch(drv, arr, lens, len(texts), iters, ctypes.byref(t)))
+    return t.as_dict()
+
+
+def gp_tuning_cache() -> list:
+    """Every entry of the process-wide tuning cache, as dicts."""
+    lib = load()
+    out = []
+    for i in range(lib.gp_tuning_cache_size()):
+        t = GpTuning()
+        _check(lib.gp_tuning_cache_get(i, ctypes.byref(t)))
+        out.append(t.as_dict())
+    return out
+
+
+def gp_tuning_cache_put(entry: dict) -> None:
+    t = GpTuning()
+    for k, _ in GpTuning._fields_:
+        if k != "cached":
+            setattr(t, k, entry[k])
+    _check(load().gp_tuning_cache_put(ctypes.byref(t)))
 
 
 def gp_set_fault_cost(drv: int, fault_cost: float) -> None:

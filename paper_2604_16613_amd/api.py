@@ -145,10 +145,14 @@ class Driver:
         return _gp.gp_circuit_info_get(self.handle).as_dict()
 
     def autotune(self, circuit: str, iters: int = 10) -> Dict[str, float]:
-        """Measure the stage-1 work split for `circuit` and keep the fastest
-        for the following compiles (see gp_autotune)."""
-        c, ms = _gp.gp_autotune(self.handle, circuit, iters)
-        return {"fault_cost": c, "ms": ms}
+        """Time the stage-1 candidates (observable range cut, work-group size)
+        on `circuit` and keep the fastest for the following compiles; a shape
+        tuned before in this process comes from the cache (see gp_autotune)."""
+        return _gp.gp_autotune(self.handle, circuit, iters)
+
+    def autotune_batch(self, circuits: Sequence[str], iters: int = 10) -> Dict[str, float]:
+        """The same for a batch of circuits (see gp_autotune_batch)."""
+        return _gp.gp_autotune_batch(self.handle, list(circuits), iters)
 
     def set_correlation_level(self, level: int) -> None:
         """Table 1 level (0, 1 or 2 = every Pauli) for the following compiles."""
@@ -230,6 +234,29 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def save_tuning(path: str) -> int:
+    """Write the process-wide tuning cache to `path` as JSON (one entry per
+    lowered shape); returns the number of entries."""
+    import json
+    entries = _gp.gp_tuning_cache()
+    for e in entries:
+        e.pop("cached", None)
+    with open(path, "w") as fh:
+        json.dump({"gp_tuning": entries}, fh, indent=1)
+    return len(entries)
+
+
+def load_tuning(path: str) -> int:
+    """Insert the entries of a JSON file written by save_tuning into the
+    cache; returns how many were read."""
+    import json
+    with open(path) as fh:
+        entries = json.load(fh)["gp_tuning"]
+    for e in entries:
+        _gp.gp_tuning_cache_put(e)
+    return len(entries)
 
 
 def get_driver(max_circuit: str, device: int = 0) -> Driver:

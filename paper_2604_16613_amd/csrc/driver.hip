@@ -8,8 +8,12 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <iterator>
+#include <map>
+#include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "driver_internal.h"
@@ -692,53 +696,143 @@ int gp_set_fault_cost(gp_driver* d, double fault_cost) {
   return GP_OK;
 }
 
-int gp_autotune(gp_driver* d, const char* text, size_t len, int iters, double* best_cost, double* best_ms) {
-  if (!d || !text) return fail(GP_E_ARG, "null argument");
+}  // extern "C"
+
+namespace {
+
+// Tuned parameters by lowered shape, shared by every driver of the process.
+std::mutex g_tune_mu;
+std::map<std::tuple<uint32_t, uint32_t, uint32_t, uint64_t, uint32_t, uint32_t, uint32_t>, gp_tuning> g_tune;
+
+std::tuple<uint32_t, uint32_t, uint32_t, uint64_t, uint32_t, uint32_t, uint32_t> tune_key(const gp_tuning& t) {
+  return {t.n_circuits, t.n_qubits, t.n_layers, t.n_faults, t.n_det, t.n_obs, t.level};
+}
+
+void shape_of(const gp::Lowered& lw, gp_tuning& t) {
+  t.n_circuits = uint32_t(lw.branches.size());
+  t.n_qubits = lw.n_qubits;
+  t.n_layers = lw.n_layers;
+  t.n_faults = lw.n_faults;
+  t.n_det = lw.n_det;
+  t.n_obs = lw.n_obs;
+  t.level = lw.level;
+}
+
+// Times every (fault cost, sweep work-group) candidate on what `lower`
+// lowers and keeps the fastest; a shape already in the cache is taken from it.
+template <typename Lower>
+int autotune(gp_driver* d, Lower&& lower, int iters, gp_tuning* out) {
   if (iters < 1) return fail(GP_E_ARG, "iters must be at least 1");
   static const double kCandidates[] = {2.5e-4, 4.0e-4, 6.2e-4, 9.0e-4, 1.4e-3};
   HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
-  hipEvent_t a = nullptr, b = nullptr;
-  HIP_TRY(hipEventCreate(&a), "hipEventCreate");
-  if (hipEventCreate(&b) != hipSuccess) {
+  const double saved_cost = d->fault_cost;
+  const uint32_t saved_shape = d->sweep_shape;
+  gp_tuning best{};
+  int rc = lower();
+  if (rc) return rc;
+  shape_of(d->lw, best);
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(tune_key(best));
+    if (it != g_tune.end()) {
+      best = it->second;
+      best.cached = 1;
+    }
+  }
+  if (!best.cached) {
+    hipEvent_t a = nullptr, b = nullptr;
+    HIP_TRY(hipEventCreate(&a), "hipEventCreate");
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return hip_fail(hipGetLastError(), "hipEventCreate");
+    }
+    // the 256-thread work-group is a candidate when the circuit fits its tables
+    const int n_blocks = gp::sweep_small_fits(d->st) ? 2 : 1;
+    best.ms = -1.0;
+    for (int blk = 0; blk < n_blocks && rc == GP_OK; blk++) {
+      for (double c : kCandidates) {
+        d->fault_cost = c;
+        d->sweep_shape = blk == 0 ? 1u : 2u;
+        if ((rc = lower()) || (rc = gp_run(d))) break;
+        float ms = 0.f;
+        if (hipEventRecord(a, d->stream) != hipSuccess) {
+          rc = hip_fail(hipGetLastError(), "hipEventRecord");
+          break;
+        }
+        for (int k = 0; k < iters && rc == GP_OK; k++) rc = gp_run(d);
+        if (rc) break;
+        if (hipEventRecord(b, d->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+            hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+          rc = hip_fail(hipGetLastError(), "timing the candidates");
+          break;
+        }
+        const double per = double(ms) / iters;
+        if (best.ms < 0 || per < best.ms) {
+          best.ms = per;
+          best.fault_cost = c;
+          best.sweep_block = blk == 0 ? 1024 : 256;
+        }
+      }
+    }
     (void)hipEventDestroy(a);
-    return hip_fail(hipGetLastError(), "hipEventCreate");
+    (void)hipEventDestroy(b);
   }
-  const double saved = d->fault_cost;
-  double bc = saved, bms = -1.0;
-  int rc = GP_OK;
-  for (double c : kCandidates) {
-    d->fault_cost = c;
-    if ((rc = gp_lower(d, text, len, nullptr, 0)) || (rc = gp_run(d))) break;
-    float ms = 0.f;
-    if (hipEventRecord(a, d->stream) != hipSuccess) {
-      rc = hip_fail(hipGetLastError(), "hipEventRecord");
-      break;
-    }
-    for (int k = 0; k < iters && rc == GP_OK; k++) rc = gp_run(d);
-    if (rc) break;
-    if (hipEventRecord(b, d->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
-        hipEventElapsedTime(&ms, a, b) != hipSuccess) {
-      rc = hip_fail(hipGetLastError(), "timing the candidates");
-      break;
-    }
-    const double per = double(ms) / iters;
-    if (bms < 0 || per < bms) {
-      bms = per;
-      bc = c;
-    }
-  }
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
   d->lowered = false;  // the tables hold the last candidate's lowering
   d->ran = false;
   d->structured = false;
   if (rc) {
-    d->fault_cost = saved;
+    d->fault_cost = saved_cost;
+    d->sweep_shape = saved_shape;
     return rc;
   }
-  d->fault_cost = bc;
-  if (best_cost) *best_cost = bc;
-  if (best_ms) *best_ms = bms;
+  d->fault_cost = best.fault_cost;
+  d->sweep_shape = best.sweep_block == 256 ? 2u : 1u;
+  if (!best.cached) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[tune_key(best)] = best;
+  }
+  if (out) *out = best;
+  return GP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gp_autotune(gp_driver* d, const char* text, size_t len, int iters, gp_tuning* out) {
+  if (!d || !text) return fail(GP_E_ARG, "null argument");
+  return autotune(d, [&]() { return gp_lower(d, text, len, nullptr, 0); }, iters, out);
+}
+
+int gp_autotune_batch(gp_driver* d, const char* const* texts, const size_t* lens, size_t n, int iters,
+                      gp_tuning* out) {
+  if (!d || !texts || !lens) return fail(GP_E_ARG, "null argument");
+  return autotune(d, [&]() { return gp_lower_batch(d, texts, lens, nullptr, nullptr, n); }, iters, out);
+}
+
+size_t gp_tuning_cache_size(void) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  return g_tune.size();
+}
+
+int gp_tuning_cache_get(size_t i, gp_tuning* out) {
+  if (!out) return fail(GP_E_ARG, "null argument");
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  if (i >= g_tune.size()) return fail(GP_E_ARG, "cache index out of range");
+  auto it = g_tune.begin();
+  std::advance(it, i);
+  *out = it->second;
+  out->cached = 1;
+  return GP_OK;
+}
+
+int gp_tuning_cache_put(const gp_tuning* t) {
+  if (!t) return fail(GP_E_ARG, "null argument");
+  if (!(t->fault_cost > 0.0 && t->fault_cost < 1.0)) return fail(GP_E_ARG, "fault cost must lie in (0, 1)");
+  if (t->sweep_block != 256 && t->sweep_block != 1024) return fail(GP_E_ARG, "sweep work-group must be 256 or 1024");
+  if (t->level > 2) return fail(GP_E_ARG, "correlation level must be 0, 1 or 2");
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune[tune_key(*t)] = *t;
   return GP_OK;
 }
 

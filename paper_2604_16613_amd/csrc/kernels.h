@@ -184,6 +184,8 @@ hipError_t enqueue_rates_gradient(const DevState& st, uint32_t n_edges, hipStrea
 
 // Dynamic LDS the sweep needs for n qubits, and the largest it may use.
 size_t sweep_lds_bytes(uint32_t n_qubits);
+// the 256-thread stage-1 work-group holds this compile's tables
+bool sweep_small_fits(const DevState& st);
 // Dynamic LDS the hash needs for w signature words.
 size_t hash_lds_bytes(uint32_t w);
 // Whether the bucket grouping's LDS fits this device (set by configure_kernels).

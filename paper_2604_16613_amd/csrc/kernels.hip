@@ -1792,7 +1792,7 @@ size_t sweep_lds_bytes(uint32_t n_qubits) { return sweep_lds_shape<1024>(n_qubit
 // The small shape is used when there are enough items to give each CU
 // several, its tables hold the circuit and two of its work-groups fit in one
 // CU's LDS.
-static bool small_sweep_fits(const DevState& st) {
+bool sweep_small_fits(const DevState& st) {
   using S = SweepShape<256>;
   return st.n_layers + 2 <= uint32_t(S::kLofs) && st.n_win <= uint32_t(S::kWinTab) &&
          st.max_win_ops <= uint32_t(S::kWin) &&
@@ -1873,8 +1873,8 @@ hipError_t enqueue_compile(DevState& st_io, hipStream_t stream, const LaunchHook
   }
   if (st.n_items) {
     // the small shape for many items of small circuits (several per CU)
-    const bool small = st.sweep_shape == 2 || (st.sweep_shape == 0 && st.n_items >= 512 && small_sweep_fits(st));
-    if (small && small_sweep_fits(st)) {
+    const bool small = st.sweep_shape == 2 || (st.sweep_shape == 0 && st.n_items >= 512 && sweep_small_fits(st));
+    if (small && sweep_small_fits(st)) {
       GP_LAUNCH(K_SWEEP, k_sweep<true, 256><<<st.n_items, 256, sweep_lds_shape<256>(st.n_qubits), stream>>>(st));
     } else if (st.n_layers + 2 <= uint32_t(kLofsMax) && st.n_win <= uint32_t(kWinTableLds)) {
       GP_LAUNCH(K_SWEEP,

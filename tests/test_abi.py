@@ -1,12 +1,13 @@
 """C-ABI library checks that need no GPU: every symbol include/gp.h declares is
 exported, host-only entry points work, errors come back as documented codes."""
 
+import ctypes
 import os
 import re
 
 import pytest
 
-from paper_2604_16613_amd import _gp
+from paper_2604_16613_amd import GpError, _gp
 from workloads import bivariate_bicycle_memory, rotated_surface_code_memory
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -105,3 +106,28 @@ def test_server_without_a_device_fails_cleanly():
     with pytest.raises(_gp.GpError) as e:
         _gp.gp_server_create(b, 0)
     assert e.value.code == -7
+
+
+def test_tuning_cache_round_trip(tmp_path):
+    """The tuning cache needs no device: entries are inserted by shape key,
+    replaced on the same key, checked, and saved to / read from JSON."""
+    from paper_2604_16613_amd import load_tuning, save_tuning
+    key = dict(n_circuits=3, n_qubits=1000003, n_layers=7, n_det=11, n_faults=123456789, n_obs=2, level=1)
+    _gp.gp_tuning_cache_put(dict(key, fault_cost=4e-4, sweep_block=256, ms=1.5))
+    _gp.gp_tuning_cache_put(dict(key, fault_cost=9e-4, sweep_block=1024, ms=1.25))
+    mine = [e for e in _gp.gp_tuning_cache() if e["n_qubits"] == 1000003]
+    assert len(mine) == 1
+    assert (mine[0]["fault_cost"], mine[0]["sweep_block"], mine[0]["ms"], mine[0]["cached"]) == (9e-4, 1024, 1.25, 1)
+    for bad in (dict(fault_cost=0.0), dict(fault_cost=1.0), dict(sweep_block=512), dict(level=3)):
+        with pytest.raises(GpError) as e:
+            _gp.gp_tuning_cache_put({**key, "fault_cost": 4e-4, "sweep_block": 256, "ms": 1.0, **bad})
+        assert e.value.code == -1
+    path = str(tmp_path / "tuning.json")
+    n = save_tuning(path)
+    assert n == len(_gp.gp_tuning_cache())
+    _gp.gp_tuning_cache_put(dict(key, fault_cost=2.5e-4, sweep_block=256, ms=9.0))
+    assert load_tuning(path) == n
+    mine = [e for e in _gp.gp_tuning_cache() if e["n_qubits"] == 1000003]
+    assert (mine[0]["fault_cost"], mine[0]["sweep_block"]) == (9e-4, 1024)
+    t = _gp.GpTuning()
+    assert _gp.load().gp_tuning_cache_get(10**9, ctypes.byref(t)) == -1

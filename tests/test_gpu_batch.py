@@ -287,3 +287,20 @@ def test_small_shape_with_long_injection_lists():
     for k in range(len(texts)):
         assert_same(small[k], big[k], f"d10 branch {k} small vs big", exact=True)
     assert_same(small[5], oracle.run(texts[5]), "d10 branch 5 vs oracle")
+
+
+def test_batch_autotune_keeps_results():
+    """Batch tuning over the work-group sizes and range cuts: the choice is one
+    of the candidates, compiles after it match the oracle, and a second call
+    comes from the cache."""
+    from workloads import iceberg_surface_batch
+    texts = [c.text for c in iceberg_surface_batch(3, n_branches=48, seed=11)]
+    say("case batch autotune")
+    with Driver.from_batch(texts) as drv:
+        res = drv.autotune_batch(texts, iters=2)
+        assert res["sweep_block"] in (256, 1024) and res["ms"] > 0 and res["n_circuits"] == 48
+        got = drv.compile_batch(texts)
+        for k in (0, 17, 47):
+            assert_same(got[k], oracle.run(texts[k]), f"branch {k} after batch tuning")
+        again = drv.autotune_batch(texts, iters=2)
+        assert again["cached"] == 1 and again["sweep_block"] == res["sweep_block"]

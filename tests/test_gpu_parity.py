@@ -324,16 +324,23 @@ def test_graph_replays_match_eager_launches(drv25):
 
 
 def test_autotune_keeps_results(drv25):
-    """The autotuner picks one of its fault costs and the compiles after it
-    still match the oracle."""
+    """The autotuner picks one of its candidates, the compiles after it still
+    match the oracle, and the same shape tuned again comes from the cache."""
     say("case autotune")
     c = rotated_surface_code_memory(11, 11)
     try:
         res = drv25.autotune(c.text, iters=3)
         assert res["fault_cost"] in (2.5e-4, 4.0e-4, 6.2e-4, 9.0e-4, 1.4e-3) and res["ms"] > 0
+        assert res["sweep_block"] in (256, 1024)
+        assert (res["n_circuits"], res["n_qubits"], res["level"]) == (1, 241, 2)
         with pytest.raises(GpError):
             drv25.run()  # no lowering is current after tuning
         check(drv25, c.text, label="after autotune")
         check(drv25, bivariate_bicycle_memory().text, label="bb after autotune")
+        again = drv25.autotune(c.text, iters=3)
+        assert again["cached"] == 1 and again["fault_cost"] == res["fault_cost"]
+        assert again["sweep_block"] == res["sweep_block"] and again["ms"] == res["ms"]
+        check(drv25, c.text, label="after cached tuning")
     finally:
         _gp.gp_set_fault_cost(drv25.handle, 6.2e-4)
+        _gp.gp_debug_set_sweep_shape(drv25.handle, 0)
