@@ -289,12 +289,15 @@ int gp_debug_set_key_bits(gp_driver* drv, int bits);
 uint64_t gp_debug_collision_retries(const gp_driver* drv);
 
 /* Test hook: stage-2 grouping method for later gp_run calls. 0 (default):
- * where the circuit allows it, one stable radix pass on the top 8-bit key
- * digit splits the faults into 256 buckets and each bucket is sorted and
- * merged in LDS (a bucket over its LDS capacity makes gp_fetch redo the
- * grouping with the full sort); 1: always the full LSD radix sort over every
- * key digit. Both give the same hyperedges (same classes, same merge order
- * within a class; the edge order may differ). GP_E_ARG for other values. */
+ * up to 1,572,864 faults one stable radix pass on the top 8-bit key digit
+ * splits the faults into 256 buckets, and from 12,000,000 to 67,108,864 faults
+ * two passes on the top two digits split them into 65,536 buckets; each bucket
+ * is sorted and merged in LDS (a bucket over its LDS capacity makes gp_fetch
+ * redo the grouping with the full sort); otherwise the full LSD radix sort
+ * over every key digit. 1: always the full sort. 2: the 65,536 buckets whenever
+ * the key has at least three digits. All give the same hyperedges (same
+ * classes, same merge order within a class; the edge order may differ).
+ * GP_E_ARG for other values. */
 int gp_debug_set_sort_mode(gp_driver* drv, int mode);
 
 /* Test hook: stage-1 work-group shape for later gp_run calls. 0 (default):

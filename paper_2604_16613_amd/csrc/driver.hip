@@ -461,6 +461,11 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   if ((rc = dev_alloc(d, &st.segstart, F, "class starts"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.big, F / 64 + 1, "large classes"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.bkt, 2 * size_t(gp::kBuckets + 1), "bucket counts"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.b16_lo, size_t(gp::kBuckets16), "16-bit bucket starts")) ||
+      (rc = dev_alloc(d, &st.b16_hi, size_t(gp::kBuckets16), "16-bit bucket ends")) ||
+      (rc = dev_alloc(d, &st.b16_cls, size_t(gp::kBuckets16) + 1, "16-bit bucket classes")) ||
+      (rc = dev_alloc(d, &st.b16_bits, size_t(gp::kBuckets16) + 1, "16-bit bucket bits")))
+    return cleanup(rc);
   if ((rc = dev_alloc(d, &st.seg_first, F, "class member offsets"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.seg_mem, F, "class member counts"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.e_first, F, "hyperedge member offsets"))) return cleanup(rc);
@@ -1156,7 +1161,8 @@ int gp_set_correlation_level(gp_driver* d, int level) {
 
 int gp_debug_set_sort_mode(gp_driver* d, int mode) {
   if (!d) return fail(GP_E_ARG, "null driver");
-  if (mode != int(gp::SORT_AUTO) && mode != int(gp::SORT_FULL)) return fail(GP_E_ARG, "sort mode must be 0 or 1");
+  if (mode != int(gp::SORT_AUTO) && mode != int(gp::SORT_FULL) && mode != int(gp::SORT_BUCKET16))
+    return fail(GP_E_ARG, "sort mode must be 0, 1 or 2");
   d->sort_mode = uint32_t(mode);
   return GP_OK;
 }

@@ -31,14 +31,24 @@ enum : uint32_t {
   FLAG_BUCKET = 16u,    // a bucket of the bucket grouping exceeded its LDS capacity (redo with the full sort)
 };
 
-// Stage-2 grouping: 0 = buckets (one stable pass on the top key digit, then
-// every bucket sorted and merged in LDS) where they apply, else the full
-// radix sort; 1 = always the full radix sort.
-enum : uint32_t { SORT_AUTO = 0, SORT_FULL = 1 };
+// Stage-2 grouping: 0 = buckets where they pay (up to kBucketMaxFaults: one
+// stable pass on the top key digit, then every bucket sorted and merged in
+// LDS; from kBucket16MinFaults to kBucket16MaxFaults: two stable passes on the
+// top two digits, then every 16-bit bucket in LDS), else the full radix sort;
+// 1 = always the full radix sort; 2 = the 16-bit buckets wherever the key has
+// the digits.
+enum : uint32_t { SORT_AUTO = 0, SORT_FULL = 1, SORT_BUCKET16 = 2 };
 constexpr uint32_t kBuckets = 256;         // buckets = values of the top 8-bit digit
 constexpr uint32_t kBucketCap = 8192;      // faults one bucket sorts in LDS
 // bucket grouping is used up to this many faults (mean bucket <= 6144)
 constexpr uint64_t kBucketMaxFaults = uint64_t(kBuckets) * 6144;
+constexpr uint32_t kBuckets16 = 65536;     // buckets = values of the top two digits
+constexpr uint32_t kBucket16Cap = 2048;    // faults one 16-bit bucket sorts in LDS
+// 16-bit buckets are used from kBucket16MinFaults (mean bucket >= 183;
+// below it a work-group's fixed cost per bucket makes the full sort faster)
+// up to kBucket16MaxFaults (mean bucket <= 1024)
+constexpr uint64_t kBucket16MinFaults = 12000000;
+constexpr uint64_t kBucket16MaxFaults = uint64_t(kBuckets16) * 1024;
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr int kTile = 4096;       // items per tile in the sort, scan and compaction kernels
@@ -126,9 +136,14 @@ struct DevState {
   uint32_t* lookback;    // per pass, tile and digit: published count with status bits
   uint32_t* tile_ctr;    // per pass: tile ticket counter
   uint32_t* tile_sum;    // scan tile sums
-  uint32_t* segstart;    // first sorted index of each class
+  uint32_t* segstart;    // first sorted index of each class (16-bit buckets: class slot of each hyperedge)
   uint32_t* big;         // classes too large for one thread
   uint32_t* bkt;         // per bucket: classes, then signature bits (kBuckets + 1 each)
+  uint32_t* b16_lo;      // 16-bit buckets: first and end sorted index (cleared per compile), classes
+  uint32_t* b16_hi;      // and signature bits per bucket (then their exclusive prefixes; kBuckets16 + 1 each)
+  uint32_t* b16_cls;
+  uint32_t* b16_bits;
+  uint32_t use_b16;      // this compile groups with 16-bit buckets (k_prepare clears their ranges)
   // the class structure a compile leaves for rate refreshes and the adjoint:
   uint32_t* ord;         // fault positions, classes contiguous, members in position order (set by enqueue_compile)
   uint32_t* seg_first;   // per class slot (bucket grouping): first index into ord, member count
@@ -140,7 +155,7 @@ struct DevState {
   double* gr;            // per channel (lowered order): dL/d(rate) (adjoint output)
   double* seg_q;         // merged probability per class
   uint32_t* seg_rep;     // representative fault position per class
-  uint32_t* seg_cnt;     // signature bits per class
+  uint32_t* seg_cnt;     // signature bits per class (16-bit buckets: first output bit of each hyperedge)
   uint32_t* seg_off;     // exclusive prefix of seg_cnt
   uint32_t* edge_off32;  // per hyperedge: first bit (n_edges + 1)
   uint32_t* edge_bits;   // output signature bits (external numbering)
@@ -154,7 +169,8 @@ struct DevState {
 // Names of the kernels (for timing tables).
 enum KernelId : int {
   K_PREPARE = 0, K_SWEEP, K_HASH, K_SCAN_SINGLE, K_COMPACT, K_ONESWEEP, K_HEADS_COUNT, K_HEADS_APPLY, K_REDUCE,
-  K_REDUCE_BIG, K_SCAN_TILES, K_SCAN_APPLY, K_EDGE_WRITE, K_BUCKET, K_COUNT
+  K_REDUCE_BIG, K_SCAN_TILES, K_SCAN_APPLY, K_EDGE_WRITE, K_BUCKET, K_BUCKET_BOUNDS, K_BUCKET_SCAN, K_SLOT_MAP,
+  K_COUNT
 };
 const char* kernel_name(int id);
 

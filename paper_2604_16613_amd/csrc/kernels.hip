@@ -218,6 +218,11 @@ __global__ __launch_bounds__(kBlock) void k_prepare(DevState st) {
     st.lookback[size_t(i / per_pass) * st.max_tiles * 256 + i % per_pass] = 0;
   if (gid < kMaxPasses) st.tile_ctr[gid] = 0;
   for (uint32_t i = gid; i < st.n_pass * 256; i += stride) st.digit_tot[i] = 0;
+  if (st.use_b16)
+    for (uint32_t i = gid; i < kBuckets16; i += stride) {
+      st.b16_lo[i] = 0;
+      st.b16_hi[i] = 0;
+    }
   if (gid == 0) {
     st.hdr->n_seg = 0;
     st.hdr->empty_seg = kNone;
@@ -1215,52 +1220,61 @@ constexpr int kBucketBlock = 1024;
 constexpr int kBucketWaves = kBucketBlock / 64;
 constexpr uint32_t kBucketSortBits = 24;  // key bits a bucket sorts in LDS; longer runs of equal bits are rare
 
-// Grouping inside one bucket: the live faults whose key has top digit d,
-// which the stable partition pass left in position order at
-// [bkt_start, bkt_start + m). Values (key bits below the top digit << 16 |
+// Grouping inside one bucket: the live faults whose key has top digit d
+// (k16: top two digits), which the stable partition passes left in position
+// order at [bkt_start, bkt_start + m). Values (key bits below the top digit << 16 |
 // index in the bucket) are sorted in LDS by stable 8-bit LSD passes over the
 // key bits, so each class is a run of equal key bits whose members are in
 // position order. Per class: Eq. 3 merge in that order (one thread, or the
 // whole block for classes of more than kBigSegment faults), the check-hash
 // comparison, the representative (first member), its bit count and the
 // class's bit offset within the bucket. Class c of the bucket is stored at
-// slot bkt_start + c; k_bucket_scan turns the per-bucket counts into offsets.
-__global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint64_t* __restrict__ keys,
-                                                         const uint32_t* __restrict__ vals) {
-  extern __shared__ __align__(16) uint64_t s_buf[];  // two buffers of kBucketCap values
-  __shared__ uint32_t s_cnt[kBucketWaves][256];
-  __shared__ uint32_t s_wave[kBucketWaves + 1];
-  __shared__ uint32_t s_big[2 * (kBucketCap / (kBigSegment + 1) + 1)];  // (class, first sorted index)
-  __shared__ uint64_t s_hb[kBucketCap / 64];                            // class heads, one bit per value
-  __shared__ uint64_t s_rb[kBucketCap / 64];                            // starts of runs of equal sorted bits
-  __shared__ uint64_t s_mb[kBucketCap / 64];                            // run members whose key differs
+// slot bkt_start + c; its members (positions) go to mem in class order. The
+// bucket's class and bit counts go to b_cls[d] and b_bits[d]. One work-group
+// of kBlk threads per bucket of at most kCap faults.
+template <int kBlk, int kCap, bool k16>
+__global__ __launch_bounds__(kBlk) void k_bucket(DevState st, const uint64_t* __restrict__ keys,
+                                                 const uint32_t* __restrict__ vals, uint32_t* __restrict__ mem,
+                                                 uint32_t* __restrict__ b_cls, uint32_t* __restrict__ b_bits) {
+  constexpr int kWaves = kBlk / 64;
+  constexpr int kPer = kCap / kBlk;  // sorted values per thread
+  static_assert(kBlk % 256 == 0 && kCap % kBlk == 0 && kPer <= 32, "bucket shape");
+  extern __shared__ __align__(16) uint64_t s_buf[];  // two buffers of kCap values
+  __shared__ uint32_t s_cnt[kWaves][256];
+  __shared__ uint32_t s_wave[kWaves + 1];
+  __shared__ uint32_t s_big[2 * (kCap / (kBigSegment + 1) + 1)];  // (class, first sorted index)
+  __shared__ uint64_t s_hb[kCap / 64];                            // class heads, one bit per value
+  __shared__ uint64_t s_rb[kCap / 64];                            // starts of runs of equal sorted bits
+  __shared__ uint64_t s_mb[kCap / 64];                            // run members whose key differs
   __shared__ int s_bad_bucket;
   __shared__ uint32_t s_nbig;
   __shared__ uint32_t s_big_end;
   __shared__ uint32_t s_start;
-  __shared__ double s_q[kBucketBlock];
+  __shared__ double s_q[kBlk];
   __shared__ int s_bad;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const uint32_t d = blockIdx.x;
   const uint32_t msd = st.n_pass - 1;
   const uint32_t* tot = st.digit_tot + msd * 256;
-  uint32_t* b_cls = st.bkt;                  // per bucket: classes (then offsets)
-  uint32_t* b_bits = st.bkt + (kBuckets + 1);  // per bucket: signature bits (then offsets)
   {
-    const uint32_t v = tid < int(kBuckets) ? tot[tid] : 0u;
-    const uint32_t ex = block_exclusive_scan<kBucketBlock>(v, s_wave);
-    if (uint32_t(tid) == d) s_start = ex;
+    if (k16) {
+      if (tid == 0) s_start = st.b16_lo[d];
+    } else {
+      const uint32_t v = tid < int(kBuckets) ? tot[tid] : 0u;
+      const uint32_t ex = block_exclusive_scan<kBlk>(v, s_wave);
+      if (uint32_t(tid) == d) s_start = ex;
+    }
     if (tid == 0) {
       s_nbig = 0;
       s_bad = 0;
       s_bad_bucket = 0;
     }
-    for (uint32_t k = tid; k < kBucketCap / 64; k += kBucketBlock) s_hb[k] = 0;
+    for (uint32_t k = tid; k < kCap / 64; k += kBlk) s_hb[k] = 0;
   }
   __syncthreads();
   const uint32_t start = s_start;
-  const uint32_t m = tot[d];
-  if (m == 0 || m > kBucketCap) {
+  const uint32_t m = k16 ? st.b16_hi[d] - start : tot[d];
+  if (m == 0 || m > kCap) {
     if (tid == 0) {
       b_cls[d] = 0;
       b_bits[d] = 0;
@@ -1268,25 +1282,26 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
     }
     return;
   }
-  const uint32_t lbits = 8 * msd;  // key bits below the top digit (at most 48)
+  const uint32_t top = k16 ? 2u : 1u;  // digits that chose the bucket
+  const uint32_t lbits = 8 * (msd + 1 - top);  // key bits below them (at most 48)
   const uint64_t lmask = (1ull << lbits) - 1;
   uint64_t* a = s_buf;
-  uint64_t* b = s_buf + kBucketCap;
-  for (uint32_t i = tid; i < m; i += kBucketBlock) a[i] = ((keys[start + i] & lmask) << 16) | i;
+  uint64_t* b = s_buf + kCap;
+  for (uint32_t i = tid; i < m; i += kBlk) a[i] = ((keys[start + i] & lmask) << 16) | i;
   // wave wv owns the contiguous values [wv*chunk, (wv+1)*chunk), 64 per round
-  const uint32_t rounds = (m + kBucketBlock - 1) / kBucketBlock;
+  const uint32_t rounds = (m + kBlk - 1) / kBlk;
   const uint32_t chunk = rounds * 64;
   const uint64_t lt = (1ull << lane) - 1;
   // stable LSD passes over the lowest kBucketSortBits key bits (fewer when
   // the key has fewer); equal keys then sit in runs of equal sorted bits
-  const uint32_t npass = min(msd, kBucketSortBits / 8);
+  const uint32_t npass = min(msd + 1 - top, kBucketSortBits / 8);
   for (uint32_t pass = 0; pass < npass; ++pass) {
     const uint32_t sh = 16 + 8 * pass;
-    for (int k = tid; k < kBucketWaves * 256; k += kBucketBlock) (&s_cnt[0][0])[k] = 0;
+    for (int k = tid; k < kWaves * 256; k += kBlk) (&s_cnt[0][0])[k] = 0;
     __syncthreads();
-    uint64_t val[kBucketCap / kBucketBlock], pe[kBucketCap / kBucketBlock];
+    uint64_t val[kPer], pe[kPer];
 #pragma unroll
-    for (int r = 0; r < int(kBucketCap / kBucketBlock); ++r) {
+    for (int r = 0; r < int(kPer); ++r) {
       if (uint32_t(r) < rounds) {
         const uint32_t i = wv * chunk + r * 64 + lane;
         const bool valid = i < m;
@@ -1298,8 +1313,10 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
     }
     __syncthreads();
     {
-      // exclusive scan in (digit, wave) order: thread t owns digit t/4, waves 4(t%4)..4(t%4)+3
-      const uint32_t dg = tid >> 2, w0 = (tid & 3) * 4;
+      // exclusive scan in (digit, wave) order: thread t owns digit t/T and
+      // waves 4(t%T)..4(t%T)+3, with T = kBlk/256 threads per digit
+      constexpr int kTpd = kBlk / 256;
+      const uint32_t dg = tid / kTpd, w0 = (tid % kTpd) * 4;
       uint32_t c[4], sum = 0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -1307,7 +1324,7 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
         sum += c[j];
       }
       uint32_t total;
-      uint32_t run = block_scan_1sync<kBucketBlock>(sum, s_wave, total);
+      uint32_t run = block_scan_1sync<kBlk>(sum, s_wave, total);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         s_cnt[w0 + j][dg] = run;
@@ -1316,7 +1333,7 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < int(kBucketCap / kBucketBlock); ++r) {
+    for (int r = 0; r < int(kPer); ++r) {
       if (uint32_t(r) < rounds) {
         const uint32_t i = wv * chunk + r * 64 + lane;
         const bool valid = i < m;
@@ -1341,7 +1358,7 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
     // run starts and mixed elements (key bits differ from the previous
     // value's inside a run) as bitmasks, read-only while runs are sorted
     const uint64_t smask = (1ull << (16 + 8 * npass)) - 1;
-    for (uint32_t k = tid; k < kBucketCap / 64; k += kBucketBlock) {
+    for (uint32_t k = tid; k < kCap / 64; k += kBlk) {
       s_rb[k] = 0;
       s_mb[k] = 0;
     }
@@ -1402,13 +1419,13 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
   // (first of a run of equal key bits) go to an LDS bitmask, and their
   // probability and check hash are gathered at once (independent loads)
   // into the two sort buffers, now free: p over a, check hash over b.
-  const uint32_t per = rounds;  // at most kBucketCap / kBucketBlock
+  const uint32_t per = rounds;  // at most kPer
   const uint32_t j0 = tid * per;
   uint32_t hmask = 0;
-  uint32_t pos[kBucketCap / kBucketBlock];
-  uint32_t idx[kBucketCap / kBucketBlock];  // index within the bucket (the pair's slot)
+  uint32_t pos[kPer];
+  uint32_t idx[kPer];  // index within the bucket (the pair's slot)
 #pragma unroll
-  for (int k = 0; k < int(kBucketCap / kBucketBlock); ++k) {
+  for (int k = 0; k < int(kPer); ++k) {
     const uint32_t j = j0 + k;
     pos[k] = 0;
     idx[k] = 0;
@@ -1426,20 +1443,20 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
   }
   // each pair's record was moved into the bucket's range by the partition
   // pass: read within the bucket instead of gathered across all faults
-  FaultRec rec[kBucketCap / kBucketBlock];
+  FaultRec rec[kPer];
 #pragma unroll
-  for (int k = 0; k < int(kBucketCap / kBucketBlock); ++k)
+  for (int k = 0; k < int(kPer); ++k)
     if (uint32_t(k) < per && j0 + k < m) {
       rec[k] = st.crp[start + idx[k]];
-      st.val[0][start + j0 + k] = pos[k];  // the class members, kept for refreshes and the adjoint
+      mem[start + j0 + k] = pos[k];  // the class members, kept for refreshes and the adjoint
     }
   const uint32_t nh = uint32_t(__popc(hmask));
-  uint32_t c = block_exclusive_scan<kBucketBlock>(nh, s_wave);  // barrier: every a[j] has been read
-  const uint32_t ncls = s_wave[kBucketWaves];
+  uint32_t c = block_exclusive_scan<kBlk>(nh, s_wave);  // barrier: every a[j] has been read
+  const uint32_t ncls = s_wave[kWaves];
   double* sp = reinterpret_cast<double*>(a);
   uint64_t* sc = b;
 #pragma unroll
-  for (int k = 0; k < int(kBucketCap / kBucketBlock); ++k)
+  for (int k = 0; k < int(kPer); ++k)
     if (uint32_t(k) < per && j0 + k < m) {
       sp[j0 + k] = rec[k].p;
       sc[j0 + k] = rec[k].chk;
@@ -1449,9 +1466,9 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
   // classes whose head this thread owns, in order: Eq. 3 over the members
   // in position order (runs longer than kBigSegment go to the block below)
   uint32_t nbits = 0;
-  uint32_t cbits[kBucketCap / kBucketBlock];
+  uint32_t cbits[kPer];
 #pragma unroll
-  for (int k = 0; k < int(kBucketCap / kBucketBlock); ++k) {
+  for (int k = 0; k < int(kPer); ++k) {
     cbits[k] = 0;
     if (!((hmask >> k) & 1u)) continue;
     const uint32_t j = j0 + k;
@@ -1480,11 +1497,11 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
     }
   }
   // bit offsets of the classes within the bucket (class order = thread order)
-  uint32_t o = block_exclusive_scan<kBucketBlock>(nbits, s_wave);
+  uint32_t o = block_exclusive_scan<kBlk>(nbits, s_wave);
   {
     uint32_t k2 = 0;
 #pragma unroll
-    for (int k = 0; k < int(kBucketCap / kBucketBlock); ++k)
+    for (int k = 0; k < int(kPer); ++k)
       if ((hmask >> k) & 1u) {
         st.seg_off[start + c + k2] = o;
         o += cbits[k];
@@ -1506,14 +1523,14 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
     const uint64_t c0 = sc[j];
     bool bad = false;
     double q = 0.0;
-    for (uint32_t i = j + tid; i < e; i += kBucketBlock) {
+    for (uint32_t i = j + tid; i < e; i += kBlk) {
       bad |= sc[i] != c0;
       q = fma(sp[i], 1.0 - 2.0 * q, q);
     }
     if (bad) s_bad = 1;
     s_q[tid] = q;
     __syncthreads();
-    for (int h = kBucketBlock / 2; h > 0; h >>= 1) {
+    for (int h = kBlk / 2; h > 0; h >>= 1) {
       if (tid < h) {
         const double x = s_q[tid], y = s_q[tid + h];
         s_q[tid] = fma(y, 1.0 - 2.0 * x, x);
@@ -1528,8 +1545,93 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
   }
   if (tid == 0) {
     b_cls[d] = ncls;
-    b_bits[d] = s_wave[kBucketWaves];
+    b_bits[d] = s_wave[kWaves];
     if (s_bad) atomicOr(&st.hdr->flags, FLAG_COLLISION);
+  }
+}
+
+// 16-bit bucket of a key: its top two digits (the two partition passes).
+__device__ __forceinline__ uint32_t bucket16_of(uint64_t k, uint32_t msd) {
+  return uint32_t(k >> (8 * (msd - 1))) & 0xFFFFu;
+}
+
+// Sorted index range [b16_lo[b], b16_hi[b]) of every non-empty 16-bit bucket
+// (empty buckets keep the cleared 0, 0): the first and last key of each run.
+__global__ __launch_bounds__(kBlock) void k_bucket_bounds(DevState st, const uint64_t* __restrict__ keys) {
+  const uint32_t n = st.hdr->n_live;
+  const uint32_t msd = st.n_pass - 1;
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const uint32_t b = bucket16_of(keys[i], msd);
+    if (i == 0 || bucket16_of(keys[i - 1], msd) != b) st.b16_lo[b] = i;
+    if (i + 1 == n || bucket16_of(keys[i + 1], msd) != b) st.b16_hi[b] = i + 1;
+  }
+}
+
+// Per-bucket class and bit counts of the 16-bit buckets -> exclusive
+// prefixes in place (entry kBuckets16 = the totals, also the compile's class
+// and bit counts). One block, in rounds of kScanRound buckets staged through
+// LDS with coalesced loads and stores; thread t scans kScanRound / block
+// consecutive buckets of the round.
+constexpr uint32_t kScanRound = 4096;
+
+__global__ __launch_bounds__(kScanSingleBlock) void k_bucket_scan(DevState st) {
+  constexpr uint32_t kPerT = kScanRound / kScanSingleBlock;
+  __shared__ uint32_t s_c[kScanRound], s_b[kScanRound];
+  __shared__ uint32_t s_wave[kScanSingleBlock / 64];
+  const uint32_t j0 = threadIdx.x * kPerT;
+  uint32_t carry_c = 0, carry_b = 0;
+  for (uint32_t r0 = 0; r0 < kBuckets16; r0 += kScanRound) {
+    for (uint32_t k = threadIdx.x; k < kScanRound; k += kScanSingleBlock) {
+      s_c[k] = st.b16_cls[r0 + k];
+      s_b[k] = st.b16_bits[r0 + k];
+    }
+    __syncthreads();
+    uint32_t c = 0, nb = 0;
+    for (uint32_t k = 0; k < kPerT; ++k) {
+      c += s_c[j0 + k];
+      nb += s_b[j0 + k];
+    }
+    uint32_t tc, tb;
+    uint32_t oc = carry_c + block_scan_1sync<kScanSingleBlock>(c, s_wave, tc);
+    __syncthreads();
+    uint32_t ob = carry_b + block_scan_1sync<kScanSingleBlock>(nb, s_wave, tb);
+    for (uint32_t k = 0; k < kPerT; ++k) {
+      const uint32_t x = s_c[j0 + k], y = s_b[j0 + k];
+      s_c[j0 + k] = oc;
+      s_b[j0 + k] = ob;
+      oc += x;
+      ob += y;
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < kScanRound; k += kScanSingleBlock) {
+      st.b16_cls[r0 + k] = s_c[k];
+      st.b16_bits[r0 + k] = s_b[k];
+    }
+    carry_c += tc;
+    carry_b += tb;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    st.b16_cls[kBuckets16] = carry_c;
+    st.b16_bits[kBuckets16] = carry_b;
+    st.hdr->n_seg = carry_c;
+    st.hdr->n_bits = carry_b;
+  }
+}
+
+// Hyperedge of every class slot of the 16-bit buckets: slot i = bucket start
+// + class c is hyperedge (classes before the bucket) + c; its first output
+// bit is the bucket's bit offset plus the class's within the bucket.
+__global__ __launch_bounds__(kBlock) void k_slot_map(DevState st, const uint64_t* __restrict__ keys) {
+  const uint32_t n = st.hdr->n_live;
+  const uint32_t msd = st.n_pass - 1;
+  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+    const uint32_t b = bucket16_of(keys[i], msd);
+    const uint32_t e = st.b16_cls[b] + (i - st.b16_lo[b]);
+    if (e < st.b16_cls[b + 1]) {
+      st.segstart[e] = i;
+      st.seg_cnt[e] = st.b16_bits[b] + st.seg_off[i];
+    }
   }
 }
 
@@ -1538,10 +1640,13 @@ __global__ __launch_bounds__(kBucketBlock) void k_bucket(DevState st, const uint
 // With kBuckets, class e lives at slot bucket_start + (e - bucket_class_offset)
 // and its bit offset is the bucket's plus the class's within the bucket.
 // The boundary fault offsets are searched in LDS when they fit.
-// With kBucketed every block turns the per-bucket class, bit and fault counts
-// into offsets itself (thread t: bucket t).
-template <bool kBucketed>
+// kMode 0: classes in sorted order (the full radix sort). kMode 1 (256
+// buckets): every block turns the per-bucket class, bit and fault counts into
+// offsets itself (thread t: bucket t). kMode 2 (16-bit buckets): k_slot_map
+// left each hyperedge's class slot and first bit.
+template <int kMode>
 __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
+  constexpr bool kBucketed = kMode == 1;
   static_assert(kBlock == int(kBuckets), "one thread per bucket");
   __shared__ uint32_t s_cls[kBuckets + 1];
   __shared__ uint32_t s_bit[kBuckets];
@@ -1596,12 +1701,15 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
     }
     s = s_fst[lo] + (e - s_cls[lo]);
     o0 = s_bit[lo] + st.seg_off[s];
+  } else if (kMode == 2) {
+    s = st.segstart[e];
+    o0 = st.seg_cnt[e];
   } else {
     o0 = st.seg_off[s];
   }
   st.edge_off32[e] = o0;
   st.edge_q[e] = st.seg_q[s];
-  if (kBucketed) {
+  if (kMode != 0) {
     st.e_first[e] = st.seg_first[s];
     st.e_cnt[e] = st.seg_mem[s];
   } else {
@@ -1609,7 +1717,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
     st.e_cnt[e] = (e + 1 < S ? st.segstart[e + 1] : st.hdr->n_live) - st.segstart[e];
   }
   const uint32_t pos = st.seg_rep[s];
-  const uint32_t cnt = kBucketed ? st.popc[pos] : st.seg_cnt[s];
+  const uint32_t cnt = kMode != 0 ? st.popc[pos] : st.seg_cnt[s];
   if (uint64_t(o0) + cnt > st.bits_cap) return;
   // the representative's circuit (last one whose first fault is <= pos) and boundary
   uint32_t bi = 0;
@@ -1765,7 +1873,8 @@ inline uint32_t cdiv(uint64_t a, uint64_t b) { return uint32_t((a + b - 1) / b);
 const char* kernel_name(int id) {
   static const char* names[K_COUNT] = {"k_prepare",    "k_sweep",       "k_hash",   "k_scan_single", "k_compact",
                                        "k_onesweep",   "k_heads_count", "k_heads_apply", "k_reduce",  "k_reduce_big",
-                                       "k_scan_tiles", "k_scan_apply",  "k_edge_write",  "k_bucket"};
+                                       "k_scan_tiles", "k_scan_apply",  "k_edge_write",  "k_bucket",
+                                       "k_bucket_bounds", "k_bucket_scan", "k_slot_map"};
   return (id >= 0 && id < K_COUNT) ? names[id] : "?";
 }
 
@@ -1834,9 +1943,9 @@ hipError_t configure_kernels() {
   // the bucket grouping needs its two sort buffers next to its static arrays
   g_bucket_ok = false;
   hipFuncAttributes fa{};
-  if (hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(&k_bucket)) == hipSuccess &&
-      fa.sharedSizeBytes + kBucketDynLds <= size_t(lds)) {
-    g_bucket_ok = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bucket),
+  const void* bucket8 = reinterpret_cast<const void*>(&k_bucket<kBucketBlock, kBucketCap, false>);
+  if (hipFuncGetAttributes(&fa, bucket8) == hipSuccess && fa.sharedSizeBytes + kBucketDynLds <= size_t(lds)) {
+    g_bucket_ok = hipFuncSetAttribute(bucket8,
                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(kBucketDynLds)) == hipSuccess;
   }
   (void)hipGetLastError();
@@ -1865,6 +1974,12 @@ hipError_t enqueue_compile(DevState& st_io, hipStream_t stream, const LaunchHook
     st.n_pass = sort_passes(n);
     if (8 * st.n_pass < st.key_bits) st.key_bits = 8 * st.n_pass;
   }
+  // 16-bit buckets: from kBucket16MinFaults faults (or when forced), while
+  // the key has two digits above the ones sorted in LDS
+  st.use_b16 = st.key_mode == 0 && n <= kBucket16MaxFaults && st.n_pass >= 3 &&
+                       (st.sort_mode == SORT_BUCKET16 || (st.sort_mode == SORT_AUTO && n >= kBucket16MinFaults))
+                   ? 1u
+                   : 0u;
   {
     const uint32_t m = st.n_chan > st.n_pass * ntiles * 256 ? st.n_chan : st.n_pass * ntiles * 256;
     uint32_t g = cdiv(m ? m : 1, kBlock);
@@ -1885,10 +2000,30 @@ hipError_t enqueue_compile(DevState& st_io, hipStream_t stream, const LaunchHook
     }
   }
   if (n == 0) {
-    GP_LAUNCH(K_EDGE_WRITE, k_edge_write<false><<<1, kBlock, 0, stream>>>(st));
+    GP_LAUNCH(K_EDGE_WRITE, k_edge_write<0><<<1, kBlock, 0, stream>>>(st));
     return hipSuccess;
   }
   GP_LAUNCH(K_HASH, k_hash<<<st.n_hchunks, kBlock, hash_lds_bytes(st.w_max), stream>>>(st));
+  if (st.use_b16) {
+    // two stable passes on the top two digits (the second carries the fault
+    // records), the bucket ranges, each bucket in LDS, then class offsets
+    const uint32_t msd = st.n_pass - 1;
+    const uint32_t g = cdiv(n, kBlock) < 8192u ? cdiv(n, kBlock) : 8192u;
+    GP_LAUNCH(K_COMPACT, k_compact<<<ntiles, kCompactBlock, 0, stream>>>(st, msd - 1));
+    GP_LAUNCH(K_ONESWEEP, k_onesweep<<<ntiles, kSortBlock, 0, stream>>>(st, msd - 1, st.key[0], st.val[0], st.key[1],
+                                                                     st.val[1], nullptr, nullptr));
+    GP_LAUNCH(K_ONESWEEP, k_onesweep<<<ntiles, kSortBlock, 0, stream>>>(st, msd, st.key[1], st.val[1], st.key[0],
+                                                                     st.val[0], st.frp, st.crp));
+    GP_LAUNCH(K_BUCKET_BOUNDS, k_bucket_bounds<<<g, kBlock, 0, stream>>>(st, st.key[0]));
+    GP_LAUNCH(K_BUCKET, k_bucket<256, kBucket16Cap, true><<<kBuckets16, 256, 2 * kBucket16Cap * sizeof(uint64_t),
+                                                            stream>>>(st, st.key[0], st.val[0], st.val[1],
+                                                                      st.b16_cls, st.b16_bits));
+    GP_LAUNCH(K_BUCKET_SCAN, k_bucket_scan<<<1, kScanSingleBlock, 0, stream>>>(st));
+    GP_LAUNCH(K_SLOT_MAP, k_slot_map<<<g, kBlock, 0, stream>>>(st, st.key[0]));
+    GP_LAUNCH(K_EDGE_WRITE, k_edge_write<2><<<cdiv(n, kBlock), kBlock, 0, stream>>>(st));
+    st_io.ord = st.val[1];
+    return hipSuccess;
+  }
   // buckets: one stable pass on the top digit, then each bucket in LDS
   const bool bucketed = st.sort_mode == SORT_AUTO && st.key_mode == 0 && g_bucket_ok && n <= kBucketMaxFaults &&
                         st.n_pass >= 2 && st.n_pass <= 7;
@@ -1897,8 +2032,9 @@ hipError_t enqueue_compile(DevState& st_io, hipStream_t stream, const LaunchHook
     GP_LAUNCH(K_COMPACT, k_compact<<<ntiles, kCompactBlock, 0, stream>>>(st, msd));
     GP_LAUNCH(K_ONESWEEP, k_onesweep<<<ntiles, kSortBlock, 0, stream>>>(st, msd, st.key[0], st.val[0], st.key[1],
                                                                      st.val[1], st.frp, st.crp));
-    GP_LAUNCH(K_BUCKET, k_bucket<<<kBuckets, kBucketBlock, kBucketDynLds, stream>>>(st, st.key[1], st.val[1]));
-    GP_LAUNCH(K_EDGE_WRITE, k_edge_write<true><<<cdiv(n, kBlock), kBlock, 0, stream>>>(st));
+    GP_LAUNCH(K_BUCKET, k_bucket<kBucketBlock, kBucketCap, false><<<kBuckets, kBucketBlock, kBucketDynLds, stream>>>(
+                            st, st.key[1], st.val[1], st.val[0], st.bkt, st.bkt + kBuckets + 1));
+    GP_LAUNCH(K_EDGE_WRITE, k_edge_write<1><<<cdiv(n, kBlock), kBlock, 0, stream>>>(st));
     return hipSuccess;
   }
   GP_LAUNCH(K_COMPACT, k_compact<<<ntiles, kCompactBlock, 0, stream>>>(st, 0));
@@ -1922,7 +2058,7 @@ hipError_t enqueue_compile(DevState& st_io, hipStream_t stream, const LaunchHook
                                                                                       &st.hdr->n_bits));
   GP_LAUNCH(K_SCAN_APPLY,
             k_scan_apply<<<ntiles, kBlock, 0, stream>>>(st.seg_cnt, st.seg_off, n, &st.hdr->n_seg, st.tile_sum));
-  GP_LAUNCH(K_EDGE_WRITE, k_edge_write<false><<<cdiv(n, kBlock), kBlock, 0, stream>>>(st));
+  GP_LAUNCH(K_EDGE_WRITE, k_edge_write<0><<<cdiv(n, kBlock), kBlock, 0, stream>>>(st));
   return hipSuccess;
 }
 

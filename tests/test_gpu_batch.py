@@ -112,7 +112,7 @@ def test_identical_circuits_do_not_merge(batch_driver):
         assert_same(hg, batch_driver.compile_hypergraph(c.text, rates[k]), f"copy {k} vs single", exact=True)
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_batch_grouping_paths(batch_driver, mode):
     cs = mixed_batch()
     _gp.gp_debug_set_sort_mode(batch_driver.handle, mode)
@@ -304,3 +304,22 @@ def test_batch_autotune_keeps_results():
             assert_same(got[k], oracle.run(texts[k]), f"branch {k} after batch tuning")
         again = drv.autotune_batch(texts, iters=2)
         assert again["cached"] == 1 and again["sweep_block"] == res["sweep_block"]
+
+
+@pytest.mark.parametrize("d,n,b16", [(5, 64, False), (7, 192, True)])
+def test_batch_past_the_256_buckets(d, n, b16):
+    """Batches larger than the 256 buckets take: 64 branches at outer distance
+    5 (1.65 M faults: the automatic grouping runs the full sort) and 192 at
+    distance 7 (13.4 M faults: the 65,536 buckets). Every branch equals its own
+    compile bitwise, three equal the oracle."""
+    from workloads import iceberg_surface_batch
+    texts = [c.text for c in iceberg_surface_batch(d, n_branches=n, seed=21)]
+    say("case past the 256 buckets", d, n)
+    with Driver.from_batch(texts) as drv:
+        got = drv.compile_batch(texts)
+        F = drv.info()["n_faults"]
+        assert F > 1572864 and (F >= 12000000) == b16
+        for k in (0, n // 2, n - 1):
+            assert_same(got[k], oracle.run(texts[k]), f"branch {k} vs oracle")
+        for k, t in enumerate(texts):
+            assert_same(got[k], drv.compile_hypergraph(t), f"branch {k} vs single", exact=True)

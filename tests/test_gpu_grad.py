@@ -83,6 +83,34 @@ def test_refresh_equals_full_compile(c5):
     assert np.array_equal(refreshed.q.view(np.uint64), full.q.view(np.uint64))
 
 
+@pytest.mark.parametrize("mode", [1, 2])
+def test_refresh_and_gradient_after_other_groupings(c5, mode):
+    """The class structure left by the full sort and by the 65,536-bucket
+    grouping: a refresh equals a full compile bitwise, and the adjoint equals
+    the oracle's gradient."""
+    c, rates, drv = c5
+    say("case refresh and gradient, sort mode", mode)
+    _gp.gp_debug_set_sort_mode(drv.handle, mode)
+    try:
+        hg = drv.compile_hypergraph(c.text, rates)
+        wmap = _weights(hg.edges().keys())
+        _, g_gpu_q = _gpu_dl_dq(hg, wmap)
+        res = oracle.run(c.text, rates=rates)
+        _, g_orc_q = _oracle_dl_dq(res, wmap)
+        g_gpu = drv.rates_gradient(g_gpu_q)
+        g_orc = oracle.gradient(c.text, g_orc_q, rates=rates)
+        err = np.abs(g_gpu - g_orc)
+        assert np.all(err <= 1e-9 * np.abs(g_orc) + 1e-300)
+        r2 = log_uniform_rates(c.n_channels, 7)
+        refreshed = drv.refresh_rates(r2)
+        full = drv.compile_hypergraph(c.text, r2)
+        assert np.array_equal(refreshed.offsets, full.offsets)
+        assert np.array_equal(refreshed.bits, full.bits)
+        assert np.array_equal(refreshed.q.view(np.uint64), full.q.view(np.uint64))
+    finally:
+        _gp.gp_debug_set_sort_mode(drv.handle, 0)
+
+
 def test_gradient_matches_device_finite_differences(c5):
     c, rates, drv = c5
     say("case c5 gradient vs central differences")

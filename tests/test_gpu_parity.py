@@ -238,10 +238,11 @@ def test_forced_key_collisions(drv25, bits):
     assert _gp.gp_debug_collision_retries(drv25.handle) == before
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_grouping_paths(drv25, mode):
-    """Both stage-2 groupings (256 buckets sorted and merged in LDS, and the
-    full LSD radix sort) against the oracle on the same workloads."""
+    """Every stage-2 grouping (256 buckets sorted and merged in LDS, the full
+    LSD radix sort, 65,536 buckets on the top two key digits) against the
+    oracle on the same workloads."""
     _gp.gp_debug_set_sort_mode(drv25.handle, mode)
     try:
         c = rotated_surface_code_memory(11, 11)
@@ -262,6 +263,22 @@ def test_large_classes(drv25, copies):
     lines = [f"X_ERROR({r:.17g}) 0" for r in rates]
     lines += ["X_ERROR(0.01) 1", "M 0 1", "DETECTOR rec[-2]", "DETECTOR rec[-1]", "OBSERVABLE_INCLUDE(0) rec[-1]"]
     check(drv25, "\n".join(lines) + "\n", label=f"{copies} copies")
+
+
+
+@pytest.mark.parametrize("copies", [1500, 3000])
+def test_large_classes_in_small_buckets(drv25, copies):
+    """The 65,536-bucket grouping: a class merged by the whole 256-thread
+    block (1500 members), and one over its 2048-fault capacity (3000), which
+    makes the compile redo the grouping with the full sort."""
+    rates = np.linspace(1e-7, 2e-5, copies)
+    lines = [f"X_ERROR({r:.17g}) 0" for r in rates]
+    lines += ["X_ERROR(0.01) 1", "M 0 1", "DETECTOR rec[-2]", "DETECTOR rec[-1]", "OBSERVABLE_INCLUDE(0) rec[-1]"]
+    _gp.gp_debug_set_sort_mode(drv25.handle, 2)
+    try:
+        check(drv25, "\n".join(lines) + "\n", label=f"{copies} copies, 16-bit buckets")
+    finally:
+        _gp.gp_debug_set_sort_mode(drv25.handle, 0)
 
 
 @pytest.mark.parametrize("level", [0, 1])
