@@ -174,6 +174,21 @@ def main() -> int:
     dom_bytes = kernel_bytes(dom, info)
     achieved = dom_bytes / (dom_avg_ms * 1e-3) / 1e9 if dom_bytes else 0.0
 
+    # stage 2 as a whole (the grouping: hash, compaction, partition or sort,
+    # bucket merge, edge writer): algorithmic and profiled HBM bytes per step
+    # over the summed kernel time
+    s2 = [k for k in per_step if k not in ("k_prepare", "k_sweep")]
+    s2_ms = sum(per_step[k][0] for k in s2)
+    s2_alg = sum(kernel_bytes(k, info) * per_step[k][1] for k in s2)
+    s2_tr = [profiled_traffic(k, args.workload) for k in s2]
+    s2_traffic = sum(t * per_step[k][1] for k, t in zip(s2, s2_tr)) if all(t is not None for t in s2_tr) else None
+    stage2 = {"kernels": sorted(s2), "ms_per_step": s2_ms, "algorithmic_bytes": s2_alg,
+              "algorithmic_GBps": s2_alg / (s2_ms * 1e-3) / 1e9, "traffic_bytes": s2_traffic,
+              "traffic_GBps": s2_traffic / (s2_ms * 1e-3) / 1e9 if s2_traffic is not None else None,
+              "peak_GBps": HBM_PEAK_GBS,
+              "frac_algorithmic": s2_alg / (s2_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+              "frac_traffic": (s2_traffic / (s2_ms * 1e-3) / 1e9 / HBM_PEAK_GBS) if s2_traffic is not None else None}
+
     # whole path latency: text -> hyperedges on the host
     lat = []
     for _ in range(args.latency_iters):
@@ -211,6 +226,7 @@ def main() -> int:
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(dom, args.workload),
                      "bytes_per_launch": dom_bytes, "avg_launch_ms": dom_avg_ms, "launches_per_step": dom_launches},
+        "stage2": stage2,
     }
 
     if not args.no_grad:
