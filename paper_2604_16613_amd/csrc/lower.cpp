@@ -39,6 +39,31 @@ const Gate kGates[] = {
 constexpr uint32_t kObsFlag = 0x80000000u;
 constexpr uint32_t kMaxIndex = (1u << 28) - 1;
 
+// Instruction name -> gate: open addressing over a 128-slot table, built once
+// (a linear scan per line cost a third of the parse on detector-heavy text).
+const Gate* find_gate(const char* name, size_t nl) {
+  struct Table {
+    const Gate* slot[128] = {};
+    static uint32_t hash(const char* s, size_t n) {
+      uint32_t h = 2166136261u;
+      for (size_t i = 0; i < n; i++) h = (h ^ uint8_t(s[i])) * 16777619u;
+      return h;
+    }
+    Table() {
+      for (const Gate& g : kGates) {
+        uint32_t h = hash(g.name, std::strlen(g.name)) & 127u;
+        while (slot[h]) h = (h + 1) & 127u;
+        slot[h] = &g;
+      }
+    }
+  };
+  static const Table t;
+  static_assert(sizeof(kGates) / sizeof(kGates[0]) < 96, "gate table load");
+  for (uint32_t h = Table::hash(name, nl) & 127u; t.slot[h]; h = (h + 1) & 127u)
+    if (!std::strcmp(t.slot[h]->name, name)) return t.slot[h];
+  return nullptr;
+}
+
 double rate_limit(uint8_t kind) {
   return kind == CH_DEP1 ? 0.75 : kind == CH_DEP2 ? 15.0 / 16.0 : 0.5;
 }
@@ -114,9 +139,7 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
     name[nl] = 0;
     if (!std::strcmp(name, "REPEAT") || name[0] == '{' || name[0] == '}')
       return set_err(err, GP_E_UNSUPPORTED, line, "%s blocks are not supported", "REPEAT");
-    const Gate* g = nullptr;
-    for (const Gate& cand : kGates)
-      if (!std::strcmp(cand.name, name)) { g = &cand; break; }
+    const Gate* g = find_gate(name, nl);
     if (!g) return set_err(err, GP_E_UNSUPPORTED, line, "unsupported instruction %s", name);
     double args[8];
     int nargs = 0;
@@ -504,13 +527,20 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
         }
       }
     }
-    std::stable_sort(inj.begin(), inj.end(), [](const Inj& x, const Inj& y) {
-      if (x.w != y.w) return x.w < y.w;
-      return x.layer > y.layer;
-    });
+    // by column (a stable counting sort), then by layer, top first, within
+    // each column (stable: equal layers keep measurement order)
     lw.inj_off.assign(size_t(lw.w) + 1, 0);
     for (const Inj& e : inj) lw.inj_off[e.w + 1]++;
     for (uint32_t w = 0; w < lw.w; w++) lw.inj_off[w + 1] += lw.inj_off[w];
+    {
+      std::vector<Inj> by_col(inj.size());
+      std::vector<uint32_t> fill(lw.inj_off.begin(), lw.inj_off.end() - 1);
+      for (const Inj& e : inj) by_col[fill[e.w]++] = e;
+      for (uint32_t w = 0; w < lw.w; w++)
+        std::stable_sort(by_col.begin() + lw.inj_off[w], by_col.begin() + lw.inj_off[w + 1],
+                         [](const Inj& x, const Inj& y) { return x.layer > y.layer; });
+      inj.swap(by_col);
+    }
     lw.inj_layer.resize(inj.size());
     lw.inj_qubit.resize(inj.size());
     lw.inj_word.resize(inj.size());
