@@ -339,8 +339,8 @@ def gp_edges_offsets(e: int) -> np.ndarray:
 
 
 def gp_edges_bits(e: int) -> np.ndarray:
-    off = gp_edges_offsets(e)
-    nb = int(off[-1])
+    n = gp_edges_count(e) + 1
+    nb = int(np.ctypeslib.as_array(load().gp_edges_offsets(e), shape=(n,))[-1])
     if nb == 0:
         return np.zeros(0, dtype=np.uint32)
     return np.ctypeslib.as_array(load().gp_edges_bits(e), shape=(nb,)).copy()

@@ -6,6 +6,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
+#include <string>
+#include <thread>
 
 #include "gp.h"
 
@@ -64,6 +67,132 @@ const Gate* find_gate(const char* name, size_t nl) {
   return nullptr;
 }
 
+// One instruction line, tokenized: its gate, arguments and targets (record
+// targets flagged), with its line number within the chunk of text it came from.
+struct Tok {
+  const Gate* g;
+  uint32_t line;
+  uint32_t t0, t1;  // targets [t0, t1) of the chunk
+  int nargs;
+  double arg0;
+};
+
+// A chunk of whole lines, tokenized on its own thread. Tokenizing stops at
+// the chunk's first syntax error, which is reported after the instructions
+// before it have been applied (so errors keep program order).
+struct TokChunk {
+  std::vector<Tok> toks;
+  std::vector<uint32_t> targets;
+  std::vector<uint8_t> is_rec;
+  uint32_t lines = 0;
+  int err_code = 0;
+  uint32_t err_line = 0;
+  const char* err_fmt = nullptr;
+  std::string err_what;
+};
+
+void tokenize(const char* p, const char* end, TokChunk& c) {
+  auto fail = [&](int code, uint32_t line, const char* fmt, const char* what) {
+    c.err_code = code;
+    c.err_line = line;
+    c.err_fmt = fmt;
+    c.err_what = what;
+  };
+  uint32_t line = 0;
+  while (p < end) {
+    line++;
+    c.lines = line;
+    const char* eol = static_cast<const char*>(std::memchr(p, '\n', size_t(end - p)));
+    if (!eol) eol = end;
+    const char* s = p;
+    p = eol + 1;
+    const char* hash = static_cast<const char*>(std::memchr(s, '#', size_t(eol - s)));
+    const char* e = hash ? hash : eol;
+    while (s < e && (*s == ' ' || *s == '\t' || *s == '\r')) s++;
+    if (s == e) continue;
+    char name[40];
+    size_t nl = 0;
+    while (s < e && *s != '(' && *s != ' ' && *s != '\t' && *s != '\r') {
+      if (nl >= sizeof(name) - 1) return fail(GP_E_UNSUPPORTED, line, "unknown instruction %s", "(too long)");
+      char ch = *s++;
+      name[nl++] = (ch >= 'a' && ch <= 'z') ? char(ch - 32) : ch;
+    }
+    name[nl] = 0;
+    if (!std::strcmp(name, "REPEAT") || name[0] == '{' || name[0] == '}')
+      return fail(GP_E_UNSUPPORTED, line, "%s blocks are not supported", "REPEAT");
+    const Gate* g = find_gate(name, nl);
+    if (!g) return fail(GP_E_UNSUPPORTED, line, "unsupported instruction %s", name);
+    Tok t{g, line, uint32_t(c.targets.size()), 0, 0, 0.0};
+    if (s < e && *s == '(') {
+      s++;
+      for (;;) {
+        while (s < e && (*s == ' ' || *s == '\t')) s++;
+        if (s < e && *s == ')') {
+          s++;
+          break;
+        }
+        char buf[64];
+        size_t bl = 0;
+        while (s < e && *s != ',' && *s != ')' && bl < sizeof(buf) - 1) buf[bl++] = *s++;
+        buf[bl] = 0;
+        char* ep;
+        double v = std::strtod(buf, &ep);
+        if (ep == buf) return fail(GP_E_PARSE, line, "bad argument in %s", g->name);
+        if (t.nargs == 0) t.arg0 = v;
+        t.nargs++;
+        if (s < e && *s == ',') s++;
+        else if (s >= e) return fail(GP_E_PARSE, line, "unterminated arguments in %s", g->name);
+      }
+    }
+    while (s < e) {
+      while (s < e && (*s == ' ' || *s == '\t' || *s == '\r')) s++;
+      if (s >= e) break;
+      if (*s >= '0' && *s <= '9') {
+        uint64_t v = 0;
+        while (s < e && *s >= '0' && *s <= '9') {
+          v = v * 10 + uint64_t(*s - '0');
+          if (v > kMaxIndex) return fail(GP_E_BOUNDS, line, "target index too large in %s", g->name);
+          s++;
+        }
+        if (s < e && *s != ' ' && *s != '\t' && *s != '\r')
+          return fail(GP_E_UNSUPPORTED, line, "unsupported target in %s", g->name);
+        c.targets.push_back(uint32_t(v));
+        c.is_rec.push_back(0);
+      } else if (e - s >= 6 && !std::strncmp(s, "rec[-", 5)) {
+        s += 5;
+        uint64_t v = 0;
+        int nd = 0;
+        while (s < e && *s >= '0' && *s <= '9') {
+          v = v * 10 + uint64_t(*s - '0');
+          if (v > kMaxIndex) return fail(GP_E_PARSE, line, "record offset too large in %s", g->name);
+          s++;
+          nd++;
+        }
+        if (!nd || s >= e || *s != ']' || v == 0) return fail(GP_E_PARSE, line, "bad record target in %s", g->name);
+        s++;
+        c.targets.push_back(uint32_t(v));
+        c.is_rec.push_back(1);
+      } else {
+        return fail(GP_E_UNSUPPORTED, line, "unsupported target in %s", g->name);
+      }
+    }
+    t.t1 = uint32_t(c.targets.size());
+    const bool qubit_targets = g->cls != G_DET && g->cls != G_OBS && g->cls != G_IGNORE;
+    if (qubit_targets) {
+      for (uint32_t k = t.t0; k < t.t1; k++)
+        if (c.is_rec[k]) return fail(GP_E_PARSE, line, "record target on %s", g->name);
+      if (t.nargs && g->cls != G_N1 && g->cls != G_N2)
+        return fail(GP_E_UNSUPPORTED, line, "arguments on %s are not supported", g->name);
+    }
+    c.toks.push_back(t);
+  }
+}
+
+// Whole-line chunks of about equal size (at most kMaxTokThreads; one below
+// kTokChunkMin bytes of text per chunk).
+constexpr size_t kMaxTokThreads = 8;
+constexpr size_t kTokChunkMin = 1 << 17;
+
 double rate_limit(uint8_t kind) {
   return kind == CH_DEP1 ? 0.75 : kind == CH_DEP2 ? 15.0 / 16.0 : 0.5;
 }
@@ -103,8 +232,6 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
   std::vector<RawChan> chans;
   std::vector<uint64_t> pairs;  // (m << 32) | code
   uint32_t n_meas = 0, n_det = 0, n_obs = 0;
-  std::vector<uint32_t> targets;
-  std::vector<uint8_t> is_rec;
   // sized from the text (typical circuits spend about four characters per
   // target) so that the vectors rarely regrow
   op_layer.reserve(len / 4);
@@ -116,184 +243,134 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
     if (q >= ready.size()) ready.resize(size_t(q) + 1, 0);
   };
 
-  const char* p = text;
-  const char* end = text + len;
-  int line = 0;
-  while (p < end) {
-    line++;
-    const char* eol = static_cast<const char*>(std::memchr(p, '\n', size_t(end - p)));
-    if (!eol) eol = end;
-    const char* s = p;
-    p = eol + 1;
-    const char* hash = static_cast<const char*>(std::memchr(s, '#', size_t(eol - s)));
-    const char* e = hash ? hash : eol;
-    while (s < e && (*s == ' ' || *s == '\t' || *s == '\r')) s++;
-    if (s == e) continue;
-    char name[40];
-    size_t nl = 0;
-    while (s < e && *s != '(' && *s != ' ' && *s != '\t' && *s != '\r') {
-      if (nl >= sizeof(name) - 1) return set_err(err, GP_E_UNSUPPORTED, line, "unknown instruction %s", "(too long)");
-      char c = *s++;
-      name[nl++] = (c >= 'a' && c <= 'z') ? char(c - 32) : c;
+  // tokenize whole-line chunks in parallel, then schedule (ASAP layers,
+  // measurement records, channels) in program order
+  std::vector<TokChunk> chunks;
+  {
+    const size_t T = std::max<size_t>(1, std::min(kMaxTokThreads, len / kTokChunkMin));
+    std::vector<const char*> cut(T + 1, text + len);
+    cut[0] = text;
+    for (size_t k = 1; k < T; k++) {
+      const char* c = text + len * k / T;
+      if (c < cut[k - 1]) c = cut[k - 1];
+      const char* nl = static_cast<const char*>(std::memchr(c, '\n', size_t(text + len - c)));
+      cut[k] = nl ? nl + 1 : text + len;
     }
-    name[nl] = 0;
-    if (!std::strcmp(name, "REPEAT") || name[0] == '{' || name[0] == '}')
-      return set_err(err, GP_E_UNSUPPORTED, line, "%s blocks are not supported", "REPEAT");
-    const Gate* g = find_gate(name, nl);
-    if (!g) return set_err(err, GP_E_UNSUPPORTED, line, "unsupported instruction %s", name);
-    double args[8];
-    int nargs = 0;
-    if (s < e && *s == '(') {
-      s++;
-      for (;;) {
-        while (s < e && (*s == ' ' || *s == '\t')) s++;
-        if (s < e && *s == ')') { s++; break; }
-        char buf[64];
-        size_t bl = 0;
-        while (s < e && *s != ',' && *s != ')' && bl < sizeof(buf) - 1) buf[bl++] = *s++;
-        buf[bl] = 0;
-        char* ep;
-        double v = std::strtod(buf, &ep);
-        if (ep == buf) return set_err(err, GP_E_PARSE, line, "bad argument in %s", name);
-        if (nargs < 8) args[nargs] = v;
-        nargs++;
-        if (s < e && *s == ',') s++;
-        else if (s >= e) return set_err(err, GP_E_PARSE, line, "unterminated arguments in %s", name);
-      }
+    chunks.resize(T);
+    if (T == 1) {
+      tokenize(cut[0], cut[1], chunks[0]);
+    } else {
+      std::vector<std::thread> pool;
+      for (size_t k = 1; k < T; k++) pool.emplace_back(tokenize, cut[k], cut[k + 1], std::ref(chunks[k]));
+      tokenize(cut[0], cut[1], chunks[0]);
+      for (std::thread& th : pool) th.join();
     }
-    targets.clear();
-    is_rec.clear();
-    while (s < e) {
-      while (s < e && (*s == ' ' || *s == '\t' || *s == '\r')) s++;
-      if (s >= e) break;
-      if (*s >= '0' && *s <= '9') {
-        uint64_t v = 0;
-        while (s < e && *s >= '0' && *s <= '9') {
-          v = v * 10 + uint64_t(*s - '0');
-          if (v > kMaxIndex) return set_err(err, GP_E_BOUNDS, line, "target index too large in %s", name);
-          s++;
-        }
-        if (s < e && *s != ' ' && *s != '\t' && *s != '\r')
-          return set_err(err, GP_E_UNSUPPORTED, line, "unsupported target in %s", name);
-        targets.push_back(uint32_t(v));
-        is_rec.push_back(0);
-      } else if (e - s >= 6 && !std::strncmp(s, "rec[-", 5)) {
-        s += 5;
-        uint64_t v = 0;
-        int nd = 0;
-        while (s < e && *s >= '0' && *s <= '9') {
-          v = v * 10 + uint64_t(*s - '0');
-          if (v > kMaxIndex) return set_err(err, GP_E_PARSE, line, "record offset too large in %s", name);
-          s++;
-          nd++;
-        }
-        if (!nd || s >= e || *s != ']' || v == 0) return set_err(err, GP_E_PARSE, line, "bad record target in %s", name);
-        s++;
-        targets.push_back(uint32_t(v));
-        is_rec.push_back(1);
-      } else {
-        return set_err(err, GP_E_UNSUPPORTED, line, "unsupported target in %s", name);
-      }
-    }
-    const size_t nt = targets.size();
-    const bool qubit_targets = g->cls != G_DET && g->cls != G_OBS && g->cls != G_IGNORE;
-    if (qubit_targets) {
-      for (size_t k = 0; k < nt; k++)
-        if (is_rec[k]) return set_err(err, GP_E_PARSE, line, "record target on %s", name);
-      if (nargs && g->cls != G_N1 && g->cls != G_N2)
-        return set_err(err, GP_E_UNSUPPORTED, line, "arguments on %s are not supported", name);
-    }
-    switch (g->cls) {
-      case G_PAULI:
-        for (size_t k = 0; k < nt; k++) touch(targets[k]);
-        break;
-      case G_1Q:
-      case G_RESET:
-        for (size_t k = 0; k < nt; k++) {
-          uint32_t q = targets[k];
-          touch(q);
-          op_layer.push_back(ready[q]);
-          op_word.push_back(pack_op(g->kind, q, 0));
-          ready[q]++;
-        }
-        break;
-      case G_2Q:
-        if (nt % 2) return set_err(err, GP_E_PARSE, line, "odd number of targets in %s", name);
-        for (size_t k = 0; k < nt; k += 2) {
-          uint32_t a = targets[k], b = targets[k + 1];
-          if (a == b) return set_err(err, GP_E_PARSE, line, "repeated qubit in %s", name);
-          touch(a);
-          touch(b);
-          uint32_t l = std::max(ready[a], ready[b]);
-          op_layer.push_back(l);
-          op_word.push_back(pack_op(g->kind, a, b));
-          ready[a] = ready[b] = l + 1;
-        }
-        break;
-      case G_MEAS:
-        for (size_t k = 0; k < nt; k++) {
-          uint32_t q = targets[k];
-          touch(q);
-          if (n_meas > kMaxIndex) return set_err(err, GP_E_BOUNDS, line, "too many measurements at %s", name);
-          op_layer.push_back(ready[q]);
-          op_word.push_back(pack_op(g->kind, q, n_meas));
-          lw.meas_layer.push_back(ready[q]);
-          ready[q]++;
-          n_meas++;
-        }
-        break;
-      case G_N1:
-      case G_N2: {
-        if (nargs != 1) return set_err(err, GP_E_PARSE, line, "%s takes one probability", name);
-        double r = args[0];
-        if (!(r >= 0.0 && r <= rate_limit(g->kind)))
-          return set_err(err, GP_E_NOISE, line, "rate out of range in %s", name);
-        if (g->cls == G_N1) {
+  }
+  uint32_t line_base = 0;
+  for (const TokChunk& ck : chunks) {
+  for (const Tok& t : ck.toks) {
+    const Gate* g = t.g;
+    const int line = int(line_base + t.line);
+      const size_t nt = t.t1 - t.t0;
+      const uint32_t* targets = ck.targets.data() + t.t0;
+      const uint8_t* is_rec = ck.is_rec.data() + t.t0;
+      const char* name = g->name;
+      const int nargs = t.nargs;
+      const double args[1] = {t.arg0};
+      switch (g->cls) {
+        case G_PAULI:
+          for (size_t k = 0; k < nt; k++) touch(targets[k]);
+          break;
+        case G_1Q:
+        case G_RESET:
           for (size_t k = 0; k < nt; k++) {
             uint32_t q = targets[k];
             touch(q);
-            chans.push_back(RawChan{ready[q], q, UINT32_MAX, g->kind, r});
+            op_layer.push_back(ready[q]);
+            op_word.push_back(pack_op(g->kind, q, 0));
+            ready[q]++;
           }
-        } else {
+          break;
+        case G_2Q:
           if (nt % 2) return set_err(err, GP_E_PARSE, line, "odd number of targets in %s", name);
           for (size_t k = 0; k < nt; k += 2) {
             uint32_t a = targets[k], b = targets[k + 1];
             if (a == b) return set_err(err, GP_E_PARSE, line, "repeated qubit in %s", name);
             touch(a);
             touch(b);
-            // both halves of the fault must sit at one boundary: later
-            // operations on either qubit may not be scheduled before it
-            uint32_t bnd = std::max(ready[a], ready[b]);
-            ready[a] = ready[b] = bnd;
-            chans.push_back(RawChan{bnd, a, b, g->kind, r});
+            uint32_t l = std::max(ready[a], ready[b]);
+            op_layer.push_back(l);
+            op_word.push_back(pack_op(g->kind, a, b));
+            ready[a] = ready[b] = l + 1;
           }
+          break;
+        case G_MEAS:
+          for (size_t k = 0; k < nt; k++) {
+            uint32_t q = targets[k];
+            touch(q);
+            if (n_meas > kMaxIndex) return set_err(err, GP_E_BOUNDS, line, "too many measurements at %s", name);
+            op_layer.push_back(ready[q]);
+            op_word.push_back(pack_op(g->kind, q, n_meas));
+            lw.meas_layer.push_back(ready[q]);
+            ready[q]++;
+            n_meas++;
+          }
+          break;
+        case G_N1:
+        case G_N2: {
+          if (nargs != 1) return set_err(err, GP_E_PARSE, line, "%s takes one probability", name);
+          double r = args[0];
+          if (!(r >= 0.0 && r <= rate_limit(g->kind)))
+            return set_err(err, GP_E_NOISE, line, "rate out of range in %s", name);
+          if (g->cls == G_N1) {
+            for (size_t k = 0; k < nt; k++) {
+              uint32_t q = targets[k];
+              touch(q);
+              chans.push_back(RawChan{ready[q], q, UINT32_MAX, g->kind, r});
+            }
+          } else {
+            if (nt % 2) return set_err(err, GP_E_PARSE, line, "odd number of targets in %s", name);
+            for (size_t k = 0; k < nt; k += 2) {
+              uint32_t a = targets[k], b = targets[k + 1];
+              if (a == b) return set_err(err, GP_E_PARSE, line, "repeated qubit in %s", name);
+              touch(a);
+              touch(b);
+              // both halves of the fault must sit at one boundary: later
+              // operations on either qubit may not be scheduled before it
+              uint32_t bnd = std::max(ready[a], ready[b]);
+              ready[a] = ready[b] = bnd;
+              chans.push_back(RawChan{bnd, a, b, g->kind, r});
+            }
+          }
+          break;
         }
-        break;
+        case G_DET:
+        case G_OBS: {
+          uint32_t code;
+          if (g->cls == G_DET) {
+            code = n_det++;
+            if (n_det > kMaxIndex) return set_err(err, GP_E_BOUNDS, line, "too many %s", "detectors");
+          } else {
+            if (nargs != 1 || args[0] < 0 || args[0] != std::floor(args[0]) || args[0] > 65535)
+              return set_err(err, GP_E_PARSE, line, "%s needs one observable index", name);
+            uint32_t k = uint32_t(args[0]);
+            n_obs = std::max(n_obs, k + 1);
+            code = kObsFlag | k;
+          }
+          for (size_t k = 0; k < nt; k++) {
+            if (!is_rec[k]) return set_err(err, GP_E_PARSE, line, "%s takes record targets", name);
+            if (targets[k] > n_meas) return set_err(err, GP_E_PARSE, line, "record looks back too far in %s", name);
+            uint32_t m = n_meas - targets[k];
+            pairs.push_back((uint64_t(m) << 32) | code);
+          }
+          break;
+        }
+        default:
+          break;
       }
-      case G_DET:
-      case G_OBS: {
-        uint32_t code;
-        if (g->cls == G_DET) {
-          code = n_det++;
-          if (n_det > kMaxIndex) return set_err(err, GP_E_BOUNDS, line, "too many %s", "detectors");
-        } else {
-          if (nargs != 1 || args[0] < 0 || args[0] != std::floor(args[0]) || args[0] > 65535)
-            return set_err(err, GP_E_PARSE, line, "%s needs one observable index", name);
-          uint32_t k = uint32_t(args[0]);
-          n_obs = std::max(n_obs, k + 1);
-          code = kObsFlag | k;
-        }
-        for (size_t k = 0; k < nt; k++) {
-          if (!is_rec[k]) return set_err(err, GP_E_PARSE, line, "%s takes record targets", name);
-          if (targets[k] > n_meas) return set_err(err, GP_E_PARSE, line, "record looks back too far in %s", name);
-          uint32_t m = n_meas - targets[k];
-          pairs.push_back((uint64_t(m) << 32) | code);
-        }
-        break;
-      }
-      default:
-        break;
-    }
+  }
+  if (ck.err_code) return set_err(err, ck.err_code, int(line_base + ck.err_line), ck.err_fmt, ck.err_what.c_str());
+  line_base += ck.lines;
   }
 
   // ---- sizes
@@ -319,7 +396,19 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
   }
 
   // ---- leaves (Eq. 2), XOR semantics for repeated memberships
-  std::sort(pairs.begin(), pairs.end());
+  {
+    // (measurement, code) pairs in ascending order: a counting sort by
+    // measurement, then each measurement's few codes sorted
+    std::vector<uint32_t> cnt(size_t(n_meas) + 1, 0);
+    for (uint64_t pr : pairs) cnt[(pr >> 32) + 1]++;
+    for (uint32_t m = 0; m < n_meas; m++) cnt[m + 1] += cnt[m];
+    std::vector<uint64_t> sorted(pairs.size());
+    std::vector<uint32_t> fill(cnt.begin(), cnt.end() - 1);
+    for (uint64_t pr : pairs) sorted[fill[pr >> 32]++] = pr;
+    for (uint32_t m = 0; m < n_meas; m++)
+      if (cnt[m + 1] - cnt[m] > 1) std::sort(sorted.begin() + cnt[m], sorted.begin() + cnt[m + 1]);
+    pairs.swap(sorted);
+  }
   lw.leaf_off.assign(size_t(n_meas) + 1, 0);
   lw.leaf_bits.clear();
   for (size_t i = 0; i < pairs.size();) {

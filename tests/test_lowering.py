@@ -89,3 +89,35 @@ def test_observable_cut_does_not_change_signatures(cost):
             assert sigs == r
     finally:
         host_check.set_fault_cost(6.2e-4)
+
+
+def test_text_split_across_tokenizer_threads():
+    """A circuit text long enough to be tokenized in four chunks (0.53 MB,
+    d = 17) replays to the oracle's signatures."""
+    c = rotated_surface_code_memory(17, 17)
+    assert len(c.text) > 4 * (1 << 17)
+    compare(c.text)
+
+
+def _error_line(text):
+    from paper_2604_16613_amd import GpError, _gp
+    with pytest.raises(GpError) as e:
+        _gp.gp_bounds_from_circuit(text)
+    return str(e.value)
+
+
+def test_error_lines_keep_program_order_across_chunks():
+    """Errors in a multi-chunk text name their own line, and the first error
+    in program order wins, whether it is found while tokenizing (a chunk's
+    syntax) or while scheduling (record look-back)."""
+    lines = rotated_surface_code_memory(25, 25).text.split("\n")
+    n = len(lines)
+    late = int(n * 0.9)
+    bad = lines[:late] + ["FOO 1"] + lines[late:]
+    assert f"line {late + 1}: unsupported instruction FOO" in _error_line("\n".join(bad))
+    early = int(n * 0.2)
+    both = lines[:early] + ["DETECTOR rec[-99999999]"] + lines[early:late] + ["FOO 1"] + lines[late:]
+    assert f"line {early + 1}: record looks back too far" in _error_line("\n".join(both))
+    mid = int(n * 0.5)
+    two = lines[:mid] + ["CX 0"] + lines[mid:late] + ["H rec[-1]"] + lines[late:]
+    assert f"line {mid + 1}: odd number of targets" in _error_line("\n".join(two))
