@@ -165,12 +165,16 @@ __device__ __forceinline__ uint32_t digit_of(uint64_t k, uint32_t pass) { return
 __constant__ KeptCodes c_kept = make_kept_codes();
 
 // A block takes 256 consecutive channels: one thread per channel computes the
-// per-fault probability and the qubits, then the block writes the faults of
-// those channels (consecutive positions) one thread per fault, coalesced.
+// per-fault probability and the qubits and marks its faults in an LDS map
+// (fault -> channel), then the block writes the faults of those channels
+// (consecutive positions) one thread per fault, coalesced.
+constexpr uint32_t kMaxChanFaults = sizeof(KeptCodes::code[0][0]);  // faults of one channel at most
+
 __global__ __launch_bounds__(kBlock) void k_prepare(DevState st) {
   __shared__ double s_p[kBlock];
   __shared__ uint32_t s_q[kBlock];          // qubit a | qubit b << 14 | kind << 28
   __shared__ uint32_t s_off[kBlock + 1];    // first fault of each channel, from the block's first
+  __shared__ uint8_t s_ch[kBlock * kMaxChanFaults];  // channel (in the block) of each fault
   const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t stride = gridDim.x * blockDim.x;
   const uint32_t n_blk = (st.n_chan + kBlock - 1) / kBlock;
@@ -186,18 +190,15 @@ __global__ __launch_bounds__(kBlock) void k_prepare(DevState st) {
       const uint32_t qb = kind == CH_DEP2 ? (st.chan_qb[c] & kQField) : qa;
       s_p[threadIdx.x] = fault_probability(kind, st.chan_rate[c]);
       s_q[threadIdx.x] = qa | (qb << kQubitBits) | (kind << 28);
-      s_off[threadIdx.x] = st.chan_foff[c] - f_lo;
+      const uint32_t o = st.chan_foff[c] - f_lo, o1 = st.chan_foff[c + 1] - f_lo;
+      s_off[threadIdx.x] = o;
+      for (uint32_t i = o; i < o1; ++i) s_ch[i] = uint8_t(threadIdx.x);
     }
     if (threadIdx.x == 0) s_off[nc] = st.chan_foff[c0 + nc] - f_lo;
     __syncthreads();
     const uint32_t nf = s_off[nc];
     for (uint32_t i = threadIdx.x; i < nf; i += kBlock) {
-      // the channel holding fault i: the last j with s_off[j] <= i
-      uint32_t lo = 0, hi = nc;
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (s_off[mid] <= i) lo = mid; else hi = mid;
-      }
+      const uint32_t lo = s_ch[i];
       const uint32_t q = s_q[lo], kind = q >> 28;
       st.frp[f_lo + i].p = s_p[lo];
       // Pauli code: x on a | z on a << 1 | x on b << 2 | z on b << 3
