@@ -61,7 +61,8 @@ enum {
   GP_E_HIP = -7,              /* HIP runtime error, or no usable gfx950 device */
   GP_E_OOM = -8,              /* host or device allocation failed */
   GP_E_COLLISION = -9,        /* two different signatures share both 64-bit hashes */
-  GP_E_STATE = -10            /* call out of order (e.g. gp_run before gp_lower) */
+  GP_E_STATE = -10,           /* call out of order (e.g. gp_run before gp_lower) */
+  GP_E_BUSY = -11             /* the server holds its limit of requests or bytes: collect results, retry */
 };
 
 typedef struct gp_driver gp_driver;
@@ -256,6 +257,15 @@ int gp_server_submit(gp_server* srv, const char* text, size_t len, const double*
                      uint64_t* ticket);
 int gp_server_wait(gp_server* srv, uint64_t ticket, int64_t timeout_us, gp_edges** out, uint64_t* latency_ns);
 int gp_server_stats(const gp_server* srv, uint64_t* batches, uint64_t* requests, uint64_t* max_batch);
+/* Admission (backpressure): a server holds at most `max_requests` live
+ * requests (submitted and not yet collected by gp_server_wait) and at most
+ * `max_bytes` of host memory for them (circuit text and rates, then the
+ * result until it is collected). gp_server_submit returns GP_E_BUSY at once,
+ * without queueing, when admitting the request would pass either limit;
+ * a request is always admitted when nothing is live. Defaults: 4096 requests,
+ * 4 GiB. GP_E_ARG for a zero limit. Device memory needs no admission: each
+ * driver is allocated once for the batch bounds. */
+int gp_server_set_admission(gp_server* srv, uint64_t max_requests, uint64_t max_bytes);
 /* Worker time so far (milliseconds) in host lowering, in merging +
  * uploading + launching, and in fetching results (waiting for the device,
  * downloading, splitting per request), with the waiting and the downloading

@@ -18,7 +18,7 @@ GP_OK = 0
 STATUS = {
     -1: "GP_E_ARG", -2: "GP_E_PARSE", -3: "GP_E_UNSUPPORTED", -4: "GP_E_BOUNDS",
     -5: "GP_E_NONDETERMINISTIC", -6: "GP_E_NOISE", -7: "GP_E_HIP", -8: "GP_E_OOM",
-    -9: "GP_E_COLLISION", -10: "GP_E_STATE",
+    -9: "GP_E_COLLISION", -10: "GP_E_STATE", -11: "GP_E_BUSY",
 }
 
 #: every symbol include/gp.h declares
@@ -35,7 +35,7 @@ EXPORTS = (
     "gp_edges_circuit_offsets", "gp_server_create", "gp_server_submit", "gp_server_wait", "gp_server_stats",
     "gp_server_destroy", "gp_server_timing", "gp_debug_set_graph", "gp_autotune", "gp_set_fault_cost",
     "gp_debug_set_sweep_shape", "gp_autotune_batch", "gp_tuning_cache_size", "gp_tuning_cache_get",
-    "gp_tuning_cache_put",
+    "gp_tuning_cache_put", "gp_server_set_admission",
 )
 
 
@@ -168,6 +168,7 @@ def load():
                               ctypes.POINTER(_u64)], ctypes.c_int),
         "gp_server_wait": ([_vp, _u64, ctypes.c_int64, ctypes.POINTER(_vp), ctypes.POINTER(_u64)], ctypes.c_int),
         "gp_server_stats": ([_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(_u64)], ctypes.c_int),
+        "gp_server_set_admission": ([_vp, _u64, _u64], ctypes.c_int),
         "gp_server_destroy": ([_vp], None),
         "gp_server_timing": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -506,6 +507,10 @@ def gp_server_wait(srv: int, ticket: int, timeout_us: int = -1) -> Tuple[int, in
     lat = _u64()
     _check(load().gp_server_wait(srv, ticket, timeout_us, ctypes.byref(h), ctypes.byref(lat)))
     return h.value, lat.value
+
+
+def gp_server_set_admission(srv: int, max_requests: int, max_bytes: int) -> None:
+    _check(load().gp_server_set_admission(srv, max_requests, max_bytes))
 
 
 def gp_server_stats(srv: int) -> Tuple[int, int, int]:

@@ -205,7 +205,14 @@ class Server:
         return cls(b, device)
 
     def submit(self, circuit: str, rates: Optional[Sequence[float]] = None) -> int:
+        """-> ticket. Raises GpError GP_E_BUSY (code -11) when the server holds
+        its admission limit (see set_admission)."""
         return _gp.gp_server_submit(self.handle, circuit, rates)
+
+    def set_admission(self, max_requests: int, max_bytes: int) -> None:
+        """Limits on live requests (submitted, not yet collected) and on the
+        host bytes they hold (see gp_server_set_admission)."""
+        _gp.gp_server_set_admission(self.handle, max_requests, max_bytes)
 
     def wait(self, ticket: int, timeout_us: int = -1) -> Tuple[Hypergraph, float]:
         """-> (hypergraph, latency in ms from submit to completion)."""

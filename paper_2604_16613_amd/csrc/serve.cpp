@@ -45,6 +45,7 @@ struct Request {
   int rc = GP_OK;
   std::string msg;
   gp_edges* edges = nullptr;
+  uint64_t held = 0;  // host bytes counted against the admission limit
 };
 
 using ReqPtr = std::shared_ptr<Request>;
@@ -62,6 +63,8 @@ struct gp_server {
   bool lowerers_done = false;
   std::deque<ReqPtr> pending;   // lowered, waiting for a batch
   std::unordered_map<uint64_t, ReqPtr> live;  // submitted and not yet collected
+  uint64_t max_live = 4096, max_bytes = uint64_t(4) << 30;  // admission limits
+  uint64_t live_bytes = 0;                                    // host bytes of the live requests
   uint64_t next_ticket = 1;
   bool stop = false;
   std::thread worker;
@@ -78,6 +81,14 @@ void complete(gp_server* s, const ReqPtr& r, int rc, const std::string& msg, gp_
   r->edges = e;
   r->t_done = now_ns();
   r->done = true;
+  // the result counts against the byte limit until it is collected
+  uint64_t rb = msg.size();
+  if (e) {
+    const uint64_t U = gp_edges_count(e);
+    rb += U * (8 + 8 + 4) + (U ? gp_edges_offsets(e)[U] * 4 : 0);
+  }
+  r->held += rb;
+  s->live_bytes += rb;
   r->lw = gp::Lowered();  // the tables are no longer needed
   s->cv_done.notify_all();
 }
@@ -250,9 +261,14 @@ int gp_server_submit(gp_server* s, const char* text, size_t len, const double* r
     r->rates.assign(rates, rates + n_rates);
     r->has_rates = true;
   }
+  r->held = len + uint64_t(n_rates) * sizeof(double);
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return gp::set_last_error(GP_E_STATE, "the server is shutting down");
+    if (!s->live.empty() && (s->live.size() >= s->max_live || s->live_bytes + r->held > s->max_bytes))
+      return gp::set_last_error(GP_E_BUSY, "admission refused: the server holds its limit of live requests or "
+                                           "bytes (collect results with gp_server_wait, then retry)");
+    s->live_bytes += r->held;
     r->ticket = s->next_ticket++;
     r->t_submit = now_ns();
     s->to_lower.push_back(r);
@@ -260,6 +276,15 @@ int gp_server_submit(gp_server* s, const char* text, size_t len, const double* r
   }
   s->cv_lower.notify_one();
   *ticket = r->ticket;
+  return GP_OK;
+}
+
+int gp_server_set_admission(gp_server* s, uint64_t max_requests, uint64_t max_bytes) {
+  if (!s) return gp::set_last_error(GP_E_ARG, "null server");
+  if (!max_requests || !max_bytes) return gp::set_last_error(GP_E_ARG, "admission limits must be positive");
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->max_live = max_requests;
+  s->max_bytes = max_bytes;
   return GP_OK;
 }
 
@@ -276,6 +301,7 @@ int gp_server_wait(gp_server* s, uint64_t ticket, int64_t timeout_us, gp_edges**
     return gp::set_last_error(GP_E_STATE, "the request has not finished yet");
   }
   s->live.erase(ticket);
+  s->live_bytes -= r->held;
   if (latency_ns) *latency_ns = r->t_done - r->t_submit;
   if (r->rc) return gp::set_last_error(r->rc, r->msg);
   *out = r->edges;

@@ -106,6 +106,8 @@ def test_server_without_a_device_fails_cleanly():
     with pytest.raises(_gp.GpError) as e:
         _gp.gp_server_create(b, 0)
     assert e.value.code == -7
+    # admission limits on no server
+    assert _gp.load().gp_server_set_admission(None, 1, 1) == -1
 
 
 def test_tuning_cache_round_trip(tmp_path):

@@ -113,3 +113,39 @@ def test_tickets_and_timeouts(branches):
         assert e.value.code == -1
         # results nobody collects are freed with the server
         srv.submit(branches[1])
+
+
+def test_admission_refuses_past_its_limits(branches):
+    """Backpressure: past the limit of live (uncollected) requests, or of the
+    host bytes they hold, a submission fails at once with GP_E_BUSY and is
+    not queued; collecting a result frees room; a request is always admitted
+    when nothing is live."""
+    say("case admission")
+    with Server.for_circuits(branches, max_batch=4) as srv, Driver.from_batch(branches) as alone:
+        with pytest.raises(GpError) as e:
+            srv.set_admission(0, 1 << 20)
+        assert e.value.code == -1
+        srv.set_admission(2, 1 << 30)
+        a = srv.submit(branches[0])
+        b = srv.submit(branches[1])
+        with pytest.raises(GpError) as e:
+            srv.submit(branches[2])
+        assert e.value.code == -11 and e.value.name == "GP_E_BUSY"
+        hg, _ = srv.wait(a)
+        same(hg, alone.compile_hypergraph(branches[0]), "admitted request a")
+        c = srv.submit(branches[2])
+        for t, k in ((b, 1), (c, 2)):
+            hg, _ = srv.wait(t)
+            same(hg, alone.compile_hypergraph(branches[k]), f"request {k}")
+        # bytes: the first request is admitted alone even over the limit, the
+        # next one waits until it is collected
+        srv.set_admission(100, len(branches[3]) // 2)
+        d = srv.submit(branches[3])
+        with pytest.raises(GpError) as e:
+            srv.submit(branches[4])
+        assert e.value.code == -11
+        srv.wait(d)
+        f = srv.submit(branches[4])
+        hg, _ = srv.wait(f)
+        same(hg, alone.compile_hypergraph(branches[4]), "request after the byte limit")
+        assert srv.stats()["requests"] == 5
