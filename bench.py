@@ -75,8 +75,9 @@ def workload(name: str):
 
 
 def kernel_bytes(name: str, info: dict) -> float:
-    """Algorithmic HBM bytes of one launch of `name` (the per-unit figures are
-    listed with the kernels in the design doc)."""
+    """Algorithmic HBM bytes of one launch of `name`: F faults, F_live with a
+    non-empty signature, U hyperedges, S_w (fault, column) pairs in the swept
+    windows of which NZ are non-zero, B output signature bits."""
     F = info["n_faults"]
     live = info["n_live_faults"]
     words = info["n_live_words"]     # (fault, column) pairs in the swept windows
