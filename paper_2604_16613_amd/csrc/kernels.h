@@ -61,6 +61,15 @@ struct __align__(16) FaultRec {
   uint64_t chk;  // check hash of the signature
 };
 
+// Per fault position, written by the hash for the edge writer: which covered
+// columns hold non-zero words, the signature weight and the boundary row (in
+// the batch's boundary tables), read in one access per representative.
+struct __align__(16) EdgeRec {
+  uint64_t nzm;
+  uint32_t popc;
+  uint32_t bnd;
+};
+
 // Everything one compile reads or writes on the device.
 struct DevState {
   // lowered tables (inputs, uploaded per circuit)
@@ -129,7 +138,7 @@ struct DevState {
   uint64_t* key[2];      // class keys: per position (key[1]) then compacted, ping-pong in the sort
   uint32_t* val[2];      // fault positions riding with the keys
   uint32_t* popc;        // per fault position: signature weight
-  uint64_t* nzm;         // per fault position: which covered columns hold non-zero words
+  EdgeRec* erec;         // per fault position: non-zero-word mask, weight, boundary row
   uint32_t* tile_cnt;    // per compaction tile: live faults, then their exclusive prefix
   uint32_t* tile_nz;     // per compaction tile: non-zero signature words
   uint32_t* digit_tot;   // per pass: total count of each digit value (summed by the compaction tiles)

@@ -147,16 +147,6 @@ __device__ __forceinline__ double fault_probability(uint32_t kind, double r) {
   return r;
 }
 
-// Boundary b holding fault position pos: bnd_fault_off[b] <= pos < bnd_fault_off[b+1].
-__device__ __forceinline__ uint32_t boundary_of(const uint32_t* off, uint32_t n_bnd, uint32_t pos) {
-  uint32_t lo = 0, hi = n_bnd;  // off has n_bnd + 1 entries
-  while (hi - lo > 1) {
-    uint32_t mid = (lo + hi) >> 1;
-    if (off[mid] <= pos) lo = mid; else hi = mid;
-  }
-  return lo;
-}
-
 __device__ __forceinline__ uint32_t digit_of(uint64_t k, uint32_t pass) { return uint32_t(k >> (8 * pass)) & 255u; }
 
 // ------------------------------------------------------------------ prepare
@@ -750,7 +740,7 @@ __global__ __launch_bounds__(kBlock) void k_hash(DevState st) {
     st.key[1][pos] = key;
     st.frp[pos].chk = h2;
     st.popc[pos] = weight;
-    st.nzm[pos] = mask;
+    st.erec[pos] = EdgeRec{mask, weight, gb};
   }
   // live faults and non-zero words per compaction tile: the chunk's
   // positions span at most two tiles; reduce over the block, then at most
@@ -1218,7 +1208,6 @@ __global__ __launch_bounds__(kBlock) void k_reduce_big(DevState st, const uint32
 // ------------------------------------------------------------------ buckets
 
 constexpr int kBucketBlock = 1024;
-constexpr int kBucketWaves = kBucketBlock / 64;
 constexpr uint32_t kBucketSortBits = 24;  // key bits a bucket sorts in LDS; longer runs of equal bits are rare
 
 // Grouping inside one bucket: the live faults whose key has top digit d
@@ -1640,7 +1629,8 @@ __global__ __launch_bounds__(kBlock) void k_slot_map(DevState st, const uint64_t
 // observable k -> D + k) and its probability.
 // With kBuckets, class e lives at slot bucket_start + (e - bucket_class_offset)
 // and its bit offset is the bucket's plus the class's within the bucket.
-// The boundary fault offsets are searched in LDS when they fit.
+// The representative's boundary row, weight and non-zero-word mask come from
+// its edge record (one access).
 // kMode 0: classes in sorted order (the full radix sort). kMode 1 (256
 // buckets): every block turns the per-bucket class, bit and fault counts into
 // offsets itself (thread t: bucket t). kMode 2 (16-bit buckets): k_slot_map
@@ -1652,7 +1642,6 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
   __shared__ uint32_t s_cls[kBuckets + 1];
   __shared__ uint32_t s_bit[kBuckets];
   __shared__ uint32_t s_fst[kBuckets];
-  __shared__ uint32_t s_bfo[kLofsMax];
   __shared__ uint32_t s_wave[kBlock / 64];
   __shared__ uint32_t s_bfb[kBranchLds];  // first fault of each circuit of the batch
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1673,10 +1662,6 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
     S = st.hdr->n_seg;
     NB = st.hdr->n_bits;
   }
-  // a single circuit searches its boundary offsets in LDS when they fit
-  const bool bfo_lds = st.n_branch == 1 && st.n_layers + 2 <= uint32_t(kLofsMax);
-  if (bfo_lds)
-    for (uint32_t k = threadIdx.x; k < st.n_layers + 2; k += blockDim.x) s_bfo[k] = st.bnd_fault_off[k];
   const bool bfb_lds = st.n_branch <= uint32_t(kBranchLds);
   if (bfb_lds)
     for (uint32_t k = threadIdx.x; k < st.n_branch; k += blockDim.x) s_bfb[k] = st.branch[k].fb;
@@ -1718,7 +1703,8 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
     st.e_cnt[e] = (e + 1 < S ? st.segstart[e + 1] : st.hdr->n_live) - st.segstart[e];
   }
   const uint32_t pos = st.seg_rep[s];
-  const uint32_t cnt = kMode != 0 ? st.popc[pos] : st.seg_cnt[s];
+  const EdgeRec er = st.erec[pos];
+  const uint32_t cnt = kMode != 0 ? er.popc : st.seg_cnt[s];
   if (uint64_t(o0) + cnt > st.bits_cap) return;
   // the representative's circuit (last one whose first fault is <= pos) and boundary
   uint32_t bi = 0;
@@ -1733,8 +1719,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
   }
   const BranchDesc br = st.branch[bi];
   st.edge_branch[e] = bi;
-  const uint32_t b =
-      br.bb + boundary_of(bfo_lds ? s_bfo : st.bnd_fault_off + br.bb, br.n_layers + 1, pos);
+  const uint32_t b = er.bnd;  // the representative's boundary row
   const uint32_t n = st.ncov[b];
   const uint32_t* cl = st.cov + size_t(b) * st.w_max;
   uint32_t o = o0;
@@ -1750,7 +1735,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
   };
   if (n <= 64) {
     // the mask names the covered columns that hold non-zero words
-    uint64_t mask = st.nzm[pos];
+    uint64_t mask = er.nzm;
     while (mask) {
       const uint32_t k = uint32_t(__builtin_ctzll(mask));
       mask &= mask - 1;
