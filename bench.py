@@ -86,7 +86,7 @@ def kernel_bytes(name: str, info: dict) -> float:
     if name == "k_sweep":
         return 8.0 * nz + words / 8.0           # non-zero words + one bitmap bit per word
     if name == "k_hash":
-        return 8.0 * nz + words / 8.0 + F * (8 + 8 + 4 + 8)  # read both; key, check, weight, mask written
+        return 8.0 * nz + words / 8.0 + F * (8 + 8 + 4 + 16)  # read both; key, check, weight, edge record written
     if name == "k_bucket":
         return live * (8 + 4 + 4 + 16) + U * (8 + 4 + 4)     # keys, positions, gathers; class records
     if name == "k_compact":
