@@ -146,6 +146,20 @@ int gp_lower(gp_driver* drv, const char* text, size_t len, const double* rates, 
 int gp_run(gp_driver* drv);
 int gp_fetch(gp_driver* drv, gp_edges** out);
 
+/* Fetch of a single circuit's result into caller-owned host arrays, with one
+ * host copy. gp_fetch_sizes does what gp_fetch does up to the download (wait,
+ * error flags, retries; the same status codes) and returns the hyperedge and
+ * signature-bit counts (n_det, n_obs: the circuit's detector and observable
+ * counts; may be NULL). gp_fetch_copy then fills offsets (n_edges + 1 entries,
+ * edge e's bits are bits[offsets[e] .. offsets[e+1])), bits (n_bits) and q
+ * (n_edges), laid out as gp_edges_offsets/bits/probabilities; it may be called
+ * again until the next gp_lower, gp_run or fetch. GP_E_STATE for a batch
+ * lowering (use gp_fetch) and for gp_fetch_copy without a current
+ * gp_fetch_sizes. Rate refreshes and the adjoint work after it as after
+ * gp_fetch. */
+int gp_fetch_sizes(gp_driver* drv, uint64_t* n_edges, uint64_t* n_bits, uint32_t* n_det, uint32_t* n_obs);
+int gp_fetch_copy(gp_driver* drv, uint64_t* offsets, uint32_t* bits, double* q);
+
 /* Lower n independent circuits as one batch; gp_run then compiles them all in
  * one pass of each stage and gp_fetch returns every circuit's hyperedges in
  * one gp_edges, tagged by circuit (gp_edges_circuit_ids). Each circuit is

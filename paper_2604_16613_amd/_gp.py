@@ -35,7 +35,7 @@ EXPORTS = (
     "gp_edges_circuit_offsets", "gp_server_create", "gp_server_submit", "gp_server_wait", "gp_server_stats",
     "gp_server_destroy", "gp_server_timing", "gp_debug_set_graph", "gp_autotune", "gp_set_fault_cost",
     "gp_debug_set_sweep_shape", "gp_autotune_batch", "gp_tuning_cache_size", "gp_tuning_cache_get",
-    "gp_tuning_cache_put", "gp_server_set_admission",
+    "gp_tuning_cache_put", "gp_server_set_admission", "gp_fetch_sizes", "gp_fetch_copy",
 )
 
 
@@ -169,6 +169,9 @@ def load():
         "gp_server_wait": ([_vp, _u64, ctypes.c_int64, ctypes.POINTER(_vp), ctypes.POINTER(_u64)], ctypes.c_int),
         "gp_server_stats": ([_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(_u64)], ctypes.c_int),
         "gp_server_set_admission": ([_vp, _u64, _u64], ctypes.c_int),
+        "gp_fetch_sizes": ([_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_uint32),
+                            ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
+        "gp_fetch_copy": ([_vp, _vp, _vp, _vp], ctypes.c_int),
         "gp_server_destroy": ([_vp], None),
         "gp_server_timing": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -286,6 +289,20 @@ def gp_fetch(drv: int) -> int:
     h = _vp()
     _check(load().gp_fetch(drv, ctypes.byref(h)))
     return h.value
+
+
+def gp_fetch_arrays(drv: int):
+    """Single-circuit result with one host copy -> (n_det, n_obs, offsets, bits, q)."""
+    lib = load()
+    U, nb = _u64(), _u64()
+    nd, no = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib.gp_fetch_sizes(drv, ctypes.byref(U), ctypes.byref(nb), ctypes.byref(nd), ctypes.byref(no)))
+    off = np.empty(U.value + 1, dtype=np.uint64)
+    bits = np.empty(nb.value, dtype=np.uint32)
+    q = np.empty(U.value, dtype=np.float64)
+    _check(lib.gp_fetch_copy(drv, off.ctypes.data, bits.ctypes.data if nb.value else None,
+                             q.ctypes.data if U.value else None))
+    return nd.value, no.value, off, bits, q
 
 
 def gp_sync(drv: int) -> None:

@@ -74,6 +74,7 @@ class Driver:
 
     def __init__(self, bounds: _gp.GpBounds, device: int = 0):
         self.bounds = bounds
+        self._batch = False  # the current lowering is a batch (fetched with gp_fetch)
         self.handle = _gp.gp_driver_create(bounds, device)
 
     @classmethod
@@ -104,7 +105,9 @@ class Driver:
 
     # whole path
     def compile_hypergraph(self, circuit: str, rates: Optional[Sequence[float]] = None) -> Hypergraph:
-        return _take(_gp.gp_compile_hypergraph(self.handle, circuit, rates))
+        self.lower(circuit, rates)
+        self.run()
+        return self.fetch()
 
     def compile_detector_error_model(self, circuit: str, rates: Optional[Sequence[float]] = None) -> str:
         h = _gp.gp_compile_hypergraph(self.handle, circuit, rates)
@@ -123,10 +126,12 @@ class Driver:
 
     # split path
     def lower(self, circuit: str, rates: Optional[Sequence[float]] = None) -> None:
+        self._batch = False
         _gp.gp_lower(self.handle, circuit, rates)
 
     def lower_batch(self, circuits: Sequence[str],
                     rates: Optional[Sequence[Optional[Sequence[float]]]] = None) -> None:
+        self._batch = True
         _gp.gp_lower_batch(self.handle, circuits, rates)
 
     def fetch_batch(self) -> List[Hypergraph]:
@@ -139,7 +144,12 @@ class Driver:
         _gp.gp_sync(self.handle)
 
     def fetch(self) -> Hypergraph:
-        return _take(_gp.gp_fetch(self.handle))
+        """The current compile's hyperedges (a batch: all circuits', listed
+        circuit by circuit, as one Hypergraph; see fetch_batch)."""
+        if self._batch:
+            return _take(_gp.gp_fetch(self.handle))
+        nd, no, off, bits, q = _gp.gp_fetch_arrays(self.handle)
+        return Hypergraph(n_detectors=nd, n_observables=no, offsets=off, bits=bits, q=q)
 
     def info(self) -> dict:
         return _gp.gp_circuit_info_get(self.handle).as_dict()

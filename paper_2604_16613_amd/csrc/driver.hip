@@ -167,6 +167,12 @@ struct gp_driver {
   bool structured = false;     // a fetched compile left its class structure on the device
   uint64_t struct_edges = 0;   // hyperedges of that compile
   std::vector<uint32_t> edge_perm;  // batch: device hyperedge of each fetched one (empty: same order)
+  // a downloaded single-circuit result in the pinned staging buffer (gp_fetch_sizes)
+  bool staged_ok = false;
+  uint64_t staged_U = 0, staged_nb = 0;
+  const uint32_t* staged_off = nullptr;
+  const uint32_t* staged_bits = nullptr;
+  const double* staged_q = nullptr;
   gp::DevState st{};
 
   uint32_t key_bits = 64;      // test hook: class keys cut to this many bits
@@ -622,6 +628,7 @@ static int upload_lowered(gp_driver* d) {
 
 int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, size_t n_rates) {
   if (!d || !text) return fail(GP_E_ARG, "null argument");
+  d->staged_ok = false;
   gp::LowerError err{};
   d->lowered = false;
   d->ran = false;
@@ -634,6 +641,7 @@ int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, si
 int gp_lower_batch(gp_driver* d, const char* const* texts, const size_t* lens, const double* const* rates,
                    const size_t* n_rates, size_t n) {
   if (!d) return fail(GP_E_ARG, "null driver");
+  d->staged_ok = false;
   d->lowered = false;
   d->ran = false;
   d->structured = false;
@@ -645,6 +653,7 @@ int gp_lower_batch(gp_driver* d, const char* const* texts, const size_t* lens, c
 int gp_run(gp_driver* d) {
   if (!d) return fail(GP_E_ARG, "null driver");
   if (!d->lowered) return fail(GP_E_STATE, "gp_run before gp_lower");
+  d->staged_ok = false;
   HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
   gp::LaunchHook hook;
   if (d->timing) {
@@ -942,9 +951,49 @@ static int fetch_staged(gp_driver* d, Staged& out) {
   return GP_OK;
 }
 
+int gp_fetch_sizes(gp_driver* d, uint64_t* n_edges, uint64_t* n_bits, uint32_t* n_det, uint32_t* n_obs) {
+  if (!d || !n_edges || !n_bits) return fail(GP_E_ARG, "null argument");
+  d->staged_ok = false;
+  if (d->lw.branches.size() > 1) return fail(GP_E_STATE, "a batch result is fetched with gp_fetch");
+  Staged sg;
+  int rc = fetch_staged(d, sg);
+  if (rc) return rc;
+  d->staged_U = sg.U;
+  d->staged_nb = sg.nb;
+  d->staged_off = sg.off32;
+  d->staged_bits = sg.bits32;
+  d->staged_q = sg.q64;
+  d->staged_ok = true;
+  d->edge_perm.clear();
+  d->structured = true;
+  d->struct_edges = sg.U;
+  *n_edges = sg.U;
+  *n_bits = sg.nb;
+  if (n_det) *n_det = d->lw.n_det;
+  if (n_obs) *n_obs = d->lw.n_obs;
+  return GP_OK;
+}
+
+int gp_fetch_copy(gp_driver* d, uint64_t* offsets, uint32_t* bits, double* q) {
+  if (!d || !offsets) return fail(GP_E_ARG, "null argument");
+  if (!d->staged_ok) return fail(GP_E_STATE, "gp_fetch_copy without a current gp_fetch_sizes");
+  if ((!bits && d->staged_nb) || (!q && d->staged_U)) return fail(GP_E_ARG, "null argument");
+  const uint64_t U = d->staged_U, nb = d->staged_nb;
+  const size_t T = split_threads(U + nb / 2);
+  run_threads(T, [&](size_t t) {
+    for (uint64_t i = (U + 1) * t / T; i < (U + 1) * (t + 1) / T; i++) offsets[i] = d->staged_off[i];
+    const uint64_t b0 = nb * t / T, b1 = nb * (t + 1) / T;
+    if (b1 > b0) std::memcpy(bits + b0, d->staged_bits + b0, size_t(b1 - b0) * 4);
+    const uint64_t q0 = U * t / T, q1 = U * (t + 1) / T;
+    if (q1 > q0) std::memcpy(q + q0, d->staged_q + q0, size_t(q1 - q0) * 8);
+  });
+  return GP_OK;
+}
+
 int gp_fetch(gp_driver* d, gp_edges** out) {
   if (!d || !out) return fail(GP_E_ARG, "null argument");
   *out = nullptr;
+  d->staged_ok = false;
   Staged sg;
   int rc = fetch_staged(d, sg);
   if (rc) return rc;
@@ -1269,6 +1318,7 @@ int driver_fetch_split(gp_driver* d, std::vector<gp_edges*>& out, uint64_t* wait
   const auto t0 = std::chrono::steady_clock::now();
   Staged sg;
   sg.t_ready = sg.t_loaded = t0;
+  d->staged_ok = false;
   int rc = fetch_staged(d, sg);
   if (wait_ns) {
     wait_ns[0] = uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(sg.t_ready - t0).count());

@@ -361,3 +361,39 @@ def test_autotune_keeps_results(drv25):
     finally:
         _gp.gp_set_fault_cost(drv25.handle, 6.2e-4)
         _gp.gp_debug_set_sweep_shape(drv25.handle, 0)
+
+
+def test_fetch_into_caller_arrays(drv25):
+    """gp_fetch_sizes + gp_fetch_copy give exactly gp_fetch's arrays; the copy
+    needs a current gp_fetch_sizes (GP_E_STATE after a new run), and a batch
+    lowering is fetched with gp_fetch only."""
+    import ctypes
+    say("case fetch into caller arrays")
+    c = rotated_surface_code_memory(11, 11)
+    rates = log_uniform_rates(c.n_channels, 4)
+    drv25.lower(c.text, rates)
+    drv25.run()
+    h = _gp.gp_fetch(drv25.handle)
+    try:
+        off, bits, q = _gp.gp_edges_offsets(h), _gp.gp_edges_bits(h), _gp.gp_edges_probabilities(h)
+        nd, no = _gp.gp_edges_detectors(h), _gp.gp_edges_observables(h)
+    finally:
+        _gp.gp_edges_free(h)
+    drv25.run()
+    nd2, no2, off2, bits2, q2 = _gp.gp_fetch_arrays(drv25.handle)
+    assert (nd2, no2) == (nd, no)
+    assert np.array_equal(off2, off) and np.array_equal(bits2, bits)
+    assert np.array_equal(q2.view(np.uint64), q.view(np.uint64))
+    hg = drv25.fetch()
+    assert_parity(hg, oracle.run(c.text, rates=rates), "fetch into caller arrays")
+    lib = _gp.load()
+    buf = np.empty(len(off), dtype=np.uint64)
+    drv25.run()
+    assert lib.gp_fetch_copy(drv25.handle, buf.ctypes.data, None, None) == -10
+    drv25.fetch()
+    with Driver.from_batch([c.text, c.text]) as bd:
+        bd.lower_batch([c.text, c.text])
+        bd.run()
+        U, nb = ctypes.c_uint64(), ctypes.c_uint64()
+        assert lib.gp_fetch_sizes(bd.handle, ctypes.byref(U), ctypes.byref(nb), None, None) == -10
+        assert len(bd.fetch_batch()) == 2
