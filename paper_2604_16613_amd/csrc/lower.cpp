@@ -385,6 +385,57 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
   lw.wo = (n_obs + 63) / 64;
   lw.w = lw.wd + lw.wo;
 
+  // ---- channels sorted by boundary (stable), fault positions; on a second
+  // thread for large circuits, beside the op sort and the leaves
+  auto channel_phase = [&](LowerError& e) -> int {
+    const size_t C = chans.size();
+    if (rates) {
+      if (n_rates != C) {
+        char buf[128];
+        std::snprintf(buf, sizeof buf, "rate array has %zu entries, circuit has %zu channels", n_rates, C);
+        return set_err(e, GP_E_NOISE, 0, "%s", buf);
+      }
+      for (size_t k = 0; k < C; k++) {
+        double r = rates[k];
+        if (!(r >= 0.0 && r <= rate_limit(chans[k].kind))) return set_err(e, GP_E_NOISE, 0, "%s", "rate out of range");
+        chans[k].rate = r;
+      }
+    }
+    lw.bnd_chan_off.assign(size_t(L) + 2, 0);
+    for (const RawChan& c : chans) lw.bnd_chan_off[c.boundary + 1]++;
+    for (uint32_t b = 0; b <= L; b++) lw.bnd_chan_off[b + 1] += lw.bnd_chan_off[b];
+    lw.chan_qa.resize(C);
+    lw.chan_qb.resize(C);
+    lw.chan_kind.resize(C);
+    lw.chan_rate.resize(C);
+    lw.chan_src.resize(C);
+    {
+      std::vector<uint32_t> fill(lw.bnd_chan_off.begin(), lw.bnd_chan_off.end() - 1);
+      for (size_t k = 0; k < C; k++) {
+        uint32_t d = fill[chans[k].boundary]++;
+        lw.chan_qa[d] = chans[k].qa;
+        lw.chan_qb[d] = chans[k].qb;
+        lw.chan_kind[d] = chans[k].kind;
+        lw.chan_rate[d] = chans[k].rate;
+        lw.chan_src[d] = uint32_t(k);
+      }
+    }
+    uint64_t total_faults = 0;
+    for (size_t c = 0; c < C; c++) total_faults += kKeptCodes.n[lw.chan_kind[c]][lw.level];
+    if (total_faults >= (1ull << 32)) return set_err(e, GP_E_BOUNDS, 0, "%s", "more than 2^32 - 1 faults");
+    lw.chan_foff.assign(C + 1, 0);
+    for (size_t c = 0; c < C; c++) lw.chan_foff[c + 1] = lw.chan_foff[c] + kKeptCodes.n[lw.chan_kind[c]][lw.level];
+    lw.n_faults = total_faults;
+    lw.bnd_fault_off.assign(size_t(L) + 2, 0);
+    for (uint32_t b = 0; b <= L + 1; b++) lw.bnd_fault_off[b] = lw.chan_foff[lw.bnd_chan_off[b]];
+    return 0;
+  };
+  LowerError ch_err{};
+  int ch_rc = 0;
+  const bool two_threads = chans.size() + op_word.size() > (size_t(1) << 16);
+  std::thread ch_thread;
+  if (two_threads) ch_thread = std::thread([&] { ch_rc = channel_phase(ch_err); });
+
   // ---- operations sorted by layer (counting sort keeps program order)
   lw.layer_off.assign(size_t(L) + 1, 0);
   for (uint32_t l : op_layer) lw.layer_off[l + 1]++;
@@ -425,47 +476,12 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
   }
   for (uint32_t m = 0; m < n_meas; m++) lw.leaf_off[m + 1] += lw.leaf_off[m];
 
-  // ---- channels sorted by boundary (stable), fault positions
-  const size_t C = chans.size();
-  if (rates) {
-    if (n_rates != C) {
-      char buf[128];
-      std::snprintf(buf, sizeof buf, "rate array has %zu entries, circuit has %zu channels", n_rates, C);
-      return set_err(err, GP_E_NOISE, 0, "%s", buf);
-    }
-    for (size_t k = 0; k < C; k++) {
-      double r = rates[k];
-      if (!(r >= 0.0 && r <= rate_limit(chans[k].kind))) return set_err(err, GP_E_NOISE, 0, "%s", "rate out of range");
-      chans[k].rate = r;
-    }
+  if (two_threads) ch_thread.join();
+  else ch_rc = channel_phase(ch_err);
+  if (ch_rc) {
+    err = ch_err;
+    return ch_rc;
   }
-  lw.bnd_chan_off.assign(size_t(L) + 2, 0);
-  for (const RawChan& c : chans) lw.bnd_chan_off[c.boundary + 1]++;
-  for (uint32_t b = 0; b <= L; b++) lw.bnd_chan_off[b + 1] += lw.bnd_chan_off[b];
-  lw.chan_qa.resize(C);
-  lw.chan_qb.resize(C);
-  lw.chan_kind.resize(C);
-  lw.chan_rate.resize(C);
-  lw.chan_src.resize(C);
-  {
-    std::vector<uint32_t> fill(lw.bnd_chan_off.begin(), lw.bnd_chan_off.end() - 1);
-    for (size_t k = 0; k < C; k++) {
-      uint32_t d = fill[chans[k].boundary]++;
-      lw.chan_qa[d] = chans[k].qa;
-      lw.chan_qb[d] = chans[k].qb;
-      lw.chan_kind[d] = chans[k].kind;
-      lw.chan_rate[d] = chans[k].rate;
-      lw.chan_src[d] = uint32_t(k);
-    }
-  }
-  uint64_t total_faults = 0;
-  for (size_t c = 0; c < C; c++) total_faults += kKeptCodes.n[lw.chan_kind[c]][lw.level];
-  if (total_faults >= (1ull << 32)) return set_err(err, GP_E_BOUNDS, 0, "%s", "more than 2^32 - 1 faults");
-  lw.chan_foff.assign(C + 1, 0);
-  for (size_t c = 0; c < C; c++) lw.chan_foff[c + 1] = lw.chan_foff[c] + kKeptCodes.n[lw.chan_kind[c]][lw.level];
-  lw.n_faults = total_faults;
-  lw.bnd_fault_off.assign(size_t(L) + 2, 0);
-  for (uint32_t b = 0; b <= L + 1; b++) lw.bnd_fault_off[b] = lw.chan_foff[lw.bnd_chan_off[b]];
 
   // ---- word columns: static live range from the layers of their leaves
   lw.col_top.assign(lw.w, -1);
@@ -495,6 +511,68 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
     if (lw.col_top[w] >= 0) bm += lw.bnd_bm_off[lw.col_top[w] + 1];
   }
   lw.bm_words = bm;
+
+  // ---- per-column leaf injections, top layer first (on a second thread for
+  // large circuits, beside the items, windows and compact ops)
+  auto injection_phase = [&]() {
+    {
+      std::vector<uint32_t> meas_qubit(n_meas, 0);
+      for (uint64_t op : lw.ops) {
+        const uint32_t kind = uint32_t(op >> 56);
+        if (kind >= OP_M) meas_qubit[uint32_t(op) & kField] = uint32_t(op >> 28) & kField;
+      }
+      struct Inj {
+        uint32_t w, layer, qubit, m;
+        uint64_t word;
+      };
+      std::vector<Inj> inj;
+      for (uint32_t m = 0; m < n_meas; m++) {
+        for (uint32_t k = lw.leaf_off[m]; k < lw.leaf_off[m + 1]; k++) {
+          const uint32_t bit = lw.leaf_bits[k];
+          const uint32_t w = bit >> 6;
+          if (!inj.empty() && inj.back().m == m && inj.back().w == w) {
+            inj.back().word |= 1ull << (bit & 63);
+          } else {
+            inj.push_back(Inj{w, lw.meas_layer[m], meas_qubit[m], m, 1ull << (bit & 63)});
+          }
+        }
+      }
+      // by column (a stable counting sort), then by layer, top first, within
+      // each column (stable: equal layers keep measurement order)
+      lw.inj_off.assign(size_t(lw.w) + 1, 0);
+      for (const Inj& e : inj) lw.inj_off[e.w + 1]++;
+      for (uint32_t w = 0; w < lw.w; w++) lw.inj_off[w + 1] += lw.inj_off[w];
+      {
+        std::vector<Inj> by_col(inj.size());
+        std::vector<uint32_t> fill(lw.inj_off.begin(), lw.inj_off.end() - 1);
+        for (const Inj& e : inj) by_col[fill[e.w]++] = e;
+        for (uint32_t w = 0; w < lw.w; w++)
+          std::stable_sort(by_col.begin() + lw.inj_off[w], by_col.begin() + lw.inj_off[w + 1],
+                           [](const Inj& x, const Inj& y) { return x.layer > y.layer; });
+        inj.swap(by_col);
+      }
+      lw.inj_layer.resize(inj.size());
+      lw.inj_qubit.resize(inj.size());
+      lw.inj_word.resize(inj.size());
+      for (size_t k = 0; k < inj.size(); k++) {
+        lw.inj_layer[k] = inj[k].layer;
+        lw.inj_qubit[k] = inj[k].qubit;
+        lw.inj_word[k] = inj[k].word;
+      }
+      lw.inj_next.resize(inj.size());
+      for (uint32_t w = 0; w < lw.w; w++) {
+        const uint32_t a = lw.inj_off[w], e = lw.inj_off[w + 1];
+        uint32_t next = e - a;
+        for (uint32_t k = e; k-- > a;) {
+          if (k + 1 < e && lw.inj_layer[k + 1] != lw.inj_layer[k]) next = k + 1 - a;
+          lw.inj_next[k] = next;
+        }
+      }
+    }
+  };
+  std::thread inj_thread;
+  if (two_threads) inj_thread = std::thread(injection_phase);
+  else injection_phase();
 
   // ---- sweep items: one per detector column; observable columns, which stay
   // live over the whole circuit, are cut into boundary ranges so that their
@@ -593,62 +671,6 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
                                                                          : 0xFFFFFFFFu;
   }
 
-  // ---- per-column leaf injections, top layer first
-  {
-    std::vector<uint32_t> meas_qubit(n_meas, 0);
-    for (uint64_t op : lw.ops) {
-      const uint32_t kind = uint32_t(op >> 56);
-      if (kind >= OP_M) meas_qubit[uint32_t(op) & kField] = uint32_t(op >> 28) & kField;
-    }
-    struct Inj {
-      uint32_t w, layer, qubit, m;
-      uint64_t word;
-    };
-    std::vector<Inj> inj;
-    for (uint32_t m = 0; m < n_meas; m++) {
-      for (uint32_t k = lw.leaf_off[m]; k < lw.leaf_off[m + 1]; k++) {
-        const uint32_t bit = lw.leaf_bits[k];
-        const uint32_t w = bit >> 6;
-        if (!inj.empty() && inj.back().m == m && inj.back().w == w) {
-          inj.back().word |= 1ull << (bit & 63);
-        } else {
-          inj.push_back(Inj{w, lw.meas_layer[m], meas_qubit[m], m, 1ull << (bit & 63)});
-        }
-      }
-    }
-    // by column (a stable counting sort), then by layer, top first, within
-    // each column (stable: equal layers keep measurement order)
-    lw.inj_off.assign(size_t(lw.w) + 1, 0);
-    for (const Inj& e : inj) lw.inj_off[e.w + 1]++;
-    for (uint32_t w = 0; w < lw.w; w++) lw.inj_off[w + 1] += lw.inj_off[w];
-    {
-      std::vector<Inj> by_col(inj.size());
-      std::vector<uint32_t> fill(lw.inj_off.begin(), lw.inj_off.end() - 1);
-      for (const Inj& e : inj) by_col[fill[e.w]++] = e;
-      for (uint32_t w = 0; w < lw.w; w++)
-        std::stable_sort(by_col.begin() + lw.inj_off[w], by_col.begin() + lw.inj_off[w + 1],
-                         [](const Inj& x, const Inj& y) { return x.layer > y.layer; });
-      inj.swap(by_col);
-    }
-    lw.inj_layer.resize(inj.size());
-    lw.inj_qubit.resize(inj.size());
-    lw.inj_word.resize(inj.size());
-    for (size_t k = 0; k < inj.size(); k++) {
-      lw.inj_layer[k] = inj[k].layer;
-      lw.inj_qubit[k] = inj[k].qubit;
-      lw.inj_word[k] = inj[k].word;
-    }
-    lw.inj_next.resize(inj.size());
-    for (uint32_t w = 0; w < lw.w; w++) {
-      const uint32_t a = lw.inj_off[w], e = lw.inj_off[w + 1];
-      uint32_t next = e - a;
-      for (uint32_t k = e; k-- > a;) {
-        if (k + 1 < e && lw.inj_layer[k + 1] != lw.inj_layer[k]) next = k + 1 - a;
-        lw.inj_next[k] = next;
-      }
-    }
-  }
-
   // ---- hash chunks: 256 positions of one boundary at most
   for (uint32_t b = 0; b <= L; b++)
     for (uint32_t p0 = lw.bnd_fault_off[b]; p0 < lw.bnd_fault_off[b + 1]; p0 += 256) {
@@ -683,6 +705,7 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
   lw.hchunk_branch.assign(lw.hchunk_pos.size(), 0);
   // layer windows share the layer-offset indexing (n_layers + 1 entries)
   lw.layer_win.resize(size_t(lw.n_layers) + 1, 0);
+  if (inj_thread.joinable()) inj_thread.join();
   return 0;
 }
 
