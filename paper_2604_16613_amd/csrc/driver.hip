@@ -457,7 +457,7 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   if ((rc = dev_alloc(d, &st.popc, F, "signature weights"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.erec, F, "edge records"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.tile_cnt, size_t(d->max_tiles) + 1, "tile counts"))) return cleanup(rc);
-  if ((rc = dev_alloc(d, &st.tile_nz, size_t(d->max_tiles) + 1, "tile non-zero word counts"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.tile_nzw, size_t(d->max_tiles) + 1, "tile word counts"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.digit_tot, size_t(gp::kMaxPasses) * 256, "digit totals"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.lookback, size_t(gp::kMaxPasses) * d->max_tiles * 256, "look-back words")))
     return cleanup(rc);

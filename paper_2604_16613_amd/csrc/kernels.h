@@ -140,7 +140,7 @@ struct DevState {
   uint32_t* popc;        // per fault position: signature weight
   EdgeRec* erec;         // per fault position: non-zero-word mask, weight, boundary row
   uint32_t* tile_cnt;    // per compaction tile: live faults, then their exclusive prefix
-  uint32_t* tile_nz;     // per compaction tile: non-zero signature words
+  uint64_t* tile_nzw;    // per compaction tile: non-zero signature words | (fault, covered column) pairs read << 32
   uint32_t* digit_tot;   // per pass: total count of each digit value (summed by the compaction tiles)
   uint32_t* lookback;    // per pass, tile and digit: published count with status bits
   uint32_t* tile_ctr;    // per pass: tile ticket counter

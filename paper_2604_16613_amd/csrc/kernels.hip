@@ -201,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_prepare(DevState st) {
   const uint32_t ntiles = (st.n_faults + kTile - 1) / kTile;
   for (uint32_t t = gid; t < ntiles + 1; t += stride) {
     st.tile_cnt[t] = 0;
-    st.tile_nz[t] = 0;
+    st.tile_nzw[t] = 0;
   }
   // look-back words of every pass (each pass owns max_tiles * 256 of them)
   const uint32_t per_pass = ntiles * 256;
@@ -675,12 +675,7 @@ __global__ __launch_bounds__(kBlock) void k_hash(DevState st) {
     n += s_wave[kBlock / 64];
     __syncthreads();
   }
-  if (first_chunk && threadIdx.x == 0) {
-    st.ncov[gb] = n;
-    // (fault, column) pairs of this boundary in the swept windows
-    const uint64_t words = uint64_t(n) * (st.bnd_fault_off[gb + 1] - fb);
-    if (words) atomicAdd(reinterpret_cast<unsigned long long*>(&st.hdr->n_words), (unsigned long long)words);
-  }
+  if (first_chunk && threadIdx.x == 0) st.ncov[gb] = n;
   for (uint32_t i = threadIdx.x; i < n * kHashBmw; i += kBlock) {
     const uint32_t k = i / kHashBmw, j = i % kHashBmw;
     s_bm[i] = wb0 + j < nwb ? st.bm[s_bmb[k] + wb0 + j] : 0ull;
@@ -764,8 +759,14 @@ __global__ __launch_bounds__(kBlock) void k_hash(DevState st) {
   __syncthreads();
   if (threadIdx.x == 0 && s_cnt[0]) atomicAdd(&st.tile_cnt[ta], s_cnt[0]);
   if (threadIdx.x == 1 && s_cnt[1]) atomicAdd(&st.tile_cnt[ta + 1], s_cnt[1]);
-  if (threadIdx.x == 2 && s_cnt[2]) atomicAdd(&st.tile_nz[ta], s_cnt[2]);
-  if (threadIdx.x == 3 && s_cnt[3]) atomicAdd(&st.tile_nz[ta + 1], s_cnt[3]);
+  // per tile: non-zero words (low half) and the (fault, covered column)
+  // pairs this chunk read (high half), in one 64-bit add; the compaction sums
+  // the tiles (one atomic per tile rather than one per boundary on a single
+  // counter)
+  const uint32_t in_tile_a = min(p1, (ta + 1) * uint32_t(kTile)) - p0;
+  const uint64_t w_a = uint64_t(n) * in_tile_a, w_b = uint64_t(n) * (p1 - p0 - in_tile_a);
+  if (threadIdx.x == 2 && (s_cnt[2] || w_a)) atomicAdd(&st.tile_nzw[ta], (w_a << 32) | s_cnt[2]);
+  if (threadIdx.x == 3 && (s_cnt[3] || w_b)) atomicAdd(&st.tile_nzw[ta + 1], (w_b << 32) | s_cnt[3]);
 }
 
 // In-place exclusive scan of n (host value, or *n_dev when given) words by one
@@ -840,8 +841,12 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(DevState st, uint32_t
     if (threadIdx.x == 0 && tile + 1 == gridDim.x) st.hdr->n_live = tb + st.tile_cnt[tile];
   }
   const uint32_t P = st.n_pass;
-  if (threadIdx.x == 0 && st.tile_nz[tile])
-    atomicAdd(reinterpret_cast<unsigned long long*>(&st.hdr->n_nz_words), (unsigned long long)st.tile_nz[tile]);
+  if (threadIdx.x == 0 || threadIdx.x == 1) {
+    const uint64_t nzw = st.tile_nzw[tile];
+    const uint64_t v = threadIdx.x == 0 ? (nzw & 0xFFFFFFFFull) : (nzw >> 32);
+    if (v) atomicAdd(reinterpret_cast<unsigned long long*>(threadIdx.x == 0 ? &st.hdr->n_nz_words : &st.hdr->n_words),
+                     (unsigned long long)v);
+  }
 #pragma unroll
   for (int k = 0; k < kCompactRounds; ++k) {
     const bool live = (flags >> k) & 1u;

@@ -130,7 +130,11 @@ def test_surface_code_d25(drv25, seed):
     c = rotated_surface_code_memory(25, 25)
     rates = None if seed is None else log_uniform_rates(c.n_channels, seed)
     check(drv25, c.text, rates, label=f"sc25 seed{seed}")
-    assert drv25.info()["n_faults"] == 1013572
+    info = drv25.info()
+    assert info["n_faults"] == 1013572
+    # (fault, column) pairs the hash read, summed per compaction tile: the
+    # value the earlier single-counter sum gave for this circuit and range cut
+    assert info["n_live_words"] == 30459023
 
 
 def test_deterministic_and_split_path(drv25):
