@@ -317,9 +317,16 @@ def test_batch_past_the_256_buckets(d, n, b16):
     say("case past the 256 buckets", d, n)
     with Driver.from_batch(texts) as drv:
         got = drv.compile_batch(texts)
-        F = drv.info()["n_faults"]
+        info = drv.info()
+        F = info["n_faults"]
         assert F > 1572864 and (F >= 12000000) == b16
         for k in (0, n // 2, n - 1):
             assert_same(got[k], oracle.run(texts[k]), f"branch {k} vs oracle")
+        live = nz = 0
         for k, t in enumerate(texts):
             assert_same(got[k], drv.compile_hypergraph(t), f"branch {k} vs single", exact=True)
+            live += drv.info()["n_live_faults"]
+            nz += drv.info()["n_nonzero_words"]
+        # the batch's counters (summed per compaction tile; over 1024 tiles by
+        # the tile-prefix pass) equal the sums over the circuits
+        assert (info["n_live_faults"], info["n_nonzero_words"]) == (live, nz)
