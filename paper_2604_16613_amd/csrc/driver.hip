@@ -127,8 +127,15 @@ void run_threads(size_t T, F&& fn) {
     fn(size_t(0));
     return;
   }
+  // a thread that cannot be started runs its share here instead
   std::vector<std::thread> pool;
-  for (size_t t = 0; t < T; t++) pool.emplace_back(fn, t);
+  for (size_t t = 0; t < T; t++) {
+    try {
+      pool.emplace_back(fn, t);
+    } catch (...) {
+      fn(t);
+    }
+  }
   for (std::thread& th : pool) th.join();
 }
 
@@ -340,7 +347,14 @@ int lower_batch(const char* const* texts, const size_t* lens, const double* cons
     lower_range(0, n);
   } else {
     std::vector<std::thread> pool;
-    for (size_t t = 0; t < n_threads; t++) pool.emplace_back(lower_range, n * t / n_threads, n * (t + 1) / n_threads);
+    for (size_t t = 0; t < n_threads; t++) {
+      const size_t a = n * t / n_threads, b = n * (t + 1) / n_threads;
+      try {
+        pool.emplace_back(lower_range, a, b);
+      } catch (...) {
+        lower_range(a, b);  // could not start a thread: lower this share here
+      }
+    }
     for (std::thread& th : pool) th.join();
   }
   for (size_t k = 0; k < n; k++)

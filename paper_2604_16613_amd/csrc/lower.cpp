@@ -261,7 +261,13 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
       tokenize(cut[0], cut[1], chunks[0]);
     } else {
       std::vector<std::thread> pool;
-      for (size_t k = 1; k < T; k++) pool.emplace_back(tokenize, cut[k], cut[k + 1], std::ref(chunks[k]));
+      for (size_t k = 1; k < T; k++) {
+        try {
+          pool.emplace_back(tokenize, cut[k], cut[k + 1], std::ref(chunks[k]));
+        } catch (...) {
+          tokenize(cut[k], cut[k + 1], chunks[k]);  // could not start a thread: tokenize here
+        }
+      }
       tokenize(cut[0], cut[1], chunks[0]);
       for (std::thread& th : pool) th.join();
     }
@@ -434,7 +440,15 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
   int ch_rc = 0;
   const bool two_threads = chans.size() + op_word.size() > (size_t(1) << 16);
   std::thread ch_thread;
-  if (two_threads) ch_thread = std::thread([&] { ch_rc = channel_phase(ch_err); });
+  bool ch_done = false;
+  if (two_threads) {
+    try {
+      ch_thread = std::thread([&] { ch_rc = channel_phase(ch_err); });
+    } catch (...) {
+      ch_rc = channel_phase(ch_err);  // could not start a thread: build the channel tables here
+      ch_done = true;
+    }
+  }
 
   // ---- operations sorted by layer (counting sort keeps program order)
   lw.layer_off.assign(size_t(L) + 1, 0);
@@ -476,8 +490,8 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
   }
   for (uint32_t m = 0; m < n_meas; m++) lw.leaf_off[m + 1] += lw.leaf_off[m];
 
-  if (two_threads) ch_thread.join();
-  else ch_rc = channel_phase(ch_err);
+  if (ch_thread.joinable()) ch_thread.join();
+  else if (!ch_done) ch_rc = channel_phase(ch_err);
   if (ch_rc) {
     err = ch_err;
     return ch_rc;
@@ -571,8 +585,15 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
     }
   };
   std::thread inj_thread;
-  if (two_threads) inj_thread = std::thread(injection_phase);
-  else injection_phase();
+  if (two_threads) {
+    try {
+      inj_thread = std::thread(injection_phase);
+    } catch (...) {
+      injection_phase();  // could not start a thread: build the lists here
+    }
+  } else {
+    injection_phase();
+  }
 
   // ---- sweep items: one per detector column; observable columns, which stay
   // live over the whole circuit, are cut into boundary ranges so that their

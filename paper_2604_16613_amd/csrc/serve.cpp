@@ -246,8 +246,13 @@ int gp_server_create(const gp_bounds* bounds, int device, gp_server** out) {
   }
   const uint32_t level = gp::driver_level(s->drv[0]);
   const size_t n_lower = std::min<size_t>(8, std::max<size_t>(1, std::thread::hardware_concurrency()));
-  for (size_t k = 0; k < n_lower; k++) s->lowerers.emplace_back(lower_loop, s, level);
-  s->worker = std::thread(worker_loop, s);
+  try {
+    for (size_t k = 0; k < n_lower; k++) s->lowerers.emplace_back(lower_loop, s, level);
+    s->worker = std::thread(worker_loop, s);
+  } catch (...) {
+    gp_server_destroy(s);  // stops and joins the threads that did start, frees the drivers
+    return gp::set_last_error(GP_E_OOM, "could not start the server's threads");
+  }
   *out = s;
   return GP_OK;
 }
