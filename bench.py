@@ -119,6 +119,9 @@ def main() -> int:
     ap.add_argument("--serve-distances", default="5,10",
                     help="outer distances of the served workload ('' skips it)")
     ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--batch-only", type=int, default=0, metavar="D",
+                    help="only time the batched workload at outer distance D (default launch choices, no "
+                         "per-branch comparison): the command a kernel trace of the batch runs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain streaming copy of MIB MiB five times (to scale HBM byte counters)")
     args = ap.parse_args()
@@ -129,6 +132,8 @@ def main() -> int:
 
     if args.copy_calibration:
         return copy_calibration(args.copy_calibration)
+    if args.batch_only:
+        return batch_only(args.batch_only, args.batch_branches, args.steps, args.warmup)
 
     from paper_2604_16613_amd import get_driver
 
@@ -376,6 +381,30 @@ def bench_batched(d: int, n_branches: int, steps: int) -> dict:
             "batched_kernels_ms": kt, "autotune": tuned,
             "timing": "device stages with tables resident (host wall clock over synced launches); "
                       "e2e = host lowering + upload + stages + download"}
+
+
+def batch_only(d: int, n_branches: int, steps: int, warmup: int) -> int:
+    """Device stages of the batched workload alone (default fault cost and
+    automatic work-group shape), for kernel traces: one JSON line."""
+    from paper_2604_16613_amd import Driver
+    from workloads import iceberg_surface_batch
+    texts = [c.text for c in iceberg_surface_batch(d, n_branches=n_branches, seed=0)]
+    drv = Driver.from_batch(texts)
+    drv.lower_batch(texts)
+    F = drv.info()["n_faults"]
+    for _ in range(max(warmup, 1)):
+        drv.run()
+    drv.fetch_batch()
+    drv.sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        drv.run()
+    drv.sync()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    drv.close()
+    print(json.dumps({"batch_only": f"iceberg_surface_d{d}: {n_branches} branches, d cycles, seeds 0..{n_branches - 1}",
+                      "faults": int(F), "ms_per_step": ms, "faults_per_s": F / (ms * 1e-3), "steps": steps}))
+    return 0
 
 
 def bench_serving(d: int, n_requests: int, rate_hz: float = 1000.0, pool: int = 64) -> dict:
