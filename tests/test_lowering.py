@@ -121,3 +121,29 @@ def test_error_lines_keep_program_order_across_chunks():
     mid = int(n * 0.5)
     two = lines[:mid] + ["CX 0"] + lines[mid:late] + ["H rec[-1]"] + lines[late:]
     assert f"line {mid + 1}: odd number of targets" in _error_line("\n".join(two))
+
+
+def test_tokenizer_chunks_ignore_layout():
+    """The same circuit written with CRLF line endings, comments, blank lines
+    and lower-case instruction names (a multi-chunk text) lowers to the same
+    signatures as the plain text."""
+    import random
+    c = rotated_surface_code_memory(17, 17)
+    rng = random.Random(9)
+    out = []
+    for ln in c.text.split("\n"):
+        if rng.random() < 0.05:
+            out.append("# a comment line")
+        if rng.random() < 0.05:
+            out.append("   ")
+        if ln and rng.random() < 0.3:
+            head, _, rest = ln.partition(" ")
+            ln = head.lower() + (" " + rest if rest else "")
+        if ln and rng.random() < 0.1:
+            ln += "  # trailing comment"
+        out.append(ln)
+    messy = "\r\n".join(out)
+    assert len(messy) > 4 * (1 << 17)
+    st_a, sig_a = host_check.run(c.text)
+    st_b, sig_b = host_check.run(messy)
+    assert st_a == st_b and sig_a == sig_b
