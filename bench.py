@@ -135,7 +135,7 @@ def main() -> int:
     if args.batch_only:
         return batch_only(args.batch_only, args.batch_branches, args.steps, args.warmup)
 
-    from paper_2604_16613_amd import get_driver
+    from paper_2604_16613_amd import _gp, get_driver
 
     circuit, rates, cfg = workload(args.workload)
     drv = get_driver(circuit.text)
@@ -155,6 +155,8 @@ def main() -> int:
     info = drv.info()
 
     # timed region: K device steps, inputs resident, bracketed by syncs
+    _gp.gp_debug_device_flags(drv.handle, clear_seen=True)
+    retries = _gp.gp_debug_retry_counts(drv.handle)
     drv.sync()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -163,6 +165,7 @@ def main() -> int:
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = F / (ms_per_step * 1e-3)
+    check_clean_steps(drv, retries, "the timed steps")
 
     # per-kernel HIP-event timings on the driver's stream (separate pass)
     drv.reset_timing()
@@ -263,15 +266,29 @@ def main() -> int:
     return 0
 
 
+def check_clean_steps(drv, retries_before: dict, what: str) -> None:
+    """After a loop of device runs: no run raised a device flag (collision,
+    bucket overflow, look-back give-up, capacity, non-deterministic detector)
+    and a fetch needs no re-run, so the time measured is the time of the
+    normal path and its result is valid; exits otherwise."""
+    from paper_2604_16613_amd import _gp
+    flags, seen = _gp.gp_debug_device_flags(drv.handle, clear_seen=True)
+    drv.fetch()
+    after = _gp.gp_debug_retry_counts(drv.handle)
+    if flags or seen or after != retries_before:
+        raise SystemExit(f"bench.py: {what} raised device flags {seen:#x} (last {flags:#x}) or needed re-runs "
+                         f"({retries_before} -> {after}); the timing is not of a valid compile")
+
+
 def bench_differentiation(get_driver, iters: int = 50) -> dict:
     """The differentiation workload: rotated surface code d = 9, 9 rounds,
     per-channel rates log-uniform in [1e-4, 5e-3) (seed 0). Times one device
     compile, one rate refresh over the fixed structure (per-fault
     probabilities + Eq. 3 over every hyperedge) and one adjoint (dL/dq up,
-    dL/d(rate) down), and checks the adjoint against the oracle."""
+    dL/d(rate) down). Its agreement with the oracle's gradient is a test
+    (tests/test_gpu_grad.py), not part of the benchmark."""
     from paper_2604_16613_amd import _gp
-    from workloads import log_uniform_rates, rotated_surface_code_memory
-    import oracle
+    from workloads import log_uniform_rates, logit_loss, rotated_surface_code_memory
     c = rotated_surface_code_memory(9, 9)
     rates = log_uniform_rates(c.n_channels, 0)
     drv = get_driver(c.text)
@@ -280,7 +297,7 @@ def bench_differentiation(get_driver, iters: int = 50) -> dict:
     sigs = [tuple(int(b) for b in hg.bits[hg.offsets[e]:hg.offsets[e + 1]]) for e in range(len(hg))]
     wmap = dict(zip(sorted(sigs), np.random.default_rng(1).uniform(-1.0, 1.0, len(sigs))))
     w = np.array([wmap[k] for k in sigs])
-    _, dl_dq = oracle.loss_and_dl_dq(hg.q, w)
+    _, dl_dq = logit_loss(hg.q, w)
 
     def timed(fn):
         fn()
@@ -297,17 +314,11 @@ def bench_differentiation(get_driver, iters: int = 50) -> dict:
     drv.fetch()
     refresh_ms = timed(lambda: _gp.gp_refresh_rates(drv.handle, rates))
     grad_ms = timed(lambda: drv.rates_gradient(dl_dq))
-    g = drv.rates_gradient(dl_dq)
-    res = oracle.run(c.text, rates=rates)
-    osigs = [tuple(int(b) for b in res.edge_bits[res.edge_off[e]:res.edge_off[e + 1]]) for e in range(res.n_edges)]
-    _, odl = oracle.loss_and_dl_dq(res.edge_q, np.array([wmap[k] for k in osigs]))
-    go = oracle.gradient(c.text, odl, rates=rates)
     drv.close()
     return {"workload": "sc_d9_r9 log-uniform rates seed 0, loss sum_k w_k log(q_k/(1-q_k)), w ~ U[-1,1] seed 1",
             "faults": int(F), "channels": int(c.n_channels), "hyperedges": len(hg),
             "compile_ms_median": compile_ms, "refresh_ms_median": refresh_ms,
             "gradient_ms_median": grad_ms, "refresh_faults_per_s": F / (refresh_ms * 1e-3),
-            "gradient_max_rel_err_vs_oracle": float(np.max(np.abs(g - go) / np.maximum(np.abs(go), 1e-300))),
             "timing": "host wall clock around each call + stream sync, median of %d" % iters}
 
 

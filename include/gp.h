@@ -62,7 +62,8 @@ enum {
   GP_E_OOM = -8,              /* host or device allocation failed */
   GP_E_COLLISION = -9,        /* two different signatures share both 64-bit hashes */
   GP_E_STATE = -10,           /* call out of order (e.g. gp_run before gp_lower) */
-  GP_E_BUSY = -11             /* the server holds its limit of requests or bytes: collect results, retry */
+  GP_E_BUSY = -11,            /* the server holds its limit of requests or bytes: collect results, retry */
+  GP_E_INTERNAL = -12         /* an unexpected internal failure (no result; the driver stays usable) */
 };
 
 typedef struct gp_driver gp_driver;
@@ -140,8 +141,10 @@ int gp_compile_hypergraph(gp_driver* drv, const char* text, size_t len,
  *   gp_run    -- enqueue stage 1 and stage 2 on the driver's stream; returns
  *                without waiting; may be called repeatedly on one lowering;
  *   gp_fetch  -- wait for the stream, check device-side error flags
- *                (GP_E_NONDETERMINISTIC, GP_E_COLLISION, GP_E_BOUNDS) and copy
- *                the hypergraph to a new host gp_edges. */
+ *                (GP_E_NONDETERMINISTIC, GP_E_COLLISION, GP_E_BOUNDS; GP_E_HIP
+ *                when a radix-sort tile gave up waiting for its predecessor
+ *                twice), redoing the compile where a flag calls for it, and
+ *                copy the hypergraph to a new host gp_edges. */
 int gp_lower(gp_driver* drv, const char* text, size_t len, const double* rates, size_t n_rates);
 int gp_run(gp_driver* drv);
 int gp_fetch(gp_driver* drv, gp_edges** out);
@@ -311,6 +314,29 @@ int gp_timing_entry(const gp_driver* drv, int index, const char** name,
  * again keyed on both hashes. gp_debug_collision_retries counts such re-runs. */
 int gp_debug_set_key_bits(gp_driver* drv, int bits);
 uint64_t gp_debug_collision_retries(const gp_driver* drv);
+
+/* Re-runs made by fetches so far, by cause: a radix-sort tile that gave up
+ * waiting for the tile before it (the same compile runs once more; a second
+ * give-up fails the fetch with GP_E_HIP and no result), a 256-bucket group too
+ * large for LDS (redone with the full sort), a key collision (redone keyed on
+ * both hashes). Any output may be NULL. */
+int gp_debug_retry_counts(const gp_driver* drv, uint64_t* lookback, uint64_t* bucket, uint64_t* collision);
+
+/* Test hook: look-back rounds a radix-sort tile waits for the tiles before it
+ * (each round reads up to 16 of them, then sleeps briefly) before giving up;
+ * default 2^22. With 0 every tile after the first gives up at once, so the
+ * fetch after a gp_run fails with GP_E_HIP; every kernel still ends normally
+ * (a give-up stops the grouping kernels that follow it). */
+int gp_debug_set_spin_limit(gp_driver* drv, uint32_t limit);
+
+/* Waits for the driver's stream and reads the device status flags: those of
+ * the last compile (*flags), and the union of those raised by every compile
+ * since the last clear (*flags_seen, which catches a flag raised by a compile
+ * whose result was never fetched, such as a timing loop of gp_run calls).
+ * Bits: 1 non-deterministic detector, 2 key collision, 4 output capacity,
+ * 8 sort look-back give-up, 16 bucket overflow. clear_seen != 0 clears the
+ * union afterwards. */
+int gp_debug_device_flags(gp_driver* drv, uint32_t* flags, uint32_t* flags_seen, int clear_seen);
 
 /* Test hook: stage-2 grouping method for later gp_run calls. 0 (default):
  * up to 1,572,864 faults one stable radix pass on the top 8-bit key digit

@@ -27,7 +27,7 @@ KIND = {"X_ERROR": 1, "Y_ERROR": 2, "Z_ERROR": 3, "DEPOLARIZE1": 4, "DEPOLARIZE2
 
 
 def build(verbose: bool = False) -> str:
-    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
+    cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-pthread",
            "-o", _LIB, _SRC, "-lm"]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -70,6 +70,10 @@ def _load():
                                    ctypes.c_int64, ctypes.c_int, ctypes.c_int64,
                                    ctypes.POINTER(ctypes.POINTER(_Result))]
         lib.oracle_run.restype = ctypes.c_int
+        lib.oracle_run_threads.argtypes = [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.c_int64, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+                                           ctypes.POINTER(ctypes.POINTER(_Result))]
+        lib.oracle_run_threads.restype = ctypes.c_int
         lib.oracle_free.argtypes = [ctypes.POINTER(_Result)]
         lib.oracle_free.restype = None
         lib.oracle_last_error.restype = ctypes.c_char_p
@@ -144,9 +148,10 @@ def _level(lib, level: int) -> None:
 
 
 def run(text: str, rates: Optional[Sequence[float]] = None, keep_faults: bool = False,
-        fault_stride: int = 1, level: int = 2) -> OracleResult:
+        fault_stride: int = 1, level: int = 2, threads: int = 1) -> OracleResult:
     """Compile `text` with the oracle. `rates`: optional per-channel rate array;
-    `level`: correlation level (Table 1), 2 = every Pauli."""
+    `level`: correlation level (Table 1), 2 = every Pauli; `threads`: host
+    threads for the forward tracking (the result is the same for any count)."""
     lib = _load()
     _level(lib, level)
     raw = text.encode()
@@ -157,7 +162,8 @@ def run(text: str, rates: Optional[Sequence[float]] = None, keep_faults: bool = 
         nr = len(r)
     else:
         rp, nr = None, 0
-    rc = lib.oracle_run(raw, len(raw), rp, nr, int(keep_faults), int(fault_stride), ctypes.byref(out))
+    rc = lib.oracle_run_threads(raw, len(raw), rp, nr, int(keep_faults), int(fault_stride), int(threads),
+                                ctypes.byref(out))
     if rc != 0:
         raise OracleError(rc, lib.oracle_last_error().decode())
     try:

@@ -28,10 +28,14 @@
  * They are evaluated in rationalised forms that have no cancellation.
  * X_ERROR / Y_ERROR / Z_ERROR(r) give one fault with p = r.
  *
- * Arithmetic is IEEE binary64 throughout. Single-threaded.
+ * Arithmetic is IEEE binary64 throughout. The forward tracking of step 2 may
+ * run on several threads, each over a contiguous range of fault ids; the
+ * signatures are concatenated in fault order before step 3, which runs on one
+ * thread, so the result does not depend on the thread count.
  */
 #define _GNU_SOURCE
 #include <ctype.h>
+#include <pthread.h>
 #include <math.h>
 #include <stdarg.h>
 #include <stdint.h>
@@ -46,7 +50,7 @@
 #define ORC_E_OOM (-8)
 #define ORC_E_ARG (-1)
 
-static char g_err[512];
+static _Thread_local char g_err[512];
 
 static int fail(int code, const char *fmt, ...) {
   va_list ap;
@@ -632,7 +636,7 @@ static int track_fault(const circ_t *c, const chan_t *ch, int code, scratch_t *s
     if (s->mark[b] && ivec_push(&s->sig, b)) return ORC_E_OOM;
   }
   for (int64_t i = 0; i < s->ntouched; i++) s->mark[s->touched[i]] = 0;
-  qsort(s->sig.v, (size_t)s->sig.n, sizeof(int32_t), cmp_i32);
+  if (s->sig.n > 1) qsort(s->sig.v, (size_t)s->sig.n, sizeof(int32_t), cmp_i32);
   int64_t w = 0;
   for (int64_t i = 0; i < s->sig.n; i++)
     if (w == 0 || s->sig.v[w - 1] != s->sig.v[i]) s->sig.v[w++] = s->sig.v[i];
@@ -684,6 +688,48 @@ static int cmp_fault(const void *pa, const void *pb, void *ctx) {
   return (a > b) - (a < b);
 }
 
+/* One thread's share of the forward tracking: faults [lo, hi) of the
+ * selected list, in order; their signatures are appended to `pool` with
+ * offsets in `off` (relative to this share). */
+typedef struct {
+  const circ_t *c;
+  const int64_t *fch;   /* selected faults: channel */
+  const int32_t *fcode; /* and Pauli code */
+  int64_t lo, hi;
+  int64_t nbits;
+  int64_t *off;         /* hi - lo + 1 */
+  ivec pool;
+  int rc;
+  char err[512];
+} share_t;
+
+static void *track_share(void *arg) {
+  share_t *sh = (share_t *)arg;
+  scratch_t s;
+  memset(&s, 0, sizeof s);
+  s.mark = (unsigned char *)calloc((size_t)sh->nbits + 1, 1);
+  s.touched = (int32_t *)malloc(((size_t)sh->nbits + 1) * sizeof(int32_t));
+  sh->off = (int64_t *)malloc((size_t)(sh->hi - sh->lo + 1) * sizeof(int64_t));
+  if (!s.mark || !s.touched || !sh->off) {
+    sh->rc = ORC_E_OOM;
+  } else {
+    for (int64_t i = sh->lo; i < sh->hi && !sh->rc; i++) {
+      sh->off[i - sh->lo] = sh->pool.n;
+      int rc = track_fault(sh->c, &sh->c->ch[sh->fch[i]], sh->fcode[i], &s);
+      if (rc) {
+        sh->rc = rc;
+        snprintf(sh->err, sizeof sh->err, "%s", g_err);  /* this thread's message */
+        break;
+      }
+      for (int64_t b = 0; b < s.sig.n; b++)
+        if (ivec_push(&sh->pool, s.sig.v[b])) { sh->rc = ORC_E_OOM; break; }
+    }
+    if (!sh->rc) sh->off[sh->hi - sh->lo] = sh->pool.n;
+  }
+  free(s.e); free(s.flip); free(s.mark); free(s.touched); free(s.sig.v);
+  return NULL;
+}
+
 /*
  * oracle_run: compile `text` (Stim-format subset) to its hypergraph.
  *   rates / n_rates : optional per-channel rates (channel order = program
@@ -691,11 +737,22 @@ static int cmp_fault(const void *pa, const void *pb, void *ctx) {
  *   keep_faults     : also return each analysed fault's signature.
  *   fault_stride    : analyse only faults whose id is a multiple of this
  *                     (1 = all); used to time the oracle on a bounded sample.
+ * oracle_run_threads: the same with the forward tracking on `n_threads`
+ * threads (contiguous fault ranges); identical output for any thread count.
  */
+int oracle_run_threads(const char *text, size_t len, const double *rates, int64_t n_rates,
+                       int keep_faults, int64_t fault_stride, int n_threads, oracle_result **out);
+
 int oracle_run(const char *text, size_t len, const double *rates, int64_t n_rates,
                int keep_faults, int64_t fault_stride, oracle_result **out) {
+  return oracle_run_threads(text, len, rates, n_rates, keep_faults, fault_stride, 1, out);
+}
+
+int oracle_run_threads(const char *text, size_t len, const double *rates, int64_t n_rates,
+                       int keep_faults, int64_t fault_stride, int n_threads, oracle_result **out) {
   *out = NULL;
   if (fault_stride < 1) return fail(ORC_E_ARG, "fault_stride must be >= 1");
+  if (n_threads < 1 || n_threads > 1024) return fail(ORC_E_ARG, "n_threads must be in [1, 1024]");
   circ_t c;
   memset(&c, 0, sizeof c);
   int rc = parse(text, len, &c);
@@ -718,50 +775,93 @@ int oracle_run(const char *text, size_t len, const double *rates, int64_t n_rate
   int64_t nbits = (int64_t)c.ndet + c.nobs;
 
   oracle_result *res = (oracle_result *)calloc(1, sizeof *res);
-  scratch_t s;
-  memset(&s, 0, sizeof s);
-  s.mark = (unsigned char *)calloc((size_t)nbits + 1, 1);
-  s.touched = (int32_t *)malloc(((size_t)nbits + 1) * sizeof(int32_t));
   ivec pool = {0};
   int64_t *foff = NULL;
   double *fp = NULL;
   int32_t *fch = NULL, *fcode = NULL;
+  int64_t *fch64 = NULL;
+  share_t *sh = NULL;
   int64_t nf = 0, capf = 0;
-  if (!res || !s.mark || !s.touched) { rc = fail(ORC_E_OOM, "out of memory"); goto fin; }
+  if (!res) { rc = fail(ORC_E_OOM, "out of memory"); goto fin; }
 
-  /* stage: one forward-tracking pass per fault, in fault order */
-  int64_t fid = 0;
-  int codes[15];
-  for (int64_t k = 0; k < c.nch; k++) {
-    int nfc = chan_faults(c.ch[k].kind, codes);
-    double p = fault_p(c.ch[k].kind, c.ch[k].rate);
-    for (int j = 0; j < nfc; j++) {
-      /* faults above the correlation level are not part of the model */
-      if (pauli_level_of(c.ch[k].kind, codes[j]) > g_level) continue;
-      if ((fid++) % fault_stride) continue;
-      if ((rc = track_fault(&c, &c.ch[k], codes[j], &s))) goto fin;
-      if (nf == capf) {
-        capf = capf ? capf * 2 : 1024;
-        foff = (int64_t *)realloc(foff, (size_t)(capf + 1) * sizeof(int64_t));
-        fp = (double *)realloc(fp, (size_t)capf * sizeof(double));
-        fch = (int32_t *)realloc(fch, (size_t)capf * sizeof(int32_t));
-        fcode = (int32_t *)realloc(fcode, (size_t)capf * sizeof(int32_t));
-        if (!foff || !fp || !fch || !fcode) { rc = fail(ORC_E_OOM, "out of memory"); goto fin; }
+  /* the faults analysed, in fault order: (channel, Pauli code, probability) */
+  {
+    int64_t fid = 0;
+    int codes[15];
+    for (int64_t k = 0; k < c.nch; k++) {
+      int nfc = chan_faults(c.ch[k].kind, codes);
+      double p = fault_p(c.ch[k].kind, c.ch[k].rate);
+      for (int j = 0; j < nfc; j++) {
+        /* faults above the correlation level are not part of the model */
+        if (pauli_level_of(c.ch[k].kind, codes[j]) > g_level) continue;
+        if ((fid++) % fault_stride) continue;
+        if (nf == capf) {
+          capf = capf ? capf * 2 : 1024;
+          fp = (double *)realloc(fp, (size_t)capf * sizeof(double));
+          fch = (int32_t *)realloc(fch, (size_t)capf * sizeof(int32_t));
+          fch64 = (int64_t *)realloc(fch64, (size_t)capf * sizeof(int64_t));
+          fcode = (int32_t *)realloc(fcode, (size_t)capf * sizeof(int32_t));
+          if (!fp || !fch || !fch64 || !fcode) { rc = fail(ORC_E_OOM, "out of memory"); goto fin; }
+        }
+        fp[nf] = p;
+        fch[nf] = (int32_t)k;
+        fch64[nf] = k;
+        fcode[nf] = codes[j];
+        nf++;
       }
-      foff[nf] = pool.n;
-      fp[nf] = p;
-      fch[nf] = (int32_t)k;
-      fcode[nf] = codes[j];
-      for (int64_t b = 0; b < s.sig.n; b++)
-        if (ivec_push(&pool, s.sig.v[b])) { rc = fail(ORC_E_OOM, "out of memory"); goto fin; }
-      nf++;
     }
   }
-  if (!foff) {
-    foff = (int64_t *)malloc(sizeof(int64_t));
-    if (!foff) { rc = fail(ORC_E_OOM, "out of memory"); goto fin; }
+
+  /* stage: one forward-tracking pass per fault, over contiguous fault
+   * ranges, then the signatures concatenated in fault order */
+  {
+    int T = n_threads;
+    if (T > 1 && nf < 4096 * (int64_t)T) T = (int)(nf / 4096 > 1 ? nf / 4096 : 1);
+    sh = (share_t *)calloc((size_t)T, sizeof *sh);
+    pthread_t *th = (pthread_t *)calloc((size_t)T, sizeof *th);
+    int *started = (int *)calloc((size_t)T, sizeof *started);
+    if (!sh || !th || !started) { free(th); free(started); rc = fail(ORC_E_OOM, "out of memory"); goto fin; }
+    for (int t = 0; t < T; t++) {
+      sh[t].c = &c;
+      sh[t].fch = fch64;
+      sh[t].fcode = fcode;
+      sh[t].lo = nf * t / T;
+      sh[t].hi = nf * (t + 1) / T;
+      sh[t].nbits = nbits;
+    }
+    for (int t = 1; t < T; t++) started[t] = pthread_create(&th[t], NULL, track_share, &sh[t]) == 0;
+    track_share(&sh[0]);
+    for (int t = 1; t < T; t++) {
+      if (started[t]) pthread_join(th[t], NULL);
+      else track_share(&sh[t]);  /* could not start a thread: run its share here */
+    }
+    free(th);
+    free(started);
+    int64_t total = 0;
+    for (int t = 0; t < T; t++) {
+      if (sh[t].rc && !rc)
+        rc = sh[t].rc == ORC_E_OOM ? fail(ORC_E_OOM, "out of memory") : fail(sh[t].rc, "%s", sh[t].err);
+      total += sh[t].pool.n;
+    }
+    if (!rc) {
+      foff = (int64_t *)malloc((size_t)(nf + 1) * sizeof(int64_t));
+      pool.v = (int32_t *)malloc((size_t)(total ? total : 1) * sizeof(int32_t));
+      pool.cap = total ? total : 1;
+      if (!foff || !pool.v) rc = fail(ORC_E_OOM, "out of memory");
+    }
+    if (!rc) {
+      for (int t = 0; t < T; t++) {
+        for (int64_t i = sh[t].lo; i < sh[t].hi; i++) foff[i] = pool.n + sh[t].off[i - sh[t].lo];
+        if (sh[t].pool.n) memcpy(pool.v + pool.n, sh[t].pool.v, (size_t)sh[t].pool.n * sizeof(int32_t));
+        pool.n += sh[t].pool.n;
+      }
+      foff[nf] = pool.n;
+    }
+    for (int t = 0; t < T; t++) { free(sh[t].off); free(sh[t].pool.v); }
+    free(sh);
+    sh = NULL;
+    if (rc) goto fin;
   }
-  foff[nf] = pool.n;
 
   /* stage: group by exact signature (sort by signature, then fault order) */
   {
@@ -820,9 +920,9 @@ int oracle_run(const char *text, size_t len, const double *rates, int64_t n_rate
     res->fault_code = fcode; fcode = NULL;
   }
 fin:
-  free(foff); free(fp); free(fch); free(fcode);
+  free(foff); free(fp); free(fch); free(fch64); free(fcode);
   free(pool.v);
-  free(s.e); free(s.flip); free(s.mark); free(s.touched); free(s.sig.v);
+  free(sh);
   circ_free(&c);
   if (rc) { oracle_free(res); return rc; }
   *out = res;

@@ -18,7 +18,7 @@ GP_OK = 0
 STATUS = {
     -1: "GP_E_ARG", -2: "GP_E_PARSE", -3: "GP_E_UNSUPPORTED", -4: "GP_E_BOUNDS",
     -5: "GP_E_NONDETERMINISTIC", -6: "GP_E_NOISE", -7: "GP_E_HIP", -8: "GP_E_OOM",
-    -9: "GP_E_COLLISION", -10: "GP_E_STATE", -11: "GP_E_BUSY",
+    -9: "GP_E_COLLISION", -10: "GP_E_STATE", -11: "GP_E_BUSY", -12: "GP_E_INTERNAL",
 }
 
 #: every symbol include/gp.h declares
@@ -36,6 +36,7 @@ EXPORTS = (
     "gp_server_destroy", "gp_server_timing", "gp_debug_set_graph", "gp_autotune", "gp_set_fault_cost",
     "gp_debug_set_sweep_shape", "gp_autotune_batch", "gp_tuning_cache_size", "gp_tuning_cache_get",
     "gp_tuning_cache_put", "gp_server_set_admission", "gp_fetch_sizes", "gp_fetch_copy",
+    "gp_debug_retry_counts", "gp_debug_set_spin_limit", "gp_debug_device_flags",
 )
 
 
@@ -180,6 +181,11 @@ def load():
                                     ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
         "gp_edges_circuit_dem_text": ([_vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p),
                                        ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+        "gp_debug_retry_counts": ([_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(_u64)],
+                                  ctypes.c_int),
+        "gp_debug_set_spin_limit": ([_vp, ctypes.c_uint32], ctypes.c_int),
+        "gp_debug_device_flags": ([_vp, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32),
+                                   ctypes.c_int], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -545,3 +551,21 @@ def gp_server_timing(srv: int) -> Tuple[float, float, float, float, float]:
     _check(load().gp_server_timing(srv, *[ctypes.byref(x) for x in v]))
     return tuple(x.value for x in v)
 
+
+
+def gp_debug_retry_counts(drv: int) -> dict:
+    """-> re-runs by cause: {"lookback", "bucket", "collision"}."""
+    a, b, c = _u64(), _u64(), _u64()
+    _check(load().gp_debug_retry_counts(drv, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return {"lookback": a.value, "bucket": b.value, "collision": c.value}
+
+
+def gp_debug_set_spin_limit(drv: int, limit: int) -> None:
+    _check(load().gp_debug_set_spin_limit(drv, limit))
+
+
+def gp_debug_device_flags(drv: int, clear_seen: bool = False) -> Tuple[int, int]:
+    """-> (flags of the last compile, flags raised since the last clear)."""
+    f, seen = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(load().gp_debug_device_flags(drv, ctypes.byref(f), ctypes.byref(seen), int(clear_seen)))
+    return f.value, seen.value

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <iterator>
 #include <map>
 #include <mutex>
@@ -25,10 +26,16 @@ namespace {
 
 thread_local std::string g_error = "no error";
 
-int fail(int code, const std::string& msg) {
-  g_error = msg;
+int fail(int code, const char* msg) noexcept {
+  try {
+    g_error = msg;
+  } catch (...) {
+    // no memory for the message: the previous one stays
+  }
   return code;
 }
+
+int fail(int code, const std::string& msg) noexcept { return fail(code, msg.c_str()); }
 
 int hip_fail(hipError_t e, const char* what) {
   return fail(GP_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
@@ -120,23 +127,35 @@ size_t split_threads(uint64_t U) {
                            std::max<uint64_t>(1, U / 65536)});
 }
 
-// Run fn(0 .. T-1) on T threads (inline when T is 1) and wait for all.
+// Run fn(0 .. T-1) on T threads (inline when T is 1) and wait for all; an
+// exception thrown by any share is rethrown here once every thread has ended.
 template <typename F>
 void run_threads(size_t T, F&& fn) {
   if (T <= 1) {
     fn(size_t(0));
     return;
   }
+  std::vector<std::exception_ptr> errs(T);
+  auto share = [&](size_t t) {
+    try {
+      fn(t);
+    } catch (...) {
+      errs[t] = std::current_exception();
+    }
+  };
   // a thread that cannot be started runs its share here instead
   std::vector<std::thread> pool;
+  pool.reserve(T);
   for (size_t t = 0; t < T; t++) {
     try {
-      pool.emplace_back(fn, t);
+      pool.emplace_back(share, t);
     } catch (...) {
-      fn(t);
+      share(t);
     }
   }
   for (std::thread& th : pool) th.join();
+  for (const std::exception_ptr& e : errs)
+    if (e) std::rethrow_exception(e);
 }
 
 
@@ -188,7 +207,8 @@ struct gp_driver {
   uint64_t bm_cap = 0;                 // non-zero-word bitmap words allocated
   uint32_t level = 2;                  // correlation level for the next lowering
   double fault_cost = gp::kDefaultFaultCost;  // observable range cut (set by gp_autotune)
-  uint64_t collision_retries = 0;
+  uint32_t spin_limit = gp::kSpinLimit;  // test hook: look-back rounds before a sort tile gives up
+  uint64_t collision_retries = 0, bucket_retries = 0, lookback_retries = 0;
 
   // optionally, the compile's launch sequence captured as a HIP graph and
   // replayed while the lowering and the modes it was captured with stay the same
@@ -196,7 +216,7 @@ struct gp_driver {
   hipGraphExec_t gexec = nullptr;
   uint64_t lower_gen = 0;      // bumped by every upload of a lowering
   uint64_t graph_gen = ~0ull;  // the lowering generation the graph was captured for
-  uint32_t graph_key_bits = 0, graph_sort_mode = 0, graph_shape = 0;
+  uint32_t graph_key_bits = 0, graph_sort_mode = 0, graph_shape = 0, graph_spin = 0;
 
   bool timing = false;
   std::vector<hipEvent_t> ev_free;
@@ -338,8 +358,15 @@ int lower_batch(const char* const* texts, const size_t* lens, const double* cons
   auto lower_range = [&](size_t lo, size_t hi) {
     for (size_t k = lo; k < hi; k++) {
       const double* r = rates ? rates[k] : nullptr;
-      rcs[k] = gp::lower_circuit(texts[k], lens[k], r, r ? n_rates[k] : 0, slots, parts[k], errs[k], level,
-                                 fault_cost);
+      try {
+        rcs[k] = gp::lower_circuit(texts[k], lens[k], r, r ? n_rates[k] : 0, slots, parts[k], errs[k], level,
+                                   fault_cost);
+      } catch (...) {
+        // on a lowering thread: nothing may be thrown out of it
+        rcs[k] = GP_E_OOM;
+        errs[k].code = GP_E_OOM;
+        errs[k].msg = "host memory allocation failed while lowering";
+      }
     }
   };
   const size_t n_threads = std::min<size_t>({n, 16, std::max<size_t>(1, std::thread::hardware_concurrency())});
@@ -372,7 +399,7 @@ extern "C" {
 
 const char* gp_last_error(void) { return g_error.c_str(); }
 
-int gp_bounds_from_circuit(const char* text, size_t len, gp_bounds* out) {
+static int gp_bounds_from_circuit_impl(const char* text, size_t len, gp_bounds* out) {
   if (!text || !out) return fail(GP_E_ARG, "null argument");
   gp::Lowered lw;
   gp::LowerError err{};
@@ -400,7 +427,7 @@ void gp_driver_destroy(gp_driver* d) {
   delete d;
 }
 
-int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
+static int gp_driver_create_impl(const gp_bounds* bounds, int device, gp_driver** out) {
   if (!bounds || !out) return fail(GP_E_ARG, "null argument");
   *out = nullptr;
   int ndev = 0;
@@ -502,6 +529,8 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   if ((rc = dev_alloc(d, &st.edge_q, F, "edge probabilities"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.edge_branch, F, "edge circuits"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.hdr, 1, "header"))) return cleanup(rc);
+  if (hipMemset(st.hdr, 0, sizeof(gp::DevHeader)) != hipSuccess)
+    return cleanup(hip_fail(hipGetLastError(), "clearing the device header"));
   if ((rc = dev_alloc(d, &st.item_clock, 2 * b.max_items, "item clocks"))) return cleanup(rc);
   st.bits_cap = d->bits_cap;
   // download staging: offsets + bits + probabilities + circuits of the largest result
@@ -512,14 +541,14 @@ int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
   return GP_OK;
 }
 
-int gp_driver_create_from_circuit(const char* text, size_t len, int device, gp_driver** out) {
+static int gp_driver_create_from_circuit_impl(const char* text, size_t len, int device, gp_driver** out) {
   gp_bounds b;
   int rc = gp_bounds_from_circuit(text, len, &b);
   if (rc) return rc;
   return gp_driver_create(&b, device, out);
 }
 
-int gp_bounds_from_batch(const char* const* texts, const size_t* lens, size_t n, gp_bounds* out) {
+static int gp_bounds_from_batch_impl(const char* const* texts, const size_t* lens, size_t n, gp_bounds* out) {
   if (!out) return fail(GP_E_ARG, "null argument");
   gp::Lowered lw;
   int rc = lower_batch(texts, lens, nullptr, nullptr, n, 2, lw);
@@ -528,7 +557,7 @@ int gp_bounds_from_batch(const char* const* texts, const size_t* lens, size_t n,
   return GP_OK;
 }
 
-int gp_driver_create_from_batch(const char* const* texts, const size_t* lens, size_t n, int device,
+static int gp_driver_create_from_batch_impl(const char* const* texts, const size_t* lens, size_t n, int device,
                                 gp_driver** out) {
   gp_bounds b;
   int rc = gp_bounds_from_batch(texts, lens, n, &b);
@@ -640,7 +669,7 @@ static int upload_lowered(gp_driver* d) {
 }
 
 
-int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, size_t n_rates) {
+static int gp_lower_impl(gp_driver* d, const char* text, size_t len, const double* rates, size_t n_rates) {
   if (!d || !text) return fail(GP_E_ARG, "null argument");
   d->staged_ok = false;
   gp::LowerError err{};
@@ -652,7 +681,7 @@ int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, si
   return upload_lowered(d);
 }
 
-int gp_lower_batch(gp_driver* d, const char* const* texts, const size_t* lens, const double* const* rates,
+static int gp_lower_batch_impl(gp_driver* d, const char* const* texts, const size_t* lens, const double* const* rates,
                    const size_t* n_rates, size_t n) {
   if (!d) return fail(GP_E_ARG, "null driver");
   d->staged_ok = false;
@@ -664,7 +693,7 @@ int gp_lower_batch(gp_driver* d, const char* const* texts, const size_t* lens, c
   return upload_lowered(d);
 }
 
-int gp_run(gp_driver* d) {
+static int gp_run_impl(gp_driver* d) {
   if (!d) return fail(GP_E_ARG, "null driver");
   if (!d->lowered) return fail(GP_E_STATE, "gp_run before gp_lower");
   d->staged_ok = false;
@@ -679,12 +708,14 @@ int gp_run(gp_driver* d) {
   d->st.key_bits = d->key_bits;
   d->st.sort_mode = d->sort_mode;
   d->st.sweep_shape = d->sweep_shape;
+  d->st.spin_limit = d->spin_limit;
   d->structured = false;
   if (d->use_graph && !d->timing) {
     // replay the captured launch sequence; capture it first if the lowering
     // or a mode changed since
     if (!d->gexec || d->graph_gen != d->lower_gen || d->graph_key_bits != d->key_bits ||
-        d->graph_sort_mode != d->sort_mode || d->graph_shape != d->sweep_shape) {
+        d->graph_sort_mode != d->sort_mode || d->graph_shape != d->sweep_shape ||
+        d->graph_spin != d->spin_limit) {
       if (d->gexec) {
         (void)hipGraphExecDestroy(d->gexec);
         d->gexec = nullptr;
@@ -706,6 +737,7 @@ int gp_run(gp_driver* d) {
       d->graph_key_bits = d->key_bits;
       d->graph_sort_mode = d->sort_mode;
       d->graph_shape = d->sweep_shape;
+      d->graph_spin = d->spin_limit;
     }
     HIP_TRY(hipGraphLaunch(d->gexec, d->stream), "hipGraphLaunch");
     d->ran = true;
@@ -827,12 +859,12 @@ int autotune(gp_driver* d, Lower&& lower, int iters, gp_tuning* out) {
 
 extern "C" {
 
-int gp_autotune(gp_driver* d, const char* text, size_t len, int iters, gp_tuning* out) {
+static int gp_autotune_impl(gp_driver* d, const char* text, size_t len, int iters, gp_tuning* out) {
   if (!d || !text) return fail(GP_E_ARG, "null argument");
   return autotune(d, [&]() { return gp_lower(d, text, len, nullptr, 0); }, iters, out);
 }
 
-int gp_autotune_batch(gp_driver* d, const char* const* texts, const size_t* lens, size_t n, int iters,
+static int gp_autotune_batch_impl(gp_driver* d, const char* const* texts, const size_t* lens, size_t n, int iters,
                       gp_tuning* out) {
   if (!d || !texts || !lens) return fail(GP_E_ARG, "null argument");
   return autotune(d, [&]() { return gp_lower_batch(d, texts, lens, nullptr, nullptr, n); }, iters, out);
@@ -854,7 +886,7 @@ int gp_tuning_cache_get(size_t i, gp_tuning* out) {
   return GP_OK;
 }
 
-int gp_tuning_cache_put(const gp_tuning* t) {
+static int gp_tuning_cache_put_impl(const gp_tuning* t) {
   if (!t) return fail(GP_E_ARG, "null argument");
   if (!(t->fault_cost > 0.0 && t->fault_cost < 1.0)) return fail(GP_E_ARG, "fault cost must lie in (0, 1)");
   if (t->sweep_block != 256 && t->sweep_block != 1024) return fail(GP_E_ARG, "sweep work-group must be 256 or 1024");
@@ -877,7 +909,7 @@ int gp_debug_set_graph(gp_driver* d, int enable) {
   return GP_OK;
 }
 
-int gp_sync(gp_driver* d) {
+static int gp_sync_impl(gp_driver* d) {
   if (!d) return fail(GP_E_ARG, "null driver");
   HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
   HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
@@ -907,11 +939,19 @@ static int fetch_staged(gp_driver* d, Staged& out) {
   collect_timing(d);
   gp::DevHeader hdr = *d->h_hdr;
   out.t_ready = std::chrono::steady_clock::now();
-  // at most two more compiles: a bucket too large for LDS redoes the grouping
-  // with the full radix sort; two signatures under one key redo it keyed on
-  // both hashes (which always takes the full sort)
-  for (int attempt = 0; attempt < 2 && !(hdr.flags & gp::FLAG_GAUGE); attempt++) {
-    if (hdr.flags & gp::FLAG_BUCKET) {
+  // at most three more compiles: a sort tile that gave up waiting for its
+  // predecessor (never expected) runs the same compile once more; a bucket
+  // too large for LDS redoes the grouping with the full radix sort; two
+  // signatures under one key redo it keyed on both hashes (which always takes
+  // the full sort)
+  bool lookback_redone = false;
+  for (int attempt = 0; attempt < 3 && !(hdr.flags & gp::FLAG_GAUGE); attempt++) {
+    if (hdr.flags & gp::FLAG_LOOKBACK) {
+      if (lookback_redone) break;
+      lookback_redone = true;
+      d->lookback_retries++;
+    } else if (hdr.flags & gp::FLAG_BUCKET) {
+      d->bucket_retries++;
       d->st.sort_mode = gp::SORT_FULL;
     } else if ((hdr.flags & gp::FLAG_COLLISION) && d->st.key_mode == 0) {
       d->collision_retries++;
@@ -933,6 +973,9 @@ static int fetch_staged(gp_driver* d, Staged& out) {
   }
   d->st.key_mode = 0;
   d->st.sort_mode = d->sort_mode;
+  if (hdr.flags & gp::FLAG_LOOKBACK)
+    return fail(GP_E_HIP, "a radix-sort tile gave up waiting for its predecessor, again after a re-run "
+                          "(the grouping was abandoned; no result)");
   if (hdr.flags & gp::FLAG_BUCKET) return fail(GP_E_HIP, "bucket grouping overflow after the full-sort retry");
   if (hdr.flags & gp::FLAG_GAUGE)
     return fail(GP_E_NONDETERMINISTIC,
@@ -965,7 +1008,7 @@ static int fetch_staged(gp_driver* d, Staged& out) {
   return GP_OK;
 }
 
-int gp_fetch_sizes(gp_driver* d, uint64_t* n_edges, uint64_t* n_bits, uint32_t* n_det, uint32_t* n_obs) {
+static int gp_fetch_sizes_impl(gp_driver* d, uint64_t* n_edges, uint64_t* n_bits, uint32_t* n_det, uint32_t* n_obs) {
   if (!d || !n_edges || !n_bits) return fail(GP_E_ARG, "null argument");
   d->staged_ok = false;
   if (d->lw.branches.size() > 1) return fail(GP_E_STATE, "a batch result is fetched with gp_fetch");
@@ -988,7 +1031,7 @@ int gp_fetch_sizes(gp_driver* d, uint64_t* n_edges, uint64_t* n_bits, uint32_t* 
   return GP_OK;
 }
 
-int gp_fetch_copy(gp_driver* d, uint64_t* offsets, uint32_t* bits, double* q) {
+static int gp_fetch_copy_impl(gp_driver* d, uint64_t* offsets, uint32_t* bits, double* q) {
   if (!d || !offsets) return fail(GP_E_ARG, "null argument");
   if (!d->staged_ok) return fail(GP_E_STATE, "gp_fetch_copy without a current gp_fetch_sizes");
   if ((!bits && d->staged_nb) || (!q && d->staged_U)) return fail(GP_E_ARG, "null argument");
@@ -1004,7 +1047,7 @@ int gp_fetch_copy(gp_driver* d, uint64_t* offsets, uint32_t* bits, double* q) {
   return GP_OK;
 }
 
-int gp_fetch(gp_driver* d, gp_edges** out) {
+static int gp_fetch_impl(gp_driver* d, gp_edges** out) {
   if (!d || !out) return fail(GP_E_ARG, "null argument");
   *out = nullptr;
   d->staged_ok = false;
@@ -1098,7 +1141,7 @@ int gp_fetch(gp_driver* d, gp_edges** out) {
   return GP_OK;
 }
 
-int gp_refresh_rates(gp_driver* d, const double* rates, size_t n_rates) {
+static int gp_refresh_rates_impl(gp_driver* d, const double* rates, size_t n_rates) {
   if (!d || !rates) return fail(GP_E_ARG, "null argument");
   if (!d->structured) return fail(GP_E_STATE, "gp_refresh_rates before a fetched compile of this circuit");
   HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
@@ -1124,7 +1167,7 @@ int gp_refresh_rates(gp_driver* d, const double* rates, size_t n_rates) {
   return GP_OK;
 }
 
-int gp_rates_gradient(gp_driver* d, const double* dl_dq, size_t n_edges, double* dl_dr, size_t n_rates) {
+static int gp_rates_gradient_impl(gp_driver* d, const double* dl_dq, size_t n_edges, double* dl_dr, size_t n_rates) {
   if (!d || (!dl_dq && n_edges) || (!dl_dr && n_rates)) return fail(GP_E_ARG, "null argument");
   if (!d->structured) return fail(GP_E_STATE, "gp_rates_gradient before a fetched compile of this circuit");
   if (n_edges != d->struct_edges) return fail(GP_E_ARG, "dl_dq length differs from the hyperedge count");
@@ -1151,7 +1194,7 @@ int gp_rates_gradient(gp_driver* d, const double* dl_dq, size_t n_edges, double*
   return GP_OK;
 }
 
-int gp_compile_hypergraph(gp_driver* d, const char* text, size_t len, const double* rates, size_t n_rates,
+static int gp_compile_hypergraph_impl(gp_driver* d, const char* text, size_t len, const double* rates, size_t n_rates,
                           gp_edges** out) {
   if (!out) return fail(GP_E_ARG, "null argument");
   int rc = gp_lower(d, text, len, rates, n_rates);
@@ -1215,6 +1258,36 @@ int gp_debug_set_key_bits(gp_driver* d, int bits) {
 
 uint64_t gp_debug_collision_retries(const gp_driver* d) { return d ? d->collision_retries : 0; }
 
+int gp_debug_retry_counts(const gp_driver* d, uint64_t* lookback, uint64_t* bucket, uint64_t* collision) {
+  if (!d) return fail(GP_E_ARG, "null driver");
+  if (lookback) *lookback = d->lookback_retries;
+  if (bucket) *bucket = d->bucket_retries;
+  if (collision) *collision = d->collision_retries;
+  return GP_OK;
+}
+
+int gp_debug_set_spin_limit(gp_driver* d, uint32_t limit) {
+  if (!d) return fail(GP_E_ARG, "null driver");
+  d->spin_limit = limit;
+  return GP_OK;
+}
+
+static int gp_debug_device_flags_impl(gp_driver* d, uint32_t* flags, uint32_t* flags_seen, int clear_seen) {
+  if (!d) return fail(GP_E_ARG, "null driver");
+  HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
+  HIP_TRY(hipMemcpyAsync(d->h_hdr, d->st.hdr, sizeof(gp::DevHeader), hipMemcpyDeviceToHost, d->stream),
+          "download header");
+  HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
+  collect_timing(d);
+  if (flags) *flags = d->h_hdr->flags;
+  if (flags_seen) *flags_seen = d->h_hdr->flags_seen;
+  if (clear_seen) {
+    HIP_TRY(hipMemsetAsync(&d->st.hdr->flags_seen, 0, sizeof(uint32_t), d->stream), "clear flags");
+    HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
+  }
+  return GP_OK;
+}
+
 int gp_set_correlation_level(gp_driver* d, int level) {
   if (!d) return fail(GP_E_ARG, "null driver");
   if (level < 0 || level > 2) return fail(GP_E_ARG, "correlation level must be 0, 1 or 2");
@@ -1273,13 +1346,13 @@ int gp_edges_circuit_shape(const gp_edges* e, uint32_t k, uint32_t* n_det, uint3
   return GP_OK;
 }
 
-int gp_edges_to_dem_text(const gp_edges* e, char** text, size_t* len) {
+static int gp_edges_to_dem_text_impl(const gp_edges* e, char** text, size_t* len) {
   if (!e || !text) return fail(GP_E_ARG, "null argument");
   if (e->c_det.size() > 1) return fail(GP_E_STATE, "a batch result: use gp_edges_circuit_dem_text");
   return gp_edges_circuit_dem_text(e, 0, text, len);
 }
 
-int gp_edges_circuit_dem_text(const gp_edges* e, uint32_t circuit, char** text, size_t* len) {
+static int gp_edges_circuit_dem_text_impl(const gp_edges* e, uint32_t circuit, char** text, size_t* len) {
   if (!e || !text) return fail(GP_E_ARG, "null argument");
   if (circuit >= std::max<size_t>(e->c_det.size(), 1)) return fail(GP_E_ARG, "circuit index out of range");
   const uint32_t n_det = e->c_det.empty() ? e->n_det : e->c_det[circuit];
@@ -1311,6 +1384,74 @@ int gp_edges_circuit_dem_text(const gp_edges* e, uint32_t circuit, char** text, 
 void gp_edges_free(gp_edges* e) { delete e; }
 void gp_free(void* p) { std::free(p); }
 
+// ---- exported entry points: the bodies above run under gp::guarded, so no
+// C++ exception (an allocation failure while lowering, splitting or copying a
+// result) crosses the C ABI
+
+#define GP_GUARD(call) gp::guarded([&] { return call; })
+
+int gp_bounds_from_circuit(const char* text, size_t len, gp_bounds* out) {
+  return GP_GUARD(gp_bounds_from_circuit_impl(text, len, out));
+}
+int gp_driver_create(const gp_bounds* bounds, int device, gp_driver** out) {
+  return GP_GUARD(gp_driver_create_impl(bounds, device, out));
+}
+int gp_driver_create_from_circuit(const char* text, size_t len, int device, gp_driver** out) {
+  return GP_GUARD(gp_driver_create_from_circuit_impl(text, len, device, out));
+}
+int gp_bounds_from_batch(const char* const* texts, const size_t* lens, size_t n, gp_bounds* out) {
+  return GP_GUARD(gp_bounds_from_batch_impl(texts, lens, n, out));
+}
+int gp_driver_create_from_batch(const char* const* texts, const size_t* lens, size_t n, int device,
+                                gp_driver** out) {
+  return GP_GUARD(gp_driver_create_from_batch_impl(texts, lens, n, device, out));
+}
+int gp_lower(gp_driver* d, const char* text, size_t len, const double* rates, size_t n_rates) {
+  return GP_GUARD(gp_lower_impl(d, text, len, rates, n_rates));
+}
+int gp_lower_batch(gp_driver* d, const char* const* texts, const size_t* lens, const double* const* rates,
+                   const size_t* n_rates, size_t n) {
+  return GP_GUARD(gp_lower_batch_impl(d, texts, lens, rates, n_rates, n));
+}
+int gp_run(gp_driver* d) { return GP_GUARD(gp_run_impl(d)); }
+int gp_autotune(gp_driver* d, const char* text, size_t len, int iters, gp_tuning* out) {
+  return GP_GUARD(gp_autotune_impl(d, text, len, iters, out));
+}
+int gp_autotune_batch(gp_driver* d, const char* const* texts, const size_t* lens, size_t n, int iters,
+                      gp_tuning* out) {
+  return GP_GUARD(gp_autotune_batch_impl(d, texts, lens, n, iters, out));
+}
+int gp_tuning_cache_put(const gp_tuning* t) { return GP_GUARD(gp_tuning_cache_put_impl(t)); }
+int gp_sync(gp_driver* d) { return GP_GUARD(gp_sync_impl(d)); }
+int gp_fetch_sizes(gp_driver* d, uint64_t* n_edges, uint64_t* n_bits, uint32_t* n_det, uint32_t* n_obs) {
+  return GP_GUARD(gp_fetch_sizes_impl(d, n_edges, n_bits, n_det, n_obs));
+}
+int gp_fetch_copy(gp_driver* d, uint64_t* offsets, uint32_t* bits, double* q) {
+  return GP_GUARD(gp_fetch_copy_impl(d, offsets, bits, q));
+}
+int gp_fetch(gp_driver* d, gp_edges** out) { return GP_GUARD(gp_fetch_impl(d, out)); }
+int gp_refresh_rates(gp_driver* d, const double* rates, size_t n_rates) {
+  return GP_GUARD(gp_refresh_rates_impl(d, rates, n_rates));
+}
+int gp_rates_gradient(gp_driver* d, const double* dl_dq, size_t n_edges, double* dl_dr, size_t n_rates) {
+  return GP_GUARD(gp_rates_gradient_impl(d, dl_dq, n_edges, dl_dr, n_rates));
+}
+int gp_compile_hypergraph(gp_driver* d, const char* text, size_t len, const double* rates, size_t n_rates,
+                          gp_edges** out) {
+  return GP_GUARD(gp_compile_hypergraph_impl(d, text, len, rates, n_rates, out));
+}
+int gp_edges_to_dem_text(const gp_edges* e, char** text, size_t* len) {
+  return GP_GUARD(gp_edges_to_dem_text_impl(e, text, len));
+}
+int gp_edges_circuit_dem_text(const gp_edges* e, uint32_t circuit, char** text, size_t* len) {
+  return GP_GUARD(gp_edges_circuit_dem_text_impl(e, circuit, text, len));
+}
+int gp_debug_device_flags(gp_driver* d, uint32_t* flags, uint32_t* flags_seen, int clear_seen) {
+  return GP_GUARD(gp_debug_device_flags_impl(d, flags, flags_seen, clear_seen));
+}
+
+#undef GP_GUARD
+
 }  // extern "C"
 
 namespace gp {
@@ -1320,13 +1461,27 @@ int driver_upload_parts(gp_driver* d, const std::vector<const Lowered*>& parts) 
   d->lowered = false;
   d->ran = false;
   d->structured = false;
-  merge_branches(parts, d->lw);
-  return upload_lowered(d);
+  return guarded([&] {
+    merge_branches(parts, d->lw);
+    return upload_lowered(d);
+  });
 }
 
 uint32_t driver_level(const gp_driver* d) { return d ? d->level : 2u; }
 
+static int driver_fetch_split_impl(gp_driver* d, std::vector<gp_edges*>& out, uint64_t* wait_ns);
+
 int driver_fetch_split(gp_driver* d, std::vector<gp_edges*>& out, uint64_t* wait_ns) {
+  const int rc = guarded([&] { return driver_fetch_split_impl(d, out, wait_ns); });
+  if (rc) {
+    // a failure part way through frees the results made so far
+    for (gp_edges* e : out) delete e;
+    out.clear();
+  }
+  return rc;
+}
+
+static int driver_fetch_split_impl(gp_driver* d, std::vector<gp_edges*>& out, uint64_t* wait_ns) {
   out.clear();
   if (!d) return fail(GP_E_ARG, "null driver");
   const auto t0 = std::chrono::steady_clock::now();
@@ -1416,6 +1571,6 @@ int driver_fetch_split(gp_driver* d, std::vector<gp_edges*>& out, uint64_t* wait
   return GP_OK;
 }
 
-int set_last_error(int code, const std::string& msg) { return fail(code, msg); }
+int set_last_error(int code, const char* msg) noexcept { return fail(code, msg); }
 
 }  // namespace gp

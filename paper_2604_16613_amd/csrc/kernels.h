@@ -21,13 +21,17 @@ struct DevHeader {
   uint32_t n_live;     // faults with a non-empty signature (the sorted ones)
   uint32_t n_big;      // classes with more faults than one thread merges
   uint64_t n_nz_words; // non-zero signature words stored by stage 1
+  uint32_t flags_seen; // FLAG_* bits raised by any compile since the host last cleared this word
+  uint32_t lookback_passes;  // bit p: a tile of radix pass p gave up its look-back (with FLAG_LOOKBACK)
 };
 
 enum : uint32_t {
   FLAG_GAUGE = 1u,      // a detector/observable is sensitive right after a reset/measurement
   FLAG_COLLISION = 2u,  // equal class keys with different check hashes
   FLAG_OVERFLOW = 4u,   // output signature bits exceed the reserved capacity
-  FLAG_LOOKBACK = 8u,   // a sort tile gave up waiting for its predecessor (never expected)
+  FLAG_LOOKBACK = 8u,   // a sort tile gave up waiting for its predecessor: the pass's placement is
+                        // wrong, so every later grouping kernel returns at once and the host redoes
+                        // the compile (an error if it happens again)
   FLAG_BUCKET = 16u,    // a bucket of the bucket grouping exceeded its LDS capacity (redo with the full sort)
 };
 
@@ -51,6 +55,8 @@ constexpr uint64_t kBucket16MinFaults = 12000000;
 constexpr uint64_t kBucket16MaxFaults = uint64_t(kBuckets16) * 1024;
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+// look-back rounds (each ends in a short sleep) before a sort tile gives up
+constexpr uint32_t kSpinLimit = 1u << 22;
 constexpr int kTile = 4096;       // items per tile in the sort, scan and compaction kernels
 constexpr int kMaxPasses = 8;     // 8-bit digits of a 64-bit key
 
@@ -124,6 +130,7 @@ struct DevState {
   uint32_t n_pass;      // radix passes (8-bit digits) over the class key
   uint32_t sort_mode;   // SORT_*
   uint32_t sweep_shape; // stage-1 work-group shape: 0 automatic, 1 = 1024 threads, 2 = 256 threads
+  uint32_t spin_limit;  // look-back rounds a sort tile waits for a predecessor before giving up
   uint32_t max_tiles;   // tiles the sort/compaction scratch is sized for
 
   // work buffers

@@ -56,7 +56,6 @@ constexpr uint32_t kBigSegment = 64;   // classes with more faults reduce in a w
 constexpr uint32_t kLbAgg = 1u << 30;  // look-back status: tile aggregate published
 constexpr uint32_t kLbPre = 2u << 30;  // look-back status: inclusive prefix published
 constexpr uint32_t kLbMask = (1u << 30) - 1;
-constexpr uint32_t kSpinLimit = 1u << 22;
 constexpr int kLookWin = 16;            // look-back: predecessor tiles read per round
 constexpr uint32_t kHashBmw = 5;        // bitmap words 256 consecutive positions span at most
 
@@ -149,6 +148,19 @@ __device__ __forceinline__ double fault_probability(uint32_t kind, double r) {
 
 __device__ __forceinline__ uint32_t digit_of(uint64_t k, uint32_t pass) { return uint32_t(k >> (8 * pass)) & 255u; }
 
+// Sets a status flag of this compile and records it in the union of the
+// flags raised since the host last cleared that union.
+__device__ __forceinline__ void raise_flag(DevHeader* hdr, uint32_t f) {
+  atomicOr(&hdr->flags, f);
+  atomicOr(&hdr->flags_seen, f);
+}
+
+// A partition pass gave up its look-back: the pairs after it are misplaced
+// (positions may be stale), so the grouping kernels that follow do nothing.
+__device__ __forceinline__ bool grouping_aborted(const DevHeader* hdr) {
+  return (__hip_atomic_load(&hdr->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_LOOKBACK) != 0u;
+}
+
 // ------------------------------------------------------------------ prepare
 
 // the Pauli codes each channel kind keeps at each correlation level
@@ -215,6 +227,7 @@ __global__ __launch_bounds__(kBlock) void k_prepare(DevState st) {
       st.b16_hi[i] = 0;
     }
   if (gid == 0) {
+    st.hdr->lookback_passes = 0;
     st.hdr->n_seg = 0;
     st.hdr->empty_seg = kNone;
     st.hdr->n_edges = 0;
@@ -621,7 +634,7 @@ __global__ __launch_bounds__(kBlk) void k_sweep(DevState st) {
     // every qubit starts in |0>: a Z error at the very start must be invisible
     for (uint32_t q = tid; q < n; q += kBlk) gauge |= frame[2 * q + 1] != 0;
   }
-  if (gauge) atomicOr(&st.hdr->flags, FLAG_GAUGE);
+  if (gauge) raise_flag(st.hdr, FLAG_GAUGE);
   if (tid == 0) st.item_clock[2 * item + 1] = wall_clock64();
 }
 
@@ -905,6 +918,10 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(DevState st, uint32_t p
   __shared__ uint32_t s_wave[kSortWaves + 1];
   __shared__ uint32_t s_tile;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // an earlier pass gave up its look-back: its output is not a permutation
+  // of valid pairs (a pass's own give-ups are not checked here, so that no
+  // tile of this pass stops publishing)
+  if (st.hdr->lookback_passes & ((1u << pass) - 1u)) return;
   const uint32_t n = st.hdr->n_live;
   const uint32_t ntiles = (n + kTile - 1) / kTile;
   if (tid == 0) s_tile = atomicAdd(&st.tile_ctr[pass], 1u);
@@ -988,6 +1005,14 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(DevState st, uint32_t p
       uint32_t spins = 0;
       bool done = false;
       while (!done) {
+        if (spins >= st.spin_limit) {
+          // gave up: the prefix is partial, so this pass misplaces pairs
+          // (every placement stays below the true one, so in bounds); later
+          // passes and grouping kernels then do nothing and the fetch fails
+          raise_flag(st.hdr, FLAG_LOOKBACK);
+          atomicOr(&st.hdr->lookback_passes, 1u << pass);
+          break;
+        }
         uint32_t x[kLookWin];
 #pragma unroll
         for (int q = 0; q < kLookWin; ++q)
@@ -1007,10 +1032,7 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(DevState st, uint32_t p
           else --j;
         }
         if (stalled && !done) {
-          if (++spins > kSpinLimit) {
-            atomicOr(&st.hdr->flags, FLAG_LOOKBACK);
-            break;
-          }
+          ++spins;
           __builtin_amdgcn_s_sleep(1);
         }
       }
@@ -1142,6 +1164,7 @@ __global__ __launch_bounds__(kBlock) void k_heads_apply(const uint64_t* __restri
 // One thread per class of at most kBigSegment faults: merge probabilities in
 // sorted (fault position) order and check that the check hashes agree.
 __global__ __launch_bounds__(kBlock) void k_reduce(DevState st, const uint32_t* __restrict__ vals) {
+  if (grouping_aborted(st.hdr)) return;
   const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t S = st.hdr->n_seg;
   if (s >= S) return;
@@ -1161,7 +1184,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(DevState st, const uint32_t* 
     bad |= r.chk != r0.chk;
     q = fma(r.p, 1.0 - 2.0 * q, q);  // Eq. 3: q(1-p) + p(1-q)
   }
-  if (bad) atomicOr(&st.hdr->flags, FLAG_COLLISION);
+  if (bad) raise_flag(st.hdr, FLAG_COLLISION);
   st.seg_q[s] = q;
   st.seg_rep[s] = rep;
   st.seg_cnt[s] = st.popc[rep];
@@ -1173,6 +1196,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(DevState st, const uint32_t* 
 __global__ __launch_bounds__(kBlock) void k_reduce_big(DevState st, const uint32_t* __restrict__ vals) {
   __shared__ double s_q[kBlock];
   __shared__ int s_bad;
+  if (grouping_aborted(st.hdr)) return;
   const uint32_t S = st.hdr->n_seg;
   const uint32_t n = st.hdr->n_live;
   const uint32_t nb = st.hdr->n_big;
@@ -1201,7 +1225,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_big(DevState st, const uint32
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      if (s_bad) atomicOr(&st.hdr->flags, FLAG_COLLISION);
+      if (s_bad) raise_flag(st.hdr, FLAG_COLLISION);
       st.seg_q[s] = s_q[0];
       st.seg_rep[s] = rep;
       st.seg_cnt[s] = st.popc[rep];
@@ -1247,6 +1271,13 @@ __global__ __launch_bounds__(kBlk) void k_bucket(DevState st, const uint64_t* __
   __shared__ uint32_t s_start;
   __shared__ double s_q[kBlk];
   __shared__ int s_bad;
+  if (grouping_aborted(st.hdr)) {
+    if (threadIdx.x == 0) {
+      b_cls[blockIdx.x] = 0;
+      b_bits[blockIdx.x] = 0;
+    }
+    return;
+  }
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const uint32_t d = blockIdx.x;
   const uint32_t msd = st.n_pass - 1;
@@ -1273,7 +1304,7 @@ __global__ __launch_bounds__(kBlk) void k_bucket(DevState st, const uint64_t* __
     if (tid == 0) {
       b_cls[d] = 0;
       b_bits[d] = 0;
-      if (m) atomicOr(&st.hdr->flags, FLAG_BUCKET);
+      if (m) raise_flag(st.hdr, FLAG_BUCKET);
     }
     return;
   }
@@ -1405,7 +1436,7 @@ __global__ __launch_bounds__(kBlk) void k_bucket(DevState st, const uint64_t* __
       if (tid == 0) {
         b_cls[d] = 0;
         b_bits[d] = 0;
-        atomicOr(&st.hdr->flags, FLAG_BUCKET);
+        raise_flag(st.hdr, FLAG_BUCKET);
       }
       return;
     }
@@ -1541,7 +1572,7 @@ __global__ __launch_bounds__(kBlk) void k_bucket(DevState st, const uint64_t* __
   if (tid == 0) {
     b_cls[d] = ncls;
     b_bits[d] = s_wave[kWaves];
-    if (s_bad) atomicOr(&st.hdr->flags, FLAG_COLLISION);
+    if (s_bad) raise_flag(st.hdr, FLAG_COLLISION);
   }
 }
 
@@ -1553,6 +1584,7 @@ __device__ __forceinline__ uint32_t bucket16_of(uint64_t k, uint32_t msd) {
 // Sorted index range [b16_lo[b], b16_hi[b]) of every non-empty 16-bit bucket
 // (empty buckets keep the cleared 0, 0): the first and last key of each run.
 __global__ __launch_bounds__(kBlock) void k_bucket_bounds(DevState st, const uint64_t* __restrict__ keys) {
+  if (grouping_aborted(st.hdr)) return;
   const uint32_t n = st.hdr->n_live;
   const uint32_t msd = st.n_pass - 1;
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
@@ -1618,6 +1650,7 @@ __global__ __launch_bounds__(kScanSingleBlock) void k_bucket_scan(DevState st) {
 // + class c is hyperedge (classes before the bucket) + c; its first output
 // bit is the bucket's bit offset plus the class's within the bucket.
 __global__ __launch_bounds__(kBlock) void k_slot_map(DevState st, const uint64_t* __restrict__ keys) {
+  if (grouping_aborted(st.hdr)) return;
   const uint32_t n = st.hdr->n_live;
   const uint32_t msd = st.n_pass - 1;
   for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
@@ -1649,6 +1682,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
   __shared__ uint32_t s_fst[kBuckets];
   __shared__ uint32_t s_wave[kBlock / 64];
   __shared__ uint32_t s_bfb[kBranchLds];  // first fault of each circuit of the batch
+  if (grouping_aborted(st.hdr)) return;
   const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t S;
   uint64_t NB;
@@ -1678,7 +1712,7 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
       st.hdr->n_bits = NB;
     }
     st.edge_off32[S] = uint32_t(NB);
-    if (NB > st.bits_cap) atomicOr(&st.hdr->flags, FLAG_OVERFLOW);
+    if (NB > st.bits_cap) raise_flag(st.hdr, FLAG_OVERFLOW);
   }
   if (e >= S) return;
   uint32_t s = e, o0;

@@ -91,7 +91,22 @@ struct TokChunk {
   std::string err_what;
 };
 
+void tokenize_text(const char* p, const char* end, TokChunk& c);
+
+// Tokenize a chunk; an allocation failure is recorded as the chunk's error
+// (this runs on its own thread, so nothing may be thrown out of it).
 void tokenize(const char* p, const char* end, TokChunk& c) {
+  try {
+    tokenize_text(p, end, c);
+  } catch (...) {
+    c.err_code = GP_E_OOM;
+    c.err_line = 0;
+    c.err_what.clear();
+    c.err_fmt = "host memory allocation failed while tokenizing%s";
+  }
+}
+
+void tokenize_text(const char* p, const char* end, TokChunk& c) {
   auto fail = [&](int code, uint32_t line, const char* fmt, const char* what) {
     c.err_code = code;
     c.err_line = line;
@@ -441,14 +456,30 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
   const bool two_threads = chans.size() + op_word.size() > (size_t(1) << 16);
   std::thread ch_thread;
   bool ch_done = false;
+  // the phases on other threads may not throw: an allocation failure there
+  // becomes their status
+  auto channel_phase_safe = [&]() {
+    try {
+      ch_rc = channel_phase(ch_err);
+    } catch (...) {
+      ch_rc = set_err(ch_err, GP_E_OOM, 0, "%s", "host memory allocation failed while lowering");
+    }
+  };
   if (two_threads) {
     try {
-      ch_thread = std::thread([&] { ch_rc = channel_phase(ch_err); });
+      ch_thread = std::thread(channel_phase_safe);
     } catch (...) {
-      ch_rc = channel_phase(ch_err);  // could not start a thread: build the channel tables here
+      channel_phase_safe();  // could not start a thread: build the channel tables here
       ch_done = true;
     }
   }
+  // joined on every way out of this function, exceptions included
+  struct Joiner {
+    std::thread& t;
+    ~Joiner() {
+      if (t.joinable()) t.join();
+    }
+  } ch_join{ch_thread};
 
   // ---- operations sorted by layer (counting sort keeps program order)
   lw.layer_off.assign(size_t(L) + 1, 0);
@@ -584,16 +615,25 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
       }
     }
   };
+  bool inj_oom = false;
+  auto injection_phase_safe = [&]() {
+    try {
+      injection_phase();
+    } catch (...) {
+      inj_oom = true;
+    }
+  };
   std::thread inj_thread;
   if (two_threads) {
     try {
-      inj_thread = std::thread(injection_phase);
+      inj_thread = std::thread(injection_phase_safe);
     } catch (...) {
-      injection_phase();  // could not start a thread: build the lists here
+      injection_phase_safe();  // could not start a thread: build the lists here
     }
   } else {
-    injection_phase();
+    injection_phase_safe();
   }
+  Joiner inj_join{inj_thread};
 
   // ---- sweep items: one per detector column; observable columns, which stay
   // live over the whole circuit, are cut into boundary ranges so that their
@@ -727,6 +767,7 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
   // layer windows share the layer-offset indexing (n_layers + 1 entries)
   lw.layer_win.resize(size_t(lw.n_layers) + 1, 0);
   if (inj_thread.joinable()) inj_thread.join();
+  if (inj_oom) return set_err(err, GP_E_OOM, 0, "%s", "host memory allocation failed while lowering");
   return 0;
 }
 

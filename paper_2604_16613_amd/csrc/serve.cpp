@@ -77,7 +77,11 @@ namespace {
 void complete(gp_server* s, const ReqPtr& r, int rc, const std::string& msg, gp_edges* e) {
   std::lock_guard<std::mutex> lk(s->mu);
   r->rc = rc;
-  r->msg = msg;
+  try {
+    r->msg = msg;
+  } catch (...) {
+    // no memory for the message: the status alone reports the failure
+  }
   r->edges = e;
   r->t_done = now_ns();
   r->done = true;
@@ -109,14 +113,31 @@ void lower_loop(gp_server* s, uint32_t level) {
     }
     const uint64_t t0 = now_ns();
     gp::LowerError err{};
-    const int rc = gp::lower_circuit(r->text.data(), r->text.size(), r->has_rates ? r->rates.data() : nullptr,
-                                     r->has_rates ? r->rates.size() : 0, slots, r->lw, err, level);
+    int rc;
+    try {
+      rc = gp::lower_circuit(r->text.data(), r->text.size(), r->has_rates ? r->rates.data() : nullptr,
+                             r->has_rates ? r->rates.size() : 0, slots, r->lw, err, level);
+    } catch (...) {
+      // nothing may leave this thread: the request fails on its own
+      r->lw = gp::Lowered();
+      rc = GP_E_OOM;
+      err.msg.clear();
+    }
     r->lowered = true;
     if (rc) {
-      complete(s, r, rc, err.msg, nullptr);
+      complete(s, r, rc, rc == GP_E_OOM && err.msg.empty() ? "host memory allocation failed while lowering" : err.msg,
+               nullptr);
     } else {
-      std::lock_guard<std::mutex> lk(s->mu);
-      s->pending.push_back(r);
+      bool queued = false;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        try {
+          s->pending.push_back(r);
+          queued = true;
+        } catch (...) {
+        }
+      }
+      if (!queued) complete(s, r, GP_E_OOM, "host memory allocation failed while queueing", nullptr);
     }
     {
       std::lock_guard<std::mutex> lk(s->mu);
@@ -160,12 +181,45 @@ void finish(gp_server* s, int slot, std::vector<ReqPtr>& batch) {
   s->ns_download += wait[1];
 }
 
+void worker_pass_loop(gp_server* s, std::vector<ReqPtr>* inflight, int& cur, std::vector<ReqPtr>& take,
+                      std::vector<ReqPtr>& batch);
+
+// The worker: passes of worker_pass_loop; an exception in a pass (host
+// allocation) fails the requests that pass held and the loop goes on.
 void worker_loop(gp_server* s) {
-  const size_t max_batch = std::max<uint32_t>(s->bounds.max_branches, 1);
   std::vector<ReqPtr> inflight[2];
   int cur = 0;
   for (;;) {
-    std::vector<ReqPtr> take;
+    std::vector<ReqPtr> take, batch;
+    try {
+      worker_pass_loop(s, inflight, cur, take, batch);
+      break;  // the loop ended normally: the server stops
+    } catch (...) {
+      try {
+        for (std::vector<ReqPtr>* v : {&take, &batch})
+          for (const ReqPtr& r : *v) {
+            bool done;
+            {
+              std::lock_guard<std::mutex> lk(s->mu);
+              done = r->done;
+            }
+            if (!done) complete(s, r, GP_E_OOM, "host memory allocation failed in the server", nullptr);
+          }
+      } catch (...) {
+        // no memory even for the failure message: the requests stay pending
+      }
+    }
+  }
+  finish(s, 0, inflight[0]);
+  finish(s, 1, inflight[1]);
+}
+
+void worker_pass_loop(gp_server* s, std::vector<ReqPtr>* inflight, int& cur, std::vector<ReqPtr>& take,
+                      std::vector<ReqPtr>& batch) {
+  const size_t max_batch = std::max<uint32_t>(s->bounds.max_branches, 1);
+  for (;;) {
+    take.clear();
+    batch.clear();
     {
       std::unique_lock<std::mutex> lk(s->mu);
       const bool busy = !inflight[0].empty() || !inflight[1].empty();
@@ -179,7 +233,7 @@ void worker_loop(gp_server* s) {
         if (solo) break;
       }
     }
-    std::vector<ReqPtr> batch = std::move(take);
+    batch.swap(take);
     // upload the largest prefix that fits the bounds; the rest waits
     while (!batch.empty()) {
       if (!inflight[cur].empty()) finish(s, cur, inflight[cur]);
@@ -222,15 +276,26 @@ void worker_loop(gp_server* s) {
       finish(s, cur, inflight[cur]);
     }
   }
-  finish(s, 0, inflight[0]);
-  finish(s, 1, inflight[1]);
 }
 
 }  // namespace
 
 extern "C" {
 
+static int gp_server_create_impl(const gp_bounds* bounds, int device, gp_server** out);
+static int gp_server_submit_impl(gp_server* s, const char* text, size_t len, const double* rates, size_t n_rates,
+                                 uint64_t* ticket);
+
 int gp_server_create(const gp_bounds* bounds, int device, gp_server** out) {
+  return gp::guarded([&] { return gp_server_create_impl(bounds, device, out); });
+}
+
+int gp_server_submit(gp_server* s, const char* text, size_t len, const double* rates, size_t n_rates,
+                     uint64_t* ticket) {
+  return gp::guarded([&] { return gp_server_submit_impl(s, text, len, rates, n_rates, ticket); });
+}
+
+static int gp_server_create_impl(const gp_bounds* bounds, int device, gp_server** out) {
   if (!bounds || !out) return gp::set_last_error(GP_E_ARG, "null argument");
   *out = nullptr;
   gp_server* s = new gp_server();
@@ -257,8 +322,8 @@ int gp_server_create(const gp_bounds* bounds, int device, gp_server** out) {
   return GP_OK;
 }
 
-int gp_server_submit(gp_server* s, const char* text, size_t len, const double* rates, size_t n_rates,
-                     uint64_t* ticket) {
+static int gp_server_submit_impl(gp_server* s, const char* text, size_t len, const double* rates, size_t n_rates,
+                                 uint64_t* ticket) {
   if (!s || !text || !ticket || (!rates && n_rates)) return gp::set_last_error(GP_E_ARG, "null argument");
   ReqPtr r = std::make_shared<Request>();
   r->text.assign(text, len);

@@ -117,14 +117,14 @@ def test_bivariate_bicycle(drv25):
     assert drv25.info()["n_observables"] == 12
 
 
-@pytest.mark.parametrize("seed", [None, 0])
+@pytest.mark.parametrize("seed", [None, 0, 1, 2])
 def test_surface_code_d17(drv25, seed):
     c = rotated_surface_code_memory(17, 17)
     rates = None if seed is None else log_uniform_rates(c.n_channels, seed)
     check(drv25, c.text, rates, label=f"sc17 seed{seed}")
 
 
-@pytest.mark.parametrize("seed", [None, 1])
+@pytest.mark.parametrize("seed", [None, 0, 1, 2])
 def test_surface_code_d25(drv25, seed):
     """The largest workload at full size, every hyperedge compared."""
     c = rotated_surface_code_memory(25, 25)

@@ -149,3 +149,25 @@ def test_admission_refuses_past_its_limits(branches):
         hg, _ = srv.wait(f)
         same(hg, alone.compile_hypergraph(branches[4]), "request after the byte limit")
         assert srv.stats()["requests"] == 5
+
+
+@pytest.mark.timeout(300)
+def test_served_d10_workload_against_the_oracle():
+    """The served workload of the benchmark (outer distance 10 branches,
+    seeds 1000..), submitted back to back so that they batch: every result
+    equals the branch compiled alone bit for bit, and two of them the oracle
+    to 1e-12."""
+    say("case served d10")
+    texts = [c.text for c in iceberg_surface_batch(10, n_branches=8, seed=1000)]
+    with Server.for_circuits(texts, max_batch=16) as srv, Driver.from_batch(texts) as alone:
+        tickets = [srv.submit(t) for t in texts]
+        got = [srv.wait(k)[0] for k in tickets]
+        for i, hg in enumerate(got):
+            same(hg, alone.compile_hypergraph(texts[i]), f"served d10 request {i}")
+    for i in (0, 7):
+        say(f"case served d10: request {i} against the oracle")
+        ref = oracle.run(texts[i]).edges()
+        e = got[i].edges()
+        assert set(e) == set(ref)
+        for k, q in ref.items():
+            assert abs(e[k] - q) <= 1e-12 * q

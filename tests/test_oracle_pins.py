@@ -349,3 +349,20 @@ def test_oracle_errors():
     assert e.value.code == -3
     with pytest.raises(oracle.OracleError):
         oracle.run("M 0\nDETECTOR rec[-2]\n")
+
+
+@pytest.mark.parametrize("threads", [2, 3, 8])
+def test_threaded_tracking_is_identical(threads):
+    """The forward tracking split over contiguous fault ranges on several
+    threads, concatenated in fault order before the grouping, gives the
+    single-thread result bit for bit (every fault's signature, every
+    hyperedge and probability), also on a sampled fault subset."""
+    c = rotated_surface_code_memory(7, 7)
+    rates = log_uniform_rates(c.n_channels, 3)
+    for stride in (1, 7):
+        a = oracle.run(c.text, rates=rates, keep_faults=True, fault_stride=stride)
+        b = oracle.run(c.text, rates=rates, keep_faults=True, fault_stride=stride, threads=threads)
+        for f in ("edge_off", "edge_bits", "fault_off", "fault_bits", "fault_channel", "fault_code"):
+            assert np.array_equal(getattr(a, f), getattr(b, f)), f
+        for f in ("edge_q", "fault_p"):
+            assert np.array_equal(getattr(a, f).view(np.uint64), getattr(b, f).view(np.uint64)), f

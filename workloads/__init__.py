@@ -21,3 +21,4 @@ from .concatenated import (  # noqa: F401
     iceberg_surface_batch,
 )
 from .rates import splitmix64_uniform, log_uniform_rates  # noqa: F401
+from .loss import logit_loss  # noqa: F401
