@@ -103,6 +103,46 @@ typedef struct gp_circuit_info {
   uint32_t n_circuits;        /* circuits lowered together (1 after gp_lower) */
 } gp_circuit_info;
 
+/* Binary form of a realised circuit (the input a simulator that realises
+ * adaptive branches produces, Sec. 3.4 and Sec. 5.2.1: no text to print or
+ * parse). One entry per elementary operation, in program order, as parallel
+ * arrays of n_ops entries:
+ *   code[k]  GP_IR_* below;
+ *   q0[k]    the qubit (the control of CX); for GP_IR_OBSERVABLE the
+ *            observable index (at most 65535); unused for GP_IR_DETECTOR;
+ *   q1[k]    the second qubit of CX / CZ / SWAP / DEPOLARIZE2 (different from
+ *            q0); for GP_IR_DETECTOR and GP_IR_OBSERVABLE the number of
+ *            records the operation takes from `rec`; unused otherwise;
+ *   rate[k]  the rate of a noise operation (X/Y/Z_ERROR at most 1/2,
+ *            DEPOLARIZE1 at most 3/4, DEPOLARIZE2 at most 15/16); unused
+ *            otherwise.
+ * rec holds the records of the annotations, concatenated in program order
+ * (n_rec entries, all used): absolute measurement indices, the first
+ * measurement of the circuit being 0, each naming a measurement made before
+ * the annotation. A measurement listed twice by one detector or observable
+ * cancels (XOR), and GP_IR_OBSERVABLE accumulates over operations, as in the
+ * text form. Each noise operation is one channel (a DEPOLARIZE2 one pair), so
+ * channels are numbered by their position among the noise operations. An
+ * array no operation reads may be NULL. The arrays are host memory owned by
+ * the caller and only read during the call. Qubit indices are below 2^28.
+ * The semantics are those of the same operations in the text form; GP_IR_PAULI
+ * (I, X, Y or Z) only makes its qubit part of the circuit. */
+enum {
+  GP_IR_PAULI = 0, GP_IR_H = 1, GP_IR_S = 2, GP_IR_SQRT_X = 3, GP_IR_CX = 4, GP_IR_CZ = 5, GP_IR_SWAP = 6,
+  GP_IR_R = 7, GP_IR_RX = 8, GP_IR_M = 9, GP_IR_MX = 10, GP_IR_MR = 11, GP_IR_MRX = 12,
+  GP_IR_X_ERROR = 16, GP_IR_Y_ERROR = 17, GP_IR_Z_ERROR = 18, GP_IR_DEPOLARIZE1 = 19, GP_IR_DEPOLARIZE2 = 20,
+  GP_IR_DETECTOR = 32, GP_IR_OBSERVABLE = 33
+};
+typedef struct gp_circuit_ir {
+  uint64_t n_ops;
+  const uint8_t* code;
+  const uint32_t* q0;
+  const uint32_t* q1;
+  const double* rate;
+  uint64_t n_rec;
+  const uint32_t* rec;
+} gp_circuit_ir;
+
 /* Thread-local description of the last non-zero status. Never NULL. */
 const char* gp_last_error(void);
 
@@ -129,10 +169,25 @@ int gp_driver_create_from_batch(const char* const* texts, const size_t* lens, si
 void gp_driver_destroy(gp_driver* drv);
 
 /* Whole path, blocking: lower, run both stages, copy the hypergraph to the
- * host. `rates` (NULL = rates written in the text) must hold exactly one rate
- * per channel. On success *out owns the result. */
+ * host (paper Listing 1, compile_detector_error_model). `rates` (NULL = rates
+ * written in the text) must hold exactly one rate per channel. `level` is the
+ * correlation level of Table 1 for this compile (0, 1, 2 = every Pauli; -1 =
+ * the driver's, see gp_set_correlation_level). On success *out owns the
+ * result. */
 int gp_compile_hypergraph(gp_driver* drv, const char* text, size_t len,
-                          const double* rates, size_t n_rates, gp_edges** out);
+                          const double* rates, size_t n_rates, int level, gp_edges** out);
+
+/* The same for a circuit in binary form (gp_circuit_ir above): lowering it
+ * gives the same tables as lowering the equivalent text, with no parsing. Its
+ * split forms, batch form and bounds (same status codes as the text forms,
+ * errors naming the operation index instead of a line): */
+int gp_compile_ir(gp_driver* drv, const gp_circuit_ir* ir, const double* rates, size_t n_rates, int level,
+                  gp_edges** out);
+int gp_lower_ir(gp_driver* drv, const gp_circuit_ir* ir, const double* rates, size_t n_rates);
+int gp_lower_batch_ir(gp_driver* drv, const gp_circuit_ir* irs, size_t n, const double* const* rates,
+                      const size_t* n_rates);
+int gp_bounds_from_ir(const gp_circuit_ir* ir, gp_bounds* out);
+int gp_bounds_from_batch_ir(const gp_circuit_ir* irs, size_t n, gp_bounds* out);
 
 /* Split form of gp_compile_hypergraph, for callers that keep state on the
  * device and time the device stages alone:
@@ -246,6 +301,35 @@ int gp_refresh_rates(gp_driver* drv, const double* rates, size_t n_rates);
  * GP_E_ARG for wrong lengths. */
 int gp_rates_gradient(gp_driver* drv, const double* dl_dq, size_t n_edges, double* dl_dr, size_t n_rates);
 
+/* Stage 2 over the cached structure with every operand in device memory, on
+ * the caller's stream: the drift-recalibration refresh (Sec. 2.2) and its
+ * adjoint, for callers (such as an autograd function) whose rates, q and
+ * gradients already live on the GPU. After a fetched compile:
+ *   gp_aggregate          d_rates -> d_q: the per-fault probabilities at the
+ *                         rates and the Eq. 3 merge of every hyperedge, as
+ *                         gp_refresh_rates computes them (bitwise the same);
+ *   gp_aggregate_backward d_rates, d_gq -> d_grates: dL/d(rate) for dL/dq,
+ *                         as gp_rates_gradient computes it, at d_rates (so it
+ *                         does not depend on which rates were applied last).
+ * d_rates: n_rates = channel count doubles, program order (a batch: circuit
+ * by circuit), each within its channel's range (not checked on the device; an
+ * out-of-range rate gives NaN); d_q, d_gq: n_edges = the fetched compile's
+ * hyperedge count doubles, in the order of the last fetch; d_grates: n_rates
+ * doubles. All device pointers on the driver's device, owned by the caller.
+ * `stream` is a hipStream_t (NULL: the driver's stream); the work is enqueued
+ * there without waiting, after everything already enqueued on the driver and
+ * before anything enqueued on it later (the driver's per-fault buffers are
+ * shared: do not overlap two of these calls on different streams). The first
+ * call after a batch fetch uploads that fetch's hyperedge order once
+ * (synchronously). GP_E_STATE without a fetched compile, GP_E_ARG for wrong
+ * lengths. gp_structure_id returns an id that changes whenever a fetch
+ * replaces the cached structure (0: none), so that a caller holding results
+ * of an earlier structure can tell. */
+int gp_aggregate(gp_driver* drv, const double* d_rates, size_t n_rates, double* d_q, size_t n_edges, void* stream);
+int gp_aggregate_backward(gp_driver* drv, const double* d_rates, size_t n_rates, const double* d_gq, size_t n_edges,
+                          double* d_grates, void* stream);
+uint64_t gp_structure_id(const gp_driver* drv);
+
 /* Request server (continuous batching). A worker thread owns two drivers
  * created with `batch_bounds` (the bounds of one batch: max_branches circuits
  * at most, totals summed over them), each on its own HIP stream of default
@@ -272,6 +356,10 @@ int gp_rates_gradient(gp_driver* drv, const double* dl_dq, size_t n_edges, doubl
 int gp_server_create(const gp_bounds* batch_bounds, int device, gp_server** out);
 int gp_server_submit(gp_server* srv, const char* text, size_t len, const double* rates, size_t n_rates,
                      uint64_t* ticket);
+/* gp_server_submit for a circuit in binary form: its arrays are copied, so
+ * the caller may reuse them as soon as the call returns. */
+int gp_server_submit_ir(gp_server* srv, const gp_circuit_ir* ir, const double* rates, size_t n_rates,
+                        uint64_t* ticket);
 int gp_server_wait(gp_server* srv, uint64_t ticket, int64_t timeout_us, gp_edges** out, uint64_t* latency_ns);
 int gp_server_stats(const gp_server* srv, uint64_t* batches, uint64_t* requests, uint64_t* max_batch);
 /* Admission (backpressure): a server holds at most `max_requests` live
@@ -394,6 +482,16 @@ int gp_edges_circuit_shape(const gp_edges* e, uint32_t circuit, uint32_t* n_det,
  * caller releases *text with gp_free. GP_E_STATE for a batch result, whose
  * circuits each have their own text (gp_edges_circuit_dem_text). */
 int gp_edges_to_dem_text(const gp_edges* e, char** text, size_t* len);
+/* Signatures packed as 64-bit words (the layout of paper Sec. 3.1.2's class
+ * bit vectors): gp_edges_words gives W, the words per signature (enough for
+ * the detectors and observables of the widest circuit of the result), and
+ * gp_edges_signatures the U x W row-major array in which bit b % 64 of word
+ * b / 64 of row e is set when hyperedge e flips signature bit b (numbered as
+ * in gp_edges_bits). The array is built on the first call (thread-safe) and
+ * stays valid until gp_edges_free; NULL with gp_last_error set if it cannot
+ * be allocated. */
+uint32_t gp_edges_words(const gp_edges* e);
+const uint64_t* gp_edges_signatures(const gp_edges* e);
 int gp_edges_circuit_dem_text(const gp_edges* e, uint32_t circuit, char** text, size_t* len);
 void gp_edges_free(gp_edges* e);
 void gp_free(void* p);

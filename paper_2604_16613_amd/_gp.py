@@ -37,6 +37,9 @@ EXPORTS = (
     "gp_debug_set_sweep_shape", "gp_autotune_batch", "gp_tuning_cache_size", "gp_tuning_cache_get",
     "gp_tuning_cache_put", "gp_server_set_admission", "gp_fetch_sizes", "gp_fetch_copy",
     "gp_debug_retry_counts", "gp_debug_set_spin_limit", "gp_debug_device_flags",
+    "gp_compile_ir", "gp_lower_ir", "gp_lower_batch_ir", "gp_bounds_from_ir", "gp_bounds_from_batch_ir",
+    "gp_server_submit_ir", "gp_edges_words", "gp_edges_signatures", "gp_aggregate", "gp_aggregate_backward",
+    "gp_structure_id",
 )
 
 
@@ -90,6 +93,40 @@ class GpTuning(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class GpCircuitIr(ctypes.Structure):
+    """gp_circuit_ir: a circuit in binary form (parallel per-operation arrays)."""
+    _fields_ = [
+        ("n_ops", ctypes.c_uint64), ("code", ctypes.POINTER(ctypes.c_uint8)),
+        ("q0", ctypes.POINTER(ctypes.c_uint32)), ("q1", ctypes.POINTER(ctypes.c_uint32)),
+        ("rate", ctypes.POINTER(ctypes.c_double)), ("n_rec", ctypes.c_uint64),
+        ("rec", ctypes.POINTER(ctypes.c_uint32)),
+    ]
+
+
+def circuit_ir(ir: dict):
+    """-> (GpCircuitIr, arrays to keep alive) for a dict of numpy arrays "code",
+    "q0", "q1", "rate" (one entry per operation) and "rec"."""
+    keep = {
+        "code": np.ascontiguousarray(ir["code"], dtype=np.uint8),
+        "q0": np.ascontiguousarray(ir["q0"], dtype=np.uint32),
+        "q1": np.ascontiguousarray(ir["q1"], dtype=np.uint32),
+        "rate": np.ascontiguousarray(ir["rate"], dtype=np.float64),
+        "rec": np.ascontiguousarray(ir["rec"], dtype=np.uint32),
+    }
+    n = len(keep["code"])
+    for k in ("q0", "q1", "rate"):
+        if len(keep[k]) != n:
+            raise ValueError(f"binary circuit: '{k}' has {len(keep[k])} entries, 'code' has {n}")
+
+    def ptr(a, t):
+        return a.ctypes.data_as(ctypes.POINTER(t)) if len(a) else ctypes.POINTER(t)()
+
+    s = GpCircuitIr(n, ptr(keep["code"], ctypes.c_uint8), ptr(keep["q0"], ctypes.c_uint32),
+                    ptr(keep["q1"], ctypes.c_uint32), ptr(keep["rate"], ctypes.c_double), len(keep["rec"]),
+                    ptr(keep["rec"], ctypes.c_uint32))
+    return s, keep
+
+
 _lib = None
 _vp = ctypes.c_void_p
 _u64 = ctypes.c_uint64
@@ -112,7 +149,24 @@ def load():
                                           ctypes.c_int),
         "gp_driver_destroy": ([_vp], None),
         "gp_compile_hypergraph": ([_vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double),
-                                   ctypes.c_size_t, ctypes.POINTER(_vp)], ctypes.c_int),
+                                   ctypes.c_size_t, ctypes.c_int, ctypes.POINTER(_vp)], ctypes.c_int),
+        "gp_compile_ir": ([_vp, ctypes.POINTER(GpCircuitIr), ctypes.POINTER(ctypes.c_double), ctypes.c_size_t,
+                           ctypes.c_int, ctypes.POINTER(_vp)], ctypes.c_int),
+        "gp_lower_ir": ([_vp, ctypes.POINTER(GpCircuitIr), ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
+                        ctypes.c_int),
+        "gp_lower_batch_ir": ([_vp, ctypes.POINTER(GpCircuitIr), ctypes.c_size_t,
+                               ctypes.POINTER(ctypes.POINTER(ctypes.c_double)), ctypes.POINTER(ctypes.c_size_t)],
+                              ctypes.c_int),
+        "gp_bounds_from_ir": ([ctypes.POINTER(GpCircuitIr), ctypes.POINTER(GpBounds)], ctypes.c_int),
+        "gp_bounds_from_batch_ir": ([ctypes.POINTER(GpCircuitIr), ctypes.c_size_t, ctypes.POINTER(GpBounds)],
+                                    ctypes.c_int),
+        "gp_server_submit_ir": ([_vp, ctypes.POINTER(GpCircuitIr), ctypes.POINTER(ctypes.c_double), ctypes.c_size_t,
+                                 ctypes.POINTER(_u64)], ctypes.c_int),
+        "gp_edges_words": ([_vp], ctypes.c_uint32),
+        "gp_aggregate": ([_vp, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
+        "gp_aggregate_backward": ([_vp, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp, _vp], ctypes.c_int),
+        "gp_structure_id": ([_vp], _u64),
+        "gp_edges_signatures": ([_vp], ctypes.POINTER(_u64)),
         "gp_lower": ([_vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
                      ctypes.c_int),
         "gp_run": ([_vp], ctypes.c_int),
@@ -273,12 +327,77 @@ def gp_driver_destroy(drv: int) -> None:
     load().gp_driver_destroy(drv)
 
 
-def gp_compile_hypergraph(drv: int, text: str, rates: Optional[Sequence[float]] = None) -> int:
+def gp_compile_hypergraph(drv: int, text: str, rates: Optional[Sequence[float]] = None, level: int = -1) -> int:
     raw = text.encode()
     rp, nr, _keep = _rates(rates)
     h = _vp()
-    _check(load().gp_compile_hypergraph(drv, raw, len(raw), rp, nr, ctypes.byref(h)))
+    _check(load().gp_compile_hypergraph(drv, raw, len(raw), rp, nr, level, ctypes.byref(h)))
     return h.value
+
+
+def gp_compile_ir(drv: int, ir: dict, rates: Optional[Sequence[float]] = None, level: int = -1) -> int:
+    s, _keep = circuit_ir(ir)
+    rp, nr, _keep_r = _rates(rates)
+    h = _vp()
+    _check(load().gp_compile_ir(drv, ctypes.byref(s), rp, nr, level, ctypes.byref(h)))
+    return h.value
+
+
+def gp_lower_ir(drv: int, ir: dict, rates: Optional[Sequence[float]] = None) -> None:
+    s, _keep = circuit_ir(ir)
+    rp, nr, _keep_r = _rates(rates)
+    _check(load().gp_lower_ir(drv, ctypes.byref(s), rp, nr))
+
+
+def _ir_array(irs: Sequence[dict]):
+    made = [circuit_ir(ir) for ir in irs]
+    arr = (GpCircuitIr * max(len(made), 1))(*[m[0] for m in made])
+    return arr, made
+
+
+def gp_lower_batch_ir(drv: int, irs: Sequence[dict],
+                      rates: Optional[Sequence[Optional[Sequence[float]]]] = None) -> None:
+    arr, _keep = _ir_array(irs)
+    n = len(irs)
+    if rates is None:
+        _check(load().gp_lower_batch_ir(drv, arr, n, None, None))
+        return
+    if len(rates) != n:
+        raise ValueError("one rate array (or None) per circuit")
+    dp = ctypes.POINTER(ctypes.c_double)
+    keep = [None if r is None else np.ascontiguousarray(r, dtype=np.float64) for r in rates]
+    ptrs = (dp * max(n, 1))(*[dp() if r is None else r.ctypes.data_as(dp) for r in keep])
+    nr = (ctypes.c_size_t * max(n, 1))(*[0 if r is None else len(r) for r in keep])
+    _check(load().gp_lower_batch_ir(drv, arr, n, ptrs, nr))
+
+
+def gp_bounds_from_ir(ir: dict) -> GpBounds:
+    s, _keep = circuit_ir(ir)
+    b = GpBounds()
+    _check(load().gp_bounds_from_ir(ctypes.byref(s), ctypes.byref(b)))
+    return b
+
+
+def gp_bounds_from_batch_ir(irs: Sequence[dict]) -> GpBounds:
+    arr, _keep = _ir_array(irs)
+    b = GpBounds()
+    _check(load().gp_bounds_from_batch_ir(arr, len(irs), ctypes.byref(b)))
+    return b
+
+
+def gp_edges_words(e: int) -> int:
+    return int(load().gp_edges_words(e))
+
+
+def gp_edges_signatures(e: int) -> np.ndarray:
+    """-> the U x W packed signatures (uint64), copied."""
+    n, w = gp_edges_count(e), gp_edges_words(e)
+    p = load().gp_edges_signatures(e)
+    if not p:
+        _check(-8)
+    if n == 0 or w == 0:
+        return np.zeros((n, w), dtype=np.uint64)
+    return np.ctypeslib.as_array(p, shape=(n * w,)).reshape(n, w).copy()
 
 
 def gp_lower(drv: int, text: str, rates: Optional[Sequence[float]] = None) -> None:
@@ -524,6 +643,14 @@ def gp_server_submit(srv: int, text: str, rates: Optional[Sequence[float]] = Non
     return t.value
 
 
+def gp_server_submit_ir(srv: int, ir: dict, rates: Optional[Sequence[float]] = None) -> int:
+    s, _keep = circuit_ir(ir)
+    rp, nr, _keep_r = _rates(rates)
+    t = _u64()
+    _check(load().gp_server_submit_ir(srv, ctypes.byref(s), rp, nr, ctypes.byref(t)))
+    return t.value
+
+
 def gp_server_wait(srv: int, ticket: int, timeout_us: int = -1) -> Tuple[int, int]:
     """-> (gp_edges handle, latency in ns from submit to completion)."""
     h = _vp()
@@ -569,3 +696,18 @@ def gp_debug_device_flags(drv: int, clear_seen: bool = False) -> Tuple[int, int]
     f, seen = ctypes.c_uint32(), ctypes.c_uint32()
     _check(load().gp_debug_device_flags(drv, ctypes.byref(f), ctypes.byref(seen), int(clear_seen)))
     return f.value, seen.value
+
+
+def gp_aggregate(drv: int, d_rates: int, n_rates: int, d_q: int, n_edges: int, stream: int = 0) -> None:
+    """Device pointers (integers) and a hipStream_t (0: the driver's stream)."""
+    _check(load().gp_aggregate(drv, d_rates or None, n_rates, d_q or None, n_edges, stream or None))
+
+
+def gp_aggregate_backward(drv: int, d_rates: int, n_rates: int, d_gq: int, n_edges: int, d_grates: int,
+                          stream: int = 0) -> None:
+    _check(load().gp_aggregate_backward(drv, d_rates or None, n_rates, d_gq or None, n_edges, d_grates or None,
+                                        stream or None))
+
+
+def gp_structure_id(drv: int) -> int:
+    return int(load().gp_structure_id(drv))

@@ -26,6 +26,9 @@ class Hypergraph:
     offsets: np.ndarray
     bits: np.ndarray
     q: np.ndarray
+    #: the signatures packed as 64-bit words (U x W, see gp_edges_signatures),
+    #: when requested
+    words: Optional[np.ndarray] = None
 
     def __len__(self) -> int:
         return len(self.q)
@@ -37,7 +40,7 @@ class Hypergraph:
         return out
 
 
-def _take(handle: int) -> Hypergraph:
+def _take(handle: int, words: bool = False) -> Hypergraph:
     try:
         return Hypergraph(
             n_detectors=_gp.gp_edges_detectors(handle),
@@ -45,6 +48,7 @@ def _take(handle: int) -> Hypergraph:
             offsets=_gp.gp_edges_offsets(handle),
             bits=_gp.gp_edges_bits(handle),
             q=_gp.gp_edges_probabilities(handle),
+            words=_gp.gp_edges_signatures(handle) if words else None,
         )
     finally:
         _gp.gp_edges_free(handle)
@@ -86,6 +90,15 @@ class Driver:
         """A driver sized for compiling `circuits` together as one batch."""
         return cls(_gp.gp_bounds_from_batch(circuits), device)
 
+    @classmethod
+    def from_ir(cls, max_ir: dict, device: int = 0) -> "Driver":
+        """A driver sized for a circuit in binary form (see gp_circuit_ir)."""
+        return cls(_gp.gp_bounds_from_ir(max_ir), device)
+
+    @classmethod
+    def from_batch_ir(cls, irs: Sequence[dict], device: int = 0) -> "Driver":
+        return cls(_gp.gp_bounds_from_batch_ir(irs), device)
+
     def close(self) -> None:
         if self.handle:
             _gp.gp_driver_destroy(self.handle)
@@ -104,10 +117,23 @@ class Driver:
             pass
 
     # whole path
-    def compile_hypergraph(self, circuit: str, rates: Optional[Sequence[float]] = None) -> Hypergraph:
-        self.lower(circuit, rates)
-        self.run()
-        return self.fetch()
+    def compile_hypergraph(self, circuit: str, rates: Optional[Sequence[float]] = None,
+                           level: Optional[int] = None, words: bool = False) -> Hypergraph:
+        """`level`: Table 1 correlation level for this compile (None: the
+        driver's); `words`: also return the packed signatures."""
+        if level is None and not words:
+            self.lower(circuit, rates)
+            self.run()
+            return self.fetch()
+        self._batch = False
+        return _take(_gp.gp_compile_hypergraph(self.handle, circuit, rates, -1 if level is None else level), words)
+
+    def compile_ir(self, ir: dict, rates: Optional[Sequence[float]] = None, level: Optional[int] = None,
+                   words: bool = False) -> Hypergraph:
+        """The same for a circuit in binary form (dict of arrays, see
+        workloads' Circuit.ir and gp_circuit_ir)."""
+        self._batch = False
+        return _take(_gp.gp_compile_ir(self.handle, ir, rates, -1 if level is None else level), words)
 
     def compile_detector_error_model(self, circuit: str, rates: Optional[Sequence[float]] = None) -> str:
         h = _gp.gp_compile_hypergraph(self.handle, circuit, rates)
@@ -133,6 +159,21 @@ class Driver:
                     rates: Optional[Sequence[Optional[Sequence[float]]]] = None) -> None:
         self._batch = True
         _gp.gp_lower_batch(self.handle, circuits, rates)
+
+    def lower_ir(self, ir: dict, rates: Optional[Sequence[float]] = None) -> None:
+        self._batch = False
+        _gp.gp_lower_ir(self.handle, ir, rates)
+
+    def lower_batch_ir(self, irs: Sequence[dict],
+                       rates: Optional[Sequence[Optional[Sequence[float]]]] = None) -> None:
+        self._batch = True
+        _gp.gp_lower_batch_ir(self.handle, irs, rates)
+
+    def compile_batch_ir(self, irs: Sequence[dict],
+                         rates: Optional[Sequence[Optional[Sequence[float]]]] = None) -> List[Hypergraph]:
+        self.lower_batch_ir(irs, rates)
+        self.run()
+        return self.fetch_batch()
 
     def fetch_batch(self) -> List[Hypergraph]:
         return _take_batch(_gp.gp_fetch(self.handle))
@@ -218,6 +259,10 @@ class Server:
         """-> ticket. Raises GpError GP_E_BUSY (code -11) when the server holds
         its admission limit (see set_admission)."""
         return _gp.gp_server_submit(self.handle, circuit, rates)
+
+    def submit_ir(self, ir: dict, rates: Optional[Sequence[float]] = None) -> int:
+        """submit() for a circuit in binary form (its arrays are copied)."""
+        return _gp.gp_server_submit_ir(self.handle, ir, rates)
 
     def set_admission(self, max_requests: int, max_bytes: int) -> None:
         """Limits on live requests (submitted, not yet collected) and on the

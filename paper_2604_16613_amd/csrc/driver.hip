@@ -56,7 +56,7 @@ uint32_t words_for(uint32_t det, uint32_t obs) { return (det + 63) / 64 + (obs +
 // Layout of the per-compile input tables inside one device arena and one
 // pinned host buffer of the same shape, so one copy uploads them all.
 struct TableLayout {
-  size_t layer_off, chan_qa, chan_qb, chan_kind, chan_rate, chan_foff, bnd_chan_off,
+  size_t layer_off, chan_qa, chan_qb, chan_kind, chan_rate, chan_src, chan_foff, bnd_chan_off,
       bnd_fault_off, col_top, col_lo, col_base, item_col, item_blo, item_bhi, fnv_pow, ops32, inj_off, inj_layer,
       inj_qubit, inj_word, inj_next, hchunk_pos, hchunk_bnd, bnd_bm_off, col_bm_base, layer_win, win_lo, win_obase,
       win_cnt, branch, item_branch, hchunk_branch, total;
@@ -85,6 +85,7 @@ TableLayout layout_for(const TableSizes& z) {
   take(t.chan_qb, z.chans * 4);
   take(t.chan_kind, z.chans);
   take(t.chan_rate, z.chans * 8);
+  take(t.chan_src, z.chans * 4);
   take(t.chan_foff, (z.chans + 1) * 4);
   take(t.bnd_chan_off, z.bnd_entries * 4);
   take(t.bnd_fault_off, z.bnd_entries * 4);
@@ -163,6 +164,11 @@ void run_threads(size_t T, F&& fn) {
 
 struct gp_edges {
   uint32_t n_det = 0, n_obs = 0;      // most detectors / observables of any circuit
+  // packed form of the signatures, made on the first request (gp_edges_signatures)
+  std::once_flag words_once;
+  uint32_t n_words = 0;
+  std::vector<uint64_t> words;
+  int words_rc = GP_OK;
   std::vector<uint64_t> off;
   std::vector<uint32_t> bits;
   std::vector<double> q;
@@ -192,7 +198,11 @@ struct gp_driver {
   bool ran = false;
   bool structured = false;     // a fetched compile left its class structure on the device
   uint64_t struct_edges = 0;   // hyperedges of that compile
+  uint64_t struct_id = 0;      // bumped by every fetch that leaves a structure (gp_structure_id)
   std::vector<uint32_t> edge_perm;  // batch: device hyperedge of each fetched one (empty: same order)
+  uint32_t* d_perm = nullptr;  // edge_perm on the device, for the device-pointer aggregate
+  uint64_t perm_id = 0;        // the struct_id whose edge_perm d_perm holds
+  hipEvent_t ev_drv = nullptr, ev_user = nullptr;  // orders the caller's stream against the driver's
   // a downloaded single-circuit result in the pinned staging buffer (gp_fetch_sizes)
   bool staged_ok = false;
   uint64_t staged_U = 0, staged_nb = 0;
@@ -340,27 +350,21 @@ void fill_bounds(const gp::Lowered& lw, gp_bounds* out) {
   *out = b;
 }
 
-// Lower every circuit of a batch (each with its share of the sweep slots) and
-// merge them; `rates` may be null (rates written in the texts), as may any rates[k].
-int lower_batch(const char* const* texts, const size_t* lens, const double* const* rates, const size_t* n_rates,
-                size_t n, uint32_t level, gp::Lowered& out, double fault_cost = gp::kDefaultFaultCost) {
-  if ((!texts || !lens) && n) return fail(GP_E_ARG, "null argument");
+// Lower every circuit of a batch, each on its own (on up to 16 host threads,
+// each circuit with its share of the sweep slots), and merge them.
+// lower_one(k, slots, out, err) lowers circuit k and returns its status.
+template <typename LowerOne>
+int lower_batch_with(size_t n, LowerOne&& lower_one, gp::Lowered& out) {
   if (n == 0) return fail(GP_E_ARG, "a batch needs at least one circuit");
-  if (rates && !n_rates) return fail(GP_E_ARG, "rate arrays without their lengths");
   if (n > (1u << 20)) return fail(GP_E_BOUNDS, "at most 2^20 circuits in one batch");
   const uint32_t slots = std::max<uint32_t>(1, uint32_t((gp::kSweepSlots + n - 1) / n));
-  for (size_t k = 0; k < n; k++)
-    if (!texts[k]) return fail(GP_E_ARG, "null circuit text in the batch");
-  // the circuits are lowered independently, on up to 16 host threads
   std::vector<gp::Lowered> parts(n);
   std::vector<gp::LowerError> errs(n);
   std::vector<int> rcs(n, 0);
   auto lower_range = [&](size_t lo, size_t hi) {
     for (size_t k = lo; k < hi; k++) {
-      const double* r = rates ? rates[k] : nullptr;
       try {
-        rcs[k] = gp::lower_circuit(texts[k], lens[k], r, r ? n_rates[k] : 0, slots, parts[k], errs[k], level,
-                                   fault_cost);
+        rcs[k] = lower_one(k, slots, parts[k], errs[k]);
       } catch (...) {
         // on a lowering thread: nothing may be thrown out of it
         rcs[k] = GP_E_OOM;
@@ -374,6 +378,7 @@ int lower_batch(const char* const* texts, const size_t* lens, const double* cons
     lower_range(0, n);
   } else {
     std::vector<std::thread> pool;
+    pool.reserve(n_threads);
     for (size_t t = 0; t < n_threads; t++) {
       const size_t a = n * t / n_threads, b = n * (t + 1) / n_threads;
       try {
@@ -393,6 +398,37 @@ int lower_batch(const char* const* texts, const size_t* lens, const double* cons
   return GP_OK;
 }
 
+// Batch of circuit texts; `rates` may be null (rates written in the texts),
+// as may any rates[k].
+int lower_batch(const char* const* texts, const size_t* lens, const double* const* rates, const size_t* n_rates,
+                size_t n, uint32_t level, gp::Lowered& out, double fault_cost = gp::kDefaultFaultCost) {
+  if ((!texts || !lens) && n) return fail(GP_E_ARG, "null argument");
+  if (rates && !n_rates) return fail(GP_E_ARG, "rate arrays without their lengths");
+  for (size_t k = 0; k < n; k++)
+    if (!texts[k]) return fail(GP_E_ARG, "null circuit text in the batch");
+  return lower_batch_with(
+      n,
+      [&](size_t k, uint32_t slots, gp::Lowered& lw, gp::LowerError& err) {
+        const double* r = rates ? rates[k] : nullptr;
+        return gp::lower_circuit(texts[k], lens[k], r, r ? n_rates[k] : 0, slots, lw, err, level, fault_cost);
+      },
+      out);
+}
+
+// Batch of circuits in binary form (irs[k], k < n).
+int lower_batch_ir(const gp_circuit_ir* irs, const double* const* rates, const size_t* n_rates, size_t n,
+                   uint32_t level, gp::Lowered& out, double fault_cost = gp::kDefaultFaultCost) {
+  if (!irs && n) return fail(GP_E_ARG, "null argument");
+  if (rates && !n_rates) return fail(GP_E_ARG, "rate arrays without their lengths");
+  return lower_batch_with(
+      n,
+      [&](size_t k, uint32_t slots, gp::Lowered& lw, gp::LowerError& err) {
+        const double* r = rates ? rates[k] : nullptr;
+        return gp::lower_ir(irs[k], r, r ? n_rates[k] : 0, slots, lw, err, level, fault_cost);
+      },
+      out);
+}
+
 }  // namespace
 
 extern "C" {
@@ -409,6 +445,25 @@ static int gp_bounds_from_circuit_impl(const char* text, size_t len, gp_bounds* 
   return GP_OK;
 }
 
+static int gp_bounds_from_ir_impl(const gp_circuit_ir* ir, gp_bounds* out) {
+  if (!ir || !out) return fail(GP_E_ARG, "null argument");
+  gp::Lowered lw;
+  gp::LowerError err{};
+  int rc = gp::lower_ir(*ir, nullptr, 0, gp::kSweepSlots, lw, err);
+  if (rc) return fail(rc, err.msg);
+  fill_bounds(lw, out);
+  return GP_OK;
+}
+
+static int gp_bounds_from_batch_ir_impl(const gp_circuit_ir* irs, size_t n, gp_bounds* out) {
+  if (!out) return fail(GP_E_ARG, "null argument");
+  gp::Lowered lw;
+  int rc = lower_batch_ir(irs, nullptr, nullptr, n, 2, lw);
+  if (rc) return rc;
+  fill_bounds(lw, out);
+  return GP_OK;
+}
+
 void gp_driver_destroy(gp_driver* d) {
   if (!d) return;
   (void)hipSetDevice(d->device);
@@ -418,6 +473,8 @@ void gp_driver_destroy(gp_driver* d) {
   if (d->h_out) (void)hipHostFree(d->h_out);
   if (d->h_hdr) (void)hipHostFree(d->h_hdr);
   if (d->gexec) (void)hipGraphExecDestroy(d->gexec);
+  if (d->ev_drv) (void)hipEventDestroy(d->ev_drv);
+  if (d->ev_user) (void)hipEventDestroy(d->ev_user);
   for (TimedLaunch& t : d->pending) {
     if (t.a) (void)hipEventDestroy(t.a);
     if (t.b) (void)hipEventDestroy(t.b);
@@ -528,6 +585,10 @@ static int gp_driver_create_impl(const gp_bounds* bounds, int device, gp_driver*
   if ((rc = dev_alloc(d, &st.edge_bits, d->bits_cap, "edge bits"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.edge_q, F, "edge probabilities"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.edge_branch, F, "edge circuits"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &d->d_perm, F, "hyperedge order"))) return cleanup(rc);
+  if (hipEventCreateWithFlags(&d->ev_drv, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&d->ev_user, hipEventDisableTiming) != hipSuccess)
+    return cleanup(hip_fail(hipGetLastError(), "hipEventCreate"));
   if ((rc = dev_alloc(d, &st.hdr, 1, "header"))) return cleanup(rc);
   if (hipMemset(st.hdr, 0, sizeof(gp::DevHeader)) != hipSuccess)
     return cleanup(hip_fail(hipGetLastError(), "clearing the device header"));
@@ -584,6 +645,7 @@ static int upload_lowered(gp_driver* d) {
   put(tl.chan_qb, lw.chan_qb.data(), lw.chan_qb.size() * 4);
   put(tl.chan_kind, lw.chan_kind.data(), lw.chan_kind.size());
   put(tl.chan_rate, lw.chan_rate.data(), lw.chan_rate.size() * 8);
+  put(tl.chan_src, lw.chan_src.data(), lw.chan_src.size() * 4);
   put(tl.chan_foff, lw.chan_foff.data(), lw.chan_foff.size() * 4);
   put(tl.bnd_chan_off, lw.bnd_chan_off.data(), lw.bnd_chan_off.size() * 4);
   put(tl.bnd_fault_off, lw.bnd_fault_off.data(), lw.bnd_fault_off.size() * 4);
@@ -620,6 +682,7 @@ static int upload_lowered(gp_driver* d) {
   st.chan_qb = reinterpret_cast<const uint32_t*>(D + tl.chan_qb);
   st.chan_kind = reinterpret_cast<const uint8_t*>(D + tl.chan_kind);
   st.chan_rate = reinterpret_cast<const double*>(D + tl.chan_rate);
+  st.chan_src = reinterpret_cast<const uint32_t*>(D + tl.chan_src);
   st.chan_foff = reinterpret_cast<const uint32_t*>(D + tl.chan_foff);
   st.bnd_chan_off = reinterpret_cast<const uint32_t*>(D + tl.bnd_chan_off);
   st.bnd_fault_off = reinterpret_cast<const uint32_t*>(D + tl.bnd_fault_off);
@@ -669,25 +732,56 @@ static int upload_lowered(gp_driver* d) {
 }
 
 
-static int gp_lower_impl(gp_driver* d, const char* text, size_t len, const double* rates, size_t n_rates) {
-  if (!d || !text) return fail(GP_E_ARG, "null argument");
+// A new lowering replaces whatever the driver held: nothing is staged, run
+// or structured until it has been run and fetched.
+static void forget_compile(gp_driver* d) {
   d->staged_ok = false;
-  gp::LowerError err{};
   d->lowered = false;
   d->ran = false;
   d->structured = false;
-  int rc = gp::lower_circuit(text, len, rates, n_rates, gp::kSweepSlots, d->lw, err, d->level, d->fault_cost);
+}
+
+static int lower_text_at(gp_driver* d, const char* text, size_t len, const double* rates, size_t n_rates,
+                         uint32_t level) {
+  if (!d || !text) return fail(GP_E_ARG, "null argument");
+  forget_compile(d);
+  gp::LowerError err{};
+  int rc = gp::lower_circuit(text, len, rates, n_rates, gp::kSweepSlots, d->lw, err, level, d->fault_cost);
   if (rc) return fail(rc, err.msg);
+  return upload_lowered(d);
+}
+
+static int lower_ir_at(gp_driver* d, const gp_circuit_ir* ir, const double* rates, size_t n_rates,
+                       uint32_t level) {
+  if (!d || !ir) return fail(GP_E_ARG, "null argument");
+  forget_compile(d);
+  gp::LowerError err{};
+  int rc = gp::lower_ir(*ir, rates, n_rates, gp::kSweepSlots, d->lw, err, level, d->fault_cost);
+  if (rc) return fail(rc, err.msg);
+  return upload_lowered(d);
+}
+
+static int gp_lower_impl(gp_driver* d, const char* text, size_t len, const double* rates, size_t n_rates) {
+  return lower_text_at(d, text, len, rates, n_rates, d ? d->level : 2u);
+}
+
+static int gp_lower_ir_impl(gp_driver* d, const gp_circuit_ir* ir, const double* rates, size_t n_rates) {
+  return lower_ir_at(d, ir, rates, n_rates, d ? d->level : 2u);
+}
+
+static int gp_lower_batch_ir_impl(gp_driver* d, const gp_circuit_ir* irs, size_t n, const double* const* rates,
+                                  const size_t* n_rates) {
+  if (!d) return fail(GP_E_ARG, "null driver");
+  forget_compile(d);
+  int rc = lower_batch_ir(irs, rates, n_rates, n, d->level, d->lw, d->fault_cost);
+  if (rc) return rc;
   return upload_lowered(d);
 }
 
 static int gp_lower_batch_impl(gp_driver* d, const char* const* texts, const size_t* lens, const double* const* rates,
                    const size_t* n_rates, size_t n) {
   if (!d) return fail(GP_E_ARG, "null driver");
-  d->staged_ok = false;
-  d->lowered = false;
-  d->ran = false;
-  d->structured = false;
+  forget_compile(d);
   int rc = lower_batch(texts, lens, rates, n_rates, n, d->level, d->lw, d->fault_cost);
   if (rc) return rc;
   return upload_lowered(d);
@@ -1024,6 +1118,7 @@ static int gp_fetch_sizes_impl(gp_driver* d, uint64_t* n_edges, uint64_t* n_bits
   d->edge_perm.clear();
   d->structured = true;
   d->struct_edges = sg.U;
+  d->struct_id++;
   *n_edges = sg.U;
   *n_bits = sg.nb;
   if (n_det) *n_det = d->lw.n_det;
@@ -1138,6 +1233,7 @@ static int gp_fetch_impl(gp_driver* d, gp_edges** out) {
   *out = e;
   d->structured = true;
   d->struct_edges = U;
+  d->struct_id++;
   return GP_OK;
 }
 
@@ -1194,11 +1290,92 @@ static int gp_rates_gradient_impl(gp_driver* d, const double* dl_dq, size_t n_ed
   return GP_OK;
 }
 
-static int gp_compile_hypergraph_impl(gp_driver* d, const char* text, size_t len, const double* rates, size_t n_rates,
-                          gp_edges** out) {
-  if (!out) return fail(GP_E_ARG, "null argument");
-  int rc = gp_lower(d, text, len, rates, n_rates);
+// Runs `enqueue(stream)` on the caller's stream (NULL: the driver's), ordered
+// after everything already enqueued on the driver's stream and before
+// everything enqueued there later.
+extern "C++" template <typename Enqueue>
+static int on_caller_stream(gp_driver* d, void* stream, Enqueue&& enqueue) {
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : d->stream;
+  if (s != d->stream) {
+    HIP_TRY(hipEventRecord(d->ev_drv, d->stream), "hipEventRecord");
+    HIP_TRY(hipStreamWaitEvent(s, d->ev_drv, 0), "hipStreamWaitEvent");
+  }
+  HIP_TRY(enqueue(s), "kernel launch");
+  if (s != d->stream) {
+    HIP_TRY(hipEventRecord(d->ev_user, s), "hipEventRecord");
+    HIP_TRY(hipStreamWaitEvent(d->stream, d->ev_user, 0), "hipStreamWaitEvent");
+  }
+  return GP_OK;
+}
+
+// The hyperedge order of the last fetch on the device (null when it is the
+// device's own order), uploaded once per fetched structure.
+static int device_perm(gp_driver* d, const uint32_t** perm) {
+  *perm = nullptr;
+  if (d->edge_perm.empty()) return GP_OK;
+  if (d->perm_id != d->struct_id) {
+    HIP_TRY(hipMemcpyAsync(d->d_perm, d->edge_perm.data(), d->edge_perm.size() * 4, hipMemcpyHostToDevice,
+                           d->stream),
+            "upload hyperedge order");
+    HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
+    d->perm_id = d->struct_id;
+  }
+  *perm = d->d_perm;
+  return GP_OK;
+}
+
+static int gp_aggregate_impl(gp_driver* d, const double* d_rates, size_t n_rates, double* d_q, size_t n_edges,
+                             void* stream) {
+  if (!d || (!d_rates && n_rates) || (!d_q && n_edges)) return fail(GP_E_ARG, "null argument");
+  if (!d->structured) return fail(GP_E_STATE, "gp_aggregate before a fetched compile");
+  if (n_edges != d->struct_edges) return fail(GP_E_ARG, "q length differs from the hyperedge count");
+  if (n_rates != d->lw.chan_kind.size()) return fail(GP_E_ARG, "rate array length differs from the channel count");
+  HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
+  const uint32_t* perm = nullptr;
+  int rc = device_perm(d, &perm);
   if (rc) return rc;
+  return on_caller_stream(d, stream, [&](hipStream_t s) {
+    return gp::enqueue_aggregate(d->st, uint32_t(n_edges), d_rates, perm, d_q, s);
+  });
+}
+
+static int gp_aggregate_backward_impl(gp_driver* d, const double* d_rates, size_t n_rates, const double* d_gq,
+                                      size_t n_edges, double* d_grates, void* stream) {
+  if (!d || (!d_rates && n_rates) || (!d_gq && n_edges) || (!d_grates && n_rates))
+    return fail(GP_E_ARG, "null argument");
+  if (!d->structured) return fail(GP_E_STATE, "gp_aggregate_backward before a fetched compile");
+  if (n_edges != d->struct_edges) return fail(GP_E_ARG, "dL/dq length differs from the hyperedge count");
+  if (n_rates != d->lw.chan_kind.size()) return fail(GP_E_ARG, "rate array length differs from the channel count");
+  HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
+  const uint32_t* perm = nullptr;
+  int rc = device_perm(d, &perm);
+  if (rc) return rc;
+  return on_caller_stream(d, stream, [&](hipStream_t s) {
+    return gp::enqueue_aggregate_backward(d->st, uint32_t(n_edges), d_rates, perm, d_gq, d_grates, s);
+  });
+}
+
+static int check_level(int level) {
+  return (level < -1 || level > 2) ? fail(GP_E_ARG, "correlation level must be -1 (the driver's), 0, 1 or 2")
+                                   : GP_OK;
+}
+
+static int gp_compile_hypergraph_impl(gp_driver* d, const char* text, size_t len, const double* rates, size_t n_rates,
+                                      int level, gp_edges** out) {
+  if (!d || !out) return fail(GP_E_ARG, "null argument");
+  int rc = check_level(level);
+  if (rc) return rc;
+  if ((rc = lower_text_at(d, text, len, rates, n_rates, level < 0 ? d->level : uint32_t(level)))) return rc;
+  if ((rc = gp_run(d))) return rc;
+  return gp_fetch(d, out);
+}
+
+static int gp_compile_ir_impl(gp_driver* d, const gp_circuit_ir* ir, const double* rates, size_t n_rates, int level,
+                              gp_edges** out) {
+  if (!d || !out) return fail(GP_E_ARG, "null argument");
+  int rc = check_level(level);
+  if (rc) return rc;
+  if ((rc = lower_ir_at(d, ir, rates, n_rates, level < 0 ? d->level : uint32_t(level)))) return rc;
   if ((rc = gp_run(d))) return rc;
   return gp_fetch(d, out);
 }
@@ -1328,6 +1505,44 @@ int gp_timing_entry(const gp_driver* d, int index, const char** name, double* to
   return GP_OK;
 }
 
+// Words per packed signature: enough for the detectors and observables of the
+// widest circuit of the result (bit b of a signature: detector b below the
+// circuit's detector count D, else observable b - D).
+static uint32_t packed_words(const gp_edges* e) {
+  uint64_t most = uint64_t(e->n_det) + e->n_obs;
+  for (size_t k = 0; k < e->c_det.size(); k++) most = std::max<uint64_t>(most, uint64_t(e->c_det[k]) + e->c_obs[k]);
+  return uint32_t((most + 63) / 64);
+}
+
+uint32_t gp_edges_words(const gp_edges* e) { return e ? packed_words(e) : 0; }
+
+const uint64_t* gp_edges_signatures(const gp_edges* e) {
+  if (!e) {
+    fail(GP_E_ARG, "null argument");
+    return nullptr;
+  }
+  gp_edges* m = const_cast<gp_edges*>(e);
+  std::call_once(m->words_once, [m] {
+    m->words_rc = gp::guarded([m] {
+      const uint32_t W = packed_words(m);
+      const uint64_t U = m->q.size();
+      m->n_words = W;
+      m->words.assign(std::max<uint64_t>(U * W, 1), 0ull);
+      for (uint64_t k = 0; k < U; k++)
+        for (uint64_t i = m->off[k]; i < m->off[k + 1]; i++) {
+          const uint32_t b = m->bits[i];
+          m->words[k * W + b / 64] |= 1ull << (b % 64);
+        }
+      return GP_OK;
+    });
+  });
+  if (m->words_rc) {
+    fail(m->words_rc, "could not build the packed signatures");
+    return nullptr;
+  }
+  return m->words.data();
+}
+
 uint64_t gp_edges_count(const gp_edges* e) { return e ? e->q.size() : 0; }
 uint32_t gp_edges_detectors(const gp_edges* e) { return e ? e->n_det : 0; }
 uint32_t gp_edges_observables(const gp_edges* e) { return e ? e->n_obs : 0; }
@@ -1437,8 +1652,23 @@ int gp_rates_gradient(gp_driver* d, const double* dl_dq, size_t n_edges, double*
   return GP_GUARD(gp_rates_gradient_impl(d, dl_dq, n_edges, dl_dr, n_rates));
 }
 int gp_compile_hypergraph(gp_driver* d, const char* text, size_t len, const double* rates, size_t n_rates,
-                          gp_edges** out) {
-  return GP_GUARD(gp_compile_hypergraph_impl(d, text, len, rates, n_rates, out));
+                          int level, gp_edges** out) {
+  return GP_GUARD(gp_compile_hypergraph_impl(d, text, len, rates, n_rates, level, out));
+}
+int gp_compile_ir(gp_driver* d, const gp_circuit_ir* ir, const double* rates, size_t n_rates, int level,
+                  gp_edges** out) {
+  return GP_GUARD(gp_compile_ir_impl(d, ir, rates, n_rates, level, out));
+}
+int gp_bounds_from_ir(const gp_circuit_ir* ir, gp_bounds* out) { return GP_GUARD(gp_bounds_from_ir_impl(ir, out)); }
+int gp_bounds_from_batch_ir(const gp_circuit_ir* irs, size_t n, gp_bounds* out) {
+  return GP_GUARD(gp_bounds_from_batch_ir_impl(irs, n, out));
+}
+int gp_lower_ir(gp_driver* d, const gp_circuit_ir* ir, const double* rates, size_t n_rates) {
+  return GP_GUARD(gp_lower_ir_impl(d, ir, rates, n_rates));
+}
+int gp_lower_batch_ir(gp_driver* d, const gp_circuit_ir* irs, size_t n, const double* const* rates,
+                      const size_t* n_rates) {
+  return GP_GUARD(gp_lower_batch_ir_impl(d, irs, n, rates, n_rates));
 }
 int gp_edges_to_dem_text(const gp_edges* e, char** text, size_t* len) {
   return GP_GUARD(gp_edges_to_dem_text_impl(e, text, len));
@@ -1449,6 +1679,14 @@ int gp_edges_circuit_dem_text(const gp_edges* e, uint32_t circuit, char** text, 
 int gp_debug_device_flags(gp_driver* d, uint32_t* flags, uint32_t* flags_seen, int clear_seen) {
   return GP_GUARD(gp_debug_device_flags_impl(d, flags, flags_seen, clear_seen));
 }
+int gp_aggregate(gp_driver* d, const double* d_rates, size_t n_rates, double* d_q, size_t n_edges, void* stream) {
+  return GP_GUARD(gp_aggregate_impl(d, d_rates, n_rates, d_q, n_edges, stream));
+}
+int gp_aggregate_backward(gp_driver* d, const double* d_rates, size_t n_rates, const double* d_gq, size_t n_edges,
+                          double* d_grates, void* stream) {
+  return GP_GUARD(gp_aggregate_backward_impl(d, d_rates, n_rates, d_gq, n_edges, d_grates, stream));
+}
+uint64_t gp_structure_id(const gp_driver* d) { return d && d->structured ? d->struct_id : 0; }
 
 #undef GP_GUARD
 

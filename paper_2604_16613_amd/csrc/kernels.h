@@ -84,6 +84,7 @@ struct DevState {
   const uint32_t* chan_qb;
   const uint8_t* chan_kind;
   const double* chan_rate;
+  const uint32_t* chan_src;    // per channel (lowered order): its program-order number
   const uint32_t* chan_foff;
   const uint32_t* bnd_chan_off;
   const uint32_t* bnd_fault_off;
@@ -213,6 +214,17 @@ hipError_t enqueue_refresh(const DevState& st, uint32_t n_edges, hipStream_t str
 // Adjoint of stage 2: with dL/dq per hyperedge in st.gq, dL/d(rate) per
 // channel (lowered order) into st.gr.
 hipError_t enqueue_rates_gradient(const DevState& st, uint32_t n_edges, hipStream_t stream);
+
+// Stage 2 over the cached structure with every operand on the device (the
+// rate refresh and its adjoint without host transfers). rates: per channel in
+// program order; perm (may be null): hyperedge j of the caller's order is
+// device hyperedge perm[j]; q, gq: per hyperedge in the caller's order;
+// grates: per channel in program order. The forward writes q; the backward
+// recomputes the per-fault probabilities at `rates` and writes grates.
+hipError_t enqueue_aggregate(const DevState& st, uint32_t n_edges, const double* rates, const uint32_t* perm,
+                             double* q, hipStream_t stream);
+hipError_t enqueue_aggregate_backward(const DevState& st, uint32_t n_edges, const double* rates,
+                                      const uint32_t* perm, const double* gq, double* grates, hipStream_t stream);
 
 // Dynamic LDS the sweep needs for n qubits, and the largest it may use.
 size_t sweep_lds_bytes(uint32_t n_qubits);

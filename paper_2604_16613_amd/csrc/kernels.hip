@@ -1791,38 +1791,51 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
 
 // ------------------------------------------------------------------ rates
 
-// Per-fault probabilities from the channel rates now in the tables.
-__global__ __launch_bounds__(kBlock) void k_fault_p(DevState st) {
+// Rate of lowered channel c: from the driver's table, or (rates != null) from
+// a device array in program order.
+__device__ __forceinline__ double channel_rate(const DevState& st, const double* rates, uint32_t c) {
+  return rates ? rates[st.chan_src[c]] : st.chan_rate[c];
+}
+
+// Per-fault probabilities from the channel rates.
+__global__ __launch_bounds__(kBlock) void k_fault_p(DevState st, const double* __restrict__ rates) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= st.n_chan) return;
-  const double p = fault_probability(st.chan_kind[c], st.chan_rate[c]);
+  const double p = fault_probability(st.chan_kind[c], channel_rate(st, rates, c));
   for (uint32_t f = st.chan_foff[c]; f < st.chan_foff[c + 1]; ++f) st.frp[f].p = p;
 }
 
 // Eq. 3 again over each hyperedge's cached members (position order), with the
 // compile's shape: up to kBigSegment + 1 members one thread folds them in
-// order; larger classes are listed for k_remerge_big.
-__global__ __launch_bounds__(kBlock) void k_remerge(DevState st, const uint32_t* __restrict__ ord, uint32_t n_edges) {
-  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n_edges) return;
+// order; larger classes are listed for k_remerge_big. Thread j serves
+// hyperedge j of the output order (device hyperedge perm[j], or j) and
+// writes out[j].
+__global__ __launch_bounds__(kBlock) void k_remerge(DevState st, const uint32_t* __restrict__ ord, uint32_t n_edges,
+                                                    const uint32_t* __restrict__ perm, double* __restrict__ out) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_edges) return;
+  const uint32_t e = perm ? perm[j] : j;
   const uint32_t i0 = st.e_first[e], cnt = st.e_cnt[e];
   if (cnt > kBigSegment + 1) {
-    st.big[atomicAdd(&st.hdr->n_big, 1u)] = e;
+    st.big[atomicAdd(&st.hdr->n_big, 1u)] = j;
     return;
   }
   double q = st.frp[ord[i0]].p;
   for (uint32_t i = 1; i < cnt; ++i) q = fma(st.frp[ord[i0 + i]].p, 1.0 - 2.0 * q, q);
-  st.edge_q[e] = q;
+  out[j] = q;
 }
 
 // One block of kBucketBlock threads per listed hyperedge: strided partial
 // merges, then the fixed tree the bucket grouping uses.
-__global__ __launch_bounds__(kBucketBlock) void k_remerge_big(DevState st, const uint32_t* __restrict__ ord) {
+__global__ __launch_bounds__(kBucketBlock) void k_remerge_big(DevState st, const uint32_t* __restrict__ ord,
+                                                             const uint32_t* __restrict__ perm,
+                                                             double* __restrict__ out) {
   __shared__ double s_q[kBucketBlock];
   const int tid = threadIdx.x;
   const uint32_t nb = st.hdr->n_big;
   for (uint32_t g = blockIdx.x; g < nb; g += gridDim.x) {
-    const uint32_t e = st.big[g];
+    const uint32_t j = st.big[g];
+    const uint32_t e = perm ? perm[j] : j;
     const uint32_t i0 = st.e_first[e], cnt = st.e_cnt[e];
     double q = 0.0;
     for (uint32_t i = tid; i < cnt; i += kBucketBlock) q = fma(st.frp[ord[i0 + i]].p, 1.0 - 2.0 * q, q);
@@ -1835,7 +1848,7 @@ __global__ __launch_bounds__(kBucketBlock) void k_remerge_big(DevState st, const
       }
       __syncthreads();
     }
-    if (tid == 0) st.edge_q[e] = s_q[0];
+    if (tid == 0) out[j] = s_q[0];
     __syncthreads();
   }
 }
@@ -1848,10 +1861,13 @@ __global__ __launch_bounds__(kBlock) void k_clear_big(DevState st) {
 // so dq/dp_i = prod_{j != i} (1 - 2 p_j): the product of the members other
 // than those with p = 1/2, divided by (1 - 2 p_i); with one member at p = 1/2
 // only that member's derivative is non-zero, with two or more none is.
+// Thread j: dL/dq = gq[j] of device hyperedge perm[j] (or j).
 __global__ __launch_bounds__(kBlock) void k_adj_edges(DevState st, const uint32_t* __restrict__ ord,
-                                                      uint32_t n_edges) {
-  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n_edges) return;
+                                                      uint32_t n_edges, const uint32_t* __restrict__ perm,
+                                                      const double* __restrict__ gq) {
+  const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_edges) return;
+  const uint32_t e = perm ? perm[j] : j;
   const uint32_t i0 = st.e_first[e], cnt = st.e_cnt[e];
   uint32_t half = 0;
   double prod = 1.0;
@@ -1860,7 +1876,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_edges(DevState st, const uint32_
     if (p == 0.5) half++;
     else prod *= 1.0 - 2.0 * p;
   }
-  const double g = st.gq[e];
+  const double g = gq[j];
   for (uint32_t i = 0; i < cnt; ++i) {
     const uint32_t pos = ord[i0 + i];
     const double p = st.frp[pos].p;
@@ -1878,13 +1894,17 @@ __device__ __forceinline__ double fault_dp_dr(uint32_t kind, double r) {
   return 1.0;
 }
 
-// Per channel: its faults' dL/dp summed in fault order, times dp/dr.
-__global__ __launch_bounds__(kBlock) void k_adj_channels(DevState st) {
+// Per channel: its faults' dL/dp summed in fault order, times dp/dr; into
+// st.gr (lowered order) or, with `out`, out[program-order channel].
+__global__ __launch_bounds__(kBlock) void k_adj_channels(DevState st, const double* __restrict__ rates,
+                                                         double* __restrict__ out) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= st.n_chan) return;
   double sum = 0.0;
   for (uint32_t f = st.chan_foff[c]; f < st.chan_foff[c + 1]; ++f) sum += st.gfault[f];
-  st.gr[c] = sum * fault_dp_dr(st.chan_kind[c], st.chan_rate[c]);
+  const double g = sum * fault_dp_dr(st.chan_kind[c], channel_rate(st, rates, c));
+  if (out) out[st.chan_src[c]] = g;
+  else st.gr[c] = g;
 }
 
 __global__ __launch_bounds__(kBlock) void k_zero_f64(double* __restrict__ a, uint32_t n) {
@@ -2088,19 +2108,33 @@ hipError_t enqueue_compile(DevState& st_io, hipStream_t stream, const LaunchHook
 }
 
 hipError_t enqueue_refresh(const DevState& st, uint32_t n_edges, hipStream_t stream) {
-  if (st.n_chan) k_fault_p<<<cdiv(st.n_chan, kBlock), kBlock, 0, stream>>>(st);
-  k_clear_big<<<1, kBlock, 0, stream>>>(st);
-  if (n_edges) {
-    k_remerge<<<cdiv(n_edges, kBlock), kBlock, 0, stream>>>(st, st.ord, n_edges);
-    k_remerge_big<<<64, kBucketBlock, 0, stream>>>(st, st.ord);
-  }
-  return hipGetLastError();
+  return enqueue_aggregate(st, n_edges, nullptr, nullptr, st.edge_q, stream);
 }
 
 hipError_t enqueue_rates_gradient(const DevState& st, uint32_t n_edges, hipStream_t stream) {
   if (st.n_faults) k_zero_f64<<<min(cdiv(st.n_faults, kBlock), 4096u), kBlock, 0, stream>>>(st.gfault, st.n_faults);
-  if (n_edges) k_adj_edges<<<cdiv(n_edges, kBlock), kBlock, 0, stream>>>(st, st.ord, n_edges);
-  if (st.n_chan) k_adj_channels<<<cdiv(st.n_chan, kBlock), kBlock, 0, stream>>>(st);
+  if (n_edges) k_adj_edges<<<cdiv(n_edges, kBlock), kBlock, 0, stream>>>(st, st.ord, n_edges, nullptr, st.gq);
+  if (st.n_chan) k_adj_channels<<<cdiv(st.n_chan, kBlock), kBlock, 0, stream>>>(st, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t enqueue_aggregate(const DevState& st, uint32_t n_edges, const double* rates, const uint32_t* perm,
+                             double* q, hipStream_t stream) {
+  if (st.n_chan) k_fault_p<<<cdiv(st.n_chan, kBlock), kBlock, 0, stream>>>(st, rates);
+  k_clear_big<<<1, kBlock, 0, stream>>>(st);
+  if (n_edges) {
+    k_remerge<<<cdiv(n_edges, kBlock), kBlock, 0, stream>>>(st, st.ord, n_edges, perm, q);
+    k_remerge_big<<<64, kBucketBlock, 0, stream>>>(st, st.ord, perm, q);
+  }
+  return hipGetLastError();
+}
+
+hipError_t enqueue_aggregate_backward(const DevState& st, uint32_t n_edges, const double* rates,
+                                      const uint32_t* perm, const double* gq, double* grates, hipStream_t stream) {
+  if (st.n_chan) k_fault_p<<<cdiv(st.n_chan, kBlock), kBlock, 0, stream>>>(st, rates);
+  if (st.n_faults) k_zero_f64<<<min(cdiv(st.n_faults, kBlock), 4096u), kBlock, 0, stream>>>(st.gfault, st.n_faults);
+  if (n_edges) k_adj_edges<<<cdiv(n_edges, kBlock), kBlock, 0, stream>>>(st, st.ord, n_edges, perm, gq);
+  if (st.n_chan) k_adj_channels<<<cdiv(st.n_chan, kBlock), kBlock, 0, stream>>>(st, rates, grates);
   return hipGetLastError();
 }
 

@@ -235,28 +235,116 @@ struct RawChan {
 
 }  // namespace
 
+namespace {
+
+// The program-order scheduling of one circuit, fed one elementary operation
+// at a time by either front end (circuit text or the binary form): ASAP
+// layers, measurement records, noise channels at their boundary, and the
+// (measurement, detector-or-observable) memberships of the leaves (Eq. 2).
+// Each call returns 0 or a GP_E_* status with a message in `msg`.
+struct Sched {
+  std::vector<uint32_t> ready;     // per qubit: the first layer it is free in
+  std::vector<uint32_t> op_layer;
+  std::vector<uint64_t> op_word;
+  std::vector<RawChan> chans;
+  std::vector<uint64_t> pairs;     // (measurement << 32) | detector index or kObsFlag | observable
+  std::vector<uint32_t> meas_layer;
+  uint32_t n_meas = 0, n_det = 0, n_obs = 0;
+  const char* msg = nullptr;
+
+  int bad(int code, const char* m) {
+    msg = m;
+    return code;
+  }
+  int touch(uint32_t q) {
+    if (q > kMaxIndex) return bad(GP_E_BOUNDS, "qubit index too large");
+    if (q >= ready.size()) ready.resize(size_t(q) + 1, 0);
+    return 0;
+  }
+  // a one-qubit gate or a reset
+  int gate1(uint8_t kind, uint32_t q) {
+    if (int rc = touch(q)) return rc;
+    op_layer.push_back(ready[q]);
+    op_word.push_back(pack_op(kind, q, 0));
+    ready[q]++;
+    return 0;
+  }
+  int gate2(uint8_t kind, uint32_t a, uint32_t b) {
+    if (a == b) return bad(GP_E_PARSE, "repeated qubit in a two-qubit gate");
+    if (int rc = touch(a)) return rc;
+    if (int rc = touch(b)) return rc;
+    const uint32_t l = std::max(ready[a], ready[b]);
+    op_layer.push_back(l);
+    op_word.push_back(pack_op(kind, a, b));
+    ready[a] = ready[b] = l + 1;
+    return 0;
+  }
+  int measure(uint8_t kind, uint32_t q) {
+    if (int rc = touch(q)) return rc;
+    if (n_meas > kMaxIndex) return bad(GP_E_BOUNDS, "too many measurements");
+    op_layer.push_back(ready[q]);
+    op_word.push_back(pack_op(kind, q, n_meas));
+    meas_layer.push_back(ready[q]);
+    ready[q]++;
+    n_meas++;
+    return 0;
+  }
+  int noise1(uint8_t kind, uint32_t q, double r) {
+    if (!(r >= 0.0 && r <= rate_limit(kind))) return bad(GP_E_NOISE, "rate out of range");
+    if (int rc = touch(q)) return rc;
+    chans.push_back(RawChan{ready[q], q, UINT32_MAX, kind, r});
+    return 0;
+  }
+  int noise2(uint8_t kind, uint32_t a, uint32_t b, double r) {
+    if (!(r >= 0.0 && r <= rate_limit(kind))) return bad(GP_E_NOISE, "rate out of range");
+    if (a == b) return bad(GP_E_PARSE, "repeated qubit in a two-qubit channel");
+    if (int rc = touch(a)) return rc;
+    if (int rc = touch(b)) return rc;
+    // both halves of the fault must sit at one boundary: later operations on
+    // either qubit may not be scheduled before it
+    const uint32_t bnd = std::max(ready[a], ready[b]);
+    ready[a] = ready[b] = bnd;
+    chans.push_back(RawChan{bnd, a, b, kind, r});
+    return 0;
+  }
+  // a new detector / an observable's membership code
+  int detector(uint32_t& code) {
+    if (n_det >= kMaxIndex) return bad(GP_E_BOUNDS, "too many detectors");
+    code = n_det++;
+    return 0;
+  }
+  int observable(uint32_t k, uint32_t& code) {
+    if (k > 65535) return bad(GP_E_PARSE, "observable index above 65535");
+    n_obs = std::max(n_obs, k + 1);
+    code = kObsFlag | k;
+    return 0;
+  }
+  // measurement m (absolute, program order) belongs to `code`
+  int member(uint32_t m, uint32_t code) {
+    if (m >= n_meas) return bad(GP_E_PARSE, "record names a measurement that has not happened yet");
+    pairs.push_back((uint64_t(m) << 32) | code);
+    return 0;
+  }
+};
+
+int finish_lowering(Sched& S, const double* rates, size_t n_rates, uint32_t sweep_slots, Lowered& lw,
+                    LowerError& err, double fault_cost);
+
+}  // namespace
+
 int lower_circuit(const char* text, size_t len, const double* rates, size_t n_rates,
                   uint32_t sweep_slots, Lowered& lw, LowerError& err, uint32_t level, double fault_cost) {
   lw = Lowered();
   if (level > 2) return set_err(err, GP_E_ARG, 0, "%s", "correlation level must be 0, 1 or 2");
   if (!(fault_cost >= 0.0 && fault_cost < 1.0)) return set_err(err, GP_E_ARG, 0, "%s", "fault cost must be in [0, 1)");
   lw.level = level;
-  std::vector<uint32_t> ready;
-  std::vector<uint32_t> op_layer;
-  std::vector<uint64_t> op_word;
-  std::vector<RawChan> chans;
-  std::vector<uint64_t> pairs;  // (m << 32) | code
-  uint32_t n_meas = 0, n_det = 0, n_obs = 0;
+  Sched S;
   // sized from the text (typical circuits spend about four characters per
   // target) so that the vectors rarely regrow
-  op_layer.reserve(len / 4);
-  op_word.reserve(len / 4);
-  chans.reserve(len / 8);
-  pairs.reserve(len / 8);
-
-  auto touch = [&](uint32_t q) {
-    if (q >= ready.size()) ready.resize(size_t(q) + 1, 0);
-  };
+  S.op_layer.reserve(len / 4);
+  S.op_word.reserve(len / 4);
+  S.chans.reserve(len / 8);
+  S.pairs.reserve(len / 8);
 
   // tokenize whole-line chunks in parallel, then schedule (ASAP layers,
   // measurement records, channels) in program order
@@ -289,110 +377,148 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
   }
   uint32_t line_base = 0;
   for (const TokChunk& ck : chunks) {
-  for (const Tok& t : ck.toks) {
-    const Gate* g = t.g;
-    const int line = int(line_base + t.line);
+    for (const Tok& t : ck.toks) {
+      const Gate* g = t.g;
+      const int line = int(line_base + t.line);
       const size_t nt = t.t1 - t.t0;
       const uint32_t* targets = ck.targets.data() + t.t0;
       const uint8_t* is_rec = ck.is_rec.data() + t.t0;
       const char* name = g->name;
-      const int nargs = t.nargs;
-      const double args[1] = {t.arg0};
+      int rc = 0;
       switch (g->cls) {
         case G_PAULI:
-          for (size_t k = 0; k < nt; k++) touch(targets[k]);
+          for (size_t k = 0; k < nt && !rc; k++) rc = S.touch(targets[k]);
           break;
         case G_1Q:
         case G_RESET:
-          for (size_t k = 0; k < nt; k++) {
-            uint32_t q = targets[k];
-            touch(q);
-            op_layer.push_back(ready[q]);
-            op_word.push_back(pack_op(g->kind, q, 0));
-            ready[q]++;
-          }
+          for (size_t k = 0; k < nt && !rc; k++) rc = S.gate1(g->kind, targets[k]);
           break;
         case G_2Q:
           if (nt % 2) return set_err(err, GP_E_PARSE, line, "odd number of targets in %s", name);
-          for (size_t k = 0; k < nt; k += 2) {
-            uint32_t a = targets[k], b = targets[k + 1];
-            if (a == b) return set_err(err, GP_E_PARSE, line, "repeated qubit in %s", name);
-            touch(a);
-            touch(b);
-            uint32_t l = std::max(ready[a], ready[b]);
-            op_layer.push_back(l);
-            op_word.push_back(pack_op(g->kind, a, b));
-            ready[a] = ready[b] = l + 1;
-          }
+          for (size_t k = 0; k < nt && !rc; k += 2) rc = S.gate2(g->kind, targets[k], targets[k + 1]);
           break;
         case G_MEAS:
-          for (size_t k = 0; k < nt; k++) {
-            uint32_t q = targets[k];
-            touch(q);
-            if (n_meas > kMaxIndex) return set_err(err, GP_E_BOUNDS, line, "too many measurements at %s", name);
-            op_layer.push_back(ready[q]);
-            op_word.push_back(pack_op(g->kind, q, n_meas));
-            lw.meas_layer.push_back(ready[q]);
-            ready[q]++;
-            n_meas++;
-          }
+          for (size_t k = 0; k < nt && !rc; k++) rc = S.measure(g->kind, targets[k]);
           break;
         case G_N1:
         case G_N2: {
-          if (nargs != 1) return set_err(err, GP_E_PARSE, line, "%s takes one probability", name);
-          double r = args[0];
+          if (t.nargs != 1) return set_err(err, GP_E_PARSE, line, "%s takes one probability", name);
+          const double r = t.arg0;
           if (!(r >= 0.0 && r <= rate_limit(g->kind)))
             return set_err(err, GP_E_NOISE, line, "rate out of range in %s", name);
           if (g->cls == G_N1) {
-            for (size_t k = 0; k < nt; k++) {
-              uint32_t q = targets[k];
-              touch(q);
-              chans.push_back(RawChan{ready[q], q, UINT32_MAX, g->kind, r});
-            }
+            for (size_t k = 0; k < nt && !rc; k++) rc = S.noise1(g->kind, targets[k], r);
           } else {
             if (nt % 2) return set_err(err, GP_E_PARSE, line, "odd number of targets in %s", name);
-            for (size_t k = 0; k < nt; k += 2) {
-              uint32_t a = targets[k], b = targets[k + 1];
-              if (a == b) return set_err(err, GP_E_PARSE, line, "repeated qubit in %s", name);
-              touch(a);
-              touch(b);
-              // both halves of the fault must sit at one boundary: later
-              // operations on either qubit may not be scheduled before it
-              uint32_t bnd = std::max(ready[a], ready[b]);
-              ready[a] = ready[b] = bnd;
-              chans.push_back(RawChan{bnd, a, b, g->kind, r});
-            }
+            for (size_t k = 0; k < nt && !rc; k += 2) rc = S.noise2(g->kind, targets[k], targets[k + 1], r);
           }
           break;
         }
         case G_DET:
         case G_OBS: {
-          uint32_t code;
+          uint32_t code = 0;
           if (g->cls == G_DET) {
-            code = n_det++;
-            if (n_det > kMaxIndex) return set_err(err, GP_E_BOUNDS, line, "too many %s", "detectors");
+            rc = S.detector(code);
           } else {
-            if (nargs != 1 || args[0] < 0 || args[0] != std::floor(args[0]) || args[0] > 65535)
+            if (t.nargs != 1 || t.arg0 < 0 || t.arg0 != std::floor(t.arg0) || t.arg0 > 65535)
               return set_err(err, GP_E_PARSE, line, "%s needs one observable index", name);
-            uint32_t k = uint32_t(args[0]);
-            n_obs = std::max(n_obs, k + 1);
-            code = kObsFlag | k;
+            rc = S.observable(uint32_t(t.arg0), code);
           }
-          for (size_t k = 0; k < nt; k++) {
+          for (size_t k = 0; k < nt && !rc; k++) {
             if (!is_rec[k]) return set_err(err, GP_E_PARSE, line, "%s takes record targets", name);
-            if (targets[k] > n_meas) return set_err(err, GP_E_PARSE, line, "record looks back too far in %s", name);
-            uint32_t m = n_meas - targets[k];
-            pairs.push_back((uint64_t(m) << 32) | code);
+            if (targets[k] > S.n_meas) return set_err(err, GP_E_PARSE, line, "record looks back too far in %s", name);
+            rc = S.member(S.n_meas - targets[k], code);
           }
           break;
         }
         default:
           break;
       }
+      if (rc) return set_err(err, rc, line, "%s", S.msg);
+    }
+    if (ck.err_code) return set_err(err, ck.err_code, int(line_base + ck.err_line), ck.err_fmt, ck.err_what.c_str());
+    line_base += ck.lines;
   }
-  if (ck.err_code) return set_err(err, ck.err_code, int(line_base + ck.err_line), ck.err_fmt, ck.err_what.c_str());
-  line_base += ck.lines;
+  return finish_lowering(S, rates, n_rates, sweep_slots, lw, err, fault_cost);
+}
+
+int lower_ir(const gp_circuit_ir& ir, const double* rates, size_t n_rates, uint32_t sweep_slots, Lowered& lw,
+             LowerError& err, uint32_t level, double fault_cost) {
+  lw = Lowered();
+  if (level > 2) return set_err(err, GP_E_ARG, 0, "%s", "correlation level must be 0, 1 or 2");
+  if (!(fault_cost >= 0.0 && fault_cost < 1.0)) return set_err(err, GP_E_ARG, 0, "%s", "fault cost must be in [0, 1)");
+  if (ir.n_ops && !ir.code) return set_err(err, GP_E_ARG, 0, "%s", "operation codes missing");
+  lw.level = level;
+  Sched S;
+  S.op_layer.reserve(ir.n_ops);
+  S.op_word.reserve(ir.n_ops);
+  uint64_t ri = 0;  // next entry of ir.rec
+  char buf[160];
+  auto op_err = [&](uint64_t k, int code, const char* what) {
+    std::snprintf(buf, sizeof buf, "operation %llu: %s", (unsigned long long)k, what);
+    return set_err(err, code, 0, "%s", buf);
+  };
+  for (uint64_t k = 0; k < ir.n_ops; k++) {
+    const uint8_t c = ir.code[k];
+    const bool needs_q0 = c != GP_IR_DETECTOR;
+    const bool needs_q1 = c == GP_IR_CX || c == GP_IR_CZ || c == GP_IR_SWAP || c == GP_IR_DEPOLARIZE2 ||
+                          c == GP_IR_DETECTOR || c == GP_IR_OBSERVABLE;
+    const bool needs_rate = c >= GP_IR_X_ERROR && c <= GP_IR_DEPOLARIZE2;
+    if ((needs_q0 && !ir.q0) || (needs_q1 && !ir.q1) || (needs_rate && !ir.rate))
+      return op_err(k, GP_E_ARG, "an array this operation needs is missing");
+    int rc = 0;
+    switch (c) {
+      case GP_IR_PAULI: rc = S.touch(ir.q0[k]); break;
+      case GP_IR_H: rc = S.gate1(OP_H, ir.q0[k]); break;
+      case GP_IR_S: rc = S.gate1(OP_S, ir.q0[k]); break;
+      case GP_IR_SQRT_X: rc = S.gate1(OP_SQRTX, ir.q0[k]); break;
+      case GP_IR_R: rc = S.gate1(OP_R, ir.q0[k]); break;
+      case GP_IR_RX: rc = S.gate1(OP_RX, ir.q0[k]); break;
+      case GP_IR_CX: rc = S.gate2(OP_CX, ir.q0[k], ir.q1[k]); break;
+      case GP_IR_CZ: rc = S.gate2(OP_CZ, ir.q0[k], ir.q1[k]); break;
+      case GP_IR_SWAP: rc = S.gate2(OP_SWAP, ir.q0[k], ir.q1[k]); break;
+      case GP_IR_M: rc = S.measure(OP_M, ir.q0[k]); break;
+      case GP_IR_MX: rc = S.measure(OP_MX, ir.q0[k]); break;
+      case GP_IR_MR: rc = S.measure(OP_MR, ir.q0[k]); break;
+      case GP_IR_MRX: rc = S.measure(OP_MRX, ir.q0[k]); break;
+      case GP_IR_X_ERROR: rc = S.noise1(CH_X, ir.q0[k], ir.rate[k]); break;
+      case GP_IR_Y_ERROR: rc = S.noise1(CH_Y, ir.q0[k], ir.rate[k]); break;
+      case GP_IR_Z_ERROR: rc = S.noise1(CH_Z, ir.q0[k], ir.rate[k]); break;
+      case GP_IR_DEPOLARIZE1: rc = S.noise1(CH_DEP1, ir.q0[k], ir.rate[k]); break;
+      case GP_IR_DEPOLARIZE2: rc = S.noise2(CH_DEP2, ir.q0[k], ir.q1[k], ir.rate[k]); break;
+      case GP_IR_DETECTOR:
+      case GP_IR_OBSERVABLE: {
+        uint32_t code = 0;
+        rc = c == GP_IR_DETECTOR ? S.detector(code) : S.observable(ir.q0[k], code);
+        const uint64_t n = ir.q1[k];
+        if (!rc && n && !ir.rec) return op_err(k, GP_E_ARG, "record array missing");
+        if (!rc && ri + n > ir.n_rec) return op_err(k, GP_E_ARG, "records run past the record array");
+        for (uint64_t j = 0; j < n && !rc; j++) rc = S.member(ir.rec[ri + j], code);
+        ri += n;
+        break;
+      }
+      default:
+        return op_err(k, GP_E_UNSUPPORTED, "unknown operation code");
+    }
+    if (rc) return op_err(k, rc, S.msg);
   }
+  if (ri != ir.n_rec) return set_err(err, GP_E_ARG, 0, "%s", "record array longer than the annotations use");
+  return finish_lowering(S, rates, n_rates, sweep_slots, lw, err, fault_cost);
+}
+
+namespace {
+
+// Everything after the program-order pass: channel and fault tables, layers,
+// leaves, word columns, sweep items, windows and hash chunks.
+int finish_lowering(Sched& S, const double* rates, size_t n_rates, uint32_t sweep_slots, Lowered& lw,
+                    LowerError& err, double fault_cost) {
+  std::vector<uint32_t>& ready = S.ready;
+  std::vector<uint32_t>& op_layer = S.op_layer;
+  std::vector<uint64_t>& op_word = S.op_word;
+  std::vector<RawChan>& chans = S.chans;
+  std::vector<uint64_t>& pairs = S.pairs;
+  const uint32_t n_meas = S.n_meas, n_det = S.n_det, n_obs = S.n_obs;
+  lw.meas_layer.swap(S.meas_layer);
 
   // ---- sizes
   lw.n_qubits = uint32_t(ready.size());
@@ -770,6 +896,8 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
   if (inj_oom) return set_err(err, GP_E_OOM, 0, "%s", "host memory allocation failed while lowering");
   return 0;
 }
+
+}  // namespace
 
 void merge_branches(const std::vector<Lowered>& in, Lowered& out) {
   std::vector<const Lowered*> ptrs;

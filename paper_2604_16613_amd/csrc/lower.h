@@ -21,6 +21,8 @@
 #include <string>
 #include <vector>
 
+struct gp_circuit_ir;
+
 namespace gp {
 
 enum OpKind : uint8_t {
@@ -206,6 +208,11 @@ constexpr double kDefaultFaultCost = 6.2e-4;
 int lower_circuit(const char* text, size_t len, const double* rates, size_t n_rates,
                   uint32_t sweep_slots, Lowered& out, LowerError& err, uint32_t level = 2,
                   double fault_cost = kDefaultFaultCost);
+
+// The same for the binary form of a circuit (gp_circuit_ir in gp.h): the
+// same tables as lowering the equivalent text. Errors name the operation.
+int lower_ir(const ::gp_circuit_ir& ir, const double* rates, size_t n_rates, uint32_t sweep_slots, Lowered& out,
+             LowerError& err, uint32_t level = 2, double fault_cost = kDefaultFaultCost);
 
 // Re-apply a rate array to an already lowered circuit (same structure).
 int apply_rates(Lowered& lw, const double* rates, size_t n_rates, LowerError& err);

@@ -35,6 +35,12 @@ uint64_t now_ns() {
 struct Request {
   uint64_t ticket = 0;
   std::string text;
+  // a circuit submitted in binary form: its arrays, copied
+  bool is_ir = false;
+  uint64_t ir_n_ops = 0;
+  std::vector<uint8_t> ir_code;
+  std::vector<uint32_t> ir_q0, ir_q1, ir_rec;
+  std::vector<double> ir_rate;
   std::vector<double> rates;
   bool has_rates = false;
   uint64_t t_submit = 0, t_done = 0;
@@ -115,8 +121,21 @@ void lower_loop(gp_server* s, uint32_t level) {
     gp::LowerError err{};
     int rc;
     try {
-      rc = gp::lower_circuit(r->text.data(), r->text.size(), r->has_rates ? r->rates.data() : nullptr,
-                             r->has_rates ? r->rates.size() : 0, slots, r->lw, err, level);
+      const double* rates = r->has_rates ? r->rates.data() : nullptr;
+      const size_t n_rates = r->has_rates ? r->rates.size() : 0;
+      if (r->is_ir) {
+        gp_circuit_ir ir{};
+        ir.n_ops = r->ir_n_ops;
+        ir.code = r->ir_code.empty() ? nullptr : r->ir_code.data();
+        ir.q0 = r->ir_q0.empty() ? nullptr : r->ir_q0.data();
+        ir.q1 = r->ir_q1.empty() ? nullptr : r->ir_q1.data();
+        ir.rate = r->ir_rate.empty() ? nullptr : r->ir_rate.data();
+        ir.n_rec = r->ir_rec.size();
+        ir.rec = r->ir_rec.empty() ? nullptr : r->ir_rec.data();
+        rc = gp::lower_ir(ir, rates, n_rates, slots, r->lw, err, level);
+      } else {
+        rc = gp::lower_circuit(r->text.data(), r->text.size(), rates, n_rates, slots, r->lw, err, level);
+      }
     } catch (...) {
       // nothing may leave this thread: the request fails on its own
       r->lw = gp::Lowered();
@@ -285,6 +304,13 @@ extern "C" {
 static int gp_server_create_impl(const gp_bounds* bounds, int device, gp_server** out);
 static int gp_server_submit_impl(gp_server* s, const char* text, size_t len, const double* rates, size_t n_rates,
                                  uint64_t* ticket);
+static int gp_server_submit_ir_impl(gp_server* s, const gp_circuit_ir* ir, const double* rates, size_t n_rates,
+                                    uint64_t* ticket);
+
+int gp_server_submit_ir(gp_server* s, const gp_circuit_ir* ir, const double* rates, size_t n_rates,
+                        uint64_t* ticket) {
+  return gp::guarded([&] { return gp_server_submit_ir_impl(s, ir, rates, n_rates, ticket); });
+}
 
 int gp_server_create(const gp_bounds* bounds, int device, gp_server** out) {
   return gp::guarded([&] { return gp_server_create_impl(bounds, device, out); });
@@ -322,16 +348,8 @@ static int gp_server_create_impl(const gp_bounds* bounds, int device, gp_server*
   return GP_OK;
 }
 
-static int gp_server_submit_impl(gp_server* s, const char* text, size_t len, const double* rates, size_t n_rates,
-                                 uint64_t* ticket) {
-  if (!s || !text || !ticket || (!rates && n_rates)) return gp::set_last_error(GP_E_ARG, "null argument");
-  ReqPtr r = std::make_shared<Request>();
-  r->text.assign(text, len);
-  if (rates) {
-    r->rates.assign(rates, rates + n_rates);
-    r->has_rates = true;
-  }
-  r->held = len + uint64_t(n_rates) * sizeof(double);
+// Admit a request (or refuse it past the limits) and queue it for lowering.
+static int enqueue(gp_server* s, const ReqPtr& r, uint64_t* ticket) {
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return gp::set_last_error(GP_E_STATE, "the server is shutting down");
@@ -347,6 +365,43 @@ static int gp_server_submit_impl(gp_server* s, const char* text, size_t len, con
   s->cv_lower.notify_one();
   *ticket = r->ticket;
   return GP_OK;
+}
+
+static int gp_server_submit_impl(gp_server* s, const char* text, size_t len, const double* rates, size_t n_rates,
+                                 uint64_t* ticket) {
+  if (!s || !text || !ticket || (!rates && n_rates)) return gp::set_last_error(GP_E_ARG, "null argument");
+  ReqPtr r = std::make_shared<Request>();
+  r->text.assign(text, len);
+  if (rates) {
+    r->rates.assign(rates, rates + n_rates);
+    r->has_rates = true;
+  }
+  r->held = len + uint64_t(n_rates) * sizeof(double);
+  return enqueue(s, r, ticket);
+}
+
+static int gp_server_submit_ir_impl(gp_server* s, const gp_circuit_ir* ir, const double* rates, size_t n_rates,
+                                    uint64_t* ticket) {
+  if (!s || !ir || !ticket || (!rates && n_rates)) return gp::set_last_error(GP_E_ARG, "null argument");
+  if ((ir->n_ops && !ir->code) || (ir->n_rec && !ir->rec))
+    return gp::set_last_error(GP_E_ARG, "binary circuit without its operation codes or records");
+  ReqPtr r = std::make_shared<Request>();
+  r->is_ir = true;
+  const size_t n = size_t(ir->n_ops);
+  r->ir_n_ops = ir->n_ops;
+  if (n) {
+    r->ir_code.assign(ir->code, ir->code + n);
+    if (ir->q0) r->ir_q0.assign(ir->q0, ir->q0 + n);
+    if (ir->q1) r->ir_q1.assign(ir->q1, ir->q1 + n);
+    if (ir->rate) r->ir_rate.assign(ir->rate, ir->rate + n);
+  }
+  if (ir->n_rec) r->ir_rec.assign(ir->rec, ir->rec + ir->n_rec);
+  if (rates) {
+    r->rates.assign(rates, rates + n_rates);
+    r->has_rates = true;
+  }
+  r->held = n * (1 + 4 + 4 + 8) + ir->n_rec * 4 + uint64_t(n_rates) * sizeof(double);
+  return enqueue(s, r, ticket);
 }
 
 int gp_server_set_admission(gp_server* s, uint64_t max_requests, uint64_t max_bytes) {

@@ -18,7 +18,7 @@ import pytest
 import oracle
 from paper_2604_16613_amd import GpError, get_driver
 from paper_2604_16613_amd import _gp
-from workloads import log_uniform_rates, rotated_surface_code_memory
+from workloads import log_uniform_rates, logit_loss, rotated_surface_code_memory
 
 pytestmark = pytest.mark.gpu
 
@@ -37,7 +37,7 @@ def _weights(sigs, seed=1):
 def _gpu_dl_dq(hg, wmap):
     sigs = [tuple(int(b) for b in hg.bits[hg.offsets[e]:hg.offsets[e + 1]]) for e in range(len(hg))]
     w = np.array([wmap[s] for s in sigs])
-    return oracle.loss_and_dl_dq(hg.q, w)
+    return logit_loss(hg.q, w)
 
 
 def _oracle_dl_dq(res, wmap):
@@ -112,22 +112,54 @@ def test_refresh_and_gradient_after_other_groupings(c5, mode):
 
 
 def test_gradient_matches_device_finite_differences(c5):
+    """Central differences (h = 1e-7) of the device forward pass against the
+    device adjoint, each within the difference quotient's own error bound:
+    truncation h^2 |L3| / 6, with the third derivative L3 taken from a
+    five-point stencil of step 1e-2 r, plus rounding 2 u_L / (2h), where u_L
+    bounds the error of evaluating L_c = sum over the hyperedges channel c
+    moves of w_k log(q_k / (1 - q_k)) (a few ulps of each q, one ulp of each
+    log). Only the hyperedges the channel touches enter L_c, as the other
+    terms cancel exactly."""
     c, rates, drv = c5
     say("case c5 gradient vs central differences")
     hg = drv.compile_hypergraph(c.text, rates)
     wmap = _weights(hg.edges().keys())
-    _, g_q = _gpu_dl_dq(hg, wmap)
+    sigs = [tuple(int(b) for b in hg.bits[hg.offsets[e]:hg.offsets[e + 1]]) for e in range(len(hg))]
+    w = np.array([wmap[s_] for s_ in sigs])
+    _, g_q = logit_loss(hg.q, w)
     grad = drv.rates_gradient(g_q)
+    base = hg.q.copy()
     h = 1e-7
+    eps = np.finfo(np.float64).eps
     rng = np.random.default_rng(3)
+    worst = 0.0
     for ch in rng.choice(c.n_channels, 24, replace=False):
-        rp, rm = rates.copy(), rates.copy()
-        rp[ch] += h
-        rm[ch] -= h
-        lp = _gpu_dl_dq(drv.refresh_rates(rp), wmap)[0]
-        lm = _gpu_dl_dq(drv.refresh_rates(rm), wmap)[0]
-        fd = (lp - lm) / (2 * h)
-        assert abs(fd - grad[ch]) <= 1e-5 * abs(grad[ch]) + 1e-5, (int(ch), fd, grad[ch])
+        def q_at(x):
+            r = rates.copy()
+            r[ch] = x
+            return drv.refresh_rates(r).q
+
+        r0 = rates[ch]
+        qp, qm = q_at(r0 + h), q_at(r0 - h)
+        touched = (qp != base) | (qm != base)
+        assert touched.any()
+        wt = w[touched]
+
+        def L(q):
+            qt = q[touched]
+            return float(np.sum(wt * np.log(qt / (1.0 - qt))))
+
+        fd = (L(qp) - L(qm)) / (2 * h)
+        H = 1e-2 * r0
+        f3 = (L(q_at(r0 + 2 * H)) - 2 * L(q_at(r0 + H)) + 2 * L(q_at(r0 - H)) - L(q_at(r0 - 2 * H))) / (2 * H ** 3)
+        trunc = h * h * abs(f3) / 6.0
+        qt = base[touched]
+        u_l = float(np.sum(np.abs(wt) * (8 * eps / (1.0 - qt) + eps * np.abs(np.log(qt / (1.0 - qt))))))
+        bound = trunc + 2 * u_l / (2 * h)
+        err = abs(fd - grad[ch])
+        worst = max(worst, err / bound)
+        assert err <= 2.0 * bound, (int(ch), fd, grad[ch], trunc, bound)
+    say(f"  worst |fd - adjoint| / bound = {worst:.3f}")
     drv.refresh_rates(rates)
 
 
@@ -179,8 +211,66 @@ def test_state_and_argument_errors(c5):
     assert np.array_equal(again.q.view(np.uint64), hg.q.view(np.uint64))
 
 
-def test_torch_autograd_wrapper(c5):
+def _cuda():
     torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("torch sees no GPU")
+    return torch
+
+
+def test_device_pointer_aggregate_and_backward(c5):
+    """gp_aggregate / gp_aggregate_backward on device arrays and torch's
+    stream give bitwise what the host-array refresh and adjoint give."""
+    torch = _cuda()
+    c, rates, drv = c5
+    say("case device-pointer aggregate")
+    hg = drv.compile_hypergraph(c.text, rates)
+    r2 = log_uniform_rates(c.n_channels, 11)
+    dr = torch.tensor(r2, dtype=torch.float64, device="cuda")
+    dq = torch.empty(len(hg), dtype=torch.float64, device="cuda")
+    s = torch.cuda.current_stream().cuda_stream
+    _gp.gp_aggregate(drv.handle, dr.data_ptr(), dr.numel(), dq.data_ptr(), dq.numel(), s)
+    ref = drv.refresh_rates(r2)
+    assert np.array_equal(dq.cpu().numpy().view(np.uint64), ref.q.view(np.uint64))
+    wmap = _weights(hg.edges().keys(), seed=9)
+    _, g_q = _gpu_dl_dq(ref, wmap)
+    dg = torch.tensor(g_q, dtype=torch.float64, device="cuda")
+    dgr = torch.empty_like(dr)
+    # the backward takes its rates as an argument: apply others first
+    drv.refresh_rates(rates)
+    _gp.gp_aggregate_backward(drv.handle, dr.data_ptr(), dr.numel(), dg.data_ptr(), dg.numel(), dgr.data_ptr(), s)
+    host = drv.refresh_rates(r2)
+    expect = drv.rates_gradient(g_q)
+    assert np.array_equal(host.q.view(np.uint64), ref.q.view(np.uint64))
+    assert np.array_equal(dgr.cpu().numpy().view(np.uint64), expect.view(np.uint64))
+    with pytest.raises(GpError) as e:
+        _gp.gp_aggregate(drv.handle, dr.data_ptr(), dr.numel() - 1, dq.data_ptr(), dq.numel(), s)
+    assert e.value.code == -1
+
+
+def test_device_pointer_aggregate_on_a_batch():
+    """A batch result is listed circuit by circuit; the device aggregate
+    writes q in that order too (bitwise equal to the host refresh)."""
+    torch = _cuda()
+    from paper_2604_16613_amd import Driver
+    from workloads import iceberg_surface_batch
+    say("case device-pointer aggregate, batch")
+    texts = [cc.text for cc in iceberg_surface_batch(3, n_branches=8, seed=40)]
+    with Driver.from_batch(texts) as drv:
+        drv.compile_batch(texts)
+        U = int(drv.info()["n_edges"])
+        C = int(drv.info()["n_channels"])
+        r = log_uniform_rates(C, 4)
+        dr = torch.tensor(r, dtype=torch.float64, device="cuda")
+        dq = torch.empty(U, dtype=torch.float64, device="cuda")
+        _gp.gp_aggregate(drv.handle, dr.data_ptr(), C, dq.data_ptr(), U, torch.cuda.current_stream().cuda_stream)
+        ref = drv.refresh_rates(r)
+        assert len(ref.q) == U
+        assert np.array_equal(dq.cpu().numpy().view(np.uint64), ref.q.view(np.uint64))
+
+
+def test_torch_autograd_wrapper(c5):
+    torch = _cuda()
     from paper_2604_16613_amd.autograd import HypergraphFunction
     c, rates, drv = c5
     say("case torch autograd")
@@ -189,12 +279,43 @@ def test_torch_autograd_wrapper(c5):
     wmap = _weights(f.structure.edges().keys())
     sigs = [tuple(int(b) for b in f.structure.bits[f.structure.offsets[e]:f.structure.offsets[e + 1]])
             for e in range(len(f.structure))]
-    w = torch.tensor([wmap[s] for s in sigs], dtype=torch.float64)
-    r = torch.tensor(rates, dtype=torch.float64, requires_grad=True)
+    w = torch.tensor([wmap[s] for s in sigs], dtype=torch.float64, device="cuda")
+    r = torch.tensor(rates, dtype=torch.float64, device="cuda", requires_grad=True)
     q = f(r)
+    assert np.array_equal(q.detach().cpu().numpy().view(np.uint64), f.structure.q.view(np.uint64))
     loss = torch.sum(w * torch.log(q / (1 - q)))
     loss.backward()
     _, g_q = _gpu_dl_dq(f.structure, wmap)
     expect = drv.rates_gradient(g_q)
     # torch differentiates log(q / (1 - q)) through the division: dL/dq agrees to rounding
-    assert np.allclose(r.grad.numpy(), expect, rtol=1e-10, atol=0)
+    assert np.allclose(r.grad.cpu().numpy(), expect, rtol=1e-10, atol=0)
+
+
+def test_torch_autograd_keeps_each_forward_rates(c5):
+    """Two forward passes at different rates, then the backward of the first
+    alone: its gradient is the one at the first rates (the backward does not
+    use whatever rates the driver applied last). A compile of another circuit
+    between forward and backward is refused."""
+    torch = _cuda()
+    from paper_2604_16613_amd.autograd import HypergraphFunction
+    c, rates, drv = c5
+    say("case autograd with two forwards")
+    f = HypergraphFunction(drv, c.text)
+    f.compile(rates)
+    wmap = _weights(f.structure.edges().keys(), seed=4)
+    sigs = [tuple(int(b) for b in f.structure.bits[f.structure.offsets[e]:f.structure.offsets[e + 1]])
+            for e in range(len(f.structure))]
+    w = torch.tensor([wmap[s] for s in sigs], dtype=torch.float64, device="cuda")
+    r1 = torch.tensor(rates, dtype=torch.float64, device="cuda", requires_grad=True)
+    r2 = torch.tensor(log_uniform_rates(c.n_channels, 5), dtype=torch.float64, device="cuda", requires_grad=True)
+    q1 = f(r1)
+    q2 = f(r2)
+    torch.sum(w * torch.log(q1 / (1 - q1))).backward()
+    hg1 = drv.refresh_rates(rates)
+    _, g_q = _gpu_dl_dq(hg1, wmap)
+    expect = drv.rates_gradient(g_q)
+    assert np.allclose(r1.grad.cpu().numpy(), expect, rtol=1e-10, atol=0)
+    assert r2.grad is None
+    drv.compile_hypergraph(rotated_surface_code_memory(3, 3).text)
+    with pytest.raises(RuntimeError):
+        torch.sum(w * torch.log(q2 / (1 - q2))).backward()

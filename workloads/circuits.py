@@ -23,6 +23,20 @@ from typing import Dict, List, Optional, Sequence, Tuple
 import numpy as np
 
 
+# Operation codes of the compiler's binary circuit form (gp_circuit_ir in
+# include/gp.h): the same circuit as the text, one entry per elementary
+# operation in program order.
+IR_CODES = {
+    "I": 0, "X": 0, "Y": 0, "Z": 0,
+    "H": 1, "H_XZ": 1, "S": 2, "S_DAG": 2, "SQRT_Z": 2, "SQRT_Z_DAG": 2, "SQRT_X": 3, "SQRT_X_DAG": 3,
+    "CX": 4, "CNOT": 4, "ZCX": 4, "CZ": 5, "ZCZ": 5, "SWAP": 6,
+    "R": 7, "RZ": 7, "RX": 8, "M": 9, "MZ": 9, "MX": 10, "MR": 11, "MRZ": 11, "MRX": 12,
+    "X_ERROR": 16, "Y_ERROR": 17, "Z_ERROR": 18, "DEPOLARIZE1": 19, "DEPOLARIZE2": 20,
+    "DETECTOR": 32, "OBSERVABLE_INCLUDE": 33,
+}
+_TWO_QUBIT = {"CX", "CNOT", "ZCX", "CZ", "ZCZ", "SWAP"}
+
+
 @dataclasses.dataclass
 class Circuit:
     text: str
@@ -33,6 +47,10 @@ class Circuit:
     n_observables: int
     rounds: int
     name: str
+    #: the same circuit in binary form: arrays "code" (uint8), "q0", "q1"
+    #: (uint32), "rate" (float64), one entry per operation, and "rec" (uint32,
+    #: absolute measurement indices of the detectors' and observables' records)
+    ir: Optional[Dict[str, np.ndarray]] = None
 
     def channel_kinds(self) -> List[str]:
         """Noise instruction name of each channel, in channel order."""
@@ -61,16 +79,33 @@ class _Builder:
         self.n_obs = 0
         self.n_chan = 0
         self.max_q = -1
+        # binary form: parallel lists, one entry per operation
+        self._code: List[int] = []
+        self._q0: List[int] = []
+        self._q1: List[int] = []
+        self._rate: List[float] = []
+        self._rec: List[int] = []
 
     def _touch(self, qs: Sequence[int]) -> None:
         if qs:
             self.max_q = max(self.max_q, max(qs))
+
+    def _op(self, name: str, q0: Sequence[int], q1, rate: float = 0.0) -> None:
+        n = len(q0)
+        self._code.extend([IR_CODES[name]] * n)
+        self._q0.extend(q0)
+        self._q1.extend([q1] * n if isinstance(q1, int) else q1)
+        self._rate.extend([rate] * n)
 
     def gate(self, name: str, qs: Sequence[int]) -> None:
         if len(qs) == 0:
             return
         self._touch(qs)
         self.lines.append(name + " " + " ".join(str(q) for q in qs))
+        if name in _TWO_QUBIT:
+            self._op(name, qs[0::2], qs[1::2])
+        else:
+            self._op(name, qs, 0)
 
     def pairs(self, name: str, ps: Sequence[Tuple[int, int]]) -> None:
         flat = [q for p in ps for q in p]
@@ -82,6 +117,7 @@ class _Builder:
         self._touch(qs)
         self.lines.append(f"{name}({p!r}) " + " ".join(str(q) for q in qs))
         self.n_chan += len(qs)
+        self._op(name, qs, 0, p)
 
     def noise2(self, p: float, ps: Sequence[Tuple[int, int]]) -> None:
         if len(ps) == 0 or p is None:
@@ -90,6 +126,7 @@ class _Builder:
         self._touch(flat)
         self.lines.append(f"DEPOLARIZE2({p!r}) " + " ".join(str(q) for q in flat))
         self.n_chan += len(ps)
+        self._op("DEPOLARIZE2", flat[0::2], flat[1::2], p)
 
     def measure(self, name: str, qs: Sequence[int]) -> List[int]:
         """Emit a measurement instruction; return absolute measurement indices."""
@@ -105,11 +142,21 @@ class _Builder:
         c = "" if coords is None else "(" + ", ".join(repr(float(x)) for x in coords) + ")"
         self.lines.append(f"DETECTOR{c} " + self._recs(meas))
         self.n_det += 1
+        self._op("DETECTOR", [0], [len(meas)])
+        self._rec.extend(meas)
         return self.n_det - 1
 
     def observable(self, k: int, meas: Sequence[int]) -> None:
         self.lines.append(f"OBSERVABLE_INCLUDE({k}) " + self._recs(meas))
         self.n_obs = max(self.n_obs, k + 1)
+        self._op("OBSERVABLE_INCLUDE", [k], [len(meas)])
+        self._rec.extend(meas)
+
+    def binary(self) -> Dict[str, np.ndarray]:
+        """The circuit so far in the compiler's binary form."""
+        return {"code": np.array(self._code, dtype=np.uint8), "q0": np.array(self._q0, dtype=np.uint32),
+                "q1": np.array(self._q1, dtype=np.uint32), "rate": np.array(self._rate, dtype=np.float64),
+                "rec": np.array(self._rec, dtype=np.uint32)}
 
     def tick(self) -> None:
         self.lines.append("TICK")
@@ -124,6 +171,7 @@ class _Builder:
             n_observables=self.n_obs,
             rounds=rounds,
             name=name,
+            ir=self.binary(),
         )
 
 
