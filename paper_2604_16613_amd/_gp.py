@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import sys
 from typing import Optional, Sequence, Tuple
 
 import numpy as np
@@ -132,6 +133,29 @@ _vp = ctypes.c_void_p
 _u64 = ctypes.c_uint64
 
 
+def _share_hip_runtime_with_torch() -> None:
+    """One HIP runtime per process. PyTorch's ROCm wheel carries its own copy
+    of the HIP and HSA runtimes and loads them by file path, while libgp.so
+    names the HIP runtime by its soname. If libgp.so came first, the process
+    would hold two runtimes and torch would see no GPU (device tensors for
+    gp_aggregate and the autograd wrapper would be impossible). Loading
+    torch's copy first (by path, without importing torch) lets libgp.so bind
+    to it by soname, and a later ``import torch`` finds the same file already
+    loaded. Without torch installed, the system runtime is used."""
+    import importlib.util
+    if "torch" in sys.modules:
+        return  # torch's runtime is already the process's runtime
+    try:
+        spec = importlib.util.find_spec("torch")
+    except (ImportError, ValueError):
+        spec = None
+    if spec is None or not spec.submodule_search_locations:
+        return
+    hip = os.path.join(list(spec.submodule_search_locations)[0], "lib", "libamdhip64.so")
+    if os.path.exists(hip):
+        ctypes.CDLL(hip, mode=ctypes.RTLD_GLOBAL)
+
+
 def load():
     """Load libgp.so (raises if it has not been built)."""
     global _lib
@@ -140,6 +164,7 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(the compiler has no other implementation to fall back to)")
+    _share_hip_runtime_with_torch()
     lib = ctypes.CDLL(LIB_PATH)
     sig = {
         "gp_last_error": ([], ctypes.c_char_p),
