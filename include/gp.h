@@ -330,6 +330,23 @@ int gp_aggregate_backward(gp_driver* drv, const double* d_rates, size_t n_rates,
                           double* d_grates, void* stream);
 uint64_t gp_structure_id(const gp_driver* drv);
 
+/* gp_aggregate_backward for callers that cannot allocate device memory in the
+ * call: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation. Same arguments, checks, stream ordering and result
+ * (bitwise) as gp_aggregate_backward, but the per-fault dL/dp it accumulates
+ * lives in a static device array of the library (16 MiB: at most 2^21 =
+ * 2,097,152 faults per compile) instead of the driver's buffer, and the call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine).
+ * Each GPU the library runs on holds its own copy of that array from the first
+ * driver created on it until the process ends. The array is cleared by a fill
+ * kernel at the start of every call (it keeps the last call's contents
+ * otherwise). Calls that overlap on one GPU (two drivers or two streams of
+ * that device at once) share the array and race: serialise them.
+ * GP_E_BOUNDS when the fetched compile has more faults than the array holds;
+ * otherwise the errors of gp_aggregate_backward. */
+int gp_aggregate_backward_noalloc(gp_driver* drv, const double* d_rates, size_t n_rates, const double* d_gq,
+                                  size_t n_edges, double* d_grates, void* stream);
+
 /* Request server (continuous batching). A worker thread owns two drivers
  * created with `batch_bounds` (the bounds of one batch: max_branches circuits
  * at most, totals summed over them), each on its own HIP stream of default

@@ -40,7 +40,7 @@ EXPORTS = (
     "gp_debug_retry_counts", "gp_debug_set_spin_limit", "gp_debug_device_flags",
     "gp_compile_ir", "gp_lower_ir", "gp_lower_batch_ir", "gp_bounds_from_ir", "gp_bounds_from_batch_ir",
     "gp_server_submit_ir", "gp_edges_words", "gp_edges_signatures", "gp_aggregate", "gp_aggregate_backward",
-    "gp_structure_id",
+    "gp_structure_id", "gp_aggregate_backward_noalloc",
 )
 
 
@@ -190,6 +190,8 @@ def load():
         "gp_edges_words": ([_vp], ctypes.c_uint32),
         "gp_aggregate": ([_vp, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
         "gp_aggregate_backward": ([_vp, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp, _vp], ctypes.c_int),
+        "gp_aggregate_backward_noalloc": ([_vp, _vp, ctypes.c_size_t, _vp, ctypes.c_size_t, _vp, _vp],
+                                          ctypes.c_int),
         "gp_structure_id": ([_vp], _u64),
         "gp_edges_signatures": ([_vp], ctypes.POINTER(_u64)),
         "gp_lower": ([_vp, ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t],
@@ -732,6 +734,14 @@ def gp_aggregate_backward(drv: int, d_rates: int, n_rates: int, d_gq: int, n_edg
                           stream: int = 0) -> None:
     _check(load().gp_aggregate_backward(drv, d_rates or None, n_rates, d_gq or None, n_edges, d_grates or None,
                                         stream or None))
+
+
+def gp_aggregate_backward_noalloc(drv: int, d_rates: int, n_rates: int, d_gq: int, n_edges: int, d_grates: int,
+                                  stream: int = 0) -> None:
+    """gp_aggregate_backward with its per-fault scratch in the library's
+    static device array (no allocation in the call)."""
+    _check(load().gp_aggregate_backward_noalloc(drv, d_rates or None, n_rates, d_gq or None, n_edges,
+                                                d_grates or None, stream or None))
 
 
 def gp_structure_id(drv: int) -> int:

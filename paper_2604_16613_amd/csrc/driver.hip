@@ -499,6 +499,7 @@ static int gp_driver_create_impl(const gp_bounds* bounds, int device, gp_driver*
     return fail(GP_E_HIP, std::string("device is ") + prop.gcnArchName + ", this library is built for gfx950");
   HIP_TRY(hipSetDevice(device), "hipSetDevice");
   HIP_TRY(gp::configure_kernels(), "configure kernels");
+  HIP_TRY(gp::scratch_init(device), "static scratch address");
 
   gp_driver* d = new gp_driver();
   d->device = device;
@@ -1351,7 +1352,31 @@ static int gp_aggregate_backward_impl(gp_driver* d, const double* d_rates, size_
   int rc = device_perm(d, &perm);
   if (rc) return rc;
   return on_caller_stream(d, stream, [&](hipStream_t s) {
-    return gp::enqueue_aggregate_backward(d->st, uint32_t(n_edges), d_rates, perm, d_gq, d_grates, s);
+    return gp::enqueue_aggregate_backward(d->st, uint32_t(n_edges), d_rates, perm, d_gq, d_grates, nullptr, s);
+  });
+}
+
+// gp_aggregate_backward with its per-fault dL/dp in the library's static
+// device scratch instead of the driver's buffer; nothing is allocated.
+static int gp_aggregate_backward_noalloc_impl(gp_driver* d, const double* d_rates, size_t n_rates,
+                                              const double* d_gq, size_t n_edges, double* d_grates, void* stream) {
+  if (!d || (!d_rates && n_rates) || (!d_gq && n_edges) || (!d_grates && n_rates))
+    return fail(GP_E_ARG, "null argument");
+  if (!d->structured) return fail(GP_E_STATE, "gp_aggregate_backward_noalloc before a fetched compile");
+  if (n_edges != d->struct_edges) return fail(GP_E_ARG, "dL/dq length differs from the hyperedge count");
+  if (n_rates != d->lw.chan_kind.size()) return fail(GP_E_ARG, "rate array length differs from the channel count");
+  if (d->st.n_faults > gp::kScratchFaults)
+    return fail(GP_E_BOUNDS, "the compile has " + std::to_string(d->st.n_faults) +
+                                 " faults; the allocation-free adjoint holds at most " +
+                                 std::to_string(gp::kScratchFaults));
+  HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
+  double* scratch = gp::scratch_for(d->device);
+  if (!scratch) return fail(GP_E_STATE, "the static scratch of this device has no address");
+  const uint32_t* perm = nullptr;
+  int rc = device_perm(d, &perm);
+  if (rc) return rc;
+  return on_caller_stream(d, stream, [&](hipStream_t s) {
+    return gp::enqueue_aggregate_backward(d->st, uint32_t(n_edges), d_rates, perm, d_gq, d_grates, scratch, s);
   });
 }
 
@@ -1685,6 +1710,10 @@ int gp_aggregate(gp_driver* d, const double* d_rates, size_t n_rates, double* d_
 int gp_aggregate_backward(gp_driver* d, const double* d_rates, size_t n_rates, const double* d_gq, size_t n_edges,
                           double* d_grates, void* stream) {
   return GP_GUARD(gp_aggregate_backward_impl(d, d_rates, n_rates, d_gq, n_edges, d_grates, stream));
+}
+int gp_aggregate_backward_noalloc(gp_driver* d, const double* d_rates, size_t n_rates, const double* d_gq,
+                                  size_t n_edges, double* d_grates, void* stream) {
+  return GP_GUARD(gp_aggregate_backward_noalloc_impl(d, d_rates, n_rates, d_gq, n_edges, d_grates, stream));
 }
 uint64_t gp_structure_id(const gp_driver* d) { return d && d->structured ? d->struct_id : 0; }
 

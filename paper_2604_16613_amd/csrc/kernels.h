@@ -223,8 +223,19 @@ hipError_t enqueue_rates_gradient(const DevState& st, uint32_t n_edges, hipStrea
 // recomputes the per-fault probabilities at `rates` and writes grates.
 hipError_t enqueue_aggregate(const DevState& st, uint32_t n_edges, const double* rates, const uint32_t* perm,
                              double* q, hipStream_t stream);
+// gfault: the per-fault dL/dp buffer (null: the driver's st.gfault).
 hipError_t enqueue_aggregate_backward(const DevState& st, uint32_t n_edges, const double* rates,
-                                      const uint32_t* perm, const double* gq, double* grates, hipStream_t stream);
+                                      const uint32_t* perm, const double* gq, double* grates, double* gfault,
+                                      hipStream_t stream);
+
+// A per-fault dL/dp buffer of kScratchFaults doubles (16 MiB) in a static
+// device array, for the adjoint entry point that allocates nothing. Each GPU
+// holds its own copy until the process ends. scratch_init(device), with
+// `device` current, looks up this device's address once (later calls return
+// at once); scratch_for(device) returns it, or null before scratch_init.
+constexpr uint64_t kScratchFaults = uint64_t(1) << 21;
+hipError_t scratch_init(int device);
+double* scratch_for(int device);
 
 // Dynamic LDS the sweep needs for n qubits, and the largest it may use.
 size_t sweep_lds_bytes(uint32_t n_qubits);

@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "kernels.h"
 #include "lower.h"
@@ -1864,7 +1865,7 @@ __global__ __launch_bounds__(kBlock) void k_clear_big(DevState st) {
 // Thread j: dL/dq = gq[j] of device hyperedge perm[j] (or j).
 __global__ __launch_bounds__(kBlock) void k_adj_edges(DevState st, const uint32_t* __restrict__ ord,
                                                       uint32_t n_edges, const uint32_t* __restrict__ perm,
-                                                      const double* __restrict__ gq) {
+                                                      const double* __restrict__ gq, double* __restrict__ gfault) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n_edges) return;
   const uint32_t e = perm ? perm[j] : j;
@@ -1881,7 +1882,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_edges(DevState st, const uint32_
     const uint32_t pos = ord[i0 + i];
     const double p = st.frp[pos].p;
     const double d = half == 0 ? prod / (1.0 - 2.0 * p) : (half == 1 && p == 0.5 ? prod : 0.0);
-    st.gfault[pos] = g * d;
+    gfault[pos] = g * d;
   }
 }
 
@@ -1897,11 +1898,11 @@ __device__ __forceinline__ double fault_dp_dr(uint32_t kind, double r) {
 // Per channel: its faults' dL/dp summed in fault order, times dp/dr; into
 // st.gr (lowered order) or, with `out`, out[program-order channel].
 __global__ __launch_bounds__(kBlock) void k_adj_channels(DevState st, const double* __restrict__ rates,
-                                                         double* __restrict__ out) {
+                                                         const double* __restrict__ gfault, double* __restrict__ out) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= st.n_chan) return;
   double sum = 0.0;
-  for (uint32_t f = st.chan_foff[c]; f < st.chan_foff[c + 1]; ++f) sum += st.gfault[f];
+  for (uint32_t f = st.chan_foff[c]; f < st.chan_foff[c + 1]; ++f) sum += gfault[f];
   const double g = sum * fault_dp_dr(st.chan_kind[c], channel_rate(st, rates, c));
   if (out) out[st.chan_src[c]] = g;
   else st.gr[c] = g;
@@ -2113,8 +2114,8 @@ hipError_t enqueue_refresh(const DevState& st, uint32_t n_edges, hipStream_t str
 
 hipError_t enqueue_rates_gradient(const DevState& st, uint32_t n_edges, hipStream_t stream) {
   if (st.n_faults) k_zero_f64<<<min(cdiv(st.n_faults, kBlock), 4096u), kBlock, 0, stream>>>(st.gfault, st.n_faults);
-  if (n_edges) k_adj_edges<<<cdiv(n_edges, kBlock), kBlock, 0, stream>>>(st, st.ord, n_edges, nullptr, st.gq);
-  if (st.n_chan) k_adj_channels<<<cdiv(st.n_chan, kBlock), kBlock, 0, stream>>>(st, nullptr, nullptr);
+  if (n_edges) k_adj_edges<<<cdiv(n_edges, kBlock), kBlock, 0, stream>>>(st, st.ord, n_edges, nullptr, st.gq, st.gfault);
+  if (st.n_chan) k_adj_channels<<<cdiv(st.n_chan, kBlock), kBlock, 0, stream>>>(st, nullptr, st.gfault, nullptr);
   return hipGetLastError();
 }
 
@@ -2130,12 +2131,50 @@ hipError_t enqueue_aggregate(const DevState& st, uint32_t n_edges, const double*
 }
 
 hipError_t enqueue_aggregate_backward(const DevState& st, uint32_t n_edges, const double* rates,
-                                      const uint32_t* perm, const double* gq, double* grates, hipStream_t stream) {
+                                      const uint32_t* perm, const double* gq, double* grates, double* gfault,
+                                      hipStream_t stream) {
+  if (!gfault) gfault = st.gfault;
   if (st.n_chan) k_fault_p<<<cdiv(st.n_chan, kBlock), kBlock, 0, stream>>>(st, rates);
-  if (st.n_faults) k_zero_f64<<<min(cdiv(st.n_faults, kBlock), 4096u), kBlock, 0, stream>>>(st.gfault, st.n_faults);
-  if (n_edges) k_adj_edges<<<cdiv(n_edges, kBlock), kBlock, 0, stream>>>(st, st.ord, n_edges, perm, gq);
-  if (st.n_chan) k_adj_channels<<<cdiv(st.n_chan, kBlock), kBlock, 0, stream>>>(st, rates, grates);
+  // faults outside every hyperedge (empty signature) keep dL/dp = 0
+  if (st.n_faults) k_zero_f64<<<min(cdiv(st.n_faults, kBlock), 4096u), kBlock, 0, stream>>>(gfault, st.n_faults);
+  if (n_edges) k_adj_edges<<<cdiv(n_edges, kBlock), kBlock, 0, stream>>>(st, st.ord, n_edges, perm, gq, gfault);
+  if (st.n_chan) k_adj_channels<<<cdiv(st.n_chan, kBlock), kBlock, 0, stream>>>(st, rates, gfault, grates);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------ static scratch
+
+// Per-fault dL/dp of the allocation-free adjoint. In host code `scratch`
+// names a host-side stand-in, not device memory: kernels receive the device
+// address that hipGetSymbolAddress gives for the current device, kept per
+// device by scratch_init.
+static __device__ __align__(256) double scratch[kScratchFaults];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+hipError_t scratch_init(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device) return hipErrorInvalidDevice;  // the caller makes `device` current
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = static_cast<double*>(ptr);
+  return hipSuccess;
+}
+
+double* scratch_for(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 }  // namespace gp
