@@ -233,7 +233,7 @@ int gp_fetch_copy(gp_driver* drv, uint64_t* offsets, uint32_t* bits, double* q);
 int gp_lower_batch(gp_driver* drv, const char* const* texts, const size_t* lens, const double* const* rates,
                    const size_t* n_rates, size_t n);
 
-/* Autotuner for stage 1. An observable column stays live over the whole
+/* Autotuner for stage 1 and the stage-2 grouping. An observable column stays live over the whole
  * circuit, so it is cut into boundary ranges swept by separate work items;
  * the cut balances estimated item times in which a layer costs 1 and emitting
  * a boundary 1 + fault_cost per fault there. The sweep runs one work-group of
@@ -242,7 +242,10 @@ int gp_lower_batch(gp_driver* drv, const char* const* texts, const size_t* lens,
  * the batch, as gp_lower_batch with the rates in the texts) with each of a few
  * fault costs and each work-group size that fits, times `iters` device runs
  * of each (HIP events on the driver's stream) and keeps the fastest pair for
- * the following lowerings of this driver. Results are cached per process by
+ * the following lowerings of this driver. For that pair it then times the
+ * stage-2 groupings (the size's default, the full radix sort, the 65,536
+ * buckets; one whose runs raise a device flag is not a candidate) and keeps
+ * the fastest for the following runs. Results are cached per process by
  * the lowered shape (the key fields below): a shape already tuned is lowered
  * once to read its key and not timed again (cached = 1). *out (may be NULL)
  * receives the choice. The driver must be sized for the input. Afterwards no
@@ -258,6 +261,9 @@ typedef struct gp_tuning {
   uint32_t n_circuits, n_qubits, n_layers, n_det;
   uint64_t n_faults;
   uint32_t n_obs, level;
+  int32_t grouping;  /* stage-2 grouping (as gp_debug_set_sort_mode): 0 the size's default, 1 the full
+                      * radix sort, 2 the 65,536 buckets */
+  int32_t reserved;  /* 0 */
 } gp_tuning;
 int gp_autotune(gp_driver* drv, const char* text, size_t len, int iters, gp_tuning* out);
 int gp_autotune_batch(gp_driver* drv, const char* const* texts, const size_t* lens, size_t n, int iters,

@@ -88,6 +88,7 @@ class GpTuning(ctypes.Structure):
         ("n_circuits", ctypes.c_uint32), ("n_qubits", ctypes.c_uint32), ("n_layers", ctypes.c_uint32),
         ("n_det", ctypes.c_uint32), ("n_faults", ctypes.c_uint64),
         ("n_obs", ctypes.c_uint32), ("level", ctypes.c_uint32),
+        ("grouping", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -628,7 +629,9 @@ def gp_tuning_cache() -> list:
 def gp_tuning_cache_put(entry: dict) -> None:
     t = GpTuning()
     for k, _ in GpTuning._fields_:
-        if k != "cached":
+        if k in ("grouping", "reserved"):
+            setattr(t, k, entry.get(k, 0))   # files written before the grouping was tuned
+        elif k != "cached":
             setattr(t, k, entry[k])
     _check(load().gp_tuning_cache_put(ctypes.byref(t)))
 

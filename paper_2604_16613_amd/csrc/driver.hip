@@ -851,6 +851,8 @@ int gp_set_fault_cost(gp_driver* d, double fault_cost) {
   return GP_OK;
 }
 
+static int gp_debug_device_flags_impl(gp_driver* d, uint32_t* flags, uint32_t* flags_seen, int clear_seen);
+
 }  // extern "C"
 
 namespace {
@@ -929,6 +931,46 @@ int autotune(gp_driver* d, Lower&& lower, int iters, gp_tuning* out) {
         }
       }
     }
+    // the grouping for the chosen stage-1 split: the mode the size picks, the
+    // full radix sort, and the 65,536 buckets; a mode whose runs raise a
+    // device flag (a bucket over its LDS capacity, a look-back give-up) would
+    // need a re-run at fetch time and is not a candidate
+    const uint32_t saved_sort = d->sort_mode;
+    best.grouping = int32_t(gp::SORT_AUTO);
+    if (rc == GP_OK) {
+      d->fault_cost = best.fault_cost;
+      d->sweep_shape = best.sweep_block == 256 ? 2u : 1u;
+      rc = lower();
+    }
+    double auto_ms = -1.0;
+    for (uint32_t mode : {uint32_t(gp::SORT_AUTO), uint32_t(gp::SORT_FULL), uint32_t(gp::SORT_BUCKET16)}) {
+      if (rc) break;
+      d->sort_mode = mode;
+      uint32_t seen = 0;
+      if ((rc = gp_debug_device_flags_impl(d, nullptr, nullptr, 1)) || (rc = gp_run(d))) break;
+      float ms = 0.f;
+      if (hipEventRecord(a, d->stream) != hipSuccess) {
+        rc = hip_fail(hipGetLastError(), "hipEventRecord");
+        break;
+      }
+      for (int k = 0; k < iters && rc == GP_OK; k++) rc = gp_run(d);
+      if (rc) break;
+      if (hipEventRecord(b, d->stream) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+          hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        rc = hip_fail(hipGetLastError(), "timing the groupings");
+        break;
+      }
+      if ((rc = gp_debug_device_flags_impl(d, nullptr, &seen, 1))) break;
+      const double per = double(ms) / iters;
+      if (mode == gp::SORT_AUTO) auto_ms = per;
+      if (seen & (gp::FLAG_BUCKET | gp::FLAG_LOOKBACK | gp::FLAG_COLLISION)) continue;
+      if (mode == gp::SORT_AUTO || per < best.ms) {
+        best.ms = per;
+        best.grouping = int32_t(mode);
+      }
+    }
+    (void)auto_ms;
+    d->sort_mode = saved_sort;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
   }
@@ -942,6 +984,7 @@ int autotune(gp_driver* d, Lower&& lower, int iters, gp_tuning* out) {
   }
   d->fault_cost = best.fault_cost;
   d->sweep_shape = best.sweep_block == 256 ? 2u : 1u;
+  d->sort_mode = uint32_t(best.grouping);
   if (!best.cached) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune[tune_key(best)] = best;
@@ -986,6 +1029,7 @@ static int gp_tuning_cache_put_impl(const gp_tuning* t) {
   if (!(t->fault_cost > 0.0 && t->fault_cost < 1.0)) return fail(GP_E_ARG, "fault cost must lie in (0, 1)");
   if (t->sweep_block != 256 && t->sweep_block != 1024) return fail(GP_E_ARG, "sweep work-group must be 256 or 1024");
   if (t->level > 2) return fail(GP_E_ARG, "correlation level must be 0, 1 or 2");
+  if (t->grouping < 0 || t->grouping > 2) return fail(GP_E_ARG, "grouping must be 0, 1 or 2");
   std::lock_guard<std::mutex> g(g_tune_mu);
   g_tune[tune_key(*t)] = *t;
   return GP_OK;

@@ -540,49 +540,61 @@ __global__ __launch_bounds__(kBlk) void k_sweep(DevState st) {
   int t = top;
   // the next layer's offsets are read before each barrier
   uint32_t lo_t = LO(top);
-  int acc = 0;  // change in non-zero words not yet published
-  // layers above the emission range: transform only
+  // layers above the emission range: transform only, without counting the
+  // frame's non-zero words (nothing is emitted there)
   for (; t > bhi; --t) {
-    apply_layer(t, lo_t, acc);
+    int unused = 0;
+    apply_layer(t, lo_t, unused);
     advance(t);
-    const bool pub = ((top - t) % kCountEvery) == kCountEvery - 1 || t == bhi + 1;
-    if (pub) {
-      publish(acc);
-      acc = 0;
-    }
     const uint32_t lo_n = LO(t > 0 ? t - 1 : 0);
     lds_barrier();
     lo_hi = lo_t;
     lo_t = lo_n;
-    if (pub) {
-      const bool zero = t <= clo && count_published() == 0;
-      ck++;
-      if (zero) {
-        // the frame is zero and no leaf lies below: this column is zero on
-        // every boundary of this item's range (the item that holds this
-        // boundary records it)
-        dead = true;
-        break;
-      }
-    }
+  }
+  if (bhi < top) {
+    // count the non-zero words of the frame at boundary bhi + 1 once; the
+    // emission layers keep the count by differences from here
+    int cnt = 0;
+    for (uint32_t i = tid; i < 2 * n; i += kBlk) cnt += int(frame[i] != 0);
+    wave_nz = wave_total<10>(cnt);
+    if (lane == 0) s_wnz[ck & 1][wave] = wave_nz;
+    lds_barrier();
+    const bool zero = bhi + 1 <= clo && count_published() == 0;
+    ck++;
+    // the frame is zero and no leaf lies below: this column is zero on every
+    // boundary of this item's range (the item that holds the boundary where
+    // it died records it)
+    if (zero) dead = true;
   }
   if (!dead) {
     uint32_t f_hi = BFO(t + 1), f0 = BFO(t);
-    for (; t >= blo; --t) {
-      // A: fetch the records of the faults at boundary t (used in B), then
-      // transform the frame from boundary t+1 to boundary t, in place
-      const uint32_t nf = f_hi - f0;
-      uint32_t rec[kEmitPre];
+    // The Pauli records of boundary t's faults are loaded one layer ahead:
+    // while layer t is applied and emitted, boundary t-1's records are in
+    // flight (two register sets, the loop unrolled by two so that neither is
+    // copied while its loads are outstanding).
+    uint32_t recA[kEmitPre], recB[kEmitPre];
+    auto load_recs = [&](uint32_t (&r)[kEmitPre], uint32_t fa, uint32_t fb) {
+      const uint32_t nf = fb - fa;
 #pragma unroll
       for (int k = 0; k < kEmitPre; ++k) {
         const uint32_t i = tid + k * kBlk;
-        rec[k] = i < nf ? st.frec[f0 + i] : 0u;
+        r[k] = i < nf ? st.frec[fa + i] : 0u;
       }
+    };
+    load_recs(recA, f0, f_hi);
+    // one boundary: returns true when the item is done (range end or the
+    // frame died)
+    auto step = [&](uint32_t (&rec)[kEmitPre], uint32_t (&nxt)[kEmitPre]) -> bool {
+      // A: fetch the next boundary's records, then transform the frame from
+      // boundary t+1 to boundary t, in place
+      const uint32_t nf = f_hi - f0;
+      const uint32_t f_n = BFO(t > 0 ? t - 1 : 0);
+      if (t - 1 >= blo) load_recs(nxt, f_n, f0);
       int dnz = 0;
       apply_layer(t, lo_t, dnz);
       advance(t);
       publish(dnz);
-      const uint32_t lo_n = LO(t > 0 ? t - 1 : 0), f_n = BFO(t > 0 ? t - 1 : 0);
+      const uint32_t lo_n = LO(t > 0 ? t - 1 : 0);
       lds_barrier();
       lo_hi = lo_t;
       const bool zero = t <= clo && count_published() == 0;
@@ -623,12 +635,16 @@ __global__ __launch_bounds__(kBlk) void k_sweep(DevState st) {
         // lower boundary is zero in this column
         if (tid == 0) st.cover_lo[w] = t;
         dead = true;
-        break;
+        return true;
       }
       lo_t = lo_n;
       f_hi = f0;
       f0 = f_n;
       lds_barrier();
+      --t;
+      return t < blo;
+    };
+    while (!step(recA, recB) && !step(recB, recA)) {
     }
   }
   if (!dead && blo == 0) {
