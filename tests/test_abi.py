@@ -38,7 +38,11 @@ def test_bounds_from_circuit_sizes():
     assert (b.max_qubits, b.max_faults, b.max_channels, b.max_detectors) == (1249, 1013572, 108674, 15600)
     c = bivariate_bicycle_memory()
     b = _gp.gp_bounds_from_circuit(c.text)
-    assert (b.max_qubits, b.max_faults, b.max_detectors, b.max_observables) == (288, 168624, 1728, 12)
+    assert (b.max_qubits, b.max_faults, b.max_detectors, b.max_observables) == (288, 163440, 1728, 12)
+    assert (b.max_channels, b.max_layers) == (14256, 86)
+    c = bivariate_bicycle_memory(schedule="sequential")
+    b = _gp.gp_bounds_from_circuit(c.text)
+    assert (b.max_qubits, b.max_faults, b.max_channels, b.max_layers) == (288, 168624, 15984, 111)
 
 
 def test_bounds_from_batch_sizes():

@@ -121,6 +121,22 @@ def test_brute_force_mirror_circuits(seed):
     check_against_brute_force(c.text)
 
 
+def test_brute_force_x_basis_measure_reset():
+    """MRX (X-basis measure and reset) as the depth-8 bivariate bicycle cycle
+    uses it: two data qubits in |+>, their X parity read through an ancilla
+    that is measured and reset in the X basis every round, flips before the
+    X-basis measurements."""
+    lines = ["RX 0 1 2", "DEPOLARIZE1(0.02) 0 1 2"]
+    for r in range(3):
+        lines += ["CX 2 0", "DEPOLARIZE2(0.03) 2 0", "CX 2 1", "DEPOLARIZE2(0.04) 2 1",
+                  "Z_ERROR(0.05) 2", "MRX 2", "DEPOLARIZE1(0.01) 2"]
+        lines.append("DETECTOR rec[-1]" if r == 0 else "DETECTOR rec[-1] rec[-2]")
+    lines += ["Z_ERROR(0.06) 0 1", "MX 0 1", "DETECTOR rec[-1] rec[-2] rec[-3]", "OBSERVABLE_INCLUDE(0) rec[-2]"]
+    text = "\n".join(lines) + "\n"
+    res = check_against_brute_force(text)
+    assert res.n_detectors == 4 and res.n_observables == 1
+
+
 def test_brute_force_mirror_state_vector_engine():
     c = mirror_circuit(3, 3, 11, x_basis=[0])
     check_against_brute_force(c.text, engine="statevector")
@@ -138,12 +154,43 @@ def test_generators_deterministic():
     the random measurement outcomes are."""
     circuits = [rotated_surface_code_memory(3, 3), rotated_surface_code_memory(5, 2),
                 repetition_code_memory(5, 3), bit_flip_code_fig1(),
-                bivariate_bicycle_memory(rounds=2, l=6, m=6)]
+                bivariate_bicycle_memory(rounds=2, l=6, m=6),
+                bivariate_bicycle_memory(rounds=2, l=6, m=6, schedule="sequential"),
+                bivariate_bicycle_memory(rounds=2, l=12, m=6)]
     circuits += [mirror_circuit(4, 4, s, x_basis=[1]) for s in range(3)]
     for c in circuits:
         for kw in (dict(forced=0), dict(forced=1), dict(seed=5)):
             r = bs.Runner(c.text, **kw)
             assert not any(r.values), (c.name, kw)
+
+
+def test_bb_depth8_schedule_condition():
+    """The depth-8 slots meet every constraint they were searched under: one CX
+    per ancilla and per data qubit in each slot, seven CX slots, and the
+    pairwise order condition for X and Z checks sharing data; an assignment
+    that breaks only the order condition gives random detectors."""
+    import workloads.circuits as wc
+    s = wc.BB_DEPTH8_SLOTS
+    assert len(set(s["A"] + s["B"])) == 6 and len(set(s["BT"] + s["AT"])) == 6
+    assert not set(s["A"]) & set(s["BT"]) and not set(s["B"]) & set(s["AT"])
+    assert max(s["A"] + s["B"] + s["BT"] + s["AT"]) == 6
+    assert all((s["A"][k] > s["BT"][m]) == (s["B"][m] > s["AT"][k]) for k in range(3) for m in range(3))
+    c = bivariate_bicycle_memory(rounds=12)
+    assert _gp_layers(c.text) == 86      # seven layers per round in steady state
+    bad = dict(s, AT=(1, 5, 6))
+    assert not all((bad["A"][k] > bad["BT"][m]) == (bad["B"][m] > bad["AT"][k]) for k in range(3) for m in range(3))
+    old = wc.BB_DEPTH8_SLOTS
+    try:
+        wc.BB_DEPTH8_SLOTS = bad
+        c = wc.bivariate_bicycle_memory(rounds=3, l=6, m=6)
+    finally:
+        wc.BB_DEPTH8_SLOTS = old
+    assert any(bs.Runner(c.text, seed=5).values)
+
+
+def _gp_layers(text):
+    from paper_2604_16613_amd import _gp
+    return _gp.gp_bounds_from_circuit(text).max_layers
 
 
 def test_generator_codes():

@@ -504,15 +504,35 @@ def bb_logical_z(l: int = 12, m: int = 6) -> np.ndarray:
     return np.array(chosen, dtype=np.uint8)
 
 
-def bivariate_bicycle_memory(rounds: int = 12, p: float = 1e-3, l: int = 12, m: int = 6) -> Circuit:
+# Depth-8 syndrome cycle of a bivariate bicycle code: the CX slot (0..6) of
+# each permutation term, X checks (A_k on L data, B_k on R data) and Z checks
+# (B_k^T on L data, A_k^T on R data), then one slot of measure-and-reset.
+# Chosen by exhaustive search over slot assignments in which every ancilla and
+# every data qubit meets at most one CX per slot, subject to the condition that
+# makes the interleaved X and Z checks measure the stabilisers: an X check and
+# a Z check that share data qubits through the terms (A_k, B_m^T) on L and
+# (B_m, A_k^T) on R see those two qubits in the same relative order
+# (slot(A_k) > slot(B_m^T) exactly when slot(B_m) > slot(A_k^T)); with the nine
+# sums a_k + b_m distinct, this is the condition term pair by term pair.
+BB_DEPTH8_SLOTS = {"A": (0, 1, 5), "B": (2, 3, 4), "BT": (2, 3, 4), "AT": (5, 6, 1)}
+
+
+def bivariate_bicycle_memory(rounds: int = 12, p: float = 1e-3, l: int = 12, m: int = 6,
+                             schedule: str = "depth8") -> Circuit:
     """Z-basis memory of the bivariate bicycle code (default [[144,12,12]]).
 
     Qubits: L data 0..lm-1, R data lm..2lm-1, X ancillas, then Z ancillas.
-    Syndrome circuit: the six permutation terms of [A|B] are applied as six CX
-    layers from the X ancillas, then the six terms of [B^T|A^T] as six CX
-    layers onto the Z ancillas (twelve CX layers per round; every layer is a
-    permutation, so each qubit is touched once per layer).
+    schedule "depth8" (default): X ancillas are prepared and read in the X
+    basis (RX, then MRX each round), and the twelve permutation terms run in
+    seven CX slots (BB_DEPTH8_SLOTS) followed by one slot of measure-and-reset:
+    eight layers per round. schedule "sequential": X ancillas use H ... H and
+    MR, the six terms of [A|B] run as six CX layers, then the six terms of
+    [B^T|A^T] onto the Z ancillas. Noise: DEPOLARIZE1 after every one-qubit
+    gate and reset, DEPOLARIZE2 after every CX, a flip before every
+    measurement (Z_ERROR before an X-basis one, X_ERROR before a Z-basis one).
     """
+    if schedule not in ("depth8", "sequential"):
+        raise ValueError(f"unknown schedule {schedule!r}")
     nd = l * m
     a_terms, b_terms = bb_matrices(l, m)
     L = list(range(nd))
@@ -523,35 +543,66 @@ def bivariate_bicycle_memory(rounds: int = 12, p: float = 1e-3, l: int = 12, m: 
     data = L + R
     allq = data + anc
     b = _Builder()
-    b.gate("R", allq)
-    b.noise1("DEPOLARIZE1", p, allq)
-    b.tick()
+
+    def x_pairs(blk, t):   # X check i -> its data qubit of term t
+        return [(xa[i], blk[int(np.nonzero(t[i])[0][0])]) for i in range(nd)]
+
+    def z_pairs(blk, t):   # data qubit of term t^T of Z check i -> Z check i
+        tt = t.T
+        return [(blk[int(np.nonzero(tt[i])[0][0])], za[i]) for i in range(nd)]
+
+    if schedule == "depth8":
+        b.gate("R", data + za)
+        b.gate("RX", xa)
+        b.noise1("DEPOLARIZE1", p, allq)
+        b.tick()
+        slots = [[] for _ in range(7)]
+        for k in range(3):
+            slots[BB_DEPTH8_SLOTS["A"][k]] += x_pairs(L, a_terms[k])
+            slots[BB_DEPTH8_SLOTS["B"][k]] += x_pairs(R, b_terms[k])
+            slots[BB_DEPTH8_SLOTS["BT"][k]] += z_pairs(L, b_terms[k])
+            slots[BB_DEPTH8_SLOTS["AT"][k]] += z_pairs(R, a_terms[k])
+    else:
+        b.gate("R", allq)
+        b.noise1("DEPOLARIZE1", p, allq)
+        b.tick()
     last: Dict[int, int] = {}
     for rnd in range(rounds):
-        b.gate("H", xa)
-        b.noise1("DEPOLARIZE1", p, xa)
-        b.tick()
-        # X checks: row i of A (on L) and of B (on R).
-        for blk, terms in ((L, a_terms), (R, b_terms)):
-            for t in terms:
-                pairs = [(xa[i], blk[int(np.nonzero(t[i])[0][0])]) for i in range(nd)]
+        if schedule == "depth8":
+            for pairs in slots:
                 b.pairs("CX", pairs)
                 b.noise2(p, pairs)
                 b.tick()
-        b.gate("H", xa)
-        b.noise1("DEPOLARIZE1", p, xa)
-        b.tick()
-        # Z checks: row i of B^T (on L) and of A^T (on R).
-        for blk, terms in ((L, b_terms), (R, a_terms)):
-            for t in terms:
-                tt = t.T
-                pairs = [(blk[int(np.nonzero(tt[i])[0][0])], za[i]) for i in range(nd)]
-                b.pairs("CX", pairs)
-                b.noise2(p, pairs)
-                b.tick()
-        b.noise1("X_ERROR", p, anc)
-        ms = b.measure("MR", anc)
-        b.noise1("DEPOLARIZE1", p, anc)
+            b.noise1("Z_ERROR", p, xa)
+            b.noise1("X_ERROR", p, za)
+            mx = b.measure("MRX", xa)
+            mz = b.measure("MR", za)
+            ms = mx + mz
+            b.noise1("DEPOLARIZE1", p, anc)
+        else:
+            b.gate("H", xa)
+            b.noise1("DEPOLARIZE1", p, xa)
+            b.tick()
+            # X checks: row i of A (on L) and of B (on R).
+            for blk, terms in ((L, a_terms), (R, b_terms)):
+                for t in terms:
+                    pairs = x_pairs(blk, t)
+                    b.pairs("CX", pairs)
+                    b.noise2(p, pairs)
+                    b.tick()
+            b.gate("H", xa)
+            b.noise1("DEPOLARIZE1", p, xa)
+            b.tick()
+            # Z checks: row i of B^T (on L) and of A^T (on R).
+            for blk, terms in ((L, b_terms), (R, a_terms)):
+                for t in terms:
+                    pairs = z_pairs(blk, t)
+                    b.pairs("CX", pairs)
+                    b.noise2(p, pairs)
+                    b.tick()
+            b.noise1("X_ERROR", p, anc)
+            ms = b.measure("MR", anc)
+            b.noise1("DEPOLARIZE1", p, anc)
         cur = dict(zip(anc, ms))
         if rnd == 0:
             for a in za:
@@ -570,7 +621,8 @@ def bivariate_bicycle_memory(rounds: int = 12, p: float = 1e-3, l: int = 12, m: 
     logicals = bb_logical_z(l, m)
     for k, v in enumerate(logicals):
         b.observable(k, [md[int(q)] for q in np.nonzero(v)[0]])
-    return b.build(rounds, f"bivariate_bicycle_{2 * nd}_r{rounds}")
+    tag = "" if schedule == "depth8" else "_seq"
+    return b.build(rounds, f"bivariate_bicycle_{2 * nd}_r{rounds}{tag}")
 
 
 # ---------------------------------------------------------------------------
