@@ -90,16 +90,21 @@ def kernel_bytes(name: str, info: dict, launches: int = 1, record_pass: bool = F
     if name == "k_hash":
         return 8.0 * nz + words / 8.0 + F * (8 + 8 + 4 + 16)  # read both; key, check, weight, edge record written
     if name == "k_bucket":
-        return live * (8 + 4 + 4 + 16) + U * (8 + 4 + 4)     # keys, positions, gathers; class records
+        return live * (8 + 4 + 4 + 16) + U * (16 + 8)        # keys, positions, members, records; class records + bitmap
     if name == "k_compact":
         return F * 4.0 + live * (8 + 8 + 4)     # weights read; live keys read, (key, pos) written
     if name == "k_onesweep":
         # (key, pos) read and written per pass; the record pass moves 16 B more each way
         return launches * live * (8 + 4) * 2.0 + (live * 16 * 2.0 if record_pass else 0.0)
     if name == "k_reduce":
-        return live * (4 + 8 + 8) + U * (4 + 8 + 4 + 4)
+        return live * (4 + 8 + 8) + U * (16 + 8)
+    if name == "k_rep_list":
+        return F / 8.0 + U * (4 + 4 + 4)        # bitmap, weights; positions and first bits written
     if name == "k_edge_write":
-        return U * (4 + 8 + 4) + info["n_edge_bits"] * 4.0
+        # position, first bit, class and edge records of each representative;
+        # q and members written; bits written, at most one 8-byte signature
+        # word read per bit
+        return U * (4 + 4 + 16 + 16) + U * (8 + 4 + 4) + info["n_edge_bits"] * (4.0 + 8.0)
     if name in ("k_heads_count", "k_heads_apply"):
         return launches * live * 8.0
     if name == "k_prepare":

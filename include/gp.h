@@ -204,27 +204,31 @@ int gp_lower(gp_driver* drv, const char* text, size_t len, const double* rates, 
 int gp_run(gp_driver* drv);
 int gp_fetch(gp_driver* drv, gp_edges** out);
 
-/* Fetch of a single circuit's result into caller-owned host arrays, with one
- * host copy. gp_fetch_sizes does what gp_fetch does up to the download (wait,
- * error flags, retries; the same status codes) and returns the hyperedge and
- * signature-bit counts (n_det, n_obs: the circuit's detector and observable
- * counts; may be NULL). gp_fetch_copy then fills offsets (n_edges + 1 entries,
- * edge e's bits are bits[offsets[e] .. offsets[e+1])), bits (n_bits) and q
- * (n_edges), laid out as gp_edges_offsets/bits/probabilities; it may be called
- * again until the next gp_lower, gp_run or fetch. GP_E_STATE for a batch
- * lowering (use gp_fetch) and for gp_fetch_copy without a current
+/* Fetch of a result into caller-owned host arrays, with one host copy.
+ * gp_fetch_sizes does what gp_fetch does up to the download (wait, error
+ * flags, retries; the same status codes) and returns the hyperedge and
+ * signature-bit counts (n_det, n_obs: the detector and observable counts, of
+ * a batch the largest of any circuit; may be NULL). gp_fetch_copy then fills
+ * offsets (n_edges + 1 entries, edge e's bits are bits[offsets[e] ..
+ * offsets[e+1])), bits (n_bits) and q (n_edges), laid out as
+ * gp_edges_offsets/bits/probabilities; a batch's hyperedges are listed circuit
+ * by circuit, and gp_fetch_circuit_offsets fills the circuits + 1 offsets
+ * (circuit k owns hyperedges circuit_offsets[k] .. circuit_offsets[k+1]-1, its
+ * bits numbered as in gp_edges_circuit_shape). Both may be called again until
+ * the next gp_lower, gp_run or fetch; GP_E_STATE without a current
  * gp_fetch_sizes. Rate refreshes and the adjoint work after it as after
  * gp_fetch. */
 int gp_fetch_sizes(gp_driver* drv, uint64_t* n_edges, uint64_t* n_bits, uint32_t* n_det, uint32_t* n_obs);
 int gp_fetch_copy(gp_driver* drv, uint64_t* offsets, uint32_t* bits, double* q);
+int gp_fetch_circuit_offsets(gp_driver* drv, uint64_t* circuit_offsets);
 
 /* Lower n independent circuits as one batch; gp_run then compiles them all in
  * one pass of each stage and gp_fetch returns every circuit's hyperedges in
  * one gp_edges, tagged by circuit (gp_edges_circuit_ids). Each circuit is
  * grouped on its own: a hyperedge never merges faults of two circuits, and
- * circuit k's hyperedges are those a compile of circuit k alone gives (same
- * bits; the same probabilities, bitwise when both compiles take the same
- * stage-2 grouping; the order may differ). `rates` (host,
+ * circuit k's hyperedges are those a compile of circuit k alone gives, in the
+ * same order (same bits; the same probabilities, bitwise when both compiles
+ * take the same stage-2 grouping). `rates` (host,
  * may be NULL) holds one rate array per circuit (rates[k] NULL = the rates in
  * texts[k]) of n_rates[k] entries. For gp_refresh_rates and gp_rates_gradient
  * the channels of a batch are numbered circuit by circuit: circuit 0's in
@@ -409,6 +413,9 @@ int gp_sync(gp_driver* drv);
 void* gp_driver_stream(gp_driver* drv);
 
 int gp_circuit_info_get(const gp_driver* drv, gp_circuit_info* out);
+/* Detector and observable counts of circuit `circuit` of the current
+ * lowering (0 after gp_lower); GP_E_ARG past the last circuit. */
+int gp_circuit_shape(const gp_driver* drv, uint32_t circuit, uint32_t* n_det, uint32_t* n_obs);
 
 /* Per-kernel timing with HIP events recorded on the driver's stream around
  * every launch while enabled. Totals accumulate over gp_run calls until reset;
@@ -484,8 +491,11 @@ int gp_debug_sweep_times(gp_driver* drv, uint64_t* out, uint64_t cap, uint64_t* 
 /* Result accessors. Hyperedge e has signature bits
  *   bits[offsets[e]] ... bits[offsets[e+1]-1]   (strictly increasing),
  * where bit b < n_detectors is detector b and bit n_detectors + k is
- * observable k, and probability probabilities[e]. Edge order is unspecified
- * (deterministic for a given circuit). Pointers stay valid until gp_edges_free.
+ * observable k, and probability probabilities[e]. Hyperedges are ordered by
+ * their lowest fault (the class member with the lowest position in the
+ * lowered fault order: channels by boundary, then program order), so the
+ * order is deterministic for a given circuit and a batch is listed circuit by
+ * circuit. Pointers stay valid until gp_edges_free.
  * A batch result lists the hyperedges circuit by circuit: circuit k owns
  * hyperedges circuit_offsets[k] .. circuit_offsets[k+1]-1 (n_circuits + 1
  * offsets; circuit_ids[e] names the circuit of each hyperedge); bits use

@@ -37,6 +37,7 @@ EXPORTS = (
     "gp_server_destroy", "gp_server_timing", "gp_debug_set_graph", "gp_autotune", "gp_set_fault_cost",
     "gp_debug_set_sweep_shape", "gp_autotune_batch", "gp_tuning_cache_size", "gp_tuning_cache_get",
     "gp_tuning_cache_put", "gp_server_set_admission", "gp_fetch_sizes", "gp_fetch_copy",
+    "gp_fetch_circuit_offsets", "gp_circuit_shape",
     "gp_debug_retry_counts", "gp_debug_set_spin_limit", "gp_debug_device_flags",
     "gp_compile_ir", "gp_lower_ir", "gp_lower_batch_ir", "gp_bounds_from_ir", "gp_bounds_from_batch_ir",
     "gp_server_submit_ir", "gp_edges_words", "gp_edges_signatures", "gp_aggregate", "gp_aggregate_backward",
@@ -255,6 +256,9 @@ def load():
         "gp_fetch_sizes": ([_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(ctypes.c_uint32),
                             ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
         "gp_fetch_copy": ([_vp, _vp, _vp, _vp], ctypes.c_int),
+        "gp_fetch_circuit_offsets": ([_vp, _vp], ctypes.c_int),
+        "gp_circuit_shape": ([_vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_uint32)],
+                             ctypes.c_int),
         "gp_server_destroy": ([_vp], None),
         "gp_server_timing": ([_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
@@ -444,8 +448,9 @@ def gp_fetch(drv: int) -> int:
     return h.value
 
 
-def gp_fetch_arrays(drv: int):
-    """Single-circuit result with one host copy -> (n_det, n_obs, offsets, bits, q)."""
+def gp_fetch_arrays(drv: int, n_circuits: int = 1):
+    """Result with one host copy -> (n_det, n_obs, offsets, bits, q,
+    circuit_offsets); the hyperedges are listed circuit by circuit."""
     lib = load()
     U, nb = _u64(), _u64()
     nd, no = ctypes.c_uint32(), ctypes.c_uint32()
@@ -455,7 +460,9 @@ def gp_fetch_arrays(drv: int):
     q = np.empty(U.value, dtype=np.float64)
     _check(lib.gp_fetch_copy(drv, off.ctypes.data, bits.ctypes.data if nb.value else None,
                              q.ctypes.data if U.value else None))
-    return nd.value, no.value, off, bits, q
+    coff = np.empty(n_circuits + 1, dtype=np.uint64)
+    _check(lib.gp_fetch_circuit_offsets(drv, coff.ctypes.data))
+    return nd.value, no.value, off, bits, q, coff
 
 
 def gp_sync(drv: int) -> None:
@@ -548,6 +555,14 @@ def gp_edges_circuit_ids(e: int) -> np.ndarray:
 def gp_edges_circuit_offsets(e: int) -> np.ndarray:
     n = gp_edges_circuits(e) + 1
     return np.ctypeslib.as_array(load().gp_edges_circuit_offsets(e), shape=(n,)).copy()
+
+
+def gp_circuit_shape(drv: int, circuit: int) -> Tuple[int, int]:
+    """(detectors, observables) of circuit `circuit` of the driver's lowering."""
+    d = ctypes.c_uint32()
+    o = ctypes.c_uint32()
+    _check(load().gp_circuit_shape(drv, circuit, ctypes.byref(d), ctypes.byref(o)))
+    return d.value, o.value
 
 
 def gp_edges_circuit_shape(e: int, circuit: int) -> Tuple[int, int]:

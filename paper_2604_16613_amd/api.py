@@ -132,6 +132,10 @@ class Driver:
                    words: bool = False) -> Hypergraph:
         """The same for a circuit in binary form (dict of arrays, see
         workloads' Circuit.ir and gp_circuit_ir)."""
+        if level is None and not words:
+            self.lower_ir(ir, rates)
+            self.run()
+            return self.fetch()
         self._batch = False
         return _take(_gp.gp_compile_ir(self.handle, ir, rates, -1 if level is None else level), words)
 
@@ -176,7 +180,18 @@ class Driver:
         return self.fetch_batch()
 
     def fetch_batch(self) -> List[Hypergraph]:
-        return _take_batch(_gp.gp_fetch(self.handle))
+        """One Hypergraph per circuit of the batch (one host copy of the
+        result; each circuit's arrays are views of it, its offsets rebased)."""
+        n = int(self.info()["n_circuits"])
+        _, _, off, bits, q, coff = _gp.gp_fetch_arrays(self.handle, n)
+        out = []
+        for k in range(n):
+            a, b = int(coff[k]), int(coff[k + 1])
+            nd, no = _gp.gp_circuit_shape(self.handle, k)
+            o = off[a:b + 1]
+            out.append(Hypergraph(n_detectors=nd, n_observables=no, offsets=o - o[0],
+                                  bits=bits[int(o[0]):int(o[-1])], q=q[a:b]))
+        return out
 
     def run(self) -> None:
         _gp.gp_run(self.handle)
@@ -189,7 +204,7 @@ class Driver:
         circuit by circuit, as one Hypergraph; see fetch_batch)."""
         if self._batch:
             return _take(_gp.gp_fetch(self.handle))
-        nd, no, off, bits, q = _gp.gp_fetch_arrays(self.handle)
+        nd, no, off, bits, q, _ = _gp.gp_fetch_arrays(self.handle)
         return Hypergraph(n_detectors=nd, n_observables=no, offsets=off, bits=bits, q=q)
 
     def info(self) -> dict:

@@ -199,9 +199,6 @@ struct gp_driver {
   bool structured = false;     // a fetched compile left its class structure on the device
   uint64_t struct_edges = 0;   // hyperedges of that compile
   uint64_t struct_id = 0;      // bumped by every fetch that leaves a structure (gp_structure_id)
-  std::vector<uint32_t> edge_perm;  // batch: device hyperedge of each fetched one (empty: same order)
-  uint32_t* d_perm = nullptr;  // edge_perm on the device, for the device-pointer aggregate
-  uint64_t perm_id = 0;        // the struct_id whose edge_perm d_perm holds
   hipEvent_t ev_drv = nullptr, ev_user = nullptr;  // orders the caller's stream against the driver's
   // a downloaded single-circuit result in the pinned staging buffer (gp_fetch_sizes)
   bool staged_ok = false;
@@ -209,6 +206,7 @@ struct gp_driver {
   const uint32_t* staged_off = nullptr;
   const uint32_t* staged_bits = nullptr;
   const double* staged_q = nullptr;
+  const uint32_t* staged_ceoff = nullptr;
   gp::DevState st{};
 
   uint32_t key_bits = 64;      // test hook: class keys cut to this many bits
@@ -565,28 +563,24 @@ static int gp_driver_create_impl(const gp_bounds* bounds, int device, gp_driver*
   st.max_tiles = d->max_tiles;
   if ((rc = dev_alloc(d, &st.segstart, F, "class starts"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.big, F / 64 + 1, "large classes"))) return cleanup(rc);
-  if ((rc = dev_alloc(d, &st.bkt, 2 * size_t(gp::kBuckets + 1), "bucket counts"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.b16_lo, size_t(gp::kBuckets16), "16-bit bucket starts")) ||
-      (rc = dev_alloc(d, &st.b16_hi, size_t(gp::kBuckets16), "16-bit bucket ends")) ||
-      (rc = dev_alloc(d, &st.b16_cls, size_t(gp::kBuckets16) + 1, "16-bit bucket classes")) ||
-      (rc = dev_alloc(d, &st.b16_bits, size_t(gp::kBuckets16) + 1, "16-bit bucket bits")))
+      (rc = dev_alloc(d, &st.b16_hi, size_t(gp::kBuckets16), "16-bit bucket ends")))
     return cleanup(rc);
-  if ((rc = dev_alloc(d, &st.seg_first, F, "class member offsets"))) return cleanup(rc);
-  if ((rc = dev_alloc(d, &st.seg_mem, F, "class member counts"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.rep_bm, F / 64 + 1, "representative bitmap"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.rrec, F, "representative records"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.out_lb, 2 * size_t(d->max_tiles), "output look-back words"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.out_ctr, 1, "output tile ticket"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.rep_pos, F, "representative positions"))) return cleanup(rc);
+  if ((rc = dev_alloc(d, &st.circ_eoff, size_t(b.max_branches) + 1, "circuit hyperedge offsets")))
+    return cleanup(rc);
   if ((rc = dev_alloc(d, &st.e_first, F, "hyperedge member offsets"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.e_cnt, F, "hyperedge member counts"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.gfault, F, "fault gradients"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.gq, F, "hyperedge gradients"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.gr, std::max<uint64_t>(b.max_channels, 1), "channel gradients"))) return cleanup(rc);
-  if ((rc = dev_alloc(d, &st.seg_q, F, "class probabilities"))) return cleanup(rc);
-  if ((rc = dev_alloc(d, &st.seg_rep, F, "class representatives"))) return cleanup(rc);
-  if ((rc = dev_alloc(d, &st.seg_cnt, F, "class bit counts"))) return cleanup(rc);
-  if ((rc = dev_alloc(d, &st.seg_off, F, "class bit offsets"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.edge_off32, F + 1, "edge offsets"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.edge_bits, d->bits_cap, "edge bits"))) return cleanup(rc);
   if ((rc = dev_alloc(d, &st.edge_q, F, "edge probabilities"))) return cleanup(rc);
-  if ((rc = dev_alloc(d, &st.edge_branch, F, "edge circuits"))) return cleanup(rc);
-  if ((rc = dev_alloc(d, &d->d_perm, F, "hyperedge order"))) return cleanup(rc);
   if (hipEventCreateWithFlags(&d->ev_drv, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&d->ev_user, hipEventDisableTiming) != hipSuccess)
     return cleanup(hip_fail(hipGetLastError(), "hipEventCreate"));
@@ -596,7 +590,7 @@ static int gp_driver_create_impl(const gp_bounds* bounds, int device, gp_driver*
   if ((rc = dev_alloc(d, &st.item_clock, 2 * b.max_items, "item clocks"))) return cleanup(rc);
   st.bits_cap = d->bits_cap;
   // download staging: offsets + bits + probabilities + circuits of the largest result
-  d->h_out_cap = (F + 1) * 4 + d->bits_cap * 4 + F * 8 + F * 4 + 4 * kAlign;
+  d->h_out_cap = (F + 1) * 4 + d->bits_cap * 4 + F * 8 + (size_t(b.max_branches) + 1) * 4 + 4 * kAlign;
   if (hipHostMalloc(&d->h_out, d->h_out_cap, hipHostMallocDefault) != hipSuccess)
     return cleanup(fail(GP_E_OOM, "pinned host allocation failed"));
   *out = d;
@@ -1062,7 +1056,8 @@ struct Staged {
   const uint32_t* off32 = nullptr;
   const uint32_t* bits32 = nullptr;
   const double* q64 = nullptr;
-  const uint32_t* cid = nullptr;  // null unless a batch
+  const uint32_t* c_eoff = nullptr;  // per circuit: its first hyperedge (circuits + 1 entries)
+  size_t n_circuits = 0;
   std::chrono::steady_clock::time_point t_ready;   // when the compile was seen finished
   std::chrono::steady_clock::time_point t_loaded;  // when the download had finished
 };
@@ -1129,13 +1124,12 @@ static int fetch_staged(gp_driver* d, Staged& out) {
   char* h = static_cast<char*>(d->h_out);
   const size_t o_off = 0, o_bits = align_up((U + 1) * 4), o_q = o_bits + align_up(nb * 4);
   const size_t o_c = o_q + align_up(U * 8);
-  const bool batch = d->lw.branches.size() > 1;
-  if (o_c + U * 4 > d->h_out_cap) return fail(GP_E_BOUNDS, "result exceeds the download staging buffer");
+  const size_t B = d->lw.branches.size();
+  if (o_c + (B + 1) * 4 > d->h_out_cap) return fail(GP_E_BOUNDS, "result exceeds the download staging buffer");
   HIP_TRY(hipMemcpyAsync(h + o_off, d->st.edge_off32, (U + 1) * 4, hipMemcpyDeviceToHost, d->stream), "download");
   if (nb) HIP_TRY(hipMemcpyAsync(h + o_bits, d->st.edge_bits, nb * 4, hipMemcpyDeviceToHost, d->stream), "download");
   if (U) HIP_TRY(hipMemcpyAsync(h + o_q, d->st.edge_q, U * 8, hipMemcpyDeviceToHost, d->stream), "download");
-  if (U && batch)
-    HIP_TRY(hipMemcpyAsync(h + o_c, d->st.edge_branch, U * 4, hipMemcpyDeviceToHost, d->stream), "download");
+  HIP_TRY(hipMemcpyAsync(h + o_c, d->st.circ_eoff, (B + 1) * 4, hipMemcpyDeviceToHost, d->stream), "download");
   HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
   out.t_loaded = std::chrono::steady_clock::now();
   out.U = U;
@@ -1143,14 +1137,19 @@ static int fetch_staged(gp_driver* d, Staged& out) {
   out.off32 = reinterpret_cast<const uint32_t*>(h + o_off);
   out.bits32 = reinterpret_cast<const uint32_t*>(h + o_bits);
   out.q64 = reinterpret_cast<const double*>(h + o_q);
-  out.cid = batch ? reinterpret_cast<const uint32_t*>(h + o_c) : nullptr;
+  out.c_eoff = reinterpret_cast<const uint32_t*>(h + o_c);
+  out.n_circuits = B;
+  // the hyperedges are listed circuit by circuit: the offsets must rise to U
+  if (out.c_eoff[0] != 0 || out.c_eoff[B] != U)
+    return fail(GP_E_HIP, "the per-circuit hyperedge offsets do not cover the result");
+  for (size_t k = 0; k < B; k++)
+    if (out.c_eoff[k + 1] < out.c_eoff[k]) return fail(GP_E_HIP, "the per-circuit hyperedge offsets decrease");
   return GP_OK;
 }
 
 static int gp_fetch_sizes_impl(gp_driver* d, uint64_t* n_edges, uint64_t* n_bits, uint32_t* n_det, uint32_t* n_obs) {
   if (!d || !n_edges || !n_bits) return fail(GP_E_ARG, "null argument");
   d->staged_ok = false;
-  if (d->lw.branches.size() > 1) return fail(GP_E_STATE, "a batch result is fetched with gp_fetch");
   Staged sg;
   int rc = fetch_staged(d, sg);
   if (rc) return rc;
@@ -1159,8 +1158,8 @@ static int gp_fetch_sizes_impl(gp_driver* d, uint64_t* n_edges, uint64_t* n_bits
   d->staged_off = sg.off32;
   d->staged_bits = sg.bits32;
   d->staged_q = sg.q64;
+  d->staged_ceoff = sg.c_eoff;
   d->staged_ok = true;
-  d->edge_perm.clear();
   d->structured = true;
   d->struct_edges = sg.U;
   d->struct_id++;
@@ -1168,6 +1167,14 @@ static int gp_fetch_sizes_impl(gp_driver* d, uint64_t* n_edges, uint64_t* n_bits
   *n_bits = sg.nb;
   if (n_det) *n_det = d->lw.n_det;
   if (n_obs) *n_obs = d->lw.n_obs;
+  return GP_OK;
+}
+
+static int gp_fetch_circuit_offsets_impl(gp_driver* d, uint64_t* circuit_offsets) {
+  if (!d || !circuit_offsets) return fail(GP_E_ARG, "null argument");
+  if (!d->staged_ok) return fail(GP_E_STATE, "gp_fetch_circuit_offsets without a current gp_fetch_sizes");
+  const size_t B = d->lw.branches.size();
+  for (size_t k = 0; k <= B; k++) circuit_offsets[k] = d->staged_ceoff[k];
   return GP_OK;
 }
 
@@ -1198,7 +1205,6 @@ static int gp_fetch_impl(gp_driver* d, gp_edges** out) {
   const uint32_t* off32 = sg.off32;
   const uint32_t* bits32 = sg.bits32;
   const double* q64 = sg.q64;
-  const bool batch = sg.cid != nullptr;
   gp_edges* e = new gp_edges();
   e->n_det = d->lw.n_det;
   e->n_obs = d->lw.n_obs;
@@ -1207,74 +1213,26 @@ static int gp_fetch_impl(gp_driver* d, gp_edges** out) {
     e->c_det.push_back(bd.n_det);
     e->c_obs.push_back(bd.n_obs);
   }
-  e->c_off.assign(B + 1, 0);
-  d->edge_perm.clear();
-  if (!batch) {
-    e->off.resize(U + 1);
-    for (uint64_t i = 0; i <= U; i++) e->off[i] = off32[i];
-    e->bits.assign(bits32, bits32 + nb);
-    e->q.assign(q64, q64 + U);
-    e->circuit.assign(U, 0u);
-    e->c_off[1] = U;
-  } else {
-    // circuit by circuit (a stable counting sort on host threads), each
-    // circuit's hyperedges in the order the device wrote them
-    const uint32_t* cid = sg.cid;
-    const size_t T = split_threads(U);
-    std::vector<uint64_t> ce(T * B, 0), cb(T * B, 0);
-    std::vector<int> bad(T, 0);
-    run_threads(T, [&](size_t t) {
-      std::vector<uint64_t> le(B, 0), lb(B, 0);  // own counters: no shared cache lines
-      for (uint64_t i = U * t / T; i < U * (t + 1) / T; i++) {
-        if (cid[i] >= B) {
-          bad[t] = 1;
-          return;
-        }
-        le[cid[i]]++;
-        lb[cid[i]] += off32[i + 1] - off32[i];
-      }
-      std::copy(le.begin(), le.end(), ce.begin() + t * B);
-      std::copy(lb.begin(), lb.end(), cb.begin() + t * B);
-    });
-    for (int v : bad)
-      if (v) {
-        delete e;
-        return fail(GP_E_HIP, "a hyperedge names a circuit outside the batch");
-      }
-    uint64_t ne = 0, nbits = 0;
+  // the device lists the hyperedges circuit by circuit (representative
+  // position order): copied as they are, on host threads
+  e->c_off.resize(B + 1);
+  for (size_t k = 0; k <= B; k++) e->c_off[k] = sg.c_eoff[k];
+  e->off.resize(U + 1);
+  e->bits.resize(nb);
+  e->q.resize(U);
+  e->circuit.resize(U);
+  const size_t T = split_threads(U + nb / 2);
+  run_threads(T, [&](size_t t) {
+    for (uint64_t i = (U + 1) * t / T; i < (U + 1) * (t + 1) / T; i++) e->off[i] = off32[i];
+    const uint64_t b0 = nb * t / T, b1 = nb * (t + 1) / T;
+    if (b1 > b0) std::memcpy(e->bits.data() + b0, bits32 + b0, size_t(b1 - b0) * 4);
+    const uint64_t q0 = U * t / T, q1 = U * (t + 1) / T;
+    if (q1 > q0) std::memcpy(e->q.data() + q0, q64 + q0, size_t(q1 - q0) * 8);
     for (size_t k = 0; k < B; k++) {
-      e->c_off[k] = ne;
-      for (size_t t = 0; t < T; t++) {
-        const uint64_t a = ce[t * B + k], b = cb[t * B + k];
-        ce[t * B + k] = ne;  // now: chunk t's first slot and bit within the result
-        cb[t * B + k] = nbits;
-        ne += a;
-        nbits += b;
-      }
+      const uint64_t a = std::max<uint64_t>(e->c_off[k], q0), z = std::min<uint64_t>(e->c_off[k + 1], q1);
+      if (z > a) std::fill(e->circuit.begin() + a, e->circuit.begin() + z, uint32_t(k));
     }
-    e->c_off[B] = ne;
-    e->off.resize(U + 1);
-    e->bits.resize(nb);
-    e->q.resize(U);
-    e->circuit.resize(U);
-    d->edge_perm.resize(U);
-    run_threads(T, [&](size_t t) {
-      std::vector<uint64_t> je(ce.begin() + t * B, ce.begin() + (t + 1) * B);
-      std::vector<uint64_t> jb(cb.begin() + t * B, cb.begin() + (t + 1) * B);
-      for (uint64_t i = U * t / T; i < U * (t + 1) / T; i++) {
-        const uint32_t k = cid[i];
-        const uint64_t j = je[k]++;
-        const uint32_t len = off32[i + 1] - off32[i];
-        d->edge_perm[j] = uint32_t(i);
-        e->q[j] = q64[i];
-        e->circuit[j] = k;
-        e->off[j] = jb[k];
-        if (len) std::memcpy(e->bits.data() + jb[k], bits32 + off32[i], size_t(len) * 4);
-        jb[k] += len;
-      }
-    });
-    e->off[U] = nb;
-  }
+  });
   *out = e;
   d->structured = true;
   d->struct_edges = U;
@@ -1316,14 +1274,6 @@ static int gp_rates_gradient_impl(gp_driver* d, const double* dl_dq, size_t n_ed
   const size_t C = lw.chan_kind.size();
   if (n_rates != C) return fail(GP_E_ARG, "dl_dr length differs from the channel count");
   HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
-  // a batch was fetched circuit by circuit: back to the device's hyperedge order
-  // (the buffer lives until the stream is synchronised below)
-  std::vector<double> dev_order;
-  if (!d->edge_perm.empty()) {
-    dev_order.resize(n_edges);
-    for (size_t j = 0; j < n_edges; j++) dev_order[d->edge_perm[j]] = dl_dq[j];
-    dl_dq = dev_order.data();
-  }
   if (n_edges)
     HIP_TRY(hipMemcpyAsync(d->st.gq, dl_dq, n_edges * 8, hipMemcpyHostToDevice, d->stream), "upload dL/dq");
   HIP_TRY(gp::enqueue_rates_gradient(d->st, uint32_t(n_edges), d->stream), "kernel launch");
@@ -1353,22 +1303,6 @@ static int on_caller_stream(gp_driver* d, void* stream, Enqueue&& enqueue) {
   return GP_OK;
 }
 
-// The hyperedge order of the last fetch on the device (null when it is the
-// device's own order), uploaded once per fetched structure.
-static int device_perm(gp_driver* d, const uint32_t** perm) {
-  *perm = nullptr;
-  if (d->edge_perm.empty()) return GP_OK;
-  if (d->perm_id != d->struct_id) {
-    HIP_TRY(hipMemcpyAsync(d->d_perm, d->edge_perm.data(), d->edge_perm.size() * 4, hipMemcpyHostToDevice,
-                           d->stream),
-            "upload hyperedge order");
-    HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
-    d->perm_id = d->struct_id;
-  }
-  *perm = d->d_perm;
-  return GP_OK;
-}
-
 static int gp_aggregate_impl(gp_driver* d, const double* d_rates, size_t n_rates, double* d_q, size_t n_edges,
                              void* stream) {
   if (!d || (!d_rates && n_rates) || (!d_q && n_edges)) return fail(GP_E_ARG, "null argument");
@@ -1376,11 +1310,8 @@ static int gp_aggregate_impl(gp_driver* d, const double* d_rates, size_t n_rates
   if (n_edges != d->struct_edges) return fail(GP_E_ARG, "q length differs from the hyperedge count");
   if (n_rates != d->lw.chan_kind.size()) return fail(GP_E_ARG, "rate array length differs from the channel count");
   HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
-  const uint32_t* perm = nullptr;
-  int rc = device_perm(d, &perm);
-  if (rc) return rc;
   return on_caller_stream(d, stream, [&](hipStream_t s) {
-    return gp::enqueue_aggregate(d->st, uint32_t(n_edges), d_rates, perm, d_q, s);
+    return gp::enqueue_aggregate(d->st, uint32_t(n_edges), d_rates, d_q, s);
   });
 }
 
@@ -1392,11 +1323,8 @@ static int gp_aggregate_backward_impl(gp_driver* d, const double* d_rates, size_
   if (n_edges != d->struct_edges) return fail(GP_E_ARG, "dL/dq length differs from the hyperedge count");
   if (n_rates != d->lw.chan_kind.size()) return fail(GP_E_ARG, "rate array length differs from the channel count");
   HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
-  const uint32_t* perm = nullptr;
-  int rc = device_perm(d, &perm);
-  if (rc) return rc;
   return on_caller_stream(d, stream, [&](hipStream_t s) {
-    return gp::enqueue_aggregate_backward(d->st, uint32_t(n_edges), d_rates, perm, d_gq, d_grates, nullptr, s);
+    return gp::enqueue_aggregate_backward(d->st, uint32_t(n_edges), d_rates, d_gq, d_grates, nullptr, s);
   });
 }
 
@@ -1416,11 +1344,8 @@ static int gp_aggregate_backward_noalloc_impl(gp_driver* d, const double* d_rate
   HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
   double* scratch = gp::scratch_for(d->device);
   if (!scratch) return fail(GP_E_STATE, "the static scratch of this device has no address");
-  const uint32_t* perm = nullptr;
-  int rc = device_perm(d, &perm);
-  if (rc) return rc;
   return on_caller_stream(d, stream, [&](hipStream_t s) {
-    return gp::enqueue_aggregate_backward(d->st, uint32_t(n_edges), d_rates, perm, d_gq, d_grates, scratch, s);
+    return gp::enqueue_aggregate_backward(d->st, uint32_t(n_edges), d_rates, d_gq, d_grates, scratch, s);
   });
 }
 
@@ -1476,6 +1401,14 @@ int gp_circuit_info_get(const gp_driver* d, gp_circuit_info* out) {
     i.n_nonzero_words = d->h_hdr->n_nz_words;
   }
   *out = i;
+  return GP_OK;
+}
+
+int gp_circuit_shape(const gp_driver* d, uint32_t circuit, uint32_t* n_det, uint32_t* n_obs) {
+  if (!d || !n_det || !n_obs) return fail(GP_E_ARG, "null argument");
+  if (circuit >= d->lw.branches.size()) return fail(GP_E_ARG, "circuit index out of range");
+  *n_det = d->lw.branches[circuit].n_det;
+  *n_obs = d->lw.branches[circuit].n_obs;
   return GP_OK;
 }
 
@@ -1710,6 +1643,9 @@ int gp_sync(gp_driver* d) { return GP_GUARD(gp_sync_impl(d)); }
 int gp_fetch_sizes(gp_driver* d, uint64_t* n_edges, uint64_t* n_bits, uint32_t* n_det, uint32_t* n_obs) {
   return GP_GUARD(gp_fetch_sizes_impl(d, n_edges, n_bits, n_det, n_obs));
 }
+int gp_fetch_circuit_offsets(gp_driver* d, uint64_t* circuit_offsets) {
+  return GP_GUARD(gp_fetch_circuit_offsets_impl(d, circuit_offsets));
+}
 int gp_fetch_copy(gp_driver* d, uint64_t* offsets, uint32_t* bits, double* q) {
   return GP_GUARD(gp_fetch_copy_impl(d, offsets, bits, q));
 }
@@ -1805,80 +1741,43 @@ static int driver_fetch_split_impl(gp_driver* d, std::vector<gp_edges*>& out, ui
     wait_ns[1] = uint64_t(std::chrono::duration_cast<std::chrono::nanoseconds>(sg.t_loaded - sg.t_ready).count());
   }
   if (rc) return rc;
-  // the split order is not the device's: no refresh or adjoint on this compile
+  // the results leave with the requests: no refresh or adjoint on this compile
   d->structured = false;
   const size_t B = d->lw.branches.size();
-  const uint64_t U = sg.U;
-  // a parallel counting sort by circuit: chunk t of the hyperedges counts,
-  // then writes at its own offsets within every circuit
-  const size_t T = split_threads(U);
-  std::vector<uint64_t> ce(T * B, 0), cb(T * B, 0);
-  std::vector<int> bad(T, 0);
-  auto parallel = [&](auto&& fn) { run_threads(T, fn); };
-  // (each thread counts in its own vectors: rows of one shared array would
-  // share cache lines between threads)
-  parallel([&](size_t t) {
-    std::vector<uint64_t> le(B, 0), lb(B, 0);
-    for (uint64_t i = U * t / T; i < U * (t + 1) / T; i++) {
-      const uint32_t k = sg.cid ? sg.cid[i] : 0u;
-      if (k >= B) {
-        bad[t] = 1;
-        return;
-      }
-      le[k]++;
-      lb[k] += sg.off32[i + 1] - sg.off32[i];
-    }
-    std::copy(le.begin(), le.end(), ce.begin() + t * B);
-    std::copy(lb.begin(), lb.end(), cb.begin() + t * B);
-  });
-  for (int v : bad)
-    if (v) return fail(GP_E_HIP, "a hyperedge names a circuit outside the batch");
+  if (sg.n_circuits != B) return fail(GP_E_INTERNAL, "circuit count of the staged result");
+  // the device lists the hyperedges circuit by circuit: each circuit's are a
+  // contiguous range, copied into its own result (on host threads, which
+  // also allocate and first touch the results)
   out.resize(B);
-  std::vector<uint64_t> tot_e(B), tot_b(B);
-  for (size_t k = 0; k < B; k++) {
-    uint64_t ne = 0, nb = 0;
-    for (size_t t = 0; t < T; t++) {
-      const uint64_t a = ce[t * B + k], b = cb[t * B + k];
-      ce[t * B + k] = ne;  // now: this chunk's first hyperedge / bit in circuit k
-      cb[t * B + k] = nb;
-      ne += a;
-      nb += b;
-    }
-    tot_e[k] = ne;
-    tot_b[k] = nb;
-  }
-  // the results are allocated (and first touched) in parallel too
-  parallel([&](size_t t) {
+  const size_t T = std::min<size_t>(split_threads(sg.U + sg.nb / 2), std::max<size_t>(B, 1));
+  std::vector<int> oom(T, 0);
+  run_threads(T, [&](size_t t) {
     for (size_t k = t; k < B; k += T) {
-      gp_edges* e = new gp_edges();
-      e->n_det = d->lw.branches[k].n_det;
-      e->n_obs = d->lw.branches[k].n_obs;
-      e->off.resize(tot_e[k] + 1);
-      e->off[0] = 0;
-      e->bits.resize(tot_b[k]);
-      e->q.resize(tot_e[k]);
-      e->circuit.assign(tot_e[k], 0u);
-      e->c_det.assign(1, e->n_det);
-      e->c_obs.assign(1, e->n_obs);
-      e->c_off = {0, tot_e[k]};
+      const uint64_t e0 = sg.c_eoff[k], e1 = sg.c_eoff[k + 1];
+      const uint64_t b0 = sg.off32[e0], b1 = sg.off32[e1];
+      gp_edges* e = nullptr;
+      try {
+        e = new gp_edges();
+        e->n_det = d->lw.branches[k].n_det;
+        e->n_obs = d->lw.branches[k].n_obs;
+        e->off.resize(e1 - e0 + 1);
+        for (uint64_t i = e0; i <= e1; i++) e->off[i - e0] = sg.off32[i] - b0;
+        e->bits.assign(sg.bits32 + b0, sg.bits32 + b1);
+        e->q.assign(sg.q64 + e0, sg.q64 + e1);
+        e->circuit.assign(e1 - e0, 0u);
+        e->c_det.assign(1, e->n_det);
+        e->c_obs.assign(1, e->n_obs);
+        e->c_off = {0, e1 - e0};
+      } catch (const std::bad_alloc&) {
+        delete e;
+        e = nullptr;
+        oom[t] = 1;
+      }
       out[k] = e;
     }
   });
-  parallel([&](size_t t) {
-    std::vector<uint64_t> je(ce.begin() + t * B, ce.begin() + (t + 1) * B);
-    std::vector<uint64_t> jb(cb.begin() + t * B, cb.begin() + (t + 1) * B);
-    for (uint64_t i = U * t / T; i < U * (t + 1) / T; i++) {
-      const uint32_t k = sg.cid ? sg.cid[i] : 0u;
-      gp_edges* e = out[k];
-      const uint64_t j = je[k]++;
-      const uint32_t len = sg.off32[i + 1] - sg.off32[i];
-      const uint64_t b = jb[k];
-      jb[k] = b + len;
-      e->q[j] = sg.q64[i];
-      e->off[j + 1] = b + len;
-      if (len) std::memcpy(e->bits.data() + b, sg.bits32 + sg.off32[i], size_t(len) * 4);
-    }
-  });
+  for (int v : oom)
+    if (v) return fail(GP_E_OOM, "host allocation of a split result failed");
   return GP_OK;
 }
 

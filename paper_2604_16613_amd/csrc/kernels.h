@@ -76,6 +76,23 @@ struct __align__(16) EdgeRec {
   uint32_t bnd;
 };
 
+// Per fault position that represents its class (the class's lowest
+// position), written by the merge for the output pass: the merged
+// probability and the class's members as a range of the sorted positions.
+struct __align__(16) RepRec {
+  double q;
+  uint32_t first;  // first index of the members in the sorted positions (ord)
+  uint32_t cnt;    // member count
+};
+
+// Hyperedges are numbered by their representative's position: hyperedge e
+// is the class of the e-th representative in position order, so the
+// hyperedges of a batch come out circuit by circuit (a circuit's positions are
+// contiguous) and each circuit's in the order it has when compiled alone.
+// Output tiles of kTile positions; a tile's count is packed as
+// (representatives << kRepShift) | signature bits.
+constexpr int kRepShift = 34;
+
 // Everything one compile reads or writes on the device.
 struct DevState {
   // lowered tables (inputs, uploaded per circuit)
@@ -153,30 +170,27 @@ struct DevState {
   uint32_t* lookback;    // per pass, tile and digit: published count with status bits
   uint32_t* tile_ctr;    // per pass: tile ticket counter
   uint32_t* tile_sum;    // scan tile sums
-  uint32_t* segstart;    // first sorted index of each class (16-bit buckets: class slot of each hyperedge)
+  uint32_t* segstart;    // full sort: first sorted index of each class
   uint32_t* big;         // classes too large for one thread
-  uint32_t* bkt;         // per bucket: classes, then signature bits (kBuckets + 1 each)
-  uint32_t* b16_lo;      // 16-bit buckets: first and end sorted index (cleared per compile), classes
-  uint32_t* b16_hi;      // and signature bits per bucket (then their exclusive prefixes; kBuckets16 + 1 each)
-  uint32_t* b16_cls;
-  uint32_t* b16_bits;
+  uint32_t* b16_lo;      // 16-bit buckets: first and end sorted index (cleared per compile)
+  uint32_t* b16_hi;
   uint32_t use_b16;      // this compile groups with 16-bit buckets (k_prepare clears their ranges)
   // the class structure a compile leaves for rate refreshes and the adjoint:
   uint32_t* ord;         // fault positions, classes contiguous, members in position order (set by enqueue_compile)
-  uint32_t* seg_first;   // per class slot (bucket grouping): first index into ord, member count
-  uint32_t* seg_mem;
   uint32_t* e_first;     // per hyperedge: first index into ord, member count
   uint32_t* e_cnt;
   double* gfault;        // per fault position: dL/dp (adjoint)
   double* gq;            // per hyperedge: dL/dq (adjoint input)
   double* gr;            // per channel (lowered order): dL/d(rate) (adjoint output)
-  double* seg_q;         // merged probability per class
-  uint32_t* seg_rep;     // representative fault position per class
-  uint32_t* seg_cnt;     // signature bits per class (16-bit buckets: first output bit of each hyperedge)
-  uint32_t* seg_off;     // exclusive prefix of seg_cnt
+  // output in representative-position order
+  uint64_t* rep_bm;      // per 64 fault positions: bit set where the position represents its class (cleared per compile)
+  RepRec* rrec;          // per representative position: merged probability, members
+  uint64_t* out_lb;      // output look-back words: hyperedges of tile t at [t], bits at [max_tiles + t]
+  uint32_t* out_ctr;     // output tile ticket
+  uint32_t* rep_pos;     // per hyperedge: its representative's position
+  uint32_t* circ_eoff;   // per circuit: its first hyperedge (n_branch + 1 entries)
   uint32_t* edge_off32;  // per hyperedge: first bit (n_edges + 1)
   uint32_t* edge_bits;   // output signature bits (external numbering)
-  uint32_t* edge_branch; // output: circuit of each hyperedge
   double* edge_q;        // output probabilities
   uint64_t bits_cap;
   DevHeader* hdr;
@@ -186,8 +200,7 @@ struct DevState {
 // Names of the kernels (for timing tables).
 enum KernelId : int {
   K_PREPARE = 0, K_SWEEP, K_HASH, K_SCAN_SINGLE, K_COMPACT, K_ONESWEEP, K_HEADS_COUNT, K_HEADS_APPLY, K_REDUCE,
-  K_REDUCE_BIG, K_SCAN_TILES, K_SCAN_APPLY, K_EDGE_WRITE, K_BUCKET, K_BUCKET_BOUNDS, K_BUCKET_SCAN, K_SLOT_MAP,
-  K_COUNT
+  K_REDUCE_BIG, K_EDGE_WRITE, K_BUCKET, K_BUCKET_BOUNDS, K_REP_LIST, K_COUNT
 };
 const char* kernel_name(int id);
 
@@ -217,16 +230,14 @@ hipError_t enqueue_rates_gradient(const DevState& st, uint32_t n_edges, hipStrea
 
 // Stage 2 over the cached structure with every operand on the device (the
 // rate refresh and its adjoint without host transfers). rates: per channel in
-// program order; perm (may be null): hyperedge j of the caller's order is
-// device hyperedge perm[j]; q, gq: per hyperedge in the caller's order;
-// grates: per channel in program order. The forward writes q; the backward
-// recomputes the per-fault probabilities at `rates` and writes grates.
-hipError_t enqueue_aggregate(const DevState& st, uint32_t n_edges, const double* rates, const uint32_t* perm,
-                             double* q, hipStream_t stream);
+// program order; q, gq: per hyperedge (the output order); grates: per
+// channel in program order. The forward writes q; the backward recomputes
+// the per-fault probabilities at `rates` and writes grates.
+hipError_t enqueue_aggregate(const DevState& st, uint32_t n_edges, const double* rates, double* q,
+                             hipStream_t stream);
 // gfault: the per-fault dL/dp buffer (null: the driver's st.gfault).
 hipError_t enqueue_aggregate_backward(const DevState& st, uint32_t n_edges, const double* rates,
-                                      const uint32_t* perm, const double* gq, double* grates, double* gfault,
-                                      hipStream_t stream);
+                                      const double* gq, double* grates, double* gfault, hipStream_t stream);
 
 // A per-fault dL/dp buffer of kScratchFaults doubles (16 MiB) in a static
 // device array, for the adjoint entry point that allocates nothing. Each GPU

@@ -158,6 +158,18 @@ __device__ __forceinline__ void raise_flag(DevHeader* hdr, uint32_t f) {
 
 // A partition pass gave up its look-back: the pairs after it are misplaced
 // (positions may be stale), so the grouping kernels that follow do nothing.
+// The merged class whose lowest fault position is `rep`: its record at that
+// position and its bit in the representative bitmap (the output pass numbers
+// the hyperedges by these bits in position order).
+__device__ __forceinline__ void put_rep(const DevState& st, uint32_t rep, double q, uint32_t first, uint32_t cnt) {
+  RepRec r;
+  r.q = q;
+  r.first = first;
+  r.cnt = cnt;
+  st.rrec[rep] = r;
+  atomicOr(reinterpret_cast<unsigned long long*>(st.rep_bm) + (rep >> 6), 1ull << (rep & 63));
+}
+
 __device__ __forceinline__ bool grouping_aborted(const DevHeader* hdr) {
   return (__hip_atomic_load(&hdr->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FLAG_LOOKBACK) != 0u;
 }
@@ -172,6 +184,9 @@ __constant__ KeptCodes c_kept = make_kept_codes();
 // (fault -> channel), then the block writes the faults of those channels
 // (consecutive positions) one thread per fault, coalesced.
 constexpr uint32_t kMaxChanFaults = sizeof(KeptCodes::code[0][0]);  // faults of one channel at most
+
+// output tiles of a compile of n faults (at least one)
+__device__ __forceinline__ uint32_t ntiles_out(uint32_t n) { return n ? (n + kTile - 1) / kTile : 1u; }
 
 __global__ __launch_bounds__(kBlock) void k_prepare(DevState st) {
   __shared__ double s_p[kBlock];
@@ -211,6 +226,12 @@ __global__ __launch_bounds__(kBlock) void k_prepare(DevState st) {
     __syncthreads();
   }
   for (uint32_t w = gid; w < st.w; w += stride) st.cover_lo[w] = 0;
+  for (uint32_t i = gid; i < (st.n_faults + 63) / 64; i += stride) st.rep_bm[i] = 0;
+  for (uint32_t t = gid; t < ntiles_out(st.n_faults); t += stride) {
+    st.out_lb[t] = 0;
+    st.out_lb[st.max_tiles + t] = 0;
+  }
+  if (gid == 0) *st.out_ctr = 0;
   const uint32_t ntiles = (st.n_faults + kTile - 1) / kTile;
   for (uint32_t t = gid; t < ntiles + 1; t += stride) {
     st.tile_cnt[t] = 0;
@@ -356,15 +377,14 @@ __device__ __forceinline__ int wave_total(int v) {
 // current one is applied), the layer, fault and bitmap offsets and the
 // column's injection list.
 // Layers above the item's emission range only transform the frame: one
-// barrier each, and no global memory access besides the window prefetch;
-// their count of non-zero frame words is published every kCountEvery layers.
-// Layers in the range fetch the new boundary's fault records, apply the ops
-// (one thread per op), then emit the non-zero signature words of the
-// boundary's faults (one thread per fault, coalesced) with a ballot bitmap of
-// which words are non-zero.
-// The count of non-zero frame words (for the early exit) is kept per wave as
-// a running sum and published in per-wave LDS slots (two sets, alternating).
-constexpr int kCountEvery = 8;
+// barrier each, and no global memory access besides the window prefetch.
+// Layers in the range apply the ops (one thread per op) while the next
+// boundary's fault records are in flight, then emit the non-zero signature
+// words of the boundary's faults (one thread per fault, coalesced) with a
+// ballot bitmap of which words are non-zero.
+// The count of non-zero frame words (for the early exit) is taken once at the
+// top of the emission range, then kept per wave as a running sum of the
+// changes and published in per-wave LDS slots (two sets, alternating).
 
 template <bool kStaged, int kBlk>
 __global__ __launch_bounds__(kBlk) void k_sweep(DevState st) {
@@ -572,16 +592,17 @@ __global__ __launch_bounds__(kBlk) void k_sweep(DevState st) {
     // while layer t is applied and emitted, boundary t-1's records are in
     // flight (two register sets, the loop unrolled by two so that neither is
     // copied while its loads are outstanding).
+    // Every load is issued whatever the boundary's fault count (indices past
+    // it are clamped into the array and their values never used), so that
+    // the number of loads in flight is known where the records are used and
+    // the wait there covers only the loads that are needed.
     uint32_t recA[kEmitPre], recB[kEmitPre];
-    auto load_recs = [&](uint32_t (&r)[kEmitPre], uint32_t fa, uint32_t fb) {
-      const uint32_t nf = fb - fa;
+    const uint32_t f_last = st.n_faults ? st.n_faults - 1 : 0u;
+    auto load_recs = [&](uint32_t (&r)[kEmitPre], uint32_t fa) {
 #pragma unroll
-      for (int k = 0; k < kEmitPre; ++k) {
-        const uint32_t i = tid + k * kBlk;
-        r[k] = i < nf ? st.frec[fa + i] : 0u;
-      }
+      for (int k = 0; k < kEmitPre; ++k) r[k] = st.frec[min(fa + tid + k * kBlk, f_last)];
     };
-    load_recs(recA, f0, f_hi);
+    load_recs(recA, f0);
     // one boundary: returns true when the item is done (range end or the
     // frame died)
     auto step = [&](uint32_t (&rec)[kEmitPre], uint32_t (&nxt)[kEmitPre]) -> bool {
@@ -589,7 +610,7 @@ __global__ __launch_bounds__(kBlk) void k_sweep(DevState st) {
       // boundary t+1 to boundary t, in place
       const uint32_t nf = f_hi - f0;
       const uint32_t f_n = BFO(t > 0 ? t - 1 : 0);
-      if (t - 1 >= blo) load_recs(nxt, f_n, f0);
+      load_recs(nxt, f_n);
       int dnz = 0;
       apply_layer(t, lo_t, dnz);
       advance(t);
@@ -1099,49 +1120,6 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(DevState st, uint32_t p
   }
 }
 
-// Tile sums of n words (n = *n_dev when given).
-__global__ __launch_bounds__(kBlock) void k_scan_tiles(const uint32_t* __restrict__ in, uint32_t n_host,
-                                                       const uint32_t* n_dev, uint32_t* __restrict__ tile_sum) {
-  __shared__ uint32_t s_wave[kBlock / 64 + 1];
-  const uint32_t n = n_dev ? *n_dev : n_host;
-  const uint32_t base = blockIdx.x * kTile;
-  if (base >= n) {
-    if (threadIdx.x == 0) tile_sum[blockIdx.x] = 0;
-    return;
-  }
-  uint32_t s = 0;
-  for (int r = 0; r < kPerThread; ++r) {
-    const uint32_t i = base + r * kBlock + threadIdx.x;
-    if (i < n) s += in[i];
-  }
-  block_exclusive_scan<kBlock>(s, s_wave);
-  if (threadIdx.x == 0) tile_sum[blockIdx.x] = s_wave[kBlock / 64];
-}
-
-// out[i] = exclusive prefix of in[i] given scanned tile sums.
-__global__ __launch_bounds__(kBlock) void k_scan_apply(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
-                                                       uint32_t n_host, const uint32_t* n_dev,
-                                                       const uint32_t* __restrict__ tile_off) {
-  __shared__ uint32_t s_wave[kBlock / 64 + 1];
-  const uint32_t n = n_dev ? *n_dev : n_host;
-  const uint32_t base = blockIdx.x * kTile;
-  if (base >= n) return;
-  const uint32_t i0 = base + threadIdx.x * kPerThread;
-  uint32_t v[kPerThread];
-  uint32_t s = 0;
-#pragma unroll
-  for (int k = 0; k < kPerThread; ++k) {
-    v[k] = (i0 + k < n) ? in[i0 + k] : 0;
-    s += v[k];
-  }
-  uint32_t run = block_exclusive_scan<kBlock>(s, s_wave) + tile_off[blockIdx.x];
-#pragma unroll
-  for (int k = 0; k < kPerThread; ++k) {
-    if (i0 + k < n) out[i0 + k] = run;
-    run += v[k];
-  }
-}
-
 // Class heads in the sorted key array (n = hdr->n_live): counts per tile.
 __global__ __launch_bounds__(kBlock) void k_heads_count(const uint64_t* __restrict__ keys, const DevHeader* hdr,
                                                         uint32_t* __restrict__ tile_sum) {
@@ -1202,9 +1180,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce(DevState st, const uint32_t* 
     q = fma(r.p, 1.0 - 2.0 * q, q);  // Eq. 3: q(1-p) + p(1-q)
   }
   if (bad) raise_flag(st.hdr, FLAG_COLLISION);
-  st.seg_q[s] = q;
-  st.seg_rep[s] = rep;
-  st.seg_cnt[s] = st.popc[rep];
+  put_rep(st, rep, q, i0, i1 - i0);
 }
 
 // One block per class of more than kBigSegment faults (the list k_reduce
@@ -1243,9 +1219,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_big(DevState st, const uint32
     }
     if (threadIdx.x == 0) {
       if (s_bad) raise_flag(st.hdr, FLAG_COLLISION);
-      st.seg_q[s] = s_q[0];
-      st.seg_rep[s] = rep;
-      st.seg_cnt[s] = st.popc[rep];
+      put_rep(st, rep, s_q[0], i0, i1 - i0);
     }
     __syncthreads();
   }
@@ -1270,15 +1244,14 @@ constexpr uint32_t kBucketSortBits = 24;  // key bits a bucket sorts in LDS; lon
 // of kBlk threads per bucket of at most kCap faults.
 template <int kBlk, int kCap, bool k16>
 __global__ __launch_bounds__(kBlk) void k_bucket(DevState st, const uint64_t* __restrict__ keys,
-                                                 const uint32_t* __restrict__ vals, uint32_t* __restrict__ mem,
-                                                 uint32_t* __restrict__ b_cls, uint32_t* __restrict__ b_bits) {
+                                                 const uint32_t* __restrict__ vals, uint32_t* __restrict__ mem) {
   constexpr int kWaves = kBlk / 64;
   constexpr int kPer = kCap / kBlk;  // sorted values per thread
   static_assert(kBlk % 256 == 0 && kCap % kBlk == 0 && kPer <= 32, "bucket shape");
   extern __shared__ __align__(16) uint64_t s_buf[];  // two buffers of kCap values
   __shared__ uint32_t s_cnt[kWaves][256];
   __shared__ uint32_t s_wave[kWaves + 1];
-  __shared__ uint32_t s_big[2 * (kCap / (kBigSegment + 1) + 1)];  // (class, first sorted index)
+  __shared__ uint32_t s_big[2 * (kCap / (kBigSegment + 1) + 1)];  // (representative, first sorted index)
   __shared__ uint64_t s_hb[kCap / 64];                            // class heads, one bit per value
   __shared__ uint64_t s_rb[kCap / 64];                            // starts of runs of equal sorted bits
   __shared__ uint64_t s_mb[kCap / 64];                            // run members whose key differs
@@ -1288,13 +1261,7 @@ __global__ __launch_bounds__(kBlk) void k_bucket(DevState st, const uint64_t* __
   __shared__ uint32_t s_start;
   __shared__ double s_q[kBlk];
   __shared__ int s_bad;
-  if (grouping_aborted(st.hdr)) {
-    if (threadIdx.x == 0) {
-      b_cls[blockIdx.x] = 0;
-      b_bits[blockIdx.x] = 0;
-    }
-    return;
-  }
+  if (grouping_aborted(st.hdr)) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const uint32_t d = blockIdx.x;
   const uint32_t msd = st.n_pass - 1;
@@ -1318,11 +1285,7 @@ __global__ __launch_bounds__(kBlk) void k_bucket(DevState st, const uint64_t* __
   const uint32_t start = s_start;
   const uint32_t m = k16 ? st.b16_hi[d] - start : tot[d];
   if (m == 0 || m > kCap) {
-    if (tid == 0) {
-      b_cls[d] = 0;
-      b_bits[d] = 0;
-      if (m) raise_flag(st.hdr, FLAG_BUCKET);
-    }
+    if (tid == 0 && m) raise_flag(st.hdr, FLAG_BUCKET);
     return;
   }
   const uint32_t top = k16 ? 2u : 1u;  // digits that chose the bucket
@@ -1450,11 +1413,7 @@ __global__ __launch_bounds__(kBlk) void k_bucket(DevState st, const uint64_t* __
     }
     __syncthreads();
     if (s_bad_bucket) {
-      if (tid == 0) {
-        b_cls[d] = 0;
-        b_bits[d] = 0;
-        raise_flag(st.hdr, FLAG_BUCKET);
-      }
+      if (tid == 0) raise_flag(st.hdr, FLAG_BUCKET);
       return;
     }
   }
@@ -1493,9 +1452,7 @@ __global__ __launch_bounds__(kBlk) void k_bucket(DevState st, const uint64_t* __
       rec[k] = st.crp[start + idx[k]];
       mem[start + j0 + k] = pos[k];  // the class members, kept for refreshes and the adjoint
     }
-  const uint32_t nh = uint32_t(__popc(hmask));
-  uint32_t c = block_exclusive_scan<kBlk>(nh, s_wave);  // barrier: every a[j] has been read
-  const uint32_t ncls = s_wave[kWaves];
+  __syncthreads();  // every a[j] has been read
   double* sp = reinterpret_cast<double*>(a);
   uint64_t* sc = b;
 #pragma unroll
@@ -1507,19 +1464,13 @@ __global__ __launch_bounds__(kBlk) void k_bucket(DevState st, const uint64_t* __
   __syncthreads();
   auto head_at = [&](uint32_t j) -> bool { return (s_hb[j >> 6] >> (j & 63)) & 1ull; };
   // classes whose head this thread owns, in order: Eq. 3 over the members
-  // in position order (runs longer than kBigSegment go to the block below)
-  uint32_t nbits = 0;
-  uint32_t cbits[kPer];
+  // in position order (runs longer than kBigSegment go to the block below);
+  // the head is the class's lowest position, its representative
 #pragma unroll
   for (int k = 0; k < int(kPer); ++k) {
-    cbits[k] = 0;
     if (!((hmask >> k) & 1u)) continue;
     const uint32_t j = j0 + k;
-    const uint32_t cls = c + uint32_t(__popc(hmask & ((1u << k) - 1)));
     const uint32_t rep = pos[k];
-    cbits[k] = st.popc[rep];
-    nbits += cbits[k];
-    st.seg_rep[start + cls] = rep;
     double q = sp[j];
     const uint64_t c0 = sc[j];
     bool bad = false;
@@ -1528,34 +1479,21 @@ __global__ __launch_bounds__(kBlk) void k_bucket(DevState st, const uint64_t* __
       bad |= sc[i] != c0;
       q = fma(sp[i], 1.0 - 2.0 * q, q);  // Eq. 3: q(1-p) + p(1-q)
     }
-    st.seg_first[start + cls] = start + j;
     if (i < m && i - j > kBigSegment && !head_at(i)) {
       const uint32_t g = atomicAdd(&s_nbig, 1u);
-      s_big[2 * g] = cls;
+      s_big[2 * g] = rep;
       s_big[2 * g + 1] = j;
     } else {
-      st.seg_q[start + cls] = q;
-      st.seg_mem[start + cls] = i - j;
+      put_rep(st, rep, q, start + j, i - j);
       if (bad) s_bad = 1;
     }
   }
-  // bit offsets of the classes within the bucket (class order = thread order)
-  uint32_t o = block_exclusive_scan<kBlk>(nbits, s_wave);
-  {
-    uint32_t k2 = 0;
-#pragma unroll
-    for (int k = 0; k < int(kPer); ++k)
-      if ((hmask >> k) & 1u) {
-        st.seg_off[start + c + k2] = o;
-        o += cbits[k];
-        k2++;
-      }
-  }
+  __syncthreads();
   // large classes: strided partial merges over the whole run, then a
   // fixed-shape tree
   const uint32_t nbig = s_nbig;
   for (uint32_t g = 0; g < nbig; ++g) {
-    const uint32_t cls = s_big[2 * g], j = s_big[2 * g + 1];
+    const uint32_t rep = s_big[2 * g], j = s_big[2 * g + 1];
     if (tid == 0) {
       uint32_t e = j + 1;
       while (e < m && !head_at(e)) ++e;
@@ -1580,17 +1518,10 @@ __global__ __launch_bounds__(kBlk) void k_bucket(DevState st, const uint64_t* __
       }
       __syncthreads();
     }
-    if (tid == 0) {
-      st.seg_q[start + cls] = s_q[0];
-      st.seg_mem[start + cls] = e - j;
-    }
+    if (tid == 0) put_rep(st, rep, s_q[0], start + j, e - j);
     __syncthreads();
   }
-  if (tid == 0) {
-    b_cls[d] = ncls;
-    b_bits[d] = s_wave[kWaves];
-    if (s_bad) raise_flag(st.hdr, FLAG_COLLISION);
-  }
+  if (tid == 0 && s_bad) raise_flag(st.hdr, FLAG_COLLISION);
 }
 
 // 16-bit bucket of a key: its top two digits (the two partition passes).
@@ -1611,158 +1542,210 @@ __global__ __launch_bounds__(kBlock) void k_bucket_bounds(DevState st, const uin
   }
 }
 
-// Per-bucket class and bit counts of the 16-bit buckets -> exclusive
-// prefixes in place (entry kBuckets16 = the totals, also the compile's class
-// and bit counts). One block, in rounds of kScanRound buckets staged through
-// LDS with coalesced loads and stores; thread t scans kScanRound / block
-// consecutive buckets of the round.
-constexpr uint32_t kScanRound = 4096;
+// ------------------------------------------------------------------ output
 
-__global__ __launch_bounds__(kScanSingleBlock) void k_bucket_scan(DevState st) {
-  constexpr uint32_t kPerT = kScanRound / kScanSingleBlock;
-  __shared__ uint32_t s_c[kScanRound], s_b[kScanRound];
-  __shared__ uint32_t s_wave[kScanSingleBlock / 64];
-  const uint32_t j0 = threadIdx.x * kPerT;
-  uint32_t carry_c = 0, carry_b = 0;
-  for (uint32_t r0 = 0; r0 < kBuckets16; r0 += kScanRound) {
-    for (uint32_t k = threadIdx.x; k < kScanRound; k += kScanSingleBlock) {
-      s_c[k] = st.b16_cls[r0 + k];
-      s_b[k] = st.b16_bits[r0 + k];
-    }
-    __syncthreads();
-    uint32_t c = 0, nb = 0;
-    for (uint32_t k = 0; k < kPerT; ++k) {
-      c += s_c[j0 + k];
-      nb += s_b[j0 + k];
-    }
-    uint32_t tc, tb;
-    uint32_t oc = carry_c + block_scan_1sync<kScanSingleBlock>(c, s_wave, tc);
-    __syncthreads();
-    uint32_t ob = carry_b + block_scan_1sync<kScanSingleBlock>(nb, s_wave, tb);
-    for (uint32_t k = 0; k < kPerT; ++k) {
-      const uint32_t x = s_c[j0 + k], y = s_b[j0 + k];
-      s_c[j0 + k] = oc;
-      s_b[j0 + k] = ob;
-      oc += x;
-      ob += y;
-    }
-    __syncthreads();
-    for (uint32_t k = threadIdx.x; k < kScanRound; k += kScanSingleBlock) {
-      st.b16_cls[r0 + k] = s_c[k];
-      st.b16_bits[r0 + k] = s_b[k];
-    }
-    carry_c += tc;
-    carry_b += tb;
-    __syncthreads();
+// Hyperedges in representative-position order. Output tiles of kTile
+// positions; thread t of a tile's block owns positions [16t, 16t + 16), a
+// quarter of one representative-bitmap word.
+constexpr int kOutPer = kTile / kBlock;
+static_assert(kOutPer == 16, "a thread owns 16 positions of a 64-bit bitmap word");
+
+__device__ __forceinline__ uint32_t rep_bits16(const DevState& st, uint32_t p0) {
+  return p0 < st.n_faults ? uint32_t(st.rep_bm[p0 >> 6] >> (p0 & 63)) & 0xFFFFu : 0u;
+}
+
+// Packed count of this thread's positions: representatives << kRepShift |
+// their signature bits.
+__device__ __forceinline__ uint64_t rep_count16(const DevState& st, uint32_t p0, uint32_t m) {
+  uint64_t v = uint64_t(__popc(m)) << kRepShift;
+  while (m) {
+    const uint32_t k = uint32_t(__builtin_ctz(m));
+    m &= m - 1;
+    v += st.popc[p0 + k];
   }
+  return v;
+}
+
+// Exclusive block scan of 64-bit values (kBlock threads); s needs kBlock / 64
+// + 1 entries and ends holding the block total at [kBlock / 64].
+__device__ __forceinline__ uint64_t block_exclusive_scan64(uint64_t v, unsigned long long* s) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint64_t inc = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t u = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += u;
+  }
+  if (lane == 63) s[wv] = inc;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    st.b16_cls[kBuckets16] = carry_c;
-    st.b16_bits[kBuckets16] = carry_b;
-    st.hdr->n_seg = carry_c;
-    st.hdr->n_bits = carry_b;
+    unsigned long long run = 0;
+    for (int k = 0; k < kBlock / 64; ++k) {
+      const unsigned long long x = s[k];
+      s[k] = run;
+      run += x;
+    }
+    s[kBlock / 64] = run;
   }
+  __syncthreads();
+  return s[wv] + inc - v;
 }
 
-// Hyperedge of every class slot of the 16-bit buckets: slot i = bucket start
-// + class c is hyperedge (classes before the bucket) + c; its first output
-// bit is the bucket's bit offset plus the class's within the bucket.
-__global__ __launch_bounds__(kBlock) void k_slot_map(DevState st, const uint64_t* __restrict__ keys) {
+// Look-back words of the output pass (64-bit: status in the top two bits).
+constexpr uint64_t kOutAgg = 1ull << 62;   // the tile's own count is published
+constexpr uint64_t kOutPre = 2ull << 62;   // the inclusive prefix up to the tile is published
+constexpr uint64_t kOutMask = kOutAgg - 1;
+constexpr uint32_t kOutLookbackBit = 1u << 31;  // lookback_passes bit of the output pass
+
+// Numbering of the hyperedges over tiles of kTile positions (tiles taken in
+// dispatch order from a ticket). A tile counts its representatives and their
+// signature bits, publishes both counts and looks back at the tiles before it
+// for their prefixes (two chains, hyperedges and bits, each on half of wave
+// 0, 32 predecessors per round), so it knows its first hyperedge and
+// first bit. Each thread then lists its representatives (their positions in
+// hyperedge order and their first bits) and gives every circuit whose first
+// fault position falls in its positions that circuit's first hyperedge; the
+// last tile writes the totals.
+__global__ __launch_bounds__(kBlock) void k_rep_list(DevState st, uint32_t ntiles) {
+  __shared__ unsigned long long s[kBlock / 64 + 1];
+  __shared__ uint32_t s_bfb[kBranchLds];  // first fault of each circuit of the batch
+  __shared__ uint64_t s_excl[2];
+  __shared__ uint32_t s_tile;
   if (grouping_aborted(st.hdr)) return;
-  const uint32_t n = st.hdr->n_live;
-  const uint32_t msd = st.n_pass - 1;
-  for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
-    const uint32_t b = bucket16_of(keys[i], msd);
-    const uint32_t e = st.b16_cls[b] + (i - st.b16_lo[b]);
-    if (e < st.b16_cls[b + 1]) {
-      st.segstart[e] = i;
-      st.seg_cnt[e] = st.b16_bits[b] + st.seg_off[i];
+  const int tid = threadIdx.x, lane = tid & 63;
+  if (tid == 0) s_tile = atomicAdd(st.out_ctr, 1u);
+  const bool bfb_lds = st.n_branch <= uint32_t(kBranchLds);
+  if (bfb_lds)
+    for (uint32_t k = tid; k < st.n_branch; k += blockDim.x) s_bfb[k] = st.branch[k].fb;
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  if (tile >= ntiles) return;
+  auto FB = [&](uint32_t k) -> uint32_t { return bfb_lds ? s_bfb[k] : st.branch[k].fb; };
+  const uint32_t p0 = tile * kTile + tid * kOutPer;
+  uint32_t m = rep_bits16(st, p0);
+  const uint64_t local = block_exclusive_scan64(rep_count16(st, p0, m), s);
+  const uint64_t agg = s[kBlock / 64];
+  const uint32_t nrep = uint32_t(agg >> kRepShift);
+  const uint64_t nbits = agg & ((1ull << kRepShift) - 1);
+  if (tid < 64) {
+    // lanes 0-31: the hyperedge chain; lanes 32-63: the bit chain
+    const int chain = lane >> 5, q = lane & 31;
+    uint64_t* lb = st.out_lb + size_t(chain) * st.max_tiles;
+    const uint64_t val = chain == 0 ? uint64_t(nrep) : nbits;
+    if (q == 0)
+      __hip_atomic_store(&lb[tile], (tile == 0 ? kOutPre : kOutAgg) | val, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t excl = 0;
+    bool done = tile == 0;
+    int jt = int(tile) - 1;
+    uint32_t spins = 0;
+    const uint64_t half = chain == 0 ? 0xFFFFFFFFull : 0xFFFFFFFF00000000ull;
+    // the whole wave runs the loop until both chains are done (the ballots
+    // and the give-up are wave-wide)
+    while (__ballot(!done) != 0) {
+      if (__ballot(spins >= st.spin_limit) != 0) {
+        // gave up: the prefix is partial (every number it gives stays below
+        // the true one, so in bounds) and the fetch redoes the compile
+        if (lane == 0) {
+          raise_flag(st.hdr, FLAG_LOOKBACK);
+          atomicOr(&st.hdr->lookback_passes, kOutLookbackBit);
+        }
+        break;
+      }
+      // tiles jt, jt-1, ... (lane q: tile jt - q); before tile 0 an inclusive
+      // prefix of zero, so a walk always ends at tile 0 at the latest
+      uint64_t x = kOutPre;
+      if (!done && jt - q >= 0) x = __hip_atomic_load(&lb[jt - q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // (__ballot takes an int: test the status bits as booleans, never the 64-bit word)
+      const uint64_t pre = __ballot((x & kOutPre) != 0ull) & half;
+      const uint64_t stall = __ballot((x & ~kOutMask) == 0ull) & half;
+      // the nearest published prefix, and the nearest tile not yet published
+      const int fp = pre ? int(__builtin_ctzll(pre >> (32 * chain))) : 32;
+      const int fs = stall ? int(__builtin_ctzll(stall >> (32 * chain))) : 32;
+      const int take = done ? 0 : (fp < fs ? fp + 1 : fs);  // predecessors summed this round
+      uint64_t add = (q < take) ? (x & kOutMask) : 0ull;
+#pragma unroll
+      for (int d = 1; d < 32; d <<= 1) add += __shfl_xor(add, d, 32);
+      if (!done) {
+        excl += add;
+        if (fp < fs) done = true;
+        else jt -= take;
+        if (fs < 32 && fp > fs) {
+          ++spins;
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+    }
+    if (q == 0) {
+      if (tile > 0)
+        __hip_atomic_store(&lb[tile], kOutPre | (excl + val), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_excl[chain] = excl;
     }
   }
+  __syncthreads();
+  const uint32_t e0 = uint32_t(s_excl[0]);
+  const uint64_t o0 = s_excl[1];
+  uint32_t e = e0 + uint32_t(local >> kRepShift);
+  uint64_t o = o0 + (local & ((1ull << kRepShift) - 1));
+  if (p0 < st.n_faults) {
+    // circuits whose first position falls in this thread's positions
+    uint32_t lo = 0, hi = st.n_branch;
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) / 2;
+      if (FB(mid) < p0) lo = mid + 1;
+      else hi = mid;
+    }
+    for (uint32_t k = lo; k < st.n_branch; ++k) {
+      const uint32_t fb = FB(k);
+      if (fb >= p0 + uint32_t(kOutPer) || fb >= st.n_faults) break;
+      st.circ_eoff[k] = e + uint32_t(__popc(m & ((1u << (fb - p0)) - 1u)));
+    }
+  }
+  while (m) {
+    const uint32_t pos = p0 + uint32_t(__builtin_ctz(m));
+    m &= m - 1;
+    st.rep_pos[e] = pos;
+    st.edge_off32[e] = uint32_t(o);
+    o += st.popc[pos];
+    ++e;
+  }
+  if (tile + 1 == ntiles && tid == 0) {
+    const uint64_t U = e0 + uint64_t(nrep), NB = o0 + nbits;
+    st.hdr->n_seg = uint32_t(U);
+    st.hdr->n_edges = uint32_t(U);
+    st.hdr->n_bits = NB;
+    st.edge_off32[U] = uint32_t(NB);
+    if (NB > st.bits_cap) raise_flag(st.hdr, FLAG_OVERFLOW);
+    // circuits that start at or past the last fault position begin at the end
+    for (uint32_t k = 0; k <= st.n_branch; ++k)
+      if (k == st.n_branch || FB(k) >= st.n_faults) st.circ_eoff[k] = uint32_t(U);
+  }
 }
 
-// Hyperedge e = class s: bits in external numbering (detector d -> d,
-// observable k -> D + k) and its probability.
-// With kBuckets, class e lives at slot bucket_start + (e - bucket_class_offset)
-// and its bit offset is the bucket's plus the class's within the bucket.
-// The representative's boundary row, weight and non-zero-word mask come from
-// its edge record (one access).
-// kMode 0: classes in sorted order (the full radix sort). kMode 1 (256
-// buckets): every block turns the per-bucket class, bit and fault counts into
-// offsets itself (thread t: bucket t). kMode 2 (16-bit buckets): k_slot_map
-// left each hyperedge's class slot and first bit.
-template <int kMode>
+// Hyperedge e = the class of the e-th representative in position order (one
+// thread per hyperedge, consecutive threads on increasing positions): its
+// probability, members and bits in external numbering (detector d -> d,
+// observable k -> D + k). The representative's boundary row, weight and
+// non-zero-word mask come from its edge record; its non-zero signature words
+// from the column slabs that cover that boundary.
 __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
-  constexpr bool kBucketed = kMode == 1;
-  static_assert(kBlock == int(kBuckets), "one thread per bucket");
-  __shared__ uint32_t s_cls[kBuckets + 1];
-  __shared__ uint32_t s_bit[kBuckets];
-  __shared__ uint32_t s_fst[kBuckets];
-  __shared__ uint32_t s_wave[kBlock / 64];
   __shared__ uint32_t s_bfb[kBranchLds];  // first fault of each circuit of the batch
   if (grouping_aborted(st.hdr)) return;
-  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t S;
-  uint64_t NB;
-  if (kBucketed) {
-    const uint32_t t = threadIdx.x;
-    uint32_t tc, tb, tf;
-    s_cls[t] = block_scan_1sync<kBlock>(st.bkt[t], s_wave, tc);
-    __syncthreads();
-    s_bit[t] = block_scan_1sync<kBlock>(st.bkt[kBuckets + 1 + t], s_wave, tb);
-    __syncthreads();
-    s_fst[t] = block_scan_1sync<kBlock>(st.digit_tot[(st.n_pass - 1) * 256 + t], s_wave, tf);
-    if (t == 0) s_cls[kBuckets] = tc;
-    S = tc;
-    NB = tb;
-  } else {
-    S = st.hdr->n_seg;
-    NB = st.hdr->n_bits;
-  }
   const bool bfb_lds = st.n_branch <= uint32_t(kBranchLds);
   if (bfb_lds)
     for (uint32_t k = threadIdx.x; k < st.n_branch; k += blockDim.x) s_bfb[k] = st.branch[k].fb;
   __syncthreads();
-  if (e == 0) {
-    st.hdr->n_edges = S;
-    if (kBucketed) {
-      st.hdr->n_seg = S;
-      st.hdr->n_bits = NB;
-    }
-    st.edge_off32[S] = uint32_t(NB);
-    if (NB > st.bits_cap) raise_flag(st.hdr, FLAG_OVERFLOW);
-  }
-  if (e >= S) return;
-  uint32_t s = e, o0;
-  if (kBucketed) {
-    // the bucket holding class e: last bucket whose class offset is <= e
-    uint32_t lo = 0, hi = kBuckets;
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) / 2;
-      if (s_cls[mid] <= e) lo = mid;
-      else hi = mid;
-    }
-    s = s_fst[lo] + (e - s_cls[lo]);
-    o0 = s_bit[lo] + st.seg_off[s];
-  } else if (kMode == 2) {
-    s = st.segstart[e];
-    o0 = st.seg_cnt[e];
-  } else {
-    o0 = st.seg_off[s];
-  }
-  st.edge_off32[e] = o0;
-  st.edge_q[e] = st.seg_q[s];
-  if (kMode != 0) {
-    st.e_first[e] = st.seg_first[s];
-    st.e_cnt[e] = st.seg_mem[s];
-  } else {
-    st.e_first[e] = st.segstart[e];
-    st.e_cnt[e] = (e + 1 < S ? st.segstart[e + 1] : st.hdr->n_live) - st.segstart[e];
-  }
-  const uint32_t pos = st.seg_rep[s];
+  const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= st.hdr->n_edges) return;
+  const uint32_t pos = st.rep_pos[e];
+  const RepRec rr = st.rrec[pos];
   const EdgeRec er = st.erec[pos];
-  const uint32_t cnt = kMode != 0 ? er.popc : st.seg_cnt[s];
-  if (uint64_t(o0) + cnt > st.bits_cap) return;
-  // the representative's circuit (last one whose first fault is <= pos) and boundary
+  const uint64_t o0 = st.edge_off32[e];
+  st.edge_q[e] = rr.q;
+  st.e_first[e] = rr.first;
+  st.e_cnt[e] = rr.cnt;
+  if (o0 + er.popc > st.bits_cap) return;
+  // the representative's circuit (last one whose first fault is <= pos)
   uint32_t bi = 0;
   {
     uint32_t lo = 0, hi = st.n_branch;
@@ -1773,19 +1756,17 @@ __global__ __launch_bounds__(kBlock) void k_edge_write(DevState st) {
     }
     bi = lo;
   }
-  const BranchDesc br = st.branch[bi];
-  st.edge_branch[e] = bi;
+  const BranchDesc& br = st.branch[bi];
   const uint32_t b = er.bnd;  // the representative's boundary row
   const uint32_t n = st.ncov[b];
   const uint32_t* cl = st.cov + size_t(b) * st.w_max;
-  uint32_t o = o0;
-  const uint32_t obs0 = br.wd * 64;
+  uint64_t o = o0;
+  const uint32_t obs0 = br.wd * 64, wb = br.wb, n_det = br.n_det;
   auto emit = [&](uint32_t w) {
     uint64_t v = st.slab[st.col_base[w] + pos];
     while (v) {
-      // the circuit's own bit numbering: detector d -> d, observable k -> D + k
-      const uint32_t bit = (w - br.wb) * 64 + uint32_t(__builtin_ctzll(v));
-      st.edge_bits[o++] = bit < obs0 ? bit : br.n_det + (bit - obs0);
+      const uint32_t bit = (w - wb) * 64 + uint32_t(__builtin_ctzll(v));
+      st.edge_bits[o++] = bit < obs0 ? bit : n_det + (bit - obs0);
       v &= v - 1;
     }
   };
@@ -1825,13 +1806,13 @@ __global__ __launch_bounds__(kBlock) void k_fault_p(DevState st, const double* _
 // Eq. 3 again over each hyperedge's cached members (position order), with the
 // compile's shape: up to kBigSegment + 1 members one thread folds them in
 // order; larger classes are listed for k_remerge_big. Thread j serves
-// hyperedge j of the output order (device hyperedge perm[j], or j) and
+// hyperedge j and
 // writes out[j].
 __global__ __launch_bounds__(kBlock) void k_remerge(DevState st, const uint32_t* __restrict__ ord, uint32_t n_edges,
-                                                    const uint32_t* __restrict__ perm, double* __restrict__ out) {
+                                                    double* __restrict__ out) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n_edges) return;
-  const uint32_t e = perm ? perm[j] : j;
+  const uint32_t e = j;
   const uint32_t i0 = st.e_first[e], cnt = st.e_cnt[e];
   if (cnt > kBigSegment + 1) {
     st.big[atomicAdd(&st.hdr->n_big, 1u)] = j;
@@ -1845,14 +1826,13 @@ __global__ __launch_bounds__(kBlock) void k_remerge(DevState st, const uint32_t*
 // One block of kBucketBlock threads per listed hyperedge: strided partial
 // merges, then the fixed tree the bucket grouping uses.
 __global__ __launch_bounds__(kBucketBlock) void k_remerge_big(DevState st, const uint32_t* __restrict__ ord,
-                                                             const uint32_t* __restrict__ perm,
                                                              double* __restrict__ out) {
   __shared__ double s_q[kBucketBlock];
   const int tid = threadIdx.x;
   const uint32_t nb = st.hdr->n_big;
   for (uint32_t g = blockIdx.x; g < nb; g += gridDim.x) {
     const uint32_t j = st.big[g];
-    const uint32_t e = perm ? perm[j] : j;
+    const uint32_t e = j;
     const uint32_t i0 = st.e_first[e], cnt = st.e_cnt[e];
     double q = 0.0;
     for (uint32_t i = tid; i < cnt; i += kBucketBlock) q = fma(st.frp[ord[i0 + i]].p, 1.0 - 2.0 * q, q);
@@ -1878,13 +1858,13 @@ __global__ __launch_bounds__(kBlock) void k_clear_big(DevState st) {
 // so dq/dp_i = prod_{j != i} (1 - 2 p_j): the product of the members other
 // than those with p = 1/2, divided by (1 - 2 p_i); with one member at p = 1/2
 // only that member's derivative is non-zero, with two or more none is.
-// Thread j: dL/dq = gq[j] of device hyperedge perm[j] (or j).
+// Thread j: dL/dq = gq[j] of hyperedge j.
 __global__ __launch_bounds__(kBlock) void k_adj_edges(DevState st, const uint32_t* __restrict__ ord,
-                                                      uint32_t n_edges, const uint32_t* __restrict__ perm,
-                                                      const double* __restrict__ gq, double* __restrict__ gfault) {
+                                                      uint32_t n_edges, const double* __restrict__ gq,
+                                                      double* __restrict__ gfault) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n_edges) return;
-  const uint32_t e = perm ? perm[j] : j;
+  const uint32_t e = j;
   const uint32_t i0 = st.e_first[e], cnt = st.e_cnt[e];
   uint32_t half = 0;
   double prod = 1.0;
@@ -1935,8 +1915,7 @@ inline uint32_t cdiv(uint64_t a, uint64_t b) { return uint32_t((a + b - 1) / b);
 const char* kernel_name(int id) {
   static const char* names[K_COUNT] = {"k_prepare",    "k_sweep",       "k_hash",   "k_scan_single", "k_compact",
                                        "k_onesweep",   "k_heads_count", "k_heads_apply", "k_reduce",  "k_reduce_big",
-                                       "k_scan_tiles", "k_scan_apply",  "k_edge_write",  "k_bucket",
-                                       "k_bucket_bounds", "k_bucket_scan", "k_slot_map"};
+                                       "k_edge_write",  "k_bucket",     "k_bucket_bounds", "k_rep_list"};
   return (id >= 0 && id < K_COUNT) ? names[id] : "?";
 }
 
@@ -2061,14 +2040,18 @@ hipError_t enqueue_compile(DevState& st_io, hipStream_t stream, const LaunchHook
                 k_sweep<false, 1024><<<st.n_items, kSweepBlock, sweep_lds_bytes(st.n_qubits), stream>>>(st));
     }
   }
-  if (n == 0) {
-    GP_LAUNCH(K_EDGE_WRITE, k_edge_write<0><<<1, kBlock, 0, stream>>>(st));
+  // hyperedges in representative-position order (after any grouping): tile
+  // counts, their prefix, the hyperedges, each circuit's first hyperedge
+  auto output = [&]() -> hipError_t {
+    GP_LAUNCH(K_REP_LIST, k_rep_list<<<ntiles, kBlock, 0, stream>>>(st, ntiles));
+    GP_LAUNCH(K_EDGE_WRITE, k_edge_write<<<cdiv(n ? n : 1, kBlock), kBlock, 0, stream>>>(st));
     return hipSuccess;
-  }
+  };
+  if (n == 0) return output();
   GP_LAUNCH(K_HASH, k_hash<<<st.n_hchunks, kBlock, hash_lds_bytes(st.w_max), stream>>>(st));
   if (st.use_b16) {
     // two stable passes on the top two digits (the second carries the fault
-    // records), the bucket ranges, each bucket in LDS, then class offsets
+    // records), the bucket ranges, then each bucket in LDS
     const uint32_t msd = st.n_pass - 1;
     const uint32_t g = cdiv(n, kBlock) < 8192u ? cdiv(n, kBlock) : 8192u;
     GP_LAUNCH(K_COMPACT, k_compact<<<ntiles, kCompactBlock, 0, stream>>>(st, msd - 1));
@@ -2078,13 +2061,9 @@ hipError_t enqueue_compile(DevState& st_io, hipStream_t stream, const LaunchHook
                                                                      st.val[0], st.frp, st.crp));
     GP_LAUNCH(K_BUCKET_BOUNDS, k_bucket_bounds<<<g, kBlock, 0, stream>>>(st, st.key[0]));
     GP_LAUNCH(K_BUCKET, k_bucket<256, kBucket16Cap, true><<<kBuckets16, 256, 2 * kBucket16Cap * sizeof(uint64_t),
-                                                            stream>>>(st, st.key[0], st.val[0], st.val[1],
-                                                                      st.b16_cls, st.b16_bits));
-    GP_LAUNCH(K_BUCKET_SCAN, k_bucket_scan<<<1, kScanSingleBlock, 0, stream>>>(st));
-    GP_LAUNCH(K_SLOT_MAP, k_slot_map<<<g, kBlock, 0, stream>>>(st, st.key[0]));
-    GP_LAUNCH(K_EDGE_WRITE, k_edge_write<2><<<cdiv(n, kBlock), kBlock, 0, stream>>>(st));
+                                                            stream>>>(st, st.key[0], st.val[0], st.val[1]));
     st_io.ord = st.val[1];
-    return hipSuccess;
+    return output();
   }
   // buckets: one stable pass on the top digit, then each bucket in LDS
   const bool bucketed = st.sort_mode == SORT_AUTO && st.key_mode == 0 && g_bucket_ok && n <= kBucketMaxFaults &&
@@ -2095,9 +2074,8 @@ hipError_t enqueue_compile(DevState& st_io, hipStream_t stream, const LaunchHook
     GP_LAUNCH(K_ONESWEEP, k_onesweep<<<ntiles, kSortBlock, 0, stream>>>(st, msd, st.key[0], st.val[0], st.key[1],
                                                                      st.val[1], st.frp, st.crp));
     GP_LAUNCH(K_BUCKET, k_bucket<kBucketBlock, kBucketCap, false><<<kBuckets, kBucketBlock, kBucketDynLds, stream>>>(
-                            st, st.key[1], st.val[1], st.val[0], st.bkt, st.bkt + kBuckets + 1));
-    GP_LAUNCH(K_EDGE_WRITE, k_edge_write<1><<<cdiv(n, kBlock), kBlock, 0, stream>>>(st));
-    return hipSuccess;
+                            st, st.key[1], st.val[1], st.val[0]));
+    return output();
   }
   GP_LAUNCH(K_COMPACT, k_compact<<<ntiles, kCompactBlock, 0, stream>>>(st, 0));
   for (uint32_t pass = 0; pass < st.n_pass; ++pass) {
@@ -2114,46 +2092,39 @@ hipError_t enqueue_compile(DevState& st_io, hipStream_t stream, const LaunchHook
                                                                          st.segstart));
   GP_LAUNCH(K_REDUCE, k_reduce<<<cdiv(n, kBlock), kBlock, 0, stream>>>(st, st.val[fin]));
   GP_LAUNCH(K_REDUCE_BIG, k_reduce_big<<<256, kBlock, 0, stream>>>(st, st.val[fin]));
-  GP_LAUNCH(K_SCAN_TILES,
-            k_scan_tiles<<<ntiles, kBlock, 0, stream>>>(st.seg_cnt, n, &st.hdr->n_seg, st.tile_sum));
-  GP_LAUNCH(K_SCAN_SINGLE, k_scan_single<uint64_t><<<1, kScanSingleBlock, 0, stream>>>(st.tile_sum, ntiles, nullptr,
-                                                                                      &st.hdr->n_bits));
-  GP_LAUNCH(K_SCAN_APPLY,
-            k_scan_apply<<<ntiles, kBlock, 0, stream>>>(st.seg_cnt, st.seg_off, n, &st.hdr->n_seg, st.tile_sum));
-  GP_LAUNCH(K_EDGE_WRITE, k_edge_write<0><<<cdiv(n, kBlock), kBlock, 0, stream>>>(st));
-  return hipSuccess;
+  return output();
 }
 
 hipError_t enqueue_refresh(const DevState& st, uint32_t n_edges, hipStream_t stream) {
-  return enqueue_aggregate(st, n_edges, nullptr, nullptr, st.edge_q, stream);
+  return enqueue_aggregate(st, n_edges, nullptr, st.edge_q, stream);
 }
 
 hipError_t enqueue_rates_gradient(const DevState& st, uint32_t n_edges, hipStream_t stream) {
   if (st.n_faults) k_zero_f64<<<min(cdiv(st.n_faults, kBlock), 4096u), kBlock, 0, stream>>>(st.gfault, st.n_faults);
-  if (n_edges) k_adj_edges<<<cdiv(n_edges, kBlock), kBlock, 0, stream>>>(st, st.ord, n_edges, nullptr, st.gq, st.gfault);
+  if (n_edges) k_adj_edges<<<cdiv(n_edges, kBlock), kBlock, 0, stream>>>(st, st.ord, n_edges, st.gq, st.gfault);
   if (st.n_chan) k_adj_channels<<<cdiv(st.n_chan, kBlock), kBlock, 0, stream>>>(st, nullptr, st.gfault, nullptr);
   return hipGetLastError();
 }
 
-hipError_t enqueue_aggregate(const DevState& st, uint32_t n_edges, const double* rates, const uint32_t* perm,
+hipError_t enqueue_aggregate(const DevState& st, uint32_t n_edges, const double* rates,
                              double* q, hipStream_t stream) {
   if (st.n_chan) k_fault_p<<<cdiv(st.n_chan, kBlock), kBlock, 0, stream>>>(st, rates);
   k_clear_big<<<1, kBlock, 0, stream>>>(st);
   if (n_edges) {
-    k_remerge<<<cdiv(n_edges, kBlock), kBlock, 0, stream>>>(st, st.ord, n_edges, perm, q);
-    k_remerge_big<<<64, kBucketBlock, 0, stream>>>(st, st.ord, perm, q);
+    k_remerge<<<cdiv(n_edges, kBlock), kBlock, 0, stream>>>(st, st.ord, n_edges, q);
+    k_remerge_big<<<64, kBucketBlock, 0, stream>>>(st, st.ord, q);
   }
   return hipGetLastError();
 }
 
 hipError_t enqueue_aggregate_backward(const DevState& st, uint32_t n_edges, const double* rates,
-                                      const uint32_t* perm, const double* gq, double* grates, double* gfault,
+                                      const double* gq, double* grates, double* gfault,
                                       hipStream_t stream) {
   if (!gfault) gfault = st.gfault;
   if (st.n_chan) k_fault_p<<<cdiv(st.n_chan, kBlock), kBlock, 0, stream>>>(st, rates);
   // faults outside every hyperedge (empty signature) keep dL/dp = 0
   if (st.n_faults) k_zero_f64<<<min(cdiv(st.n_faults, kBlock), 4096u), kBlock, 0, stream>>>(gfault, st.n_faults);
-  if (n_edges) k_adj_edges<<<cdiv(n_edges, kBlock), kBlock, 0, stream>>>(st, st.ord, n_edges, perm, gq, gfault);
+  if (n_edges) k_adj_edges<<<cdiv(n_edges, kBlock), kBlock, 0, stream>>>(st, st.ord, n_edges, gq, gfault);
   if (st.n_chan) k_adj_channels<<<cdiv(st.n_chan, kBlock), kBlock, 0, stream>>>(st, rates, gfault, grates);
   return hipGetLastError();
 }

@@ -369,8 +369,8 @@ def test_autotune_keeps_results(drv25):
 
 def test_fetch_into_caller_arrays(drv25):
     """gp_fetch_sizes + gp_fetch_copy give exactly gp_fetch's arrays; the copy
-    needs a current gp_fetch_sizes (GP_E_STATE after a new run), and a batch
-    lowering is fetched with gp_fetch only."""
+    needs a current gp_fetch_sizes (GP_E_STATE after a new run); a batch is
+    fetched the same way, with its per-circuit hyperedge offsets."""
     import ctypes
     say("case fetch into caller arrays")
     c = rotated_surface_code_memory(11, 11)
@@ -384,8 +384,8 @@ def test_fetch_into_caller_arrays(drv25):
     finally:
         _gp.gp_edges_free(h)
     drv25.run()
-    nd2, no2, off2, bits2, q2 = _gp.gp_fetch_arrays(drv25.handle)
-    assert (nd2, no2) == (nd, no)
+    nd2, no2, off2, bits2, q2, coff2 = _gp.gp_fetch_arrays(drv25.handle)
+    assert (nd2, no2) == (nd, no) and list(coff2) == [0, len(q)]
     assert np.array_equal(off2, off) and np.array_equal(bits2, bits)
     assert np.array_equal(q2.view(np.uint64), q.view(np.uint64))
     hg = drv25.fetch()
@@ -395,9 +395,20 @@ def test_fetch_into_caller_arrays(drv25):
     drv25.run()
     assert lib.gp_fetch_copy(drv25.handle, buf.ctypes.data, None, None) == -10
     drv25.fetch()
+    # a batch comes out circuit by circuit, each circuit's hyperedges in the
+    # order (and with the bits and probabilities) of its compile alone
     with Driver.from_batch([c.text, c.text]) as bd:
-        bd.lower_batch([c.text, c.text])
+        bd.lower_batch([c.text, c.text], [rates, rates])
         bd.run()
-        U, nb = ctypes.c_uint64(), ctypes.c_uint64()
-        assert lib.gp_fetch_sizes(bd.handle, ctypes.byref(U), ctypes.byref(nb), None, None) == -10
-        assert len(bd.fetch_batch()) == 2
+        nd3, no3, off3, bits3, q3, coff3 = _gp.gp_fetch_arrays(bd.handle, 2)
+        U = len(q2)
+        assert (nd3, no3) == (nd, no) and list(coff3) == [0, U, 2 * U]
+        nb = int(off2[-1])
+        for k in range(2):
+            assert np.array_equal(off3[k * U:(k + 1) * U + 1] - off3[k * U], off2)
+            assert np.array_equal(bits3[int(off3[k * U]):int(off3[(k + 1) * U])], bits2)
+            assert np.array_equal(q3[k * U:(k + 1) * U].view(np.uint64), q2.view(np.uint64))
+        assert int(off3[-1]) == 2 * nb
+        bd.run()
+        got = bd.fetch_batch()
+        assert len(got) == 2 and all(np.array_equal(g.q.view(np.uint64), q2.view(np.uint64)) for g in got)
