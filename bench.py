@@ -148,6 +148,8 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-grad", action="store_true", help="skip the differentiation workload")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default stage-1 work split")
+    ap.add_argument("--no-graph-replay", action="store_true",
+                    help="skip the eager-vs-graph-replay comparison (kernel traces then hold eager launches only)")
     ap.add_argument("--batch-distances", default="3,5,7,10",
                     help="outer distances of the batched [[4,2,2]]-concatenated workload ('' skips it)")
     ap.add_argument("--batch-branches", type=int, default=256)
@@ -209,6 +211,9 @@ def main() -> int:
     value = F / (ms_per_step * 1e-3)
     check_clean_steps(drv, retries, "the timed steps")
 
+    # the same runs replayed from a captured HIP graph (separate pass)
+    graph = None if args.no_graph_replay else graph_replay(drv, args.steps)
+
     # per-kernel HIP-event timings on the driver's stream (separate pass)
     per_step = kernel_times(drv, args.steps)
     event_ms_per_step = sum(v[0] for v in per_step.values())
@@ -220,7 +225,7 @@ def main() -> int:
     stage2 = stage2_block(per_step, info, args.workload)
 
     # whole path latency: text (and binary form) -> hyperedges on the host
-    latency = whole_path_latency(drv, circuit, rates, args.latency_iters)
+    latency = whole_path_latency(drv, circuit, rates, args.latency_iters) if args.latency_iters > 0 else None
 
     out = {
         "metric": "faults analysed/s (JIT latency p50/p99 alongside)",
@@ -241,13 +246,14 @@ def main() -> int:
         "hyperedges_per_s": info["n_edges"] / (ms_per_step * 1e-3),
         "autotune": tuned,
         "latency_ms": latency,
-        "e2e_faults_per_s": F / (latency["text"]["p50"] * 1e-3),
+        "e2e_faults_per_s": F / (latency["text"]["p50"] * 1e-3) if latency else None,
         "kernels_ms_per_step": {k: round(v[0], 5) for k, v in sorted(per_step.items(), key=lambda x: -x[1][0])},
         "event_ms_per_step": event_ms_per_step,
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(dom, args.workload),
                      "bytes_per_launch": dom_bytes, "avg_launch_ms": dom_avg_ms, "launches_per_step": dom_launches},
         "stage2": stage2,
+        "graph_replay": graph,
     }
     drv.close()
 
@@ -256,7 +262,7 @@ def main() -> int:
     if not args.no_grad:
         out["differentiation"] = bench_differentiation(get_driver)
     if args.batch_distances:
-        out["batching"] = [bench_batched(int(d), args.batch_branches, args.steps)
+        out["batching"] = [bench_batched(int(d), args.batch_branches, args.steps, not args.no_graph_replay)
                            for d in args.batch_distances.split(",")]
     if args.serve_distances:
         dists = [int(d) for d in args.serve_distances.split(",")]
@@ -406,6 +412,48 @@ def oracle_rate(circuit, rates, seconds: float, threads: int) -> dict:
     return {"faults_per_s": faults / dt, "runs": runs, "seconds": dt}
 
 
+def graph_replay(drv, steps: int, single_iters: int = 200) -> dict:
+    """The same device runs launched eagerly and replayed from a captured
+    HIP graph (the lowering stays resident): back-to-back steps (throughput)
+    and single synchronised runs (median latency of one run + sync). Both
+    modes are checked for device flags and re-runs afterwards."""
+    from paper_2604_16613_amd import _gp
+
+    def back_to_back():
+        drv.run()
+        drv.sync()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            drv.run()
+        drv.sync()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    def single():
+        t = []
+        for _ in range(single_iters):
+            s = time.perf_counter()
+            drv.run()
+            drv.sync()
+            t.append((time.perf_counter() - s) * 1e3)
+        return float(np.median(t))
+
+    out = {}
+    for mode, flag in (("eager", 0), ("graph", 1)):
+        _gp.gp_debug_set_graph(drv.handle, flag)
+        try:
+            _gp.gp_debug_device_flags(drv.handle, clear_seen=True)
+            retries = _gp.gp_debug_retry_counts(drv.handle)
+            out[mode] = {"ms_per_step": back_to_back(), "single_run_ms_median": single()}
+            check_clean_steps(drv, retries, f"the {mode} runs")
+        finally:
+            _gp.gp_debug_set_graph(drv.handle, 0)
+    out["step_speedup"] = out["eager"]["ms_per_step"] / out["graph"]["ms_per_step"]
+    out["single_run_speedup"] = out["eager"]["single_run_ms_median"] / out["graph"]["single_run_ms_median"]
+    out["timing"] = (f"host wall clock: {steps} back-to-back runs then one sync; "
+                     f"median of {single_iters} runs each followed by a sync")
+    return out
+
+
 def check_clean_steps(drv, retries_before: dict, what: str) -> None:
     """After a loop of device runs: no run raised a device flag (collision,
     bucket overflow, look-back give-up, capacity, non-deterministic detector)
@@ -462,7 +510,7 @@ def bench_differentiation(get_driver, iters: int = 50) -> dict:
             "timing": "host wall clock around each call + stream sync, median of %d" % iters}
 
 
-def bench_batched(d: int, n_branches: int, steps: int) -> dict:
+def bench_batched(d: int, n_branches: int, steps: int, with_graph: bool = True) -> dict:
     """The batched workload: `n_branches` realised branches of the adaptive
     [[4,2,2]]-concatenated surface code, outer distance d, d cycles (seeds
     0 .. n_branches-1), uniform p = 1e-3. Device stages over the whole batch
@@ -487,6 +535,7 @@ def bench_batched(d: int, n_branches: int, steps: int) -> dict:
         drv.run()
     drv.sync()
     batch_ms = (time.perf_counter() - t0) * 1e3 / steps
+    graph = graph_replay(drv, steps, single_iters=20) if with_graph else None
     per_step = kernel_times(drv, max(2, steps // 4))
     kt = {k: round(v[0], 4) for k, v in sorted(per_step.items(), key=lambda x: -x[1][0])}
     info = drv.info()
@@ -535,7 +584,7 @@ def bench_batched(d: int, n_branches: int, steps: int) -> dict:
             "speedup_batched_vs_per_branch": per_ms / batch_ms,
             "batched_e2e_ms": batch_e2e_ms, "per_branch_e2e_ms_sum": per_e2e_ms,
             "batched_e2e_split_ms": split, "batched_e2e_host_share": (split["lower"] + split["fetch"]) / batch_e2e_ms,
-            "batched_kernels_ms": kt, "stage2": stage2, "autotune": tuned,
+            "batched_kernels_ms": kt, "stage2": stage2, "autotune": tuned, "graph_replay": graph,
             "timing": "device stages with tables resident (host wall clock over synced launches); "
                       "e2e = host lowering + upload + stages + download"}
 

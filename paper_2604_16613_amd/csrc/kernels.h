@@ -148,6 +148,7 @@ struct DevState {
   uint32_t n_pass;      // radix passes (8-bit digits) over the class key
   uint32_t sort_mode;   // SORT_*
   uint32_t sweep_shape; // stage-1 work-group shape: 0 automatic, 1 = 1024 threads, 2 = 256 threads
+  uint32_t item_xcd;    // 1: sweep work-group b runs the item of its XCD's contiguous share (all items resident)
   uint32_t spin_limit;  // look-back rounds a sort tile waits for a predecessor before giving up
   uint32_t max_tiles;   // tiles the sort/compaction scratch is sized for
 

@@ -36,6 +36,7 @@ namespace gp {
 namespace {
 
 constexpr int kSweepBlock = 1024;
+constexpr uint32_t kXcds = 8;          // accelerator dies of the MI355X, each with its own L2
 constexpr int kWinOps = int(kSweepWinOps);  // compact ops per LDS window buffer (two buffers)
 constexpr int kEmitPre = 8;            // fault records per thread fetched during the op phase
 constexpr int kLofsMax = 2048;         // layer offsets staged in LDS when the circuit has fewer layers
@@ -398,7 +399,15 @@ __global__ __launch_bounds__(kBlk) void k_sweep(DevState st) {
   __shared__ int s_wnz[2][kBlk / 64];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const uint32_t item = blockIdx.x;
+  // Work-groups are dispatched to the XCDs round robin (b mod kXcds). When
+  // every item is resident at once, XCD x takes a contiguous share of the
+  // items (columns in time order), so the fault records of a layer are
+  // fetched into one XCD's L2 instead of all eight.
+  uint32_t item = blockIdx.x;
+  if (st.item_xcd) {
+    const uint32_t x = item % kXcds, q = gridDim.x / kXcds, r = gridDim.x % kXcds;
+    item = x * q + min(x, r) + item / kXcds;
+  }
   const BranchDesc br = st.branch[st.item_branch[item]];
   const uint32_t n = br.n_qubits;
   // this circuit's layer, boundary and window tables
@@ -1950,6 +1959,7 @@ bool sweep_small_fits(const DevState& st) {
 }
 
 static size_t g_lds_limit = 64 * 1024;
+static uint32_t g_n_cus = 0;  // compute units of the device (0: unknown)
 static bool g_bucket_ok = false;
 
 size_t sweep_lds_limit() { return g_lds_limit; }
@@ -1963,6 +1973,10 @@ hipError_t configure_kernels() {
   int lds = 0;
   e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
   if (e != hipSuccess) return e;
+  int cus = 0;
+  e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  g_n_cus = cus > 0 ? uint32_t(cus) : 0u;
   // leave room for the sweep's static shared words
   size_t lim = size_t(lds) > 1024 ? size_t(lds) - 1024 : size_t(lds);
   if (lim > 64 * 1024) {
@@ -2030,6 +2044,9 @@ hipError_t enqueue_compile(DevState& st_io, hipStream_t stream, const LaunchHook
   if (st.n_items) {
     // the small shape for many items of small circuits (several per CU)
     const bool small = st.sweep_shape == 2 || (st.sweep_shape == 0 && st.n_items >= 512 && sweep_small_fits(st));
+    // one 1024-thread item per CU: the XCD-contiguous item order when they
+    // all fit at once
+    st.item_xcd = !small && st.n_items <= g_n_cus ? 1u : 0u;
     if (small && sweep_small_fits(st)) {
       GP_LAUNCH(K_SWEEP, k_sweep<true, 256><<<st.n_items, 256, sweep_lds_shape<256>(st.n_qubits), stream>>>(st));
     } else if (st.n_layers + 2 <= uint32_t(kLofsMax) && st.n_win <= uint32_t(kWinTableLds)) {

@@ -42,7 +42,7 @@ def test_profiled_traffic_reads_the_byte_columns():
 @pytest.mark.gpu
 def test_one_json_line_with_the_contract_fields():
     cmd = [sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--steps", "3", "--warmup", "1", "--latency-iters", "2",
-           "--no-cpu-baseline", "--no-grad", "--no-autotune", "--batch-distances=", "--serve-distances="]
+           "--no-cpu-baseline", "--no-grad", "--no-autotune", "--batch-distances=", "--serve-distances=", "--configs="]
     print("case bench contract", flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=240, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-2000:]
@@ -60,3 +60,6 @@ def test_one_json_line_with_the_contract_fields():
     assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
     assert abs(roof["frac"] - roof["achieved"] / roof["peak"]) < 1e-12
     assert 0 < j["stage2"]["frac_algorithmic"] < 1
+    g = j["graph_replay"]
+    for mode in ("eager", "graph"):
+        assert g[mode]["ms_per_step"] > 0 and g[mode]["single_run_ms_median"] > 0, mode
