@@ -89,6 +89,16 @@ struct TokChunk {
   uint32_t err_line = 0;
   const char* err_fmt = nullptr;
   std::string err_what;
+  void reset() {  // empty, keeping storage
+    toks.clear();
+    targets.clear();
+    is_rec.clear();
+    lines = 0;
+    err_code = 0;
+    err_line = 0;
+    err_fmt = nullptr;
+    err_what.clear();
+  }
 };
 
 void tokenize_text(const char* p, const char* end, TokChunk& c);
@@ -207,6 +217,10 @@ void tokenize_text(const char* p, const char* end, TokChunk& c) {
 // kTokChunkMin bytes of text per chunk).
 constexpr size_t kMaxTokThreads = 8;
 constexpr size_t kTokChunkMin = 1 << 17;
+// The channel tables are built on up to this many threads, one per this many
+// channels at least.
+constexpr size_t kMaxChanThreads = 4;
+constexpr size_t kChanChunkMin = 1 << 15;
 
 double rate_limit(uint8_t kind) {
   return kind == CH_DEP1 ? 0.75 : kind == CH_DEP2 ? 15.0 / 16.0 : 0.5;
@@ -237,6 +251,13 @@ struct RawChan {
 
 namespace {
 
+// A column's leaf word from one measurement: column, layer, qubit,
+// measurement, word.
+struct InjEntry {
+  uint32_t w, layer, qubit, m;
+  uint64_t word;
+};
+
 // The program-order scheduling of one circuit, fed one elementary operation
 // at a time by either front end (circuit text or the binary form): ASAP
 // layers, measurement records, noise channels at their boundary, and the
@@ -249,9 +270,21 @@ struct Sched {
   std::vector<RawChan> chans;
   std::vector<uint64_t> pairs;     // (measurement << 32) | detector index or kObsFlag | observable
   std::vector<uint32_t> meas_layer;
+  std::vector<uint32_t> meas_qubit;  // per measurement: its qubit
   uint32_t n_meas = 0, n_det = 0, n_obs = 0;
   const char* msg = nullptr;
 
+  void reset() {  // empty, keeping storage
+    ready.clear();
+    op_layer.clear();
+    op_word.clear();
+    chans.clear();
+    pairs.clear();
+    meas_layer.clear();
+    meas_qubit.clear();
+    n_meas = n_det = n_obs = 0;
+    msg = nullptr;
+  }
   int bad(int code, const char* m) {
     msg = m;
     return code;
@@ -285,6 +318,7 @@ struct Sched {
     op_layer.push_back(ready[q]);
     op_word.push_back(pack_op(kind, q, n_meas));
     meas_layer.push_back(ready[q]);
+    meas_qubit.push_back(q);
     ready[q]++;
     n_meas++;
     return 0;
@@ -332,23 +366,63 @@ int finish_lowering(Sched& S, const double* rates, size_t n_rates, uint32_t swee
 
 }  // namespace
 
+void Lowered::reset() {
+  // every field; the size check below fails when one is added, so that it is
+  // added here too
+  static_assert(sizeof(Lowered) == 960, "a field of Lowered is missing from reset()");
+  n_qubits = n_layers = n_meas = n_det = n_obs = 0;
+  wd = wo = w = 0;
+  n_faults = 0;
+  slab_words = 0;
+  level = 2;
+  bm_words = 0;
+  w_max = 0;
+  for (auto* v : {&layer_off, &leaf_off, &leaf_bits, &meas_layer, &chan_qa, &chan_qb, &chan_src, &chan_foff,
+                  &bnd_chan_off, &bnd_fault_off, &item_col, &item_blo, &item_bhi, &ops32, &inj_off, &inj_layer,
+                  &inj_qubit, &inj_next, &hchunk_pos, &hchunk_bnd, &layer_win, &win_lo, &win_obase, &win_cnt,
+                  &bnd_bm_off, &item_branch, &hchunk_branch})
+    v->clear();
+  for (auto* v : {&ops, &col_base, &fnv_pow, &inj_word, &col_bm_base}) v->clear();
+  col_top.clear();
+  col_lo.clear();
+  chan_kind.clear();
+  chan_rate.clear();
+  branches.clear();
+}
+
+namespace {
+// Scratch that a thread keeps from one lowering to the next (capacity only:
+// every use starts from cleared vectors), so that large lowerings do not touch
+// fresh pages each time.
+struct LowerScratch {
+  Sched sched;
+  std::vector<TokChunk> chunks;
+  std::vector<uint64_t> pairs_sorted;
+  std::vector<InjEntry> inj, inj_by_col;
+};
+thread_local LowerScratch t_scratch;
+}  // namespace
+
 int lower_circuit(const char* text, size_t len, const double* rates, size_t n_rates,
                   uint32_t sweep_slots, Lowered& lw, LowerError& err, uint32_t level, double fault_cost) {
-  lw = Lowered();
+  lw.reset();
   if (level > 2) return set_err(err, GP_E_ARG, 0, "%s", "correlation level must be 0, 1 or 2");
   if (!(fault_cost >= 0.0 && fault_cost < 1.0)) return set_err(err, GP_E_ARG, 0, "%s", "fault cost must be in [0, 1)");
   lw.level = level;
-  Sched S;
+  Sched& S = t_scratch.sched;
+  S.reset();
   // sized from the text (typical circuits spend about four characters per
   // target) so that the vectors rarely regrow
   S.op_layer.reserve(len / 4);
   S.op_word.reserve(len / 4);
   S.chans.reserve(len / 8);
   S.pairs.reserve(len / 8);
+  S.meas_layer.reserve(len / 8);
+  S.meas_qubit.reserve(len / 8);
 
   // tokenize whole-line chunks in parallel, then schedule (ASAP layers,
   // measurement records, channels) in program order
-  std::vector<TokChunk> chunks;
+  std::vector<TokChunk>& chunks = t_scratch.chunks;
   {
     const size_t T = std::max<size_t>(1, std::min(kMaxTokThreads, len / kTokChunkMin));
     std::vector<const char*> cut(T + 1, text + len);
@@ -360,6 +434,7 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
       cut[k] = nl ? nl + 1 : text + len;
     }
     chunks.resize(T);
+    for (TokChunk& ck : chunks) ck.reset();
     if (T == 1) {
       tokenize(cut[0], cut[1], chunks[0]);
     } else {
@@ -444,14 +519,21 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
 
 int lower_ir(const gp_circuit_ir& ir, const double* rates, size_t n_rates, uint32_t sweep_slots, Lowered& lw,
              LowerError& err, uint32_t level, double fault_cost) {
-  lw = Lowered();
+  lw.reset();
   if (level > 2) return set_err(err, GP_E_ARG, 0, "%s", "correlation level must be 0, 1 or 2");
   if (!(fault_cost >= 0.0 && fault_cost < 1.0)) return set_err(err, GP_E_ARG, 0, "%s", "fault cost must be in [0, 1)");
   if (ir.n_ops && !ir.code) return set_err(err, GP_E_ARG, 0, "%s", "operation codes missing");
   lw.level = level;
-  Sched S;
+  Sched& S = t_scratch.sched;
+  S.reset();
+  // upper bounds, so that the vectors never regrow (untouched capacity costs
+  // no memory traffic)
   S.op_layer.reserve(ir.n_ops);
   S.op_word.reserve(ir.n_ops);
+  S.chans.reserve(ir.n_ops);
+  S.meas_layer.reserve(ir.n_ops);
+  S.meas_qubit.reserve(ir.n_ops);
+  S.pairs.reserve(ir.n_rec);
   uint64_t ri = 0;  // next entry of ir.rec
   char buf[160];
   auto op_err = [&](uint64_t k, int code, const char* what) {
@@ -548,25 +630,62 @@ int finish_lowering(Sched& S, const double* rates, size_t n_rates, uint32_t swee
         chans[k].rate = r;
       }
     }
-    lw.bnd_chan_off.assign(size_t(L) + 2, 0);
-    for (const RawChan& c : chans) lw.bnd_chan_off[c.boundary + 1]++;
-    for (uint32_t b = 0; b <= L; b++) lw.bnd_chan_off[b + 1] += lw.bnd_chan_off[b];
     lw.chan_qa.resize(C);
     lw.chan_qb.resize(C);
     lw.chan_kind.resize(C);
     lw.chan_rate.resize(C);
     lw.chan_src.resize(C);
-    {
-      std::vector<uint32_t> fill(lw.bnd_chan_off.begin(), lw.bnd_chan_off.end() - 1);
-      for (size_t k = 0; k < C; k++) {
-        uint32_t d = fill[chans[k].boundary]++;
+    // stable counting sort by boundary; large circuits split the channels
+    // over a few threads (per-thread boundary counts, one prefix over
+    // (boundary, thread), then each thread scatters its own range)
+    const size_t T = std::max<size_t>(1, std::min<size_t>(kMaxChanThreads, C / kChanChunkMin));
+    const size_t nb = size_t(L) + 1;
+    std::vector<uint32_t> cnt(T * nb, 0);
+    auto part = [&](size_t t) { return std::make_pair(C * t / T, C * (t + 1) / T); };
+    auto count = [&](size_t t) {
+      uint32_t* c = cnt.data() + t * nb;
+      const auto r = part(t);
+      for (size_t k = r.first; k < r.second; k++) c[chans[k].boundary]++;
+    };
+    auto scatter = [&](size_t t) {
+      uint32_t* f = cnt.data() + t * nb;
+      const auto r = part(t);
+      for (size_t k = r.first; k < r.second; k++) {
+        const uint32_t d = f[chans[k].boundary]++;
         lw.chan_qa[d] = chans[k].qa;
         lw.chan_qb[d] = chans[k].qb;
         lw.chan_kind[d] = chans[k].kind;
         lw.chan_rate[d] = chans[k].rate;
         lw.chan_src[d] = uint32_t(k);
       }
+    };
+    auto on_threads = [&](auto&& fn) {
+      std::vector<std::thread> pool;
+      for (size_t t = 1; t < T; t++) {
+        try {
+          pool.emplace_back(fn, t);
+        } catch (...) {
+          fn(t);  // could not start a thread: do its part here
+        }
+      }
+      fn(size_t(0));
+      for (std::thread& th : pool) th.join();
+    };
+    on_threads(count);
+    lw.bnd_chan_off.assign(size_t(L) + 2, 0);
+    {
+      uint32_t run = 0;
+      for (size_t b = 0; b < nb; b++) {
+        lw.bnd_chan_off[b] = run;
+        for (size_t t = 0; t < T; t++) {
+          const uint32_t x = cnt[t * nb + b];
+          cnt[t * nb + b] = run;
+          run += x;
+        }
+      }
+      lw.bnd_chan_off[nb] = run;
     }
+    on_threads(scatter);
     uint64_t total_faults = 0;
     for (size_t c = 0; c < C; c++) total_faults += kKeptCodes.n[lw.chan_kind[c]][lw.level];
     if (total_faults >= (1ull << 32)) return set_err(e, GP_E_BOUNDS, 0, "%s", "more than 2^32 - 1 faults");
@@ -624,7 +743,8 @@ int finish_lowering(Sched& S, const double* rates, size_t n_rates, uint32_t swee
     std::vector<uint32_t> cnt(size_t(n_meas) + 1, 0);
     for (uint64_t pr : pairs) cnt[(pr >> 32) + 1]++;
     for (uint32_t m = 0; m < n_meas; m++) cnt[m + 1] += cnt[m];
-    std::vector<uint64_t> sorted(pairs.size());
+    std::vector<uint64_t>& sorted = t_scratch.pairs_sorted;
+    sorted.resize(pairs.size());
     std::vector<uint32_t> fill(cnt.begin(), cnt.end() - 1);
     for (uint64_t pr : pairs) sorted[fill[pr >> 32]++] = pr;
     for (uint32_t m = 0; m < n_meas; m++)
@@ -685,18 +805,14 @@ int finish_lowering(Sched& S, const double* rates, size_t n_rates, uint32_t swee
 
   // ---- per-column leaf injections, top layer first (on a second thread for
   // large circuits, beside the items, windows and compact ops)
+  // (it may run on another thread: its buffers are this thread's scratch)
+  std::vector<InjEntry>& inj = t_scratch.inj;
+  std::vector<InjEntry>& by_col = t_scratch.inj_by_col;
   auto injection_phase = [&]() {
     {
-      std::vector<uint32_t> meas_qubit(n_meas, 0);
-      for (uint64_t op : lw.ops) {
-        const uint32_t kind = uint32_t(op >> 56);
-        if (kind >= OP_M) meas_qubit[uint32_t(op) & kField] = uint32_t(op >> 28) & kField;
-      }
-      struct Inj {
-        uint32_t w, layer, qubit, m;
-        uint64_t word;
-      };
-      std::vector<Inj> inj;
+      const std::vector<uint32_t>& meas_qubit = S.meas_qubit;
+      using Inj = InjEntry;
+      inj.clear();
       for (uint32_t m = 0; m < n_meas; m++) {
         for (uint32_t k = lw.leaf_off[m]; k < lw.leaf_off[m + 1]; k++) {
           const uint32_t bit = lw.leaf_bits[k];
@@ -714,7 +830,7 @@ int finish_lowering(Sched& S, const double* rates, size_t n_rates, uint32_t swee
       for (const Inj& e : inj) lw.inj_off[e.w + 1]++;
       for (uint32_t w = 0; w < lw.w; w++) lw.inj_off[w + 1] += lw.inj_off[w];
       {
-        std::vector<Inj> by_col(inj.size());
+        by_col.resize(inj.size());
         std::vector<uint32_t> fill(lw.inj_off.begin(), lw.inj_off.end() - 1);
         for (const Inj& e : inj) by_col[fill[e.w]++] = e;
         for (uint32_t w = 0; w < lw.w; w++)

@@ -181,6 +181,10 @@ struct Lowered {
   std::vector<BranchDesc> branches;
   std::vector<uint32_t> item_branch, hchunk_branch;
   uint32_t w_max = 0;
+
+  // Empty tables, keeping the vectors' storage: a driver lowers circuit after
+  // circuit into one Lowered without touching fresh pages each time.
+  void reset();
 };
 
 // Concatenate independently lowered circuits into one batch: tables are

@@ -22,10 +22,14 @@ def _load():
         newest = max(os.path.getmtime(SRC), os.path.getmtime(LOWER),
                      os.path.getmtime(os.path.join(ROOT, "paper_2604_16613_amd", "csrc", "lower.h")))
         if not os.path.exists(OUT) or os.path.getmtime(OUT) < newest:
+            # built under a name of this process's own, then renamed into place
+            # in one step: parallel test workers never load a half-written file
+            tmp = f"{OUT}.{os.getpid()}.tmp"
             subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC",
                             "-I", os.path.join(ROOT, "include"),
                             "-I", os.path.join(ROOT, "paper_2604_16613_amd", "csrc"),
-                            SRC, LOWER, "-o", OUT], check=True)
+                            SRC, LOWER, "-o", tmp], check=True)
+            os.replace(tmp, OUT)
         lib = ctypes.CDLL(OUT)
         P = ctypes.POINTER
         lib.hc_run.argtypes = [ctypes.c_char_p, ctypes.c_size_t, P(ctypes.c_double), ctypes.c_size_t,
