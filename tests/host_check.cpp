@@ -349,3 +349,46 @@ extern "C" int hc_run_batch(const char* const* texts, const size_t* lens, size_t
     for (uint32_t p = lw.branches[k].fb; p < lw.branches[k].fe; p++) fault_circuit[p] = uint32_t(k);
   return replay(lw, off, bits, bits_cap, src, code, stats, max_faults);
 }
+
+// A digest (FNV-1a over the bytes) of every table of a lowering, lowered into
+// a Lowered kept across calls (reuse != 0) or into a fresh one: the kept one
+// must give the fresh one's tables whatever was lowered into it before.
+static uint64_t digest_bytes(uint64_t h, const void* p, size_t n) {
+  const unsigned char* c = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < n; i++) h = (h ^ c[i]) * 1099511628211ull;
+  return (h ^ n) * 1099511628211ull;
+}
+template <typename V>
+static uint64_t digest_vec(uint64_t h, const V& v) {
+  return digest_bytes(h, v.data(), v.size() * sizeof(v[0]));
+}
+extern "C" int hc_lower_digest(const char* text, size_t len, int reuse, uint64_t* out) {
+  static Lowered kept;
+  Lowered fresh;
+  Lowered& lw = reuse ? kept : fresh;
+  LowerError err{0, ""};
+  const int rc = lower_circuit(text, len, nullptr, 0, kSweepSlots, lw, err, 2, g_fault_cost);
+  if (rc) {
+    g_msg = err.msg;
+    return rc;
+  }
+  uint64_t h = 1469598103934665603ull;
+  const uint64_t scal[] = {lw.n_qubits, lw.n_layers, lw.n_meas, lw.n_det, lw.n_obs, lw.wd, lw.wo, lw.w,
+                           lw.n_faults, lw.slab_words, lw.level, lw.bm_words, lw.w_max};
+  h = digest_bytes(h, scal, sizeof scal);
+  h = digest_vec(h, lw.ops), h = digest_vec(h, lw.layer_off), h = digest_vec(h, lw.leaf_off);
+  h = digest_vec(h, lw.leaf_bits), h = digest_vec(h, lw.meas_layer), h = digest_vec(h, lw.chan_qa);
+  h = digest_vec(h, lw.chan_qb), h = digest_vec(h, lw.chan_kind), h = digest_vec(h, lw.chan_rate);
+  h = digest_vec(h, lw.chan_src), h = digest_vec(h, lw.chan_foff), h = digest_vec(h, lw.bnd_chan_off);
+  h = digest_vec(h, lw.bnd_fault_off), h = digest_vec(h, lw.col_top), h = digest_vec(h, lw.col_lo);
+  h = digest_vec(h, lw.col_base), h = digest_vec(h, lw.item_col), h = digest_vec(h, lw.item_blo);
+  h = digest_vec(h, lw.item_bhi), h = digest_vec(h, lw.fnv_pow), h = digest_vec(h, lw.ops32);
+  h = digest_vec(h, lw.inj_off), h = digest_vec(h, lw.inj_layer), h = digest_vec(h, lw.inj_qubit);
+  h = digest_vec(h, lw.inj_word), h = digest_vec(h, lw.inj_next), h = digest_vec(h, lw.hchunk_pos);
+  h = digest_vec(h, lw.hchunk_bnd), h = digest_vec(h, lw.layer_win), h = digest_vec(h, lw.win_lo);
+  h = digest_vec(h, lw.win_obase), h = digest_vec(h, lw.win_cnt), h = digest_vec(h, lw.bnd_bm_off);
+  h = digest_vec(h, lw.col_bm_base), h = digest_vec(h, lw.item_branch), h = digest_vec(h, lw.hchunk_branch);
+  h = digest_bytes(h, lw.branches.data(), lw.branches.size() * sizeof(BranchDesc));
+  *out = h;
+  return 0;
+}

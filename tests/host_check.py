@@ -37,6 +37,8 @@ def _load():
                                P(ctypes.c_uint32), P(ctypes.c_uint64), ctypes.c_uint64]
         lib.hc_run.restype = ctypes.c_int
         lib.hc_error.restype = ctypes.c_char_p
+        lib.hc_lower_digest.argtypes = [ctypes.c_char_p, ctypes.c_size_t, ctypes.c_int, P(ctypes.c_uint64)]
+        lib.hc_lower_digest.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -120,3 +122,15 @@ def set_fault_cost(c: float) -> None:
     lib.hc_set_fault_cost.restype = None
     lib.hc_set_fault_cost(c)
 
+
+
+def lower_digest(text, reuse):
+    """Digest of every lowered table of `text`, lowered into tables kept
+    across calls (reuse) or into fresh ones."""
+    lib = _load()
+    raw = text.encode()
+    out = ctypes.c_uint64()
+    rc = lib.hc_lower_digest(raw, len(raw), int(bool(reuse)), ctypes.byref(out))
+    if rc:
+        raise RuntimeError(f"lowering failed ({rc}): {lib.hc_error().decode()}")
+    return out.value

@@ -147,3 +147,20 @@ def test_tokenizer_chunks_ignore_layout():
     st_a, sig_a = host_check.run(c.text)
     st_b, sig_b = host_check.run(messy)
     assert st_a == st_b and sig_a == sig_b
+
+
+def test_tables_lowered_into_reused_storage_equal_fresh_ones():
+    """A driver lowers circuit after circuit into the same tables, keeping
+    their storage: each lowering must give exactly the tables a fresh lowering
+    gives, whatever was lowered before (larger, smaller, other families, the
+    multi-threaded path of a large circuit included)."""
+    circuits = [rotated_surface_code_memory(23, 23).text,  # large: tokenizer, channel-table and injection threads
+                bit_flip_code_fig1().text,
+                bivariate_bicycle_memory(rounds=3).text,
+                mirror_circuit(12, 6, seed=3).text,
+                rotated_surface_code_memory(5, 5).text,
+                rotated_surface_code_memory(23, 23).text]
+    fresh = [host_check.lower_digest(t, reuse=False) for t in circuits]
+    kept = [host_check.lower_digest(t, reuse=True) for t in circuits]
+    assert kept == fresh
+    assert fresh[0] == fresh[-1] and len(set(fresh[:-1])) == len(circuits) - 1
