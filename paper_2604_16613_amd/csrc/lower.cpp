@@ -89,16 +89,6 @@ struct TokChunk {
   uint32_t err_line = 0;
   const char* err_fmt = nullptr;
   std::string err_what;
-  void reset() {  // empty, keeping storage
-    toks.clear();
-    targets.clear();
-    is_rec.clear();
-    lines = 0;
-    err_code = 0;
-    err_line = 0;
-    err_fmt = nullptr;
-    err_what.clear();
-  }
 };
 
 void tokenize_text(const char* p, const char* end, TokChunk& c);
@@ -274,17 +264,6 @@ struct Sched {
   uint32_t n_meas = 0, n_det = 0, n_obs = 0;
   const char* msg = nullptr;
 
-  void reset() {  // empty, keeping storage
-    ready.clear();
-    op_layer.clear();
-    op_word.clear();
-    chans.clear();
-    pairs.clear();
-    meas_layer.clear();
-    meas_qubit.clear();
-    n_meas = n_det = n_obs = 0;
-    msg = nullptr;
-  }
   int bad(int code, const char* m) {
     msg = m;
     return code;
@@ -390,27 +369,13 @@ void Lowered::reset() {
   branches.clear();
 }
 
-namespace {
-// Scratch that a thread keeps from one lowering to the next (capacity only:
-// every use starts from cleared vectors), so that large lowerings do not touch
-// fresh pages each time.
-struct LowerScratch {
-  Sched sched;
-  std::vector<TokChunk> chunks;
-  std::vector<uint64_t> pairs_sorted;
-  std::vector<InjEntry> inj, inj_by_col;
-};
-thread_local LowerScratch t_scratch;
-}  // namespace
-
 int lower_circuit(const char* text, size_t len, const double* rates, size_t n_rates,
                   uint32_t sweep_slots, Lowered& lw, LowerError& err, uint32_t level, double fault_cost) {
   lw.reset();
   if (level > 2) return set_err(err, GP_E_ARG, 0, "%s", "correlation level must be 0, 1 or 2");
   if (!(fault_cost >= 0.0 && fault_cost < 1.0)) return set_err(err, GP_E_ARG, 0, "%s", "fault cost must be in [0, 1)");
   lw.level = level;
-  Sched& S = t_scratch.sched;
-  S.reset();
+  Sched S;
   // sized from the text (typical circuits spend about four characters per
   // target) so that the vectors rarely regrow
   S.op_layer.reserve(len / 4);
@@ -422,7 +387,7 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
 
   // tokenize whole-line chunks in parallel, then schedule (ASAP layers,
   // measurement records, channels) in program order
-  std::vector<TokChunk>& chunks = t_scratch.chunks;
+  std::vector<TokChunk> chunks;
   {
     const size_t T = std::max<size_t>(1, std::min(kMaxTokThreads, len / kTokChunkMin));
     std::vector<const char*> cut(T + 1, text + len);
@@ -434,7 +399,6 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
       cut[k] = nl ? nl + 1 : text + len;
     }
     chunks.resize(T);
-    for (TokChunk& ck : chunks) ck.reset();
     if (T == 1) {
       tokenize(cut[0], cut[1], chunks[0]);
     } else {
@@ -524,8 +488,7 @@ int lower_ir(const gp_circuit_ir& ir, const double* rates, size_t n_rates, uint3
   if (!(fault_cost >= 0.0 && fault_cost < 1.0)) return set_err(err, GP_E_ARG, 0, "%s", "fault cost must be in [0, 1)");
   if (ir.n_ops && !ir.code) return set_err(err, GP_E_ARG, 0, "%s", "operation codes missing");
   lw.level = level;
-  Sched& S = t_scratch.sched;
-  S.reset();
+  Sched S;
   // upper bounds, so that the vectors never regrow (untouched capacity costs
   // no memory traffic)
   S.op_layer.reserve(ir.n_ops);
@@ -743,8 +706,7 @@ int finish_lowering(Sched& S, const double* rates, size_t n_rates, uint32_t swee
     std::vector<uint32_t> cnt(size_t(n_meas) + 1, 0);
     for (uint64_t pr : pairs) cnt[(pr >> 32) + 1]++;
     for (uint32_t m = 0; m < n_meas; m++) cnt[m + 1] += cnt[m];
-    std::vector<uint64_t>& sorted = t_scratch.pairs_sorted;
-    sorted.resize(pairs.size());
+    std::vector<uint64_t> sorted(pairs.size());
     std::vector<uint32_t> fill(cnt.begin(), cnt.end() - 1);
     for (uint64_t pr : pairs) sorted[fill[pr >> 32]++] = pr;
     for (uint32_t m = 0; m < n_meas; m++)
@@ -805,14 +767,11 @@ int finish_lowering(Sched& S, const double* rates, size_t n_rates, uint32_t swee
 
   // ---- per-column leaf injections, top layer first (on a second thread for
   // large circuits, beside the items, windows and compact ops)
-  // (it may run on another thread: its buffers are this thread's scratch)
-  std::vector<InjEntry>& inj = t_scratch.inj;
-  std::vector<InjEntry>& by_col = t_scratch.inj_by_col;
   auto injection_phase = [&]() {
     {
       const std::vector<uint32_t>& meas_qubit = S.meas_qubit;
       using Inj = InjEntry;
-      inj.clear();
+      std::vector<Inj> inj;
       for (uint32_t m = 0; m < n_meas; m++) {
         for (uint32_t k = lw.leaf_off[m]; k < lw.leaf_off[m + 1]; k++) {
           const uint32_t bit = lw.leaf_bits[k];
@@ -830,7 +789,7 @@ int finish_lowering(Sched& S, const double* rates, size_t n_rates, uint32_t swee
       for (const Inj& e : inj) lw.inj_off[e.w + 1]++;
       for (uint32_t w = 0; w < lw.w; w++) lw.inj_off[w + 1] += lw.inj_off[w];
       {
-        by_col.resize(inj.size());
+        std::vector<Inj> by_col(inj.size());
         std::vector<uint32_t> fill(lw.inj_off.begin(), lw.inj_off.end() - 1);
         for (const Inj& e : inj) by_col[fill[e.w]++] = e;
         for (uint32_t w = 0; w < lw.w; w++)
