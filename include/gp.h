@@ -483,6 +483,21 @@ int gp_debug_set_sweep_shape(gp_driver* drv, int shape);
  * enabled (gp_set_timing) are never captured. */
 int gp_debug_set_graph(gp_driver* drv, int enable);
 
+/* Test hook for the class key of Sec. 3.2. With enable = 1, every later gp_run
+ * copies the per-position class keys (written by the hash kernel, before the
+ * grouping passes reuse that buffer) into a buffer this call allocates once
+ * (8 B per fault of the driver's bounds); runs with the hook on are never
+ * replayed as a graph. gp_debug_class_keys synchronises the driver's stream
+ * and copies min(cap, n) keys of the last gp_run to out (host memory, may be
+ * NULL when cap is 0): position order (the lowered fault order), each key the
+ * 64-bit FNV-1a of the fault's signature (the 8W little-endian octets of its W
+ * signature words: detector words, then observable words) cut to its low
+ * *key_bits bits; a circuit of a batch other than the first also has a
+ * per-circuit salt in it. *n_faults gets n; key_bits may be NULL.
+ * GP_E_STATE when no gp_run has run with the hook on. */
+int gp_debug_capture_keys(gp_driver* drv, int enable);
+int gp_debug_class_keys(gp_driver* drv, uint64_t* out, uint64_t cap, uint64_t* n_faults, uint32_t* key_bits);
+
 /* Profiling hook: device wall-clock stamps of every stage-1 sweep item of the
  * last gp_run (start, end pairs; `cap` entries at most), the item count, and
  * the clock rate in Hz. Synchronises the driver's stream. */

@@ -30,7 +30,7 @@ EXPORTS = (
     "gp_timing_entry", "gp_edges_count", "gp_edges_detectors", "gp_edges_observables",
     "gp_edges_offsets", "gp_edges_bits", "gp_edges_probabilities", "gp_edges_to_dem_text",
     "gp_edges_free", "gp_free", "gp_debug_set_key_bits", "gp_debug_collision_retries",
-    "gp_debug_sweep_times", "gp_debug_set_sort_mode", "gp_refresh_rates", "gp_rates_gradient",
+    "gp_debug_sweep_times", "gp_debug_capture_keys", "gp_debug_class_keys", "gp_debug_set_sort_mode", "gp_refresh_rates", "gp_rates_gradient",
     "gp_set_correlation_level", "gp_bounds_from_batch", "gp_driver_create_from_batch", "gp_lower_batch",
     "gp_edges_circuits", "gp_edges_circuit_ids", "gp_edges_circuit_shape", "gp_edges_circuit_dem_text",
     "gp_edges_circuit_offsets", "gp_server_create", "gp_server_submit", "gp_server_wait", "gp_server_stats",
@@ -237,6 +237,9 @@ def load():
                                ctypes.POINTER(ctypes.c_double), ctypes.c_size_t], ctypes.c_int),
         "gp_debug_sweep_times": ([_vp, ctypes.POINTER(_u64), _u64, ctypes.POINTER(_u64),
                                   ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "gp_debug_capture_keys": ([_vp, ctypes.c_int], ctypes.c_int),
+        "gp_debug_class_keys": ([_vp, ctypes.POINTER(_u64), _u64, ctypes.POINTER(_u64),
+                                 ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
         "gp_bounds_from_batch": ([ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_size_t), ctypes.c_size_t,
                                   ctypes.POINTER(GpBounds)], ctypes.c_int),
         "gp_driver_create_from_batch": ([ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_size_t),
@@ -672,6 +675,21 @@ def gp_debug_sweep_times(drv: int, cap: int = 1 << 16):
                                        ctypes.byref(hz)))
     m = min(int(n.value), cap // 2)
     return buf[:2 * m].reshape(-1, 2), hz.value
+
+
+def gp_debug_capture_keys(drv: int, enable: bool = True) -> None:
+    _check(load().gp_debug_capture_keys(drv, int(enable)))
+
+
+def gp_debug_class_keys(drv: int):
+    """-> (per-position class keys of the last gp_run as uint64, key bits kept)."""
+    n = _u64()
+    bits = ctypes.c_uint32()
+    _check(load().gp_debug_class_keys(drv, None, 0, ctypes.byref(n), ctypes.byref(bits)))
+    buf = np.zeros(max(int(n.value), 1), dtype=np.uint64)
+    _check(load().gp_debug_class_keys(drv, buf.ctypes.data_as(ctypes.POINTER(_u64)), int(n.value),
+                                      ctypes.byref(n), ctypes.byref(bits)))
+    return buf[:int(n.value)], int(bits.value)
 
 
 def gp_server_create(bounds: GpBounds, device: int = 0) -> int:

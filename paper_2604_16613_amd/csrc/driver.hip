@@ -217,6 +217,12 @@ struct gp_driver {
   double fault_cost = gp::kDefaultFaultCost;  // observable range cut (set by gp_autotune)
   uint32_t spin_limit = gp::kSpinLimit;  // test hook: look-back rounds before a sort tile gives up
   uint64_t collision_retries = 0, bucket_retries = 0, lookback_retries = 0;
+  // test hook: each gp_run copies the per-position class keys here once the
+  // hash kernel has written them (the grouping passes overwrite them after)
+  bool capture_keys = false;
+  uint64_t* key_copy = nullptr;
+  uint32_t captured_key_bits = 0;
+  uint64_t captured_faults = 0;
 
   // optionally, the compile's launch sequence captured as a HIP graph and
   // replayed while the lowering and the modes it was captured with stay the same
@@ -267,6 +273,14 @@ void hook_before(void* ctx, int id) {
 void hook_after(void* ctx, int) {
   gp_driver* d = static_cast<gp_driver*>(ctx);
   if (!d->pending.empty() && d->pending.back().b) (void)hipEventRecord(d->pending.back().b, d->stream);
+}
+
+void hook_after_keys(void* ctx, int id) {
+  gp_driver* d = static_cast<gp_driver*>(ctx);
+  if (d->timing) hook_after(ctx, id);
+  if (id == gp::K_HASH && d->st.n_faults)
+    (void)hipMemcpyAsync(d->key_copy, d->st.key[1], size_t(d->st.n_faults) * sizeof(uint64_t),
+                         hipMemcpyDeviceToDevice, d->stream);
 }
 
 void collect_timing(gp_driver* d) {
@@ -793,13 +807,19 @@ static int gp_run_impl(gp_driver* d) {
     hook.after = hook_after;
     hook.ctx = d;
   }
+  if (d->capture_keys) {
+    hook.after = hook_after_keys;
+    hook.ctx = d;
+    d->captured_faults = d->st.n_faults;
+    d->captured_key_bits = gp::class_key_bits(d->st.n_faults, d->key_bits);
+  }
   d->st.key_mode = 0;
   d->st.key_bits = d->key_bits;
   d->st.sort_mode = d->sort_mode;
   d->st.sweep_shape = d->sweep_shape;
   d->st.spin_limit = d->spin_limit;
   d->structured = false;
-  if (d->use_graph && !d->timing) {
+  if (d->use_graph && !d->timing && !d->capture_keys) {
     // replay the captured launch sequence; capture it first if the lowering
     // or a mode changed since
     if (!d->gexec || d->graph_gen != d->lower_gen || d->graph_key_bits != d->key_bits ||
@@ -1479,6 +1499,29 @@ int gp_debug_set_sort_mode(gp_driver* d, int mode) {
   if (mode != int(gp::SORT_AUTO) && mode != int(gp::SORT_FULL) && mode != int(gp::SORT_BUCKET16))
     return fail(GP_E_ARG, "sort mode must be 0, 1 or 2");
   d->sort_mode = uint32_t(mode);
+  return GP_OK;
+}
+
+int gp_debug_capture_keys(gp_driver* d, int enable) {
+  if (!d) return fail(GP_E_ARG, "null driver");
+  if (enable && !d->key_copy) {
+    HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
+    if (int rc = dev_alloc(d, &d->key_copy, d->bounds.max_faults, "captured class keys")) return rc;
+  }
+  d->capture_keys = enable != 0;
+  d->captured_faults = 0;
+  return GP_OK;
+}
+
+int gp_debug_class_keys(gp_driver* d, uint64_t* out, uint64_t cap, uint64_t* n_faults, uint32_t* key_bits) {
+  if (!d || !n_faults || (cap && !out)) return fail(GP_E_ARG, "null argument");
+  if (!d->capture_keys || !d->ran) return fail(GP_E_STATE, "no compile has run with key capture on");
+  HIP_TRY(hipSetDevice(d->device), "hipSetDevice");
+  HIP_TRY(hipStreamSynchronize(d->stream), "hipStreamSynchronize");
+  *n_faults = d->captured_faults;
+  if (key_bits) *key_bits = d->captured_key_bits;
+  const uint64_t m = std::min<uint64_t>(cap, d->captured_faults);
+  if (m) HIP_TRY(hipMemcpy(out, d->key_copy, m * 8, hipMemcpyDeviceToHost), "download class keys");
   return GP_OK;
 }
 

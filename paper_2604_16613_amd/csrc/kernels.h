@@ -215,6 +215,9 @@ struct LaunchHook {
 // Radix passes needed for `n` keys: enough key bits that two distinct classes
 // share them with probability below about 2^-12 (collisions are still caught).
 uint32_t sort_passes(uint64_t n);
+// key bits a first (FNV-1a keyed) compile of n faults keeps: those its sort
+// passes cover, at most cap
+uint32_t class_key_bits(uint64_t n, uint32_t cap);
 
 // Enqueue both stages for the lowered circuit described by `st`; st.ord is
 // set to the buffer that then holds the class members.

@@ -1937,6 +1937,11 @@ uint32_t sort_passes(uint64_t n) {
   return p > uint32_t(kMaxPasses) ? uint32_t(kMaxPasses) : p;
 }
 
+uint32_t class_key_bits(uint64_t n, uint32_t cap) {
+  const uint32_t b = 8 * sort_passes(n);
+  return cap < b ? cap : b;
+}
+
 size_t hash_lds_bytes(uint32_t w) { return (size_t(w) + 1) * 8 + size_t(w) * (8 + 8 + 8 * kHashBmw + 4); }
 
 template <int kBlk>
@@ -2027,7 +2032,7 @@ hipError_t enqueue_compile(DevState& st_io, hipStream_t stream, const LaunchHook
     st.key_bits = 64;
   } else {
     st.n_pass = sort_passes(n);
-    if (8 * st.n_pass < st.key_bits) st.key_bits = 8 * st.n_pass;
+    st.key_bits = class_key_bits(n, st.key_bits);
   }
   // 16-bit buckets: from kBucket16MinFaults faults (or when forced), while
   // the key has two digits above the ones sorted in LDS
