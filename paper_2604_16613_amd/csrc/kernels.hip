@@ -1563,15 +1563,31 @@ __device__ __forceinline__ uint32_t rep_bits16(const DevState& st, uint32_t p0) 
   return p0 < st.n_faults ? uint32_t(st.rep_bm[p0 >> 6] >> (p0 & 63)) & 0xFFFFu : 0u;
 }
 
+// The signature weights of a thread's 16 positions, loaded at once (64
+// contiguous bytes; positions past the last fault read as zero).
+__device__ __forceinline__ void weights16(const DevState& st, uint32_t p0, uint32_t (&pc)[kOutPer]) {
+  if (p0 + uint32_t(kOutPer) <= st.n_faults) {
+    const uint4* src = reinterpret_cast<const uint4*>(st.popc + p0);
+#pragma unroll
+    for (int j = 0; j < kOutPer / 4; ++j) {
+      const uint4 x = src[j];
+      pc[4 * j] = x.x;
+      pc[4 * j + 1] = x.y;
+      pc[4 * j + 2] = x.z;
+      pc[4 * j + 3] = x.w;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kOutPer; ++k) pc[k] = p0 + uint32_t(k) < st.n_faults ? st.popc[p0 + k] : 0u;
+  }
+}
+
 // Packed count of this thread's positions: representatives << kRepShift |
 // their signature bits.
-__device__ __forceinline__ uint64_t rep_count16(const DevState& st, uint32_t p0, uint32_t m) {
+__device__ __forceinline__ uint64_t rep_count16(uint32_t m, const uint32_t (&pc)[kOutPer]) {
   uint64_t v = uint64_t(__popc(m)) << kRepShift;
-  while (m) {
-    const uint32_t k = uint32_t(__builtin_ctz(m));
-    m &= m - 1;
-    v += st.popc[p0 + k];
-  }
+#pragma unroll
+  for (int k = 0; k < kOutPer; ++k) v += ((m >> k) & 1u) ? pc[k] : 0u;
   return v;
 }
 
@@ -1631,8 +1647,10 @@ __global__ __launch_bounds__(kBlock) void k_rep_list(DevState st, uint32_t ntile
   if (tile >= ntiles) return;
   auto FB = [&](uint32_t k) -> uint32_t { return bfb_lds ? s_bfb[k] : st.branch[k].fb; };
   const uint32_t p0 = tile * kTile + tid * kOutPer;
-  uint32_t m = rep_bits16(st, p0);
-  const uint64_t local = block_exclusive_scan64(rep_count16(st, p0, m), s);
+  const uint32_t m = rep_bits16(st, p0);
+  uint32_t pc[kOutPer];
+  weights16(st, p0, pc);
+  const uint64_t local = block_exclusive_scan64(rep_count16(m, pc), s);
   const uint64_t agg = s[kBlock / 64];
   const uint32_t nrep = uint32_t(agg >> kRepShift);
   const uint64_t nbits = agg & ((1ull << kRepShift) - 1);
@@ -1710,14 +1728,14 @@ __global__ __launch_bounds__(kBlock) void k_rep_list(DevState st, uint32_t ntile
       st.circ_eoff[k] = e + uint32_t(__popc(m & ((1u << (fb - p0)) - 1u)));
     }
   }
-  while (m) {
-    const uint32_t pos = p0 + uint32_t(__builtin_ctz(m));
-    m &= m - 1;
-    st.rep_pos[e] = pos;
-    st.edge_off32[e] = uint32_t(o);
-    o += st.popc[pos];
-    ++e;
-  }
+#pragma unroll
+  for (int k = 0; k < kOutPer; ++k)
+    if ((m >> k) & 1u) {
+      st.rep_pos[e] = p0 + uint32_t(k);
+      st.edge_off32[e] = uint32_t(o);
+      o += pc[k];
+      ++e;
+    }
   if (tile + 1 == ntiles && tid == 0) {
     const uint64_t U = e0 + uint64_t(nrep), NB = o0 + nbits;
     st.hdr->n_seg = uint32_t(U);
