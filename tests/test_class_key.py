@@ -157,3 +157,28 @@ def test_device_keys_cut_to_forced_bits(key_driver):
     finally:
         _gp.gp_debug_set_key_bits(key_driver.handle, 64)
     assert bits == 12
+
+
+@pytest.mark.gpu
+def test_batch_keys_salted_after_the_first_circuit():
+    """In a batch the first circuit's positions carry the plain FNV-1a keys of
+    its signatures; a later circuit's keys carry a per-circuit salt, so even an
+    identical circuit in the second slot gets other keys (classes are never
+    merged across circuits)."""
+    c = rotated_surface_code_memory(5, 5).text
+    say("batch of two identical d=5 circuits, key capture on")
+    d = Driver.from_batch([c, c])
+    try:
+        _gp.gp_debug_capture_keys(d.handle, True)
+        d.compile_batch([c, c])
+        keys, bits = _gp.gp_debug_class_keys(d.handle)
+    finally:
+        d.close()
+    res = oracle.run(c, keep_faults=True)
+    f0 = res.n_faults
+    assert len(keys) == 2 * f0
+    mask = np.uint64(M64 if bits >= 64 else (1 << bits) - 1)
+    want = np.sort(fnv1a64_words(signature_words(res)) & mask)
+    assert np.array_equal(np.sort(keys[:f0]), want)
+    assert not np.array_equal(np.sort(keys[f0:]), want)
+    assert len(np.intersect1d(keys[:f0], keys[f0:])) == 0
