@@ -212,10 +212,12 @@ def test_batch_bounds_errors():
             _gp.gp_edges_free(h)
 
 
-@pytest.mark.parametrize("d,n", [(3, 64), (5, 16)])
+@pytest.mark.parametrize("d,n", [(3, 64), (4, 32), (5, 16), (6, 8), (8, 4)])
 def test_concatenated_branches_batch(d, n):
     """Realised branches of the adaptive [[4,2,2]]-concatenated surface code
-    (uneven lengths), compiled as one batch, against the oracle per branch."""
+    (uneven lengths), compiled as one batch, against the oracle per branch;
+    the even outer distances are those of the paper's adaptive benchmark
+    (Table 3)."""
     from workloads import iceberg_surface_batch
     texts = [c.text for c in iceberg_surface_batch(d, n_branches=n, seed=100)]
     say("case concatenated batch", d, n)
