@@ -154,6 +154,8 @@ def main() -> int:
                     help="outer distances of the batched [[4,2,2]]-concatenated workload ('' skips it; "
                          "the paper's adaptive benchmark, Table 3, uses 4, 6, 8 and 10)")
     ap.add_argument("--batch-branches", type=int, default=256)
+    ap.add_argument("--table2-iters", type=int, default=1000,
+                    help="repeats per workload and level of the paper's Table 2 memory workloads (0 skips them)")
     ap.add_argument("--serve-distances", default="5,10",
                     help="outer distances of the served workload ('' skips it)")
     ap.add_argument("--serve-requests", type=int, default=1000)
@@ -260,6 +262,8 @@ def main() -> int:
 
     if args.configs:
         out["configs"] = config_table(args)
+    if args.table2_iters > 0:
+        out["paper_table2"] = paper_table2(args.table2_iters)
     if not args.no_grad:
         out["differentiation"] = bench_differentiation(get_driver)
     if args.batch_distances:
@@ -396,6 +400,52 @@ def config_table(args) -> list:
                      "device_hyperedges_per_s": U / (dev_ms * 1e-3),
                      "whole_path_ms": st, "whole_path_faults_per_s": F / (st["mean"] * 1e-3),
                      "whole_path_ms_per_round": st["mean"] / c.rounds})
+    return rows
+
+
+def paper_table2(iters: int) -> list:
+    """The paper's memory benchmark (Table 2) as workloads here: rotated surface
+    codes d = 3, 5, 7, 9 and the bivariate bicycle codes [[72,12,6]] and
+    [[144,12,12]], d rounds each, p = 1e-3 under the paper's noise preset, at
+    correlation levels 0, 1 and 2. Per workload and level: device stages
+    (tables resident, mean over back-to-back runs) and whole-path compiles
+    (mean, p50, p99), `iters` repeats each."""
+    from paper_2604_16613_amd import get_driver
+    from workloads import bivariate_bicycle_memory, paper_noise, rotated_surface_code_memory
+    noise = paper_noise(1e-3)
+    work = [(f"sc_d{d}_r{d} preset", rotated_surface_code_memory(d, d, p=1e-3, **noise)) for d in (3, 5, 7, 9)]
+    work += [(f"bb{2 * l * m}_r{r} preset", bivariate_bicycle_memory(rounds=r, l=l, m=m, **noise))
+             for l, m, r in ((6, 6, 6), (12, 6, 12))]
+    rows = []
+    for name, c in work:
+        print(f"table 2 workload {name}: {iters} repeats per level", file=sys.stderr, flush=True)
+        with get_driver(c.text) as drv:
+            for level in (0, 1, 2):
+                drv.set_correlation_level(level)
+                drv.lower(c.text, None)
+                for _ in range(10):
+                    drv.run()
+                drv.fetch()
+                info = drv.info()
+                drv.sync()
+                t0 = time.perf_counter()
+                for _ in range(iters):
+                    drv.run()
+                drv.sync()
+                dev_ms = (time.perf_counter() - t0) * 1e3 / iters
+                for _ in range(10):
+                    drv.compile_hypergraph(c.text)
+                lat = []
+                for _ in range(iters):
+                    t0 = time.perf_counter()
+                    drv.compile_hypergraph(c.text)
+                    lat.append((time.perf_counter() - t0) * 1e3)
+                F, U = info["n_faults"], info["n_edges"]
+                st = stats_ms(lat)
+                rows.append({"workload": name, "level": level, "faults": F, "hyperedges": U, "rounds": c.rounds,
+                             "device_ms_mean": dev_ms, "device_faults_per_s": F / (dev_ms * 1e-3),
+                             "whole_path_ms": st, "whole_path_ms_per_round": st["mean"] / c.rounds})
+            drv.set_correlation_level(2)
     return rows
 
 

@@ -42,7 +42,8 @@ def test_profiled_traffic_reads_the_byte_columns():
 @pytest.mark.gpu
 def test_one_json_line_with_the_contract_fields():
     cmd = [sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--steps", "3", "--warmup", "1", "--latency-iters", "2",
-           "--no-cpu-baseline", "--no-grad", "--no-autotune", "--batch-distances=", "--serve-distances=", "--configs="]
+           "--no-cpu-baseline", "--no-grad", "--no-autotune", "--batch-distances=", "--serve-distances=", "--configs=",
+           "--table2-iters", "3"]
     print("case bench contract", flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=240, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-2000:]
@@ -60,6 +61,10 @@ def test_one_json_line_with_the_contract_fields():
     assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
     assert abs(roof["frac"] - roof["achieved"] / roof["peak"]) < 1e-12
     assert 0 < j["stage2"]["frac_algorithmic"] < 1
+    t2 = j["paper_table2"]
+    assert len(t2) == 18 and {r["level"] for r in t2} == {0, 1, 2}
+    for r in t2:
+        assert r["faults"] > 0 and r["device_ms_mean"] > 0 and r["whole_path_ms"]["n"] == 3, r["workload"]
     g = j["graph_replay"]
     for mode in ("eager", "graph"):
         assert g[mode]["ms_per_step"] > 0 and g[mode]["single_run_ms_median"] > 0, mode

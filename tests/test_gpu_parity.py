@@ -69,10 +69,10 @@ def drv25():
     d.close()
 
 
-def check(drv, text, rates=None, label=""):
+def check(drv, text, rates=None, label="", level=2):
     say("case", label)
     hg = drv.compile_hypergraph(text, rates)
-    ref = oracle.run(text, rates=rates)
+    ref = oracle.run(text, rates=rates, level=level)
     return assert_parity(hg, ref, label)
 
 
@@ -306,6 +306,25 @@ def test_correlation_levels(drv25, level):
     with pytest.raises(GpError) as e:
         drv25.set_correlation_level(3)
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("level", [0, 1, 2])
+def test_paper_table2_workloads(drv25, level):
+    """The paper's memory benchmark (Table 2): rotated surface codes d = 3, 5, 7, 9
+    and the bivariate bicycle codes [[72,12,6]] and [[144,12,12]], d rounds each,
+    under its noise preset, at each correlation level."""
+    from workloads import paper_noise
+    noise = paper_noise(1e-3)
+    drv25.set_correlation_level(level)
+    try:
+        for d in (3, 5, 7, 9):
+            c = rotated_surface_code_memory(d, d, p=1e-3, **noise)
+            check(drv25, c.text, label=f"level {level} sc{d} preset", level=level)
+        for l, m, r in ((6, 6, 6), (12, 6, 12)):
+            c = bivariate_bicycle_memory(rounds=r, l=l, m=m, **noise)
+            check(drv25, c.text, label=f"level {level} bb{2 * l * m} preset", level=level)
+    finally:
+        drv25.set_correlation_level(2)
 
 
 def test_graph_replays_match_eager_launches(drv25):

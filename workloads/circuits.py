@@ -518,7 +518,9 @@ BB_DEPTH8_SLOTS = {"A": (0, 1, 5), "B": (2, 3, 4), "BT": (2, 3, 4), "AT": (5, 6,
 
 
 def bivariate_bicycle_memory(rounds: int = 12, p: float = 1e-3, l: int = 12, m: int = 6,
-                             schedule: str = "depth8") -> Circuit:
+                             schedule: str = "depth8", p1: Optional[float] = None, p2: Optional[float] = None,
+                             pm: Optional[float] = None, pr: Optional[float] = None, pi: float = 0.0,
+                             reset_noise: str = "DEPOLARIZE1") -> Circuit:
     """Z-basis memory of the bivariate bicycle code (default [[144,12,12]]).
 
     Qubits: L data 0..lm-1, R data lm..2lm-1, X ancillas, then Z ancillas.
@@ -530,9 +532,20 @@ def bivariate_bicycle_memory(rounds: int = 12, p: float = 1e-3, l: int = 12, m: 
     [B^T|A^T] onto the Z ancillas. Noise: DEPOLARIZE1 after every one-qubit
     gate and reset, DEPOLARIZE2 after every CX, a flip before every
     measurement (Z_ERROR before an X-basis one, X_ERROR before a Z-basis one).
+    The rates default to p; p1 (one-qubit gates), p2 (CX), pm (measurements),
+    pr (resets) and pi (DEPOLARIZE1 on the qubits idle in a gate or
+    measurement layer, when pi > 0) set them apart, as in the paper's preset
+    (`paper_noise`). reset_noise "X_ERROR" makes a reset fail by a flip in its
+    own basis (X_ERROR after a Z-basis reset, Z_ERROR after an X-basis one).
     """
     if schedule not in ("depth8", "sequential"):
         raise ValueError(f"unknown schedule {schedule!r}")
+    if reset_noise not in ("DEPOLARIZE1", "X_ERROR"):
+        raise ValueError(f"unknown reset noise {reset_noise!r}")
+    p1 = p if p1 is None else p1
+    p2 = p if p2 is None else p2
+    pm = p if pm is None else pm
+    pr = p if pr is None else pr
     nd = l * m
     a_terms, b_terms = bb_matrices(l, m)
     L = list(range(nd))
@@ -544,6 +557,20 @@ def bivariate_bicycle_memory(rounds: int = 12, p: float = 1e-3, l: int = 12, m: 
     allq = data + anc
     b = _Builder()
 
+    def reset_noise_on(z_basis, x_basis):
+        # after resets: one DEPOLARIZE1 over both sets, or a flip in each set's basis
+        if reset_noise == "DEPOLARIZE1":
+            b.noise1("DEPOLARIZE1", pr, list(z_basis) + list(x_basis))
+        else:
+            if z_basis:
+                b.noise1("X_ERROR", pr, z_basis)
+            if x_basis:
+                b.noise1("Z_ERROR", pr, x_basis)
+
+    def idle(qs):
+        if pi > 0 and qs:
+            b.noise1("DEPOLARIZE1", pi, qs)
+
     def x_pairs(blk, t):   # X check i -> its data qubit of term t
         return [(xa[i], blk[int(np.nonzero(t[i])[0][0])]) for i in range(nd)]
 
@@ -554,7 +581,10 @@ def bivariate_bicycle_memory(rounds: int = 12, p: float = 1e-3, l: int = 12, m: 
     if schedule == "depth8":
         b.gate("R", data + za)
         b.gate("RX", xa)
-        b.noise1("DEPOLARIZE1", p, allq)
+        if reset_noise == "DEPOLARIZE1":
+            b.noise1("DEPOLARIZE1", pr, allq)
+        else:
+            reset_noise_on(data + za, xa)
         b.tick()
         slots = [[] for _ in range(7)]
         for k in range(3):
@@ -564,45 +594,58 @@ def bivariate_bicycle_memory(rounds: int = 12, p: float = 1e-3, l: int = 12, m: 
             slots[BB_DEPTH8_SLOTS["AT"][k]] += z_pairs(R, a_terms[k])
     else:
         b.gate("R", allq)
-        b.noise1("DEPOLARIZE1", p, allq)
+        reset_noise_on(allq, [])
         b.tick()
     last: Dict[int, int] = {}
     for rnd in range(rounds):
         if schedule == "depth8":
             for pairs in slots:
                 b.pairs("CX", pairs)
-                b.noise2(p, pairs)
+                b.noise2(p2, pairs)
+                busy = {q for pr_ in pairs for q in pr_}
+                idle([q for q in allq if q not in busy])
                 b.tick()
-            b.noise1("Z_ERROR", p, xa)
-            b.noise1("X_ERROR", p, za)
+            b.noise1("Z_ERROR", pm, xa)
+            b.noise1("X_ERROR", pm, za)
             mx = b.measure("MRX", xa)
             mz = b.measure("MR", za)
             ms = mx + mz
-            b.noise1("DEPOLARIZE1", p, anc)
+            if reset_noise == "DEPOLARIZE1":
+                b.noise1("DEPOLARIZE1", pr, anc)
+            else:
+                reset_noise_on(za, xa)
+            idle(data)
         else:
             b.gate("H", xa)
-            b.noise1("DEPOLARIZE1", p, xa)
+            b.noise1("DEPOLARIZE1", p1, xa)
+            idle([q for q in allq if q not in set(xa)])
             b.tick()
             # X checks: row i of A (on L) and of B (on R).
             for blk, terms in ((L, a_terms), (R, b_terms)):
                 for t in terms:
                     pairs = x_pairs(blk, t)
                     b.pairs("CX", pairs)
-                    b.noise2(p, pairs)
+                    b.noise2(p2, pairs)
+                    busy = {q for pr_ in pairs for q in pr_}
+                    idle([q for q in allq if q not in busy])
                     b.tick()
             b.gate("H", xa)
-            b.noise1("DEPOLARIZE1", p, xa)
+            b.noise1("DEPOLARIZE1", p1, xa)
+            idle([q for q in allq if q not in set(xa)])
             b.tick()
             # Z checks: row i of B^T (on L) and of A^T (on R).
             for blk, terms in ((L, b_terms), (R, a_terms)):
                 for t in terms:
                     pairs = z_pairs(blk, t)
                     b.pairs("CX", pairs)
-                    b.noise2(p, pairs)
+                    b.noise2(p2, pairs)
+                    busy = {q for pr_ in pairs for q in pr_}
+                    idle([q for q in allq if q not in busy])
                     b.tick()
-            b.noise1("X_ERROR", p, anc)
+            b.noise1("X_ERROR", pm, anc)
             ms = b.measure("MR", anc)
-            b.noise1("DEPOLARIZE1", p, anc)
+            reset_noise_on(anc, [])
+            idle(data)
         cur = dict(zip(anc, ms))
         if rnd == 0:
             for a in za:
@@ -612,7 +655,7 @@ def bivariate_bicycle_memory(rounds: int = 12, p: float = 1e-3, l: int = 12, m: 
                 b.detector([cur[a], last[a]])
         last = cur
         b.tick()
-    b.noise1("X_ERROR", p, data)
+    b.noise1("X_ERROR", pm, data)
     md = b.measure("M", data)
     hx, hz = bb_check_matrices(l, m)
     for i, a in enumerate(za):
