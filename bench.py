@@ -405,8 +405,8 @@ def config_table(args) -> list:
 
 def paper_table2(iters: int) -> list:
     """The paper's memory benchmark (Table 2) as workloads here: rotated surface
-    codes d = 3, 5, 7, 9 and the bivariate bicycle codes [[72,12,6]] and
-    [[144,12,12]], d rounds each, p = 1e-3 under the paper's noise preset, at
+    codes d = 3, 5, 7, 9 and the bivariate bicycle codes [[72,12,6]],
+    [[108,8,10]] and [[144,12,12]], d rounds each, p = 1e-3 under the paper's noise preset, at
     correlation levels 0, 1 and 2. Per workload and level: device stages
     (tables resident, mean over back-to-back runs) and whole-path compiles
     (mean, p50, p99), `iters` repeats each."""
@@ -415,7 +415,7 @@ def paper_table2(iters: int) -> list:
     noise = paper_noise(1e-3)
     work = [(f"sc_d{d}_r{d} preset", rotated_surface_code_memory(d, d, p=1e-3, **noise)) for d in (3, 5, 7, 9)]
     work += [(f"bb{2 * l * m}_r{r} preset", bivariate_bicycle_memory(rounds=r, l=l, m=m, **noise))
-             for l, m, r in ((6, 6, 6), (12, 6, 12))]
+             for l, m, r in ((6, 6, 6), (9, 6, 10), (12, 6, 12))]
     rows = []
     for name, c in work:
         print(f"table 2 workload {name}: {iters} repeats per level", file=sys.stderr, flush=True)

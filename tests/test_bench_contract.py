@@ -62,7 +62,7 @@ def test_one_json_line_with_the_contract_fields():
     assert abs(roof["frac"] - roof["achieved"] / roof["peak"]) < 1e-12
     assert 0 < j["stage2"]["frac_algorithmic"] < 1
     t2 = j["paper_table2"]
-    assert len(t2) == 18 and {r["level"] for r in t2} == {0, 1, 2}
+    assert len(t2) == 21 and {r["level"] for r in t2} == {0, 1, 2}
     for r in t2:
         assert r["faults"] > 0 and r["device_ms_mean"] > 0 and r["whole_path_ms"]["n"] == 3, r["workload"]
     g = j["graph_replay"]

@@ -311,8 +311,8 @@ def test_correlation_levels(drv25, level):
 @pytest.mark.parametrize("level", [0, 1, 2])
 def test_paper_table2_workloads(drv25, level):
     """The paper's memory benchmark (Table 2): rotated surface codes d = 3, 5, 7, 9
-    and the bivariate bicycle codes [[72,12,6]] and [[144,12,12]], d rounds each,
-    under its noise preset, at each correlation level."""
+    and the bivariate bicycle codes [[72,12,6]], [[108,8,10]] and [[144,12,12]],
+    d rounds each, under its noise preset, at each correlation level."""
     from workloads import paper_noise
     noise = paper_noise(1e-3)
     drv25.set_correlation_level(level)
@@ -320,7 +320,7 @@ def test_paper_table2_workloads(drv25, level):
         for d in (3, 5, 7, 9):
             c = rotated_surface_code_memory(d, d, p=1e-3, **noise)
             check(drv25, c.text, label=f"level {level} sc{d} preset", level=level)
-        for l, m, r in ((6, 6, 6), (12, 6, 12)):
+        for l, m, r in ((6, 6, 6), (9, 6, 10), (12, 6, 12)):
             c = bivariate_bicycle_memory(rounds=r, l=l, m=m, **noise)
             check(drv25, c.text, label=f"level {level} bb{2 * l * m} preset", level=level)
     finally:

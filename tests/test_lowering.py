@@ -44,10 +44,10 @@ def test_bivariate_bicycle_short():
 
 
 def test_bivariate_bicycle_paper_preset():
-    """[[72,12,6]] and [[144,12,12]] under the paper's noise preset (idle noise,
+    """[[72,12,6]], [[108,8,10]] and [[144,12,12]] under the paper's noise preset (idle noise,
     resets that fail by a flip in their basis), both schedules."""
     from workloads import paper_noise
-    for l, m, sched in ((6, 6, "depth8"), (12, 6, "depth8"), (6, 6, "sequential")):
+    for l, m, sched in ((6, 6, "depth8"), (9, 6, "depth8"), (12, 6, "depth8"), (6, 6, "sequential")):
         st = compare(bivariate_bicycle_memory(rounds=2, l=l, m=m, schedule=sched, **paper_noise(1e-3)).text)
         assert st["qubits"] == 4 * l * m
 
