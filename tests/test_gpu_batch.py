@@ -227,6 +227,24 @@ def test_concatenated_branches_batch(d, n):
             assert_same(hg, oracle.run(t), f"d{d} branch {k}")
 
 
+@pytest.mark.parametrize("level", [0, 1])
+def test_concatenated_batch_at_correlation_levels(level):
+    """The adaptive benchmark at the lower correlation levels (Table 3 reports
+    all three): a batch of branches at outer distance 4 keeps, per branch, the
+    oracle's classes at that level, and equals the branch compiled alone at that
+    level."""
+    from workloads import iceberg_surface_batch
+    texts = [c.text for c in iceberg_surface_batch(4, n_branches=12, seed=300)]
+    say("case concatenated batch at level", level)
+    with Driver.from_batch(texts) as drv:
+        drv.set_correlation_level(level)
+        got = drv.compile_batch(texts)
+        for k in (0, 5, 11):
+            assert_same(got[k], oracle.run(texts[k], level=level), f"level {level} branch {k} vs oracle")
+        for k, t in enumerate(texts):
+            assert_same(got[k], drv.compile_hypergraph(t), f"level {level} branch {k} vs single", exact=True)
+
+
 def test_concatenated_d10_batch_samples():
     """Outer distance 10: a batch of 12 branches; every branch equals its own
     compile, two of them are checked against the oracle."""
