@@ -1962,10 +1962,14 @@ uint32_t class_key_bits(uint64_t n, uint32_t cap) {
 
 size_t hash_lds_bytes(uint32_t w) { return (size_t(w) + 1) * 8 + size_t(w) * (8 + 8 + 8 * kHashBmw + 4); }
 
+// LDS of one sweep work-group, in the order k_sweep lays it out: the frame
+// (2n words) and the two pending-leaf buffers (2n words), the injection
+// words, then the 32-bit tables (op windows, layer / fault / bitmap offsets,
+// injection layers, qubits and group ends, the window table).
 template <int kBlk>
 static size_t sweep_lds_shape(uint32_t n_qubits) {
   using S = SweepShape<kBlk>;
-  return (size_t(5) * n_qubits + S::kInj) * sizeof(uint64_t) +
+  return (size_t(4) * n_qubits + S::kInj) * sizeof(uint64_t) +
          (size_t(2) * S::kWin + 3 * S::kLofs + 2 + 3 * S::kInj + 3 * S::kWinTab) * sizeof(uint32_t);
 }
 

@@ -436,17 +436,17 @@ def test_fetch_into_caller_arrays(drv25):
 def test_widest_frame_the_lds_holds():
     """The sweep keeps a column's whole qubit frame in LDS. On gfx950 (160 KB per
     work-group, 1 KB kept for static arrays) the 1024-thread sweep holds
-    2,227 qubits: a circuit that reaches qubit 2,226 compiles and equals the
-    oracle, one that reaches qubit 2,227 fails with GP_E_BOUNDS (-4) and
-    leaves the driver usable."""
+    2,783 qubits (32 bytes each next to 72 KB of tables): a circuit that
+    reaches qubit 2,782 compiles and equals the oracle, one that reaches qubit
+    2,783 fails with GP_E_BOUNDS (-4) and leaves the driver usable."""
     def far(q):
         return (f"R 0 {q}\nX_ERROR(0.1) 0 {q}\nCX 0 {q}\nDEPOLARIZE2(0.01) 0 {q}\nM 0 {q}\n"
                 "DETECTOR rec[-1]\nDETECTOR rec[-2]\nOBSERVABLE_INCLUDE(0) rec[-1]\n")
-    fits, over = far(2226), far(2227)
+    fits, over = far(2782), far(2783)
     say("case widest frame")
     with Driver(merged_bounds([fits, over])) as d:
-        assert_parity(d.compile_hypergraph(fits), oracle.run(fits), "2,227 qubits")
+        assert_parity(d.compile_hypergraph(fits), oracle.run(fits), "2,783 qubits")
         with pytest.raises(GpError) as e:
             d.compile_hypergraph(over)
         assert e.value.code == -4 and "LDS" in str(e.value)
-        assert_parity(d.compile_hypergraph(fits), oracle.run(fits), "2,227 qubits again")
+        assert_parity(d.compile_hypergraph(fits), oracle.run(fits), "2,783 qubits again")
