@@ -909,9 +909,14 @@ int finish_lowering(Sched& S, const double* rates, size_t n_rates, uint32_t swee
   }
 
   // ---- op windows (a layer has at most n ops; the driver rejects circuits
-  // whose largest layer exceeds a window)
+  // whose largest layer exceeds a window). A circuit of a batch (fewer sweep
+  // slots than the device has) with at most kSmallWinOps qubits gets windows
+  // the 256-thread sweep holds; a circuit lowered alone runs on the
+  // 1024-thread sweep, whose larger windows mean fewer window swaps on the
+  // layer chain.
   lw.layer_win.assign(L, 0);
-  const uint32_t win_ops = lw.n_qubits <= kSmallWinOps ? kSmallWinOps : kSweepWinOps;
+  const uint32_t win_ops =
+      (lw.n_qubits <= kSmallWinOps && sweep_slots < kSweepSlots) ? kSmallWinOps : kSweepWinOps;
   for (int32_t hi = int32_t(L) - 1; hi >= 0;) {
     int32_t lo = hi;
     while (lo > 0 && lw.layer_off[hi + 1] - lw.layer_off[lo - 1] <= win_ops) lo--;
