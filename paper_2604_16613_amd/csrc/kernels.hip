@@ -504,17 +504,21 @@ __global__ __launch_bounds__(kBlk) void k_sweep(DevState st) {
     }
   };
   scatter(top);
-  // the next window (layers below wlo) into registers, if the item needs it
+  // the next window (layers below wlo) into registers, if the item needs it;
+  // its op count, first op and lowest layer stay in registers too, so that
+  // the swap reads no table entry before it stores the window
   uint32_t pre[kPreN];
-  uint32_t nbase = 0;
+  uint32_t nbase = 0, ncnt = 0;
+  int nwlo = 0;
   auto prefetch = [&]() {
     const bool need = wlo - 1 >= blo;
-    const uint32_t cnt = need ? WCN(wid + 1) : 0u;
+    ncnt = need ? WCN(wid + 1) : 0u;
     nbase = need ? WOB(wid + 1) : 0u;
+    nwlo = need ? int(WLO(wid + 1)) : 0;
 #pragma unroll
     for (int k = 0; k < kPreN; ++k) {
       const uint32_t i = tid + k * kBlk;
-      pre[k] = i < cnt ? st.ops32[nbase + i] : 0u;
+      pre[k] = i < ncnt ? st.ops32[nbase + i] : 0u;
     }
   };
   prefetch();
@@ -550,17 +554,16 @@ __global__ __launch_bounds__(kBlk) void k_sweep(DevState st) {
     if (t == wlo && t - 1 >= blo) {
       // the prefetched window becomes current (the other buffer is no longer
       // read), and the window after it is fetched into registers
-      const uint32_t cnt = WCN(wid + 1);
       uint32_t* nb = opbuf + (cur ^ 1) * kWinN;
 #pragma unroll
       for (int k = 0; k < kPreN; ++k) {
         const uint32_t i = tid + k * kBlk;
-        if (i < cnt) nb[i] = pre[k];
+        if (i < ncnt) nb[i] = pre[k];
       }
       cur ^= 1;
       wid++;
       o_base = nbase;
-      wlo = int(WLO(wid));
+      wlo = nwlo;
       prefetch();
     }
   };
