@@ -58,7 +58,7 @@ constexpr uint32_t kBigSegment = 64;   // classes with more faults reduce in a w
 constexpr uint32_t kLbAgg = 1u << 30;  // look-back status: tile aggregate published
 constexpr uint32_t kLbPre = 2u << 30;  // look-back status: inclusive prefix published
 constexpr uint32_t kLbMask = (1u << 30) - 1;
-constexpr int kLookWin = 16;            // look-back: predecessor tiles read per round
+constexpr int kLookWin = 8;             // look-back: predecessor tiles read per round
 constexpr uint32_t kHashBmw = 5;        // bitmap words 256 consecutive positions span at most
 
 // Barrier that orders LDS only: global loads issued before it (prefetches)
@@ -1046,8 +1046,9 @@ __global__ __launch_bounds__(kSortBlock) void k_onesweep(DevState st, uint32_t p
     // thread d: counts of digit d in the tiles before this one, kLookWin at a
     // time, until a tile that already published its inclusive prefix. Every
     // tile runs at once, so the inclusive prefixes spread from tile 0 while
-    // all tiles walk back; a wide window keeps the number of (cross-XCD
-    // latency) rounds small.
+    // all tiles walk back. Each round's loads are issued together and waited
+    // for together: a window of 8 balances their cost against the number of
+    // (cross-XCD latency) rounds.
     const uint32_t d = tid;
     uint32_t excl = 0;
     if (tile > 0) {
