@@ -180,8 +180,8 @@ __device__ __forceinline__ bool grouping_aborted(const DevHeader* hdr) {
 // the Pauli codes each channel kind keeps at each correlation level
 __constant__ KeptCodes c_kept = make_kept_codes();
 
-// A block takes 256 consecutive channels: one thread per channel computes the
-// per-fault probability and the qubits and marks its faults in an LDS map
+// A block takes kPrepChan consecutive channels: one thread per channel computes
+// the per-fault probability and the qubits and marks its faults in an LDS map
 // (fault -> channel), then the block writes the faults of those channels
 // (consecutive positions) one thread per fault, coalesced.
 constexpr uint32_t kMaxChanFaults = sizeof(KeptCodes::code[0][0]);  // faults of one channel at most
@@ -189,16 +189,21 @@ constexpr uint32_t kMaxChanFaults = sizeof(KeptCodes::code[0][0]);  // faults of
 // output tiles of a compile of n faults (at least one)
 __device__ __forceinline__ uint32_t ntiles_out(uint32_t n) { return n ? (n + kTile - 1) / kTile : 1u; }
 
+// Channels per block: small blocks spread a compile's channels over several
+// work-groups per CU (one 256-channel block per CU wrote the records of about
+// 3,800 faults with 4 waves).
+constexpr uint32_t kPrepChan = 64;
+
 __global__ __launch_bounds__(kBlock) void k_prepare(DevState st) {
-  __shared__ double s_p[kBlock];
-  __shared__ uint32_t s_q[kBlock];          // qubit a | qubit b << 14 | kind << 28
-  __shared__ uint32_t s_off[kBlock + 1];    // first fault of each channel, from the block's first
-  __shared__ uint8_t s_ch[kBlock * kMaxChanFaults];  // channel (in the block) of each fault
+  __shared__ double s_p[kPrepChan];
+  __shared__ uint32_t s_q[kPrepChan];          // qubit a | qubit b << 14 | kind << 28
+  __shared__ uint32_t s_off[kPrepChan + 1];    // first fault of each channel, from the block's first
+  __shared__ uint8_t s_ch[kPrepChan * kMaxChanFaults];  // channel (in the block) of each fault
   const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t stride = gridDim.x * blockDim.x;
-  const uint32_t n_blk = (st.n_chan + kBlock - 1) / kBlock;
+  const uint32_t n_blk = (st.n_chan + kPrepChan - 1) / kPrepChan;
   for (uint32_t cb = blockIdx.x; cb < n_blk; cb += gridDim.x) {
-    const uint32_t c0 = cb * kBlock, nc = min(uint32_t(kBlock), st.n_chan - c0);
+    const uint32_t c0 = cb * kPrepChan, nc = min(kPrepChan, st.n_chan - c0);
     const uint32_t f_lo = st.chan_foff[c0];
     if (threadIdx.x < nc) {
       const uint32_t c = c0 + threadIdx.x;
@@ -2067,8 +2072,10 @@ hipError_t enqueue_compile(DevState& st_io, hipStream_t stream, const LaunchHook
                    ? 1u
                    : 0u;
   {
-    const uint32_t m = st.n_chan > st.n_pass * ntiles * 256 ? st.n_chan : st.n_pass * ntiles * 256;
-    uint32_t g = cdiv(m ? m : 1, kBlock);
+    // a block per kPrepChan channels, or per kBlock look-back words to clear
+    const uint32_t g_chan = cdiv(st.n_chan ? st.n_chan : 1, kPrepChan);
+    const uint32_t g_clear = cdiv(st.n_pass * ntiles * 256, kBlock);
+    uint32_t g = g_chan > g_clear ? g_chan : g_clear;
     if (g > 4096) g = 4096;
     GP_LAUNCH(K_PREPARE, k_prepare<<<g, kBlock, 0, stream>>>(st));
   }
