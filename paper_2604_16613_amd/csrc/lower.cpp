@@ -2,11 +2,13 @@
 #include "lower.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <memory>
 #include <string>
 #include <thread>
 
@@ -203,10 +205,12 @@ void tokenize_text(const char* p, const char* end, TokChunk& c) {
   }
 }
 
-// Whole-line chunks of about equal size (at most kMaxTokThreads; one below
-// kTokChunkMin bytes of text per chunk).
+// Whole-line chunks of about equal size (at most kMaxTokChunks; one below
+// kTokChunkMin bytes of text per chunk), tokenized on at most kMaxTokThreads
+// threads, the scheduling thread included.
 constexpr size_t kMaxTokThreads = 8;
-constexpr size_t kTokChunkMin = 1 << 17;
+constexpr size_t kMaxTokChunks = 64;
+constexpr size_t kTokChunkMin = 1 << 15;
 // The channel tables are built on up to this many threads, one per this many
 // channels at least.
 constexpr size_t kMaxChanThreads = 4;
@@ -385,37 +389,62 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
   S.meas_layer.reserve(len / 8);
   S.meas_qubit.reserve(len / 8);
 
-  // tokenize whole-line chunks in parallel, then schedule (ASAP layers,
-  // measurement records, channels) in program order
-  std::vector<TokChunk> chunks;
-  {
-    const size_t T = std::max<size_t>(1, std::min(kMaxTokThreads, len / kTokChunkMin));
-    std::vector<const char*> cut(T + 1, text + len);
-    cut[0] = text;
-    for (size_t k = 1; k < T; k++) {
-      const char* c = text + len * k / T;
-      if (c < cut[k - 1]) c = cut[k - 1];
-      const char* nl = static_cast<const char*>(std::memchr(c, '\n', size_t(text + len - c)));
-      cut[k] = nl ? nl + 1 : text + len;
-    }
-    chunks.resize(T);
-    if (T == 1) {
-      tokenize(cut[0], cut[1], chunks[0]);
-    } else {
-      std::vector<std::thread> pool;
-      for (size_t k = 1; k < T; k++) {
-        try {
-          pool.emplace_back(tokenize, cut[k], cut[k + 1], std::ref(chunks[k]));
-        } catch (...) {
-          tokenize(cut[k], cut[k + 1], chunks[k]);  // could not start a thread: tokenize here
-        }
-      }
-      tokenize(cut[0], cut[1], chunks[0]);
+  // Tokenize whole-line chunks on up to kMaxTokThreads threads while this
+  // thread schedules them (ASAP layers, measurement records, channels) in
+  // program order: chunks are claimed in order from one counter, a chunk is
+  // scheduled as soon as it is tokenized, and this thread tokenizes the next
+  // unclaimed chunk itself while the one it needs is still being tokenized.
+  const size_t n_chunks = std::max<size_t>(1, std::min(kMaxTokChunks, len / kTokChunkMin));
+  std::vector<const char*> cut(n_chunks + 1, text + len);
+  cut[0] = text;
+  for (size_t k = 1; k < n_chunks; k++) {
+    const char* c = text + len * k / n_chunks;
+    if (c < cut[k - 1]) c = cut[k - 1];
+    const char* nl = static_cast<const char*>(std::memchr(c, '\n', size_t(text + len - c)));
+    cut[k] = nl ? nl + 1 : text + len;
+  }
+  std::vector<TokChunk> chunks(n_chunks);
+  std::unique_ptr<std::atomic<uint8_t>[]> ready(new std::atomic<uint8_t>[n_chunks]);
+  for (size_t k = 0; k < n_chunks; k++) ready[k].store(0, std::memory_order_relaxed);
+  std::atomic<size_t> next_chunk{0};
+  std::atomic<bool> stop{false};
+  // tokenize the next unclaimed chunk; false once none is left or the
+  // schedule has stopped on an error
+  auto claim = [&]() -> bool {
+    if (stop.load(std::memory_order_relaxed)) return false;
+    const size_t k = next_chunk.fetch_add(1, std::memory_order_relaxed);
+    if (k >= n_chunks) return false;
+    tokenize(cut[k], cut[k + 1], chunks[k]);
+    ready[k].store(1, std::memory_order_release);
+    return true;
+  };
+  std::vector<std::thread> pool;
+  // joins the tokenizer threads on every return below, before the chunks
+  // they write go away
+  struct Joiner {
+    std::vector<std::thread>& pool;
+    std::atomic<bool>& stop;
+    ~Joiner() {
+      stop.store(true, std::memory_order_relaxed);
       for (std::thread& th : pool) th.join();
+    }
+  } joiner{pool, stop};
+  const size_t n_workers = std::min(kMaxTokThreads - 1, n_chunks - 1);
+  for (size_t w = 0; w < n_workers; w++) {
+    try {
+      pool.emplace_back([&claim] {
+        while (claim()) {
+        }
+      });
+    } catch (...) {
+      break;  // could not start a thread: this thread claims the rest itself
     }
   }
   uint32_t line_base = 0;
-  for (const TokChunk& ck : chunks) {
+  for (size_t ci = 0; ci < n_chunks; ci++) {
+    while (!ready[ci].load(std::memory_order_acquire))
+      if (!claim()) std::this_thread::yield();
+    const TokChunk& ck = chunks[ci];
     for (const Tok& t : ck.toks) {
       const Gate* g = t.g;
       const int line = int(line_base + t.line);

@@ -101,8 +101,9 @@ def test_observable_cut_does_not_change_signatures(cost):
 
 
 def test_text_split_across_tokenizer_threads():
-    """A circuit text long enough to be tokenized in four chunks (0.53 MB,
-    d = 17) replays to the oracle's signatures."""
+    """A circuit text long enough to be tokenized in many chunks on several
+    threads while the first chunks are scheduled (0.53 MB, d = 17) replays to
+    the oracle's signatures."""
     c = rotated_surface_code_memory(17, 17)
     assert len(c.text) > 4 * (1 << 17)
     compare(c.text)
