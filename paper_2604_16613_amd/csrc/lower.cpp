@@ -206,9 +206,12 @@ void tokenize_text(const char* p, const char* end, TokChunk& c) {
 }
 
 // Whole-line chunks of about equal size (at most kMaxTokChunks; one below
-// kTokChunkMin bytes of text per chunk), tokenized on at most kMaxTokThreads
-// threads, the scheduling thread included.
+// kTokChunkMin bytes of text per chunk), tokenized on one thread per
+// kTokThreadMin bytes of text, at most kMaxTokThreads, the scheduling thread
+// included (texts lowered side by side, as a batch's or a server's, are
+// mostly below that size and so start no threads of their own).
 constexpr size_t kMaxTokThreads = 8;
+constexpr size_t kTokThreadMin = 1 << 17;
 constexpr size_t kMaxTokChunks = 64;
 constexpr size_t kTokChunkMin = 1 << 15;
 // The channel tables are built on up to this many threads, one per this many
@@ -429,7 +432,7 @@ int lower_circuit(const char* text, size_t len, const double* rates, size_t n_ra
       for (std::thread& th : pool) th.join();
     }
   } joiner{pool, stop};
-  const size_t n_workers = std::min(kMaxTokThreads - 1, n_chunks - 1);
+  const size_t n_workers = std::min(std::min(kMaxTokThreads, std::max<size_t>(1, len / kTokThreadMin)), n_chunks) - 1;
   for (size_t w = 0; w < n_workers; w++) {
     try {
       pool.emplace_back([&claim] {
