@@ -802,42 +802,66 @@ int finish_lowering(Sched& S, const double* rates, size_t n_rates, uint32_t swee
   auto injection_phase = [&]() {
     {
       const std::vector<uint32_t>& meas_qubit = S.meas_qubit;
-      using Inj = InjEntry;
-      std::vector<Inj> inj;
-      for (uint32_t m = 0; m < n_meas; m++) {
-        for (uint32_t k = lw.leaf_off[m]; k < lw.leaf_off[m + 1]; k++) {
-          const uint32_t bit = lw.leaf_bits[k];
-          const uint32_t w = bit >> 6;
-          if (!inj.empty() && inj.back().m == m && inj.back().w == w) {
-            inj.back().word |= 1ull << (bit & 63);
-          } else {
-            inj.push_back(Inj{w, lw.meas_layer[m], meas_qubit[m], m, 1ull << (bit & 63)});
-          }
+      // one entry per (measurement, column) that the measurement's leaves
+      // hit; a measurement's leaf bits ascend, so those of one column are
+      // adjacent. Counted per column, then placed straight into the tables.
+      lw.inj_off.assign(size_t(lw.w) + 1, 0);
+      for (uint32_t m = 0; m < n_meas; m++)
+        for (uint32_t k = lw.leaf_off[m]; k < lw.leaf_off[m + 1]; k++)
+          if (k == lw.leaf_off[m] || (lw.leaf_bits[k] >> 6) != (lw.leaf_bits[k - 1] >> 6))
+            lw.inj_off[(lw.leaf_bits[k] >> 6) + 1]++;
+      for (uint32_t w = 0; w < lw.w; w++) lw.inj_off[w + 1] += lw.inj_off[w];
+      const size_t n_inj = lw.inj_off[lw.w];
+      lw.inj_layer.resize(n_inj);
+      lw.inj_qubit.resize(n_inj);
+      lw.inj_word.resize(n_inj);
+      // placed in descending measurement order, which lists a column top
+      // layer first wherever its measurements come in layer order
+      std::vector<uint32_t> fill(lw.inj_off.begin(), lw.inj_off.end() - 1);
+      for (uint32_t m = n_meas; m-- > 0;) {
+        for (uint32_t k = lw.leaf_off[m], e = lw.leaf_off[m + 1]; k < e;) {
+          const uint32_t w = lw.leaf_bits[k] >> 6;
+          uint64_t word = 0;
+          for (; k < e && (lw.leaf_bits[k] >> 6) == w; k++) word |= 1ull << (lw.leaf_bits[k] & 63);
+          const uint32_t pos = fill[w]++;
+          lw.inj_layer[pos] = lw.meas_layer[m];
+          lw.inj_qubit[pos] = meas_qubit[m];
+          lw.inj_word[pos] = word;
         }
       }
-      // by column (a stable counting sort), then by layer, top first, within
-      // each column (stable: equal layers keep measurement order)
-      lw.inj_off.assign(size_t(lw.w) + 1, 0);
-      for (const Inj& e : inj) lw.inj_off[e.w + 1]++;
-      for (uint32_t w = 0; w < lw.w; w++) lw.inj_off[w + 1] += lw.inj_off[w];
-      {
-        std::vector<Inj> by_col(inj.size());
-        std::vector<uint32_t> fill(lw.inj_off.begin(), lw.inj_off.end() - 1);
-        for (const Inj& e : inj) by_col[fill[e.w]++] = e;
-        for (uint32_t w = 0; w < lw.w; w++)
-          std::stable_sort(by_col.begin() + lw.inj_off[w], by_col.begin() + lw.inj_off[w + 1],
-                           [](const Inj& x, const Inj& y) { return x.layer > y.layer; });
-        inj.swap(by_col);
+      // within each column: top layer first, the entries of one layer in
+      // measurement order (a stable sort by layer where the column is not in
+      // layer order already, then each run of one layer reversed)
+      std::vector<uint32_t> perm;
+      std::vector<uint32_t> tmp32;
+      std::vector<uint64_t> tmp64;
+      for (uint32_t w = 0; w < lw.w; w++) {
+        const uint32_t a = lw.inj_off[w], e = lw.inj_off[w + 1];
+        uint32_t* layer = lw.inj_layer.data();
+        if (!std::is_sorted(layer + a, layer + e, [](uint32_t x, uint32_t y) { return x > y; })) {
+          perm.resize(e - a);
+          for (uint32_t i = 0; i < e - a; i++) perm[i] = a + i;
+          std::stable_sort(perm.begin(), perm.end(), [&](uint32_t x, uint32_t y) { return layer[x] > layer[y]; });
+          auto gather32 = [&](std::vector<uint32_t>& v) {
+            tmp32.resize(e - a);
+            for (uint32_t i = 0; i < e - a; i++) tmp32[i] = v[perm[i]];
+            std::copy(tmp32.begin(), tmp32.end(), v.begin() + a);
+          };
+          gather32(lw.inj_layer);
+          gather32(lw.inj_qubit);
+          tmp64.resize(e - a);
+          for (uint32_t i = 0; i < e - a; i++) tmp64[i] = lw.inj_word[perm[i]];
+          std::copy(tmp64.begin(), tmp64.end(), lw.inj_word.begin() + a);
+        }
+        for (uint32_t r = a; r < e;) {
+          uint32_t q = r + 1;
+          while (q < e && layer[q] == layer[r]) q++;
+          std::reverse(lw.inj_qubit.begin() + r, lw.inj_qubit.begin() + q);
+          std::reverse(lw.inj_word.begin() + r, lw.inj_word.begin() + q);
+          r = q;
+        }
       }
-      lw.inj_layer.resize(inj.size());
-      lw.inj_qubit.resize(inj.size());
-      lw.inj_word.resize(inj.size());
-      for (size_t k = 0; k < inj.size(); k++) {
-        lw.inj_layer[k] = inj[k].layer;
-        lw.inj_qubit[k] = inj[k].qubit;
-        lw.inj_word[k] = inj[k].word;
-      }
-      lw.inj_next.resize(inj.size());
+      lw.inj_next.resize(n_inj);
       for (uint32_t w = 0; w < lw.w; w++) {
         const uint32_t a = lw.inj_off[w], e = lw.inj_off[w + 1];
         uint32_t next = e - a;
