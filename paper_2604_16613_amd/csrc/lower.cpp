@@ -248,13 +248,6 @@ struct RawChan {
 
 namespace {
 
-// A column's leaf word from one measurement: column, layer, qubit,
-// measurement, word.
-struct InjEntry {
-  uint32_t w, layer, qubit, m;
-  uint64_t word;
-};
-
 // The program-order scheduling of one circuit, fed one elementary operation
 // at a time by either front end (circuit text or the binary form): ASAP
 // layers, measurement records, noise channels at their boundary, and the
