@@ -109,6 +109,15 @@ def test_text_split_across_tokenizer_threads():
     compare(c.text)
 
 
+def test_text_in_chunks_on_the_scheduling_thread():
+    """A text of several 32 KB chunks but below the 256 KB that start
+    tokenizer threads (0.23 MB, d = 13) is tokenized chunk by chunk on the
+    scheduling thread and replays to the oracle's signatures."""
+    c = rotated_surface_code_memory(13, 13)
+    assert 4 * (1 << 15) < len(c.text) < 2 * (1 << 17)
+    compare(c.text)
+
+
 def _error_line(text):
     from paper_2604_16613_amd import GpError, _gp
     with pytest.raises(GpError) as e:
