@@ -77,3 +77,38 @@ def test_host_code_is_clean_under_sanitizers(sanitized):
     r = subprocess.run([exe, *files], capture_output=True, text=True, env=env, timeout=600)
     assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-6000:]
     assert "batch of" in r.stdout
+
+
+def test_lowering_threads_are_race_free_under_tsan(tmp_path):
+    """The host lowering built with -fsanitize=thread: large texts (the
+    tokenizer threads claiming chunks while the scheduling thread works
+    through them, the channel-table and injection-list threads), a multi-chunk
+    text below the thread size, and large texts with an error early, in the
+    middle or at the end (tokenizer errors and schedule errors: the scheduling
+    thread stops while tokenizer threads still run). Any data race fails the
+    run."""
+    exe = str(tmp_path / "tsan_lower")
+    subprocess.run(["g++", "-std=c++17", "-pthread", "-fsanitize=thread", "-g", "-O1", "-I",
+                    os.path.join(ROOT, "include"), "-I", CSRC, os.path.join(HERE, "tsan_lower_main.cpp"),
+                    os.path.join(CSRC, "lower.cpp"), "-o", exe], check=True)
+    big = rotated_surface_code_memory(17, 17).text
+    lines = big.split("\n")
+    n = len(lines)
+    files = {
+        "sc17.stim": big,
+        "sc13.stim": rotated_surface_code_memory(13, 13).text,
+        "bb144.stim": bivariate_bicycle_memory().text,
+        "early.bad": "\n".join(lines[:50] + ["FOO 1"] + lines[50:]),
+        "middle.bad": "\n".join(lines[:n // 2] + ["CX 0"] + lines[n // 2:]),
+        "late.bad": "\n".join(lines[:n - 20] + ["H rec[-1]"] + lines[n - 20:]),
+    }
+    paths = []
+    for name, text in files.items():
+        p = tmp_path / name
+        p.write_text(text)
+        paths.append(str(p))
+    env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1:exitcode=66")
+    r = subprocess.run([exe, *paths], capture_output=True, text=True, env=env, timeout=600)
+    assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-6000:]
+    assert "WARNING: ThreadSanitizer" not in r.stderr
+    assert r.stdout.count("lowered ") == 3 and r.stdout.count("rejected ") == 3
